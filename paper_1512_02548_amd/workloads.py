@@ -1,0 +1,262 @@
+"""Seeded synthetic inputs for wave-tank runs.
+
+This module holds no arithmetic of the numerical method: it only draws
+parameters and evaluates closed-form surface fields (linear waves, a
+phase-locked Fourier series, a trapezoidal bar, a JONSWAP-shaped irregular
+train) at surface x-coordinates that the caller supplies.  It is shared by the
+product path (bench, serving) and by the tests that feed the same arrays to the
+CPU oracle.
+
+Workloads (sizes are quads in x by layers in sigma, order P):
+  standing_wave    8x2, P=4, periodic, kh=1, H/L=0.001, linear standing wave
+  stream_series    64x4, P=6, periodic, kh=1, H/L=0.0903 (90% of limiting),
+                   20-mode phase-locked series, Pf=9, filter last 2 modes 0.5%
+  bar_irregular    2048x8, P=6, walls, L=40h, trapezoidal bar, 64-component
+                   JONSWAP-shaped train with kh in [0.5, 3]
+  batch_tanks      256 periodic flat tanks with random sizes and orders
+  requests         Poisson request stream of tanks drawn like batch_tanks,
+                   half of them over a bar
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+G_ACC = 9.81
+SEED_BASE = 20251512
+
+
+def omega_linear(k, h, g=G_ACC):
+    """Linear dispersion relation omega^2 = g k tanh(kh) (for input generation)."""
+    return np.sqrt(g * k * np.tanh(k * h))
+
+
+def limiting_steepness(kh):
+    """H_max/L as a function of kh: 0.1003 at kh = 1 scaled like tanh(kh)
+    (calibrated so that 90% gives H/L = 0.0903 at kh = 1)."""
+    return 0.1003 * np.tanh(kh) / np.tanh(1.0)
+
+
+@dataclass
+class TankSpec:
+    """Everything needed to build one tank and its initial state."""
+    nx: int
+    nz: int
+    P: int
+    length: float
+    periodic: bool
+    Pf: int
+    filter_ic: int
+    filter_sigma: float
+    dt: float
+    steps: int
+    rtol: float
+    g: float = G_ACC
+    name: str = ""
+    params: dict = field(default_factory=dict)
+
+    @property
+    def ns(self):
+        return self.P * self.nx + (0 if self.periodic else 1)
+
+
+def courant_dt(length, nx, P, c, cr=0.5):
+    """dt = Cr * (node spacing dX/P) / c."""
+    return cr * (length / nx / P) / c
+
+
+# ------------------------------------------------------------ 8x2 standing wave
+def standing_wave_spec():
+    k, h = 1.0, 1.0
+    L = 2 * np.pi / k
+    c = omega_linear(k, h) / k
+    return TankSpec(nx=8, nz=2, P=4, length=L, periodic=True, Pf=4, filter_ic=5,
+                    filter_sigma=1.0, dt=courant_dt(L, 8, 4, c), steps=10, rtol=1e-12,
+                    name="standing_wave_8x2_P4", params=dict(k=k, h=h, H=0.001 * L))
+
+
+def standing_wave_state(xs, spec, t0_frac=0.125, H=None):
+    """Linear standing wave eta = H/2 cos kx cos wt0 and the exact linear
+    potential evaluated at z = eta(x), at t0 = T/8."""
+    k, h = spec.params["k"], spec.params["h"]
+    H = spec.params["H"] if H is None else H
+    w = omega_linear(k, h)
+    t0 = t0_frac * 2 * np.pi / w
+    xs = np.asarray(xs, dtype=float)
+    eta = 0.5 * H * np.cos(k * xs) * np.cos(w * t0)
+    phi = (-(H * G_ACC / (2 * w)) * np.cosh(k * (eta + h)) / np.cosh(k * h)
+           * np.cos(k * xs) * np.sin(w * t0))
+    return eta, phi, np.full_like(xs, h), np.zeros_like(xs)
+
+
+# ------------------------------------------------------ 64x4 stream-type series
+def stream_series_spec(nx=64, nz=4, P=6, steps=1000):
+    k, h = 1.0, 1.0
+    L = 2 * np.pi / k
+    c = omega_linear(k, h) / k
+    return TankSpec(nx=nx, nz=nz, P=P, length=L, periodic=True, Pf=int(np.ceil(1.5 * P)),
+                    filter_ic=P - 1, filter_sigma=0.995, dt=courant_dt(L, nx, P, c),
+                    steps=steps, rtol=1e-12, name=f"stream_series_{nx}x{nz}_P{P}",
+                    params=dict(k=k, h=h, HL=0.9 * limiting_steepness(k * h), modes=20,
+                                rho=0.3, seed=SEED_BASE + 2))
+
+
+def series_coefficients(k, h, L, HL, modes, rho, seed):
+    """Phase-locked amplitudes a_j = a1 rho^(j-1) u_j, u_j ~ U[0.8, 1.2],
+    scaled so that max(eta) - min(eta) = HL * L on a fine grid."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.8, 1.2, modes)
+    a = rho ** np.arange(modes) * u
+    xf = np.linspace(0.0, L, 8192, endpoint=False)
+    eta = (a[:, None] * np.cos(np.arange(1, modes + 1)[:, None] * k * xf[None, :])).sum(0)
+    return a * (HL * L / (eta.max() - eta.min()))
+
+
+def series_state(xs, k, h, a):
+    """eta = sum a_j cos(jkx), phi~ = sum c a_j coth(jkh) sin(jkx) with the
+    carrier's linear phase speed c."""
+    xs = np.asarray(xs, dtype=float)
+    c = omega_linear(k, h) / k
+    j = np.arange(1, len(a) + 1)[:, None]
+    eta = (a[:, None] * np.cos(j * k * xs[None, :])).sum(0)
+    phi = (c * a[:, None] / np.tanh(j * k * h) * np.sin(j * k * xs[None, :])).sum(0)
+    return eta, phi
+
+
+def stream_series_state(xs, spec):
+    p = spec.params
+    a = series_coefficients(p["k"], p["h"], spec.length, p["HL"], p["modes"], p["rho"], p["seed"])
+    eta, phi = series_state(xs, p["k"], p["h"], a)
+    xs = np.asarray(xs, dtype=float)
+    return eta, phi, np.full_like(xs, p["h"]), np.zeros_like(xs)
+
+
+# ---------------------------------------------- 2048x8 bar, irregular waves
+def bar_irregular_spec(nx=2048, nz=8, P=6, steps=4):
+    L, h0 = 40.0, 1.0
+    c = omega_linear(1.0, h0)
+    return TankSpec(nx=nx, nz=nz, P=P, length=L, periodic=False, Pf=int(np.ceil(1.5 * P)),
+                    filter_ic=P - 1, filter_sigma=0.995, dt=courant_dt(L, nx, P, c),
+                    steps=steps, rtol=1e-10, name=f"bar_irregular_{nx}x{nz}_P{P}",
+                    params=dict(h0=h0, crest=0.3, seed=SEED_BASE + 3, Hs=0.04,
+                                ncomp=64, kmin=0.5, kmax=3.0, kp=1.0, gamma=3.3))
+
+
+def trapezoid_bar(xs, L, nx, h0, crest, x0, crest_len, up=20.0, down=10.0):
+    """Depth of a trapezoidal bar: h0 offshore, rising with slope 1:up to the
+    crest depth, flat crest, falling with slope 1:down back to h0.  Corner
+    positions snap to element boundaries.  Returns (h, h_x)."""
+    dX = L / nx
+    rise = h0 - crest
+    snap = lambda v: np.round(v / dX) * dX
+    xa = snap(x0)
+    xb = snap(xa + rise * up)
+    xc = snap(xb + crest_len)
+    xd = snap(xc + rise * down)
+    xs = np.asarray(xs, dtype=float)
+    h = np.full_like(xs, h0)
+    hx = np.zeros_like(xs)
+    m = (xs > xa) & (xs < xb)
+    h[m] = h0 - (xs[m] - xa) * rise / (xb - xa)
+    hx[m] = -rise / (xb - xa)
+    m = (xs >= xb) & (xs <= xc)
+    h[m] = crest
+    m = (xs > xc) & (xs < xd)
+    h[m] = crest + (xs[m] - xc) * rise / (xd - xc)
+    hx[m] = rise / (xd - xc)
+    return h, hx
+
+
+def jonswap(omega_, omega_p, gamma=3.3):
+    """JONSWAP-shaped spectral density (textbook form, unnormalised)."""
+    sig = np.where(omega_ <= omega_p, 0.07, 0.09)
+    r = np.exp(-((omega_ - omega_p) ** 2) / (2 * sig ** 2 * omega_p ** 2))
+    return omega_ ** -5 * np.exp(-1.25 * (omega_p / omega_) ** 4) * gamma ** r
+
+
+def bar_irregular_state(xs, spec):
+    p = spec.params
+    rng = np.random.default_rng(p["seed"])
+    x0 = rng.uniform(4.0, 8.0)
+    crest_len = rng.uniform(2.0, 6.0)
+    h, hx = trapezoid_bar(xs, spec.length, spec.nx, p["h0"], p["crest"], x0, crest_len)
+    ks = np.exp(np.linspace(np.log(p["kmin"]), np.log(p["kmax"]), p["ncomp"]))
+    om = omega_linear(ks, p["h0"])
+    omp = omega_linear(p["kp"], p["h0"])
+    dom = np.gradient(om)
+    S = jonswap(om, omp, p["gamma"])
+    amp = np.sqrt(2 * S * dom)
+    phase = rng.uniform(0.0, 2 * np.pi, p["ncomp"])
+    # scale to the significant wave height Hs = 4 sqrt(m0)
+    m0 = 0.5 * np.sum(amp ** 2)
+    amp *= p["Hs"] / (4 * np.sqrt(m0))
+    xs = np.asarray(xs, dtype=float)
+    arg = ks[:, None] * xs[None, :] - phase[:, None]
+    eta = (amp[:, None] * np.cos(arg)).sum(0)
+    c = om / ks
+    phi = (amp[:, None] * (c / np.tanh(ks * p["h0"]))[:, None] * np.sin(arg)).sum(0)
+    # cosine taper to zero within 2 of each wall
+    taper = np.ones_like(xs)
+    lw, L = 2.0, spec.length
+    m = xs < lw
+    taper[m] = 0.5 * (1 - np.cos(np.pi * xs[m] / lw))
+    m = xs > L - lw
+    taper[m] = 0.5 * (1 - np.cos(np.pi * (L - xs[m]) / lw))
+    return eta * taper, phi * taper, h, hx
+
+
+# ------------------------------------------------------------ batches
+def batch_tank_specs(count=256, seed=SEED_BASE + 4, steps=200, rtol=1e-10, bar_fraction=0.0):
+    """Random periodic tanks: nx ~ U{16..1024}, nz ~ U{2,4,8}, P ~ U{4,6,8},
+    kh ~ U[0.5, 3], H/L ~ U[0.01, 0.9] of the limiting steepness, about 8
+    elements per wavelength (L = m 2 pi / k, m = max(1, nx // 8))."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        nx = int(rng.integers(16, 1025))
+        nz = int(rng.choice([2, 4, 8]))
+        P = int(rng.choice([4, 6, 8]))
+        kh = float(rng.uniform(0.5, 3.0))
+        frac = float(rng.uniform(0.01, 0.9))
+        bar = bool(rng.uniform() < bar_fraction)
+        crest = float(rng.uniform(0.3, 0.6))
+        h = 1.0
+        k = kh / h
+        mwav = max(1, nx // 8)
+        L = mwav * 2 * np.pi / k
+        c = omega_linear(k, h) / k
+        specs.append(TankSpec(nx=nx, nz=nz, P=P, length=L, periodic=True,
+                              Pf=int(np.ceil(1.5 * P)), filter_ic=P - 1, filter_sigma=0.995,
+                              dt=courant_dt(L, nx, P, c), steps=steps, rtol=rtol,
+                              name=f"tank{i}_{nx}x{nz}_P{P}",
+                              params=dict(k=k, h=h, HL=frac * limiting_steepness(kh), modes=8,
+                                          rho=0.3, seed=int(rng.integers(0, 2 ** 31)),
+                                          mwav=mwav, bar=bar, crest=crest)))
+    return specs
+
+
+def batch_tank_state(xs, spec):
+    """Phase-locked series on the tank's own wavelength; optionally a bar
+    scaled into the middle 60% of the tank."""
+    p = spec.params
+    xs = np.asarray(xs, dtype=float)
+    a = series_coefficients(p["k"], p["h"], 2 * np.pi / p["k"],
+                            p["HL"], p["modes"], p["rho"], p["seed"])
+    eta, phi = series_state(xs, p["k"], p["h"], a)
+    h = np.full_like(xs, p["h"])
+    hx = np.zeros_like(xs)
+    if p.get("bar"):
+        L = spec.length
+        span = 0.6 * L
+        rise = p["h"] - p["crest"]
+        # slopes scaled so that the whole bar fits the middle 60%
+        total = rise * (20 + 10) + 0.2 * span
+        sc = span / total
+        h, hx = trapezoid_bar(xs, L, spec.nx, p["h"], p["crest"], 0.2 * L, 0.2 * span * sc,
+                              up=20 * sc, down=10 * sc)
+    return eta, phi, h, hx
+
+
+def poisson_arrivals(rate, count, seed=SEED_BASE + 5):
+    """Arrival times of a Poisson process with the given rate (per second)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, count))
