@@ -1,0 +1,184 @@
+/* sem.h -- C ABI of the MI355X hot path of the stabilised nodal spectral
+ * element method for fully nonlinear potential-flow water waves
+ * (Engsig-Karup, Eskilsson & Bigoni, arXiv:1512.02548).
+ *
+ * Model (paper Sec. 2): the free-surface elevation eta(x,t) and surface
+ * potential phi~(x,t) evolve by the Zakharov equations; the vertical surface
+ * velocity w~ comes from the Laplace problem for the potential, solved in the
+ * sigma-transformed domain (x, sigma) in [0,L] x [0,1] with
+ * sigma = (z + h)/(eta + h), Dirichlet phi = phi~ at the surface and the
+ * natural (impermeable) condition at the bed and at walls.
+ *
+ * Discretisation (Sec. 3): Nx columns x Nz layers of quadrilaterals, each cut
+ * into two order-P nodal triangles (warp-and-blend nodes); quadrature-free
+ * element operators built from D_r, D_s and M = (V V^T)^{-1}; global L2
+ * projections for gradients; over-integrated free-surface right-hand side;
+ * classical RK4; per-element modal filter.
+ *
+ * Conventions
+ *  - Array arguments are DEVICE pointers to contiguous FP64 data unless the
+ *    comment says HOST.  All device work is ordered on `stream` (a
+ *    hipStream_t passed as void*; NULL = the default stream).
+ *  - Surface arrays have length ns and are ordered by x.  Volume arrays have
+ *    length n in the library's node numbering, exposed by
+ *    sem_mesh_node_coords.
+ *  - The caller owns every buffer.  The library allocates no device memory:
+ *    sem_mesh_query reports the workspace size, the caller allocates it and
+ *    hands it to sem_mesh_bind.  The library never frees caller memory.
+ *  - Errors are return codes; no exceptions cross the ABI and nothing is
+ *    printed.  sem_last_error() gives a thread-local message.  Argument
+ *    errors are detected before any launch.  Device-detected conditions
+ *    (DOMAIN, NONFINITE, BREAKDOWN, NOCONV) are accumulated in a device
+ *    status word and returned when the call ends; every call that returns
+ *    such a status synchronises `stream`.
+ *  - A mesh is used by one stream at a time (its workspace holds scratch
+ *    state); distinct meshes may run concurrently on distinct streams.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_mesh sem_mesh;
+typedef struct sem_batch sem_batch;
+
+typedef enum {
+  SEM_OK = 0,
+  SEM_E_INVAL = 1,      /* bad argument (host-checked, nothing launched)      */
+  SEM_E_NOMEM = 2,      /* workspace too small                                */
+  SEM_E_DOMAIN = 3,     /* some water column height d = eta + h <= 0 (Sec. 2)  */
+  SEM_E_NOCONV = 4,     /* Krylov solver hit max_iter before rtol             */
+  SEM_E_BREAKDOWN = 5,  /* Krylov breakdown (zero Arnoldi norm with r != 0)   */
+  SEM_E_NONFINITE = 6,  /* NaN or Inf detected                                */
+  SEM_E_DEVICE = 7      /* HIP runtime error                                  */
+} sem_status;
+
+typedef enum {
+  SEM_PREC_FP64 = 0,     /* plain FP64 Krylov solve                            */
+  SEM_PREC_FP32_IR = 1,  /* FP64 iterative refinement, FP32 inner solves       */
+  SEM_PREC_BF16_IR = 2   /* FP64 iterative refinement, BF16-stored inner solve */
+} sem_precision;
+
+typedef enum {
+  SEM_RECOVER_DX = 0,    /* 1D: f[ns] -> f_x[ns]  (M' f_x = S_x f, Sec. 3.1.3)         */
+  SEM_RECOVER_W = 1      /* 2D: Phi[n], eta[ns] -> w~[ns] (M w = S_z Phi, Sec. 3.1.3) */
+} sem_recover_kind;
+
+typedef enum {
+  SEM_OP_STIFFNESS = 0,  /* y = A u, quadrature-free Laplace operator (Sec. 3.1.2, 3.2) */
+  SEM_OP_MASS2D = 1,     /* y = M u, 2D mass of the computational domain             */
+  SEM_OP_PRECOND = 2,    /* y = B u, Laplace preconditioner (surface rows zero)      */
+  SEM_OP_SZ = 3          /* y = S_z u (vertical-derivative projection right side)    */
+} sem_operator;
+
+typedef struct {
+  int32_t nx, nz;              /* quads in x, layers in sigma (both >= 1)           */
+  int32_t order;               /* polynomial order P, 1..10                         */
+  int32_t periodic;            /* 1: periodic in x; 0: impermeable walls            */
+  double length;               /* L > 0                                             */
+  double g;                    /* gravity (9.81)                                    */
+  const double *h, *h_x;       /* HOST, ns: still-water depth and slope at the surface nodes */
+  const double *sigma_levels;  /* HOST, nz+1 increasing from 0 to 1, or NULL = uniform */
+  int32_t filter_ic;           /* modal filter: modes >= ic scaled by filter_sigma (ic >= 2) */
+  double filter_sigma;         /* 1.0 = filter off                                  */
+  int32_t overint_order;       /* Pf >= P: GLL(Pf) fine grid for the FS right side; Pf == P: none */
+  int32_t restart;             /* GMRES restart length, 0 = default (30)            */
+} sem_mesh_desc;
+
+typedef struct {
+  int64_t n, ns, n_free, n_elem;
+  int32_t np, nblocks;
+  uint64_t workspace_bytes;    /* bytes the caller must allocate (256-byte aligned) */
+} sem_mesh_info;
+
+typedef struct {
+  double rtol;          /* ||b - A x||_2 <= rtol ||b||_2 (free nodes)              */
+  int32_t max_iter;     /* total Krylov iterations (inner iterations for IR)       */
+  int32_t prec;         /* sem_precision                                           */
+  double inner_rtol;    /* IR: relative tolerance of each inner solve              */
+  int32_t max_refine;   /* IR: maximum outer refinements                           */
+  int32_t warm_start;   /* 1: phi holds the initial guess on entry                 */
+  int32_t poll_every;   /* iterations launched between host convergence polls      */
+  int32_t reserved;
+} sem_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* Krylov iterations (all inner iterations under IR)   */
+  int32_t refinements;  /* outer IR steps (0 for FP64)                         */
+  double rel_residual;  /* final ||r||/||b|| (FP64 true residual under IR)     */
+  double seconds;       /* wall time of the call (host clock, synchronised)    */
+  int32_t status;       /* sem_status of this solve                            */
+  int32_t reserved;
+} sem_solve_stats;
+
+/* Build the host-side description of a tank (reference element, mesh tables,
+ * preconditioner blocks).  Host work only; no device call. */
+sem_status sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out);
+sem_status sem_mesh_query(const sem_mesh* mesh, sem_mesh_info* out);
+/* Upload constants into caller memory `workspace` (device, >= workspace_bytes,
+ * 256-byte aligned) on `stream`.  Must precede every device call. */
+sem_status sem_mesh_bind(sem_mesh* mesh, void* workspace, size_t bytes, void* stream);
+/* HOST outputs, length n: x and sigma of every volume node. */
+sem_status sem_mesh_node_coords(const sem_mesh* mesh, double* x_host, double* sigma_host);
+/* HOST output, length ns: volume index of each (x-ordered) surface node. */
+sem_status sem_mesh_surface_nodes(const sem_mesh* mesh, int64_t* idx_host);
+void sem_mesh_destroy(sem_mesh* mesh);
+
+/* Geometric factors of the sigma-map at every element node (Sec. 2, the
+ * Jacobian and K = J J^T / det J with q = (1-sigma) h_x - sigma eta_x):
+ * stores G = |J| Lam K Lam^T and 1/d in the workspace.  eta, eta_x: [ns]. */
+sem_status sem_set_surface(sem_mesh* mesh, const double* eta, const double* eta_x, void* stream);
+
+/* y = op(u) on full-length vectors [n] with the factors of the last
+ * sem_set_surface (diagnostic access to the operators of Secs. 3.1.2-3.2). */
+sem_status sem_apply(sem_mesh* mesh, sem_operator op, const double* u, double* y, void* stream);
+
+/* Laplace problem of Sec. 3.1.2 for the surface state (eta, eta_x, phi~):
+ * A_FF Phi_F = -A_FS phi~, Phi_S = phi~.  phi [n]: in = initial guess when
+ * opts->warm_start, out = Phi including the surface values.  stats may be
+ * NULL. */
+sem_status sem_laplace_solve(sem_mesh* mesh, const double* eta, const double* eta_x,
+                             const double* phi_s, double* phi, const sem_solve_opts* opts,
+                             sem_solve_stats* stats, void* stream);
+
+/* Gradient recovery by global L2 projection (Sec. 3.1.3).
+ * SEM_RECOVER_DX: in = f [ns], eta unused (may be NULL), out = f_x [ns].
+ * SEM_RECOVER_W:  in = Phi [n], eta [ns], out = w~ [ns]. */
+sem_status sem_gradient_recover(sem_mesh* mesh, sem_recover_kind kind, const double* in,
+                                const double* eta, double* out, void* stream);
+
+/* Over-integrated Galerkin right-hand side of the free-surface equations
+ * (Secs. 3.1.1, 3.3) followed by the M' solves: (deta_dt, dphi_dt) [ns]. */
+sem_status sem_free_surface_rhs(sem_mesh* mesh, const double* eta, const double* eta_x,
+                                const double* phi_x, const double* w_s, double* deta_dt,
+                                double* dphi_dt, void* stream);
+
+/* One classical RK4 step of (eta, phi~) [ns] followed by the modal filter
+ * (Secs. 3.1.1, 3.4).  phi_ws [n] carries the warm start of the Laplace
+ * solves across calls.  Transactional: on error eta and phi_s are left
+ * unchanged.  stats: HOST array of 4 (one per stage) or NULL. */
+sem_status sem_rk4_step(sem_mesh* mesh, double* eta, double* phi_s, double* phi_ws, double dt,
+                        const sem_solve_opts* opts, sem_solve_stats* stats, void* stream);
+
+/* Batching: many independent tanks advanced together, each with its own
+ * workspace; kernels of all active tanks share launches.  Results per tank
+ * do not depend on which other tanks are in the batch. */
+sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, sem_batch** out);
+sem_status sem_batch_rk4_step(sem_batch* batch, double* const* eta, double* const* phi_s,
+                              double* const* phi_ws, const double* dt_host,
+                              const uint8_t* active_host, const sem_solve_opts* opts,
+                              int32_t* per_tank_status_host, int32_t* per_tank_iters_host,
+                              void* stream);
+void sem_batch_destroy(sem_batch* batch);
+
+const char* sem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEM_H */

@@ -1,0 +1,888 @@
+// HIP kernels (gfx950) of the spectral element free-surface path.
+//
+// Data layout (one tank):
+//   volume vectors [n]: column-major node numbering.  Column c owns nc =
+//     P*(P*nz+1) nodes: its left vertical line (nl = P*nz+1 nodes, ordered
+//     by sigma) followed by its interior nodes.  The right line of column c is
+//     the left line of column c+1 (periodic wrap, or the extra wall line
+//     stored at nx*nc).
+//   element blocks: workgroup b handles cb consecutive columns (EB = cb*2nz
+//     elements, T = ceil(EB/16) MFMA tiles).  Inputs are staged through LDS,
+//     element results are summed per node in a fixed order, interior nodes
+//     and the block's left line are stored, the contribution to the right
+//     line goes to a side buffer and is added by a fix-up pass (two fixed
+//     contributions per shared line: results are deterministic).
+//   geometric factors G: MFMA tile layout [blk][tile][comp][perm(row)][16].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sem_internal.hpp"
+
+namespace sem {
+
+// ------------------------------------------------------------ helpers
+__device__ inline double block_sum(double v, double* red) {
+  // deterministic tree reduction over a 256-thread workgroup
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline bool finite(double v) { return v - v == 0.0; }
+
+__device__ inline int64_t right_line_base(const TankDev& d, int c) {
+  // global index of the first node of the vertical line at x_c (c in 0..nx)
+  if (c < d.nx) return (int64_t)c * d.nc;
+  return d.periodic ? 0 : (int64_t)d.nx * d.nc;
+}
+
+// ------------------------------------------------------------ coefficients
+// G = |J| Lam K Lam^T and 1/d at every element node (paper Sec. 2).
+template <int P>
+__global__ void k_coef(const TankDev* __restrict__ td, const double* __restrict__ eta,
+                       const double* __restrict__ etax, int what) {
+  const TankDev& d = *td;
+  constexpr int Np = (P + 1) * (P + 2) / 2;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)d.nx * 2 * d.nz * Np;
+  if (gid >= total) return;
+  int m = gid % Np;
+  int64_t e = gid / Np;
+  int jt = e % (2 * d.nz);
+  int c = e / (2 * d.nz);
+  int t = jt & 1, j = jt >> 1;
+  int b = c / d.cb, lc = c % d.cb;
+  int eb = lc * 2 * d.nz + jt;
+  const double* lay = d.lay + jt * 8;
+  const double* w = d.colw + ((size_t)t * d.NpP + m) * (P + 1);
+  double et = 0, ex = 0, hh = 0, hxx = 0;
+  for (int k = 0; k <= P; ++k) {
+    int s = c * P + k;
+    if (s >= d.ns) s -= d.ns;  // periodic wrap
+    et += w[k] * eta[s];
+    ex += w[k] * (etax ? etax[s] : 0.0);
+    hh += w[k] * d.h[s];
+    hxx += w[k] * d.hx[s];
+  }
+  double zeta = d.nodeq[((size_t)t * d.NpP + m) * 2 + 1];
+  double sig = lay[5] + zeta * lay[6];
+  double dd = et + hh;
+  if (!(dd > 0.0)) atomicOr(d.status, finite(dd) ? ST_DOMAIN : ST_NONFINITE);
+  double q = (1.0 - sig) * hxx - sig * ex;
+  double K00 = dd, K01 = q, K11 = (1.0 + q * q) / dd;
+  double l00 = lay[0], l01 = lay[1], l10 = lay[2], l11 = lay[3], J = lay[4];
+  // G = J Lam K Lam^T
+  double a0 = l00 * K00 + l01 * K01, a1 = l00 * K01 + l01 * K11;
+  double b0 = l10 * K00 + l11 * K01, b1 = l10 * K01 + l11 * K11;
+  double Grr = J * (a0 * l00 + a1 * l01);
+  double Grs = J * (a0 * l10 + a1 * l11);
+  double Gss = J * (b0 * l10 + b1 * l11);
+  if (what & 2) d.invd[tile_index(d.T, d.NpP, b, eb, m, 1, 0)] = 1.0 / dd;
+  if (!(what & 1)) return;
+  d.G[tile_index(d.T, d.NpP, b, eb, m, 3, 0)] = Grr;
+  d.G[tile_index(d.T, d.NpP, b, eb, m, 3, 1)] = Grs;
+  d.G[tile_index(d.T, d.NpP, b, eb, m, 3, 2)] = Gss;
+  d.G32[tile_index(d.T, d.NpP, b, eb, m, 3, 0)] = (float)Grr;
+  d.G32[tile_index(d.T, d.NpP, b, eb, m, 3, 1)] = (float)Grs;
+  d.G32[tile_index(d.T, d.NpP, b, eb, m, 3, 2)] = (float)Gss;
+}
+
+// ------------------------------------------------------------ gather kernels
+enum { OP_STIFF = 0, OP_MASS = 1, OP_PRE_LAP = 2, OP_PRE_MASS = 3, OP_SZ = 4 };
+enum { F_MASK_SURF = 1, F_NEG = 2 };
+
+// Per block: y_owned = sum over the block's elements of op_e(u_e).
+// LDS: region of the input (cb*nc + nl), per-element stage buffers.
+template <int P, int OP>
+__global__ void __launch_bounds__(kBlockThreads)
+k_gather(const TankDev* __restrict__ td, const double* __restrict__ u, double* __restrict__ y,
+         double* __restrict__ side, int flags) {
+  const TankDev& d = *td;
+  constexpr int Np = (P + 1) * (P + 2) / 2;
+  constexpr int NpP = (Np + 15) / 16 * 16;
+  extern __shared__ double lds[];
+  const int b = blockIdx.x;
+  const int c0 = b * d.cb;
+  const int cbb = min(d.cb, d.nx - c0);
+  const int nc = d.nc, nl = d.nl;
+  const int nreg = cbb * nc + nl;
+  const int EBb = cbb * 2 * d.nz;
+  double* ureg = lds;                         // [cb*nc + nl]
+  double* st1 = ureg + (d.cb * nc + nl);      // [EB][NpP] first stage
+  double* st2 = st1 + d.EB * NpP;             // [EB][NpP] second stage
+  double* st3 = st2 + d.EB * NpP;             // [EB][NpP] element outputs
+  // 1. stage the input region
+  for (int q = threadIdx.x; q < nreg; q += blockDim.x) {
+    int lc = q / nc, ql = q - lc * nc;
+    int64_t gi;
+    if (lc < cbb) gi = (int64_t)(c0 + lc) * nc + ql;
+    else gi = (ql < nl) ? right_line_base(d, c0 + cbb) + ql : -1;
+    ureg[q] = gi >= 0 ? u[gi] : 0.0;
+  }
+  __syncthreads();
+  // 2. per-element work, thread per (element, node)
+  const int work = EBb * Np;
+  if (OP == OP_STIFF || OP == OP_SZ) {
+    // phase 1: derivatives and pointwise flux f_a = sum_b G_ab D_b u
+    for (int it = threadIdx.x; it < work; it += blockDim.x) {
+      int eb = it / Np, i = it - eb * Np;
+      int lc = eb / (2 * d.nz), jt = eb - lc * 2 * d.nz;
+      const int32_t* loc = d.elem_loc + jt * NpP;
+      double tr = 0, ts = 0;
+      for (int k = 0; k < Np; ++k) {
+        double uk = ureg[lc * nc + loc[k]];
+        tr += d.Dr[i * NpP + k] * uk;
+        ts += d.Ds[i * NpP + k] * uk;
+      }
+      if (OP == OP_STIFF) {
+        double grr = d.G[tile_index(d.T, NpP, b, eb, i, 3, 0)];
+        double grs = d.G[tile_index(d.T, NpP, b, eb, i, 3, 1)];
+        double gss = d.G[tile_index(d.T, NpP, b, eb, i, 3, 2)];
+        st1[eb * NpP + i] = grr * tr + grs * ts;
+        st2[eb * NpP + i] = grs * tr + gss * ts;
+      } else {
+        const double* lay = d.lay + jt * 8;
+        double dsig = lay[1] * tr + lay[3] * ts;
+        st1[eb * NpP + i] = dsig * d.invd[tile_index(d.T, NpP, b, eb, i, 1, 0)];
+      }
+    }
+    __syncthreads();
+    // phase 2
+    for (int it = threadIdx.x; it < work; it += blockDim.x) {
+      int eb = it / Np, i = it - eb * Np;
+      double acc = 0;
+      if (OP == OP_STIFF) {
+        for (int k = 0; k < Np; ++k)
+          acc += d.MDr[k * NpP + i] * st1[eb * NpP + k] + d.MDs[k * NpP + i] * st2[eb * NpP + k];
+      } else {
+        int jt = eb % (2 * d.nz);
+        double J = d.lay[jt * 8 + 4];
+        for (int k = 0; k < Np; ++k) acc += d.Mref[i * NpP + k] * st1[eb * NpP + k];
+        acc *= J;
+      }
+      st3[eb * NpP + i] = acc;
+    }
+  } else {
+    for (int it = threadIdx.x; it < work; it += blockDim.x) {
+      int eb = it / Np, i = it - eb * Np;
+      int lc = eb / (2 * d.nz), jt = eb - lc * 2 * d.nz;
+      const int32_t* loc = d.elem_loc + jt * NpP;
+      const double* A;
+      double scale = 1.0;
+      if (OP == OP_MASS) {
+        A = d.Mref;
+        scale = d.lay[jt * 8 + 4];
+      } else {
+        int c = c0 + lc;
+        int cls = d.nclass_col == 1 ? 0 : (c == 0 ? 0 : (c == d.nx - 1 ? 2 : 1));
+        if (d.nclass_col == 3 && d.nx == 1) cls = 0;
+        const double* base = (OP == OP_PRE_LAP) ? d.pre_lap : d.pre_mass;
+        A = base + ((size_t)(cls * 2 * d.nz + jt)) * NpP * NpP;
+      }
+      double acc = 0;
+      for (int k = 0; k < Np; ++k) acc += A[i * NpP + k] * ureg[lc * nc + loc[k]];
+      st3[eb * NpP + i] = scale * acc;
+    }
+  }
+  __syncthreads();
+  // 3. node sums in a fixed order; store owned nodes, side buffer for the right line
+  const double sgn = (flags & F_NEG) ? -1.0 : 1.0;
+  const int nown = cbb * nc;
+  for (int q = threadIdx.x; q < nown + nl; q += blockDim.x) {
+    int lc = q / nc, ql = q - lc * nc;
+    double acc = 0;
+    if (lc < cbb) {
+      int cnt = d.acc_cnt[ql];
+      for (int k = 0; k < cnt; ++k) {
+        int e = d.acc_ent[ql * kMaxContrib + k];
+        int prev = (e >> 30) & 1;
+        int off = e & 0x3fffffff;
+        if (prev) {
+          if (lc == 0) continue;  // previous column belongs to the left block
+          acc += st3[(lc - 1) * 2 * d.nz * NpP + off];
+        } else {
+          acc += st3[lc * 2 * d.nz * NpP + off];
+        }
+      }
+      acc *= sgn;
+      if ((flags & F_MASK_SURF) && d.is_surf_loc[ql]) acc = 0.0;
+      y[(int64_t)(c0 + lc) * nc + ql] = acc;
+    } else {
+      // right line: contributions of column cbb-1 through its right-line nodes
+      if (ql >= nl) continue;
+      int cnt = d.acc_cnt[ql];
+      for (int k = 0; k < cnt; ++k) {
+        int e = d.acc_ent[ql * kMaxContrib + k];
+        if (((e >> 30) & 1) == 0) continue;
+        acc += st3[(cbb - 1) * 2 * d.nz * NpP + (e & 0x3fffffff)];
+      }
+      acc *= sgn;
+      if ((flags & F_MASK_SURF) && d.is_surf_loc[ql]) acc = 0.0;
+      side[(size_t)b * nl + ql] = acc;
+    }
+  }
+}
+
+// adds the right-line contributions of each block to the stored left lines
+__global__ void k_fixup(const TankDev* __restrict__ td, double* __restrict__ y,
+                        const double* __restrict__ side) {
+  const TankDev& d = *td;
+  int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= d.nb * d.nl) return;
+  int b = gid / d.nl, ql = gid - b * d.nl;
+  // side[b] belongs to the line at x_{c0 + cbb}
+  int c0 = b * d.cb;
+  int cend = min(c0 + d.cb, d.nx);
+  double v = side[(size_t)b * d.nl + ql];
+  if (cend < d.nx) {
+    y[(int64_t)cend * d.nc + ql] += v;
+  } else if (d.periodic) {
+    y[ql] += v;
+  } else {
+    y[(int64_t)d.nx * d.nc + ql] = v;   // the wall line has one contribution
+  }
+}
+
+// ------------------------------------------------------------ vector kernels
+// y = a*x + b*y over [0, n) (optionally masked at surface nodes)
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double bb,
+                        double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + bb * y[i];
+}
+
+__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+__device__ inline bool is_surface_node(const TankDev& d, int64_t i) {
+  int64_t c = i / d.nc;
+  int ql = (int)(i - c * d.nc);
+  return d.is_surf_loc[ql] != 0;  // the wall line shares the line pattern
+}
+
+__global__ void k_mask_surface(const TankDev* __restrict__ td, double* __restrict__ y) {
+  const TankDev& d = *td;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.n && is_surface_node(d, i)) y[i] = 0.0;
+}
+
+// u = 0 except at the surface nodes, where u = phi_s
+__global__ void k_scatter_surface(const TankDev* __restrict__ td, const double* __restrict__ phis,
+                                  double* __restrict__ u, int zero_rest) {
+  const TankDev& d = *td;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  int64_t c = i / d.nc;
+  int ql = (int)(i - c * d.nc);
+  if (d.is_surf_loc[ql]) {
+    int m;
+    if (ql == d.nl - 1) m = 0;
+    else {
+      m = -1;
+      for (int k = 1; k < d.P; ++k)
+        if (d.surf_loc[k] == ql) m = k;
+    }
+    u[i] = phis[c * d.P + m];
+  } else if (zero_rest) {
+    u[i] = 0.0;
+  }
+}
+
+__global__ void k_gather_surface(const TankDev* __restrict__ td, const double* __restrict__ u,
+                                 double* __restrict__ out) {
+  const TankDev& d = *td;
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.ns) return;
+  int c = s / d.P, m = s - c * d.P;
+  out[s] = u[(int64_t)c * d.nc + d.surf_loc[m]];
+}
+
+// partial dot products: part[blk][k] = sum over the chunk of X_k . w
+// X_k = X + k*ldx, k < nvec; chunk = [blk*chunk, (blk+1)*chunk)
+__global__ void __launch_bounds__(kBlockThreads)
+k_dots(int64_t n, int nvec, const double* __restrict__ X, int64_t ldx, const double* __restrict__ w,
+       double* __restrict__ part, int ldp, int64_t chunk) {
+  __shared__ double red[kBlockThreads];
+  int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
+  for (int k = 0; k < nvec; ++k) {
+    const double* x = X + k * ldx;
+    double s = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += x[i] * w[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp + k] = s;
+  }
+}
+
+// out[k] = sum_blk part[blk][k], k < nvec (one workgroup, fixed order)
+__global__ void __launch_bounds__(kBlockThreads)
+k_reduce(int nblk, int nvec, const double* __restrict__ part, int ldp, double* __restrict__ out) {
+  __shared__ double red[kBlockThreads];
+  for (int k = 0; k < nvec; ++k) {
+    double s = 0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[(size_t)i * ldp + k];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[k] = s;
+  }
+}
+
+// ------------------------------------------------------------ GMRES pieces
+// w' = w - sum_{i<=j} h_i V_i  and partial ||w'||^2
+__global__ void __launch_bounds__(kBlockThreads)
+k_orth(int64_t n, int j, const double* __restrict__ V, const double* __restrict__ hcol,
+       double* __restrict__ w, double* __restrict__ part, int ldp, int64_t chunk,
+       const KrylovState* __restrict__ ks) {
+  __shared__ double red[kBlockThreads];
+  if (ks->done) return;
+  int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
+  double s = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double v = w[i];
+    for (int k = 0; k <= j; ++k) v -= hcol[k] * V[(int64_t)k * n + i];
+    w[i] = v;
+    s += v * v;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp] = s;
+}
+
+// Givens update of column j (single thread).  H column j holds h_{0..j},
+// hnext = ||w'||^2 reduced.  Sets done/converged, V_{j+1} scale.
+__global__ void k_givens(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m, int j,
+                         const double* __restrict__ hnorm2, int32_t* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (ks->done) return;
+  double* H = Hbase;                       // (m+1) x m, column-major: H[i + j*(m+1)]
+  double* cs = Hbase + (m + 1) * m;
+  double* sn = cs + m;
+  double* g = sn + m;
+  double* col = H + (size_t)j * (m + 1);
+  double hn = sqrt(fmax(hnorm2[0], 0.0));
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  double den = hypot(col[j], col[j + 1]);
+  if (!(den > 0.0) || !finite(den)) {
+    atomicOr(status, finite(den) ? ST_BREAKDOWN : ST_NONFINITE);
+    ks->done = 1;
+    ks->status |= finite(den) ? ST_BREAKDOWN : ST_NONFINITE;
+    return;
+  }
+  cs[j] = col[j] / den;
+  sn[j] = col[j + 1] / den;
+  col[j] = den;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  ks->j = j + 1;
+  ks->iters += 1;
+  ks->resid = fabs(g[j + 1]);
+  if (ks->resid <= ks->rtol * ks->bnorm) {
+    ks->converged = 1;
+    ks->done = 1;
+  } else if (j + 1 >= m) {
+    ks->done = 1;
+  }
+  // store the normalisation of V_{j+1}
+  g[m + 1 + j] = hn;  // y[] area reused as scratch for the norms
+}
+
+// V_{j+1} = w' / hn
+__global__ void k_scale_next(int64_t n, int j, const double* __restrict__ w, double* __restrict__ V,
+                             const double* __restrict__ Hbase, int m, const KrylovState* __restrict__ ks) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (ks->converged) return;
+  const double* g = Hbase + (m + 1) * m + 2 * m;
+  double hn = g[m + 1 + j];
+  if (j + 1 < m + 1) V[(int64_t)(j + 1) * n + i] = (hn > 0.0) ? w[i] / hn : 0.0;
+}
+
+// solve the triangular system for y (single thread) then x += Z y (all threads)
+__global__ void k_solve_y(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int jn = ks->j;
+  double* H = Hbase;
+  double* g = Hbase + (m + 1) * m + 2 * m;
+  double* y = g + (m + 1) + m;     // after the norm scratch
+  for (int i = jn - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int k = i + 1; k < jn; ++k) s -= H[(size_t)k * (m + 1) + i] * y[k];
+    y[i] = s / H[(size_t)i * (m + 1) + i];
+  }
+}
+
+__global__ void k_update_x(int64_t n, const double* __restrict__ Z, const double* __restrict__ Hbase,
+                           int m, const KrylovState* __restrict__ ks, double* __restrict__ x) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* g = Hbase + (m + 1) * m + 2 * m;
+  const double* y = g + (m + 1) + m;
+  int jn = ks->j;
+  double v = x[i];
+  for (int k = 0; k < jn; ++k) v += y[k] * Z[(int64_t)k * n + i];
+  x[i] = v;
+}
+
+// start of a cycle: r is in V_0 (masked); beta = sqrt(rr); V_0 = r/beta; g = (beta, 0, ...)
+__global__ void k_cycle_start(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
+                              const double* __restrict__ rr, int first, int32_t* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double beta = sqrt(fmax(rr[0], 0.0));
+  if (first) {
+    ks->bnorm = sqrt(fmax(rr[1], 0.0));
+    if (ks->bnorm == 0.0) ks->bnorm = beta;  // zero right side: relative to the first residual
+  }
+  if (!finite(beta) || !finite(ks->bnorm)) {
+    atomicOr(status, ST_NONFINITE);
+    ks->status |= ST_NONFINITE;
+    ks->done = 1;
+    ks->converged = 0;
+    return;
+  }
+  ks->beta = beta;
+  ks->resid = beta;
+  ks->j = 0;
+  double* g = Hbase + (m + 1) * m + 2 * m;
+  for (int i = 0; i <= m; ++i) g[i] = 0.0;
+  g[0] = beta;
+  if (beta <= ks->rtol * ks->bnorm) {
+    ks->converged = 1;
+    ks->done = 1;
+  } else {
+    ks->done = 0;
+  }
+}
+
+__global__ void k_scale_v0(int64_t n, double* __restrict__ V, const KrylovState* __restrict__ ks) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || ks->done) return;
+  V[i] = V[i] / ks->beta;
+}
+
+// r = b - y (masked at the surface for the Laplace problem)
+__global__ void k_residual(const TankDev* __restrict__ td, int64_t n, const double* __restrict__ bvec,
+                           const double* __restrict__ y, double* __restrict__ r, int mask) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = bvec[i] - y[i];
+  if (mask && is_surface_node(*td, i)) v = 0.0;
+  r[i] = v;
+}
+
+// ------------------------------------------------------------ 1D surface work
+// One workgroup per tank.  1D element e (column) holds surface nodes
+// e*P + k, k = 0..P (wrapped when periodic).
+__device__ inline int s_index(const TankDev& d, int e, int k) {
+  int s = e * d.P + k;
+  return s >= d.ns ? s - d.ns : s;
+}
+
+// y = sum_e R_e^T (scale * A_e) u_e with A_e one of the (P+1)^2 matrices,
+// gathered per node in a fixed order (the node's left element first).
+template <int P>
+__device__ void s_apply(const TankDev& d, const double* A, double scale, const double* u, double* y) {
+  for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
+    int e = s / P, k = s - e * P;
+    double acc = 0;
+    // element e with local index k (k < P), and for k == 0 element e-1 with local P
+    if (e < d.nx) {
+      for (int q = 0; q <= P; ++q) acc += A[k * (P + 1) + q] * u[s_index(d, e, q)];
+    }
+    if (k == 0) {
+      int ep = e - 1;
+      if (ep < 0 && d.periodic) ep = d.nx - 1;
+      if (ep >= 0) {
+        double a2 = 0;
+        for (int q = 0; q <= P; ++q) a2 += A[P * (P + 1) + q] * u[s_index(d, ep, q)];
+        acc += a2;
+      }
+    }
+    y[s] = scale * acc;
+  }
+}
+
+template <int P>
+__device__ void s_precond(const TankDev& d, const double* r, double* z) {
+  // element-block Jacobi of M': classes 0 first, 1 interior, 2 last (walls)
+  for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
+    int e = s / P, k = s - e * P;
+    double acc = 0;
+    auto cls = [&](int ee) {
+      if (d.periodic) return 1;
+      if (d.nx == 1) return 0;
+      return ee == 0 ? 0 : (ee == d.nx - 1 ? 2 : 1);
+    };
+    if (e < d.nx) {
+      const double* C = d.pre1d + cls(e) * (P + 1) * (P + 1);
+      for (int q = 0; q <= P; ++q) acc += C[k * (P + 1) + q] * r[s_index(d, e, q)];
+    }
+    if (k == 0) {
+      int ep = e - 1;
+      if (ep < 0 && d.periodic) ep = d.nx - 1;
+      if (ep >= 0) {
+        const double* C = d.pre1d + cls(ep) * (P + 1) * (P + 1);
+        double a2 = 0;
+        for (int q = 0; q <= P; ++q) a2 += C[P * (P + 1) + q] * r[s_index(d, ep, q)];
+        acc += a2;
+      }
+    }
+    z[s] = acc;
+  }
+}
+
+__device__ inline double s_dot(const TankDev& d, const double* a, const double* b, double* red) {
+  double s = 0;
+  for (int i = threadIdx.x; i < d.ns; i += blockDim.x) s += a[i] * b[i];
+  return block_sum(s, red);
+}
+
+// PCG for M' x = rhs (x holds the initial guess); work arrays r, z, p, q
+template <int P>
+__device__ int s_mass_solve(const TankDev& d, const double* rhs, double* x, double* r, double* z,
+                            double* p, double* q, double* red) {
+  const double J = 0.5 * d.dX;
+  s_apply<P>(d, d.M1, J, x, q);
+  __syncthreads();
+  for (int i = threadIdx.x; i < d.ns; i += blockDim.x) r[i] = rhs[i] - q[i];
+  __syncthreads();
+  double bn = sqrt(s_dot(d, rhs, rhs, red));
+  s_precond<P>(d, r, z);
+  __syncthreads();
+  for (int i = threadIdx.x; i < d.ns; i += blockDim.x) p[i] = z[i];
+  __syncthreads();
+  double rz = s_dot(d, r, z, red);
+  int it = 0;
+  const double tol = 1e-15 * (bn > 0 ? bn : 1.0);
+  for (; it < 500; ++it) {
+    double rn = sqrt(s_dot(d, r, r, red));
+    if (rn <= tol) break;
+    s_apply<P>(d, d.M1, J, p, q);
+    __syncthreads();
+    double alpha = rz / s_dot(d, p, q, red);
+    for (int i = threadIdx.x; i < d.ns; i += blockDim.x) {
+      x[i] += alpha * p[i];
+      r[i] -= alpha * q[i];
+    }
+    __syncthreads();
+    s_precond<P>(d, r, z);
+    __syncthreads();
+    double rzn = s_dot(d, r, z, red);
+    double beta = rzn / rz;
+    rz = rzn;
+    for (int i = threadIdx.x; i < d.ns; i += blockDim.x) p[i] = z[i] + beta * p[i];
+    __syncthreads();
+  }
+  return it;
+}
+
+// f_x from M' f_x = S_x f for up to two fields (in0 -> out0, in1 -> out1)
+template <int P>
+__global__ void __launch_bounds__(kBlockThreads)
+k_recover_dx(const TankDev* __restrict__ td, const double* __restrict__ in0, double* __restrict__ out0,
+             const double* __restrict__ in1, double* __restrict__ out1) {
+  const TankDev& d = *td;
+  __shared__ double red[kBlockThreads];
+  double* rhs = d.s1d;
+  double* r = d.s1d + 1 * (size_t)d.ns;
+  double* z = d.s1d + 2 * (size_t)d.ns;
+  double* p = d.s1d + 3 * (size_t)d.ns;
+  double* q = d.s1d + 4 * (size_t)d.ns;
+  for (int f = 0; f < 2; ++f) {
+    const double* in = f == 0 ? in0 : in1;
+    double* out = f == 0 ? out0 : out1;
+    if (!in) continue;
+    s_apply<P>(d, d.S1, 1.0, in, rhs);
+    __syncthreads();
+    for (int i = threadIdx.x; i < d.ns; i += blockDim.x) out[i] = 0.0;
+    __syncthreads();
+    s_mass_solve<P>(d, rhs, out, r, z, p, q, red);
+    __syncthreads();
+  }
+}
+
+// Over-integrated free-surface right-hand sides (Secs. 3.1.1, 3.3), then M' solves.
+template <int P>
+__global__ void __launch_bounds__(kBlockThreads)
+k_fs_rhs(const TankDev* __restrict__ td, const double* __restrict__ eta, const double* __restrict__ etax,
+         const double* __restrict__ phix, const double* __restrict__ ws, double* __restrict__ eta_t,
+         double* __restrict__ phi_t) {
+  const TankDev& d = *td;
+  __shared__ double red[kBlockThreads];
+  const int Pf = d.Pf, nf = Pf + 1;
+  double* loc = d.s1d + 5 * (size_t)d.ns;    // [nx][P+1][2] element contributions (needs 2(P+1)nx <= 6 ns)
+  double* rhs_e = d.s1d + 11 * (size_t)d.ns;
+  double* rhs_p = d.s1d + 12 * (size_t)d.ns;
+  double* r = d.s1d + 1 * (size_t)d.ns;
+  double* z = d.s1d + 2 * (size_t)d.ns;
+  double* p = d.s1d + 3 * (size_t)d.ns;
+  double* q = d.s1d + 4 * (size_t)d.ns;
+  const double J = 0.5 * d.dX;
+  // thread per (element, coarse node i): RHS_i = J sum_a I[a][i] sum_b Mf[a][b] F[b]
+  for (int it = threadIdx.x; it < d.nx * (P + 1); it += blockDim.x) {
+    int e = it / (P + 1), i = it - e * (P + 1);
+    double acc_e = 0, acc_p = 0;
+    for (int a = 0; a < nf; ++a) {
+      if (d.Ifine[a * (P + 1) + i] == 0.0) continue;
+      double se = 0, sp = 0;
+      for (int bq = 0; bq < nf; ++bq) {
+        double et = 0, ex = 0, px = 0, ww = 0;
+        for (int k = 0; k <= P; ++k) {
+          double Ik = d.Ifine[bq * (P + 1) + k];
+          int s = s_index(d, e, k);
+          et += Ik * eta[s];
+          ex += Ik * etax[s];
+          px += Ik * phix[s];
+          ww += Ik * ws[s];
+        }
+        double fe = -ex * px + ww * (1.0 + ex * ex);
+        double fp = -d.g * et - 0.5 * (px * px - ww * ww * (1.0 + ex * ex));
+        double mf = d.Mfine[a * nf + bq];
+        se += mf * fe;
+        sp += mf * fp;
+      }
+      acc_e += d.Ifine[a * (P + 1) + i] * se;
+      acc_p += d.Ifine[a * (P + 1) + i] * sp;
+    }
+    loc[(size_t)it * 2 + 0] = J * acc_e;
+    loc[(size_t)it * 2 + 1] = J * acc_p;
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
+    int e = s / P, k = s - e * P;
+    double ae = 0, ap = 0;
+    if (e < d.nx) {
+      ae = loc[((size_t)e * (P + 1) + k) * 2 + 0];
+      ap = loc[((size_t)e * (P + 1) + k) * 2 + 1];
+    }
+    if (k == 0) {
+      int ep = e - 1;
+      if (ep < 0 && d.periodic) ep = d.nx - 1;
+      if (ep >= 0) {
+        ae += loc[((size_t)ep * (P + 1) + P) * 2 + 0];
+        ap += loc[((size_t)ep * (P + 1) + P) * 2 + 1];
+      }
+    }
+    rhs_e[s] = ae;
+    rhs_p[s] = ap;
+    eta_t[s] = 0.0;
+    phi_t[s] = 0.0;
+  }
+  __syncthreads();
+  s_mass_solve<P>(d, rhs_e, eta_t, r, z, p, q, red);
+  __syncthreads();
+  s_mass_solve<P>(d, rhs_p, phi_t, r, z, p, q, red);
+}
+
+// ------------------------------------------------------------ RK4 + filter
+// stage: ye = y0e + a*dt*ke, yp = y0p + a*dt*kp ; acc += w * k
+__global__ void k_rk4_stage(int ns, double adt, double wgt, int first, const double* __restrict__ y0e,
+                            const double* __restrict__ y0p, const double* __restrict__ ke,
+                            const double* __restrict__ kp, double* __restrict__ ye, double* __restrict__ yp,
+                            double* __restrict__ acce, double* __restrict__ accp) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  double a = ke[s], bq = kp[s];
+  acce[s] = (first ? 0.0 : acce[s]) + wgt * a;
+  accp[s] = (first ? 0.0 : accp[s]) + wgt * bq;
+  ye[s] = y0e[s] + adt * a;
+  yp[s] = y0p[s] + adt * bq;
+}
+
+// y = y0 + dt*acc, then the element filter on interior nodes; writes the
+// caller's arrays only when the status word is clean (transactional step).
+template <int P>
+__global__ void __launch_bounds__(kBlockThreads)
+k_rk4_final(const TankDev* __restrict__ td, double dt, const double* __restrict__ acce,
+            const double* __restrict__ accp, double* __restrict__ eta, double* __restrict__ phi,
+            int use_filter) {
+  const TankDev& d = *td;
+  double* ne = d.s1d + 13 * (size_t)d.ns;
+  double* np_ = d.s1d + 14 * (size_t)d.ns;
+  for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
+    ne[s] = eta[s] + dt * acce[s];
+    np_[s] = phi[s] + dt * accp[s];
+  }
+  __syncthreads();
+  // filtered values into the scratch pair, then a block-wide validity check,
+  // then the write-back (all or nothing)
+  double* fe = d.s1d + 15 * (size_t)d.ns;
+  double* fp = d.s1d + 11 * (size_t)d.ns;
+  __shared__ double red[kBlockThreads];
+  double bad = 0.0;
+  for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
+    double ve = ne[s], vp = np_[s];
+    int e = s / P, k = s - e * P;
+    if (use_filter && k > 0) {
+      ve = 0;
+      vp = 0;
+      for (int q = 0; q <= P; ++q) {
+        double f = d.Filt[k * (P + 1) + q];
+        ve += f * ne[s_index(d, e, q)];
+        vp += f * np_[s_index(d, e, q)];
+      }
+    }
+    if (!finite(ve) || !finite(vp)) bad = 1.0;
+    fe[s] = ve;
+    fp[s] = vp;
+  }
+  bad = block_sum(bad, red);
+  if (bad > 0.0) {
+    if (threadIdx.x == 0) atomicOr(d.status, ST_NONFINITE);
+    return;
+  }
+  if (*d.status != 0) return;
+  for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
+    eta[s] = fe[s];
+    phi[s] = fp[s];
+  }
+}
+
+// ------------------------------------------------------------ launchers
+#define SEM_P_CASE(V, ...) \
+  case V: {                \
+    constexpr int PP = V;  \
+    __VA_ARGS__;           \
+  } break;
+#define SEM_P_SWITCH(P, ...)              \
+  switch (P) {                            \
+    SEM_P_CASE(1, __VA_ARGS__)            \
+    SEM_P_CASE(2, __VA_ARGS__)            \
+    SEM_P_CASE(3, __VA_ARGS__)            \
+    SEM_P_CASE(4, __VA_ARGS__)            \
+    SEM_P_CASE(5, __VA_ARGS__)            \
+    SEM_P_CASE(6, __VA_ARGS__)            \
+    SEM_P_CASE(7, __VA_ARGS__)            \
+    SEM_P_CASE(8, __VA_ARGS__)            \
+    default: break;                       \
+  }
+
+static inline unsigned nblk(int64_t n, int t = kBlockThreads) { return (unsigned)((n + t - 1) / t); }
+
+size_t gather_lds_bytes(const TankDev& h) {
+  return sizeof(double) * ((size_t)h.cb * h.nc + h.nl + 3 * (size_t)h.EB * h.NpP);
+}
+
+void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const double* etax, int what,
+                 hipStream_t st) {
+  int64_t total = (int64_t)h.nx * 2 * h.nz * h.Np;
+  SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_coef<PP>, dim3(nblk(total)), dim3(kBlockThreads), 0, st, d, eta, etax, what));
+}
+
+void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side,
+                   int flags, hipStream_t st) {
+  size_t lds = gather_lds_bytes(h);
+  dim3 g(h.nb), b(kBlockThreads);
+#define SEM_G(OPV) SEM_P_SWITCH(h.P, hipLaunchKernelGGL((k_gather<PP, OPV>), g, b, lds, st, d, u, y, side, flags))
+  switch (op) {
+    case OP_STIFF: SEM_G(OP_STIFF); break;
+    case OP_MASS: SEM_G(OP_MASS); break;
+    case OP_PRE_LAP: SEM_G(OP_PRE_LAP); break;
+    case OP_PRE_MASS: SEM_G(OP_PRE_MASS); break;
+    case OP_SZ: SEM_G(OP_SZ); break;
+  }
+#undef SEM_G
+  hipLaunchKernelGGL(k_fixup, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side);
+}
+
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, a, x, b, y);
+}
+void launch_fill(int64_t n, double v, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, v, y);
+}
+void launch_mask_surface(const TankDev& h, const TankDev* d, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_mask_surface, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, y);
+}
+void launch_scatter_surface(const TankDev& h, const TankDev* d, const double* phis, double* u, int zero_rest,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_surface, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, phis, u, zero_rest);
+}
+void launch_gather_surface(const TankDev& h, const TankDev* d, const double* u, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_surface, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, u, out);
+}
+
+// chunking of [0, n) for deterministic partial reductions
+void dot_layout(int64_t n, int* nchunk, int64_t* chunk) {
+  int64_t c = 4096;
+  int64_t k = (n + c - 1) / c;
+  if (k > 1024) {
+    k = 1024;
+    c = (n + k - 1) / k;
+  }
+  if (k < 1) k = 1;
+  *nchunk = (int)k;
+  *chunk = c;
+}
+
+void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
+                 double* out, hipStream_t st) {
+  int nc;
+  int64_t chunk;
+  dot_layout(n, &nc, &chunk);
+  hipLaunchKernelGGL(k_dots, dim3(nc), dim3(kBlockThreads), 0, st, n, nvec, X, ldx, w, part, ldp, chunk);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlockThreads), 0, st, nc, nvec, part, ldp, out);
+}
+
+void launch_orth(int64_t n, int j, const double* V, const double* hcol, double* w, double* part, int ldp,
+                 double* out, const KrylovState* ks, hipStream_t st) {
+  int nc;
+  int64_t chunk;
+  dot_layout(n, &nc, &chunk);
+  hipLaunchKernelGGL(k_orth, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, hcol, w, part, ldp, chunk, ks);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlockThreads), 0, st, nc, 1, part, ldp, out);
+}
+
+void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, ks, H, m, j, hn2, status);
+}
+void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m,
+                       const KrylovState* ks, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_next, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, j, w, V, H, m, ks);
+}
+void launch_solve_update(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, ks, H, m);
+  hipLaunchKernelGGL(k_update_x, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
+}
+void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status,
+                        int64_t n, double* V, hipStream_t st) {
+  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status);
+  hipLaunchKernelGGL(k_scale_v0, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, V, ks);
+}
+void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
+                     int mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual, dim3(nblk(n)), dim3(kBlockThreads), 0, st, d, n, b, y, r, mask);
+}
+
+void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, double* out0, const double* in1,
+                       double* out1, hipStream_t st) {
+  SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_recover_dx<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, in0, out0, in1, out1));
+}
+void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const double* etax, const double* phix,
+                   const double* ws, double* et, double* pt, hipStream_t st) {
+  SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_fs_rhs<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, eta, etax, phix, ws, et, pt));
+}
+void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,
+                      const double* ke, const double* kp, double* ye, double* yp, double* acce, double* accp,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_rk4_stage, dim3(nblk(ns)), dim3(kBlockThreads), 0, st, ns, adt, wgt, first, y0e, y0p, ke, kp,
+                     ye, yp, acce, accp);
+}
+void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const double* acce, const double* accp,
+                      double* eta, double* phi, int use_filter, hipStream_t st) {
+  SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_rk4_final<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, dt, acce, accp, eta, phi, use_filter));
+}
+
+}  // namespace sem

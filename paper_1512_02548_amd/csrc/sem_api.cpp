@@ -1,0 +1,1005 @@
+// C ABI of the library (include/sem.h): host-side mesh construction, workspace
+// layout, and the drivers that sequence the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+#include "host_refelem.hpp"
+#include "sem_internal.hpp"
+
+namespace sem {
+// kernel launchers (kernels.hip)
+size_t gather_lds_bytes(const TankDev& h);
+void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const double* etax, int what, hipStream_t st);
+void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side, int flags,
+                   hipStream_t st);
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
+void launch_fill(int64_t n, double v, double* y, hipStream_t st);
+void launch_mask_surface(const TankDev& h, const TankDev* d, double* y, hipStream_t st);
+void launch_scatter_surface(const TankDev& h, const TankDev* d, const double* phis, double* u, int zero_rest,
+                            hipStream_t st);
+void launch_gather_surface(const TankDev& h, const TankDev* d, const double* u, double* out, hipStream_t st);
+void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
+                 double* out, hipStream_t st);
+void launch_orth(int64_t n, int j, const double* V, const double* hcol, double* w, double* part, int ldp,
+                 double* out, const KrylovState* ks, hipStream_t st);
+void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, int32_t* status, hipStream_t st);
+void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m,
+                       const KrylovState* ks, hipStream_t st);
+void launch_solve_update(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x,
+                         hipStream_t st);
+void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status,
+                        int64_t n, double* V, hipStream_t st);
+void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
+                     int mask, hipStream_t st);
+void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, double* out0, const double* in1,
+                       double* out1, hipStream_t st);
+void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const double* etax, const double* phix,
+                   const double* ws, double* et, double* pt, hipStream_t st);
+void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,
+                      const double* ke, const double* kp, double* ye, double* yp, double* acce, double* accp,
+                      hipStream_t st);
+void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const double* acce, const double* accp,
+                      double* eta, double* phi, int use_filter, hipStream_t st);
+void dot_layout(int64_t n, int* nchunk, int64_t* chunk);
+}  // namespace sem
+
+using namespace sem;
+
+// ------------------------------------------------------------ error state
+static thread_local std::string g_err;
+static sem_status fail(sem_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+extern "C" const char* sem_last_error(void) { return g_err.c_str(); }
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) return fail(SEM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------ mesh object
+struct Upload {
+  size_t off;
+  std::vector<char> data;
+};
+
+struct sem_mesh {
+  // description
+  int nx = 0, nz = 0, P = 0, periodic = 1, Pf = 0, ic = 2, m = 30;
+  double L = 0, g = 9.81, sf = 1.0;
+  std::vector<double> h, hx, slev;
+  // derived sizes
+  int Np = 0, NpP = 0, nl = 0, nc = 0, cb = 1, nb = 1, T = 1, EB = 0, nclass_col = 1;
+  int64_t n = 0, ns = 0, E = 0;
+  // host tables
+  std::vector<int32_t> elem_loc, acc_cnt, acc_ent, surf_loc, is_surf_loc;
+  std::vector<double> node_x, node_sig;
+  std::vector<int64_t> surf_nodes;
+  // layout
+  size_t ws_bytes = 0;
+  std::vector<Upload> uploads;
+  TankDev hd{};             // device pointers filled at bind (offsets before)
+  char* ws = nullptr;
+  TankDev* dtank = nullptr;
+  double* scal = nullptr;   // small device scalars
+  bool bound = false;
+  // offsets of dynamic arrays
+  std::map<std::string, size_t> off;
+  // RK4 scratch (surface arrays)
+  double *rk = nullptr;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <class T>
+static size_t put(sem_mesh* M, const char* name, const std::vector<T>& v) {
+  size_t o = M->ws_bytes;
+  Upload u;
+  u.off = o;
+  u.data.resize(v.size() * sizeof(T));
+  if (!v.empty()) std::memcpy(u.data.data(), v.data(), u.data.size());
+  M->uploads.push_back(std::move(u));
+  M->off[name] = o;
+  M->ws_bytes = align256(o + v.size() * sizeof(T));
+  return o;
+}
+
+static size_t reserve(sem_mesh* M, const char* name, size_t bytes) {
+  size_t o = M->ws_bytes;
+  M->off[name] = o;
+  M->ws_bytes = align256(o + bytes);
+  return o;
+}
+
+// pad an Np x Np matrix to NpP x NpP
+static std::vector<double> pad(const Mat& A, int Np, int NpP) {
+  std::vector<double> out((size_t)NpP * NpP, 0.0);
+  for (int i = 0; i < Np; ++i)
+    for (int j = 0; j < Np; ++j) out[(size_t)i * NpP + j] = A[(size_t)i * Np + j];
+  return out;
+}
+static std::vector<float> tof(const std::vector<double>& v) {
+  std::vector<float> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+  return o;
+}
+
+// Build column template, tables, preconditioner blocks and the workspace layout.
+static sem_status build_mesh(sem_mesh* M) {
+  const int P = M->P, nz = M->nz, nx = M->nx;
+  RefTri ref(P);
+  Ref1D r1(P);
+  M->Np = ref.Np;
+  M->NpP = (ref.Np + 15) / 16 * 16;
+  const int Np = M->Np, NpP = M->NpP;
+  M->nl = P * nz + 1;
+  M->nc = P * M->nl;
+  const int nl = M->nl, nc = M->nc;
+  M->n = (int64_t)nx * nc + (M->periodic ? 0 : nl);
+  M->ns = (int64_t)nx * P + (M->periodic ? 0 : 1);
+  M->E = (int64_t)2 * nx * nz;
+  const double dX = M->L / nx;
+  std::vector<double> sl(nz + 1);
+  if (M->slev.empty())
+    for (int j = 0; j <= nz; ++j) sl[j] = double(j) / nz;
+  else
+    sl = M->slev;
+
+  // reference-node positions in the unit quad per triangle type:
+  // lower (t=0): A=(0,0) B=(1,0) C=(1,1); upper (t=1): A=(0,0) B=(1,1) C=(0,1)
+  std::vector<double> nodeq((size_t)2 * NpP * 2, 0.0);
+  for (int t = 0; t < 2; ++t)
+    for (int k = 0; k < Np; ++k) {
+      double a = 0.5 * (1 + ref.r[k]), bb = 0.5 * (1 + ref.s[k]);
+      double xi = t == 0 ? a + bb : a;
+      double ze = t == 0 ? bb : a + bb;
+      nodeq[((size_t)t * NpP + k) * 2 + 0] = xi;
+      nodeq[((size_t)t * NpP + k) * 2 + 1] = ze;
+    }
+  // column-local numbering: left line by sigma, then interior in first-appearance order
+  const double tol = 1e-9;
+  std::vector<double> line_sig;
+  for (int j = 0; j < nz; ++j)
+    for (int t = 0; t < 2; ++t)
+      for (int k = 0; k < Np; ++k) {
+        double xi = nodeq[((size_t)t * NpP + k) * 2], ze = nodeq[((size_t)t * NpP + k) * 2 + 1];
+        if (std::fabs(xi) < tol) line_sig.push_back(sl[j] + ze * (sl[j + 1] - sl[j]));
+      }
+  std::sort(line_sig.begin(), line_sig.end());
+  std::vector<double> uniq;
+  for (double v : line_sig)
+    if (uniq.empty() || std::fabs(v - uniq.back()) > tol) uniq.push_back(v);
+  if ((int)uniq.size() != nl) return fail(SEM_E_INVAL, "column template: unexpected line node count");
+  auto line_index = [&](double sg) {
+    for (int q = 0; q < nl; ++q)
+      if (std::fabs(uniq[q] - sg) < tol) return q;
+    return -1;
+  };
+  struct IP { double xi, sg; };
+  std::vector<IP> interior;
+  M->elem_loc.assign((size_t)2 * nz * NpP, -1);
+  for (int j = 0; j < nz; ++j)
+    for (int t = 0; t < 2; ++t)
+      for (int k = 0; k < Np; ++k) {
+        double xi = nodeq[((size_t)t * NpP + k) * 2], ze = nodeq[((size_t)t * NpP + k) * 2 + 1];
+        double sg = sl[j] + ze * (sl[j + 1] - sl[j]);
+        int loc;
+        if (std::fabs(xi) < tol) loc = line_index(sg);
+        else if (std::fabs(xi - 1.0) < tol) loc = nc + line_index(sg);
+        else {
+          loc = -1;
+          for (size_t q = 0; q < interior.size(); ++q)
+            if (std::fabs(interior[q].xi - xi) < tol && std::fabs(interior[q].sg - sg) < tol) loc = nl + (int)q;
+          if (loc < 0) {
+            interior.push_back({xi, sg});
+            loc = nl + (int)interior.size() - 1;
+          }
+        }
+        if (loc < 0) return fail(SEM_E_INVAL, "column template: node identification failed");
+        M->elem_loc[(size_t)(j * 2 + t) * NpP + k] = loc;
+      }
+  if ((int)interior.size() + nl != nc) return fail(SEM_E_INVAL, "column template: unexpected interior count");
+  // column-local coordinates
+  std::vector<double> cx(nc + nl), cs(nc + nl);
+  for (int q = 0; q < nl; ++q) {
+    cx[q] = 0.0;
+    cs[q] = uniq[q];
+    cx[nc + q] = 1.0;
+    cs[nc + q] = uniq[q];
+  }
+  for (size_t q = 0; q < interior.size(); ++q) {
+    cx[nl + q] = interior[q].xi;
+    cs[nl + q] = interior[q].sg;
+  }
+  M->is_surf_loc.assign(nc + nl, 0);
+  for (int q = 0; q < nc + nl; ++q) M->is_surf_loc[q] = std::fabs(cs[q] - 1.0) < tol ? 1 : 0;
+  // surface nodes of a column, ordered by x: left-line top first
+  std::vector<std::pair<double, int>> sv;
+  for (int q = 0; q < nc; ++q)
+    if (M->is_surf_loc[q]) sv.push_back({cx[q], q});
+  std::sort(sv.begin(), sv.end());
+  if ((int)sv.size() != P) return fail(SEM_E_INVAL, "column template: surface count");
+  M->surf_loc.resize(P);
+  for (int k = 0; k < P; ++k) M->surf_loc[k] = sv[k].second;
+  // accumulation table: contributions to column-local node q < nc
+  M->acc_cnt.assign(nc, 0);
+  M->acc_ent.assign((size_t)nc * kMaxContrib, 0);
+  auto add = [&](int q, int code) -> bool {
+    if (M->acc_cnt[q] >= kMaxContrib) return false;
+    M->acc_ent[(size_t)q * kMaxContrib + M->acc_cnt[q]++] = code;
+    return true;
+  };
+  for (int q = 0; q < nc; ++q) {
+    for (int e = 0; e < 2 * nz; ++e)
+      for (int k = 0; k < Np; ++k)
+        if (M->elem_loc[(size_t)e * NpP + k] == q && !add(q, e * NpP + k))
+          return fail(SEM_E_INVAL, "accumulation table overflow");
+    if (q < nl)
+      for (int e = 0; e < 2 * nz; ++e)
+        for (int k = 0; k < Np; ++k)
+          if (M->elem_loc[(size_t)e * NpP + k] == nc + q && !add(q, (1 << 30) | (e * NpP + k)))
+            return fail(SEM_E_INVAL, "accumulation table overflow");
+  }
+  // global coordinates
+  M->node_x.assign(M->n, 0.0);
+  M->node_sig.assign(M->n, 0.0);
+  for (int c = 0; c < nx; ++c)
+    for (int q = 0; q < nc; ++q) {
+      M->node_x[(size_t)c * nc + q] = (c + cx[q]) * dX;
+      M->node_sig[(size_t)c * nc + q] = cs[q];
+    }
+  if (!M->periodic)
+    for (int q = 0; q < nl; ++q) {
+      M->node_x[(size_t)nx * nc + q] = M->L;
+      M->node_sig[(size_t)nx * nc + q] = cs[q];
+    }
+  M->surf_nodes.resize(M->ns);
+  for (int c = 0; c < nx; ++c)
+    for (int k = 0; k < P; ++k) M->surf_nodes[(size_t)c * P + k] = (int64_t)c * nc + M->surf_loc[k];
+  if (!M->periodic) M->surf_nodes[M->ns - 1] = (int64_t)nx * nc + nl - 1;
+
+  // per-layer geometry: Lam = d(r,s)/d(x,sigma), J
+  std::vector<double> lay((size_t)2 * nz * 8, 0.0);
+  for (int j = 0; j < nz; ++j) {
+    double ds = sl[j + 1] - sl[j];
+    for (int t = 0; t < 2; ++t) {
+      // d(x,sig)/d(r,s) = [[(B-A)/2, (C-A)/2]] in physical units
+      double bx = dX, bs = t == 0 ? 0.0 : ds;      // B - A
+      double cxv = t == 0 ? dX : 0.0, csv = ds;    // C - A
+      double a00 = bx / 2, a01 = cxv / 2, a10 = bs / 2, a11 = csv / 2;
+      double det = a00 * a11 - a01 * a10;
+      double* L = &lay[(size_t)(j * 2 + t) * 8];
+      L[0] = a11 / det;   // dr/dx
+      L[1] = -a01 / det;  // dr/dsig
+      L[2] = -a10 / det;  // ds/dx
+      L[3] = a00 / det;   // ds/dsig
+      L[4] = det;         // |J|
+      L[5] = sl[j];
+      L[6] = ds;
+    }
+  }
+  // column interpolation weights
+  std::vector<double> colw((size_t)2 * NpP * (P + 1), 0.0);
+  for (int t = 0; t < 2; ++t)
+    for (int k = 0; k < Np; ++k) {
+      Mat I = r1.interp_to({2.0 * nodeq[((size_t)t * NpP + k) * 2] - 1.0});
+      for (int q = 0; q <= P; ++q) colw[((size_t)t * NpP + k) * (P + 1) + q] = I[q];
+    }
+  // block decomposition
+  M->cb = std::max(1, (32 + 2 * nz - 1) / (2 * nz));
+  M->cb = std::min(M->cb, nx);
+  M->nb = (nx + M->cb - 1) / M->cb;
+  M->EB = M->cb * 2 * nz;
+  M->T = (M->EB + 15) / 16;
+
+  // ---- preconditioner blocks from the still-water flat-bed operator at the mean depth
+  double h0 = 0;
+  for (double v : M->h) h0 += v;
+  h0 /= (double)M->h.size();
+  M->nclass_col = M->periodic ? 1 : 3;
+  Mat MDr = matmul(ref.M, ref.Dr, Np, Np, Np), MDs = matmul(ref.M, ref.Ds, Np, Np, Np);
+  auto elem_matrix = [&](int jt, bool mass) {
+    const double* L = &lay[(size_t)jt * 8];
+    Mat A((size_t)Np * Np, 0.0);
+    if (mass) {
+      for (size_t i = 0; i < A.size(); ++i) A[i] = L[4] * ref.M[i];
+      return A;
+    }
+    double K00 = h0, K11 = 1.0 / h0;
+    double grr = L[4] * (L[0] * L[0] * K00 + L[1] * L[1] * K11);
+    double grs = L[4] * (L[0] * L[2] * K00 + L[1] * L[3] * K11);
+    double gss = L[4] * (L[2] * L[2] * K00 + L[3] * L[3] * K11);
+    // sum_ab G_ab D_a^T M D_b with constant G
+    Mat DrT = transpose(ref.Dr, Np, Np), DsT = transpose(ref.Ds, Np, Np);
+    Mat t1 = matmul(DrT, MDr, Np, Np, Np), t2 = matmul(DrT, MDs, Np, Np, Np);
+    Mat t3 = matmul(DsT, MDr, Np, Np, Np), t4 = matmul(DsT, MDs, Np, Np, Np);
+    for (size_t i = 0; i < A.size(); ++i) A[i] = grr * t1[i] + grs * (t2[i] + t3[i]) + gss * t4[i];
+    return A;
+  };
+  // global node id of (column c, elem jt, node k)
+  auto gnode = [&](int c, int jt, int k) -> int64_t {
+    int loc = M->elem_loc[(size_t)jt * NpP + k];
+    if (loc < nc) return (int64_t)c * nc + loc;
+    int c2 = c + 1;
+    if (c2 == nx) return M->periodic ? (int64_t)(loc - nc) : (int64_t)nx * nc + (loc - nc);
+    return (int64_t)c2 * nc + (loc - nc);
+  };
+  // multiplicities (elements per node) of one column neighbourhood are enough; compute globally
+  std::vector<int> mult(M->n, 0);
+  for (int c = 0; c < nx; ++c)
+    for (int jt = 0; jt < 2 * nz; ++jt)
+      for (int k = 0; k < Np; ++k) mult[gnode(c, jt, k)]++;
+  auto surf_global = [&](int64_t gi) {
+    int64_t c = gi / nc;
+    return M->is_surf_loc[gi - c * nc] != 0;
+  };
+  const int ncls = M->nclass_col * 2 * nz;
+  std::vector<double> pre_lap((size_t)ncls * NpP * NpP, 0.0), pre_mass((size_t)ncls * NpP * NpP, 0.0);
+  for (int cc = 0; cc < M->nclass_col; ++cc) {
+    int crep = M->periodic ? 0 : (cc == 0 ? 0 : (cc == 2 ? nx - 1 : 1));
+    if (!M->periodic && cc == 1 && nx < 3) continue;
+    if (!M->periodic && cc == 2 && nx < 2) continue;
+    std::set<int> cols;
+    for (int dc = -1; dc <= 1; ++dc) {
+      int c = crep + dc;
+      if (M->periodic) c = ((c % nx) + nx) % nx;
+      else if (c < 0 || c >= nx) continue;
+      cols.insert(c);
+    }
+    for (int mass = 0; mass < 2; ++mass) {
+      // assemble the patch
+      std::map<int64_t, int> lid;
+      for (int c : cols)
+        for (int jt = 0; jt < 2 * nz; ++jt)
+          for (int k = 0; k < Np; ++k) {
+            int64_t gi = gnode(c, jt, k);
+            if (!lid.count(gi)) {
+              int id = (int)lid.size();
+              lid[gi] = id;
+            }
+          }
+      int nloc = (int)lid.size();
+      Mat Ap((size_t)nloc * nloc, 0.0);
+      for (int c : cols)
+        for (int jt = 0; jt < 2 * nz; ++jt) {
+          Mat Ae = elem_matrix(jt, mass != 0);
+          for (int a = 0; a < Np; ++a)
+            for (int b = 0; b < Np; ++b)
+              Ap[(size_t)lid[gnode(c, jt, a)] * nloc + lid[gnode(c, jt, b)]] += Ae[(size_t)a * Np + b];
+        }
+      for (int jt = 0; jt < 2 * nz; ++jt) {
+        std::vector<int> keep;
+        for (int k = 0; k < Np; ++k)
+          if (mass || !surf_global(gnode(crep, jt, k))) keep.push_back(k);
+        int nk = (int)keep.size();
+        Mat C((size_t)nk * nk);
+        for (int a = 0; a < nk; ++a)
+          for (int b = 0; b < nk; ++b)
+            C[(size_t)a * nk + b] = Ap[(size_t)lid[gnode(crep, jt, keep[a])] * nloc + lid[gnode(crep, jt, keep[b])]];
+        if (!invert(C, nk)) return fail(SEM_E_INVAL, "singular preconditioner block");
+        std::vector<double>& dst = mass ? pre_mass : pre_lap;
+        double* blk = &dst[(size_t)(cc * 2 * nz + jt) * NpP * NpP];
+        for (int a = 0; a < nk; ++a)
+          for (int b = 0; b < nk; ++b) {
+            double wa = 1.0 / std::sqrt((double)mult[gnode(crep, jt, keep[a])]);
+            double wb = 1.0 / std::sqrt((double)mult[gnode(crep, jt, keep[b])]);
+            blk[(size_t)keep[a] * NpP + keep[b]] = wa * C[(size_t)a * nk + b] * wb;
+          }
+      }
+    }
+  }
+  // ---- 1D operators
+  const int P1 = P + 1;
+  Mat S1 = matmul(r1.M, r1.D, P1, P1, P1);
+  Ref1D rf(M->Pf);
+  Mat If = r1.interp_to(rf.r);
+  Mat Filt = filter_matrix(P, M->ic, M->sf);
+  // 1D block Jacobi of M' (classes: first, interior, last)
+  std::vector<double> pre1d((size_t)3 * P1 * P1, 0.0);
+  for (int cls = 0; cls < 3; ++cls) {
+    bool left_shared = M->periodic || cls != 0;
+    bool right_shared = M->periodic || cls != 2;
+    if (!M->periodic && nx == 1) left_shared = right_shared = false;
+    Mat C((size_t)P1 * P1);
+    for (int i = 0; i < P1 * P1; ++i) C[i] = 0.5 * dX * r1.M[i];
+    if (left_shared) C[0] += 0.5 * dX * r1.M[(size_t)P * P1 + P];
+    if (right_shared) C[(size_t)P * P1 + P] += 0.5 * dX * r1.M[0];
+    if (!invert(C, P1)) return fail(SEM_E_INVAL, "singular 1D block");
+    std::vector<double> w(P1, 1.0);
+    if (left_shared) w[0] = 1.0 / std::sqrt(2.0);
+    if (right_shared) w[P] = 1.0 / std::sqrt(2.0);
+    for (int a = 0; a < P1; ++a)
+      for (int b = 0; b < P1; ++b) pre1d[(size_t)cls * P1 * P1 + a * P1 + b] = w[a] * C[(size_t)a * P1 + b] * w[b];
+  }
+
+  // ---- workspace layout: constants
+  M->ws_bytes = 0;
+  M->uploads.clear();
+  reserve(M, "tank", sizeof(TankDev));
+  reserve(M, "scal", 64 * sizeof(double));
+  std::vector<double> Drp = pad(ref.Dr, Np, NpP), Dsp = pad(ref.Ds, Np, NpP);
+  std::vector<double> MDrp = pad(MDr, Np, NpP), MDsp = pad(MDs, Np, NpP), Mp = pad(ref.M, Np, NpP);
+  put(M, "Dr", Drp);
+  put(M, "Ds", Dsp);
+  put(M, "MDr", MDrp);
+  put(M, "MDs", MDsp);
+  put(M, "M", Mp);
+  put(M, "Dr32", tof(Drp));
+  put(M, "Ds32", tof(Dsp));
+  put(M, "MDr32", tof(MDrp));
+  put(M, "MDs32", tof(MDsp));
+  put(M, "M32", tof(Mp));
+  put(M, "elem_loc", M->elem_loc);
+  put(M, "acc_cnt", M->acc_cnt);
+  put(M, "acc_ent", M->acc_ent);
+  put(M, "surf_loc", M->surf_loc);
+  put(M, "is_surf_loc", M->is_surf_loc);
+  put(M, "lay", lay);
+  put(M, "nodeq", nodeq);
+  put(M, "colw", colw);
+  put(M, "pre_lap", pre_lap);
+  put(M, "pre_mass", pre_mass);
+  put(M, "pre_lap32", tof(pre_lap));
+  put(M, "M1", r1.M);
+  put(M, "S1", S1);
+  put(M, "Ifine", If);
+  put(M, "Mfine", rf.M);
+  put(M, "Filt", Filt);
+  put(M, "pre1d", pre1d);
+  put(M, "h", M->h);
+  put(M, "hx", M->hx);
+  // dynamic
+  const int m = M->m;
+  const size_t n = (size_t)M->n, ns1 = (size_t)M->ns;
+  const size_t tiles = (size_t)M->nb * M->T * 16 * NpP;
+  int nchunk;
+  int64_t chunk;
+  dot_layout(M->n, &nchunk, &chunk);
+  const int ldp = m + 2;
+  reserve(M, "G", tiles * 3 * sizeof(double));
+  reserve(M, "G32", tiles * 3 * sizeof(float));
+  reserve(M, "invd", tiles * sizeof(double));
+  reserve(M, "status", 64);
+  reserve(M, "ks", sizeof(KrylovState));
+  reserve(M, "H", ((size_t)(m + 1) * m + 5 * m + 1) * sizeof(double));
+  reserve(M, "part", (size_t)std::max<int64_t>(nchunk, M->nb) * ldp * sizeof(double));
+  reserve(M, "V", (size_t)(m + 1) * n * sizeof(double));
+  reserve(M, "Z", (size_t)m * n * sizeof(double));
+  reserve(M, "w", n * sizeof(double));
+  reserve(M, "b", n * sizeof(double));
+  reserve(M, "tmp", n * sizeof(double));
+  reserve(M, "xs", n * sizeof(double));
+  reserve(M, "wmass", n * sizeof(double));
+  reserve(M, "side", (size_t)4 * M->nb * nl * sizeof(double));
+  reserve(M, "s1d", 16 * ns1 * sizeof(double));
+  reserve(M, "rk", 16 * ns1 * sizeof(double));
+  reserve(M, "V32", (size_t)(m + 1) * n * sizeof(float));
+  reserve(M, "Z32", (size_t)m * n * sizeof(float));
+  reserve(M, "w32", n * sizeof(float));
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
+  if (!desc || !out) return fail(SEM_E_INVAL, "null argument");
+  *out = nullptr;
+  if (desc->nx < 1 || desc->nz < 1) return fail(SEM_E_INVAL, "nx and nz must be >= 1");
+  if (desc->order < 1 || desc->order > kMaxOrder) return fail(SEM_E_INVAL, "order must be in 1..8");
+  if (!(desc->length > 0)) return fail(SEM_E_INVAL, "length must be positive");
+  if (desc->periodic && desc->nx < 2) return fail(SEM_E_INVAL, "a periodic tank needs nx >= 2");
+  if (desc->filter_ic < 2 || desc->filter_ic > desc->order + 1)
+    return fail(SEM_E_INVAL, "filter_ic must be in 2..order+1 (vertex modes are never filtered)");
+  if (desc->overint_order < desc->order || desc->overint_order > 32)
+    return fail(SEM_E_INVAL, "overint_order must be in order..32");
+  if (!desc->h || !desc->h_x) return fail(SEM_E_INVAL, "h and h_x are required");
+  std::unique_ptr<sem_mesh> M(new (std::nothrow) sem_mesh());
+  if (!M) return fail(SEM_E_NOMEM, "host allocation failed");
+  M->nx = desc->nx;
+  M->nz = desc->nz;
+  M->P = desc->order;
+  M->periodic = desc->periodic ? 1 : 0;
+  M->L = desc->length;
+  M->g = desc->g;
+  M->ic = desc->filter_ic;
+  M->sf = desc->filter_sigma;
+  M->Pf = desc->overint_order;
+  M->m = desc->restart > 0 ? desc->restart : 30;
+  if (M->m > 200) return fail(SEM_E_INVAL, "restart must be <= 200");
+  int64_t ns = (int64_t)M->nx * M->P + (M->periodic ? 0 : 1);
+  M->h.assign(desc->h, desc->h + ns);
+  M->hx.assign(desc->h_x, desc->h_x + ns);
+  for (double v : M->h)
+    if (!(v > 0)) return fail(SEM_E_INVAL, "still-water depth must be positive");
+  if (desc->sigma_levels) {
+    M->slev.assign(desc->sigma_levels, desc->sigma_levels + M->nz + 1);
+    if (M->slev[0] != 0.0 || M->slev[M->nz] != 1.0) return fail(SEM_E_INVAL, "sigma_levels must run from 0 to 1");
+    for (int j = 0; j < M->nz; ++j)
+      if (!(M->slev[j + 1] > M->slev[j])) return fail(SEM_E_INVAL, "sigma_levels must increase");
+  }
+  sem_status s;
+  try {
+    s = build_mesh(M.get());
+  } catch (const std::exception& e) {
+    return fail(SEM_E_INVAL, e.what());
+  }
+  if (s != SEM_OK) return s;
+  *out = M.release();
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_mesh_query(const sem_mesh* M, sem_mesh_info* out) {
+  if (!M || !out) return fail(SEM_E_INVAL, "null argument");
+  out->n = M->n;
+  out->ns = M->ns;
+  out->n_free = M->n - M->ns;
+  out->n_elem = M->E;
+  out->np = M->Np;
+  out->nblocks = M->nb;
+  out->workspace_bytes = M->ws_bytes;
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_mesh_node_coords(const sem_mesh* M, double* x, double* sg) {
+  if (!M || !x || !sg) return fail(SEM_E_INVAL, "null argument");
+  std::memcpy(x, M->node_x.data(), M->n * sizeof(double));
+  std::memcpy(sg, M->node_sig.data(), M->n * sizeof(double));
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_mesh_surface_nodes(const sem_mesh* M, int64_t* idx) {
+  if (!M || !idx) return fail(SEM_E_INVAL, "null argument");
+  std::memcpy(idx, M->surf_nodes.data(), M->ns * sizeof(int64_t));
+  return SEM_OK;
+}
+
+extern "C" void sem_mesh_destroy(sem_mesh* M) { delete M; }
+
+template <class T>
+static T* at(sem_mesh* M, const char* name) {
+  return reinterpret_cast<T*>(M->ws + M->off.at(name));
+}
+
+extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, void* stream) {
+  if (!M || !workspace) return fail(SEM_E_INVAL, "null argument");
+  if (bytes < M->ws_bytes) return fail(SEM_E_NOMEM, "workspace smaller than sem_mesh_query reports");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SEM_E_INVAL, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  M->ws = (char*)workspace;
+  TankDev& h = M->hd;
+  h = TankDev{};
+  h.P = M->P;
+  h.Np = M->Np;
+  h.NpP = M->NpP;
+  h.nx = M->nx;
+  h.nz = M->nz;
+  h.periodic = M->periodic;
+  h.nl = M->nl;
+  h.nc = M->nc;
+  h.n = (int32_t)M->n;
+  h.ns = (int32_t)M->ns;
+  h.E = (int32_t)M->E;
+  h.cb = M->cb;
+  h.nb = M->nb;
+  h.T = M->T;
+  h.EB = M->EB;
+  h.m = M->m;
+  h.Pf = M->Pf;
+  h.L = M->L;
+  h.dX = M->L / M->nx;
+  h.g = M->g;
+  h.nclass_col = M->nclass_col;
+  h.Dr = at<double>(M, "Dr");
+  h.Ds = at<double>(M, "Ds");
+  h.MDr = at<double>(M, "MDr");
+  h.MDs = at<double>(M, "MDs");
+  h.Mref = at<double>(M, "M");
+  h.Dr32 = at<float>(M, "Dr32");
+  h.Ds32 = at<float>(M, "Ds32");
+  h.MDr32 = at<float>(M, "MDr32");
+  h.MDs32 = at<float>(M, "MDs32");
+  h.Mref32 = at<float>(M, "M32");
+  h.elem_loc = at<int32_t>(M, "elem_loc");
+  h.acc_cnt = at<int32_t>(M, "acc_cnt");
+  h.acc_ent = at<int32_t>(M, "acc_ent");
+  h.surf_loc = at<int32_t>(M, "surf_loc");
+  h.is_surf_loc = at<int32_t>(M, "is_surf_loc");
+  h.lay = at<double>(M, "lay");
+  h.nodeq = at<double>(M, "nodeq");
+  h.colw = at<double>(M, "colw");
+  h.pre_lap = at<double>(M, "pre_lap");
+  h.pre_mass = at<double>(M, "pre_mass");
+  h.pre_lap32 = at<float>(M, "pre_lap32");
+  h.M1 = at<double>(M, "M1");
+  h.S1 = at<double>(M, "S1");
+  h.Ifine = at<double>(M, "Ifine");
+  h.Mfine = at<double>(M, "Mfine");
+  h.Filt = at<double>(M, "Filt");
+  h.pre1d = at<double>(M, "pre1d");
+  h.h = at<double>(M, "h");
+  h.hx = at<double>(M, "hx");
+  h.G = at<double>(M, "G");
+  h.G32 = at<float>(M, "G32");
+  h.invd = at<double>(M, "invd");
+  h.status = at<int32_t>(M, "status");
+  h.ks = at<KrylovState>(M, "ks");
+  h.H = at<double>(M, "H");
+  h.part = at<double>(M, "part");
+  h.V = at<double>(M, "V");
+  h.Zb = at<double>(M, "Z");
+  h.w = at<double>(M, "w");
+  h.b = at<double>(M, "b");
+  h.tmp = at<double>(M, "tmp");
+  h.xs = at<double>(M, "xs");
+  h.wmass = at<double>(M, "wmass");
+  h.side = at<double>(M, "side");
+  h.s1d = at<double>(M, "s1d");
+  h.V32 = at<float>(M, "V32");
+  h.Z32 = at<float>(M, "Z32");
+  h.w32 = at<float>(M, "w32");
+  M->rk = at<double>(M, "rk");
+  M->scal = at<double>(M, "scal");
+  M->dtank = at<TankDev>(M, "tank");
+  for (const Upload& u : M->uploads)
+    HIPCHK(hipMemcpyAsync(M->ws + u.off, u.data.data(), u.data.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(M->dtank, &h, sizeof(TankDev), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(h.status, 0, 64, st));
+  HIPCHK(hipMemsetAsync(h.wmass, 0, M->n * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(h.G, 0, M->off.at("G32") - M->off.at("G"), st));
+  HIPCHK(hipMemsetAsync(h.G32, 0, M->off.at("invd") - M->off.at("G32"), st));
+  HIPCHK(hipMemsetAsync(h.invd, 0, M->off.at("status") - M->off.at("invd"), st));
+  HIPCHK(hipStreamSynchronize(st));
+  M->bound = true;
+  return SEM_OK;
+}
+
+// ------------------------------------------------------------ helpers
+static sem_status check_bound(sem_mesh* M) {
+  if (!M) return fail(SEM_E_INVAL, "null mesh");
+  if (!M->bound) return fail(SEM_E_INVAL, "mesh not bound to a workspace");
+  return SEM_OK;
+}
+
+static sem_status status_from_word(int32_t w) {
+  if (w & ST_NONFINITE) return SEM_E_NONFINITE;
+  if (w & ST_DOMAIN) return SEM_E_DOMAIN;
+  if (w & ST_BREAKDOWN) return SEM_E_BREAKDOWN;
+  if (w & ST_NOCONV) return SEM_E_NOCONV;
+  return SEM_OK;
+}
+
+static sem_status read_status(sem_mesh* M, hipStream_t st, int32_t* word) {
+  int32_t w = 0;
+  HIPCHK(hipMemcpyAsync(&w, M->hd.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (word) *word = w;
+  sem_status s = status_from_word(w);
+  if (s != SEM_OK) return fail(s, "device reported status " + std::to_string(w));
+  return SEM_OK;
+}
+
+struct GmresCfg {
+  int op, pre;
+  bool mask;
+  double rtol;
+  int max_iter;
+  int poll;
+};
+
+// Restarted right-preconditioned GMRES on device vectors: x (in: guess, out:
+// solution), b.  Iterations and final estimate are returned.
+static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, double* x, const double* b, int* iters_out,
+                        double* relres_out, hipStream_t st) {
+  const TankDev& h = M->hd;
+  const TankDev* d = M->dtank;
+  const int m = M->m;
+  const int64_t n = M->n;
+  const int ldp = m + 2;
+  double* scal = M->scal;
+  double* side = h.side;
+  const int flags = cfg.mask ? 1 : 0;
+  KrylovState ks0{};
+  ks0.rtol = cfg.rtol;
+  HIPCHK(hipMemcpyAsync(h.ks, &ks0, sizeof(ks0), hipMemcpyHostToDevice, st));
+  // ||b||
+  launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, st);
+  int total = 0;
+  KrylovState hks{};
+  bool first = true;
+  int poll = std::max(1, cfg.poll);
+  while (true) {
+    // r = b - A x
+    launch_gather(h, d, cfg.op, x, h.w, side, flags, st);
+    launch_residual(h, d, n, b, h.w, h.V, cfg.mask ? 1 : 0, st);
+    launch_dots(n, 1, h.V, 0, h.V, h.part, ldp, scal + 0, st);
+    launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, h.V, st);
+    first = false;
+    HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hks.status) break;
+    if (hks.converged) break;
+    if (total >= cfg.max_iter) break;
+    for (int j = 0; j < m; ++j) {
+      double* Vj = h.V + (size_t)j * n;
+      double* Zj = h.Zb + (size_t)j * n;
+      launch_gather(h, d, cfg.pre, Vj, Zj, side, flags, st);
+      launch_gather(h, d, cfg.op, Zj, h.w, side, flags, st);
+      double* Hcol = h.H + (size_t)j * (m + 1);
+      launch_dots(n, j + 1, h.V, n, h.w, h.part, ldp, Hcol, st);
+      launch_orth(n, j, h.V, Hcol, h.w, h.part, ldp, scal + 2, h.ks, st);
+      launch_givens(h.ks, h.H, m, j, scal + 2, h.status, st);
+      launch_scale_next(n, j, h.w, h.V, h.H, m, h.ks, st);
+      if ((j + 1) % poll == 0 || j == m - 1 || total + j + 1 >= cfg.max_iter) {
+        HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hks.done || total + j + 1 >= cfg.max_iter) break;
+      }
+    }
+    launch_solve_update(n, h.Zb, h.H, m, h.ks, x, st);
+    HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    total = hks.iters;
+    if (hks.status) break;
+    if (hks.converged) break;
+    if (total >= cfg.max_iter) break;
+  }
+  *iters_out = hks.iters;
+  *relres_out = hks.bnorm > 0 ? hks.resid / hks.bnorm : 0.0;
+  if (hks.status) return status_from_word(hks.status);
+  if (!hks.converged) {
+    int32_t w = ST_NOCONV;
+    HIPCHK(hipMemcpyAsync(&w, h.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    w |= ST_NOCONV;
+    HIPCHK(hipMemcpyAsync(h.status, &w, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    return SEM_E_NOCONV;
+  }
+  return SEM_OK;
+}
+
+static void default_opts(sem_solve_opts* o) {
+  o->rtol = 1e-12;
+  o->max_iter = 5000;
+  o->prec = SEM_PREC_FP64;
+  o->inner_rtol = 1e-4;
+  o->max_refine = 30;
+  o->warm_start = 0;
+  o->poll_every = 10;
+}
+
+// ------------------------------------------------------------ public calls
+extern "C" sem_status sem_set_surface(sem_mesh* M, const double* eta, const double* eta_x, void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!eta || !eta_x) return fail(SEM_E_INVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemsetAsync(M->hd.status, 0, sizeof(int32_t), st));
+  launch_coef(M->hd, M->dtank, eta, eta_x, 3, st);
+  return read_status(M, st, nullptr);
+}
+
+extern "C" sem_status sem_apply(sem_mesh* M, sem_operator op, const double* u, double* y, void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!u || !y) return fail(SEM_E_INVAL, "null argument");
+  int kop;
+  switch (op) {
+    case SEM_OP_STIFFNESS: kop = 0; break;
+    case SEM_OP_MASS2D: kop = 1; break;
+    case SEM_OP_PRECOND: kop = 2; break;
+    case SEM_OP_SZ: kop = 4; break;
+    default: return fail(SEM_E_INVAL, "unknown operator");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  launch_gather(M->hd, M->dtank, kop, u, y, M->hd.side, 0, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return SEM_OK;
+}
+
+// Laplace solve on the device with factors already set; phi in/out [n].
+static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, const sem_solve_opts* o,
+                               sem_solve_stats* stats, hipStream_t st) {
+  const TankDev& h = M->hd;
+  const TankDev* d = M->dtank;
+  const int64_t n = M->n;
+  auto t0 = std::chrono::steady_clock::now();
+  // b = -(A [0; phi~])_F
+  launch_scatter_surface(h, d, phi_s, h.tmp, 1, st);
+  launch_gather(h, d, 0, h.tmp, h.b, h.side, 1 | 2, st);
+  // x = warm start (free part) or 0
+  if (o->warm_start) {
+    HIPCHK(hipMemcpyAsync(h.xs, phi, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_mask_surface(h, d, h.xs, st);
+  } else {
+    launch_fill(n, 0.0, h.xs, st);
+  }
+  GmresCfg cfg{0, 2, true, o->rtol, o->max_iter, o->poll_every};
+  int iters = 0;
+  double rel = 0;
+  sem_status s = gmres(M, cfg, h.xs, h.b, &iters, &rel, st);
+  // Phi = x_F + lift
+  HIPCHK(hipMemcpyAsync(phi, h.xs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  launch_scatter_surface(h, d, phi_s, phi, 0, st);
+  HIPCHK(hipStreamSynchronize(st));
+  if (stats) {
+    stats->iters = iters;
+    stats->refinements = 0;
+    stats->rel_residual = rel;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->status = s;
+  }
+  return s;
+}
+
+extern "C" sem_status sem_laplace_solve(sem_mesh* M, const double* eta, const double* eta_x, const double* phi_s,
+                                        double* phi, const sem_solve_opts* opts, sem_solve_stats* stats,
+                                        void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!eta || !eta_x || !phi_s || !phi) return fail(SEM_E_INVAL, "null argument");
+  sem_solve_opts o;
+  if (opts) o = *opts;
+  else default_opts(&o);
+  if (!(o.rtol > 0) || o.max_iter < 1) return fail(SEM_E_INVAL, "rtol > 0 and max_iter >= 1 required");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemsetAsync(M->hd.status, 0, sizeof(int32_t), st));
+  launch_coef(M->hd, M->dtank, eta, eta_x, 3, st);
+  s = read_status(M, st, nullptr);
+  if (s) return s;
+  return laplace_core(M, phi_s, phi, &o, stats, st);
+}
+
+// w~ from M w = S_z Phi (factors 1/d must be current); out [ns]
+static sem_status recover_w_core(sem_mesh* M, const double* Phi, double* out, hipStream_t st) {
+  const TankDev& h = M->hd;
+  const TankDev* d = M->dtank;
+  launch_gather(h, d, 4, Phi, h.b, h.side, 0, st);
+  GmresCfg cfg{1, 3, false, 1e-14, 400, 10};
+  int iters;
+  double rel;
+  sem_status s = gmres(M, cfg, h.wmass, h.b, &iters, &rel, st);
+  launch_gather_surface(h, d, h.wmass, out, st);
+  return s;
+}
+
+extern "C" sem_status sem_gradient_recover(sem_mesh* M, sem_recover_kind kind, const double* in, const double* eta,
+                                           double* out, void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!in || !out) return fail(SEM_E_INVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemsetAsync(M->hd.status, 0, sizeof(int32_t), st));
+  if (kind == SEM_RECOVER_DX) {
+    launch_recover_dx(M->hd, M->dtank, in, out, nullptr, nullptr, st);
+    return read_status(M, st, nullptr);
+  }
+  if (kind != SEM_RECOVER_W) return fail(SEM_E_INVAL, "unknown recovery kind");
+  if (!eta) return fail(SEM_E_INVAL, "eta required for w recovery");
+  launch_coef(M->hd, M->dtank, eta, nullptr, 2, st);
+  s = read_status(M, st, nullptr);
+  if (s) return s;
+  s = recover_w_core(M, in, out, st);
+  if (s) return s;
+  return read_status(M, st, nullptr);
+}
+
+extern "C" sem_status sem_free_surface_rhs(sem_mesh* M, const double* eta, const double* eta_x, const double* phi_x,
+                                           const double* w_s, double* deta, double* dphi, void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!eta || !eta_x || !phi_x || !w_s || !deta || !dphi) return fail(SEM_E_INVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemsetAsync(M->hd.status, 0, sizeof(int32_t), st));
+  launch_fs_rhs(M->hd, M->dtank, eta, eta_x, phi_x, w_s, deta, dphi, st);
+  return read_status(M, st, nullptr);
+}
+
+extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, double* phi_ws, double dt,
+                                   const sem_solve_opts* opts, sem_solve_stats* stats, void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!eta || !phi_s || !phi_ws) return fail(SEM_E_INVAL, "null argument");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(SEM_E_INVAL, "dt must be positive");
+  sem_solve_opts o;
+  if (opts) o = *opts;
+  else default_opts(&o);
+  hipStream_t st = (hipStream_t)stream;
+  const TankDev& h = M->hd;
+  const TankDev* d = M->dtank;
+  const int ns = (int)M->ns;
+  double* rk = M->rk;
+  double* ye = rk + 0 * ns;   // stage state
+  double* yp = rk + 1 * ns;
+  double* ex = rk + 2 * ns;   // eta_x
+  double* px = rk + 3 * ns;   // phi_x
+  double* wsf = rk + 4 * ns;  // w~
+  double* ke = rk + 5 * ns;   // stage slopes
+  double* kp = rk + 6 * ns;
+  double* ae = rk + 7 * ns;   // accumulated slopes
+  double* ap = rk + 8 * ns;
+  HIPCHK(hipMemsetAsync(h.status, 0, sizeof(int32_t), st));
+  const double cnode[4] = {0.0, 0.5, 0.5, 1.0};
+  const double wts[4] = {1.0 / 6, 2.0 / 6, 2.0 / 6, 1.0 / 6};
+  sem_solve_opts lo = o;
+  lo.warm_start = 1;
+  sem_status first_err = SEM_OK;
+  for (int sidx = 0; sidx < 4; ++sidx) {
+    const double* se = sidx == 0 ? eta : ye;
+    const double* sp = sidx == 0 ? phi_s : yp;
+    launch_recover_dx(h, d, se, ex, sp, px, st);
+    launch_coef(h, d, se, ex, 3, st);
+    int32_t w = 0;
+    s = read_status(M, st, &w);
+    if (s) {
+      first_err = s;
+      break;
+    }
+    sem_solve_stats ls{};
+    s = laplace_core(M, sp, phi_ws, &lo, &ls, st);
+    if (stats) stats[sidx] = ls;
+    if (s) {
+      first_err = s;
+      break;
+    }
+    s = recover_w_core(M, phi_ws, wsf, st);
+    if (s) {
+      first_err = s;
+      break;
+    }
+    launch_fs_rhs(h, d, se, ex, px, wsf, ke, kp, st);
+    if (sidx < 3)
+      launch_rk4_stage(ns, cnode[sidx + 1] * dt, wts[sidx], sidx == 0, eta, phi_s, ke, kp, ye, yp, ae, ap, st);
+    else
+      launch_rk4_stage(ns, 0.0, wts[sidx], 0, eta, phi_s, ke, kp, ye, yp, ae, ap, st);
+  }
+  if (first_err) return first_err;
+  launch_rk4_final(h, d, dt, ae, ap, eta, phi_s, M->sf != 1.0 ? 1 : 0, st);
+  return read_status(M, st, nullptr);
+}
+
+// ------------------------------------------------------------ batches (sequential over tanks for now)
+struct sem_batch {
+  std::vector<sem_mesh*> meshes;
+};
+
+extern "C" sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, sem_batch** out) {
+  if (!meshes || count < 1 || !out) return fail(SEM_E_INVAL, "bad batch arguments");
+  for (int i = 0; i < count; ++i)
+    if (!meshes[i] || !meshes[i]->bound) return fail(SEM_E_INVAL, "every mesh must be bound");
+  sem_batch* B = new (std::nothrow) sem_batch();
+  if (!B) return fail(SEM_E_NOMEM, "host allocation failed");
+  B->meshes.assign(meshes, meshes + count);
+  *out = B;
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_batch_rk4_step(sem_batch* B, double* const* eta, double* const* phi_s,
+                                         double* const* phi_ws, const double* dt, const uint8_t* active,
+                                         const sem_solve_opts* opts, int32_t* per_status, int32_t* per_iters,
+                                         void* stream) {
+  if (!B || !eta || !phi_s || !phi_ws || !dt) return fail(SEM_E_INVAL, "null argument");
+  sem_status worst = SEM_OK;
+  for (size_t i = 0; i < B->meshes.size(); ++i) {
+    if (active && !active[i]) continue;
+    sem_solve_stats st4[4];
+    sem_status s = sem_rk4_step(B->meshes[i], eta[i], phi_s[i], phi_ws[i], dt[i], opts, st4, stream);
+    if (per_status) per_status[i] = s;
+    if (per_iters) per_iters[i] = st4[0].iters + st4[1].iters + st4[2].iters + st4[3].iters;
+    if (s && !worst) worst = s;
+  }
+  return worst;
+}
+
+extern "C" void sem_batch_destroy(sem_batch* B) { delete B; }

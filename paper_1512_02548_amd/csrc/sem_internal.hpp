@@ -1,0 +1,108 @@
+// Internal data structures shared by the host driver and the HIP kernels.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace sem {
+
+constexpr int kMaxOrder = 8;
+constexpr int kMaxContrib = 8;      // element contributions to one column-local node
+constexpr int kBlockThreads = 256;
+
+// status bits accumulated on the device
+enum : int32_t {
+  ST_DOMAIN = 1,
+  ST_NOCONV = 2,
+  ST_BREAKDOWN = 4,
+  ST_NONFINITE = 8,
+};
+
+// Krylov state of one solve, resident in the workspace.
+struct KrylovState {
+  double bnorm;       // ||b||
+  double beta;        // ||r0|| of the current cycle
+  double resid;       // current residual estimate |g_{j+1}|
+  double rtol;
+  int32_t j;          // columns completed in the current cycle
+  int32_t done;       // 1 when the cycle ended (converged or restart)
+  int32_t converged;  // 1 when rtol met
+  int32_t iters;      // total iterations
+  int32_t status;
+  int32_t pad[3];
+};
+
+// Everything a kernel needs about one tank; lives in device memory at the
+// start of the tank's workspace.  Pointers are device addresses.
+struct TankDev {
+  // sizes
+  int32_t P, Np, NpP, nx, nz, periodic, nl, nc, n, ns, E;
+  int32_t cb, nb, T, EB;          // columns per block, blocks, tiles per block, elems per block (cb*2nz)
+  int32_t m;                      // GMRES restart length
+  int32_t Pf;
+  double L, dX, g;
+  // reference operators (padded to NpP, row-major)
+  const double* Dr;               // NpP x NpP
+  const double* Ds;
+  const double* MDr;              // M Dr
+  const double* MDs;
+  const double* Mref;             // M
+  const float* Dr32;
+  const float* Ds32;
+  const float* MDr32;
+  const float* MDs32;
+  const float* Mref32;
+  // mesh tables
+  const int32_t* elem_loc;        // [2nz][NpP] column-local node (< nc + nl), -1 = padding
+  const int32_t* acc_cnt;         // [nc] number of contributions
+  const int32_t* acc_ent;         // [nc][kMaxContrib]: bit 30 = previous column, low bits e_in_col*NpP + m
+  const int32_t* surf_loc;        // [P] column-local index of the surface nodes of a column
+  const int32_t* is_surf_loc;     // [nc + nl] 1 if the column-local node lies on sigma = 1
+  const double* lay;              // [2nz][8]: Lam_rx, Lam_rs(sig), Lam_sx, Lam_ss, J, sigma_j, dsigma_j, 0
+  const double* nodeq;            // [2][NpP][2]: xi, zeta of each reference node in the unit quad
+  const double* colw;             // [2][NpP][P+1]: column interpolation weights at xi
+  const double* pre_lap;          // [nclass][NpP][NpP] W C^{-1} W (free nodes), zero padded
+  const double* pre_mass;         // [nclass][NpP][NpP]
+  const float* pre_lap32;
+  int32_t nclass_col;             // 1 (periodic) or 3 (walls: first, interior, last)
+  int32_t pad0;
+  // 1D surface operators (P+1)^2 etc.
+  const double* M1;
+  const double* S1;               // M1 D1
+  const double* Ifine;            // (Pf+1) x (P+1)
+  const double* Mfine;            // (Pf+1) x (Pf+1)
+  const double* Filt;             // (P+1) x (P+1)
+  const double* pre1d;            // [3][(P+1)^2] W C^{-1} W for the 1D mass (classes: first, interior, last)
+  const double* h;                // [ns]
+  const double* hx;               // [ns]
+  // dynamic fields
+  double* G;                      // [nb][T][3][NpP][16]
+  float* G32;
+  double* invd;                   // [nb][T][NpP][16]
+  int32_t* status;                // one word
+  KrylovState* ks;
+  double* H;                      // (m+1) x m Hessenberg, then cs[m], sn[m], g[m+1], y[m]
+  double* part;                   // [nb][m+2] block partial sums
+  double* V;                      // (m+1) x n
+  double* Zb;                     // m x n
+  double* w;                      // n
+  double* b;                      // n
+  double* tmp;                    // n
+  double* xs;                     // n  solution accumulator
+  double* wmass;                  // n  warm start of the mass solve
+  double* side;                   // [4][nb][nl] line contributions of assembled outputs
+  double* s1d;                    // [16][ns] 1D work arrays
+  // FP32 inner-solve storage
+  float* V32;
+  float* Z32;
+  float* w32;
+};
+
+// index of the element-node value of component c in the MFMA tile layout
+__host__ __device__ inline int64_t tile_index(int T, int NpP, int64_t blk, int eb, int m, int ncomp,
+                                              int c) {
+  int tile = eb >> 4, e = eb & 15;
+  int perm = (m >> 4) * 16 + (m & 3) * 4 + ((m & 15) >> 2);
+  return (((blk * T + tile) * ncomp + c) * (int64_t)NpP + perm) * 16 + e;
+}
+
+}  // namespace sem
