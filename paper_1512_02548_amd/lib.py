@@ -13,6 +13,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libsem.so")
 
+# The library must share PyTorch's HIP runtime (streams and allocations come
+# from torch): load torch first so that its libamdhip64 satisfies libsem.so's
+# dependency instead of a second runtime instance.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIBPATH):
     raise ImportError(f"{LIBPATH} is missing: build it with `python -m paper_1512_02548_amd.build` "
                       "(there is no CPU fallback)")
