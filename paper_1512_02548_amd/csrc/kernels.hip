@@ -251,6 +251,113 @@ __global__ void k_fixup(const TankDev* __restrict__ td, double* __restrict__ y,
   }
 }
 
+// ------------------------------------------------------------ exact still-water preconditioner
+// Periodic tanks.  z = A0_FF^{-1} r for the still-water flat-bed operator A0:
+// each column's interior free nodes are condensed onto the vertical lines
+// (Schur complement), the resulting block-circulant line system is solved
+// mode by mode after a DFT along x, and the interiors are recovered.
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_interior(const TankDev* __restrict__ td, const double* __restrict__ r) {
+  const TankDev& d = *td;
+  extern __shared__ double sh[];
+  const int c = blockIdx.x, nI = d.nI, q = d.q;
+  double* rI = sh;
+  double* y = sh + nI;
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) rI[i] = r[(int64_t)c * d.nc + d.I_idx[i]];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
+    const double* A = d.AinvII + (size_t)i * nI;
+    double acc = 0;
+    for (int j = 0; j < nI; ++j) acc += A[j] * rI[j];
+    y[i] = acc;
+    d.yI[(size_t)c * nI + i] = acc;
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < 2 * q; a += blockDim.x) {
+    const double* A = a < q ? d.ALI + (size_t)a * nI : d.ARI + (size_t)(a - q) * nI;
+    double acc = 0;
+    for (int i = 0; i < nI; ++i) acc += A[i] * y[i];
+    if (a < q) d.TL[(size_t)c * q + a] = acc;
+    else d.TR[(size_t)c * q + a - q] = acc;
+  }
+}
+
+__global__ void k_sd_modes(const TankDev* __restrict__ td, const double* __restrict__ r) {
+  const TankDev& d = *td;
+  extern __shared__ double gh[];  // [q][2]
+  const int k = blockIdx.x, q = d.q, nx = d.nx;
+  for (int j = threadIdx.x; j < q; j += blockDim.x) {
+    double re = 0, im = 0;
+    for (int c = 0; c < nx; ++c) {
+      int cm = c == 0 ? nx - 1 : c - 1;
+      double g = r[(int64_t)c * d.nc + j] - d.TL[(size_t)c * q + j] - d.TR[(size_t)cm * q + j];
+      int mm = (int)(((int64_t)k * c) % nx);
+      re += g * d.twid[2 * mm];
+      im += g * d.twid[2 * mm + 1];
+    }
+    gh[2 * j] = re;
+    gh[2 * j + 1] = im;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < q; i += blockDim.x) {
+    const double* S = d.Shat + ((size_t)k * q + i) * q * 2;
+    double xr = 0, xi = 0;
+    for (int j = 0; j < q; ++j) {
+      double sr = S[2 * j], si = S[2 * j + 1];
+      xr += sr * gh[2 * j] - si * gh[2 * j + 1];
+      xi += sr * gh[2 * j + 1] + si * gh[2 * j];
+    }
+    d.XH[((size_t)k * q + i) * 2] = xr;
+    d.XH[((size_t)k * q + i) * 2 + 1] = xi;
+  }
+}
+
+__global__ void k_sd_lines(const TankDev* __restrict__ td, double* __restrict__ z) {
+  const TankDev& d = *td;
+  const int c = blockIdx.x, q = d.q, nx = d.nx;
+  for (int j = threadIdx.x; j < q; j += blockDim.x) {
+    double acc = 0;
+    for (int k = 0; k < nx; ++k) {
+      int mm = (int)(((int64_t)k * c) % nx);
+      // Re[(xr + i xi) * exp(+2 pi i k c / nx)], exp(+..) = conj(twid)
+      acc += d.XH[((size_t)k * q + j) * 2] * d.twid[2 * mm] + d.XH[((size_t)k * q + j) * 2 + 1] * d.twid[2 * mm + 1];
+    }
+    acc /= nx;
+    z[(int64_t)c * d.nc + j] = acc;
+    d.XL[(size_t)c * q + j] = acc;
+  }
+  if (threadIdx.x == 0) z[(int64_t)c * d.nc + d.nl - 1] = 0.0;
+}
+
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_back(const TankDev* __restrict__ td, double* __restrict__ z) {
+  const TankDev& d = *td;
+  extern __shared__ double sh[];
+  const int c = blockIdx.x, nI = d.nI, q = d.q;
+  const int cn = c + 1 == d.nx ? 0 : c + 1;
+  double* xl = sh;
+  double* xr = sh + q;
+  double* v = sh + 2 * q;
+  for (int a = threadIdx.x; a < q; a += blockDim.x) {
+    xl[a] = d.XL[(size_t)c * q + a];
+    xr[a] = d.XL[(size_t)cn * q + a];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
+    double acc = 0;
+    for (int a = 0; a < q; ++a) acc += d.ALI[(size_t)a * nI + i] * xl[a] + d.ARI[(size_t)a * nI + i] * xr[a];
+    v[i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
+    const double* A = d.AinvII + (size_t)i * nI;
+    double acc = 0;
+    for (int j = 0; j < nI; ++j) acc += A[j] * v[j];
+    z[(int64_t)c * d.nc + d.I_idx[i]] = d.yI[(size_t)c * nI + i] - acc;
+  }
+  for (int k = 1 + threadIdx.x; k < d.P; k += blockDim.x) z[(int64_t)c * d.nc + d.surf_loc[k]] = 0.0;
+}
+
 // ------------------------------------------------------------ vector kernels
 // y = a*x + b*y over [0, n) (optionally masked at surface nodes)
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double bb,
@@ -782,6 +889,14 @@ void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const do
 
 void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side,
                    int flags, hipStream_t st) {
+  if (op == OP_PRE_LAP && h.pre_kind == 1) {
+    size_t s1 = sizeof(double) * 2 * h.nI, s4 = sizeof(double) * (2 * h.q + h.nI);
+    hipLaunchKernelGGL(k_sd_interior, dim3(h.nx), dim3(kBlockThreads), s1, st, d, u);
+    hipLaunchKernelGGL(k_sd_modes, dim3(h.nx), dim3(64), sizeof(double) * 2 * h.q, st, d, u);
+    hipLaunchKernelGGL(k_sd_lines, dim3(h.nx), dim3(64), 0, st, d, y);
+    hipLaunchKernelGGL(k_sd_back, dim3(h.nx), dim3(kBlockThreads), s4, st, d, y);
+    return;
+  }
   size_t lds = gather_lds_bytes(h);
   dim3 g(h.nb), b(kBlockThreads);
 #define SEM_G(OPV) SEM_P_SWITCH(h.P, hipLaunchKernelGGL((k_gather<PP, OPV>), g, b, lds, st, d, u, y, side, flags))

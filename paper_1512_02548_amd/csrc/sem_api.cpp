@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <complex>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -83,6 +84,7 @@ struct sem_mesh {
   std::vector<double> h, hx, slev;
   // derived sizes
   int Np = 0, NpP = 0, nl = 0, nc = 0, cb = 1, nb = 1, T = 1, EB = 0, nclass_col = 1;
+  int pre_kind = 0, nI = 0, q = 0;
   int64_t n = 0, ns = 0, E = 0;
   // host tables
   std::vector<int32_t> elem_loc, acc_cnt, acc_ent, surf_loc, is_surf_loc;
@@ -401,6 +403,102 @@ static sem_status build_mesh(sem_mesh* M) {
       }
     }
   }
+  // ---- exact still-water preconditioner for periodic tanks: column interiors
+  // condensed onto the vertical lines, line system diagonalised by a DFT in x
+  std::vector<int32_t> I_idx;
+  std::vector<double> AinvII, ALI, ARI, Shat, twid;
+  M->pre_kind = M->periodic ? 1 : 0;
+  if (M->pre_kind == 1) {
+    const int nloc = nc + nl;
+    Mat A0c((size_t)nloc * nloc, 0.0);
+    for (int jt = 0; jt < 2 * nz; ++jt) {
+      Mat Ae = elem_matrix(jt, false);
+      for (int a = 0; a < Np; ++a)
+        for (int b = 0; b < Np; ++b)
+          A0c[(size_t)M->elem_loc[(size_t)jt * NpP + a] * nloc + M->elem_loc[(size_t)jt * NpP + b]] +=
+              Ae[(size_t)a * Np + b];
+    }
+    const int q = nl - 1;
+    for (int loc = nl; loc < nc; ++loc)
+      if (!M->is_surf_loc[loc]) I_idx.push_back(loc);
+    const int nI = (int)I_idx.size();
+    M->q = q;
+    M->nI = nI;
+    std::vector<int> Gam(2 * q);
+    for (int a = 0; a < q; ++a) {
+      Gam[a] = a;
+      Gam[q + a] = nc + a;
+    }
+    AinvII.assign((size_t)nI * nI, 0.0);
+    for (int i = 0; i < nI; ++i)
+      for (int j = 0; j < nI; ++j) AinvII[(size_t)i * nI + j] = A0c[(size_t)I_idx[i] * nloc + I_idx[j]];
+    if (!invert(AinvII, nI)) return fail(SEM_E_INVAL, "singular column interior block");
+    ALI.assign((size_t)q * nI, 0.0);
+    ARI.assign((size_t)q * nI, 0.0);
+    for (int a = 0; a < q; ++a)
+      for (int i = 0; i < nI; ++i) {
+        ALI[(size_t)a * nI + i] = A0c[(size_t)Gam[a] * nloc + I_idx[i]];
+        ARI[(size_t)a * nI + i] = A0c[(size_t)Gam[q + a] * nloc + I_idx[i]];
+      }
+    // Schur complement of the column on its two lines: S = A_GG - A_GI AinvII A_IG
+    Mat AGI((size_t)2 * q * nI);
+    for (int a = 0; a < 2 * q; ++a)
+      for (int i = 0; i < nI; ++i) AGI[(size_t)a * nI + i] = A0c[(size_t)Gam[a] * nloc + I_idx[i]];
+    Mat W = matmul(AinvII, transpose(AGI, 2 * q, nI), nI, nI, 2 * q);   // nI x 2q
+    Mat SW = matmul(AGI, W, 2 * q, nI, 2 * q);
+    Mat S((size_t)4 * q * q);
+    for (int a = 0; a < 2 * q; ++a)
+      for (int b = 0; b < 2 * q; ++b)
+        S[(size_t)a * 2 * q + b] = A0c[(size_t)Gam[a] * nloc + Gam[b]] - SW[(size_t)a * 2 * q + b];
+    auto Sblk = [&](int A, int B, int a, int b) { return S[(size_t)(A * q + a) * 2 * q + B * q + b]; };
+    // per-mode symbol S_LL + S_RR + S_LR e^{i k} + S_RL e^{-i k}, inverted
+    using cd = std::complex<double>;
+    Shat.assign((size_t)nx * q * q * 2, 0.0);
+    for (int k = 0; k < nx; ++k) {
+      double kap = 2.0 * M_PI * k / nx;
+      cd ep(std::cos(kap), std::sin(kap)), em = std::conj(ep);
+      std::vector<cd> Ak((size_t)q * q), Ik((size_t)q * q, 0.0);
+      for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b)
+          Ak[(size_t)a * q + b] = Sblk(0, 0, a, b) + Sblk(1, 1, a, b) + Sblk(0, 1, a, b) * ep + Sblk(1, 0, a, b) * em;
+      for (int a = 0; a < q; ++a) Ik[(size_t)a * q + a] = 1.0;
+      // complex Gauss-Jordan with partial pivoting
+      for (int cc = 0; cc < q; ++cc) {
+        int piv = cc;
+        for (int rr = cc + 1; rr < q; ++rr)
+          if (std::abs(Ak[(size_t)rr * q + cc]) > std::abs(Ak[(size_t)piv * q + cc])) piv = rr;
+        if (std::abs(Ak[(size_t)piv * q + cc]) == 0.0) return fail(SEM_E_INVAL, "singular line symbol");
+        if (piv != cc)
+          for (int j = 0; j < q; ++j) {
+            std::swap(Ak[(size_t)cc * q + j], Ak[(size_t)piv * q + j]);
+            std::swap(Ik[(size_t)cc * q + j], Ik[(size_t)piv * q + j]);
+          }
+        cd inv = 1.0 / Ak[(size_t)cc * q + cc];
+        for (int j = 0; j < q; ++j) {
+          Ak[(size_t)cc * q + j] *= inv;
+          Ik[(size_t)cc * q + j] *= inv;
+        }
+        for (int rr = 0; rr < q; ++rr) {
+          if (rr == cc) continue;
+          cd f = Ak[(size_t)rr * q + cc];
+          if (f == 0.0) continue;
+          for (int j = 0; j < q; ++j) {
+            Ak[(size_t)rr * q + j] -= f * Ak[(size_t)cc * q + j];
+            Ik[(size_t)rr * q + j] -= f * Ik[(size_t)cc * q + j];
+          }
+        }
+      }
+      for (int a = 0; a < q * q; ++a) {
+        Shat[((size_t)k * q * q + a) * 2] = Ik[a].real();
+        Shat[((size_t)k * q * q + a) * 2 + 1] = Ik[a].imag();
+      }
+    }
+    twid.resize((size_t)2 * nx);
+    for (int mm = 0; mm < nx; ++mm) {
+      twid[2 * mm] = std::cos(2.0 * M_PI * mm / nx);
+      twid[2 * mm + 1] = -std::sin(2.0 * M_PI * mm / nx);
+    }
+  }
   // ---- 1D operators
   const int P1 = P + 1;
   Mat S1 = matmul(r1.M, r1.D, P1, P1, P1);
@@ -461,6 +559,17 @@ static sem_status build_mesh(sem_mesh* M) {
   put(M, "pre1d", pre1d);
   put(M, "h", M->h);
   put(M, "hx", M->hx);
+  put(M, "I_idx", I_idx);
+  put(M, "AinvII", AinvII);
+  put(M, "ALI", ALI);
+  put(M, "ARI", ARI);
+  put(M, "Shat", Shat);
+  put(M, "twid", twid);
+  reserve(M, "yI", (size_t)nx * std::max(1, M->nI) * sizeof(double));
+  reserve(M, "TL", (size_t)nx * std::max(1, M->q) * sizeof(double));
+  reserve(M, "TR", (size_t)nx * std::max(1, M->q) * sizeof(double));
+  reserve(M, "XH", (size_t)nx * std::max(1, M->q) * 2 * sizeof(double));
+  reserve(M, "XL", (size_t)nx * std::max(1, M->q) * sizeof(double));
   // dynamic
   const int m = M->m;
   const size_t n = (size_t)M->n, ns1 = (size_t)M->ns;
@@ -600,6 +709,20 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.dX = M->L / M->nx;
   h.g = M->g;
   h.nclass_col = M->nclass_col;
+  h.pre_kind = M->pre_kind;
+  h.nI = M->nI;
+  h.q = M->q;
+  h.I_idx = at<int32_t>(M, "I_idx");
+  h.AinvII = at<double>(M, "AinvII");
+  h.ALI = at<double>(M, "ALI");
+  h.ARI = at<double>(M, "ARI");
+  h.Shat = at<double>(M, "Shat");
+  h.twid = at<double>(M, "twid");
+  h.yI = at<double>(M, "yI");
+  h.TL = at<double>(M, "TL");
+  h.TR = at<double>(M, "TR");
+  h.XH = at<double>(M, "XH");
+  h.XL = at<double>(M, "XL");
   h.Dr = at<double>(M, "Dr");
   h.Ds = at<double>(M, "Ds");
   h.MDr = at<double>(M, "MDr");

@@ -64,7 +64,20 @@ struct TankDev {
   const double* pre_mass;         // [nclass][NpP][NpP]
   const float* pre_lap32;
   int32_t nclass_col;             // 1 (periodic) or 3 (walls: first, interior, last)
-  int32_t pad0;
+  int32_t pre_kind;               // 0 element-block Jacobi, 1 exact still-water (line Schur + DFT)
+  // exact still-water preconditioner (periodic tanks)
+  int32_t nI, q;                  // interior free nodes per column, free nodes per line
+  const int32_t* I_idx;           // [nI] column-local indices of the interior free nodes
+  const double* AinvII;           // [nI][nI]
+  const double* ALI;              // [q][nI] coupling of the left line to the interior
+  const double* ARI;              // [q][nI] coupling of the right line to the interior
+  const double* Shat;             // [nx][q][q][2] inverse of the line Schur symbol per Fourier mode
+  const double* twid;             // [nx][2] exp(-2 pi i m / nx)
+  double* yI;                     // [nx][nI] interior solves
+  double* TL;                     // [nx][q]
+  double* TR;                     // [nx][q]
+  double* XH;                     // [nx][q][2] modal line solution
+  double* XL;                     // [nx][q] line solution
   // 1D surface operators (P+1)^2 etc.
   const double* M1;
   const double* S1;               // M1 D1
