@@ -78,7 +78,7 @@ typedef enum {
 
 typedef struct {
   int32_t nx, nz;              /* quads in x, layers in sigma (both >= 1)           */
-  int32_t order;               /* polynomial order P, 1..10                         */
+  int32_t order;               /* polynomial order P, 1..8                          */
   int32_t periodic;            /* 1: periodic in x; 0: impermeable walls            */
   double length;               /* L > 0                                             */
   double g;                    /* gravity (9.81)                                    */
@@ -137,6 +137,16 @@ sem_status sem_set_surface(sem_mesh* mesh, const double* eta, const double* eta_
 /* y = op(u) on full-length vectors [n] with the factors of the last
  * sem_set_surface (diagnostic access to the operators of Secs. 3.1.2-3.2). */
 sem_status sem_apply(sem_mesh* mesh, sem_operator op, const double* u, double* y, void* stream);
+
+/* Benchmark support: launch the element kernel of `op` reps times back to
+ * back on `stream` (same inputs, no host synchronisation in between) and
+ * return the mean duration per launch in *ms_host, measured with HIP events
+ * recorded on `stream`.  prec is a sem_precision: FP64 takes double vectors,
+ * FP32_IR and BF16_IR the inner-solve kernels on float vectors (stiffness and
+ * preconditioner only).  Output y as for sem_apply (its shared vertical lines
+ * hold only one block's contribution: use sem_apply for values). */
+sem_status sem_apply_timed(sem_mesh* mesh, sem_operator op, int32_t prec, const void* u, void* y,
+                           int32_t reps, float* ms_host, void* stream);
 
 /* Laplace problem of Sec. 3.1.2 for the surface state (eta, eta_x, phi~):
  * A_FF Phi_F = -A_FS phi~, Phi_S = phi~.  phi [n]: in = initial guess when

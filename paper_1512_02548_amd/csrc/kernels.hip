@@ -17,7 +17,7 @@
 
 #include <cmath>
 
-#include "sem_internal.hpp"
+#include "launch.hpp"
 
 namespace sem {
 
@@ -43,6 +43,50 @@ __device__ inline int64_t right_line_base(const TankDev& d, int c) {
   if (c < d.nx) return (int64_t)c * d.nc;
   return d.periodic ? 0 : (int64_t)d.nx * d.nc;
 }
+
+// precision traits: working type T of vectors and operators, storage type
+// of the geometric factors (double, float or bfloat16 bits)
+struct BF16 {};
+__device__ inline float bf16_to_float(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
+__device__ inline uint16_t float_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  uint32_t r = 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+  return (uint16_t)((u + r) >> 16);
+}
+template <typename T, typename GS>
+struct Prec;
+template <>
+struct Prec<double, double> {
+  __device__ static const double* Dr(const TankDev& d) { return d.Dr; }
+  __device__ static const double* Ds(const TankDev& d) { return d.Ds; }
+  __device__ static const double* MDr(const TankDev& d) { return d.MDr; }
+  __device__ static const double* MDs(const TankDev& d) { return d.MDs; }
+  __device__ static const double* Mref(const TankDev& d) { return d.Mref; }
+  __device__ static const double* pre_lap(const TankDev& d) { return d.pre_lap; }
+  __device__ static const double* AinvII(const TankDev& d) { return d.AinvII; }
+  __device__ static const double* ALI(const TankDev& d) { return d.ALI; }
+  __device__ static const double* ARI(const TankDev& d) { return d.ARI; }
+  __device__ static const double* Shat(const TankDev& d) { return d.Shat; }
+  __device__ static double G(const TankDev& d, int64_t i) { return d.G[i]; }
+};
+template <>
+struct Prec<float, float> {
+  __device__ static const float* Dr(const TankDev& d) { return d.Dr32; }
+  __device__ static const float* Ds(const TankDev& d) { return d.Ds32; }
+  __device__ static const float* MDr(const TankDev& d) { return d.MDr32; }
+  __device__ static const float* MDs(const TankDev& d) { return d.MDs32; }
+  __device__ static const float* Mref(const TankDev& d) { return d.Mref32; }
+  __device__ static const float* pre_lap(const TankDev& d) { return d.pre_lap32; }
+  __device__ static const float* AinvII(const TankDev& d) { return d.AinvII32; }
+  __device__ static const float* ALI(const TankDev& d) { return d.ALI32; }
+  __device__ static const float* ARI(const TankDev& d) { return d.ARI32; }
+  __device__ static const float* Shat(const TankDev& d) { return d.Shat32; }
+  __device__ static float G(const TankDev& d, int64_t i) { return d.G32[i]; }
+};
+template <>
+struct Prec<float, BF16> : Prec<float, float> {
+  __device__ static float G(const TankDev& d, int64_t i) { return bf16_to_float(d.G16[i]); }
+};
 
 // ------------------------------------------------------------ coefficients
 // G = |J| Lam K Lam^T and 1/d at every element node (paper Sec. 2).
@@ -93,39 +137,42 @@ __global__ void k_coef(const TankDev* __restrict__ td, const double* __restrict_
   d.G32[tile_index(d.T, d.NpP, b, eb, m, 3, 0)] = (float)Grr;
   d.G32[tile_index(d.T, d.NpP, b, eb, m, 3, 1)] = (float)Grs;
   d.G32[tile_index(d.T, d.NpP, b, eb, m, 3, 2)] = (float)Gss;
+  d.G16[tile_index(d.T, d.NpP, b, eb, m, 3, 0)] = float_to_bf16((float)Grr);
+  d.G16[tile_index(d.T, d.NpP, b, eb, m, 3, 1)] = float_to_bf16((float)Grs);
+  d.G16[tile_index(d.T, d.NpP, b, eb, m, 3, 2)] = float_to_bf16((float)Gss);
 }
 
 // ------------------------------------------------------------ gather kernels
-enum { OP_STIFF = 0, OP_MASS = 1, OP_PRE_LAP = 2, OP_PRE_MASS = 3, OP_SZ = 4 };
-enum { F_MASK_SURF = 1, F_NEG = 2 };
 
 // Per block: y_owned = sum over the block's elements of op_e(u_e).
 // LDS: region of the input (cb*nc + nl), per-element stage buffers.
-template <int P, int OP>
+template <int P, int OP, typename T = double, typename GS = double>
 __global__ void __launch_bounds__(kBlockThreads)
-k_gather(const TankDev* __restrict__ td, const double* __restrict__ u, double* __restrict__ y,
-         double* __restrict__ side, int flags) {
+k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict__ y,
+         T* __restrict__ side, int flags) {
   const TankDev& d = *td;
+  using PR = Prec<T, GS>;
   constexpr int Np = (P + 1) * (P + 2) / 2;
   constexpr int NpP = (Np + 15) / 16 * 16;
-  extern __shared__ double lds[];
+  extern __shared__ unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
   const int b = blockIdx.x;
   const int c0 = b * d.cb;
   const int cbb = min(d.cb, d.nx - c0);
   const int nc = d.nc, nl = d.nl;
   const int nreg = cbb * nc + nl;
   const int EBb = cbb * 2 * d.nz;
-  double* ureg = lds;                         // [cb*nc + nl]
-  double* st1 = ureg + (d.cb * nc + nl);      // [EB][NpP] first stage
-  double* st2 = st1 + d.EB * NpP;             // [EB][NpP] second stage
-  double* st3 = st2 + d.EB * NpP;             // [EB][NpP] element outputs
+  T* ureg = lds;                         // [cb*nc + nl]
+  T* st1 = ureg + (d.cb * nc + nl);      // [EB][NpP] first stage
+  T* st2 = st1 + d.EB * NpP;             // [EB][NpP] second stage
+  T* st3 = st2 + d.EB * NpP;             // [EB][NpP] element outputs
   // 1. stage the input region
   for (int q = threadIdx.x; q < nreg; q += blockDim.x) {
     int lc = q / nc, ql = q - lc * nc;
     int64_t gi;
     if (lc < cbb) gi = (int64_t)(c0 + lc) * nc + ql;
     else gi = (ql < nl) ? right_line_base(d, c0 + cbb) + ql : -1;
-    ureg[q] = gi >= 0 ? u[gi] : 0.0;
+    ureg[q] = gi >= 0 ? u[gi] : T(0);
   }
   __syncthreads();
   // 2. per-element work, thread per (element, node)
@@ -136,36 +183,41 @@ k_gather(const TankDev* __restrict__ td, const double* __restrict__ u, double* _
       int eb = it / Np, i = it - eb * Np;
       int lc = eb / (2 * d.nz), jt = eb - lc * 2 * d.nz;
       const int32_t* loc = d.elem_loc + jt * NpP;
-      double tr = 0, ts = 0;
+      T tr = 0, ts = 0;
+      const T* Dr = PR::Dr(d);
+      const T* Ds = PR::Ds(d);
       for (int k = 0; k < Np; ++k) {
-        double uk = ureg[lc * nc + loc[k]];
-        tr += d.Dr[i * NpP + k] * uk;
-        ts += d.Ds[i * NpP + k] * uk;
+        T uk = ureg[lc * nc + loc[k]];
+        tr += Dr[i * NpP + k] * uk;
+        ts += Ds[i * NpP + k] * uk;
       }
       if (OP == OP_STIFF) {
-        double grr = d.G[tile_index(d.T, NpP, b, eb, i, 3, 0)];
-        double grs = d.G[tile_index(d.T, NpP, b, eb, i, 3, 1)];
-        double gss = d.G[tile_index(d.T, NpP, b, eb, i, 3, 2)];
+        T grr = PR::G(d, tile_index(d.T, NpP, b, eb, i, 3, 0));
+        T grs = PR::G(d, tile_index(d.T, NpP, b, eb, i, 3, 1));
+        T gss = PR::G(d, tile_index(d.T, NpP, b, eb, i, 3, 2));
         st1[eb * NpP + i] = grr * tr + grs * ts;
         st2[eb * NpP + i] = grs * tr + gss * ts;
       } else {
         const double* lay = d.lay + jt * 8;
-        double dsig = lay[1] * tr + lay[3] * ts;
-        st1[eb * NpP + i] = dsig * d.invd[tile_index(d.T, NpP, b, eb, i, 1, 0)];
+        T dsig = T(lay[1]) * tr + T(lay[3]) * ts;
+        st1[eb * NpP + i] = dsig * T(d.invd[tile_index(d.T, NpP, b, eb, i, 1, 0)]);
       }
     }
     __syncthreads();
     // phase 2
     for (int it = threadIdx.x; it < work; it += blockDim.x) {
       int eb = it / Np, i = it - eb * Np;
-      double acc = 0;
+      T acc = 0;
       if (OP == OP_STIFF) {
+        const T* MDr = PR::MDr(d);
+        const T* MDs = PR::MDs(d);
         for (int k = 0; k < Np; ++k)
-          acc += d.MDr[k * NpP + i] * st1[eb * NpP + k] + d.MDs[k * NpP + i] * st2[eb * NpP + k];
+          acc += MDr[k * NpP + i] * st1[eb * NpP + k] + MDs[k * NpP + i] * st2[eb * NpP + k];
       } else {
         int jt = eb % (2 * d.nz);
-        double J = d.lay[jt * 8 + 4];
-        for (int k = 0; k < Np; ++k) acc += d.Mref[i * NpP + k] * st1[eb * NpP + k];
+        T J = T(d.lay[jt * 8 + 4]);
+        const T* Mr = PR::Mref(d);
+        for (int k = 0; k < Np; ++k) acc += Mr[i * NpP + k] * st1[eb * NpP + k];
         acc *= J;
       }
       st3[eb * NpP + i] = acc;
@@ -175,30 +227,30 @@ k_gather(const TankDev* __restrict__ td, const double* __restrict__ u, double* _
       int eb = it / Np, i = it - eb * Np;
       int lc = eb / (2 * d.nz), jt = eb - lc * 2 * d.nz;
       const int32_t* loc = d.elem_loc + jt * NpP;
-      const double* A;
-      double scale = 1.0;
+      const T* A;
+      T scale = 1;
       if (OP == OP_MASS) {
-        A = d.Mref;
-        scale = d.lay[jt * 8 + 4];
+        A = PR::Mref(d);
+        scale = T(d.lay[jt * 8 + 4]);
       } else {
         int c = c0 + lc;
         int cls = d.nclass_col == 1 ? 0 : (c == 0 ? 0 : (c == d.nx - 1 ? 2 : 1));
         if (d.nclass_col == 3 && d.nx == 1) cls = 0;
-        const double* base = (OP == OP_PRE_LAP) ? d.pre_lap : d.pre_mass;
+        const T* base = (OP == OP_PRE_LAP) ? PR::pre_lap(d) : reinterpret_cast<const T*>(d.pre_mass);
         A = base + ((size_t)(cls * 2 * d.nz + jt)) * NpP * NpP;
       }
-      double acc = 0;
+      T acc = 0;
       for (int k = 0; k < Np; ++k) acc += A[i * NpP + k] * ureg[lc * nc + loc[k]];
       st3[eb * NpP + i] = scale * acc;
     }
   }
   __syncthreads();
   // 3. node sums in a fixed order; store owned nodes, side buffer for the right line
-  const double sgn = (flags & F_NEG) ? -1.0 : 1.0;
+  const T sgn = (flags & F_NEG) ? T(-1) : T(1);
   const int nown = cbb * nc;
   for (int q = threadIdx.x; q < nown + nl; q += blockDim.x) {
     int lc = q / nc, ql = q - lc * nc;
-    double acc = 0;
+    T acc = 0;
     if (lc < cbb) {
       int cnt = d.acc_cnt[ql];
       for (int k = 0; k < cnt; ++k) {
@@ -213,7 +265,7 @@ k_gather(const TankDev* __restrict__ td, const double* __restrict__ u, double* _
         }
       }
       acc *= sgn;
-      if ((flags & F_MASK_SURF) && d.is_surf_loc[ql]) acc = 0.0;
+      if ((flags & F_MASK_SURF) && d.is_surf_loc[ql]) acc = T(0);
       y[(int64_t)(c0 + lc) * nc + ql] = acc;
     } else {
       // right line: contributions of column cbb-1 through its right-line nodes
@@ -225,15 +277,15 @@ k_gather(const TankDev* __restrict__ td, const double* __restrict__ u, double* _
         acc += st3[(cbb - 1) * 2 * d.nz * NpP + (e & 0x3fffffff)];
       }
       acc *= sgn;
-      if ((flags & F_MASK_SURF) && d.is_surf_loc[ql]) acc = 0.0;
+      if ((flags & F_MASK_SURF) && d.is_surf_loc[ql]) acc = T(0);
       side[(size_t)b * nl + ql] = acc;
     }
   }
 }
 
 // adds the right-line contributions of each block to the stored left lines
-__global__ void k_fixup(const TankDev* __restrict__ td, double* __restrict__ y,
-                        const double* __restrict__ side) {
+template <typename T>
+__global__ void k_fixup(const TankDev* __restrict__ td, T* __restrict__ y, const T* __restrict__ side) {
   const TankDev& d = *td;
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= d.nb * d.nl) return;
@@ -241,7 +293,7 @@ __global__ void k_fixup(const TankDev* __restrict__ td, double* __restrict__ y,
   // side[b] belongs to the line at x_{c0 + cbb}
   int c0 = b * d.cb;
   int cend = min(c0 + d.cb, d.nx);
-  double v = side[(size_t)b * d.nl + ql];
+  T v = side[(size_t)b * d.nl + ql];
   if (cend < d.nx) {
     y[(int64_t)cend * d.nc + ql] += v;
   } else if (d.periodic) {
@@ -256,9 +308,11 @@ __global__ void k_fixup(const TankDev* __restrict__ td, double* __restrict__ y,
 // each column's interior free nodes are condensed onto the vertical lines
 // (Schur complement), the resulting block-circulant line system is solved
 // mode by mode after a DFT along x, and the interiors are recovered.
+template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_interior(const TankDev* __restrict__ td, const double* __restrict__ r) {
+k_sd_interior(const TankDev* __restrict__ td, const T* __restrict__ r) {
   const TankDev& d = *td;
+  using PR = Prec<T, T>;
   extern __shared__ double sh[];
   const int c = blockIdx.x, nI = d.nI, q = d.q;
   double* rI = sh;
@@ -266,7 +320,7 @@ k_sd_interior(const TankDev* __restrict__ td, const double* __restrict__ r) {
   for (int i = threadIdx.x; i < nI; i += blockDim.x) rI[i] = r[(int64_t)c * d.nc + d.I_idx[i]];
   __syncthreads();
   for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    const double* A = d.AinvII + (size_t)i * nI;
+    const T* A = PR::AinvII(d) + (size_t)i * nI;
     double acc = 0;
     for (int j = 0; j < nI; ++j) acc += A[j] * rI[j];
     y[i] = acc;
@@ -274,7 +328,7 @@ k_sd_interior(const TankDev* __restrict__ td, const double* __restrict__ r) {
   }
   __syncthreads();
   for (int a = threadIdx.x; a < 2 * q; a += blockDim.x) {
-    const double* A = a < q ? d.ALI + (size_t)a * nI : d.ARI + (size_t)(a - q) * nI;
+    const T* A = a < q ? PR::ALI(d) + (size_t)a * nI : PR::ARI(d) + (size_t)(a - q) * nI;
     double acc = 0;
     for (int i = 0; i < nI; ++i) acc += A[i] * y[i];
     if (a < q) d.TL[(size_t)c * q + a] = acc;
@@ -282,8 +336,10 @@ k_sd_interior(const TankDev* __restrict__ td, const double* __restrict__ r) {
   }
 }
 
-__global__ void k_sd_modes(const TankDev* __restrict__ td, const double* __restrict__ r) {
+template <typename T>
+__global__ void k_sd_modes(const TankDev* __restrict__ td, const T* __restrict__ r) {
   const TankDev& d = *td;
+  using PR = Prec<T, T>;
   extern __shared__ double gh[];  // [q][2]
   const int k = blockIdx.x, q = d.q, nx = d.nx;
   for (int j = threadIdx.x; j < q; j += blockDim.x) {
@@ -300,7 +356,7 @@ __global__ void k_sd_modes(const TankDev* __restrict__ td, const double* __restr
   }
   __syncthreads();
   for (int i = threadIdx.x; i < q; i += blockDim.x) {
-    const double* S = d.Shat + ((size_t)k * q + i) * q * 2;
+    const T* S = PR::Shat(d) + ((size_t)k * q + i) * q * 2;
     double xr = 0, xi = 0;
     for (int j = 0; j < q; ++j) {
       double sr = S[2 * j], si = S[2 * j + 1];
@@ -312,7 +368,8 @@ __global__ void k_sd_modes(const TankDev* __restrict__ td, const double* __restr
   }
 }
 
-__global__ void k_sd_lines(const TankDev* __restrict__ td, double* __restrict__ z) {
+template <typename T>
+__global__ void k_sd_lines(const TankDev* __restrict__ td, T* __restrict__ z) {
   const TankDev& d = *td;
   const int c = blockIdx.x, q = d.q, nx = d.nx;
   for (int j = threadIdx.x; j < q; j += blockDim.x) {
@@ -326,12 +383,14 @@ __global__ void k_sd_lines(const TankDev* __restrict__ td, double* __restrict__ 
     z[(int64_t)c * d.nc + j] = acc;
     d.XL[(size_t)c * q + j] = acc;
   }
-  if (threadIdx.x == 0) z[(int64_t)c * d.nc + d.nl - 1] = 0.0;
+  if (threadIdx.x == 0) z[(int64_t)c * d.nc + d.nl - 1] = T(0);
 }
 
+template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_back(const TankDev* __restrict__ td, double* __restrict__ z) {
+k_sd_back(const TankDev* __restrict__ td, T* __restrict__ z) {
   const TankDev& d = *td;
+  using PR = Prec<T, T>;
   extern __shared__ double sh[];
   const int c = blockIdx.x, nI = d.nI, q = d.q;
   const int cn = c + 1 == d.nx ? 0 : c + 1;
@@ -345,17 +404,19 @@ k_sd_back(const TankDev* __restrict__ td, double* __restrict__ z) {
   __syncthreads();
   for (int i = threadIdx.x; i < nI; i += blockDim.x) {
     double acc = 0;
-    for (int a = 0; a < q; ++a) acc += d.ALI[(size_t)a * nI + i] * xl[a] + d.ARI[(size_t)a * nI + i] * xr[a];
+    const T* ALI = PR::ALI(d);
+    const T* ARI = PR::ARI(d);
+    for (int a = 0; a < q; ++a) acc += ALI[(size_t)a * nI + i] * xl[a] + ARI[(size_t)a * nI + i] * xr[a];
     v[i] = acc;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    const double* A = d.AinvII + (size_t)i * nI;
+    const T* A = PR::AinvII(d) + (size_t)i * nI;
     double acc = 0;
     for (int j = 0; j < nI; ++j) acc += A[j] * v[j];
-    z[(int64_t)c * d.nc + d.I_idx[i]] = d.yI[(size_t)c * nI + i] - acc;
+    z[(int64_t)c * d.nc + d.I_idx[i]] = T(d.yI[(size_t)c * nI + i] - acc);
   }
-  for (int k = 1 + threadIdx.x; k < d.P; k += blockDim.x) z[(int64_t)c * d.nc + d.surf_loc[k]] = 0.0;
+  for (int k = 1 + threadIdx.x; k < d.P; k += blockDim.x) z[(int64_t)c * d.nc + d.surf_loc[k]] = T(0);
 }
 
 // ------------------------------------------------------------ vector kernels
@@ -416,15 +477,16 @@ __global__ void k_gather_surface(const TankDev* __restrict__ td, const double* _
 
 // partial dot products: part[blk][k] = sum over the chunk of X_k . w
 // X_k = X + k*ldx, k < nvec; chunk = [blk*chunk, (blk+1)*chunk)
+template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_dots(int64_t n, int nvec, const double* __restrict__ X, int64_t ldx, const double* __restrict__ w,
+k_dots(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, const T* __restrict__ w,
        double* __restrict__ part, int ldp, int64_t chunk) {
   __shared__ double red[kBlockThreads];
   int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
   for (int k = 0; k < nvec; ++k) {
-    const double* x = X + k * ldx;
+    const T* x = X + k * ldx;
     double s = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += x[i] * w[i];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += (double)x[i] * (double)w[i];
     s = block_sum(s, red);
     if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp + k] = s;
   }
@@ -444,9 +506,10 @@ k_reduce(int nblk, int nvec, const double* __restrict__ part, int ldp, double* _
 
 // ------------------------------------------------------------ GMRES pieces
 // w' = w - sum_{i<=j} h_i V_i  and partial ||w'||^2
+template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_orth(int64_t n, int j, const double* __restrict__ V, const double* __restrict__ hcol,
-       double* __restrict__ w, double* __restrict__ part, int ldp, int64_t chunk,
+k_orth(int64_t n, int j, const T* __restrict__ V, const double* __restrict__ hcol,
+       T* __restrict__ w, double* __restrict__ part, int ldp, int64_t chunk,
        const KrylovState* __restrict__ ks) {
   __shared__ double red[kBlockThreads];
   if (ks->done) return;
@@ -454,9 +517,10 @@ k_orth(int64_t n, int j, const double* __restrict__ V, const double* __restrict_
   double s = 0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     double v = w[i];
-    for (int k = 0; k <= j; ++k) v -= hcol[k] * V[(int64_t)k * n + i];
-    w[i] = v;
-    s += v * v;
+    for (int k = 0; k <= j; ++k) v -= hcol[k] * (double)V[(int64_t)k * n + i];
+    T vt = T(v);
+    w[i] = vt;
+    s += (double)vt * (double)vt;
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp] = s;
@@ -506,14 +570,15 @@ __global__ void k_givens(KrylovState* __restrict__ ks, double* __restrict__ Hbas
 }
 
 // V_{j+1} = w' / hn
-__global__ void k_scale_next(int64_t n, int j, const double* __restrict__ w, double* __restrict__ V,
+template <typename T>
+__global__ void k_scale_next(int64_t n, int j, const T* __restrict__ w, T* __restrict__ V,
                              const double* __restrict__ Hbase, int m, const KrylovState* __restrict__ ks) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (ks->converged) return;
   const double* g = Hbase + (m + 1) * m + 2 * m;
   double hn = g[m + 1 + j];
-  if (j + 1 < m + 1) V[(int64_t)(j + 1) * n + i] = (hn > 0.0) ? w[i] / hn : 0.0;
+  if (j + 1 < m + 1) V[(int64_t)(j + 1) * n + i] = (hn > 0.0) ? T((double)w[i] / hn) : T(0);
 }
 
 // solve the triangular system for y (single thread) then x += Z y (all threads)
@@ -530,16 +595,17 @@ __global__ void k_solve_y(KrylovState* __restrict__ ks, double* __restrict__ Hba
   }
 }
 
-__global__ void k_update_x(int64_t n, const double* __restrict__ Z, const double* __restrict__ Hbase,
-                           int m, const KrylovState* __restrict__ ks, double* __restrict__ x) {
+template <typename T>
+__global__ void k_update_x(int64_t n, const T* __restrict__ Z, const double* __restrict__ Hbase,
+                           int m, const KrylovState* __restrict__ ks, T* __restrict__ x) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double* g = Hbase + (m + 1) * m + 2 * m;
   const double* y = g + (m + 1) + m;
   int jn = ks->j;
   double v = x[i];
-  for (int k = 0; k < jn; ++k) v += y[k] * Z[(int64_t)k * n + i];
-  x[i] = v;
+  for (int k = 0; k < jn; ++k) v += y[k] * (double)Z[(int64_t)k * n + i];
+  x[i] = T(v);
 }
 
 // start of a cycle: r is in V_0 (masked); beta = sqrt(rr); V_0 = r/beta; g = (beta, 0, ...)
@@ -572,20 +638,34 @@ __global__ void k_cycle_start(KrylovState* __restrict__ ks, double* __restrict__
   }
 }
 
-__global__ void k_scale_v0(int64_t n, double* __restrict__ V, const KrylovState* __restrict__ ks) {
+template <typename T>
+__global__ void k_scale_v0(int64_t n, T* __restrict__ V, const KrylovState* __restrict__ ks) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || ks->done) return;
-  V[i] = V[i] / ks->beta;
+  V[i] = T((double)V[i] / ks->beta);
 }
 
 // r = b - y (masked at the surface for the Laplace problem)
-__global__ void k_residual(const TankDev* __restrict__ td, int64_t n, const double* __restrict__ bvec,
-                           const double* __restrict__ y, double* __restrict__ r, int mask) {
+template <typename T>
+__global__ void k_residual(const TankDev* __restrict__ td, int64_t n, const T* __restrict__ bvec,
+                           const T* __restrict__ y, T* __restrict__ r, int mask) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double v = bvec[i] - y[i];
-  if (mask && is_surface_node(*td, i)) v = 0.0;
+  T v = bvec[i] - y[i];
+  if (mask && is_surface_node(*td, i)) v = T(0);
   r[i] = v;
+}
+
+// r32 = (float)(r * scale)
+__global__ void k_to_float(int64_t n, const double* __restrict__ r, double scale, float* __restrict__ r32) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r32[i] = (float)(r[i] * scale);
+}
+
+// x += scale * x32
+__global__ void k_add_float(int64_t n, const float* __restrict__ x32, double scale, double* __restrict__ x) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += scale * (double)x32[i];
 }
 
 // ------------------------------------------------------------ 1D surface work
@@ -877,8 +957,8 @@ k_rk4_final(const TankDev* __restrict__ td, double dt, const double* __restrict_
 
 static inline unsigned nblk(int64_t n, int t = kBlockThreads) { return (unsigned)((n + t - 1) / t); }
 
-size_t gather_lds_bytes(const TankDev& h) {
-  return sizeof(double) * ((size_t)h.cb * h.nc + h.nl + 3 * (size_t)h.EB * h.NpP);
+size_t gather_lds_bytes(const TankDev& h, size_t word) {
+  return word * ((size_t)h.cb * h.nc + h.nl + 3 * (size_t)h.EB * h.NpP);
 }
 
 void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const double* etax, int what,
@@ -887,28 +967,72 @@ void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const do
   SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_coef<PP>, dim3(nblk(total)), dim3(kBlockThreads), 0, st, d, eta, etax, what));
 }
 
-void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side,
-                   int flags, hipStream_t st) {
-  if (op == OP_PRE_LAP && h.pre_kind == 1) {
-    size_t s1 = sizeof(double) * 2 * h.nI, s4 = sizeof(double) * (2 * h.q + h.nI);
-    hipLaunchKernelGGL(k_sd_interior, dim3(h.nx), dim3(kBlockThreads), s1, st, d, u);
-    hipLaunchKernelGGL(k_sd_modes, dim3(h.nx), dim3(64), sizeof(double) * 2 * h.q, st, d, u);
-    hipLaunchKernelGGL(k_sd_lines, dim3(h.nx), dim3(64), 0, st, d, y);
-    hipLaunchKernelGGL(k_sd_back, dim3(h.nx), dim3(kBlockThreads), s4, st, d, y);
-    return;
-  }
-  size_t lds = gather_lds_bytes(h);
+template <typename T>
+static void launch_sd(const TankDev& h, const TankDev* d, const T* u, T* y, hipStream_t st) {
+  size_t s1 = sizeof(double) * 2 * h.nI, s4 = sizeof(double) * (2 * h.q + h.nI);
+  hipLaunchKernelGGL(k_sd_interior<T>, dim3(h.nx), dim3(kBlockThreads), s1, st, d, u);
+  hipLaunchKernelGGL(k_sd_modes<T>, dim3(h.nx), dim3(64), sizeof(double) * 2 * h.q, st, d, u);
+  hipLaunchKernelGGL(k_sd_lines<T>, dim3(h.nx), dim3(64), 0, st, d, y);
+  hipLaunchKernelGGL(k_sd_back<T>, dim3(h.nx), dim3(kBlockThreads), s4, st, d, y);
+}
+
+// element kernel only (no line fix-up)
+template <typename T, typename GS>
+static void gather_kernel(const TankDev& h, const TankDev* d, int op, const T* u, T* y, T* side, int flags,
+                          hipStream_t st) {
+  size_t lds = gather_lds_bytes(h, sizeof(T));
   dim3 g(h.nb), b(kBlockThreads);
-#define SEM_G(OPV) SEM_P_SWITCH(h.P, hipLaunchKernelGGL((k_gather<PP, OPV>), g, b, lds, st, d, u, y, side, flags))
-  switch (op) {
-    case OP_STIFF: SEM_G(OP_STIFF); break;
-    case OP_MASS: SEM_G(OP_MASS); break;
-    case OP_PRE_LAP: SEM_G(OP_PRE_LAP); break;
-    case OP_PRE_MASS: SEM_G(OP_PRE_MASS); break;
-    case OP_SZ: SEM_G(OP_SZ); break;
+#define SEM_G(OPV) SEM_P_SWITCH(h.P, hipLaunchKernelGGL((k_gather<PP, OPV, T, GS>), g, b, lds, st, d, u, y, side, flags))
+  if (sizeof(T) == sizeof(double)) {
+    switch (op) {
+      case OP_STIFF: SEM_G(OP_STIFF); break;
+      case OP_MASS: SEM_G(OP_MASS); break;
+      case OP_PRE_LAP: SEM_G(OP_PRE_LAP); break;
+      case OP_PRE_MASS: SEM_G(OP_PRE_MASS); break;
+      case OP_SZ: SEM_G(OP_SZ); break;
+    }
+  } else {
+    switch (op) {
+      case OP_STIFF: SEM_G(OP_STIFF); break;
+      case OP_PRE_LAP: SEM_G(OP_PRE_LAP); break;
+    }
   }
 #undef SEM_G
-  hipLaunchKernelGGL(k_fixup, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side);
+}
+
+template <typename T, typename GS>
+static void gather_full(const TankDev& h, const TankDev* d, int op, const T* u, T* y, T* side, int flags,
+                        hipStream_t st) {
+  if (op == OP_PRE_LAP && h.pre_kind == 1) {
+    launch_sd<T>(h, d, u, y, st);
+    return;
+  }
+  gather_kernel<T, GS>(h, d, op, u, y, side, flags, st);
+  hipLaunchKernelGGL(k_fixup<T>, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side);
+}
+
+void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side,
+                   int flags, hipStream_t st) {
+  gather_full<double, double>(h, d, op, u, y, side, flags, st);
+}
+void launch_gather(const TankDev& h, const TankDev* d, int op, const float* u, float* y, float* side, int flags,
+                   int gstore, hipStream_t st) {
+  if (gstore == 2) gather_full<float, BF16>(h, d, op, u, y, side, flags, st);
+  else gather_full<float, float>(h, d, op, u, y, side, flags, st);
+}
+
+// element kernel of an operator without the line fix-up (timing support);
+// prec 0 = FP64, 1 = FP32, 2 = FP32 with bfloat16 factors
+void launch_gather_only(const TankDev& h, const TankDev* d, int op, int prec, const void* u, void* y, void* side,
+                        hipStream_t st) {
+  if (prec == 0) {
+    if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<double>(h, d, (const double*)u, (double*)y, st);
+    else gather_kernel<double, double>(h, d, op, (const double*)u, (double*)y, (double*)side, 0, st);
+  } else {
+    if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<float>(h, d, (const float*)u, (float*)y, st);
+    else if (prec == 2) gather_kernel<float, BF16>(h, d, op, (const float*)u, (float*)y, (float*)side, 0, st);
+    else gather_kernel<float, float>(h, d, op, (const float*)u, (float*)y, (float*)side, 0, st);
+  }
 }
 
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
@@ -941,22 +1065,40 @@ void dot_layout(int64_t n, int* nchunk, int64_t* chunk) {
   *chunk = c;
 }
 
-void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
-                 double* out, hipStream_t st) {
+template <typename T>
+static void dots_t(int64_t n, int nvec, const T* X, int64_t ldx, const T* w, double* part, int ldp, double* out,
+                   hipStream_t st) {
   int nc;
   int64_t chunk;
   dot_layout(n, &nc, &chunk);
-  hipLaunchKernelGGL(k_dots, dim3(nc), dim3(kBlockThreads), 0, st, n, nvec, X, ldx, w, part, ldp, chunk);
+  hipLaunchKernelGGL(k_dots<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, nvec, X, ldx, w, part, ldp, chunk);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlockThreads), 0, st, nc, nvec, part, ldp, out);
 }
+void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
+                 double* out, hipStream_t st) {
+  dots_t<double>(n, nvec, X, ldx, w, part, ldp, out, st);
+}
+void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
+                 double* out, hipStream_t st) {
+  dots_t<float>(n, nvec, X, ldx, w, part, ldp, out, st);
+}
 
-void launch_orth(int64_t n, int j, const double* V, const double* hcol, double* w, double* part, int ldp,
-                 double* out, const KrylovState* ks, hipStream_t st) {
+template <typename T>
+static void orth_t(int64_t n, int j, const T* V, const double* hcol, T* w, double* part, int ldp, double* out,
+                   const KrylovState* ks, hipStream_t st) {
   int nc;
   int64_t chunk;
   dot_layout(n, &nc, &chunk);
-  hipLaunchKernelGGL(k_orth, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, hcol, w, part, ldp, chunk, ks);
+  hipLaunchKernelGGL(k_orth<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, hcol, w, part, ldp, chunk, ks);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlockThreads), 0, st, nc, 1, part, ldp, out);
+}
+void launch_orth(int64_t n, int j, const double* V, const double* hcol, double* w, double* part, int ldp,
+                 double* out, const KrylovState* ks, hipStream_t st) {
+  orth_t<double>(n, j, V, hcol, w, part, ldp, out, ks, st);
+}
+void launch_orth(int64_t n, int j, const float* V, const double* hcol, float* w, double* part, int ldp,
+                 double* out, const KrylovState* ks, hipStream_t st) {
+  orth_t<float>(n, j, V, hcol, w, part, ldp, out, ks, st);
 }
 
 void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, int32_t* status, hipStream_t st) {
@@ -964,22 +1106,47 @@ void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, 
 }
 void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m,
                        const KrylovState* ks, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_next, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, j, w, V, H, m, ks);
+  hipLaunchKernelGGL(k_scale_next<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, j, w, V, H, m, ks);
+}
+void launch_scale_next(int64_t n, int j, const float* w, float* V, const double* H, int m,
+                       const KrylovState* ks, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_next<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, j, w, V, H, m, ks);
 }
 void launch_solve_update(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x,
                          hipStream_t st) {
   hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, ks, H, m);
-  hipLaunchKernelGGL(k_update_x, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
+  hipLaunchKernelGGL(k_update_x<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
+}
+void launch_solve_update(int64_t n, const float* Z, double* H, int m, KrylovState* ks, float* x,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, ks, H, m);
+  hipLaunchKernelGGL(k_update_x<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
 }
 void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status,
                         int64_t n, double* V, hipStream_t st) {
   hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status);
-  hipLaunchKernelGGL(k_scale_v0, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, V, ks);
+  hipLaunchKernelGGL(k_scale_v0<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, V, ks);
+}
+void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status,
+                        int64_t n, float* V, hipStream_t st) {
+  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status);
+  hipLaunchKernelGGL(k_scale_v0<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, V, ks);
 }
 void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
                      int mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual, dim3(nblk(n)), dim3(kBlockThreads), 0, st, d, n, b, y, r, mask);
+  hipLaunchKernelGGL(k_residual<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, d, n, b, y, r, mask);
 }
+void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y, float* r,
+                     int mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, d, n, b, y, r, mask);
+}
+void launch_to_float(int64_t n, const double* r, double scale, float* r32, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_float, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, r, scale, r32);
+}
+void launch_add_float(int64_t n, const float* x32, double scale, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_float, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, x32, scale, x);
+}
+void launch_fill_f(int64_t n, float* y, hipStream_t st) { hipMemsetAsync(y, 0, n * sizeof(float), st); }
 
 void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, double* out0, const double* in1,
                        double* out1, hipStream_t st) {

@@ -1,0 +1,62 @@
+// Host-side declarations of the kernel launchers (kernels.hip).  Overloads
+// select the working precision from the pointer types.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sem_internal.hpp"
+
+namespace sem {
+enum { OP_STIFF = 0, OP_MASS = 1, OP_PRE_LAP = 2, OP_PRE_MASS = 3, OP_SZ = 4 };
+enum { F_MASK_SURF = 1, F_NEG = 2 };
+
+size_t gather_lds_bytes(const TankDev& h, size_t word);
+void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const double* etax, int what, hipStream_t st);
+void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side, int flags,
+                   hipStream_t st);
+void launch_gather(const TankDev& h, const TankDev* d, int op, const float* u, float* y, float* side, int flags,
+                   int gstore, hipStream_t st);
+void launch_gather_only(const TankDev& h, const TankDev* d, int op, int prec, const void* u, void* y, void* side,
+                        hipStream_t st);
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
+void launch_fill(int64_t n, double v, double* y, hipStream_t st);
+void launch_fill_f(int64_t n, float* y, hipStream_t st);
+void launch_mask_surface(const TankDev& h, const TankDev* d, double* y, hipStream_t st);
+void launch_scatter_surface(const TankDev& h, const TankDev* d, const double* phis, double* u, int zero_rest,
+                            hipStream_t st);
+void launch_gather_surface(const TankDev& h, const TankDev* d, const double* u, double* out, hipStream_t st);
+void dot_layout(int64_t n, int* nchunk, int64_t* chunk);
+void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
+                 double* out, hipStream_t st);
+void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
+                 double* out, hipStream_t st);
+void launch_orth(int64_t n, int j, const double* V, const double* hcol, double* w, double* part, int ldp,
+                 double* out, const KrylovState* ks, hipStream_t st);
+void launch_orth(int64_t n, int j, const float* V, const double* hcol, float* w, double* part, int ldp,
+                 double* out, const KrylovState* ks, hipStream_t st);
+void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, int32_t* status, hipStream_t st);
+void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m, const KrylovState* ks,
+                       hipStream_t st);
+void launch_scale_next(int64_t n, int j, const float* w, float* V, const double* H, int m, const KrylovState* ks,
+                       hipStream_t st);
+void launch_solve_update(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x, hipStream_t st);
+void launch_solve_update(int64_t n, const float* Z, double* H, int m, KrylovState* ks, float* x, hipStream_t st);
+void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status, int64_t n,
+                        double* V, hipStream_t st);
+void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status, int64_t n,
+                        float* V, hipStream_t st);
+void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
+                     int mask, hipStream_t st);
+void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y, float* r,
+                     int mask, hipStream_t st);
+void launch_to_float(int64_t n, const double* r, double scale, float* r32, hipStream_t st);
+void launch_add_float(int64_t n, const float* x32, double scale, double* x, hipStream_t st);
+void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, double* out0, const double* in1,
+                       double* out1, hipStream_t st);
+void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const double* etax, const double* phix,
+                   const double* ws, double* et, double* pt, hipStream_t st);
+void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,
+                      const double* ke, const double* kp, double* ye, double* yp, double* acce, double* accp,
+                      hipStream_t st);
+void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const double* acce, const double* accp,
+                      double* eta, double* phi, int use_filter, hipStream_t st);
+}  // namespace sem

@@ -18,42 +18,7 @@
 #include "host_refelem.hpp"
 #include "sem_internal.hpp"
 
-namespace sem {
-// kernel launchers (kernels.hip)
-size_t gather_lds_bytes(const TankDev& h);
-void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const double* etax, int what, hipStream_t st);
-void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side, int flags,
-                   hipStream_t st);
-void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
-void launch_fill(int64_t n, double v, double* y, hipStream_t st);
-void launch_mask_surface(const TankDev& h, const TankDev* d, double* y, hipStream_t st);
-void launch_scatter_surface(const TankDev& h, const TankDev* d, const double* phis, double* u, int zero_rest,
-                            hipStream_t st);
-void launch_gather_surface(const TankDev& h, const TankDev* d, const double* u, double* out, hipStream_t st);
-void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
-                 double* out, hipStream_t st);
-void launch_orth(int64_t n, int j, const double* V, const double* hcol, double* w, double* part, int ldp,
-                 double* out, const KrylovState* ks, hipStream_t st);
-void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, int32_t* status, hipStream_t st);
-void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m,
-                       const KrylovState* ks, hipStream_t st);
-void launch_solve_update(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x,
-                         hipStream_t st);
-void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status,
-                        int64_t n, double* V, hipStream_t st);
-void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
-                     int mask, hipStream_t st);
-void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, double* out0, const double* in1,
-                       double* out1, hipStream_t st);
-void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const double* etax, const double* phix,
-                   const double* ws, double* et, double* pt, hipStream_t st);
-void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,
-                      const double* ke, const double* kp, double* ye, double* yp, double* acce, double* accp,
-                      hipStream_t st);
-void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const double* acce, const double* accp,
-                      double* eta, double* phi, int use_filter, hipStream_t st);
-void dot_layout(int64_t n, int* nchunk, int64_t* chunk);
-}  // namespace sem
+#include "launch.hpp"
 
 using namespace sem;
 
@@ -565,6 +530,10 @@ static sem_status build_mesh(sem_mesh* M) {
   put(M, "ARI", ARI);
   put(M, "Shat", Shat);
   put(M, "twid", twid);
+  put(M, "AinvII32", tof(AinvII));
+  put(M, "ALI32", tof(ALI));
+  put(M, "ARI32", tof(ARI));
+  put(M, "Shat32", tof(Shat));
   reserve(M, "yI", (size_t)nx * std::max(1, M->nI) * sizeof(double));
   reserve(M, "TL", (size_t)nx * std::max(1, M->q) * sizeof(double));
   reserve(M, "TR", (size_t)nx * std::max(1, M->q) * sizeof(double));
@@ -580,6 +549,7 @@ static sem_status build_mesh(sem_mesh* M) {
   const int ldp = m + 2;
   reserve(M, "G", tiles * 3 * sizeof(double));
   reserve(M, "G32", tiles * 3 * sizeof(float));
+  reserve(M, "G16", tiles * 3 * sizeof(uint16_t));
   reserve(M, "invd", tiles * sizeof(double));
   reserve(M, "status", 64);
   reserve(M, "ks", sizeof(KrylovState));
@@ -598,6 +568,8 @@ static sem_status build_mesh(sem_mesh* M) {
   reserve(M, "V32", (size_t)(m + 1) * n * sizeof(float));
   reserve(M, "Z32", (size_t)m * n * sizeof(float));
   reserve(M, "w32", n * sizeof(float));
+  reserve(M, "x32", n * sizeof(float));
+  reserve(M, "b32", n * sizeof(float));
   return SEM_OK;
 }
 
@@ -718,6 +690,13 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.ARI = at<double>(M, "ARI");
   h.Shat = at<double>(M, "Shat");
   h.twid = at<double>(M, "twid");
+  h.AinvII32 = at<float>(M, "AinvII32");
+  h.ALI32 = at<float>(M, "ALI32");
+  h.ARI32 = at<float>(M, "ARI32");
+  h.Shat32 = at<float>(M, "Shat32");
+  h.G16 = at<uint16_t>(M, "G16");
+  h.x32 = at<float>(M, "x32");
+  h.b32 = at<float>(M, "b32");
   h.yI = at<double>(M, "yI");
   h.TL = at<double>(M, "TL");
   h.TR = at<double>(M, "TR");
@@ -780,7 +759,8 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   HIPCHK(hipMemsetAsync(h.status, 0, 64, st));
   HIPCHK(hipMemsetAsync(h.wmass, 0, M->n * sizeof(double), st));
   HIPCHK(hipMemsetAsync(h.G, 0, M->off.at("G32") - M->off.at("G"), st));
-  HIPCHK(hipMemsetAsync(h.G32, 0, M->off.at("invd") - M->off.at("G32"), st));
+  HIPCHK(hipMemsetAsync(h.G32, 0, M->off.at("G16") - M->off.at("G32"), st));
+  HIPCHK(hipMemsetAsync(h.G16, 0, M->off.at("invd") - M->off.at("G16"), st));
   HIPCHK(hipMemsetAsync(h.invd, 0, M->off.at("status") - M->off.at("invd"), st));
   HIPCHK(hipStreamSynchronize(st));
   M->bound = true;
@@ -818,11 +798,30 @@ struct GmresCfg {
   double rtol;
   int max_iter;
   int poll;
+  int gstore;   // FP32 path: 1 = FP32 factors, 2 = bfloat16 factors
 };
 
-// Restarted right-preconditioned GMRES on device vectors: x (in: guess, out:
-// solution), b.  Iterations and final estimate are returned.
-static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, double* x, const double* b, int* iters_out,
+struct KrylovBuf {
+  double *V, *Z, *w, *side;
+};
+struct KrylovBufF {
+  float *V, *Z, *w, *side;
+};
+
+static void gather_t(sem_mesh* M, const GmresCfg& c, int op, const double* u, double* y, double* side, int flags,
+                     hipStream_t st) {
+  launch_gather(M->hd, M->dtank, op, u, y, side, flags, st);
+}
+static void gather_t(sem_mesh* M, const GmresCfg& c, int op, const float* u, float* y, float* side, int flags,
+                     hipStream_t st) {
+  launch_gather(M->hd, M->dtank, op, u, y, side, flags, c.gstore, st);
+}
+
+// Restarted right-preconditioned GMRES (classical Gram-Schmidt, Givens
+// rotations) on device vectors of type T: x (in: guess, out: solution), b.
+// Inner products, the Hessenberg matrix and the rotations are FP64.
+template <typename T, typename Buf>
+static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, const T* b, int* iters_out,
                         double* relres_out, hipStream_t st) {
   const TankDev& h = M->hd;
   const TankDev* d = M->dtank;
@@ -830,12 +829,10 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, double* x, const doubl
   const int64_t n = M->n;
   const int ldp = m + 2;
   double* scal = M->scal;
-  double* side = h.side;
   const int flags = cfg.mask ? 1 : 0;
   KrylovState ks0{};
   ks0.rtol = cfg.rtol;
   HIPCHK(hipMemcpyAsync(h.ks, &ks0, sizeof(ks0), hipMemcpyHostToDevice, st));
-  // ||b||
   launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, st);
   int total = 0;
   KrylovState hks{};
@@ -843,52 +840,56 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, double* x, const doubl
   int poll = std::max(1, cfg.poll);
   while (true) {
     // r = b - A x
-    launch_gather(h, d, cfg.op, x, h.w, side, flags, st);
-    launch_residual(h, d, n, b, h.w, h.V, cfg.mask ? 1 : 0, st);
-    launch_dots(n, 1, h.V, 0, h.V, h.part, ldp, scal + 0, st);
-    launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, h.V, st);
+    gather_t(M, cfg, cfg.op, x, B.w, B.side, flags, st);
+    launch_residual(h, d, n, b, B.w, B.V, cfg.mask ? 1 : 0, st);
+    launch_dots(n, 1, B.V, 0, B.V, h.part, ldp, scal + 0, st);
+    launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, B.V, st);
     first = false;
     HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (hks.status) break;
-    if (hks.converged) break;
-    if (total >= cfg.max_iter) break;
+    if (hks.status || hks.converged || total >= cfg.max_iter) break;
     for (int j = 0; j < m; ++j) {
-      double* Vj = h.V + (size_t)j * n;
-      double* Zj = h.Zb + (size_t)j * n;
-      launch_gather(h, d, cfg.pre, Vj, Zj, side, flags, st);
-      launch_gather(h, d, cfg.op, Zj, h.w, side, flags, st);
+      T* Vj = B.V + (size_t)j * n;
+      T* Zj = B.Z + (size_t)j * n;
+      gather_t(M, cfg, cfg.pre, Vj, Zj, B.side, flags, st);
+      gather_t(M, cfg, cfg.op, Zj, B.w, B.side, flags, st);
       double* Hcol = h.H + (size_t)j * (m + 1);
-      launch_dots(n, j + 1, h.V, n, h.w, h.part, ldp, Hcol, st);
-      launch_orth(n, j, h.V, Hcol, h.w, h.part, ldp, scal + 2, h.ks, st);
+      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, st);
+      launch_orth(n, j, B.V, Hcol, B.w, h.part, ldp, scal + 2, h.ks, st);
       launch_givens(h.ks, h.H, m, j, scal + 2, h.status, st);
-      launch_scale_next(n, j, h.w, h.V, h.H, m, h.ks, st);
+      launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
       if ((j + 1) % poll == 0 || j == m - 1 || total + j + 1 >= cfg.max_iter) {
         HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (hks.done || total + j + 1 >= cfg.max_iter) break;
       }
     }
-    launch_solve_update(n, h.Zb, h.H, m, h.ks, x, st);
+    launch_solve_update(n, B.Z, h.H, m, h.ks, x, st);
     HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     total = hks.iters;
-    if (hks.status) break;
-    if (hks.converged) break;
-    if (total >= cfg.max_iter) break;
+    if (hks.status || hks.converged || total >= cfg.max_iter) break;
   }
   *iters_out = hks.iters;
   *relres_out = hks.bnorm > 0 ? hks.resid / hks.bnorm : 0.0;
   if (hks.status) return status_from_word(hks.status);
-  if (!hks.converged) {
-    int32_t w = ST_NOCONV;
-    HIPCHK(hipMemcpyAsync(&w, h.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    w |= ST_NOCONV;
-    HIPCHK(hipMemcpyAsync(h.status, &w, sizeof(int32_t), hipMemcpyHostToDevice, st));
-    return SEM_E_NOCONV;
-  }
+  if (!hks.converged) return SEM_E_NOCONV;
   return SEM_OK;
+}
+
+static sem_status set_status_bits(sem_mesh* M, int32_t bits, hipStream_t st) {
+  int32_t w = 0;
+  HIPCHK(hipMemcpyAsync(&w, M->hd.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  w |= bits;
+  HIPCHK(hipMemcpyAsync(M->hd.status, &w, sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SEM_OK;
+}
+
+static KrylovBuf buf64(sem_mesh* M) { return KrylovBuf{M->hd.V, M->hd.Zb, M->hd.w, M->hd.side}; }
+static KrylovBufF buf32(sem_mesh* M) {
+  return KrylovBufF{M->hd.V32, M->hd.Z32, M->hd.w32, reinterpret_cast<float*>(M->hd.side)};
 }
 
 static void default_opts(sem_solve_opts* o) {
@@ -931,7 +932,44 @@ extern "C" sem_status sem_apply(sem_mesh* M, sem_operator op, const double* u, d
   return SEM_OK;
 }
 
+extern "C" sem_status sem_apply_timed(sem_mesh* M, sem_operator op, int32_t prec, const void* u, void* y,
+                                      int32_t reps, float* ms, void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!u || !y || !ms || reps < 1) return fail(SEM_E_INVAL, "bad argument");
+  if (prec < 0 || prec > 2) return fail(SEM_E_INVAL, "unknown precision");
+  if (prec != 0 && op != SEM_OP_STIFFNESS && op != SEM_OP_PRECOND)
+    return fail(SEM_E_INVAL, "reduced precision exists for the stiffness and the preconditioner only");
+  int kop;
+  switch (op) {
+    case SEM_OP_STIFFNESS: kop = 0; break;
+    case SEM_OP_MASS2D: kop = 1; break;
+    case SEM_OP_PRECOND: kop = 2; break;
+    case SEM_OP_SZ: kop = 4; break;
+    default: return fail(SEM_E_INVAL, "unknown operator");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  void* side = prec == 0 ? (void*)M->hd.side : (void*)M->hd.w32;
+  launch_gather_only(M->hd, M->dtank, kop, prec, u, y, side, st);   // warm-up launch
+  HIPCHK(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i) launch_gather_only(M->hd, M->dtank, kop, prec, u, y, side, st);
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  *ms = t / reps;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return SEM_OK;
+}
+
 // Laplace solve on the device with factors already set; phi in/out [n].
+// FP64: GMRES on A_FF x = b.  FP32_IR / BF16_IR: FP64 iterative refinement,
+// each correction from an FP32 GMRES solve (FP32 vectors and operators, FP32
+// or bfloat16 geometric factors, FP64 inner products) scaled by ||r||.
 static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, const sem_solve_opts* o,
                                sem_solve_stats* stats, hipStream_t st) {
   const TankDev& h = M->hd;
@@ -940,25 +978,70 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   auto t0 = std::chrono::steady_clock::now();
   // b = -(A [0; phi~])_F
   launch_scatter_surface(h, d, phi_s, h.tmp, 1, st);
-  launch_gather(h, d, 0, h.tmp, h.b, h.side, 1 | 2, st);
-  // x = warm start (free part) or 0
+  launch_gather(h, d, OP_STIFF, h.tmp, h.b, h.side, F_MASK_SURF | F_NEG, st);
   if (o->warm_start) {
     HIPCHK(hipMemcpyAsync(h.xs, phi, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     launch_mask_surface(h, d, h.xs, st);
   } else {
     launch_fill(n, 0.0, h.xs, st);
   }
-  GmresCfg cfg{0, 2, true, o->rtol, o->max_iter, o->poll_every};
-  int iters = 0;
+  int iters = 0, refinements = 0;
   double rel = 0;
-  sem_status s = gmres(M, cfg, h.xs, h.b, &iters, &rel, st);
+  sem_status s = SEM_OK;
+  if (o->prec == SEM_PREC_FP64) {
+    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->rtol, o->max_iter, o->poll_every, 0};
+    s = gmres(M, cfg, buf64(M), h.xs, h.b, &iters, &rel, st);
+  } else {
+    const int ldp = M->m + 2;
+    double* scal = M->scal;
+    double nb2 = 0, rr = 0;
+    launch_dots(n, 1, h.b, 0, h.b, h.part, ldp, scal + 4, st);
+    HIPCHK(hipMemcpyAsync(&nb2, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double bnorm = std::sqrt(nb2);
+    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->inner_rtol, 0, o->poll_every, o->prec == SEM_PREC_BF16_IR ? 2 : 1};
+    s = SEM_E_NOCONV;
+    for (int k = 0; k <= o->max_refine; ++k) {
+      // FP64 residual r = b - A x
+      launch_gather(h, d, OP_STIFF, h.xs, h.w, h.side, F_MASK_SURF, st);
+      launch_residual(h, d, n, h.b, h.w, h.tmp, 1, st);
+      launch_dots(n, 1, h.tmp, 0, h.tmp, h.part, ldp, scal + 4, st);
+      HIPCHK(hipMemcpyAsync(&rr, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      double rn = std::sqrt(rr);
+      rel = bnorm > 0 ? rn / bnorm : rn;
+      if (!std::isfinite(rn)) {
+        s = SEM_E_NONFINITE;
+        break;
+      }
+      if (rn <= o->rtol * bnorm || rn == 0.0) {
+        s = SEM_OK;
+        break;
+      }
+      if (k == o->max_refine || iters >= o->max_iter) break;
+      launch_to_float(n, h.tmp, 1.0 / rn, h.b32, st);
+      launch_fill_f(n, h.x32, st);
+      cfg.max_iter = o->max_iter - iters;
+      int it = 0;
+      double rr32 = 0;
+      sem_status si = gmres(M, cfg, buf32(M), h.x32, h.b32, &it, &rr32, st);
+      iters += it;
+      refinements++;
+      if (si != SEM_OK && si != SEM_E_NOCONV) {
+        s = si;
+        break;
+      }
+      launch_add_float(n, h.x32, rn, h.xs, st);
+    }
+  }
+  if (s == SEM_E_NOCONV) set_status_bits(M, ST_NOCONV, st);
   // Phi = x_F + lift
   HIPCHK(hipMemcpyAsync(phi, h.xs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   launch_scatter_surface(h, d, phi_s, phi, 0, st);
   HIPCHK(hipStreamSynchronize(st));
   if (stats) {
     stats->iters = iters;
-    stats->refinements = 0;
+    stats->refinements = refinements;
     stats->rel_residual = rel;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     stats->status = s;
@@ -976,6 +1059,9 @@ extern "C" sem_status sem_laplace_solve(sem_mesh* M, const double* eta, const do
   if (opts) o = *opts;
   else default_opts(&o);
   if (!(o.rtol > 0) || o.max_iter < 1) return fail(SEM_E_INVAL, "rtol > 0 and max_iter >= 1 required");
+  if (o.prec < 0 || o.prec > 2) return fail(SEM_E_INVAL, "unknown precision");
+  if (o.prec != SEM_PREC_FP64 && !(o.inner_rtol > 0 && o.inner_rtol < 1))
+    return fail(SEM_E_INVAL, "inner_rtol must lie in (0, 1)");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipMemsetAsync(M->hd.status, 0, sizeof(int32_t), st));
   launch_coef(M->hd, M->dtank, eta, eta_x, 3, st);
@@ -988,11 +1074,12 @@ extern "C" sem_status sem_laplace_solve(sem_mesh* M, const double* eta, const do
 static sem_status recover_w_core(sem_mesh* M, const double* Phi, double* out, hipStream_t st) {
   const TankDev& h = M->hd;
   const TankDev* d = M->dtank;
-  launch_gather(h, d, 4, Phi, h.b, h.side, 0, st);
-  GmresCfg cfg{1, 3, false, 1e-14, 400, 10};
+  launch_gather(h, d, OP_SZ, Phi, h.b, h.side, 0, st);
+  GmresCfg cfg{OP_MASS, OP_PRE_MASS, false, 1e-14, 400, 10, 0};
   int iters;
   double rel;
-  sem_status s = gmres(M, cfg, h.wmass, h.b, &iters, &rel, st);
+  sem_status s = gmres(M, cfg, buf64(M), h.wmass, h.b, &iters, &rel, st);
+  if (s == SEM_E_NOCONV) set_status_bits(M, ST_NOCONV, st);
   launch_gather_surface(h, d, h.wmass, out, st);
   return s;
 }

@@ -73,6 +73,10 @@ struct TankDev {
   const double* ARI;              // [q][nI] coupling of the right line to the interior
   const double* Shat;             // [nx][q][q][2] inverse of the line Schur symbol per Fourier mode
   const double* twid;             // [nx][2] exp(-2 pi i m / nx)
+  const float* AinvII32;
+  const float* ALI32;
+  const float* ARI32;
+  const float* Shat32;
   double* yI;                     // [nx][nI] interior solves
   double* TL;                     // [nx][q]
   double* TR;                     // [nx][q]
@@ -90,6 +94,7 @@ struct TankDev {
   // dynamic fields
   double* G;                      // [nb][T][3][NpP][16]
   float* G32;
+  uint16_t* G16;                  // bfloat16 copy of G (same layout)
   double* invd;                   // [nb][T][NpP][16]
   int32_t* status;                // one word
   KrylovState* ks;
@@ -108,6 +113,8 @@ struct TankDev {
   float* V32;
   float* Z32;
   float* w32;
+  float* x32;
+  float* b32;
 };
 
 // index of the element-node value of component c in the MFMA tile layout

@@ -71,6 +71,7 @@ _SIGS = {
     "sem_mesh_destroy": (None, [_P]),
     "sem_set_surface": (C.c_int, [_P, _P, _P, _P]),
     "sem_apply": (C.c_int, [_P, C.c_int, _P, _P, _P]),
+    "sem_apply_timed": (C.c_int, [_P, C.c_int, C.c_int32, _P, _P, C.c_int32, C.POINTER(C.c_float), _P]),
     "sem_laplace_solve": (C.c_int, [_P, _P, _P, _P, _P, C.POINTER(sem_solve_opts),
                                     C.POINTER(sem_solve_stats), _P]),
     "sem_gradient_recover": (C.c_int, [_P, C.c_int, _P, _P, _P, _P]),
@@ -168,6 +169,12 @@ class Mesh:
 
     def apply(self, op, u, y, stream=None):
         check(sem_apply(self.handle, op, _ptr(u), _ptr(y), _stream(stream)), "sem_apply")
+
+    def apply_timed(self, op, u, y, reps, prec=SEM_PREC_FP64, stream=None):
+        ms = C.c_float()
+        check(sem_apply_timed(self.handle, op, prec, _ptr(u), _ptr(y), int(reps), C.byref(ms), _stream(stream)),
+              "sem_apply_timed")
+        return ms.value
 
     def laplace_solve(self, eta, etax, phis, phi, opts=None, stream=None):
         st = sem_solve_stats()

@@ -197,3 +197,20 @@ def test_rk4_domain_error_is_transactional():
     code, _ = pair.m.rk4_step(e_t, p_t, ws, 0.01, raise_on_error=False)
     assert code == pair.lib.SEM_E_DOMAIN
     assert np.array_equal(host(e_t), eta) and np.array_equal(host(p_t), phi)
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[2]])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_laplace_solve_mixed_precision(case, prec):
+    """FP64 iterative refinement around FP32 (prec=1) or bfloat16-factor
+    (prec=2) inner GMRES solves reaches the FP64 oracle to 1e-8 when refined
+    to rtol 1e-10."""
+    pair, eta, phi = make_pair(case, bar=True)
+    of = oracle_fields(pair, eta, phi)
+    m = pair.m
+    out = cuda(np.zeros(m.n))
+    opts = pair.lib.default_opts(rtol=1e-10, max_iter=20000, prec=prec, inner_rtol=1e-3)
+    st = m.laplace_solve(cuda(eta), cuda(of["etax"]), cuda(phi), out, opts)
+    err = rel_err(pair.to_oracle(host(out)), of["Phi"])
+    assert err < 1e-8, (err, st)
+    assert st["refinements"] >= 1 and st["rel_residual"] <= 1e-10
