@@ -175,10 +175,16 @@ sem_status sem_free_surface_rhs(sem_mesh* mesh, const double* eta, const double*
 sem_status sem_rk4_step(sem_mesh* mesh, double* eta, double* phi_s, double* phi_ws, double dt,
                         const sem_solve_opts* opts, sem_solve_stats* stats, void* stream);
 
-/* Batching: many independent tanks advanced together, each with its own
- * workspace; kernels of all active tanks share launches.  Results per tank
- * do not depend on which other tanks are in the batch. */
-sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, sem_batch** out);
+/* Batching: many independent tanks (each bound to its own workspace)
+ * advanced by one call.  The tanks are spread over `nstreams` worker
+ * threads, each driving its own HIP stream (created here, default priority),
+ * so the kernels of different tanks overlap on the device.  Work recorded on
+ * the caller's `stream` before the call is visible to the workers and the
+ * caller's stream waits for all of them.  A tank's results do not depend on
+ * which other tanks are in the batch.  per_tank_status / per_tank_iters: HOST
+ * arrays of `count` (may be NULL).  Each tank step is transactional as in
+ * sem_rk4_step; the call returns the first failing status. */
+sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, int32_t nstreams, sem_batch** out);
 sem_status sem_batch_rk4_step(sem_batch* batch, double* const* eta, double* const* phi_s,
                               double* const* phi_ws, const double* dt_host,
                               const uint8_t* active_host, const sem_solve_opts* opts,

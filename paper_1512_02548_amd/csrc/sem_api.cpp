@@ -12,6 +12,7 @@
 #include <new>
 #include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/sem.h"
@@ -1179,19 +1180,40 @@ extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, doub
   return read_status(M, st, nullptr);
 }
 
-// ------------------------------------------------------------ batches (sequential over tanks for now)
+// ------------------------------------------------------------ batches
+// A batch advances many independent tanks per call.  The tanks are spread
+// over worker threads, each driving its own HIP stream, so that the kernels
+// of different tanks run concurrently on the device.  Every tank runs exactly
+// the kernels it would run alone (results do not depend on the batch).
 struct sem_batch {
   std::vector<sem_mesh*> meshes;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  hipEvent_t start = nullptr;
 };
 
-extern "C" sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, sem_batch** out) {
+extern "C" sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, int32_t nstreams, sem_batch** out) {
   if (!meshes || count < 1 || !out) return fail(SEM_E_INVAL, "bad batch arguments");
+  if (nstreams < 1 || nstreams > 64) return fail(SEM_E_INVAL, "nstreams must be in 1..64");
   for (int i = 0; i < count; ++i)
     if (!meshes[i] || !meshes[i]->bound) return fail(SEM_E_INVAL, "every mesh must be bound");
-  sem_batch* B = new (std::nothrow) sem_batch();
+  for (int i = 0; i < count; ++i)
+    for (int j = i + 1; j < count; ++j)
+      if (meshes[i] == meshes[j]) return fail(SEM_E_INVAL, "a mesh appears twice in the batch");
+  std::unique_ptr<sem_batch> B(new (std::nothrow) sem_batch());
   if (!B) return fail(SEM_E_NOMEM, "host allocation failed");
   B->meshes.assign(meshes, meshes + count);
-  *out = B;
+  int ns = std::min<int>(nstreams, count);
+  for (int i = 0; i < ns; ++i) {
+    hipStream_t st;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    B->streams.push_back(st);
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    B->events.push_back(ev);
+  }
+  HIPCHK(hipEventCreateWithFlags(&B->start, hipEventDisableTiming));
+  *out = B.release();
   return SEM_OK;
 }
 
@@ -1200,16 +1222,59 @@ extern "C" sem_status sem_batch_rk4_step(sem_batch* B, double* const* eta, doubl
                                          const sem_solve_opts* opts, int32_t* per_status, int32_t* per_iters,
                                          void* stream) {
   if (!B || !eta || !phi_s || !phi_ws || !dt) return fail(SEM_E_INVAL, "null argument");
-  sem_status worst = SEM_OK;
-  for (size_t i = 0; i < B->meshes.size(); ++i) {
+  const int count = (int)B->meshes.size();
+  for (int i = 0; i < count; ++i) {
     if (active && !active[i]) continue;
-    sem_solve_stats st4[4];
-    sem_status s = sem_rk4_step(B->meshes[i], eta[i], phi_s[i], phi_ws[i], dt[i], opts, st4, stream);
-    if (per_status) per_status[i] = s;
-    if (per_iters) per_iters[i] = st4[0].iters + st4[1].iters + st4[2].iters + st4[3].iters;
-    if (s && !worst) worst = s;
+    if (!eta[i] || !phi_s[i] || !phi_ws[i] || !(dt[i] > 0)) return fail(SEM_E_INVAL, "bad per-tank argument");
   }
+  hipStream_t cst = (hipStream_t)stream;
+  // inputs written on the caller's stream must be visible to the workers
+  HIPCHK(hipEventRecord(B->start, cst));
+  const int W = (int)B->streams.size();
+  for (int w = 0; w < W; ++w) HIPCHK(hipStreamWaitEvent(B->streams[w], B->start, 0));
+  // largest tanks first, dealt to the least-loaded worker
+  std::vector<int> order;
+  for (int i = 0; i < count; ++i)
+    if (!active || active[i]) order.push_back(i);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return B->meshes[a]->n > B->meshes[b]->n; });
+  std::vector<std::vector<int>> work(W);
+  std::vector<double> load(W, 0.0);
+  for (int i : order) {
+    int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    work[w].push_back(i);
+    load[w] += (double)B->meshes[i]->n;
+  }
+  std::vector<sem_status> res(count, SEM_OK);
+  std::vector<int32_t> its(count, 0);
+  auto run = [&](int w) {
+    for (int i : work[w]) {
+      sem_solve_stats st4[4] = {};
+      res[i] = sem_rk4_step(B->meshes[i], eta[i], phi_s[i], phi_ws[i], dt[i], opts, st4, B->streams[w]);
+      its[i] = st4[0].iters + st4[1].iters + st4[2].iters + st4[3].iters;
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < W; ++w) th.emplace_back(run, w);
+  run(0);
+  for (auto& t : th) t.join();
+  for (int w = 0; w < W; ++w) {
+    HIPCHK(hipEventRecord(B->events[w], B->streams[w]));
+    HIPCHK(hipStreamWaitEvent(cst, B->events[w], 0));
+  }
+  sem_status worst = SEM_OK;
+  for (int i = 0; i < count; ++i) {
+    if (per_status) per_status[i] = (active && !active[i]) ? SEM_OK : res[i];
+    if (per_iters) per_iters[i] = its[i];
+    if (res[i] != SEM_OK && worst == SEM_OK) worst = res[i];
+  }
+  if (worst != SEM_OK) g_err = "at least one tank failed; see per_tank_status";
   return worst;
 }
 
-extern "C" void sem_batch_destroy(sem_batch* B) { delete B; }
+extern "C" void sem_batch_destroy(sem_batch* B) {
+  if (!B) return;
+  for (auto s : B->streams) hipStreamDestroy(s);
+  for (auto e : B->events) hipEventDestroy(e);
+  if (B->start) hipEventDestroy(B->start);
+  delete B;
+}
