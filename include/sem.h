@@ -88,6 +88,7 @@ typedef struct {
   double filter_sigma;         /* 1.0 = filter off                                  */
   int32_t overint_order;       /* Pf >= P: GLL(Pf) fine grid for the FS right side; Pf == P: none */
   int32_t restart;             /* GMRES restart length, 0 = default (30)            */
+  int32_t variant;             /* stiffness kernel: 0 = matrix cores (MFMA), 1 = reference vector-ALU kernel */
 } sem_mesh_desc;
 
 typedef struct {
@@ -191,6 +192,12 @@ sem_status sem_batch_rk4_step(sem_batch* batch, double* const* eta, double* cons
                               int32_t* per_tank_status_host, int32_t* per_tank_iters_host,
                               void* stream);
 void sem_batch_destroy(sem_batch* batch);
+
+/* Self-test of the matrix-core instructions' lane layout: runs one 16x16x4
+ * FP64 and one FP32 MFMA on known operands in the mesh's scratch space and
+ * returns the largest deviation from the expected product in *max_err_host
+ * (0 when the layout the kernels assume holds). */
+sem_status sem_selftest_mfma(sem_mesh* mesh, double* max_err_host, void* stream);
 
 const char* sem_last_error(void);
 

@@ -1000,6 +1000,15 @@ static void gather_kernel(const TankDev& h, const TankDev* d, int op, const T* u
 #undef SEM_G
 }
 
+static void stiff_mfma(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, int flags,
+                       int gstore, hipStream_t st) {
+  launch_stiff_mfma(h, d, u, y, side, flags, st);
+}
+static void stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
+                       int gstore, hipStream_t st) {
+  launch_stiff_mfma(h, d, u, y, side, flags, gstore, st);
+}
+
 template <typename T, typename GS>
 static void gather_full(const TankDev& h, const TankDev* d, int op, const T* u, T* y, T* side, int flags,
                         hipStream_t st) {
@@ -1007,7 +1016,8 @@ static void gather_full(const TankDev& h, const TankDev* d, int op, const T* u, 
     launch_sd<T>(h, d, u, y, st);
     return;
   }
-  gather_kernel<T, GS>(h, d, op, u, y, side, flags, st);
+  if (op == OP_STIFF && h.use_mfma) stiff_mfma(h, d, u, y, side, flags, sizeof(GS) == 1 ? 2 : 1, st);
+  else gather_kernel<T, GS>(h, d, op, u, y, side, flags, st);
   hipLaunchKernelGGL(k_fixup<T>, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side);
 }
 
@@ -1027,9 +1037,12 @@ void launch_gather_only(const TankDev& h, const TankDev* d, int op, int prec, co
                         hipStream_t st) {
   if (prec == 0) {
     if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<double>(h, d, (const double*)u, (double*)y, st);
+    else if (op == OP_STIFF && h.use_mfma) launch_stiff_mfma(h, d, (const double*)u, (double*)y, (double*)side, 0, st);
     else gather_kernel<double, double>(h, d, op, (const double*)u, (double*)y, (double*)side, 0, st);
   } else {
     if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<float>(h, d, (const float*)u, (float*)y, st);
+    else if (op == OP_STIFF && h.use_mfma)
+      launch_stiff_mfma(h, d, (const float*)u, (float*)y, (float*)side, 0, prec == 2 ? 2 : 1, st);
     else if (prec == 2) gather_kernel<float, BF16>(h, d, op, (const float*)u, (float*)y, (float*)side, 0, st);
     else gather_kernel<float, float>(h, d, op, (const float*)u, (float*)y, (float*)side, 0, st);
   }

@@ -17,6 +17,11 @@ void launch_gather(const TankDev& h, const TankDev* d, int op, const float* u, f
                    int gstore, hipStream_t st);
 void launch_gather_only(const TankDev& h, const TankDev* d, int op, int prec, const void* u, void* y, void* side,
                         hipStream_t st);
+void launch_stiff_mfma(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, int flags,
+                       hipStream_t st);
+void launch_stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
+                       int gstore, hipStream_t st);
+void launch_mfma_probe(double* out64, float* out32, hipStream_t st);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
 void launch_fill(int64_t n, double v, double* y, hipStream_t st);
 void launch_fill_f(int64_t n, float* y, hipStream_t st);

@@ -50,7 +50,7 @@ struct sem_mesh {
   std::vector<double> h, hx, slev;
   // derived sizes
   int Np = 0, NpP = 0, nl = 0, nc = 0, cb = 1, nb = 1, T = 1, EB = 0, nclass_col = 1;
-  int pre_kind = 0, nI = 0, q = 0;
+  int pre_kind = 0, nI = 0, q = 0, variant = 0;
   int64_t n = 0, ns = 0, E = 0;
   // host tables
   std::vector<int32_t> elem_loc, acc_cnt, acc_ent, surf_loc, is_surf_loc;
@@ -549,6 +549,7 @@ static sem_status build_mesh(sem_mesh* M) {
   dot_layout(M->n, &nchunk, &chunk);
   const int ldp = m + 2;
   reserve(M, "G", tiles * 3 * sizeof(double));
+  reserve(M, "probe", 512 * sizeof(double));
   reserve(M, "G32", tiles * 3 * sizeof(float));
   reserve(M, "G16", tiles * 3 * sizeof(uint16_t));
   reserve(M, "invd", tiles * sizeof(double));
@@ -598,6 +599,8 @@ extern "C" sem_status sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out)
   M->sf = desc->filter_sigma;
   M->Pf = desc->overint_order;
   M->m = desc->restart > 0 ? desc->restart : 30;
+  if (desc->variant < 0 || desc->variant > 1) return fail(SEM_E_INVAL, "variant must be 0 or 1");
+  M->variant = desc->variant;
   if (M->m > 200) return fail(SEM_E_INVAL, "restart must be <= 200");
   int64_t ns = (int64_t)M->nx * M->P + (M->periodic ? 0 : 1);
   M->h.assign(desc->h, desc->h + ns);
@@ -683,6 +686,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.g = M->g;
   h.nclass_col = M->nclass_col;
   h.pre_kind = M->pre_kind;
+  h.use_mfma = M->variant == 0 ? 1 : 0;
   h.nI = M->nI;
   h.q = M->q;
   h.I_idx = at<int32_t>(M, "I_idx");
@@ -964,6 +968,32 @@ extern "C" sem_status sem_apply_timed(sem_mesh* M, sem_operator op, int32_t prec
   *ms = t / reps;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_selftest_mfma(sem_mesh* M, double* max_err, void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!max_err) return fail(SEM_E_INVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  double* o64 = at<double>(M, "probe");
+  float* o32 = reinterpret_cast<float*>(o64 + 256);
+  launch_mfma_probe(o64, o32, st);
+  std::vector<double> h64(256);
+  std::vector<float> h32(256);
+  HIPCHK(hipMemcpyAsync(h64.data(), o64, 256 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(h32.data(), o32, 256 * sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double err = 0;
+  for (int lane = 0; lane < 64; ++lane)
+    for (int v = 0; v < 4; ++v) {
+      int i = 4 * (lane >> 4) + v, j = lane & 15;
+      double ref = 0;
+      for (int k = 0; k < 4; ++k) ref += (1.0 + i + 16.0 * k) * (1.0 + 2.0 * k + 3.0 * j);
+      err = std::max(err, std::fabs(h64[lane * 4 + v] - ref));
+      err = std::max(err, std::fabs((double)h32[lane * 4 + v] - ref));
+    }
+  *max_err = err;
   return SEM_OK;
 }
 

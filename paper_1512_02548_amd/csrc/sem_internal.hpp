@@ -65,6 +65,8 @@ struct TankDev {
   const float* pre_lap32;
   int32_t nclass_col;             // 1 (periodic) or 3 (walls: first, interior, last)
   int32_t pre_kind;               // 0 element-block Jacobi, 1 exact still-water (line Schur + DFT)
+  int32_t use_mfma;               // stiffness apply on matrix cores (1) or the reference kernel (0)
+  int32_t pad1;
   // exact still-water preconditioner (periodic tanks)
   int32_t nI, q;                  // interior free nodes per column, free nodes per line
   const int32_t* I_idx;           // [nI] column-local indices of the interior free nodes
