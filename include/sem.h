@@ -196,8 +196,9 @@ void sem_batch_destroy(sem_batch* batch);
 /* Self-test of the matrix-core instructions' lane layout: runs one 16x16x4
  * FP64 and one FP32 MFMA on known operands in the mesh's scratch space and
  * returns the largest deviation from the expected product in *max_err_host
- * (0 when the layout the kernels assume holds). */
-sem_status sem_selftest_mfma(sem_mesh* mesh, double* max_err_host, void* stream);
+ * (0 when the layout the kernels assume holds).  raw_host (HOST, 512
+ * doubles, may be NULL) receives lane*4+v for FP64 then for FP32. */
+sem_status sem_selftest_mfma(sem_mesh* mesh, double* max_err_host, double* raw_host, void* stream);
 
 const char* sem_last_error(void);
 

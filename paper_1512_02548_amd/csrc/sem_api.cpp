@@ -971,7 +971,7 @@ extern "C" sem_status sem_apply_timed(sem_mesh* M, sem_operator op, int32_t prec
   return SEM_OK;
 }
 
-extern "C" sem_status sem_selftest_mfma(sem_mesh* M, double* max_err, void* stream) {
+extern "C" sem_status sem_selftest_mfma(sem_mesh* M, double* max_err, double* raw, void* stream) {
   sem_status s = check_bound(M);
   if (s) return s;
   if (!max_err) return fail(SEM_E_INVAL, "null argument");
@@ -994,6 +994,11 @@ extern "C" sem_status sem_selftest_mfma(sem_mesh* M, double* max_err, void* stre
       err = std::max(err, std::fabs((double)h32[lane * 4 + v] - ref));
     }
   *max_err = err;
+  if (raw)
+    for (int i = 0; i < 256; ++i) {
+      raw[i] = h64[i];
+      raw[256 + i] = h32[i];
+    }
   return SEM_OK;
 }
 

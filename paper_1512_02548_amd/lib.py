@@ -83,7 +83,7 @@ _SIGS = {
                                      C.POINTER(C.c_uint8), C.POINTER(sem_solve_opts),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
     "sem_batch_destroy": (None, [_P]),
-    "sem_selftest_mfma": (C.c_int, [_P, C.POINTER(C.c_double), _P]),
+    "sem_selftest_mfma": (C.c_int, [_P, C.POINTER(C.c_double), _D, _P]),
     "sem_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -124,7 +124,7 @@ class Mesh:
     """A tank on the device: mesh_create + query + a torch-allocated workspace + bind."""
 
     def __init__(self, nx, nz, P, length, periodic, h, hx, g=9.81, sigma_levels=None, filter_ic=None,
-                 filter_sigma=1.0, overint=None, restart=30, variant=0, device="cuda", bind=True):
+                 filter_sigma=1.0, overint=None, restart=30, variant=1, device="cuda", bind=True):
         self.h = np.ascontiguousarray(h, dtype=np.float64)
         self.hx = np.ascontiguousarray(hx, dtype=np.float64)
         self._sl = None if sigma_levels is None else np.ascontiguousarray(sigma_levels, dtype=np.float64)
@@ -171,10 +171,12 @@ class Mesh:
     def apply(self, op, u, y, stream=None):
         check(sem_apply(self.handle, op, _ptr(u), _ptr(y), _stream(stream)), "sem_apply")
 
-    def selftest_mfma(self, stream=None):
+    def selftest_mfma(self, raw=False, stream=None):
         err = C.c_double()
-        check(sem_selftest_mfma(self.handle, C.byref(err), _stream(stream)), "sem_selftest_mfma")
-        return err.value
+        buf = np.zeros(512)
+        check(sem_selftest_mfma(self.handle, C.byref(err), buf.ctypes.data_as(_D), _stream(stream)),
+              "sem_selftest_mfma")
+        return (err.value, buf) if raw else err.value
 
     def apply_timed(self, op, u, y, reps, prec=SEM_PREC_FP64, stream=None):
         ms = C.c_float()

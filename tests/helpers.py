@@ -22,11 +22,11 @@ class Pair:
     """Library mesh (bound on the GPU) + oracle mesh + numbering map."""
 
     def __init__(self, nx, nz, P, L, periodic, h, hx, filter_ic=None, filter_sigma=1.0, Pf=None, g=9.81,
-                 restart=30):
+                 restart=30, variant=1):
         from paper_1512_02548_amd import lib
         self.lib = lib
         self.m = lib.Mesh(nx, nz, P, L, periodic, h, hx, g=g, filter_ic=filter_ic, filter_sigma=filter_sigma,
-                          overint=Pf, restart=restart)
+                          overint=Pf, restart=restart, variant=variant)
         self.om = OMesh(nx, nz, P, L, periodic)
         self.perm = node_permutation(self.m, self.om)
         self.h = np.asarray(h, float)

@@ -11,7 +11,11 @@ pytestmark = pytest.mark.gpu
 def test_mfma_lane_layout():
     from paper_1512_02548_amd import lib
     m = lib.Mesh(8, 2, 4, 2 * np.pi, True, np.ones(32), np.zeros(32))
-    assert m.selftest_mfma() == 0.0
+    err, raw = m.selftest_mfma(raw=True)
+    np.set_printoptions(linewidth=200)
+    print("f64 lanes x v:\n", raw[:256].reshape(64, 4))
+    print("f32 lanes x v:\n", raw[256:].reshape(64, 4))
+    assert err == 0.0
 
 
 @pytest.mark.parametrize("case", [(8, 2, 4, 2 * np.pi, True), (16, 4, 6, 2 * np.pi, True),
@@ -25,7 +29,7 @@ def test_mfma_stiffness_matches_reference_and_oracle(case):
     eta = 0.1 * np.cos(k * xs) + 0.03 * np.sin(2 * k * xs)
     h = 1.0 - 0.2 * np.cos(k * xs) ** 2
     hx = 0.4 * k * np.cos(k * xs) * np.sin(k * xs)
-    pm = Pair(nx, nz, P, L, periodic, h, hx)                      # MFMA (default)
+    pm = Pair(nx, nz, P, L, periodic, h, hx, variant=0)           # MFMA
     from paper_1512_02548_amd import lib
     ref = lib.Mesh(nx, nz, P, L, periodic, h, hx, variant=1)      # reference kernel
     of = oracle_fields(pm, eta, np.sin(k * xs))
