@@ -67,7 +67,9 @@ struct Prec<double, double> {
   __device__ static const double* ALI(const TankDev& d) { return d.ALI; }
   __device__ static const double* ARI(const TankDev& d) { return d.ARI; }
   __device__ static const double* Shat(const TankDev& d) { return d.Shat; }
-  __device__ static double G(const TankDev& d, int64_t i) { return d.G[i]; }
+  __device__ static double G(const TankDev& d, int64_t b, int eb, int i, int c) {
+    return d.G[tile_index64(d.T, d.NpP, b, eb, i, 3, c)];
+  }
 };
 template <>
 struct Prec<float, float> {
@@ -81,11 +83,15 @@ struct Prec<float, float> {
   __device__ static const float* ALI(const TankDev& d) { return d.ALI32; }
   __device__ static const float* ARI(const TankDev& d) { return d.ARI32; }
   __device__ static const float* Shat(const TankDev& d) { return d.Shat32; }
-  __device__ static float G(const TankDev& d, int64_t i) { return d.G32[i]; }
+  __device__ static float G(const TankDev& d, int64_t b, int eb, int i, int c) {
+    return d.G32[tile_index(d.T, d.NpP, b, eb, i, 3, c)];
+  }
 };
 template <>
 struct Prec<float, BF16> : Prec<float, float> {
-  __device__ static float G(const TankDev& d, int64_t i) { return bf16_to_float(d.G16[i]); }
+  __device__ static float G(const TankDev& d, int64_t b, int eb, int i, int c) {
+    return bf16_to_float(d.G16[tile_index(d.T, d.NpP, b, eb, i, 3, c)]);
+  }
 };
 
 // ------------------------------------------------------------ coefficients
@@ -131,9 +137,9 @@ __global__ void k_coef(const TankDev* __restrict__ td, const double* __restrict_
   double Gss = J * (b0 * l10 + b1 * l11);
   if (what & 2) d.invd[tile_index(d.T, d.NpP, b, eb, m, 1, 0)] = 1.0 / dd;
   if (!(what & 1)) return;
-  d.G[tile_index(d.T, d.NpP, b, eb, m, 3, 0)] = Grr;
-  d.G[tile_index(d.T, d.NpP, b, eb, m, 3, 1)] = Grs;
-  d.G[tile_index(d.T, d.NpP, b, eb, m, 3, 2)] = Gss;
+  d.G[tile_index64(d.T, d.NpP, b, eb, m, 3, 0)] = Grr;
+  d.G[tile_index64(d.T, d.NpP, b, eb, m, 3, 1)] = Grs;
+  d.G[tile_index64(d.T, d.NpP, b, eb, m, 3, 2)] = Gss;
   d.G32[tile_index(d.T, d.NpP, b, eb, m, 3, 0)] = (float)Grr;
   d.G32[tile_index(d.T, d.NpP, b, eb, m, 3, 1)] = (float)Grs;
   d.G32[tile_index(d.T, d.NpP, b, eb, m, 3, 2)] = (float)Gss;
@@ -192,9 +198,9 @@ k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict_
         ts += Ds[i * NpP + k] * uk;
       }
       if (OP == OP_STIFF) {
-        T grr = PR::G(d, tile_index(d.T, NpP, b, eb, i, 3, 0));
-        T grs = PR::G(d, tile_index(d.T, NpP, b, eb, i, 3, 1));
-        T gss = PR::G(d, tile_index(d.T, NpP, b, eb, i, 3, 2));
+        T grr = PR::G(d, b, eb, i, 0);
+        T grs = PR::G(d, b, eb, i, 1);
+        T gss = PR::G(d, b, eb, i, 2);
         st1[eb * NpP + i] = grr * tr + grs * ts;
         st2[eb * NpP + i] = grs * tr + gss * ts;
       } else {

@@ -7,11 +7,12 @@
 //   mixing:   F_r = G_rr T_r + G_rs T_s,  F_s = G_rs T_r + G_ss T_s (registers)
 //   stage 2:  Y (NpP x 16)  = [(M Dr)^T | (M Ds)^T] (NpP x 2NpP) . [F_r; F_s]
 // with 16x16x4 MFMA tiles.  The accumulator layout of stage 1 (lane l holds
-// rows 4(l/16)+v of column l%16) is read directly as the B operand of stage 2
-// by ordering stage 2's K index as (block, M-tile, v, l/16): no data movement
-// between the two contractions.  U is gathered from the LDS-staged input
-// region, G streams from HBM in the matching tile order, Y goes to LDS for the
-// deterministic per-node sums shared with the reference kernel.
+// column l%16, rows 4v+l/16 for FP64 and 4(l/16)+v for FP32, v = 0..3) is
+// read directly as the B operand of stage 2 by ordering stage 2's K index as
+// (block, M-tile, v, l/16): no data movement between the two contractions.
+// U is gathered from the LDS-staged input region, G streams from HBM in the
+// matching tile order, Y goes to LDS for the deterministic per-node sums
+// shared with the reference kernel.
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -23,14 +24,18 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Mfma;
+// Accumulator row of (v, lane group g) in a 16x16 output tile: the FP64
+// instruction interleaves (row 4v+g), the FP32 one blocks (row 4g+v).
 template <>
 struct Mfma<double> {
   using V4 = d4;
+  __device__ static constexpr int row(int v, int g) { return 4 * v + g; }
   __device__ static V4 op(double a, double b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 };
 template <>
 struct Mfma<float> {
   using V4 = f4;
+  __device__ static constexpr int row(int v, int g) { return 4 * g + v; }
   __device__ static V4 op(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
 
@@ -121,6 +126,8 @@ k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restr
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+        // FP64 copy: natural rows, node 16mt+4v+g at row 16mt+4v+g -> contiguous in lane
+        // FP32 copies: perm rows, node 16mt+4g+v at row 16mt+4v+g -> contiguous in lane
         const int64_t o = (int64_t)(mt * 16 + v * 4) * 16 + lane;
         T grr = load_g<T, GS>(d, gbase + o);
         T grs = load_g<T, GS>(d, gbase + (int64_t)NpP * 16 + o);
@@ -129,7 +136,7 @@ k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restr
         fr[mt][v] = grr * tr + grs * ts;
         fs[mt][v] = grs * tr + gss * ts;
       }
-    // stage 2: K index (blk, mt, v, grp) -> operator row 16 mt + 4 grp + v
+    // stage 2: K index (blk, mt, v, grp) -> operator row 16 mt + row(v, grp)
     V4 out[MT];
 #pragma unroll
     for (int mo = 0; mo < MT; ++mo) out[mo] = V4{0, 0, 0, 0};
@@ -137,7 +144,7 @@ k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restr
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int krow = 16 * mt + 4 * grp + v;
+        const int krow = 16 * mt + MF::row(v, grp);
 #pragma unroll
         for (int mo = 0; mo < MT; ++mo) {
           const int icol = 16 * mo + col;
@@ -150,7 +157,7 @@ k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restr
       for (int mo = 0; mo < MT; ++mo)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = 16 * mo + 4 * grp + v;
+          const int i = 16 * mo + MF::row(v, grp);
           st3[eb * NpP + i] = out[mo][v];
         }
     }

@@ -985,13 +985,17 @@ extern "C" sem_status sem_selftest_mfma(sem_mesh* M, double* max_err, double* ra
   HIPCHK(hipMemcpyAsync(h32.data(), o32, 256 * sizeof(float), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   double err = 0;
+  // expected accumulator rows: FP64 4v + lane/16 (interleaved), FP32 4(lane/16) + v
+  auto D = [](int i, int j) {
+    double ref = 0;
+    for (int k = 0; k < 4; ++k) ref += (1.0 + i + 16.0 * k) * (1.0 + 2.0 * k + 3.0 * j);
+    return ref;
+  };
   for (int lane = 0; lane < 64; ++lane)
     for (int v = 0; v < 4; ++v) {
-      int i = 4 * (lane >> 4) + v, j = lane & 15;
-      double ref = 0;
-      for (int k = 0; k < 4; ++k) ref += (1.0 + i + 16.0 * k) * (1.0 + 2.0 * k + 3.0 * j);
-      err = std::max(err, std::fabs(h64[lane * 4 + v] - ref));
-      err = std::max(err, std::fabs((double)h32[lane * 4 + v] - ref));
+      int j = lane & 15, g = lane >> 4;
+      err = std::max(err, std::fabs(h64[lane * 4 + v] - D(4 * v + g, j)));
+      err = std::max(err, std::fabs((double)h32[lane * 4 + v] - D(4 * g + v, j)));
     }
   *max_err = err;
   if (raw)

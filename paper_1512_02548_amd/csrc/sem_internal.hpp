@@ -119,12 +119,22 @@ struct TankDev {
   float* b32;
 };
 
-// index of the element-node value of component c in the MFMA tile layout
+// Index of the element-node value of component c in the MFMA tile layout.
+// FP32 copies: row order perm(m) = 16(m/16) + 4(m%4) + (m%16)/4 (the FP32
+// 16x16x4 accumulator holds rows 4(lane/16)+v); FP64 copies keep the natural
+// row order (the FP64 16x16x4 accumulator holds rows 4v+lane/16), see
+// tile_index64.  Either way one (component, M-tile, v) load is 64 contiguous
+// values.
 __host__ __device__ inline int64_t tile_index(int T, int NpP, int64_t blk, int eb, int m, int ncomp,
                                               int c) {
   int tile = eb >> 4, e = eb & 15;
   int perm = (m >> 4) * 16 + (m & 3) * 4 + ((m & 15) >> 2);
   return (((blk * T + tile) * ncomp + c) * (int64_t)NpP + perm) * 16 + e;
+}
+
+__host__ __device__ inline int64_t tile_index64(int T, int NpP, int64_t blk, int eb, int m, int ncomp, int c) {
+  int tile = eb >> 4, e = eb & 15;
+  return (((blk * T + tile) * ncomp + c) * (int64_t)NpP + m) * 16 + e;
 }
 
 }  // namespace sem
