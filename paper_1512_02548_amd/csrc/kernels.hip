@@ -15,6 +15,7 @@
 //   geometric factors G: MFMA tile layout [blk][tile][comp][perm(row)][16].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "launch.hpp"
@@ -63,10 +64,10 @@ struct Prec<double, double> {
   __device__ static const double* MDs(const TankDev& d) { return d.MDs; }
   __device__ static const double* Mref(const TankDev& d) { return d.Mref; }
   __device__ static const double* pre_lap(const TankDev& d) { return d.pre_lap; }
-  __device__ static const double* AinvII(const TankDev& d) { return d.AinvII; }
-  __device__ static const double* ALI(const TankDev& d) { return d.ALI; }
-  __device__ static const double* ARI(const TankDev& d) { return d.ARI; }
-  __device__ static const double* Shat(const TankDev& d) { return d.Shat; }
+  __device__ static const double* AinvII(const SDData& d) { return d.AinvII; }
+  __device__ static const double* ALI(const SDData& d) { return d.ALI; }
+  __device__ static const double* ARI(const SDData& d) { return d.ARI; }
+  __device__ static const double* Shat(const SDData& d) { return d.Shat; }
   __device__ static double G(const TankDev& d, int64_t b, int eb, int i, int c) {
     return d.G[tile_index64(d.T, d.NpP, b, eb, i, 3, c)];
   }
@@ -79,10 +80,10 @@ struct Prec<float, float> {
   __device__ static const float* MDs(const TankDev& d) { return d.MDs32; }
   __device__ static const float* Mref(const TankDev& d) { return d.Mref32; }
   __device__ static const float* pre_lap(const TankDev& d) { return d.pre_lap32; }
-  __device__ static const float* AinvII(const TankDev& d) { return d.AinvII32; }
-  __device__ static const float* ALI(const TankDev& d) { return d.ALI32; }
-  __device__ static const float* ARI(const TankDev& d) { return d.ARI32; }
-  __device__ static const float* Shat(const TankDev& d) { return d.Shat32; }
+  __device__ static const float* AinvII(const SDData& d) { return d.AinvII32; }
+  __device__ static const float* ALI(const SDData& d) { return d.ALI32; }
+  __device__ static const float* ARI(const SDData& d) { return d.ARI32; }
+  __device__ static const float* Shat(const SDData& d) { return d.Shat32; }
   __device__ static float G(const TankDev& d, int64_t b, int eb, int i, int c) {
     return d.G32[tile_index(d.T, d.NpP, b, eb, i, 3, c)];
   }
@@ -309,51 +310,54 @@ __global__ void k_fixup(const TankDev* __restrict__ td, T* __restrict__ y, const
   }
 }
 
-// ------------------------------------------------------------ exact still-water preconditioner
-// Periodic tanks.  z = A0_FF^{-1} r for the still-water flat-bed operator A0:
-// each column's interior free nodes are condensed onto the vertical lines
-// (Schur complement), the resulting block-circulant line system is solved
-// mode by mode after a DFT along x, and the interiors are recovered.
+// ------------------------------------------------------------ exact inverses on periodic tanks
+// z = A^{-1} r for a column-coupled operator A (the still-water Laplace
+// operator on the free nodes, or the 2D mass matrix): each column's interior
+// unknowns are condensed onto the vertical lines (Schur complement), the
+// block-circulant line system is solved mode by mode after a DFT along x,
+// and the interiors are recovered.
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_interior(const TankDev* __restrict__ td, const T* __restrict__ r) {
+k_sd_interior(const TankDev* __restrict__ td, int which, const T* __restrict__ r) {
   const TankDev& d = *td;
+  const SDData& sd = d.sd[which];
   using PR = Prec<T, T>;
   extern __shared__ double sh[];
-  const int c = blockIdx.x, nI = d.nI, q = d.q;
+  const int c = blockIdx.x, nI = sd.nI, q = sd.q;
   double* rI = sh;
   double* y = sh + nI;
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) rI[i] = r[(int64_t)c * d.nc + d.I_idx[i]];
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) rI[i] = r[(int64_t)c * d.nc + sd.I_idx[i]];
   __syncthreads();
   for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    const T* A = PR::AinvII(d) + (size_t)i * nI;
+    const T* A = PR::AinvII(sd) + (size_t)i * nI;
     double acc = 0;
     for (int j = 0; j < nI; ++j) acc += A[j] * rI[j];
     y[i] = acc;
-    d.yI[(size_t)c * nI + i] = acc;
+    sd.yI[(size_t)c * nI + i] = acc;
   }
   __syncthreads();
   for (int a = threadIdx.x; a < 2 * q; a += blockDim.x) {
-    const T* A = a < q ? PR::ALI(d) + (size_t)a * nI : PR::ARI(d) + (size_t)(a - q) * nI;
+    const T* A = a < q ? PR::ALI(sd) + (size_t)a * nI : PR::ARI(sd) + (size_t)(a - q) * nI;
     double acc = 0;
     for (int i = 0; i < nI; ++i) acc += A[i] * y[i];
-    if (a < q) d.TL[(size_t)c * q + a] = acc;
-    else d.TR[(size_t)c * q + a - q] = acc;
+    if (a < q) sd.TL[(size_t)c * q + a] = acc;
+    else sd.TR[(size_t)c * q + a - q] = acc;
   }
 }
 
 template <typename T>
-__global__ void k_sd_modes(const TankDev* __restrict__ td, const T* __restrict__ r) {
+__global__ void k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r) {
   const TankDev& d = *td;
+  const SDData& sd = d.sd[which];
   using PR = Prec<T, T>;
   extern __shared__ double gh[];  // [q][2]
-  const int k = blockIdx.x, q = d.q, nx = d.nx;
+  const int k = blockIdx.x, q = sd.q, nx = d.nx;
   for (int j = threadIdx.x; j < q; j += blockDim.x) {
     double re = 0, im = 0;
-    for (int c = 0; c < nx; ++c) {
+    int mm = 0;   // (k c) mod nx, advanced incrementally
+    for (int c = 0; c < nx; ++c, mm = (mm + k >= nx) ? mm + k - nx : mm + k) {
       int cm = c == 0 ? nx - 1 : c - 1;
-      double g = r[(int64_t)c * d.nc + j] - d.TL[(size_t)c * q + j] - d.TR[(size_t)cm * q + j];
-      int mm = (int)(((int64_t)k * c) % nx);
+      double g = r[(int64_t)c * d.nc + j] - sd.TL[(size_t)c * q + j] - sd.TR[(size_t)cm * q + j];
       re += g * d.twid[2 * mm];
       im += g * d.twid[2 * mm + 1];
     }
@@ -362,67 +366,70 @@ __global__ void k_sd_modes(const TankDev* __restrict__ td, const T* __restrict__
   }
   __syncthreads();
   for (int i = threadIdx.x; i < q; i += blockDim.x) {
-    const T* S = PR::Shat(d) + ((size_t)k * q + i) * q * 2;
+    const T* S = PR::Shat(sd) + ((size_t)k * q + i) * q * 2;
     double xr = 0, xi = 0;
     for (int j = 0; j < q; ++j) {
       double sr = S[2 * j], si = S[2 * j + 1];
       xr += sr * gh[2 * j] - si * gh[2 * j + 1];
       xi += sr * gh[2 * j + 1] + si * gh[2 * j];
     }
-    d.XH[((size_t)k * q + i) * 2] = xr;
-    d.XH[((size_t)k * q + i) * 2 + 1] = xi;
+    sd.XH[((size_t)k * q + i) * 2] = xr;
+    sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
   }
 }
 
 template <typename T>
-__global__ void k_sd_lines(const TankDev* __restrict__ td, T* __restrict__ z) {
+__global__ void k_sd_lines(const TankDev* __restrict__ td, int which, T* __restrict__ z) {
   const TankDev& d = *td;
-  const int c = blockIdx.x, q = d.q, nx = d.nx;
+  const SDData& sd = d.sd[which];
+  const int c = blockIdx.x, q = sd.q, nx = d.nx;
   for (int j = threadIdx.x; j < q; j += blockDim.x) {
     double acc = 0;
-    for (int k = 0; k < nx; ++k) {
-      int mm = (int)(((int64_t)k * c) % nx);
+    int mm = 0;   // (k c) mod nx, advanced incrementally
+    for (int k = 0; k < nx; ++k, mm = (mm + c >= nx) ? mm + c - nx : mm + c) {
       // Re[(xr + i xi) * exp(+2 pi i k c / nx)], exp(+..) = conj(twid)
-      acc += d.XH[((size_t)k * q + j) * 2] * d.twid[2 * mm] + d.XH[((size_t)k * q + j) * 2 + 1] * d.twid[2 * mm + 1];
+      acc += sd.XH[((size_t)k * q + j) * 2] * d.twid[2 * mm] + sd.XH[((size_t)k * q + j) * 2 + 1] * d.twid[2 * mm + 1];
     }
     acc /= nx;
     z[(int64_t)c * d.nc + j] = acc;
-    d.XL[(size_t)c * q + j] = acc;
+    sd.XL[(size_t)c * q + j] = acc;
   }
-  if (threadIdx.x == 0) z[(int64_t)c * d.nc + d.nl - 1] = T(0);
+  if (sd.zero_surface && threadIdx.x == 0) z[(int64_t)c * d.nc + d.nl - 1] = T(0);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_back(const TankDev* __restrict__ td, T* __restrict__ z) {
+k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z) {
   const TankDev& d = *td;
+  const SDData& sd = d.sd[which];
   using PR = Prec<T, T>;
   extern __shared__ double sh[];
-  const int c = blockIdx.x, nI = d.nI, q = d.q;
+  const int c = blockIdx.x, nI = sd.nI, q = sd.q;
   const int cn = c + 1 == d.nx ? 0 : c + 1;
   double* xl = sh;
   double* xr = sh + q;
   double* v = sh + 2 * q;
   for (int a = threadIdx.x; a < q; a += blockDim.x) {
-    xl[a] = d.XL[(size_t)c * q + a];
-    xr[a] = d.XL[(size_t)cn * q + a];
+    xl[a] = sd.XL[(size_t)c * q + a];
+    xr[a] = sd.XL[(size_t)cn * q + a];
   }
   __syncthreads();
+  const T* ALI = PR::ALI(sd);
+  const T* ARI = PR::ARI(sd);
   for (int i = threadIdx.x; i < nI; i += blockDim.x) {
     double acc = 0;
-    const T* ALI = PR::ALI(d);
-    const T* ARI = PR::ARI(d);
     for (int a = 0; a < q; ++a) acc += ALI[(size_t)a * nI + i] * xl[a] + ARI[(size_t)a * nI + i] * xr[a];
     v[i] = acc;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    const T* A = PR::AinvII(d) + (size_t)i * nI;
+    const T* A = PR::AinvII(sd) + (size_t)i * nI;
     double acc = 0;
     for (int j = 0; j < nI; ++j) acc += A[j] * v[j];
-    z[(int64_t)c * d.nc + d.I_idx[i]] = T(d.yI[(size_t)c * nI + i] - acc);
+    z[(int64_t)c * d.nc + sd.I_idx[i]] = T(sd.yI[(size_t)c * nI + i] - acc);
   }
-  for (int k = 1 + threadIdx.x; k < d.P; k += blockDim.x) z[(int64_t)c * d.nc + d.surf_loc[k]] = T(0);
+  if (sd.zero_surface)
+    for (int k = 1 + threadIdx.x; k < d.P; k += blockDim.x) z[(int64_t)c * d.nc + d.surf_loc[k]] = T(0);
 }
 
 // ------------------------------------------------------------ vector kernels
@@ -510,6 +517,86 @@ k_reduce(int nblk, int nvec, const double* __restrict__ part, int ldp, double* _
   }
 }
 
+// ------------------------------------------------------------ fused reductions
+// Partial sums per workgroup (wave butterflies, fixed order), then the last
+// workgroup to finish (device-scope counter) adds the partials in block order:
+// one launch, deterministic results.
+__device__ void givens_update(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m, int j,
+                              double hnorm2, int32_t* __restrict__ status);
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline bool last_block(int32_t* counter) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last != 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, const T* __restrict__ w,
+             double* __restrict__ part, int ldp, double* __restrict__ out, int64_t chunk,
+             int32_t* __restrict__ counter) {
+  __shared__ double red[4][kMaxVec];
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = 0; k < nvec; ++k) {
+    const T* x = X + k * ldx;
+    double sacc = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) sacc += (double)x[i] * (double)w[i];
+    sacc = wave_sum(sacc);
+    if (lane == 0) red[wv][k] = sacc;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nvec; k += blockDim.x)
+    part[(size_t)blockIdx.x * ldp + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  if (!last_block(counter)) return;
+  for (int k = threadIdx.x; k < nvec; k += blockDim.x) {
+    double t = 0;
+    for (int b2 = 0; b2 < (int)gridDim.x; ++b2) t += part[(size_t)b2 * ldp + k];
+    out[k] = t;
+  }
+  if (threadIdx.x == 0) *counter = 0;
+}
+
+// w' = w - sum_{i<=j} h_i V_i; ||w'||^2 reduced; Givens update of column j
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase, int m, T* __restrict__ w,
+             double* __restrict__ part, int ldp, int64_t chunk, KrylovState* __restrict__ ks,
+             int32_t* __restrict__ counter, int32_t* __restrict__ status) {
+  __shared__ double red[4];
+  if (ks->done) return;
+  const double* hcol = Hbase + (size_t)j * (m + 1);
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
+  double sacc = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double v = w[i];
+    for (int k = 0; k <= j; ++k) v -= hcol[k] * (double)V[(int64_t)k * n + i];
+    T vt = T(v);
+    w[i] = vt;
+    sacc += (double)vt * (double)vt;
+  }
+  sacc = wave_sum(sacc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sacc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (!last_block(counter)) return;
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int b2 = 0; b2 < (int)gridDim.x; ++b2) t += part[(size_t)b2 * ldp];
+    givens_update(ks, Hbase, m, j, t, status);
+    *counter = 0;
+  }
+}
+
 // ------------------------------------------------------------ GMRES pieces
 // w' = w - sum_{i<=j} h_i V_i  and partial ||w'||^2
 template <typename T>
@@ -534,16 +621,17 @@ k_orth(int64_t n, int j, const T* __restrict__ V, const double* __restrict__ hco
 
 // Givens update of column j (single thread).  H column j holds h_{0..j},
 // hnext = ||w'||^2 reduced.  Sets done/converged, V_{j+1} scale.
-__global__ void k_givens(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m, int j,
-                         const double* __restrict__ hnorm2, int32_t* __restrict__ status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Givens update of Hessenberg column j (one thread).  The column holds
+// h_{0..j}; hnorm2 = ||w'||^2.  Sets done/converged and the norm of V_{j+1}.
+__device__ void givens_update(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m, int j,
+                              double hnorm2, int32_t* __restrict__ status) {
   if (ks->done) return;
   double* H = Hbase;                       // (m+1) x m, column-major: H[i + j*(m+1)]
   double* cs = Hbase + (m + 1) * m;
   double* sn = cs + m;
   double* g = sn + m;
   double* col = H + (size_t)j * (m + 1);
-  double hn = sqrt(fmax(hnorm2[0], 0.0));
+  double hn = sqrt(fmax(hnorm2, 0.0));
   col[j + 1] = hn;
   for (int i = 0; i < j; ++i) {
     double t = cs[i] * col[i] + sn[i] * col[i + 1];
@@ -573,6 +661,12 @@ __global__ void k_givens(KrylovState* __restrict__ ks, double* __restrict__ Hbas
   }
   // store the normalisation of V_{j+1}
   g[m + 1 + j] = hn;  // y[] area reused as scratch for the norms
+}
+
+__global__ void k_givens(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m, int j,
+                         const double* __restrict__ hnorm2, int32_t* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  givens_update(ks, Hbase, m, j, hnorm2[0], status);
 }
 
 // V_{j+1} = w' / hn
@@ -878,6 +972,91 @@ k_fs_rhs(const TankDev* __restrict__ td, const double* __restrict__ eta, const d
   s_mass_solve<P>(d, rhs_p, phi_t, r, z, p, q, red);
 }
 
+// ------------------------------------------------------------ 1D periodic direct solves
+// y = A x for a block-circulant A given by its first block-row [P][ns]:
+// y[eP + a] = sum_j row[a][j] x[(eP + j) mod ns].
+__global__ void k_circ_apply(const TankDev* __restrict__ td, int which, const double* __restrict__ x,
+                             double* __restrict__ y) {
+  const TankDev& d = *td;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.ns) return;
+  const int P = d.P, ns = d.ns;
+  const int e = s / P, a = s - e * P;
+  const double* row = (which == 0 ? d.Rrow : d.Brow) + (size_t)a * ns;
+  const int base = e * P;
+  double acc = 0;
+  int j0 = ns - base;                  // split the wrap-around into two contiguous runs
+  for (int j = 0; j < j0; ++j) acc += row[j] * x[base + j];
+  for (int j = j0; j < ns; ++j) acc += row[j] * x[base + j - ns];
+  y[s] = acc;
+}
+
+// Over-integrated element right-hand sides (Secs. 3.1.1, 3.3), element by
+// element: loc[e][i][2] = J_e (I^T M_f F)_i for F_eta and F_phi.
+__global__ void k_fs_local(const TankDev* __restrict__ td, const double* __restrict__ eta,
+                           const double* __restrict__ etax, const double* __restrict__ phix,
+                           const double* __restrict__ ws, double* __restrict__ loc) {
+  const TankDev& d = *td;
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = d.P;
+  if (it >= d.nx * (P + 1)) return;
+  const int Pf = d.Pf, nf = Pf + 1;
+  const int e = it / (P + 1), i = it - e * (P + 1);
+  double acc_e = 0, acc_p = 0;
+  for (int a = 0; a < nf; ++a) {
+    double Iai = d.Ifine[a * (P + 1) + i];
+    if (Iai == 0.0) continue;
+    double se = 0, sp = 0;
+    for (int bq = 0; bq < nf; ++bq) {
+      double et = 0, ex = 0, px = 0, ww = 0;
+      for (int k = 0; k <= P; ++k) {
+        double Ik = d.Ifine[bq * (P + 1) + k];
+        int s = e * P + k;
+        if (s >= d.ns) s -= d.ns;
+        et += Ik * eta[s];
+        ex += Ik * etax[s];
+        px += Ik * phix[s];
+        ww += Ik * ws[s];
+      }
+      double fe = -ex * px + ww * (1.0 + ex * ex);
+      double fp = -d.g * et - 0.5 * (px * px - ww * ww * (1.0 + ex * ex));
+      double mf = d.Mfine[a * nf + bq];
+      se += mf * fe;
+      sp += mf * fp;
+    }
+    acc_e += Iai * se;
+    acc_p += Iai * sp;
+  }
+  const double J = 0.5 * d.dX;
+  loc[(size_t)it * 2 + 0] = J * acc_e;
+  loc[(size_t)it * 2 + 1] = J * acc_p;
+}
+
+// node sums of the element right-hand sides (left element first)
+__global__ void k_fs_gather(const TankDev* __restrict__ td, const double* __restrict__ loc,
+                            double* __restrict__ re, double* __restrict__ rp) {
+  const TankDev& d = *td;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.ns) return;
+  const int P = d.P;
+  const int e = s / P, k = s - e * P;
+  double ae = 0, ap = 0;
+  if (e < d.nx) {
+    ae = loc[((size_t)e * (P + 1) + k) * 2 + 0];
+    ap = loc[((size_t)e * (P + 1) + k) * 2 + 1];
+  }
+  if (k == 0) {
+    int ep = e - 1;
+    if (ep < 0 && d.periodic) ep = d.nx - 1;
+    if (ep >= 0) {
+      ae += loc[((size_t)ep * (P + 1) + P) * 2 + 0];
+      ap += loc[((size_t)ep * (P + 1) + P) * 2 + 1];
+    }
+  }
+  re[s] = ae;
+  rp[s] = ap;
+}
+
 // ------------------------------------------------------------ RK4 + filter
 // stage: ye = y0e + a*dt*ke, yp = y0p + a*dt*kp ; acc += w * k
 __global__ void k_rk4_stage(int ns, double adt, double wgt, int first, const double* __restrict__ y0e,
@@ -974,12 +1153,13 @@ void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const do
 }
 
 template <typename T>
-static void launch_sd(const TankDev& h, const TankDev* d, const T* u, T* y, hipStream_t st) {
-  size_t s1 = sizeof(double) * 2 * h.nI, s4 = sizeof(double) * (2 * h.q + h.nI);
-  hipLaunchKernelGGL(k_sd_interior<T>, dim3(h.nx), dim3(kBlockThreads), s1, st, d, u);
-  hipLaunchKernelGGL(k_sd_modes<T>, dim3(h.nx), dim3(64), sizeof(double) * 2 * h.q, st, d, u);
-  hipLaunchKernelGGL(k_sd_lines<T>, dim3(h.nx), dim3(64), 0, st, d, y);
-  hipLaunchKernelGGL(k_sd_back<T>, dim3(h.nx), dim3(kBlockThreads), s4, st, d, y);
+static void launch_sd(const TankDev& h, const TankDev* d, int which, const T* u, T* y, hipStream_t st) {
+  const SDData& sd = h.sd[which];
+  size_t s1 = sizeof(double) * 2 * sd.nI, s4 = sizeof(double) * (2 * sd.q + sd.nI);
+  hipLaunchKernelGGL(k_sd_interior<T>, dim3(h.nx), dim3(kBlockThreads), s1, st, d, which, u);
+  hipLaunchKernelGGL(k_sd_modes<T>, dim3(h.nx), dim3(64), sizeof(double) * 2 * sd.q, st, d, which, u);
+  hipLaunchKernelGGL(k_sd_lines<T>, dim3(h.nx), dim3(64), 0, st, d, which, y);
+  hipLaunchKernelGGL(k_sd_back<T>, dim3(h.nx), dim3(kBlockThreads), s4, st, d, which, y);
 }
 
 // element kernel only (no line fix-up)
@@ -1018,9 +1198,11 @@ static void stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float
 template <typename T, typename GS>
 static void gather_full(const TankDev& h, const TankDev* d, int op, const T* u, T* y, T* side, int flags,
                         hipStream_t st) {
-  if (op == OP_PRE_LAP && h.pre_kind == 1) {
-    launch_sd<T>(h, d, u, y, st);
-    return;
+  if ((op == OP_PRE_LAP || op == OP_PRE_MASS) && h.pre_kind == 1) {
+    if (op == OP_PRE_LAP || sizeof(T) == sizeof(double)) {
+      launch_sd<T>(h, d, op == OP_PRE_LAP ? 0 : 1, u, y, st);
+      return;
+    }
   }
   if (op == OP_STIFF && h.use_mfma) stiff_mfma(h, d, u, y, side, flags, sizeof(GS) == 1 ? 2 : 1, st);
   else gather_kernel<T, GS>(h, d, op, u, y, side, flags, st);
@@ -1042,11 +1224,12 @@ void launch_gather(const TankDev& h, const TankDev* d, int op, const float* u, f
 void launch_gather_only(const TankDev& h, const TankDev* d, int op, int prec, const void* u, void* y, void* side,
                         hipStream_t st) {
   if (prec == 0) {
-    if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<double>(h, d, (const double*)u, (double*)y, st);
+    if ((op == OP_PRE_LAP || op == OP_PRE_MASS) && h.pre_kind == 1)
+      launch_sd<double>(h, d, op == OP_PRE_LAP ? 0 : 1, (const double*)u, (double*)y, st);
     else if (op == OP_STIFF && h.use_mfma) launch_stiff_mfma(h, d, (const double*)u, (double*)y, (double*)side, 0, st);
     else gather_kernel<double, double>(h, d, op, (const double*)u, (double*)y, (double*)side, 0, st);
   } else {
-    if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<float>(h, d, (const float*)u, (float*)y, st);
+    if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<float>(h, d, 0, (const float*)u, (float*)y, st);
     else if (op == OP_STIFF && h.use_mfma)
       launch_stiff_mfma(h, d, (const float*)u, (float*)y, (float*)side, 0, prec == 2 ? 2 : 1, st);
     else if (prec == 2) gather_kernel<float, BF16>(h, d, op, (const float*)u, (float*)y, (float*)side, 0, st);
@@ -1071,14 +1254,10 @@ void launch_gather_surface(const TankDev& h, const TankDev* d, const double* u, 
   hipLaunchKernelGGL(k_gather_surface, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, u, out);
 }
 
-// chunking of [0, n) for deterministic partial reductions
+// chunking of [0, n) for the reductions: at most 256 workgroups
 void dot_layout(int64_t n, int* nchunk, int64_t* chunk) {
-  int64_t c = 4096;
+  int64_t c = std::max<int64_t>(512, (n + 255) / 256);
   int64_t k = (n + c - 1) / c;
-  if (k > 1024) {
-    k = 1024;
-    c = (n + k - 1) / k;
-  }
   if (k < 1) k = 1;
   *nchunk = (int)k;
   *chunk = c;
@@ -1086,38 +1265,38 @@ void dot_layout(int64_t n, int* nchunk, int64_t* chunk) {
 
 template <typename T>
 static void dots_t(int64_t n, int nvec, const T* X, int64_t ldx, const T* w, double* part, int ldp, double* out,
-                   hipStream_t st) {
+                   int32_t* counter, hipStream_t st) {
   int nc;
   int64_t chunk;
   dot_layout(n, &nc, &chunk);
-  hipLaunchKernelGGL(k_dots<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, nvec, X, ldx, w, part, ldp, chunk);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlockThreads), 0, st, nc, nvec, part, ldp, out);
+  hipLaunchKernelGGL(k_dots_fused<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, nvec, X, ldx, w, part, ldp, out,
+                     chunk, counter);
 }
 void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
-                 double* out, hipStream_t st) {
-  dots_t<double>(n, nvec, X, ldx, w, part, ldp, out, st);
+                 double* out, int32_t* counter, hipStream_t st) {
+  dots_t<double>(n, nvec, X, ldx, w, part, ldp, out, counter, st);
 }
 void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
-                 double* out, hipStream_t st) {
-  dots_t<float>(n, nvec, X, ldx, w, part, ldp, out, st);
+                 double* out, int32_t* counter, hipStream_t st) {
+  dots_t<float>(n, nvec, X, ldx, w, part, ldp, out, counter, st);
 }
 
 template <typename T>
-static void orth_t(int64_t n, int j, const T* V, const double* hcol, T* w, double* part, int ldp, double* out,
-                   const KrylovState* ks, hipStream_t st) {
+static void orth_t(int64_t n, int j, const T* V, double* H, int m, T* w, double* part, int ldp, KrylovState* ks,
+                   int32_t* counter, int32_t* status, hipStream_t st) {
   int nc;
   int64_t chunk;
   dot_layout(n, &nc, &chunk);
-  hipLaunchKernelGGL(k_orth<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, hcol, w, part, ldp, chunk, ks);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlockThreads), 0, st, nc, 1, part, ldp, out);
+  hipLaunchKernelGGL(k_orth_fused<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, H, m, w, part, ldp, chunk, ks,
+                     counter, status);
 }
-void launch_orth(int64_t n, int j, const double* V, const double* hcol, double* w, double* part, int ldp,
-                 double* out, const KrylovState* ks, hipStream_t st) {
-  orth_t<double>(n, j, V, hcol, w, part, ldp, out, ks, st);
+void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
+                        KrylovState* ks, int32_t* counter, int32_t* status, hipStream_t st) {
+  orth_t<double>(n, j, V, H, m, w, part, ldp, ks, counter, status, st);
 }
-void launch_orth(int64_t n, int j, const float* V, const double* hcol, float* w, double* part, int ldp,
-                 double* out, const KrylovState* ks, hipStream_t st) {
-  orth_t<float>(n, j, V, hcol, w, part, ldp, out, ks, st);
+void launch_orth_givens(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
+                        KrylovState* ks, int32_t* counter, int32_t* status, hipStream_t st) {
+  orth_t<float>(n, j, V, H, m, w, part, ldp, ks, counter, status, st);
 }
 
 void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, int32_t* status, hipStream_t st) {
@@ -1169,10 +1348,26 @@ void launch_fill_f(int64_t n, float* y, hipStream_t st) { hipMemsetAsync(y, 0, n
 
 void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, double* out0, const double* in1,
                        double* out1, hipStream_t st) {
+  if (h.circ1d) {
+    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, 0, in0, out0);
+    if (in1) hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, 0, in1, out1);
+    return;
+  }
   SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_recover_dx<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, in0, out0, in1, out1));
 }
 void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const double* etax, const double* phix,
                    const double* ws, double* et, double* pt, hipStream_t st) {
+  if (h.circ1d) {
+    double* loc = h.s1d + 5 * (size_t)h.ns;
+    double* re = h.s1d + 11 * (size_t)h.ns;
+    double* rp = h.s1d + 12 * (size_t)h.ns;
+    hipLaunchKernelGGL(k_fs_local, dim3(nblk((int64_t)h.nx * (h.P + 1))), dim3(kBlockThreads), 0, st, d, eta, etax,
+                       phix, ws, loc);
+    hipLaunchKernelGGL(k_fs_gather, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, loc, re, rp);
+    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, 1, re, et);
+    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, 1, rp, pt);
+    return;
+  }
   SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_fs_rhs<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, eta, etax, phix, ws, et, pt));
 }
 void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,

@@ -31,13 +31,13 @@ void launch_scatter_surface(const TankDev& h, const TankDev* d, const double* ph
 void launch_gather_surface(const TankDev& h, const TankDev* d, const double* u, double* out, hipStream_t st);
 void dot_layout(int64_t n, int* nchunk, int64_t* chunk);
 void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
-                 double* out, hipStream_t st);
+                 double* out, int32_t* counter, hipStream_t st);
 void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
-                 double* out, hipStream_t st);
-void launch_orth(int64_t n, int j, const double* V, const double* hcol, double* w, double* part, int ldp,
-                 double* out, const KrylovState* ks, hipStream_t st);
-void launch_orth(int64_t n, int j, const float* V, const double* hcol, float* w, double* part, int ldp,
-                 double* out, const KrylovState* ks, hipStream_t st);
+                 double* out, int32_t* counter, hipStream_t st);
+void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
+                        KrylovState* ks, int32_t* counter, int32_t* status, hipStream_t st);
+void launch_orth_givens(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
+                        KrylovState* ks, int32_t* counter, int32_t* status, hipStream_t st);
 void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, int32_t* status, hipStream_t st);
 void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m, const KrylovState* ks,
                        hipStream_t st);

@@ -50,7 +50,9 @@ struct sem_mesh {
   std::vector<double> h, hx, slev;
   // derived sizes
   int Np = 0, NpP = 0, nl = 0, nc = 0, cb = 1, nb = 1, T = 1, EB = 0, nclass_col = 1;
-  int pre_kind = 0, nI = 0, q = 0, variant = 0;
+  int pre_kind = 0, variant = 0;
+  int sd_nI[2] = {0, 0}, sd_q[2] = {0, 0};
+  int circ1d = 0;
   int64_t n = 0, ns = 0, E = 0;
   // host tables
   std::vector<int32_t> elem_loc, acc_cnt, acc_ent, surf_loc, is_surf_loc;
@@ -369,94 +371,104 @@ static sem_status build_mesh(sem_mesh* M) {
       }
     }
   }
-  // ---- exact still-water preconditioner for periodic tanks: column interiors
-  // condensed onto the vertical lines, line system diagonalised by a DFT in x
-  std::vector<int32_t> I_idx;
-  std::vector<double> AinvII, ALI, ARI, Shat, twid;
+  // ---- exact inverses for periodic tanks: column interiors condensed onto the
+  // vertical lines, line system diagonalised by a DFT in x.  [0] still-water
+  // Laplace operator on the free nodes (preconditioner), [1] 2D mass matrix.
+  struct SDHost {
+    int nI = 0, q = 0;
+    std::vector<int32_t> I_idx;
+    std::vector<double> AinvII, ALI, ARI, Shat;
+  } sdh[2];
+  std::vector<double> twid;
   M->pre_kind = M->periodic ? 1 : 0;
   if (M->pre_kind == 1) {
     const int nloc = nc + nl;
-    Mat A0c((size_t)nloc * nloc, 0.0);
-    for (int jt = 0; jt < 2 * nz; ++jt) {
-      Mat Ae = elem_matrix(jt, false);
-      for (int a = 0; a < Np; ++a)
-        for (int b = 0; b < Np; ++b)
-          A0c[(size_t)M->elem_loc[(size_t)jt * NpP + a] * nloc + M->elem_loc[(size_t)jt * NpP + b]] +=
-              Ae[(size_t)a * Np + b];
-    }
-    const int q = nl - 1;
-    for (int loc = nl; loc < nc; ++loc)
-      if (!M->is_surf_loc[loc]) I_idx.push_back(loc);
-    const int nI = (int)I_idx.size();
-    M->q = q;
-    M->nI = nI;
-    std::vector<int> Gam(2 * q);
-    for (int a = 0; a < q; ++a) {
-      Gam[a] = a;
-      Gam[q + a] = nc + a;
-    }
-    AinvII.assign((size_t)nI * nI, 0.0);
-    for (int i = 0; i < nI; ++i)
-      for (int j = 0; j < nI; ++j) AinvII[(size_t)i * nI + j] = A0c[(size_t)I_idx[i] * nloc + I_idx[j]];
-    if (!invert(AinvII, nI)) return fail(SEM_E_INVAL, "singular column interior block");
-    ALI.assign((size_t)q * nI, 0.0);
-    ARI.assign((size_t)q * nI, 0.0);
-    for (int a = 0; a < q; ++a)
-      for (int i = 0; i < nI; ++i) {
-        ALI[(size_t)a * nI + i] = A0c[(size_t)Gam[a] * nloc + I_idx[i]];
-        ARI[(size_t)a * nI + i] = A0c[(size_t)Gam[q + a] * nloc + I_idx[i]];
+    for (int which = 0; which < 2; ++which) {
+      const bool lap = which == 0;
+      SDHost& H = sdh[which];
+      Mat A0c((size_t)nloc * nloc, 0.0);
+      for (int jt = 0; jt < 2 * nz; ++jt) {
+        Mat Ae = elem_matrix(jt, !lap);
+        for (int a = 0; a < Np; ++a)
+          for (int b = 0; b < Np; ++b)
+            A0c[(size_t)M->elem_loc[(size_t)jt * NpP + a] * nloc + M->elem_loc[(size_t)jt * NpP + b]] +=
+                Ae[(size_t)a * Np + b];
       }
-    // Schur complement of the column on its two lines: S = A_GG - A_GI AinvII A_IG
-    Mat AGI((size_t)2 * q * nI);
-    for (int a = 0; a < 2 * q; ++a)
-      for (int i = 0; i < nI; ++i) AGI[(size_t)a * nI + i] = A0c[(size_t)Gam[a] * nloc + I_idx[i]];
-    Mat W = matmul(AinvII, transpose(AGI, 2 * q, nI), nI, nI, 2 * q);   // nI x 2q
-    Mat SW = matmul(AGI, W, 2 * q, nI, 2 * q);
-    Mat S((size_t)4 * q * q);
-    for (int a = 0; a < 2 * q; ++a)
-      for (int b = 0; b < 2 * q; ++b)
-        S[(size_t)a * 2 * q + b] = A0c[(size_t)Gam[a] * nloc + Gam[b]] - SW[(size_t)a * 2 * q + b];
-    auto Sblk = [&](int A, int B, int a, int b) { return S[(size_t)(A * q + a) * 2 * q + B * q + b]; };
-    // per-mode symbol S_LL + S_RR + S_LR e^{i k} + S_RL e^{-i k}, inverted
-    using cd = std::complex<double>;
-    Shat.assign((size_t)nx * q * q * 2, 0.0);
-    for (int k = 0; k < nx; ++k) {
-      double kap = 2.0 * M_PI * k / nx;
-      cd ep(std::cos(kap), std::sin(kap)), em = std::conj(ep);
-      std::vector<cd> Ak((size_t)q * q), Ik((size_t)q * q, 0.0);
+      // line unknowns: sigma-ordered line nodes (the surface node is Dirichlet for the Laplace problem)
+      const int q = lap ? nl - 1 : nl;
+      for (int loc = nl; loc < nc; ++loc)
+        if (!lap || !M->is_surf_loc[loc]) H.I_idx.push_back(loc);
+      const int nI = (int)H.I_idx.size();
+      H.q = q;
+      H.nI = nI;
+      std::vector<int> Gam(2 * q);
+      for (int a = 0; a < q; ++a) {
+        Gam[a] = a;
+        Gam[q + a] = nc + a;
+      }
+      H.AinvII.assign((size_t)nI * nI, 0.0);
+      for (int i = 0; i < nI; ++i)
+        for (int j = 0; j < nI; ++j) H.AinvII[(size_t)i * nI + j] = A0c[(size_t)H.I_idx[i] * nloc + H.I_idx[j]];
+      if (!invert(H.AinvII, nI)) return fail(SEM_E_INVAL, "singular column interior block");
+      H.ALI.assign((size_t)q * nI, 0.0);
+      H.ARI.assign((size_t)q * nI, 0.0);
       for (int a = 0; a < q; ++a)
-        for (int b = 0; b < q; ++b)
-          Ak[(size_t)a * q + b] = Sblk(0, 0, a, b) + Sblk(1, 1, a, b) + Sblk(0, 1, a, b) * ep + Sblk(1, 0, a, b) * em;
-      for (int a = 0; a < q; ++a) Ik[(size_t)a * q + a] = 1.0;
-      // complex Gauss-Jordan with partial pivoting
-      for (int cc = 0; cc < q; ++cc) {
-        int piv = cc;
-        for (int rr = cc + 1; rr < q; ++rr)
-          if (std::abs(Ak[(size_t)rr * q + cc]) > std::abs(Ak[(size_t)piv * q + cc])) piv = rr;
-        if (std::abs(Ak[(size_t)piv * q + cc]) == 0.0) return fail(SEM_E_INVAL, "singular line symbol");
-        if (piv != cc)
-          for (int j = 0; j < q; ++j) {
-            std::swap(Ak[(size_t)cc * q + j], Ak[(size_t)piv * q + j]);
-            std::swap(Ik[(size_t)cc * q + j], Ik[(size_t)piv * q + j]);
-          }
-        cd inv = 1.0 / Ak[(size_t)cc * q + cc];
-        for (int j = 0; j < q; ++j) {
-          Ak[(size_t)cc * q + j] *= inv;
-          Ik[(size_t)cc * q + j] *= inv;
+        for (int i = 0; i < nI; ++i) {
+          H.ALI[(size_t)a * nI + i] = A0c[(size_t)Gam[a] * nloc + H.I_idx[i]];
+          H.ARI[(size_t)a * nI + i] = A0c[(size_t)Gam[q + a] * nloc + H.I_idx[i]];
         }
-        for (int rr = 0; rr < q; ++rr) {
-          if (rr == cc) continue;
-          cd f = Ak[(size_t)rr * q + cc];
-          if (f == 0.0) continue;
+      // Schur complement of the column on its two lines: S = A_GG - A_GI AinvII A_IG
+      Mat AGI((size_t)2 * q * nI);
+      for (int a = 0; a < 2 * q; ++a)
+        for (int i = 0; i < nI; ++i) AGI[(size_t)a * nI + i] = A0c[(size_t)Gam[a] * nloc + H.I_idx[i]];
+      Mat W = matmul(H.AinvII, transpose(AGI, 2 * q, nI), nI, nI, 2 * q);   // nI x 2q
+      Mat SW = matmul(AGI, W, 2 * q, nI, 2 * q);
+      Mat S((size_t)4 * q * q);
+      for (int a = 0; a < 2 * q; ++a)
+        for (int b = 0; b < 2 * q; ++b)
+          S[(size_t)a * 2 * q + b] = A0c[(size_t)Gam[a] * nloc + Gam[b]] - SW[(size_t)a * 2 * q + b];
+      auto Sblk = [&](int A, int B, int a, int b) { return S[(size_t)(A * q + a) * 2 * q + B * q + b]; };
+      // per-mode symbol S_LL + S_RR + S_LR e^{i k} + S_RL e^{-i k}, inverted
+      using cd = std::complex<double>;
+      H.Shat.assign((size_t)nx * q * q * 2, 0.0);
+      for (int k = 0; k < nx; ++k) {
+        double kap = 2.0 * M_PI * k / nx;
+        cd ep(std::cos(kap), std::sin(kap)), em = std::conj(ep);
+        std::vector<cd> Ak((size_t)q * q), Ik((size_t)q * q, 0.0);
+        for (int a = 0; a < q; ++a)
+          for (int b = 0; b < q; ++b)
+            Ak[(size_t)a * q + b] = Sblk(0, 0, a, b) + Sblk(1, 1, a, b) + Sblk(0, 1, a, b) * ep + Sblk(1, 0, a, b) * em;
+        for (int a = 0; a < q; ++a) Ik[(size_t)a * q + a] = 1.0;
+        // complex Gauss-Jordan with partial pivoting
+        for (int cc = 0; cc < q; ++cc) {
+          int piv = cc;
+          for (int rr = cc + 1; rr < q; ++rr)
+            if (std::abs(Ak[(size_t)rr * q + cc]) > std::abs(Ak[(size_t)piv * q + cc])) piv = rr;
+          if (std::abs(Ak[(size_t)piv * q + cc]) == 0.0) return fail(SEM_E_INVAL, "singular line symbol");
+          if (piv != cc)
+            for (int j = 0; j < q; ++j) {
+              std::swap(Ak[(size_t)cc * q + j], Ak[(size_t)piv * q + j]);
+              std::swap(Ik[(size_t)cc * q + j], Ik[(size_t)piv * q + j]);
+            }
+          cd inv = 1.0 / Ak[(size_t)cc * q + cc];
           for (int j = 0; j < q; ++j) {
-            Ak[(size_t)rr * q + j] -= f * Ak[(size_t)cc * q + j];
-            Ik[(size_t)rr * q + j] -= f * Ik[(size_t)cc * q + j];
+            Ak[(size_t)cc * q + j] *= inv;
+            Ik[(size_t)cc * q + j] *= inv;
+          }
+          for (int rr = 0; rr < q; ++rr) {
+            if (rr == cc) continue;
+            cd f = Ak[(size_t)rr * q + cc];
+            if (f == 0.0) continue;
+            for (int j = 0; j < q; ++j) {
+              Ak[(size_t)rr * q + j] -= f * Ak[(size_t)cc * q + j];
+              Ik[(size_t)rr * q + j] -= f * Ik[(size_t)cc * q + j];
+            }
           }
         }
-      }
-      for (int a = 0; a < q * q; ++a) {
-        Shat[((size_t)k * q * q + a) * 2] = Ik[a].real();
-        Shat[((size_t)k * q * q + a) * 2 + 1] = Ik[a].imag();
+        for (int a = 0; a < q * q; ++a) {
+          H.Shat[((size_t)k * q * q + a) * 2] = Ik[a].real();
+          H.Shat[((size_t)k * q * q + a) * 2 + 1] = Ik[a].imag();
+        }
       }
     }
     twid.resize((size_t)2 * nx);
@@ -464,6 +476,10 @@ static sem_status build_mesh(sem_mesh* M) {
       twid[2 * mm] = std::cos(2.0 * M_PI * mm / nx);
       twid[2 * mm + 1] = -std::sin(2.0 * M_PI * mm / nx);
     }
+  }
+  for (int w = 0; w < 2; ++w) {
+    M->sd_nI[w] = sdh[w].nI;
+    M->sd_q[w] = sdh[w].q;
   }
   // ---- 1D operators
   const int P1 = P + 1;
@@ -487,6 +503,89 @@ static sem_status build_mesh(sem_mesh* M) {
     if (right_shared) w[P] = 1.0 / std::sqrt(2.0);
     for (int a = 0; a < P1; ++a)
       for (int b = 0; b < P1; ++b) pre1d[(size_t)cls * P1 * P1 + a * P1 + b] = w[a] * C[(size_t)a * P1 + b] * w[b];
+  }
+
+  // 1D periodic: first block-rows of M'^{-1} and M'^{-1} S_x from the block
+  // symbol (blocks of the P nodes e*P..e*P+P-1 of element e)
+  std::vector<double> Brow, Rrow;
+  M->circ1d = M->periodic ? 1 : 0;
+  if (M->circ1d) {
+    using cd = std::complex<double>;
+    const int ns1 = (int)M->ns;
+    const double Je = 0.5 * dX;
+    // A(0), A(+1), A(-1) blocks of M' and S_x
+    Mat Dm((size_t)P * P, 0.0), Um((size_t)P * P, 0.0), Lm((size_t)P * P, 0.0);
+    Mat Ds_((size_t)P * P, 0.0), Us((size_t)P * P, 0.0), Ls((size_t)P * P, 0.0);
+    for (int a = 0; a <= P; ++a)
+      for (int b = 0; b <= P; ++b) {
+        double mv = Je * r1.M[(size_t)a * P1 + b], sv = S1[(size_t)a * P1 + b];
+        // element e holds nodes eP+a; a = P is node 0 of block e+1
+        int ba = a == P ? 1 : 0, ia = a == P ? 0 : a;
+        int bb = b == P ? 1 : 0, ib = b == P ? 0 : b;
+        int off = bb - ba;   // block offset of the column relative to the row
+        Mat& Mt = off == 0 ? Dm : (off == 1 ? Um : Lm);
+        Mat& St = off == 0 ? Ds_ : (off == 1 ? Us : Ls);
+        Mt[(size_t)ia * P + ib] += mv;
+        St[(size_t)ia * P + ib] += sv;
+      }
+    std::vector<cd> Bk((size_t)nx * P * P), Rk((size_t)nx * P * P);
+    for (int k = 0; k < nx; ++k) {
+      double kap = 2.0 * M_PI * k / nx;
+      cd ep(std::cos(kap), std::sin(kap)), em = std::conj(ep);
+      std::vector<cd> C((size_t)P * P), Sx((size_t)P * P), I((size_t)P * P, 0.0);
+      for (int i = 0; i < P * P; ++i) {
+        C[i] = Dm[i] + Um[i] * ep + Lm[i] * em;
+        Sx[i] = Ds_[i] + Us[i] * ep + Ls[i] * em;
+      }
+      for (int a = 0; a < P; ++a) I[(size_t)a * P + a] = 1.0;
+      for (int cc = 0; cc < P; ++cc) {
+        int piv = cc;
+        for (int rr = cc + 1; rr < P; ++rr)
+          if (std::abs(C[(size_t)rr * P + cc]) > std::abs(C[(size_t)piv * P + cc])) piv = rr;
+        if (piv != cc)
+          for (int j = 0; j < P; ++j) {
+            std::swap(C[(size_t)cc * P + j], C[(size_t)piv * P + j]);
+            std::swap(I[(size_t)cc * P + j], I[(size_t)piv * P + j]);
+          }
+        cd inv = 1.0 / C[(size_t)cc * P + cc];
+        for (int j = 0; j < P; ++j) {
+          C[(size_t)cc * P + j] *= inv;
+          I[(size_t)cc * P + j] *= inv;
+        }
+        for (int rr = 0; rr < P; ++rr) {
+          if (rr == cc) continue;
+          cd f = C[(size_t)rr * P + cc];
+          for (int j = 0; j < P; ++j) {
+            C[(size_t)rr * P + j] -= f * C[(size_t)cc * P + j];
+            I[(size_t)rr * P + j] -= f * I[(size_t)cc * P + j];
+          }
+        }
+      }
+      for (int a = 0; a < P; ++a)
+        for (int b = 0; b < P; ++b) {
+          Bk[((size_t)k * P + a) * P + b] = I[(size_t)a * P + b];
+          cd acc = 0;
+          for (int c2 = 0; c2 < P; ++c2) acc += I[(size_t)a * P + c2] * Sx[(size_t)c2 * P + b];
+          Rk[((size_t)k * P + a) * P + b] = acc;
+        }
+    }
+    Brow.assign((size_t)P * ns1, 0.0);
+    Rrow.assign((size_t)P * ns1, 0.0);
+    std::vector<cd> tw(nx);
+    for (int mm = 0; mm < nx; ++mm) tw[mm] = cd(std::cos(-2.0 * M_PI * mm / nx), std::sin(-2.0 * M_PI * mm / nx));
+    for (int dd = 0; dd < nx; ++dd)
+      for (int a = 0; a < P; ++a)
+        for (int b = 0; b < P; ++b) {
+          cd sb = 0, sr = 0;
+          int idx = 0;   // (k dd) mod nx
+          for (int k = 0; k < nx; ++k, idx = (idx + dd) % nx) {
+            const cd& e = tw[idx];
+            sb += Bk[((size_t)k * P + a) * P + b] * e;
+            sr += Rk[((size_t)k * P + a) * P + b] * e;
+          }
+          Brow[(size_t)a * ns1 + dd * P + b] = sb.real() / nx;
+          Rrow[(size_t)a * ns1 + dd * P + b] = sr.real() / nx;
+        }
   }
 
   // ---- workspace layout: constants
@@ -523,23 +622,29 @@ static sem_status build_mesh(sem_mesh* M) {
   put(M, "Mfine", rf.M);
   put(M, "Filt", Filt);
   put(M, "pre1d", pre1d);
+  put(M, "Brow", Brow);
+  put(M, "Rrow", Rrow);
   put(M, "h", M->h);
   put(M, "hx", M->hx);
-  put(M, "I_idx", I_idx);
-  put(M, "AinvII", AinvII);
-  put(M, "ALI", ALI);
-  put(M, "ARI", ARI);
-  put(M, "Shat", Shat);
   put(M, "twid", twid);
-  put(M, "AinvII32", tof(AinvII));
-  put(M, "ALI32", tof(ALI));
-  put(M, "ARI32", tof(ARI));
-  put(M, "Shat32", tof(Shat));
-  reserve(M, "yI", (size_t)nx * std::max(1, M->nI) * sizeof(double));
-  reserve(M, "TL", (size_t)nx * std::max(1, M->q) * sizeof(double));
-  reserve(M, "TR", (size_t)nx * std::max(1, M->q) * sizeof(double));
-  reserve(M, "XH", (size_t)nx * std::max(1, M->q) * 2 * sizeof(double));
-  reserve(M, "XL", (size_t)nx * std::max(1, M->q) * sizeof(double));
+  for (int w = 0; w < 2; ++w) {
+    std::string p = w == 0 ? "sd0_" : "sd1_";
+    const SDHost& H = sdh[w];
+    put(M, (p + "I_idx").c_str(), H.I_idx);
+    put(M, (p + "AinvII").c_str(), H.AinvII);
+    put(M, (p + "ALI").c_str(), H.ALI);
+    put(M, (p + "ARI").c_str(), H.ARI);
+    put(M, (p + "Shat").c_str(), H.Shat);
+    put(M, (p + "AinvII32").c_str(), tof(H.AinvII));
+    put(M, (p + "ALI32").c_str(), tof(H.ALI));
+    put(M, (p + "ARI32").c_str(), tof(H.ARI));
+    put(M, (p + "Shat32").c_str(), tof(H.Shat));
+    reserve(M, (p + "yI").c_str(), (size_t)nx * std::max(1, H.nI) * sizeof(double));
+    reserve(M, (p + "TL").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
+    reserve(M, (p + "TR").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
+    reserve(M, (p + "XH").c_str(), (size_t)nx * std::max(1, H.q) * 2 * sizeof(double));
+    reserve(M, (p + "XL").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
+  }
   // dynamic
   const int m = M->m;
   const size_t n = (size_t)M->n, ns1 = (size_t)M->ns;
@@ -601,7 +706,7 @@ extern "C" sem_status sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out)
   M->m = desc->restart > 0 ? desc->restart : 30;
   if (desc->variant < 0 || desc->variant > 1) return fail(SEM_E_INVAL, "variant must be 0 or 1");
   M->variant = desc->variant;
-  if (M->m > 200) return fail(SEM_E_INVAL, "restart must be <= 200");
+  if (M->m > kMaxRestart) return fail(SEM_E_INVAL, "restart must be <= 64");
   int64_t ns = (int64_t)M->nx * M->P + (M->periodic ? 0 : 1);
   M->h.assign(desc->h, desc->h + ns);
   M->hx.assign(desc->h_x, desc->h_x + ns);
@@ -687,53 +792,37 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.nclass_col = M->nclass_col;
   h.pre_kind = M->pre_kind;
   h.use_mfma = M->variant == 0 ? 1 : 0;
-  h.nI = M->nI;
-  h.q = M->q;
-  h.I_idx = at<int32_t>(M, "I_idx");
-  h.AinvII = at<double>(M, "AinvII");
-  h.ALI = at<double>(M, "ALI");
-  h.ARI = at<double>(M, "ARI");
-  h.Shat = at<double>(M, "Shat");
   h.twid = at<double>(M, "twid");
-  h.AinvII32 = at<float>(M, "AinvII32");
-  h.ALI32 = at<float>(M, "ALI32");
-  h.ARI32 = at<float>(M, "ARI32");
-  h.Shat32 = at<float>(M, "Shat32");
-  h.G16 = at<uint16_t>(M, "G16");
-  h.x32 = at<float>(M, "x32");
-  h.b32 = at<float>(M, "b32");
-  h.yI = at<double>(M, "yI");
-  h.TL = at<double>(M, "TL");
-  h.TR = at<double>(M, "TR");
-  h.XH = at<double>(M, "XH");
-  h.XL = at<double>(M, "XL");
-  h.Dr = at<double>(M, "Dr");
-  h.Ds = at<double>(M, "Ds");
-  h.MDr = at<double>(M, "MDr");
-  h.MDs = at<double>(M, "MDs");
-  h.Mref = at<double>(M, "M");
-  h.Dr32 = at<float>(M, "Dr32");
-  h.Ds32 = at<float>(M, "Ds32");
-  h.MDr32 = at<float>(M, "MDr32");
-  h.MDs32 = at<float>(M, "MDs32");
-  h.Mref32 = at<float>(M, "M32");
-  h.elem_loc = at<int32_t>(M, "elem_loc");
-  h.acc_cnt = at<int32_t>(M, "acc_cnt");
-  h.acc_ent = at<int32_t>(M, "acc_ent");
-  h.surf_loc = at<int32_t>(M, "surf_loc");
-  h.is_surf_loc = at<int32_t>(M, "is_surf_loc");
-  h.lay = at<double>(M, "lay");
-  h.nodeq = at<double>(M, "nodeq");
-  h.colw = at<double>(M, "colw");
-  h.pre_lap = at<double>(M, "pre_lap");
-  h.pre_mass = at<double>(M, "pre_mass");
-  h.pre_lap32 = at<float>(M, "pre_lap32");
+  for (int w = 0; w < 2; ++w) {
+    std::string p = w == 0 ? "sd0_" : "sd1_";
+    SDData& sd = h.sd[w];
+    sd.nI = M->sd_nI[w];
+    sd.q = M->sd_q[w];
+    sd.zero_surface = w == 0 ? 1 : 0;
+    sd.I_idx = at<int32_t>(M, (p + "I_idx").c_str());
+    sd.AinvII = at<double>(M, (p + "AinvII").c_str());
+    sd.ALI = at<double>(M, (p + "ALI").c_str());
+    sd.ARI = at<double>(M, (p + "ARI").c_str());
+    sd.Shat = at<double>(M, (p + "Shat").c_str());
+    sd.AinvII32 = at<float>(M, (p + "AinvII32").c_str());
+    sd.ALI32 = at<float>(M, (p + "ALI32").c_str());
+    sd.ARI32 = at<float>(M, (p + "ARI32").c_str());
+    sd.Shat32 = at<float>(M, (p + "Shat32").c_str());
+    sd.yI = at<double>(M, (p + "yI").c_str());
+    sd.TL = at<double>(M, (p + "TL").c_str());
+    sd.TR = at<double>(M, (p + "TR").c_str());
+    sd.XH = at<double>(M, (p + "XH").c_str());
+    sd.XL = at<double>(M, (p + "XL").c_str());
+  }
   h.M1 = at<double>(M, "M1");
   h.S1 = at<double>(M, "S1");
   h.Ifine = at<double>(M, "Ifine");
   h.Mfine = at<double>(M, "Mfine");
   h.Filt = at<double>(M, "Filt");
   h.pre1d = at<double>(M, "pre1d");
+  h.circ1d = M->circ1d;
+  h.Brow = at<double>(M, "Brow");
+  h.Rrow = at<double>(M, "Rrow");
   h.h = at<double>(M, "h");
   h.hx = at<double>(M, "hx");
   h.G = at<double>(M, "G");
@@ -838,7 +927,8 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
   KrylovState ks0{};
   ks0.rtol = cfg.rtol;
   HIPCHK(hipMemcpyAsync(h.ks, &ks0, sizeof(ks0), hipMemcpyHostToDevice, st));
-  launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, st);
+  int32_t* cnt = &h.ks->pad[0];
+  launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, cnt, st);
   int total = 0;
   KrylovState hks{};
   bool first = true;
@@ -847,7 +937,7 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
     // r = b - A x
     gather_t(M, cfg, cfg.op, x, B.w, B.side, flags, st);
     launch_residual(h, d, n, b, B.w, B.V, cfg.mask ? 1 : 0, st);
-    launch_dots(n, 1, B.V, 0, B.V, h.part, ldp, scal + 0, st);
+    launch_dots(n, 1, B.V, 0, B.V, h.part, ldp, scal + 0, cnt, st);
     launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, B.V, st);
     first = false;
     HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
@@ -859,9 +949,8 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       gather_t(M, cfg, cfg.pre, Vj, Zj, B.side, flags, st);
       gather_t(M, cfg, cfg.op, Zj, B.w, B.side, flags, st);
       double* Hcol = h.H + (size_t)j * (m + 1);
-      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, st);
-      launch_orth(n, j, B.V, Hcol, B.w, h.part, ldp, scal + 2, h.ks, st);
-      launch_givens(h.ks, h.H, m, j, scal + 2, h.status, st);
+      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, st);
+      launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, st);
       launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
       if ((j + 1) % poll == 0 || j == m - 1 || total + j + 1 >= cfg.max_iter) {
         HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
@@ -1035,7 +1124,8 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
     const int ldp = M->m + 2;
     double* scal = M->scal;
     double nb2 = 0, rr = 0;
-    launch_dots(n, 1, h.b, 0, h.b, h.part, ldp, scal + 4, st);
+    int32_t* cnt = &h.ks->pad[0];
+    launch_dots(n, 1, h.b, 0, h.b, h.part, ldp, scal + 4, cnt, st);
     HIPCHK(hipMemcpyAsync(&nb2, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     double bnorm = std::sqrt(nb2);
@@ -1045,7 +1135,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
       // FP64 residual r = b - A x
       launch_gather(h, d, OP_STIFF, h.xs, h.w, h.side, F_MASK_SURF, st);
       launch_residual(h, d, n, h.b, h.w, h.tmp, 1, st);
-      launch_dots(n, 1, h.tmp, 0, h.tmp, h.part, ldp, scal + 4, st);
+      launch_dots(n, 1, h.tmp, 0, h.tmp, h.part, ldp, scal + 4, cnt, st);
       HIPCHK(hipMemcpyAsync(&rr, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       double rn = std::sqrt(rr);

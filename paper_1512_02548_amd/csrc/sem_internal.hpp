@@ -8,6 +8,8 @@ namespace sem {
 constexpr int kMaxOrder = 8;
 constexpr int kMaxContrib = 8;      // element contributions to one column-local node
 constexpr int kBlockThreads = 256;
+constexpr int kMaxRestart = 64;     // GMRES restart length limit
+constexpr int kMaxVec = kMaxRestart + 1;
 
 // status bits accumulated on the device
 enum : int32_t {
@@ -29,6 +31,28 @@ struct KrylovState {
   int32_t iters;      // total iterations
   int32_t status;
   int32_t pad[3];
+};
+
+// Exact inverse of a column-coupled operator on a periodic tank: the interior
+// nodes of every column are condensed onto the vertical lines, the resulting
+// block-circulant line system is diagonalised by a DFT along x.
+struct SDData {
+  int32_t nI, q;                  // interior unknowns per column, unknowns per line
+  int32_t zero_surface, pad;      // 1: surface nodes are Dirichlet (set to 0)
+  const int32_t* I_idx;           // [nI] column-local indices of the interior unknowns
+  const double* AinvII;           // [nI][nI]
+  const double* ALI;              // [q][nI] coupling of the left line to the interior
+  const double* ARI;              // [q][nI] coupling of the right line to the interior
+  const double* Shat;             // [nx][q][q][2] inverse line symbol per Fourier mode
+  const float* AinvII32;
+  const float* ALI32;
+  const float* ARI32;
+  const float* Shat32;
+  double* yI;                     // [nx][nI] interior solves
+  double* TL;                     // [nx][q]
+  double* TR;                     // [nx][q]
+  double* XH;                     // [nx][q][2] modal line solution
+  double* XL;                     // [nx][q] line solution
 };
 
 // Everything a kernel needs about one tank; lives in device memory at the
@@ -64,26 +88,13 @@ struct TankDev {
   const double* pre_mass;         // [nclass][NpP][NpP]
   const float* pre_lap32;
   int32_t nclass_col;             // 1 (periodic) or 3 (walls: first, interior, last)
-  int32_t pre_kind;               // 0 element-block Jacobi, 1 exact still-water (line Schur + DFT)
+  int32_t pre_kind;               // 0 element-block Jacobi, 1 exact inverses (line Schur + DFT)
+  const double* twid;             // [nx][2] exp(-2 pi i m / nx)
   int32_t use_mfma;               // stiffness apply on matrix cores (1) or the reference kernel (0)
   int32_t pad1;
-  // exact still-water preconditioner (periodic tanks)
-  int32_t nI, q;                  // interior free nodes per column, free nodes per line
-  const int32_t* I_idx;           // [nI] column-local indices of the interior free nodes
-  const double* AinvII;           // [nI][nI]
-  const double* ALI;              // [q][nI] coupling of the left line to the interior
-  const double* ARI;              // [q][nI] coupling of the right line to the interior
-  const double* Shat;             // [nx][q][q][2] inverse of the line Schur symbol per Fourier mode
-  const double* twid;             // [nx][2] exp(-2 pi i m / nx)
-  const float* AinvII32;
-  const float* ALI32;
-  const float* ARI32;
-  const float* Shat32;
-  double* yI;                     // [nx][nI] interior solves
-  double* TL;                     // [nx][q]
-  double* TR;                     // [nx][q]
-  double* XH;                     // [nx][q][2] modal line solution
-  double* XL;                     // [nx][q] line solution
+  // exact inverses by line condensation + DFT (periodic tanks): [0] the
+  // still-water Laplace operator on the free nodes, [1] the 2D mass matrix
+  SDData sd[2];
   // 1D surface operators (P+1)^2 etc.
   const double* M1;
   const double* S1;               // M1 D1
@@ -91,6 +102,9 @@ struct TankDev {
   const double* Mfine;            // (Pf+1) x (Pf+1)
   const double* Filt;             // (P+1) x (P+1)
   const double* pre1d;            // [3][(P+1)^2] W C^{-1} W for the 1D mass (classes: first, interior, last)
+  int32_t circ1d, pad2;           // periodic: M'^{-1} and M'^{-1} S_x applied as block-circulant rows
+  const double* Brow;             // [P][ns] first block-row of M'^{-1}
+  const double* Rrow;             // [P][ns] first block-row of M'^{-1} S_x
   const double* h;                // [ns]
   const double* hx;               // [ns]
   // dynamic fields

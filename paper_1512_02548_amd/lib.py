@@ -211,7 +211,7 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and sem_mesh_destroy is not None:
             sem_mesh_destroy(h)
             self.handle = None
 
@@ -241,7 +241,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and sem_batch_destroy is not None:
             sem_batch_destroy(h)
             self.handle = None
 
