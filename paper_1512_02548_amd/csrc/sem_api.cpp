@@ -827,6 +827,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.hx = at<double>(M, "hx");
   h.G = at<double>(M, "G");
   h.G32 = at<float>(M, "G32");
+  h.G16 = at<uint16_t>(M, "G16");
   h.invd = at<double>(M, "invd");
   h.status = at<int32_t>(M, "status");
   h.ks = at<KrylovState>(M, "ks");
@@ -844,9 +845,20 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.V32 = at<float>(M, "V32");
   h.Z32 = at<float>(M, "Z32");
   h.w32 = at<float>(M, "w32");
+  h.x32 = at<float>(M, "x32");
+  h.b32 = at<float>(M, "b32");
   M->rk = at<double>(M, "rk");
   M->scal = at<double>(M, "scal");
   M->dtank = at<TankDev>(M, "tank");
+  // every device array the kernels use must have been laid out
+  const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,
+                        h.acc_cnt, h.acc_ent, h.surf_loc, h.is_surf_loc, h.lay, h.nodeq, h.colw, h.pre_lap,
+                        h.pre_mass, h.pre_lap32, h.M1, h.S1, h.Ifine, h.Mfine, h.Filt, h.pre1d, h.h, h.hx, h.G,
+                        h.G32, h.G16, h.invd, h.status, h.ks, h.H, h.part, h.V, h.Zb, h.w, h.b, h.tmp, h.xs,
+                        h.wmass, h.side, h.s1d, h.V32, h.Z32, h.w32, h.x32, h.b32, h.twid, h.Brow, h.Rrow,
+                        h.sd[0].yI, h.sd[1].yI, M->rk, M->scal};
+  for (const void* p : need)
+    if (!p) return fail(SEM_E_INVAL, "internal: workspace layout incomplete");
   for (const Upload& u : M->uploads)
     HIPCHK(hipMemcpyAsync(M->ws + u.off, u.data.data(), u.data.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(M->dtank, &h, sizeof(TankDev), hipMemcpyHostToDevice, st));
