@@ -792,6 +792,27 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.nclass_col = M->nclass_col;
   h.pre_kind = M->pre_kind;
   h.use_mfma = M->variant == 0 ? 1 : 0;
+  h.Dr = at<double>(M, "Dr");
+  h.Ds = at<double>(M, "Ds");
+  h.MDr = at<double>(M, "MDr");
+  h.MDs = at<double>(M, "MDs");
+  h.Mref = at<double>(M, "M");
+  h.Dr32 = at<float>(M, "Dr32");
+  h.Ds32 = at<float>(M, "Ds32");
+  h.MDr32 = at<float>(M, "MDr32");
+  h.MDs32 = at<float>(M, "MDs32");
+  h.Mref32 = at<float>(M, "M32");
+  h.elem_loc = at<int32_t>(M, "elem_loc");
+  h.acc_cnt = at<int32_t>(M, "acc_cnt");
+  h.acc_ent = at<int32_t>(M, "acc_ent");
+  h.surf_loc = at<int32_t>(M, "surf_loc");
+  h.is_surf_loc = at<int32_t>(M, "is_surf_loc");
+  h.lay = at<double>(M, "lay");
+  h.nodeq = at<double>(M, "nodeq");
+  h.colw = at<double>(M, "colw");
+  h.pre_lap = at<double>(M, "pre_lap");
+  h.pre_mass = at<double>(M, "pre_mass");
+  h.pre_lap32 = at<float>(M, "pre_lap32");
   h.twid = at<double>(M, "twid");
   for (int w = 0; w < 2; ++w) {
     std::string p = w == 0 ? "sd0_" : "sd1_";
@@ -857,8 +878,8 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
                         h.G32, h.G16, h.invd, h.status, h.ks, h.H, h.part, h.V, h.Zb, h.w, h.b, h.tmp, h.xs,
                         h.wmass, h.side, h.s1d, h.V32, h.Z32, h.w32, h.x32, h.b32, h.twid, h.Brow, h.Rrow,
                         h.sd[0].yI, h.sd[1].yI, M->rk, M->scal};
-  for (const void* p : need)
-    if (!p) return fail(SEM_E_INVAL, "internal: workspace layout incomplete");
+  for (size_t i = 0; i < sizeof(need) / sizeof(need[0]); ++i)
+    if (!need[i]) return fail(SEM_E_INVAL, "internal: workspace layout incomplete (" + std::to_string(i) + ")");
   for (const Upload& u : M->uploads)
     HIPCHK(hipMemcpyAsync(M->ws + u.off, u.data.data(), u.data.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(M->dtank, &h, sizeof(TankDev), hipMemcpyHostToDevice, st));

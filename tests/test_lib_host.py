@@ -66,3 +66,18 @@ def test_host_argument_checks():
     import ctypes as C
     code = lib.sem_set_surface(m.handle, None, None, None)
     assert code == lib.SEM_E_INVAL
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_workspace_layout_complete(periodic):
+    """sem_mesh_bind checks that every device array the kernels use has a
+    place in the workspace before it uploads anything; on a host without a
+    GPU the call must get past that check and fail only at the first upload."""
+    import ctypes as C
+    import torch
+    from paper_1512_02548_amd import lib
+    if torch.cuda.is_available():
+        pytest.skip("checks the no-device path")
+    m = make(8, 2, 4, 6.28, periodic)
+    code = lib.sem_mesh_bind(m.handle, C.c_void_p(1 << 20), m.info.workspace_bytes, None)
+    assert code == lib.SEM_E_DEVICE, lib.sem_last_error()
