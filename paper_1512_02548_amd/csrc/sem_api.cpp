@@ -884,6 +884,8 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     HIPCHK(hipMemcpyAsync(M->ws + u.off, u.data.data(), u.data.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(M->dtank, &h, sizeof(TankDev), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(h.status, 0, 64, st));
+  // Krylov state, including the completion counter of the fused reductions
+  HIPCHK(hipMemsetAsync(h.ks, 0, sizeof(KrylovState), st));
   HIPCHK(hipMemsetAsync(h.wmass, 0, M->n * sizeof(double), st));
   HIPCHK(hipMemsetAsync(h.G, 0, M->off.at("G32") - M->off.at("G"), st));
   HIPCHK(hipMemsetAsync(h.G32, 0, M->off.at("G16") - M->off.at("G32"), st));
@@ -1158,6 +1160,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
     double* scal = M->scal;
     double nb2 = 0, rr = 0;
     int32_t* cnt = &h.ks->pad[0];
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t), st));
     launch_dots(n, 1, h.b, 0, h.b, h.part, ldp, scal + 4, cnt, st);
     HIPCHK(hipMemcpyAsync(&nb2, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
