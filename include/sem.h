@@ -104,7 +104,7 @@ typedef struct {
   double inner_rtol;    /* IR: relative tolerance of each inner solve              */
   int32_t max_refine;   /* IR: maximum outer refinements                           */
   int32_t warm_start;   /* 1: phi holds the initial guess on entry                 */
-  int32_t poll_every;   /* iterations launched between host convergence polls      */
+  int32_t lookahead;    /* Krylov steps the host may queue ahead of the device (>=1) */
   int32_t reserved;
 } sem_solve_opts;
 

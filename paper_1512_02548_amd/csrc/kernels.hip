@@ -39,6 +39,12 @@ __device__ inline double block_sum(double v, double* red) {
 
 __device__ inline bool finite(double v) { return v - v == 0.0; }
 
+// butterfly sum over a 64-lane wavefront (every lane gets the total)
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ inline int64_t right_line_base(const TankDev& d, int c) {
   // global index of the first node of the vertical line at x_c (c in 0..nx)
   if (c < d.nx) return (int64_t)c * d.nc;
@@ -158,6 +164,7 @@ __global__ void __launch_bounds__(kBlockThreads)
 k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict__ y,
          T* __restrict__ side, int flags) {
   const TankDev& d = *td;
+  if ((flags & F_GATE) && d.ks->done) return;
   using PR = Prec<T, GS>;
   constexpr int Np = (P + 1) * (P + 2) / 2;
   constexpr int NpP = (Np + 15) / 16 * 16;
@@ -292,8 +299,9 @@ k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict_
 
 // adds the right-line contributions of each block to the stored left lines
 template <typename T>
-__global__ void k_fixup(const TankDev* __restrict__ td, T* __restrict__ y, const T* __restrict__ side) {
+__global__ void k_fixup(const TankDev* __restrict__ td, T* __restrict__ y, const T* __restrict__ side, int flags) {
   const TankDev& d = *td;
+  if ((flags & F_GATE) && d.ks->done) return;
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= d.nb * d.nl) return;
   int b = gid / d.nl, ql = gid - b * d.nl;
@@ -315,63 +323,105 @@ __global__ void k_fixup(const TankDev* __restrict__ td, T* __restrict__ y, const
 // operator on the free nodes, or the 2D mass matrix): each column's interior
 // unknowns are condensed onto the vertical lines (Schur complement), the
 // block-circulant line system is solved mode by mode after a DFT along x,
-// and the interiors are recovered.
+// and the interiors are recovered.  Three launches:
+//   k_sd_interior  (block per column)  y_I = A_II^{-1} r_I, T_L = A_LI y_I, T_R = A_RI y_I
+//   k_sd_modes     (block per mode k)  g^_k = DFT_c(r_L - T_L - T_R(c-1)), x^_k = S^_k^{-1} g^_k
+//   k_sd_back      (block per column)  x_L at lines c, c+1 by inverse DFT,
+//                                      z_I = y_I - A_II^{-1}(A_IL x_L + A_IR x_R)
+// Matrices are stored so that consecutive threads read consecutive words:
+// A_II^{-1} and S^_k column-major, A_LI and A_RI row-major [line][interior].
+constexpr int kSdWaves = kBlockThreads / 64;
+
+template <typename T>
+__device__ inline void sd_matvec_t(const T* __restrict__ At, int nI, const double* __restrict__ x,
+                                   double* __restrict__ y) {
+  // y[i] = sum_j At[j*nI + i] x[j]   (thread per row, coalesced columns)
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
+    double acc = 0;
+    for (int j = 0; j < nI; ++j) acc += (double)At[(size_t)j * nI + i] * x[j];
+    y[i] = acc;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_interior(const TankDev* __restrict__ td, int which, const T* __restrict__ r) {
+k_sd_interior(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
   const TankDev& d = *td;
+  if (gate && d.ks->done) return;
   const SDData& sd = d.sd[which];
   using PR = Prec<T, T>;
   extern __shared__ double sh[];
   const int c = blockIdx.x, nI = sd.nI, q = sd.q;
   double* rI = sh;
   double* y = sh + nI;
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) rI[i] = r[(int64_t)c * d.nc + sd.I_idx[i]];
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) rI[i] = (double)r[(int64_t)c * d.nc + sd.I_idx[i]];
   __syncthreads();
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    const T* A = PR::AinvII(sd) + (size_t)i * nI;
-    double acc = 0;
-    for (int j = 0; j < nI; ++j) acc += A[j] * rI[j];
-    y[i] = acc;
-    sd.yI[(size_t)c * nI + i] = acc;
-  }
+  sd_matvec_t(PR::AinvII(sd), nI, rI, y);
   __syncthreads();
-  for (int a = threadIdx.x; a < 2 * q; a += blockDim.x) {
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) sd.yI[(size_t)c * nI + i] = y[i];
+  // T_L, T_R: one wavefront per line unknown, lanes over the interior
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int a = wv; a < 2 * q; a += kSdWaves) {
     const T* A = a < q ? PR::ALI(sd) + (size_t)a * nI : PR::ARI(sd) + (size_t)(a - q) * nI;
     double acc = 0;
-    for (int i = 0; i < nI; ++i) acc += A[i] * y[i];
-    if (a < q) sd.TL[(size_t)c * q + a] = acc;
-    else sd.TR[(size_t)c * q + a - q] = acc;
+    for (int i = lane; i < nI; i += 64) acc += (double)A[i] * y[i];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      if (a < q) sd.TL[(size_t)c * q + a] = acc;
+      else sd.TR[(size_t)c * q + a - q] = acc;
+    }
   }
 }
 
 template <typename T>
-__global__ void k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r) {
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
   const TankDev& d = *td;
+  if (gate && d.ks->done) return;
   const SDData& sd = d.sd[which];
   using PR = Prec<T, T>;
-  extern __shared__ double gh[];  // [q][2]
+  extern __shared__ double gh[];  // [kSdWaves][q][2] partial transforms, then [q][2]
   const int k = blockIdx.x, q = sd.q, nx = d.nx;
-  for (int j = threadIdx.x; j < q; j += blockDim.x) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // forward DFT along x: wave w takes columns c = w, w + 4, ...
+  const int step = (int)(((int64_t)kSdWaves * k) % nx);
+  for (int j0 = 0; j0 < q; j0 += 64) {
+    const int j = j0 + lane;
     double re = 0, im = 0;
-    int mm = 0;   // (k c) mod nx, advanced incrementally
-    for (int c = 0; c < nx; ++c, mm = (mm + k >= nx) ? mm + k - nx : mm + k) {
-      int cm = c == 0 ? nx - 1 : c - 1;
-      double g = r[(int64_t)c * d.nc + j] - sd.TL[(size_t)c * q + j] - sd.TR[(size_t)cm * q + j];
-      re += g * d.twid[2 * mm];
-      im += g * d.twid[2 * mm + 1];
+    if (j < q) {
+      int mm = (int)(((int64_t)k * wv) % nx);   // (k c) mod nx
+      for (int c = wv; c < nx; c += kSdWaves) {
+        int cm = c == 0 ? nx - 1 : c - 1;
+        double g = (double)r[(int64_t)c * d.nc + j] - sd.TL[(size_t)c * q + j] - sd.TR[(size_t)cm * q + j];
+        re += g * d.twid[2 * mm];
+        im += g * d.twid[2 * mm + 1];
+        mm += step;
+        if (mm >= nx) mm -= nx;
+      }
+      gh[(wv * q + j) * 2] = re;
+      gh[(wv * q + j) * 2 + 1] = im;
     }
-    gh[2 * j] = re;
-    gh[2 * j + 1] = im;
   }
   __syncthreads();
+  double* g = gh + (size_t)kSdWaves * q * 2;
+  for (int j = threadIdx.x; j < q; j += blockDim.x) {
+    double re = 0, im = 0;
+    for (int w = 0; w < kSdWaves; ++w) {
+      re += gh[(w * q + j) * 2];
+      im += gh[(w * q + j) * 2 + 1];
+    }
+    g[2 * j] = re;
+    g[2 * j + 1] = im;
+  }
+  __syncthreads();
+  // x^ = S^_k^{-1} g^ (column-major: thread per row)
+  const T* S = PR::Shat(sd) + (size_t)k * q * q * 2;
   for (int i = threadIdx.x; i < q; i += blockDim.x) {
-    const T* S = PR::Shat(sd) + ((size_t)k * q + i) * q * 2;
     double xr = 0, xi = 0;
     for (int j = 0; j < q; ++j) {
-      double sr = S[2 * j], si = S[2 * j + 1];
-      xr += sr * gh[2 * j] - si * gh[2 * j + 1];
-      xi += sr * gh[2 * j + 1] + si * gh[2 * j];
+      double sr = S[((size_t)j * q + i) * 2], si = S[((size_t)j * q + i) * 2 + 1];
+      xr += sr * g[2 * j] - si * g[2 * j + 1];
+      xi += sr * g[2 * j + 1] + si * g[2 * j];
     }
     sd.XH[((size_t)k * q + i) * 2] = xr;
     sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
@@ -379,53 +429,67 @@ __global__ void k_sd_modes(const TankDev* __restrict__ td, int which, const T* _
 }
 
 template <typename T>
-__global__ void k_sd_lines(const TankDev* __restrict__ td, int which, T* __restrict__ z) {
-  const TankDev& d = *td;
-  const SDData& sd = d.sd[which];
-  const int c = blockIdx.x, q = sd.q, nx = d.nx;
-  for (int j = threadIdx.x; j < q; j += blockDim.x) {
-    double acc = 0;
-    int mm = 0;   // (k c) mod nx, advanced incrementally
-    for (int k = 0; k < nx; ++k, mm = (mm + c >= nx) ? mm + c - nx : mm + c) {
-      // Re[(xr + i xi) * exp(+2 pi i k c / nx)], exp(+..) = conj(twid)
-      acc += sd.XH[((size_t)k * q + j) * 2] * d.twid[2 * mm] + sd.XH[((size_t)k * q + j) * 2 + 1] * d.twid[2 * mm + 1];
-    }
-    acc /= nx;
-    z[(int64_t)c * d.nc + j] = acc;
-    sd.XL[(size_t)c * q + j] = acc;
-  }
-  if (sd.zero_surface && threadIdx.x == 0) z[(int64_t)c * d.nc + d.nl - 1] = T(0);
-}
-
-template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z) {
+k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate) {
   const TankDev& d = *td;
+  if (gate && d.ks->done) return;
   const SDData& sd = d.sd[which];
   using PR = Prec<T, T>;
   extern __shared__ double sh[];
-  const int c = blockIdx.x, nI = sd.nI, q = sd.q;
-  const int cn = c + 1 == d.nx ? 0 : c + 1;
-  double* xl = sh;
-  double* xr = sh + q;
-  double* v = sh + 2 * q;
-  for (int a = threadIdx.x; a < q; a += blockDim.x) {
-    xl[a] = sd.XL[(size_t)c * q + a];
-    xr[a] = sd.XL[(size_t)cn * q + a];
+  const int c = blockIdx.x, nI = sd.nI, q = sd.q, nx = d.nx;
+  const int cn = c + 1 == nx ? 0 : c + 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double* part = sh;                            // [kSdWaves][2][q]
+  double* xl = sh + (size_t)kSdWaves * 2 * q;   // [q]
+  double* xr = xl + q;                          // [q]
+  double* v = xr + q;                           // [nI]
+  // inverse DFT at lines c and c+1: x_L[j] = Re sum_k x^_k[j] e^{+2 pi i k c / nx} / nx
+  const int st0 = (int)(((int64_t)kSdWaves * c) % nx), st1 = (int)(((int64_t)kSdWaves * cn) % nx);
+  for (int j0 = 0; j0 < q; j0 += 64) {
+    const int j = j0 + lane;
+    if (j < q) {
+      double a0 = 0, a1 = 0;
+      int m0 = (int)(((int64_t)c * wv) % nx), m1 = (int)(((int64_t)cn * wv) % nx);
+      for (int k = wv; k < nx; k += kSdWaves) {
+        double hr = sd.XH[((size_t)k * q + j) * 2], hi = sd.XH[((size_t)k * q + j) * 2 + 1];
+        a0 += hr * d.twid[2 * m0] + hi * d.twid[2 * m0 + 1];
+        a1 += hr * d.twid[2 * m1] + hi * d.twid[2 * m1 + 1];
+        m0 += st0;
+        if (m0 >= nx) m0 -= nx;
+        m1 += st1;
+        if (m1 >= nx) m1 -= nx;
+      }
+      part[(wv * 2 + 0) * q + j] = a0;
+      part[(wv * 2 + 1) * q + j] = a1;
+    }
   }
+  __syncthreads();
+  const double inx = 1.0 / nx;
+  for (int j = threadIdx.x; j < q; j += blockDim.x) {
+    double a0 = 0, a1 = 0;
+    for (int w = 0; w < kSdWaves; ++w) {
+      a0 += part[(w * 2 + 0) * q + j];
+      a1 += part[(w * 2 + 1) * q + j];
+    }
+    xl[j] = a0 * inx;
+    xr[j] = a1 * inx;
+    z[(int64_t)c * d.nc + j] = T(a0 * inx);
+  }
+  if (sd.zero_surface && threadIdx.x == 0) z[(int64_t)c * d.nc + d.nl - 1] = T(0);
   __syncthreads();
   const T* ALI = PR::ALI(sd);
   const T* ARI = PR::ARI(sd);
   for (int i = threadIdx.x; i < nI; i += blockDim.x) {
     double acc = 0;
-    for (int a = 0; a < q; ++a) acc += ALI[(size_t)a * nI + i] * xl[a] + ARI[(size_t)a * nI + i] * xr[a];
+    for (int a = 0; a < q; ++a)
+      acc += (double)ALI[(size_t)a * nI + i] * xl[a] + (double)ARI[(size_t)a * nI + i] * xr[a];
     v[i] = acc;
   }
   __syncthreads();
+  const T* At = PR::AinvII(sd);
   for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    const T* A = PR::AinvII(sd) + (size_t)i * nI;
     double acc = 0;
-    for (int j = 0; j < nI; ++j) acc += A[j] * v[j];
+    for (int j = 0; j < nI; ++j) acc += (double)At[(size_t)j * nI + i] * v[j];
     z[(int64_t)c * d.nc + sd.I_idx[i]] = T(sd.yI[(size_t)c * nI + i] - acc);
   }
   if (sd.zero_surface)
@@ -488,35 +552,6 @@ __global__ void k_gather_surface(const TankDev* __restrict__ td, const double* _
   out[s] = u[(int64_t)c * d.nc + d.surf_loc[m]];
 }
 
-// partial dot products: part[blk][k] = sum over the chunk of X_k . w
-// X_k = X + k*ldx, k < nvec; chunk = [blk*chunk, (blk+1)*chunk)
-template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_dots(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, const T* __restrict__ w,
-       double* __restrict__ part, int ldp, int64_t chunk) {
-  __shared__ double red[kBlockThreads];
-  int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
-  for (int k = 0; k < nvec; ++k) {
-    const T* x = X + k * ldx;
-    double s = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += (double)x[i] * (double)w[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp + k] = s;
-  }
-}
-
-// out[k] = sum_blk part[blk][k], k < nvec (one workgroup, fixed order)
-__global__ void __launch_bounds__(kBlockThreads)
-k_reduce(int nblk, int nvec, const double* __restrict__ part, int ldp, double* __restrict__ out) {
-  __shared__ double red[kBlockThreads];
-  for (int k = 0; k < nvec; ++k) {
-    double s = 0;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[(size_t)i * ldp + k];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) out[k] = s;
-  }
-}
-
 // ------------------------------------------------------------ fused reductions
 // Partial sums per workgroup (wave butterflies, fixed order), then the last
 // workgroup to finish (device-scope counter) adds the partials in block order:
@@ -524,10 +559,15 @@ k_reduce(int nblk, int nvec, const double* __restrict__ part, int ldp, double* _
 __device__ void givens_update(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m, int j,
                               double hnorm2, int32_t* __restrict__ status);
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Progress of the current Krylov cycle written to host-visible memory
+// (steps done, cycle done, converged) so the host can stop queueing steps
+// without synchronising the stream.
+__device__ inline void publish_progress(const KrylovState* ks, int32_t* mirror) {
+  if (!mirror) return;
+  int32_t v = (ks->j & PROG_STEPS) | (ks->done ? PROG_DONE : 0) | (ks->converged ? PROG_CONV : 0);
+  __hip_atomic_store(mirror, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+
 
 __device__ inline bool last_block(int32_t* counter) {
   __shared__ int is_last;
@@ -543,16 +583,30 @@ template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, const T* __restrict__ w,
              double* __restrict__ part, int ldp, double* __restrict__ out, int64_t chunk,
-             int32_t* __restrict__ counter) {
+             int32_t* __restrict__ counter, const KrylovState* __restrict__ gate) {
   __shared__ double red[4][kMaxVec];
+  if (gate && gate->done) return;
   const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k = 0; k < nvec; ++k) {
-    const T* x = X + k * ldx;
-    double sacc = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) sacc += (double)x[i] * (double)w[i];
-    sacc = wave_sum(sacc);
-    if (lane == 0) red[wv][k] = sacc;
+  // eight vectors per pass, their loads issued together (clamped indices,
+  // zero weights past nvec keep the loads unconditional)
+  for (int k0 = 0; k0 < nvec; k0 += 8) {
+    double sacc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sacc[u] = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const double wi = (double)w[i];
+      T xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = X[(int64_t)min(k0 + u, nvec - 1) * ldx + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sacc[u] += (double)xv[u] * wi;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      double t = wave_sum(sacc[u]);
+      if (lane == 0 && k0 + u < nvec) red[wv][k0 + u] = t;
+    }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nvec; k += blockDim.x)
@@ -571,7 +625,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase, int m, T* __restrict__ w,
              double* __restrict__ part, int ldp, int64_t chunk, KrylovState* __restrict__ ks,
-             int32_t* __restrict__ counter, int32_t* __restrict__ status) {
+             int32_t* __restrict__ counter, int32_t* __restrict__ status, int32_t* __restrict__ mirror) {
   __shared__ double red[4];
   if (ks->done) return;
   const double* hcol = Hbase + (size_t)j * (m + 1);
@@ -579,7 +633,14 @@ k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hba
   double sacc = 0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     double v = w[i];
-    for (int k = 0; k <= j; ++k) v -= hcol[k] * (double)V[(int64_t)k * n + i];
+    for (int k0 = 0; k0 <= j; k0 += 8) {
+      T vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) vv[u] = V[(int64_t)min(k0 + u, j) * n + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u <= j) v -= hcol[k0 + u] * (double)vv[u];
+    }
     T vt = T(v);
     w[i] = vt;
     sacc += (double)vt * (double)vt;
@@ -594,33 +655,11 @@ k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hba
     for (int b2 = 0; b2 < (int)gridDim.x; ++b2) t += part[(size_t)b2 * ldp];
     givens_update(ks, Hbase, m, j, t, status);
     *counter = 0;
+    publish_progress(ks, mirror);
   }
 }
 
 // ------------------------------------------------------------ GMRES pieces
-// w' = w - sum_{i<=j} h_i V_i  and partial ||w'||^2
-template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_orth(int64_t n, int j, const T* __restrict__ V, const double* __restrict__ hcol,
-       T* __restrict__ w, double* __restrict__ part, int ldp, int64_t chunk,
-       const KrylovState* __restrict__ ks) {
-  __shared__ double red[kBlockThreads];
-  if (ks->done) return;
-  int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
-  double s = 0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double v = w[i];
-    for (int k = 0; k <= j; ++k) v -= hcol[k] * (double)V[(int64_t)k * n + i];
-    T vt = T(v);
-    w[i] = vt;
-    s += (double)vt * (double)vt;
-  }
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp] = s;
-}
-
-// Givens update of column j (single thread).  H column j holds h_{0..j},
-// hnext = ||w'||^2 reduced.  Sets done/converged, V_{j+1} scale.
 // Givens update of Hessenberg column j (one thread).  The column holds
 // h_{0..j}; hnorm2 = ||w'||^2.  Sets done/converged and the norm of V_{j+1}.
 __device__ void givens_update(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m, int j,
@@ -663,12 +702,6 @@ __device__ void givens_update(KrylovState* __restrict__ ks, double* __restrict__
   g[m + 1 + j] = hn;  // y[] area reused as scratch for the norms
 }
 
-__global__ void k_givens(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m, int j,
-                         const double* __restrict__ hnorm2, int32_t* __restrict__ status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  givens_update(ks, Hbase, m, j, hnorm2[0], status);
-}
-
 // V_{j+1} = w' / hn
 template <typename T>
 __global__ void k_scale_next(int64_t n, int j, const T* __restrict__ w, T* __restrict__ V,
@@ -704,14 +737,30 @@ __global__ void k_update_x(int64_t n, const T* __restrict__ Z, const double* __r
   const double* y = g + (m + 1) + m;
   int jn = ks->j;
   double v = x[i];
-  for (int k = 0; k < jn; ++k) v += y[k] * (double)Z[(int64_t)k * n + i];
+  for (int k0 = 0; k0 < jn; k0 += 8) {
+    T zz[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) zz[u] = Z[(int64_t)min(k0 + u, jn - 1) * n + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < jn) v += y[k0 + u] * (double)zz[u];
+  }
   x[i] = T(v);
 }
 
 // start of a cycle: r is in V_0 (masked); beta = sqrt(rr); V_0 = r/beta; g = (beta, 0, ...)
+__device__ void cycle_start(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
+                            const double* __restrict__ rr, int first, int32_t* __restrict__ status);
 __global__ void k_cycle_start(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
-                              const double* __restrict__ rr, int first, int32_t* __restrict__ status) {
+                              const double* __restrict__ rr, int first, int32_t* __restrict__ status,
+                              int32_t* __restrict__ mirror) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  cycle_start(ks, Hbase, m, rr, first, status);
+  publish_progress(ks, mirror);
+}
+
+__device__ void cycle_start(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
+                            const double* __restrict__ rr, int first, int32_t* __restrict__ status) {
   double beta = sqrt(fmax(rr[0], 0.0));
   if (first) {
     ks->bnorm = sqrt(fmax(rr[1], 0.0));
@@ -974,62 +1023,89 @@ k_fs_rhs(const TankDev* __restrict__ td, const double* __restrict__ eta, const d
 
 // ------------------------------------------------------------ 1D periodic direct solves
 // y = A x for a block-circulant A given by its first block-row [P][ns]:
-// y[eP + a] = sum_j row[a][j] x[(eP + j) mod ns].
-__global__ void k_circ_apply(const TankDev* __restrict__ td, int which, const double* __restrict__ x,
-                             double* __restrict__ y) {
+// y[eP + a] = sum_j row[a][j] x[(eP + j) mod ns].  One wavefront per output
+// node: lanes stride over j, then a butterfly sum (fixed order).  x1/y1, when
+// given, is a second vector with the same operator.
+__global__ void __launch_bounds__(kBlockThreads)
+k_circ_apply(const TankDev* __restrict__ td, int which, const double* __restrict__ x0, double* __restrict__ y0,
+             const double* __restrict__ x1, double* __restrict__ y1) {
   const TankDev& d = *td;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.x * (kBlockThreads / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (s >= d.ns) return;
   const int P = d.P, ns = d.ns;
   const int e = s / P, a = s - e * P;
   const double* row = (which == 0 ? d.Rrow : d.Brow) + (size_t)a * ns;
   const int base = e * P;
-  double acc = 0;
-  int j0 = ns - base;                  // split the wrap-around into two contiguous runs
-  for (int j = 0; j < j0; ++j) acc += row[j] * x[base + j];
-  for (int j = j0; j < ns; ++j) acc += row[j] * x[base + j - ns];
-  y[s] = acc;
+  double acc0 = 0, acc1 = 0;
+  for (int j = lane; j < ns; j += 64) {
+    int src = base + j;
+    if (src >= ns) src -= ns;
+    double r = row[j];
+    acc0 += r * x0[src];
+    if (x1) acc1 += r * x1[src];
+  }
+  acc0 = wave_sum(acc0);
+  if (x1) acc1 = wave_sum(acc1);
+  if (lane == 0) {
+    y0[s] = acc0;
+    if (x1) y1[s] = acc1;
+  }
 }
 
-// Over-integrated element right-hand sides (Secs. 3.1.1, 3.3), element by
-// element: loc[e][i][2] = J_e (I^T M_f F)_i for F_eta and F_phi.
-__global__ void k_fs_local(const TankDev* __restrict__ td, const double* __restrict__ eta,
-                           const double* __restrict__ etax, const double* __restrict__ phix,
-                           const double* __restrict__ ws, double* __restrict__ loc) {
+// Over-integrated element right-hand sides (Secs. 3.1.1, 3.3): loc[e][i][2]
+// = J_e (I^T M_f F)_i for F_eta and F_phi.  One wavefront per element: the
+// fluxes at the P_f+1 fine nodes, their mass-weighted sums, then the
+// projection back onto the P+1 element nodes.
+__global__ void __launch_bounds__(kBlockThreads)
+k_fs_local(const TankDev* __restrict__ td, const double* __restrict__ eta, const double* __restrict__ etax,
+           const double* __restrict__ phix, const double* __restrict__ ws, double* __restrict__ loc) {
   const TankDev& d = *td;
-  const int it = blockIdx.x * blockDim.x + threadIdx.x;
-  const int P = d.P;
-  if (it >= d.nx * (P + 1)) return;
-  const int Pf = d.Pf, nf = Pf + 1;
-  const int e = it / (P + 1), i = it - e * (P + 1);
-  double acc_e = 0, acc_p = 0;
-  for (int a = 0; a < nf; ++a) {
-    double Iai = d.Ifine[a * (P + 1) + i];
-    if (Iai == 0.0) continue;
-    double se = 0, sp = 0;
-    for (int bq = 0; bq < nf; ++bq) {
-      double et = 0, ex = 0, px = 0, ww = 0;
-      for (int k = 0; k <= P; ++k) {
-        double Ik = d.Ifine[bq * (P + 1) + k];
-        int s = e * P + k;
-        if (s >= d.ns) s -= d.ns;
-        et += Ik * eta[s];
-        ex += Ik * etax[s];
-        px += Ik * phix[s];
-        ww += Ik * ws[s];
-      }
-      double fe = -ex * px + ww * (1.0 + ex * ex);
-      double fp = -d.g * et - 0.5 * (px * px - ww * ww * (1.0 + ex * ex));
-      double mf = d.Mfine[a * nf + bq];
-      se += mf * fe;
-      sp += mf * fp;
+  constexpr int kW = kBlockThreads / 64;
+  __shared__ double fl[kW][2][64];
+  __shared__ double mf[kW][2][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x * kW + wv;
+  const bool live = e < d.nx;
+  const int P = d.P, nf = d.Pf + 1;
+  if (live && lane < nf) {
+    double et = 0, ex = 0, px = 0, ww = 0;
+    for (int k = 0; k <= P; ++k) {
+      double Ik = d.Ifine[lane * (P + 1) + k];
+      int s = e * P + k;
+      if (s >= d.ns) s -= d.ns;
+      et += Ik * eta[s];
+      ex += Ik * etax[s];
+      px += Ik * phix[s];
+      ww += Ik * ws[s];
     }
-    acc_e += Iai * se;
-    acc_p += Iai * sp;
+    fl[wv][0][lane] = -ex * px + ww * (1.0 + ex * ex);
+    fl[wv][1][lane] = -d.g * et - 0.5 * (px * px - ww * ww * (1.0 + ex * ex));
   }
-  const double J = 0.5 * d.dX;
-  loc[(size_t)it * 2 + 0] = J * acc_e;
-  loc[(size_t)it * 2 + 1] = J * acc_p;
+  __syncthreads();
+  if (live && lane < nf) {
+    double se = 0, sp = 0;
+    for (int b = 0; b < nf; ++b) {
+      double m = d.Mfine[lane * nf + b];
+      se += m * fl[wv][0][b];
+      sp += m * fl[wv][1][b];
+    }
+    mf[wv][0][lane] = se;
+    mf[wv][1][lane] = sp;
+  }
+  __syncthreads();
+  if (live && lane <= P) {
+    double ae = 0, ap = 0;
+    for (int a = 0; a < nf; ++a) {
+      double I = d.Ifine[a * (P + 1) + lane];
+      ae += I * mf[wv][0][a];
+      ap += I * mf[wv][1][a];
+    }
+    const double J = 0.5 * d.dX;
+    const size_t it = (size_t)e * (P + 1) + lane;
+    loc[it * 2 + 0] = J * ae;
+    loc[it * 2 + 1] = J * ap;
+  }
 }
 
 // node sums of the element right-hand sides (left element first)
@@ -1153,13 +1229,14 @@ void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const do
 }
 
 template <typename T>
-static void launch_sd(const TankDev& h, const TankDev* d, int which, const T* u, T* y, hipStream_t st) {
+static void launch_sd(const TankDev& h, const TankDev* d, int which, const T* u, T* y, int gate, hipStream_t st) {
   const SDData& sd = h.sd[which];
-  size_t s1 = sizeof(double) * 2 * sd.nI, s4 = sizeof(double) * (2 * sd.q + sd.nI);
-  hipLaunchKernelGGL(k_sd_interior<T>, dim3(h.nx), dim3(kBlockThreads), s1, st, d, which, u);
-  hipLaunchKernelGGL(k_sd_modes<T>, dim3(h.nx), dim3(64), sizeof(double) * 2 * sd.q, st, d, which, u);
-  hipLaunchKernelGGL(k_sd_lines<T>, dim3(h.nx), dim3(64), 0, st, d, which, y);
-  hipLaunchKernelGGL(k_sd_back<T>, dim3(h.nx), dim3(kBlockThreads), s4, st, d, which, y);
+  size_t s1 = sizeof(double) * 2 * sd.nI;
+  size_t s2 = sizeof(double) * (kSdWaves + 1) * 2 * sd.q;
+  size_t s3 = sizeof(double) * ((kSdWaves * 2 + 2) * (size_t)sd.q + sd.nI);
+  hipLaunchKernelGGL(k_sd_interior<T>, dim3(h.nx), dim3(kBlockThreads), s1, st, d, which, u, gate);
+  hipLaunchKernelGGL(k_sd_modes<T>, dim3(h.nx), dim3(kBlockThreads), s2, st, d, which, u, gate);
+  hipLaunchKernelGGL(k_sd_back<T>, dim3(h.nx), dim3(kBlockThreads), s3, st, d, which, y, gate);
 }
 
 // element kernel only (no line fix-up)
@@ -1200,13 +1277,13 @@ static void gather_full(const TankDev& h, const TankDev* d, int op, const T* u, 
                         hipStream_t st) {
   if ((op == OP_PRE_LAP || op == OP_PRE_MASS) && h.pre_kind == 1) {
     if (op == OP_PRE_LAP || sizeof(T) == sizeof(double)) {
-      launch_sd<T>(h, d, op == OP_PRE_LAP ? 0 : 1, u, y, st);
+      launch_sd<T>(h, d, op == OP_PRE_LAP ? 0 : 1, u, y, (flags & F_GATE) ? 1 : 0, st);
       return;
     }
   }
   if (op == OP_STIFF && h.use_mfma) stiff_mfma(h, d, u, y, side, flags, sizeof(GS) == 1 ? 2 : 1, st);
   else gather_kernel<T, GS>(h, d, op, u, y, side, flags, st);
-  hipLaunchKernelGGL(k_fixup<T>, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side);
+  hipLaunchKernelGGL(k_fixup<T>, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side, flags);
 }
 
 void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side,
@@ -1225,11 +1302,11 @@ void launch_gather_only(const TankDev& h, const TankDev* d, int op, int prec, co
                         hipStream_t st) {
   if (prec == 0) {
     if ((op == OP_PRE_LAP || op == OP_PRE_MASS) && h.pre_kind == 1)
-      launch_sd<double>(h, d, op == OP_PRE_LAP ? 0 : 1, (const double*)u, (double*)y, st);
+      launch_sd<double>(h, d, op == OP_PRE_LAP ? 0 : 1, (const double*)u, (double*)y, 0, st);
     else if (op == OP_STIFF && h.use_mfma) launch_stiff_mfma(h, d, (const double*)u, (double*)y, (double*)side, 0, st);
     else gather_kernel<double, double>(h, d, op, (const double*)u, (double*)y, (double*)side, 0, st);
   } else {
-    if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<float>(h, d, 0, (const float*)u, (float*)y, st);
+    if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<float>(h, d, 0, (const float*)u, (float*)y, 0, st);
     else if (op == OP_STIFF && h.use_mfma)
       launch_stiff_mfma(h, d, (const float*)u, (float*)y, (float*)side, 0, prec == 2 ? 2 : 1, st);
     else if (prec == 2) gather_kernel<float, BF16>(h, d, op, (const float*)u, (float*)y, (float*)side, 0, st);
@@ -1265,43 +1342,40 @@ void dot_layout(int64_t n, int* nchunk, int64_t* chunk) {
 
 template <typename T>
 static void dots_t(int64_t n, int nvec, const T* X, int64_t ldx, const T* w, double* part, int ldp, double* out,
-                   int32_t* counter, hipStream_t st) {
+                   int32_t* counter, const KrylovState* gate, hipStream_t st) {
   int nc;
   int64_t chunk;
   dot_layout(n, &nc, &chunk);
   hipLaunchKernelGGL(k_dots_fused<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, nvec, X, ldx, w, part, ldp, out,
-                     chunk, counter);
+                     chunk, counter, gate);
 }
 void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
-                 double* out, int32_t* counter, hipStream_t st) {
-  dots_t<double>(n, nvec, X, ldx, w, part, ldp, out, counter, st);
+                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st) {
+  dots_t<double>(n, nvec, X, ldx, w, part, ldp, out, counter, gate, st);
 }
 void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
-                 double* out, int32_t* counter, hipStream_t st) {
-  dots_t<float>(n, nvec, X, ldx, w, part, ldp, out, counter, st);
+                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st) {
+  dots_t<float>(n, nvec, X, ldx, w, part, ldp, out, counter, gate, st);
 }
 
 template <typename T>
 static void orth_t(int64_t n, int j, const T* V, double* H, int m, T* w, double* part, int ldp, KrylovState* ks,
-                   int32_t* counter, int32_t* status, hipStream_t st) {
+                   int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st) {
   int nc;
   int64_t chunk;
   dot_layout(n, &nc, &chunk);
   hipLaunchKernelGGL(k_orth_fused<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, H, m, w, part, ldp, chunk, ks,
-                     counter, status);
+                     counter, status, mirror);
 }
 void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
-                        KrylovState* ks, int32_t* counter, int32_t* status, hipStream_t st) {
-  orth_t<double>(n, j, V, H, m, w, part, ldp, ks, counter, status, st);
+                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st) {
+  orth_t<double>(n, j, V, H, m, w, part, ldp, ks, counter, status, mirror, st);
 }
 void launch_orth_givens(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
-                        KrylovState* ks, int32_t* counter, int32_t* status, hipStream_t st) {
-  orth_t<float>(n, j, V, H, m, w, part, ldp, ks, counter, status, st);
+                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st) {
+  orth_t<float>(n, j, V, H, m, w, part, ldp, ks, counter, status, mirror, st);
 }
 
-void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, int32_t* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, ks, H, m, j, hn2, status);
-}
 void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m,
                        const KrylovState* ks, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_next<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, j, w, V, H, m, ks);
@@ -1321,13 +1395,13 @@ void launch_solve_update(int64_t n, const float* Z, double* H, int m, KrylovStat
   hipLaunchKernelGGL(k_update_x<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
 }
 void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status,
-                        int64_t n, double* V, hipStream_t st) {
-  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status);
+                        int64_t n, double* V, int32_t* mirror, hipStream_t st) {
+  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status, mirror);
   hipLaunchKernelGGL(k_scale_v0<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, V, ks);
 }
 void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status,
-                        int64_t n, float* V, hipStream_t st) {
-  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status);
+                        int64_t n, float* V, int32_t* mirror, hipStream_t st) {
+  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status, mirror);
   hipLaunchKernelGGL(k_scale_v0<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, V, ks);
 }
 void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
@@ -1349,8 +1423,8 @@ void launch_fill_f(int64_t n, float* y, hipStream_t st) { hipMemsetAsync(y, 0, n
 void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, double* out0, const double* in1,
                        double* out1, hipStream_t st) {
   if (h.circ1d) {
-    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, 0, in0, out0);
-    if (in1) hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, 0, in1, out1);
+    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, 0, in0,
+                       out0, in1, out1);
     return;
   }
   SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_recover_dx<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, in0, out0, in1, out1));
@@ -1361,11 +1435,11 @@ void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const 
     double* loc = h.s1d + 5 * (size_t)h.ns;
     double* re = h.s1d + 11 * (size_t)h.ns;
     double* rp = h.s1d + 12 * (size_t)h.ns;
-    hipLaunchKernelGGL(k_fs_local, dim3(nblk((int64_t)h.nx * (h.P + 1))), dim3(kBlockThreads), 0, st, d, eta, etax,
+    hipLaunchKernelGGL(k_fs_local, dim3(nblk(h.nx, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, eta, etax,
                        phix, ws, loc);
     hipLaunchKernelGGL(k_fs_gather, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, loc, re, rp);
-    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, 1, re, et);
-    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, 1, rp, pt);
+    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, 1, re, et,
+                       rp, pt);
     return;
   }
   SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_fs_rhs<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, eta, etax, phix, ws, et, pt));

@@ -69,6 +69,7 @@ k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restr
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const TankDev& d = *td;
+  if ((flags & F_GATE) && d.ks->done) return;
   constexpr int Np = (P + 1) * (P + 2) / 2;
   constexpr int NpP = (Np + 15) / 16 * 16;
   constexpr int MT = NpP / 16;      // M-tiles per operator block

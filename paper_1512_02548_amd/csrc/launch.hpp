@@ -7,7 +7,11 @@
 
 namespace sem {
 enum { OP_STIFF = 0, OP_MASS = 1, OP_PRE_LAP = 2, OP_PRE_MASS = 3, OP_SZ = 4 };
-enum { F_MASK_SURF = 1, F_NEG = 2 };
+// gather flags: mask the surface rows, negate, skip the launch once the
+// tank's Krylov cycle is done (kernels queued ahead of a convergence test)
+enum { F_MASK_SURF = 1, F_NEG = 2, F_GATE = 4 };
+// progress word mirrored to host memory by the Krylov kernels
+enum { PROG_STEPS = 0xffff, PROG_DONE = 1 << 16, PROG_CONV = 1 << 17 };
 
 size_t gather_lds_bytes(const TankDev& h, size_t word);
 void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const double* etax, int what, hipStream_t st);
@@ -31,14 +35,13 @@ void launch_scatter_surface(const TankDev& h, const TankDev* d, const double* ph
 void launch_gather_surface(const TankDev& h, const TankDev* d, const double* u, double* out, hipStream_t st);
 void dot_layout(int64_t n, int* nchunk, int64_t* chunk);
 void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
-                 double* out, int32_t* counter, hipStream_t st);
+                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st);
 void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
-                 double* out, int32_t* counter, hipStream_t st);
+                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st);
 void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
-                        KrylovState* ks, int32_t* counter, int32_t* status, hipStream_t st);
+                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st);
 void launch_orth_givens(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
-                        KrylovState* ks, int32_t* counter, int32_t* status, hipStream_t st);
-void launch_givens(KrylovState* ks, double* H, int m, int j, const double* hn2, int32_t* status, hipStream_t st);
+                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st);
 void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m, const KrylovState* ks,
                        hipStream_t st);
 void launch_scale_next(int64_t n, int j, const float* w, float* V, const double* H, int m, const KrylovState* ks,
@@ -46,9 +49,9 @@ void launch_scale_next(int64_t n, int j, const float* w, float* V, const double*
 void launch_solve_update(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x, hipStream_t st);
 void launch_solve_update(int64_t n, const float* Z, double* H, int m, KrylovState* ks, float* x, hipStream_t st);
 void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status, int64_t n,
-                        double* V, hipStream_t st);
+                        double* V, int32_t* mirror, hipStream_t st);
 void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status, int64_t n,
-                        float* V, hipStream_t st);
+                        float* V, int32_t* mirror, hipStream_t st);
 void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
                      int mask, hipStream_t st);
 void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y, float* r,

@@ -70,6 +70,13 @@ struct sem_mesh {
   std::map<std::string, size_t> off;
   // RK4 scratch (surface arrays)
   double *rk = nullptr;
+  // progress word of the running Krylov cycle in pinned host memory (written
+  // by the device, read by the host while it queues steps)
+  int32_t* prog_host = nullptr;
+  int32_t* prog_dev = nullptr;
+  ~sem_mesh() {
+    if (prog_host) (void)hipHostFree(prog_host);
+  }
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -431,7 +438,8 @@ static sem_status build_mesh(sem_mesh* M) {
       // per-mode symbol S_LL + S_RR + S_LR e^{i k} + S_RL e^{-i k}, inverted
       using cd = std::complex<double>;
       H.Shat.assign((size_t)nx * q * q * 2, 0.0);
-      for (int k = 0; k < nx; ++k) {
+      // the symbol of mode nx-k is the conjugate of mode k's (S is real)
+      for (int k = 0; k <= nx / 2; ++k) {
         double kap = 2.0 * M_PI * k / nx;
         cd ep(std::cos(kap), std::sin(kap)), em = std::conj(ep);
         std::vector<cd> Ak((size_t)q * q), Ik((size_t)q * q, 0.0);
@@ -468,6 +476,10 @@ static sem_status build_mesh(sem_mesh* M) {
         for (int a = 0; a < q * q; ++a) {
           H.Shat[((size_t)k * q * q + a) * 2] = Ik[a].real();
           H.Shat[((size_t)k * q * q + a) * 2 + 1] = Ik[a].imag();
+          if (k > 0 && nx - k != k) {
+            H.Shat[((size_t)(nx - k) * q * q + a) * 2] = Ik[a].real();
+            H.Shat[((size_t)(nx - k) * q * q + a) * 2 + 1] = -Ik[a].imag();
+          }
         }
       }
     }
@@ -629,8 +641,20 @@ static sem_status build_mesh(sem_mesh* M) {
   put(M, "twid", twid);
   for (int w = 0; w < 2; ++w) {
     std::string p = w == 0 ? "sd0_" : "sd1_";
-    const SDHost& H = sdh[w];
+    SDHost& H = sdh[w];
     put(M, (p + "I_idx").c_str(), H.I_idx);
+    // A_II^{-1} and the per-mode inverses are uploaded column-major
+    H.AinvII = transpose(H.AinvII, H.nI, H.nI);
+    {
+      std::vector<double> St(H.Shat.size());
+      const size_t qq = (size_t)H.q * H.q;
+      for (int k = 0; k < nx; ++k)
+        for (int a = 0; a < H.q; ++a)
+          for (int b = 0; b < H.q; ++b)
+            for (int ri = 0; ri < 2; ++ri)
+              St[((k * qq) + (size_t)b * H.q + a) * 2 + ri] = H.Shat[((k * qq) + (size_t)a * H.q + b) * 2 + ri];
+      H.Shat.swap(St);
+    }
     put(M, (p + "AinvII").c_str(), H.AinvII);
     put(M, (p + "ALI").c_str(), H.ALI);
     put(M, (p + "ARI").c_str(), H.ARI);
@@ -643,7 +667,6 @@ static sem_status build_mesh(sem_mesh* M) {
     reserve(M, (p + "TL").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
     reserve(M, (p + "TR").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
     reserve(M, (p + "XH").c_str(), (size_t)nx * std::max(1, H.q) * 2 * sizeof(double));
-    reserve(M, (p + "XL").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
   }
   // dynamic
   const int m = M->m;
@@ -766,6 +789,15 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   if (bytes < M->ws_bytes) return fail(SEM_E_NOMEM, "workspace smaller than sem_mesh_query reports");
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SEM_E_INVAL, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
+  if (!M->prog_host) {
+    void* p = nullptr;
+    HIPCHK(hipHostMalloc(&p, 256, hipHostMallocMapped | hipHostMallocCoherent));
+    M->prog_host = (int32_t*)p;
+    void* dp = nullptr;
+    HIPCHK(hipHostGetDevicePointer(&dp, p, 0));
+    M->prog_dev = (int32_t*)dp;
+    *(volatile int32_t*)M->prog_host = 0;
+  }
   M->ws = (char*)workspace;
   TankDev& h = M->hd;
   h = TankDev{};
@@ -833,7 +865,6 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     sd.TL = at<double>(M, (p + "TL").c_str());
     sd.TR = at<double>(M, (p + "TR").c_str());
     sd.XH = at<double>(M, (p + "XH").c_str());
-    sd.XL = at<double>(M, (p + "XL").c_str());
   }
   h.M1 = at<double>(M, "M1");
   h.S1 = at<double>(M, "S1");
@@ -926,7 +957,7 @@ struct GmresCfg {
   bool mask;
   double rtol;
   int max_iter;
-  int poll;
+  int ahead;   // Krylov steps queued ahead of the device
   int gstore;   // FP32 path: 1 = FP32 factors, 2 = bfloat16 factors
 };
 
@@ -949,6 +980,12 @@ static void gather_t(sem_mesh* M, const GmresCfg& c, int op, const float* u, flo
 // Restarted right-preconditioned GMRES (classical Gram-Schmidt, Givens
 // rotations) on device vectors of type T: x (in: guess, out: solution), b.
 // Inner products, the Hessenberg matrix and the rotations are FP64.
+//
+// The host queues Arnoldi steps without synchronising: every step's kernels
+// return at once when the cycle is done, and the device publishes its
+// progress to pinned host memory, so the host stops queueing when it sees
+// convergence and never runs more than `ahead` steps in front of the device.
+// The stream is synchronised once per cycle.
 template <typename T, typename Buf>
 static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, const T* b, int* iters_out,
                         double* relres_out, hipStream_t st) {
@@ -959,39 +996,52 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
   const int ldp = m + 2;
   double* scal = M->scal;
   const int flags = cfg.mask ? 1 : 0;
+  const int gflags = flags | F_GATE;
+  const int ahead = std::max(1, cfg.ahead);
+  volatile int32_t* prog = M->prog_host;
   KrylovState ks0{};
   ks0.rtol = cfg.rtol;
   HIPCHK(hipMemcpyAsync(h.ks, &ks0, sizeof(ks0), hipMemcpyHostToDevice, st));
   int32_t* cnt = &h.ks->pad[0];
-  launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, cnt, st);
+  launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, cnt, nullptr, st);
   int total = 0;
   KrylovState hks{};
   bool first = true;
-  int poll = std::max(1, cfg.poll);
   while (true) {
+    *prog = 0;
     // r = b - A x
     gather_t(M, cfg, cfg.op, x, B.w, B.side, flags, st);
     launch_residual(h, d, n, b, B.w, B.V, cfg.mask ? 1 : 0, st);
-    launch_dots(n, 1, B.V, 0, B.V, h.part, ldp, scal + 0, cnt, st);
-    launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, B.V, st);
+    launch_dots(n, 1, B.V, 0, B.V, h.part, ldp, scal + 0, cnt, nullptr, st);
+    launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, B.V, M->prog_dev, st);
     first = false;
-    HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (hks.status || hks.converged || total >= cfg.max_iter) break;
-    for (int j = 0; j < m; ++j) {
+    for (int j = 0; j < m && total + j < cfg.max_iter; ++j) {
       T* Vj = B.V + (size_t)j * n;
       T* Zj = B.Z + (size_t)j * n;
-      gather_t(M, cfg, cfg.pre, Vj, Zj, B.side, flags, st);
-      gather_t(M, cfg, cfg.op, Zj, B.w, B.side, flags, st);
+      gather_t(M, cfg, cfg.pre, Vj, Zj, B.side, gflags, st);
+      gather_t(M, cfg, cfg.op, Zj, B.w, B.side, gflags, st);
       double* Hcol = h.H + (size_t)j * (m + 1);
-      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, st);
-      launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, st);
+      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st);
+      launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
       launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
-      if ((j + 1) % poll == 0 || j == m - 1 || total + j + 1 >= cfg.max_iter) {
-        HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (hks.done || total + j + 1 >= cfg.max_iter) break;
+      // wait while the device is more than `ahead` steps behind
+      bool stop = false;
+      while (true) {
+        int32_t v = *prog;
+        if (v & PROG_DONE) {
+          stop = true;
+          break;
+        }
+        if (j + 1 - (v & PROG_STEPS) <= ahead) break;
+        hipError_t q = hipStreamQuery(st);
+        if (q == hipSuccess) {          // queue drained: the word is final
+          stop = (*prog & PROG_DONE) != 0;
+          break;
+        }
+        if (q != hipErrorNotReady) HIPCHK(q);
+        std::this_thread::yield();
       }
+      if (stop) break;
     }
     launch_solve_update(n, B.Z, h.H, m, h.ks, x, st);
     HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
@@ -1028,7 +1078,7 @@ static void default_opts(sem_solve_opts* o) {
   o->inner_rtol = 1e-4;
   o->max_refine = 30;
   o->warm_start = 0;
-  o->poll_every = 10;
+  o->lookahead = 3;
 }
 
 // ------------------------------------------------------------ public calls
@@ -1153,7 +1203,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   double rel = 0;
   sem_status s = SEM_OK;
   if (o->prec == SEM_PREC_FP64) {
-    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->rtol, o->max_iter, o->poll_every, 0};
+    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->rtol, o->max_iter, o->lookahead, 0};
     s = gmres(M, cfg, buf64(M), h.xs, h.b, &iters, &rel, st);
   } else {
     const int ldp = M->m + 2;
@@ -1161,17 +1211,17 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
     double nb2 = 0, rr = 0;
     int32_t* cnt = &h.ks->pad[0];
     HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t), st));
-    launch_dots(n, 1, h.b, 0, h.b, h.part, ldp, scal + 4, cnt, st);
+    launch_dots(n, 1, h.b, 0, h.b, h.part, ldp, scal + 4, cnt, nullptr, st);
     HIPCHK(hipMemcpyAsync(&nb2, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     double bnorm = std::sqrt(nb2);
-    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->inner_rtol, 0, o->poll_every, o->prec == SEM_PREC_BF16_IR ? 2 : 1};
+    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->inner_rtol, 0, o->lookahead, o->prec == SEM_PREC_BF16_IR ? 2 : 1};
     s = SEM_E_NOCONV;
     for (int k = 0; k <= o->max_refine; ++k) {
       // FP64 residual r = b - A x
       launch_gather(h, d, OP_STIFF, h.xs, h.w, h.side, F_MASK_SURF, st);
       launch_residual(h, d, n, h.b, h.w, h.tmp, 1, st);
-      launch_dots(n, 1, h.tmp, 0, h.tmp, h.part, ldp, scal + 4, cnt, st);
+      launch_dots(n, 1, h.tmp, 0, h.tmp, h.part, ldp, scal + 4, cnt, nullptr, st);
       HIPCHK(hipMemcpyAsync(&rr, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       double rn = std::sqrt(rr);
@@ -1241,7 +1291,13 @@ static sem_status recover_w_core(sem_mesh* M, const double* Phi, double* out, hi
   const TankDev& h = M->hd;
   const TankDev* d = M->dtank;
   launch_gather(h, d, OP_SZ, Phi, h.b, h.side, 0, st);
-  GmresCfg cfg{OP_MASS, OP_PRE_MASS, false, 1e-14, 400, 10, 0};
+  if (h.pre_kind == 1) {
+    // periodic tanks: the mass matrix is inverted exactly (line condensation + DFT)
+    launch_gather(h, d, OP_PRE_MASS, h.b, h.wmass, h.side, 0, st);
+    launch_gather_surface(h, d, h.wmass, out, st);
+    return SEM_OK;
+  }
+  GmresCfg cfg{OP_MASS, OP_PRE_MASS, false, 1e-14, 400, 4, 0};
   int iters;
   double rel;
   sem_status s = gmres(M, cfg, buf64(M), h.wmass, h.b, &iters, &rel, st);

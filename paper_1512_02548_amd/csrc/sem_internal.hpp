@@ -40,10 +40,10 @@ struct SDData {
   int32_t nI, q;                  // interior unknowns per column, unknowns per line
   int32_t zero_surface, pad;      // 1: surface nodes are Dirichlet (set to 0)
   const int32_t* I_idx;           // [nI] column-local indices of the interior unknowns
-  const double* AinvII;           // [nI][nI]
+  const double* AinvII;           // [nI][nI] column-major
   const double* ALI;              // [q][nI] coupling of the left line to the interior
   const double* ARI;              // [q][nI] coupling of the right line to the interior
-  const double* Shat;             // [nx][q][q][2] inverse line symbol per Fourier mode
+  const double* Shat;             // [nx][q][q][2] inverse line symbol per Fourier mode, column-major
   const float* AinvII32;
   const float* ALI32;
   const float* ARI32;
@@ -52,7 +52,6 @@ struct SDData {
   double* TL;                     // [nx][q]
   double* TR;                     // [nx][q]
   double* XH;                     // [nx][q][2] modal line solution
-  double* XL;                     // [nx][q] line solution
 };
 
 // Everything a kernel needs about one tank; lives in device memory at the

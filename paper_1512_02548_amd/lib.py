@@ -48,7 +48,7 @@ class sem_mesh_info(C.Structure):
 class sem_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32),
                 ("inner_rtol", C.c_double), ("max_refine", C.c_int32), ("warm_start", C.c_int32),
-                ("poll_every", C.c_int32), ("reserved", C.c_int32)]
+                ("lookahead", C.c_int32), ("reserved", C.c_int32)]
 
 
 class sem_solve_stats(C.Structure):
@@ -116,15 +116,15 @@ def _stream(stream=None):
 
 
 def default_opts(rtol=1e-12, max_iter=5000, prec=SEM_PREC_FP64, inner_rtol=1e-4, max_refine=30,
-                 warm_start=0, poll_every=10):
-    return sem_solve_opts(rtol, max_iter, prec, inner_rtol, max_refine, warm_start, poll_every, 0)
+                 warm_start=0, lookahead=3):
+    return sem_solve_opts(rtol, max_iter, prec, inner_rtol, max_refine, warm_start, lookahead, 0)
 
 
 class Mesh:
     """A tank on the device: mesh_create + query + a torch-allocated workspace + bind."""
 
     def __init__(self, nx, nz, P, length, periodic, h, hx, g=9.81, sigma_levels=None, filter_ic=None,
-                 filter_sigma=1.0, overint=None, restart=30, variant=1, device="cuda", bind=True):
+                 filter_sigma=1.0, overint=None, restart=30, variant=0, device="cuda", bind=True):
         self.h = np.ascontiguousarray(h, dtype=np.float64)
         self.hx = np.ascontiguousarray(hx, dtype=np.float64)
         self._sl = None if sigma_levels is None else np.ascontiguousarray(sigma_levels, dtype=np.float64)

@@ -56,7 +56,7 @@ class GpuBackend:
         self.nstreams = nstreams
         self.device = device
         self.opts = opts if opts is not None else lib.default_opts(
-            rtol=1e-8, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-3, poll_every=8)
+            rtol=1e-8, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-3, lookahead=3)
         self._batch = None
         self._batch_key = None
 
@@ -228,7 +228,7 @@ def main():
     from . import workloads as wl
     reqs = make_requests(a.requests, a.rate, a.steps, max_nx=a.max_nx)
     if a.sequential_fp64:
-        be = GpuBackend(nstreams=1, opts=lib.default_opts(rtol=1e-8, warm_start=1, poll_every=8))
+        be = GpuBackend(nstreams=1, opts=lib.default_opts(rtol=1e-8, warm_start=1, lookahead=3))
         srv = Server(be, wl.batch_tank_state, max_slots=1)
         for r in reqs:
             r.arrival = 0.0

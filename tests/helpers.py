@@ -22,7 +22,7 @@ class Pair:
     """Library mesh (bound on the GPU) + oracle mesh + numbering map."""
 
     def __init__(self, nx, nz, P, L, periodic, h, hx, filter_ic=None, filter_sigma=1.0, Pf=None, g=9.81,
-                 restart=30, variant=1):
+                 restart=30, variant=0):
         from paper_1512_02548_amd import lib
         self.lib = lib
         self.m = lib.Mesh(nx, nz, P, L, periodic, h, hx, g=g, filter_ic=filter_ic, filter_sigma=filter_sigma,

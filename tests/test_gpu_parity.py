@@ -46,8 +46,10 @@ def make_pair(case, bar=False, **kw):
 
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("bar", [False, True])
-def test_apply_operators(case, bar):
-    pair, eta, phi = make_pair(case, bar)
+@pytest.mark.parametrize("variant", [0, 1])
+def test_apply_operators(case, bar, variant):
+    """variant 0: stiffness on matrix cores; 1: the reference (vector) kernel."""
+    pair, eta, phi = make_pair(case, bar, variant=variant)
     of = oracle_fields(pair, eta, phi)
     m = pair.m
     m.set_surface(cuda(eta), cuda(of["etax"]))
