@@ -70,10 +70,6 @@ struct Prec<double, double> {
   __device__ static const double* MDs(const TankDev& d) { return d.MDs; }
   __device__ static const double* Mref(const TankDev& d) { return d.Mref; }
   __device__ static const double* pre_lap(const TankDev& d) { return d.pre_lap; }
-  __device__ static const double* AinvII(const SDData& d) { return d.AinvII; }
-  __device__ static const double* ALI(const SDData& d) { return d.ALI; }
-  __device__ static const double* ARI(const SDData& d) { return d.ARI; }
-  __device__ static const double* Shat(const SDData& d) { return d.Shat; }
   __device__ static double G(const TankDev& d, int64_t b, int eb, int i, int c) {
     return d.G[tile_index64(d.T, d.NpP, b, eb, i, 3, c)];
   }
@@ -86,10 +82,6 @@ struct Prec<float, float> {
   __device__ static const float* MDs(const TankDev& d) { return d.MDs32; }
   __device__ static const float* Mref(const TankDev& d) { return d.Mref32; }
   __device__ static const float* pre_lap(const TankDev& d) { return d.pre_lap32; }
-  __device__ static const float* AinvII(const SDData& d) { return d.AinvII32; }
-  __device__ static const float* ALI(const SDData& d) { return d.ALI32; }
-  __device__ static const float* ARI(const SDData& d) { return d.ARI32; }
-  __device__ static const float* Shat(const SDData& d) { return d.Shat32; }
   __device__ static float G(const TankDev& d, int64_t b, int eb, int i, int c) {
     return d.G32[tile_index(d.T, d.NpP, b, eb, i, 3, c)];
   }
@@ -181,6 +173,7 @@ k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict_
   T* st2 = st1 + d.EB * NpP;             // [EB][NpP] second stage
   T* st3 = st2 + d.EB * NpP;             // [EB][NpP] element outputs
   // 1. stage the input region
+#pragma unroll 4
   for (int q = threadIdx.x; q < nreg; q += blockDim.x) {
     int lc = q / nc, ql = q - lc * nc;
     int64_t gi;
@@ -266,11 +259,18 @@ k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict_
     int lc = q / nc, ql = q - lc * nc;
     T acc = 0;
     if (lc < cbb) {
-      int cnt = d.acc_cnt[ql];
-      for (int k = 0; k < cnt; ++k) {
-        int e = d.acc_ent[ql * kMaxContrib + k];
-        int prev = (e >> 30) & 1;
-        int off = e & 0x3fffffff;
+      // the node's contributions: count and up to kMaxContrib table entries,
+      // loaded together (two 16-byte loads)
+      const int cnt = d.acc_cnt[ql];
+      const int4* e4 = reinterpret_cast<const int4*>(d.acc_ent + (size_t)ql * kMaxContrib);
+      const int4 ea = e4[0], eb = e4[1];
+      const int ent[kMaxContrib] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+#pragma unroll
+      for (int k = 0; k < kMaxContrib; ++k) {
+        if (k >= cnt) break;
+        const int e = ent[k];
+        const int prev = (e >> 30) & 1;
+        const int off = e & 0x3fffffff;
         if (prev) {
           if (lc == 0) continue;  // previous column belongs to the left block
           acc += st3[(lc - 1) * 2 * d.nz * NpP + off];
@@ -284,9 +284,14 @@ k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict_
     } else {
       // right line: contributions of column cbb-1 through its right-line nodes
       if (ql >= nl) continue;
-      int cnt = d.acc_cnt[ql];
-      for (int k = 0; k < cnt; ++k) {
-        int e = d.acc_ent[ql * kMaxContrib + k];
+      const int cnt = d.acc_cnt[ql];
+      const int4* e4 = reinterpret_cast<const int4*>(d.acc_ent + (size_t)ql * kMaxContrib);
+      const int4 ea = e4[0], eb = e4[1];
+      const int ent[kMaxContrib] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+#pragma unroll
+      for (int k = 0; k < kMaxContrib; ++k) {
+        if (k >= cnt) break;
+        const int e = ent[k];
         if (((e >> 30) & 1) == 0) continue;
         acc += st3[(cbb - 1) * 2 * d.nz * NpP + (e & 0x3fffffff)];
       }
@@ -316,184 +321,6 @@ __global__ void k_fixup(const TankDev* __restrict__ td, T* __restrict__ y, const
   } else {
     y[(int64_t)d.nx * d.nc + ql] = v;   // the wall line has one contribution
   }
-}
-
-// ------------------------------------------------------------ exact inverses on periodic tanks
-// z = A^{-1} r for a column-coupled operator A (the still-water Laplace
-// operator on the free nodes, or the 2D mass matrix): each column's interior
-// unknowns are condensed onto the vertical lines (Schur complement), the
-// block-circulant line system is solved mode by mode after a DFT along x,
-// and the interiors are recovered.  Three launches:
-//   k_sd_interior  (block per column)  y_I = A_II^{-1} r_I, T_L = A_LI y_I, T_R = A_RI y_I
-//   k_sd_modes     (block per mode k)  g^_k = DFT_c(r_L - T_L - T_R(c-1)), x^_k = S^_k^{-1} g^_k
-//   k_sd_back      (block per column)  x_L at lines c, c+1 by inverse DFT,
-//                                      z_I = y_I - A_II^{-1}(A_IL x_L + A_IR x_R)
-// Matrices are stored so that consecutive threads read consecutive words:
-// A_II^{-1} and S^_k column-major, A_LI and A_RI row-major [line][interior].
-constexpr int kSdWaves = kBlockThreads / 64;
-
-template <typename T>
-__device__ inline void sd_matvec_t(const T* __restrict__ At, int nI, const double* __restrict__ x,
-                                   double* __restrict__ y) {
-  // y[i] = sum_j At[j*nI + i] x[j]   (thread per row, coalesced columns)
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    double acc = 0;
-    for (int j = 0; j < nI; ++j) acc += (double)At[(size_t)j * nI + i] * x[j];
-    y[i] = acc;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sd_interior(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
-  const SDData& sd = d.sd[which];
-  using PR = Prec<T, T>;
-  extern __shared__ double sh[];
-  const int c = blockIdx.x, nI = sd.nI, q = sd.q;
-  double* rI = sh;
-  double* y = sh + nI;
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) rI[i] = (double)r[(int64_t)c * d.nc + sd.I_idx[i]];
-  __syncthreads();
-  sd_matvec_t(PR::AinvII(sd), nI, rI, y);
-  __syncthreads();
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) sd.yI[(size_t)c * nI + i] = y[i];
-  // T_L, T_R: one wavefront per line unknown, lanes over the interior
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int a = wv; a < 2 * q; a += kSdWaves) {
-    const T* A = a < q ? PR::ALI(sd) + (size_t)a * nI : PR::ARI(sd) + (size_t)(a - q) * nI;
-    double acc = 0;
-    for (int i = lane; i < nI; i += 64) acc += (double)A[i] * y[i];
-    acc = wave_sum(acc);
-    if (lane == 0) {
-      if (a < q) sd.TL[(size_t)c * q + a] = acc;
-      else sd.TR[(size_t)c * q + a - q] = acc;
-    }
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
-  const SDData& sd = d.sd[which];
-  using PR = Prec<T, T>;
-  extern __shared__ double gh[];  // [kSdWaves][q][2] partial transforms, then [q][2]
-  const int k = blockIdx.x, q = sd.q, nx = d.nx;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // forward DFT along x: wave w takes columns c = w, w + 4, ...
-  const int step = (int)(((int64_t)kSdWaves * k) % nx);
-  for (int j0 = 0; j0 < q; j0 += 64) {
-    const int j = j0 + lane;
-    double re = 0, im = 0;
-    if (j < q) {
-      int mm = (int)(((int64_t)k * wv) % nx);   // (k c) mod nx
-      for (int c = wv; c < nx; c += kSdWaves) {
-        int cm = c == 0 ? nx - 1 : c - 1;
-        double g = (double)r[(int64_t)c * d.nc + j] - sd.TL[(size_t)c * q + j] - sd.TR[(size_t)cm * q + j];
-        re += g * d.twid[2 * mm];
-        im += g * d.twid[2 * mm + 1];
-        mm += step;
-        if (mm >= nx) mm -= nx;
-      }
-      gh[(wv * q + j) * 2] = re;
-      gh[(wv * q + j) * 2 + 1] = im;
-    }
-  }
-  __syncthreads();
-  double* g = gh + (size_t)kSdWaves * q * 2;
-  for (int j = threadIdx.x; j < q; j += blockDim.x) {
-    double re = 0, im = 0;
-    for (int w = 0; w < kSdWaves; ++w) {
-      re += gh[(w * q + j) * 2];
-      im += gh[(w * q + j) * 2 + 1];
-    }
-    g[2 * j] = re;
-    g[2 * j + 1] = im;
-  }
-  __syncthreads();
-  // x^ = S^_k^{-1} g^ (column-major: thread per row)
-  const T* S = PR::Shat(sd) + (size_t)k * q * q * 2;
-  for (int i = threadIdx.x; i < q; i += blockDim.x) {
-    double xr = 0, xi = 0;
-    for (int j = 0; j < q; ++j) {
-      double sr = S[((size_t)j * q + i) * 2], si = S[((size_t)j * q + i) * 2 + 1];
-      xr += sr * g[2 * j] - si * g[2 * j + 1];
-      xi += sr * g[2 * j + 1] + si * g[2 * j];
-    }
-    sd.XH[((size_t)k * q + i) * 2] = xr;
-    sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
-  const SDData& sd = d.sd[which];
-  using PR = Prec<T, T>;
-  extern __shared__ double sh[];
-  const int c = blockIdx.x, nI = sd.nI, q = sd.q, nx = d.nx;
-  const int cn = c + 1 == nx ? 0 : c + 1;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double* part = sh;                            // [kSdWaves][2][q]
-  double* xl = sh + (size_t)kSdWaves * 2 * q;   // [q]
-  double* xr = xl + q;                          // [q]
-  double* v = xr + q;                           // [nI]
-  // inverse DFT at lines c and c+1: x_L[j] = Re sum_k x^_k[j] e^{+2 pi i k c / nx} / nx
-  const int st0 = (int)(((int64_t)kSdWaves * c) % nx), st1 = (int)(((int64_t)kSdWaves * cn) % nx);
-  for (int j0 = 0; j0 < q; j0 += 64) {
-    const int j = j0 + lane;
-    if (j < q) {
-      double a0 = 0, a1 = 0;
-      int m0 = (int)(((int64_t)c * wv) % nx), m1 = (int)(((int64_t)cn * wv) % nx);
-      for (int k = wv; k < nx; k += kSdWaves) {
-        double hr = sd.XH[((size_t)k * q + j) * 2], hi = sd.XH[((size_t)k * q + j) * 2 + 1];
-        a0 += hr * d.twid[2 * m0] + hi * d.twid[2 * m0 + 1];
-        a1 += hr * d.twid[2 * m1] + hi * d.twid[2 * m1 + 1];
-        m0 += st0;
-        if (m0 >= nx) m0 -= nx;
-        m1 += st1;
-        if (m1 >= nx) m1 -= nx;
-      }
-      part[(wv * 2 + 0) * q + j] = a0;
-      part[(wv * 2 + 1) * q + j] = a1;
-    }
-  }
-  __syncthreads();
-  const double inx = 1.0 / nx;
-  for (int j = threadIdx.x; j < q; j += blockDim.x) {
-    double a0 = 0, a1 = 0;
-    for (int w = 0; w < kSdWaves; ++w) {
-      a0 += part[(w * 2 + 0) * q + j];
-      a1 += part[(w * 2 + 1) * q + j];
-    }
-    xl[j] = a0 * inx;
-    xr[j] = a1 * inx;
-    z[(int64_t)c * d.nc + j] = T(a0 * inx);
-  }
-  if (sd.zero_surface && threadIdx.x == 0) z[(int64_t)c * d.nc + d.nl - 1] = T(0);
-  __syncthreads();
-  const T* ALI = PR::ALI(sd);
-  const T* ARI = PR::ARI(sd);
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    double acc = 0;
-    for (int a = 0; a < q; ++a)
-      acc += (double)ALI[(size_t)a * nI + i] * xl[a] + (double)ARI[(size_t)a * nI + i] * xr[a];
-    v[i] = acc;
-  }
-  __syncthreads();
-  const T* At = PR::AinvII(sd);
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    double acc = 0;
-    for (int j = 0; j < nI; ++j) acc += (double)At[(size_t)j * nI + i] * v[j];
-    z[(int64_t)c * d.nc + sd.I_idx[i]] = T(sd.yI[(size_t)c * nI + i] - acc);
-  }
-  if (sd.zero_surface)
-    for (int k = 1 + threadIdx.x; k < d.P; k += blockDim.x) z[(int64_t)c * d.nc + d.surf_loc[k]] = T(0);
 }
 
 // ------------------------------------------------------------ vector kernels
@@ -612,10 +439,13 @@ k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, const T*
   for (int k = threadIdx.x; k < nvec; k += blockDim.x)
     part[(size_t)blockIdx.x * ldp + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
   if (!last_block(counter)) return;
-  for (int k = threadIdx.x; k < nvec; k += blockDim.x) {
+  // final sums: wave w takes vectors w, w+4, ...; lanes stride over the
+  // workgroup partials in a fixed order, then a butterfly
+  for (int k = wv; k < nvec; k += kBlockThreads / 64) {
     double t = 0;
-    for (int b2 = 0; b2 < (int)gridDim.x; ++b2) t += part[(size_t)b2 * ldp + k];
-    out[k] = t;
+    for (int b2 = lane; b2 < (int)gridDim.x; b2 += 64) t += part[(size_t)b2 * ldp + k];
+    t = wave_sum(t);
+    if (lane == 0) out[k] = t;
   }
   if (threadIdx.x == 0) *counter = 0;
 }
@@ -650,12 +480,15 @@ k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hba
   __syncthreads();
   if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp] = ((red[0] + red[1]) + red[2]) + red[3];
   if (!last_block(counter)) return;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     double t = 0;
-    for (int b2 = 0; b2 < (int)gridDim.x; ++b2) t += part[(size_t)b2 * ldp];
-    givens_update(ks, Hbase, m, j, t, status);
-    *counter = 0;
-    publish_progress(ks, mirror);
+    for (int b2 = threadIdx.x; b2 < (int)gridDim.x; b2 += 64) t += part[(size_t)b2 * ldp];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) {
+      givens_update(ks, Hbase, m, j, t, status);
+      *counter = 0;
+      publish_progress(ks, mirror);
+    }
   }
 }
 
@@ -708,10 +541,12 @@ __global__ void k_scale_next(int64_t n, int j, const T* __restrict__ w, T* __res
                              const double* __restrict__ Hbase, int m, const KrylovState* __restrict__ ks) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (ks->converged) return;
+  // independent loads first, then the test
   const double* g = Hbase + (m + 1) * m + 2 * m;
-  double hn = g[m + 1 + j];
-  if (j + 1 < m + 1) V[(int64_t)(j + 1) * n + i] = (hn > 0.0) ? T((double)w[i] / hn) : T(0);
+  const double hn = g[m + 1 + j];
+  const double wi = (double)w[i];
+  if (ks->converged) return;
+  if (j + 1 < m + 1) V[(int64_t)(j + 1) * n + i] = (hn > 0.0) ? T(wi / hn) : T(0);
 }
 
 // solve the triangular system for y (single thread) then x += Z y (all threads)
@@ -1228,17 +1063,6 @@ void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const do
   SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_coef<PP>, dim3(nblk(total)), dim3(kBlockThreads), 0, st, d, eta, etax, what));
 }
 
-template <typename T>
-static void launch_sd(const TankDev& h, const TankDev* d, int which, const T* u, T* y, int gate, hipStream_t st) {
-  const SDData& sd = h.sd[which];
-  size_t s1 = sizeof(double) * 2 * sd.nI;
-  size_t s2 = sizeof(double) * (kSdWaves + 1) * 2 * sd.q;
-  size_t s3 = sizeof(double) * ((kSdWaves * 2 + 2) * (size_t)sd.q + sd.nI);
-  hipLaunchKernelGGL(k_sd_interior<T>, dim3(h.nx), dim3(kBlockThreads), s1, st, d, which, u, gate);
-  hipLaunchKernelGGL(k_sd_modes<T>, dim3(h.nx), dim3(kBlockThreads), s2, st, d, which, u, gate);
-  hipLaunchKernelGGL(k_sd_back<T>, dim3(h.nx), dim3(kBlockThreads), s3, st, d, which, y, gate);
-}
-
 // element kernel only (no line fix-up)
 template <typename T, typename GS>
 static void gather_kernel(const TankDev& h, const TankDev* d, int op, const T* u, T* y, T* side, int flags,
@@ -1277,7 +1101,7 @@ static void gather_full(const TankDev& h, const TankDev* d, int op, const T* u, 
                         hipStream_t st) {
   if ((op == OP_PRE_LAP || op == OP_PRE_MASS) && h.pre_kind == 1) {
     if (op == OP_PRE_LAP || sizeof(T) == sizeof(double)) {
-      launch_sd<T>(h, d, op == OP_PRE_LAP ? 0 : 1, u, y, (flags & F_GATE) ? 1 : 0, st);
+      launch_sd(h, d, op == OP_PRE_LAP ? 0 : 1, u, y, (flags & F_GATE) ? 1 : 0, st);
       return;
     }
   }
@@ -1302,11 +1126,11 @@ void launch_gather_only(const TankDev& h, const TankDev* d, int op, int prec, co
                         hipStream_t st) {
   if (prec == 0) {
     if ((op == OP_PRE_LAP || op == OP_PRE_MASS) && h.pre_kind == 1)
-      launch_sd<double>(h, d, op == OP_PRE_LAP ? 0 : 1, (const double*)u, (double*)y, 0, st);
+      launch_sd(h, d, op == OP_PRE_LAP ? 0 : 1, (const double*)u, (double*)y, 0, st);
     else if (op == OP_STIFF && h.use_mfma) launch_stiff_mfma(h, d, (const double*)u, (double*)y, (double*)side, 0, st);
     else gather_kernel<double, double>(h, d, op, (const double*)u, (double*)y, (double*)side, 0, st);
   } else {
-    if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd<float>(h, d, 0, (const float*)u, (float*)y, 0, st);
+    if (op == OP_PRE_LAP && h.pre_kind == 1) launch_sd(h, d, 0, (const float*)u, (float*)y, 0, st);
     else if (op == OP_STIFF && h.use_mfma)
       launch_stiff_mfma(h, d, (const float*)u, (float*)y, (float*)side, 0, prec == 2 ? 2 : 1, st);
     else if (prec == 2) gather_kernel<float, BF16>(h, d, op, (const float*)u, (float*)y, (float*)side, 0, st);

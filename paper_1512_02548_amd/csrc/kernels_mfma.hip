@@ -16,28 +16,9 @@
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
+#include "mfma.hpp"
 
 namespace sem {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Mfma;
-// Accumulator row of (v, lane group g) in a 16x16 output tile: the FP64
-// instruction interleaves (row 4v+g), the FP32 one blocks (row 4g+v).
-template <>
-struct Mfma<double> {
-  using V4 = d4;
-  __device__ static constexpr int row(int v, int g) { return 4 * v + g; }
-  __device__ static V4 op(double a, double b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-};
-template <>
-struct Mfma<float> {
-  using V4 = f4;
-  __device__ static constexpr int row(int v, int g) { return 4 * g + v; }
-  __device__ static V4 op(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-};
 
 template <typename T, typename GS>
 __device__ inline T load_g(const TankDev& d, int64_t i);
@@ -84,6 +65,7 @@ k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restr
   const int EBb = cbb * nz2;
   T* ureg = lds;                          // [cb*nc + nl]
   T* st3 = ureg + (d.cb * nc + nl);       // [T*16][NpP]
+#pragma unroll 4
   for (int q = threadIdx.x; q < nreg; q += blockDim.x) {
     int lc = q / nc, ql = q - lc * nc;
     int64_t gi;
@@ -171,13 +153,20 @@ k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restr
     int lc = q / nc, ql = q - lc * nc;
     T a = 0;
     if (lc < cbb) {
-      int cnt = d.acc_cnt[ql];
-      for (int k = 0; k < cnt; ++k) {
-        int e = d.acc_ent[ql * kMaxContrib + k];
-        int prev = (e >> 30) & 1;
-        int off = e & 0x3fffffff;
+      // the node's contributions: count and up to kMaxContrib table entries,
+      // loaded together (two 16-byte loads)
+      const int cnt = d.acc_cnt[ql];
+      const int4* e4 = reinterpret_cast<const int4*>(d.acc_ent + (size_t)ql * kMaxContrib);
+      const int4 ea = e4[0], eb = e4[1];
+      const int ent[kMaxContrib] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+#pragma unroll
+      for (int k = 0; k < kMaxContrib; ++k) {
+        if (k >= cnt) break;
+        const int e = ent[k];
+        const int prev = (e >> 30) & 1;
+        const int off = e & 0x3fffffff;
         if (prev) {
-          if (lc == 0) continue;
+          if (lc == 0) continue;  // previous column belongs to the left block
           a += st3[(lc - 1) * nz2 * NpP + off];
         } else {
           a += st3[lc * nz2 * NpP + off];
@@ -188,9 +177,14 @@ k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restr
       y[(int64_t)(c0 + lc) * nc + ql] = a;
     } else {
       if (ql >= nl) continue;
-      int cnt = d.acc_cnt[ql];
-      for (int k = 0; k < cnt; ++k) {
-        int e = d.acc_ent[ql * kMaxContrib + k];
+      const int cnt = d.acc_cnt[ql];
+      const int4* e4 = reinterpret_cast<const int4*>(d.acc_ent + (size_t)ql * kMaxContrib);
+      const int4 ea = e4[0], eb = e4[1];
+      const int ent[kMaxContrib] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+#pragma unroll
+      for (int k = 0; k < kMaxContrib; ++k) {
+        if (k >= cnt) break;
+        const int e = ent[k];
         if (((e >> 30) & 1) == 0) continue;
         a += st3[(cbb - 1) * nz2 * NpP + (e & 0x3fffffff)];
       }

@@ -1,0 +1,449 @@
+// Exact inverse of a column-coupled operator on a periodic tank, on matrix
+// cores.
+//
+// The operator A (the still-water flat-bed Laplace operator on the free
+// nodes, used as the preconditioner, or the 2D mass matrix) couples the
+// nodes of one element column to its two vertical lines only.  Condensing
+// each column's interior unknowns onto the lines leaves a block-circulant
+// system in x, which a DFT along x splits into one q x q complex system per
+// Fourier mode.  With R_c the interior right side of column c:
+//
+//   condense   [Y; T_L; T_R](:, c) = [A_II^-1; A_LI A_II^-1; A_RI A_II^-1] R_c
+//   modes      g_c = r_L,c - T_L,c - T_R,c-1,   g^_k = sum_c e^{-2 pi i k c/nx} g_c,
+//              x^_k = S^_k^{-1} g^_k
+//   back       x_L,c = Re sum_k e^{+2 pi i k c/nx} x^_k / nx,
+//              z_I,c = Y_c - A_II^-1 [A_IL | A_IR] [x_L,c; x_L,c+1]
+//
+// Every step over many columns (or modes) is a dense product, run as 16x16x4
+// MFMA tiles with 16 columns (or modes) per N (or M) tile; the per-mode
+// solves are small complex matrix-vector products.  Matrices are uploaded in
+// MFMA fragment order ([M-tile][K-step][lane]) so each operand load is 64
+// consecutive words.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "mfma.hpp"
+
+namespace sem {
+
+namespace {
+constexpr int kWaves = kBlockThreads / 64;
+constexpr int kMtw = 2;   // M-tiles per wave in the condensation product
+
+__device__ inline double wsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+struct SdMat;
+template <>
+struct SdMat<double> {
+  __device__ static const double* A1(const SDData& s) { return s.A1; }
+  __device__ static const double* C3(const SDData& s) { return s.C3; }
+  __device__ static const double* Shat(const SDData& s) { return s.Shat; }
+};
+template <>
+struct SdMat<float> {
+  __device__ static const float* A1(const SDData& s) { return s.A1_32; }
+  __device__ static const float* C3(const SDData& s) { return s.C3_32; }
+  __device__ static const float* Shat(const SDData& s) { return s.Shat32; }
+};
+}  // namespace
+
+// condense: grid (column tiles, M-tile groups)
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  const SDData& sd = d.sd[which];
+  extern __shared__ unsigned char lds_raw[];
+  T* Rt = reinterpret_cast<T*>(lds_raw);   // [4 KS][16] interior right sides of 16 columns
+  const int nI = sd.nI, q = sd.q, nx = d.nx, KS = sd.KS1, nMT = sd.nMT1;
+  const int c0 = blockIdx.x * 16;
+#pragma unroll 8
+  for (int t = threadIdx.x; t < 4 * KS * 16; t += blockDim.x) {
+    const int k = t >> 4, c = c0 + (t & 15);
+    Rt[t] = (k < nI && c < nx) ? r[(int64_t)c * d.nc + sd.I_idx[k]] : T(0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const int mt0 = (blockIdx.y * kWaves + wv) * kMtw;
+  if (mt0 >= nMT) return;
+  const T* A = SdMat<T>::A1(sd);
+  V4 acc[kMtw];
+#pragma unroll
+  for (int u = 0; u < kMtw; ++u) acc[u] = V4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int s = 0; s < KS; ++s) {
+    const T b = Rt[(4 * s + grp) * 16 + col];
+#pragma unroll
+    for (int u = 0; u < kMtw; ++u) {
+      const int mt = min(mt0 + u, nMT - 1);   // a clamped tile is computed, never stored
+      acc[u] = MF::op(A[((size_t)mt * KS + s) * 64 + lane], b, acc[u]);
+    }
+  }
+  const int c = c0 + col;
+  if (c >= nx) return;
+#pragma unroll
+  for (int u = 0; u < kMtw; ++u) {
+    const int mt = mt0 + u;
+    if (mt >= nMT) break;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * mt + MF::row(v, grp);
+      const double val = (double)acc[u][v];
+      if (row < nI) sd.yI[(size_t)c * nI + row] = val;
+      else if (row < nI + q) sd.TL[(size_t)c * q + row - nI] = val;
+      else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
+    }
+  }
+}
+
+// modes: one block per 16 Fourier modes; waves split the sum over columns
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  const SDData& sd = d.sd[which];
+  extern __shared__ double sh[];
+  double* part = sh;                      // [kWaves][16][16][2]
+  double* gh = sh + kWaves * 16 * 16 * 2; // [16][q][2]
+  const int q = sd.q, nx = d.nx, nc = d.nc;
+  const int nNT = (q + 15) / 16, KS = (nx + 3) / 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const int k0 = blockIdx.x * 16;
+  const int kmode = k0 + col;              // A row of this lane
+  const bool kval = kmode < nx;
+  const int kr = kval ? kmode : 0;
+  // twiddle index (kmode * c) mod nx for c = 4 s + grp, s = wv, wv + 4, ...
+  const int step = (int)(((int64_t)16 * kr) % nx);
+  for (int nt0 = 0; nt0 < nNT; nt0 += 4) {
+    const int ntn = min(4, nNT - nt0);
+    V4 are[4], aim[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) are[u] = aim[u] = V4{0, 0, 0, 0};
+    int mm = (int)(((int64_t)kr * (4 * wv + grp)) % nx);
+#pragma unroll 4
+    for (int s = wv; s < KS; s += kWaves) {
+      const int c = 4 * s + grp;
+      const bool cv = c < nx;
+      const T fre = (cv && kval) ? T(d.twid[2 * mm]) : T(0);
+      const T fim = (cv && kval) ? T(d.twid[2 * mm + 1]) : T(0);
+      const int cm = c == 0 ? nx - 1 : c - 1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u >= ntn) break;
+        const int j = 16 * (nt0 + u) + col;
+        T gv = T(0);
+        if (cv && j < q) {
+          double rv = (double)r[(int64_t)c * nc + j];
+          if (sd.wall && c == 0) rv += (double)r[(int64_t)nx * nc + j];   // wall line folded onto line 0
+          gv = T(rv - sd.TL[(size_t)c * q + j] - sd.TR[(size_t)cm * q + j]);
+        }
+        are[u] = MF::op(fre, gv, are[u]);
+        aim[u] = MF::op(fim, gv, aim[u]);
+      }
+      mm += step;
+      if (mm >= nx) mm -= nx;
+    }
+    for (int u = 0; u < ntn; ++u) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = MF::row(v, grp);
+        part[((wv * 16 + row) * 16 + col) * 2] = (double)are[u][v];
+        part[((wv * 16 + row) * 16 + col) * 2 + 1] = (double)aim[u][v];
+      }
+      __syncthreads();
+      {
+        const int row = threadIdx.x >> 4, jc = threadIdx.x & 15;
+        const int j = 16 * (nt0 + u) + jc;
+        double sr = 0, si = 0;
+        for (int w = 0; w < kWaves; ++w) {
+          sr += part[((w * 16 + row) * 16 + jc) * 2];
+          si += part[((w * 16 + row) * 16 + jc) * 2 + 1];
+        }
+        if (j < q) {
+          gh[(row * q + j) * 2] = sr;
+          gh[(row * q + j) * 2 + 1] = si;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // x^_k = S^_k^{-1} g^_k (column-major: thread per (mode, row))
+  for (int t = threadIdx.x; t < 16 * q; t += blockDim.x) {
+    const int kk = t / q, i = t - kk * q, k = k0 + kk;
+    if (k >= nx) continue;
+    const T* S = SdMat<T>::Shat(sd) + (size_t)k * q * q * 2;
+    double xr = 0, xi = 0;
+#pragma unroll 8
+    for (int j = 0; j < q; ++j) {
+      const double sr = (double)S[((size_t)j * q + i) * 2], si = (double)S[((size_t)j * q + i) * 2 + 1];
+      const double gr = gh[(kk * q + j) * 2], gi = gh[(kk * q + j) * 2 + 1];
+      xr += sr * gr - si * gi;
+      xi += sr * gi + si * gr;
+    }
+    sd.XH[((size_t)k * q + i) * 2] = xr;
+    sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
+  }
+}
+
+// back: grid (column tiles, M-tile groups of the back-substitution)
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  const SDData& sd = d.sd[which];
+  extern __shared__ double sh[];
+  double* part = sh;                     // [kWaves][16][16]
+  double* xl = sh + kWaves * 16 * 16;    // [17][q] line solutions of columns c0 .. c0+16
+  const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc;
+  const int nNT = (q + 15) / 16, KS = (2 * nx + 3) / 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const int c0 = blockIdx.x * 16;
+  const double inx = 1.0 / nx;
+  // inverse DFT for lines c0 .. c0+15: A[c][kk] = twiddle part (kk & 1) of mode
+  // kk / 2 at line c, B[kk][j] = part (kk & 1) of x^_{kk/2}[j]
+  {
+    // rows past the last column wrap: row nx - c0 is the right neighbour
+    // (line 0) of the last column of a partial tile
+    const int cr = (c0 + col) % nx;
+    const int kfirst = 2 * wv + (grp >> 1), pr = grp & 1;
+    const int step = (int)(((int64_t)8 * cr) % nx);   // mode advances by 8 per pass
+    for (int nt = 0; nt < nNT; ++nt) {
+      V4 acc = V4{0, 0, 0, 0};
+      int mm = (int)(((int64_t)cr * kfirst) % nx);
+#pragma unroll 4
+      for (int s = wv; s < KS; s += kWaves) {
+        const int k = 2 * s + (grp >> 1);
+        const bool kv = k < nx;
+        const T a = kv ? T(d.twid[2 * mm + pr]) : T(0);
+        const int j = 16 * nt + col;
+        const T b = (kv && j < q) ? T(sd.XH[((size_t)k * q + j) * 2 + pr]) : T(0);
+        acc = MF::op(a, b, acc);
+        mm += step;
+        if (mm >= nx) mm -= nx;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) part[(wv * 16 + MF::row(v, grp)) * 16 + col] = (double)acc[v];
+      __syncthreads();
+      {
+        const int row = threadIdx.x >> 4, jc = threadIdx.x & 15, j = 16 * nt + jc;
+        double sacc = 0;
+        for (int w = 0; w < kWaves; ++w) sacc += part[(w * 16 + row) * 16 + jc];
+        if (j < q) xl[row * q + j] = sacc * inx;
+      }
+      __syncthreads();
+    }
+  }
+  // line c0+16 (wraps): lanes over j, waves over modes, fixed-order sums
+  {
+    const int c16 = (c0 + 16) % nx;
+    const int step = (int)(((int64_t)kWaves * c16) % nx);
+    for (int j0 = 0; j0 < q; j0 += 64) {
+      const int j = j0 + lane;
+      double acc = 0;
+      if (j < q) {
+        int mm = (int)(((int64_t)c16 * wv) % nx);
+#pragma unroll 4
+        for (int k = wv; k < nx; k += kWaves) {
+          acc += sd.XH[((size_t)k * q + j) * 2] * d.twid[2 * mm] + sd.XH[((size_t)k * q + j) * 2 + 1] * d.twid[2 * mm + 1];
+          mm += step;
+          if (mm >= nx) mm -= nx;
+        }
+      }
+      part[wv * 64 + lane] = acc;
+      __syncthreads();
+      if (threadIdx.x < 64 && j0 + threadIdx.x < q) {
+        double sacc = 0;
+        for (int w = 0; w < kWaves; ++w) sacc += part[w * 64 + threadIdx.x];
+        xl[16 * q + j0 + threadIdx.x] = sacc * inx;
+      }
+      __syncthreads();
+    }
+  }
+  // line values of the block's columns
+  if (blockIdx.y == 0) {
+    for (int t = threadIdx.x; t < 16 * q; t += blockDim.x) {
+      const int cc = t / q, j = t - cc * q, c = c0 + cc;
+      if (c < nx) z[(int64_t)c * nc + j] = T(xl[cc * q + j]);
+    }
+    if (sd.zero_surface) {
+      for (int t = threadIdx.x; t < 16 * d.P; t += blockDim.x) {
+        const int cc = t / d.P, k = t - cc * d.P, c = c0 + cc;
+        if (c < nx) z[(int64_t)c * nc + (k == 0 ? d.nl - 1 : d.surf_loc[k])] = T(0);
+      }
+    }
+  }
+  // wall line = line 0 + v
+  if (sd.wall && blockIdx.x == 0 && blockIdx.y == 0) {
+    for (int j = threadIdx.x; j < q; j += blockDim.x) z[(int64_t)nx * nc + j] = T(xl[j] + sd.vbuf[j]);
+    if (sd.zero_surface && threadIdx.x == 0) z[(int64_t)nx * nc + d.nl - 1] = T(0);
+  }
+  // z_I = Y - C [x_L,c; x_L,c+1]: one M-tile per wave
+  const int mt = blockIdx.y * kWaves + wv;
+  if (mt >= sd.nMT3) return;
+  const T* C = SdMat<T>::C3(sd);
+  const int KS3 = sd.KS3;
+  V4 acc = V4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int s = 0; s < KS3; ++s) {
+    const int kk = 4 * s + grp;
+    T b = T(0);
+    if (kk < q) b = T(xl[col * q + kk]);
+    else if (kk < 2 * q) b = T(xl[(col + 1) * q + kk - q]);
+    acc = MF::op(C[((size_t)mt * KS3 + s) * 64 + lane], b, acc);
+  }
+  const int c = c0 + col;
+  if (c >= nx) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = 16 * mt + MF::row(v, grp);
+    if (row < nI) z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - (double)acc[v]);
+  }
+}
+
+// Wall correction (one workgroup): the first solve's values on the last
+// column and line 0, the jump v = Sc^-1 (r_wall - B21 y), and the last
+// column's interior update y_I -= Q v.
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  const SDData& sd = d.sd[which];
+  extern __shared__ double sh[];
+  const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc;
+  const int np = 2 * q + nI;
+  double* part = sh;              // [kWaves][2][64]
+  double* yg = part + kWaves * 2 * 64;   // [np]: line nx-1, interior of column nx-1, line 0
+  double* t = yg + np;            // [q]
+  double* v = t + q;              // [q]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int a0 = nx - 1;
+  const double inx = 1.0 / nx;
+  // lines nx-1 and 0 of the first solve from its modes
+  const int step = (int)(((int64_t)kWaves * a0) % nx);
+  for (int j0 = 0; j0 < q; j0 += 64) {
+    const int j = j0 + lane;
+    double s0 = 0, s1 = 0;
+    if (j < q) {
+      int mm = (int)(((int64_t)a0 * wv) % nx);
+#pragma unroll 4
+      for (int k = wv; k < nx; k += kWaves) {
+        const double hr = sd.XH[((size_t)k * q + j) * 2], hi = sd.XH[((size_t)k * q + j) * 2 + 1];
+        s0 += hr * d.twid[2 * mm] + hi * d.twid[2 * mm + 1];
+        s1 += hr;                 // line 0: e^{0} = 1
+        mm += step;
+        if (mm >= nx) mm -= nx;
+      }
+    }
+    part[(wv * 2 + 0) * 64 + lane] = s0;
+    part[(wv * 2 + 1) * 64 + lane] = s1;
+    __syncthreads();
+    if (threadIdx.x < 64 && j0 + threadIdx.x < q) {
+      double x0 = 0, x1 = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        x0 += part[(w * 2 + 0) * 64 + threadIdx.x];
+        x1 += part[(w * 2 + 1) * 64 + threadIdx.x];
+      }
+      yg[j0 + threadIdx.x] = x0 * inx;
+      yg[q + nI + j0 + threadIdx.x] = x1 * inx;
+    }
+    __syncthreads();
+  }
+  // interior of column nx-1: y_I - C [x_{nx-1}; x_0]
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
+    double acc = sd.yI[(size_t)a0 * nI + i];
+#pragma unroll 4
+    for (int p = 0; p < q; ++p) acc -= sd.Crm[(size_t)p * nI + i] * yg[p];
+#pragma unroll 4
+    for (int p = 0; p < q; ++p) acc -= sd.Crm[(size_t)(q + p) * nI + i] * yg[q + nI + p];
+    yg[q + i] = acc;
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < q; a += blockDim.x) {
+    double acc = (double)r[(int64_t)nx * nc + a];
+#pragma unroll 4
+    for (int p = 0; p < np; ++p) acc -= sd.Bt[(size_t)p * q + a] * yg[p];
+    t[a] = acc;
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < q; a += blockDim.x) {
+    double acc = 0;
+#pragma unroll 4
+    for (int b = 0; b < q; ++b) acc += sd.Wv[(size_t)b * q + a] * t[b];
+    v[a] = acc;
+    sd.vbuf[a] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
+    double acc = 0;
+#pragma unroll 4
+    for (int a = 0; a < q; ++a) acc += sd.Qm[(size_t)a * nI + i] * v[a];
+    sd.yI[(size_t)a0 * nI + i] -= acc;
+  }
+}
+
+// x^_k -= H_k v for every mode (thread per mode and line unknown)
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_wall_modes(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  const SDData& sd = d.sd[which];
+  const int q = sd.q;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)d.nx * q) return;
+  const int64_t k = t / q;
+  const int i = (int)(t - k * q);
+  const double* Hk = sd.Hm + (size_t)k * q * q * 2;
+  double xr = 0, xi = 0;
+#pragma unroll 4
+  for (int a = 0; a < q; ++a) {
+    const double va = sd.vbuf[a];
+    xr += Hk[((size_t)a * q + i) * 2] * va;
+    xi += Hk[((size_t)a * q + i) * 2 + 1] * va;
+  }
+  sd.XH[((size_t)k * q + i) * 2] -= xr;
+  sd.XH[((size_t)k * q + i) * 2 + 1] -= xi;
+}
+
+template <typename T>
+static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y, int gate, hipStream_t st) {
+  const SDData& sd = h.sd[which];
+  const unsigned ct = (unsigned)((h.nx + 15) / 16);
+  const size_t l1 = sizeof(T) * 4 * (size_t)sd.KS1 * 16;
+  const size_t l2 = sizeof(double) * (kWaves * 16 * 16 * 2 + 16 * (size_t)sd.q * 2);
+  const size_t l3 = sizeof(double) * (kWaves * 16 * 16 + 17 * (size_t)sd.q);
+  const unsigned g1 = (unsigned)((sd.nMT1 + kWaves * kMtw - 1) / (kWaves * kMtw));
+  const unsigned g3 = (unsigned)((sd.nMT3 + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(k_sd_cond<T>, dim3(ct, g1), dim3(kBlockThreads), l1, st, d, which, u, gate);
+  hipLaunchKernelGGL(k_sd_modes<T>, dim3(ct), dim3(kBlockThreads), l2, st, d, which, u, gate);
+  if (sd.wall) {
+    const size_t lw = sizeof(double) * (kWaves * 2 * 64 + 2 * (size_t)sd.q + sd.nI + 2 * (size_t)sd.q);
+    hipLaunchKernelGGL(k_sd_wall<T>, dim3(1), dim3(kBlockThreads), lw, st, d, which, u, gate);
+    const int64_t nm = (int64_t)h.nx * sd.q;
+    hipLaunchKernelGGL(k_sd_wall_modes, dim3((unsigned)((nm + kBlockThreads - 1) / kBlockThreads)),
+                       dim3(kBlockThreads), 0, st, d, which, gate);
+  }
+  hipLaunchKernelGGL(k_sd_back<T>, dim3(ct, g3), dim3(kBlockThreads), l3, st, d, which, y, gate);
+}
+
+void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st) {
+  sd_t<double>(h, d, which, u, y, gate, st);
+}
+void launch_sd(const TankDev& h, const TankDev* d, int which, const float* u, float* y, int gate, hipStream_t st) {
+  sd_t<float>(h, d, which, u, y, gate, st);
+}
+
+}  // namespace sem

@@ -26,6 +26,8 @@ void launch_stiff_mfma(const TankDev& h, const TankDev* d, const double* u, doub
 void launch_stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
                        int gstore, hipStream_t st);
 void launch_mfma_probe(double* out64, float* out32, hipStream_t st);
+void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st);
+void launch_sd(const TankDev& h, const TankDev* d, int which, const float* u, float* y, int gate, hipStream_t st);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
 void launch_fill(int64_t n, double v, double* y, hipStream_t st);
 void launch_fill_f(int64_t n, float* y, hipStream_t st);

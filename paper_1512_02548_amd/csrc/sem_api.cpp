@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <complex>
 #include <cmath>
@@ -52,6 +53,8 @@ struct sem_mesh {
   int Np = 0, NpP = 0, nl = 0, nc = 0, cb = 1, nb = 1, T = 1, EB = 0, nclass_col = 1;
   int pre_kind = 0, variant = 0;
   int sd_nI[2] = {0, 0}, sd_q[2] = {0, 0};
+  int sd_M1[2] = {0, 0}, sd_nMT1[2] = {0, 0}, sd_KS1[2] = {0, 0}, sd_nMT3[2] = {0, 0}, sd_KS3[2] = {0, 0};
+  int sd_wall[2] = {0, 0};
   int circ1d = 0;
   int64_t n = 0, ns = 0, E = 0;
   // host tables
@@ -112,6 +115,21 @@ static std::vector<float> tof(const std::vector<double>& v) {
   std::vector<float> o(v.size());
   for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
   return o;
+}
+
+// Runs f(0 .. n-1) on the host's hardware threads.
+template <class F>
+static void parallel_for(int n, F&& f) {
+  int nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+  nt = std::min(nt, std::max(1, n));
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int i = next++; i < n; i = next++) f(i);
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
 }
 
 // Build column template, tables, preconditioner blocks and the workspace layout.
@@ -382,12 +400,27 @@ static sem_status build_mesh(sem_mesh* M) {
   // vertical lines, line system diagonalised by a DFT in x.  [0] still-water
   // Laplace operator on the free nodes (preconditioner), [1] 2D mass matrix.
   struct SDHost {
-    int nI = 0, q = 0;
+    int nI = 0, q = 0, M1 = 0, nMT1 = 0, KS1 = 0, nMT3 = 0, KS3 = 0, wall = 0;
     std::vector<int32_t> I_idx;
-    std::vector<double> AinvII, ALI, ARI, Shat;
+    std::vector<double> A1, C3, Shat;   // fragment-ordered factors, per-mode inverses
+    std::vector<double> Wv, Hm, Qm, Bt, Crm;   // wall-line correction (tanks with walls)
   } sdh[2];
+  // MFMA fragment order of a rows x cols row-major matrix: [M-tile][K-step][lane]
+  auto fragments = [](const Mat& A, int rows, int cols, int* nmt, int* ks) {
+    *nmt = (rows + 15) / 16;
+    *ks = (cols + 3) / 4;
+    std::vector<double> f((size_t)*nmt * *ks * 64, 0.0);
+    for (int mt = 0; mt < *nmt; ++mt)
+      for (int st = 0; st < *ks; ++st)
+        for (int l = 0; l < 64; ++l) {
+          int r = 16 * mt + l % 16, c = 4 * st + l / 16;
+          if (r < rows && c < cols) f[((size_t)mt * *ks + st) * 64 + l] = A[(size_t)r * cols + c];
+        }
+    return f;
+  };
   std::vector<double> twid;
-  M->pre_kind = M->periodic ? 1 : 0;
+  // exact inverses need the interior right sides of 16 columns in LDS (64 KiB)
+  M->pre_kind = ((M->periodic || nx >= 2) && (size_t)((nc - nl + 3) / 4) * 4 * 16 * sizeof(double) <= 65536) ? 1 : 0;
   if (M->pre_kind == 1) {
     const int nloc = nc + nl;
     for (int which = 0; which < 2; ++which) {
@@ -413,46 +446,61 @@ static sem_status build_mesh(sem_mesh* M) {
         Gam[a] = a;
         Gam[q + a] = nc + a;
       }
-      H.AinvII.assign((size_t)nI * nI, 0.0);
+      Mat Ainv((size_t)nI * nI, 0.0);
       for (int i = 0; i < nI; ++i)
-        for (int j = 0; j < nI; ++j) H.AinvII[(size_t)i * nI + j] = A0c[(size_t)H.I_idx[i] * nloc + H.I_idx[j]];
-      if (!invert(H.AinvII, nI)) return fail(SEM_E_INVAL, "singular column interior block");
-      H.ALI.assign((size_t)q * nI, 0.0);
-      H.ARI.assign((size_t)q * nI, 0.0);
-      for (int a = 0; a < q; ++a)
-        for (int i = 0; i < nI; ++i) {
-          H.ALI[(size_t)a * nI + i] = A0c[(size_t)Gam[a] * nloc + H.I_idx[i]];
-          H.ARI[(size_t)a * nI + i] = A0c[(size_t)Gam[q + a] * nloc + H.I_idx[i]];
-        }
-      // Schur complement of the column on its two lines: S = A_GG - A_GI AinvII A_IG
-      Mat AGI((size_t)2 * q * nI);
+        for (int j = 0; j < nI; ++j) Ainv[(size_t)i * nI + j] = A0c[(size_t)H.I_idx[i] * nloc + H.I_idx[j]];
+      if (!invert(Ainv, nI)) return fail(SEM_E_INVAL, "singular column interior block");
+      // line-interior couplings A_GI (2q x nI, lines left then right) and A_IG (nI x 2q)
+      Mat AGI((size_t)2 * q * nI), AIG((size_t)nI * 2 * q);
       for (int a = 0; a < 2 * q; ++a)
-        for (int i = 0; i < nI; ++i) AGI[(size_t)a * nI + i] = A0c[(size_t)Gam[a] * nloc + H.I_idx[i]];
-      Mat W = matmul(H.AinvII, transpose(AGI, 2 * q, nI), nI, nI, 2 * q);   // nI x 2q
+        for (int i = 0; i < nI; ++i) {
+          AGI[(size_t)a * nI + i] = A0c[(size_t)Gam[a] * nloc + H.I_idx[i]];
+          AIG[(size_t)i * 2 * q + a] = A0c[(size_t)H.I_idx[i] * nloc + Gam[a]];
+        }
+      // condensation factor [A_II^-1; A_GI A_II^-1] and back-substitution factor A_II^-1 A_IG
+      {
+        Mat GA = matmul(AGI, Ainv, 2 * q, nI, nI);
+        Mat A1((size_t)(nI + 2 * q) * nI);
+        std::copy(Ainv.begin(), Ainv.end(), A1.begin());
+        std::copy(GA.begin(), GA.end(), A1.begin() + (size_t)nI * nI);
+        H.M1 = nI + 2 * q;
+        H.A1 = fragments(A1, H.M1, nI, &H.nMT1, &H.KS1);
+        Mat C = matmul(Ainv, AIG, nI, nI, 2 * q);
+        H.C3 = fragments(C, nI, 2 * q, &H.nMT3, &H.KS3);
+      }
+      // Schur complement of the column on its two lines: S = A_GG - A_GI A_II^-1 A_IG
+      Mat W = matmul(Ainv, AIG, nI, nI, 2 * q);   // nI x 2q
       Mat SW = matmul(AGI, W, 2 * q, nI, 2 * q);
       Mat S((size_t)4 * q * q);
       for (int a = 0; a < 2 * q; ++a)
         for (int b = 0; b < 2 * q; ++b)
           S[(size_t)a * 2 * q + b] = A0c[(size_t)Gam[a] * nloc + Gam[b]] - SW[(size_t)a * 2 * q + b];
       auto Sblk = [&](int A, int B, int a, int b) { return S[(size_t)(A * q + a) * 2 * q + B * q + b]; };
-      // per-mode symbol S_LL + S_RR + S_LR e^{i k} + S_RL e^{-i k}, inverted
-      using cd = std::complex<double>;
-      H.Shat.assign((size_t)nx * q * q * 2, 0.0);
+      // per-mode symbol S_LL + S_RR + S_LR e^{i k} + S_RL e^{-i k}, inverted;
       // the symbol of mode nx-k is the conjugate of mode k's (S is real)
-      for (int k = 0; k <= nx / 2; ++k) {
+      using cd = std::complex<double>;
+      const int nk = nx / 2 + 1;
+      std::vector<cd> Sinv((size_t)nk * q * q);
+      std::atomic<bool> singular{false};
+      parallel_for(nk, [&](int k) {
         double kap = 2.0 * M_PI * k / nx;
         cd ep(std::cos(kap), std::sin(kap)), em = std::conj(ep);
-        std::vector<cd> Ak((size_t)q * q), Ik((size_t)q * q, 0.0);
+        std::vector<cd> Ak((size_t)q * q);
+        cd* Ik = Sinv.data() + (size_t)k * q * q;
         for (int a = 0; a < q; ++a)
-          for (int b = 0; b < q; ++b)
+          for (int b = 0; b < q; ++b) {
             Ak[(size_t)a * q + b] = Sblk(0, 0, a, b) + Sblk(1, 1, a, b) + Sblk(0, 1, a, b) * ep + Sblk(1, 0, a, b) * em;
-        for (int a = 0; a < q; ++a) Ik[(size_t)a * q + a] = 1.0;
+            Ik[(size_t)a * q + b] = a == b ? 1.0 : 0.0;
+          }
         // complex Gauss-Jordan with partial pivoting
         for (int cc = 0; cc < q; ++cc) {
           int piv = cc;
           for (int rr = cc + 1; rr < q; ++rr)
             if (std::abs(Ak[(size_t)rr * q + cc]) > std::abs(Ak[(size_t)piv * q + cc])) piv = rr;
-          if (std::abs(Ak[(size_t)piv * q + cc]) == 0.0) return fail(SEM_E_INVAL, "singular line symbol");
+          if (std::abs(Ak[(size_t)piv * q + cc]) == 0.0) {
+            singular = true;
+            return;
+          }
           if (piv != cc)
             for (int j = 0; j < q; ++j) {
               std::swap(Ak[(size_t)cc * q + j], Ak[(size_t)piv * q + j]);
@@ -473,14 +521,150 @@ static sem_status build_mesh(sem_mesh* M) {
             }
           }
         }
-        for (int a = 0; a < q * q; ++a) {
-          H.Shat[((size_t)k * q * q + a) * 2] = Ik[a].real();
-          H.Shat[((size_t)k * q * q + a) * 2 + 1] = Ik[a].imag();
-          if (k > 0 && nx - k != k) {
-            H.Shat[((size_t)(nx - k) * q * q + a) * 2] = Ik[a].real();
-            H.Shat[((size_t)(nx - k) * q * q + a) * 2 + 1] = -Ik[a].imag();
+      });
+      if (singular) return fail(SEM_E_INVAL, "singular line symbol");
+      auto sinv = [&](int k, int a, int b) -> cd {
+        if (k < nk) return Sinv[((size_t)k * q + a) * q + b];
+        return std::conj(Sinv[((size_t)(nx - k) * q + a) * q + b]);
+      };
+      H.Shat.assign((size_t)nx * q * q * 2, 0.0);
+      for (int k = 0; k < nx; ++k)
+        for (int a = 0; a < q; ++a)
+          for (int b = 0; b < q; ++b) {
+            cd v = sinv(k, a, b);
+            H.Shat[(((size_t)k * q + a) * q + b) * 2] = v.real();
+            H.Shat[(((size_t)k * q + a) * q + b) * 2 + 1] = v.imag();
+          }
+      if (!M->periodic) {
+        // Walls: the walled operator A_w is the periodic one A_p (line nx
+        // identified with line 0) plus the jump v between lines nx and 0.
+        // In the basis u = E u_p + F v (E copies line 0 onto line nx, F puts
+        // v on line nx):  [A_p B12; B21 C] [u_p; v] = [E^T r; F^T r], solved
+        // through the Schur complement Sc = C - B21 A_p^-1 B12 (q x q).  B12,
+        // B21 and C are blocks of the last column's matrix (its right line is
+        // line nx); A_p^-1 restricted to that column and line 0 follows from
+        // the line Green's function G(d) = (1/nx) sum_k e^{i th_k d} S^_k^-1.
+        H.wall = 1;
+        auto A0 = [&](int r, int c) { return A0c[(size_t)r * nloc + c]; };
+        Mat G0((size_t)q * q, 0.0), Gp((size_t)q * q, 0.0), Gm((size_t)q * q, 0.0);
+        for (int k = 0; k < nx; ++k) {
+          double th = 2.0 * M_PI * k / nx;
+          cd e1(std::cos(th), std::sin(th));
+          for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b) {
+              cd v = sinv(k, a, b);
+              G0[(size_t)a * q + b] += v.real();
+              Gp[(size_t)a * q + b] += (e1 * v).real();
+              Gm[(size_t)a * q + b] += (std::conj(e1) * v).real();
+            }
+        }
+        for (size_t t = 0; t < G0.size(); ++t) {
+          G0[t] /= nx;
+          Gp[t] /= nx;
+          Gm[t] /= nx;
+        }
+        Mat B12L((size_t)q * q), B12R((size_t)q * q), B12I((size_t)nI * q);
+        Mat B21L((size_t)q * q), B21R((size_t)q * q), B21I((size_t)q * nI);
+        for (int a = 0; a < q; ++a)
+          for (int j = 0; j < q; ++j) {
+            B12L[(size_t)a * q + j] = A0(Gam[a], Gam[q + j]);
+            B12R[(size_t)a * q + j] = A0(Gam[q + a], Gam[q + j]);
+            B21L[(size_t)j * q + a] = A0(Gam[q + j], Gam[a]);
+            B21R[(size_t)j * q + a] = A0(Gam[q + j], Gam[q + a]);
+          }
+        for (int i = 0; i < nI; ++i)
+          for (int j = 0; j < q; ++j) {
+            B12I[(size_t)i * q + j] = A0(H.I_idx[i], Gam[q + j]);
+            B21I[(size_t)j * nI + i] = A0(Gam[q + j], H.I_idx[i]);
+          }
+        auto mv = [](const Mat& A, const std::vector<double>& x, int rows, int cols) {
+          std::vector<double> y(rows, 0.0);
+          for (int r = 0; r < rows; ++r) {
+            double t = 0;
+            for (int c = 0; c < cols; ++c) t += A[(size_t)r * cols + c] * x[c];
+            y[r] = t;
+          }
+          return y;
+        };
+        Mat ALI((size_t)q * nI), ARI((size_t)q * nI), AIL((size_t)nI * q), AIR((size_t)nI * q);
+        for (int a = 0; a < q; ++a)
+          for (int i = 0; i < nI; ++i) {
+            ALI[(size_t)a * nI + i] = AGI[(size_t)a * nI + i];
+            ARI[(size_t)a * nI + i] = AGI[(size_t)(q + a) * nI + i];
+            AIL[(size_t)i * q + a] = AIG[(size_t)i * 2 * q + a];
+            AIR[(size_t)i * q + a] = AIG[(size_t)i * 2 * q + q + a];
+          }
+        Mat Sc = B12R;   // C = the right line's own block
+        for (int j = 0; j < q; ++j) {
+          std::vector<double> rL(q), rI(nI), rR(q);
+          for (int a = 0; a < q; ++a) {
+            rL[a] = B12L[(size_t)a * q + j];
+            rR[a] = B12R[(size_t)a * q + j];
+          }
+          for (int i = 0; i < nI; ++i) rI[i] = B12I[(size_t)i * q + j];
+          std::vector<double> y = mv(Ainv, rI, nI, nI);
+          std::vector<double> gL = mv(ALI, y, q, nI), gR = mv(ARI, y, q, nI);
+          for (int a = 0; a < q; ++a) {
+            gL[a] = rL[a] - gL[a];
+            gR[a] = rR[a] - gR[a];
+          }
+          std::vector<double> xL = mv(G0, gL, q, q), t1 = mv(Gm, gR, q, q);
+          std::vector<double> xR = mv(Gp, gL, q, q), t2 = mv(G0, gR, q, q);
+          for (int a = 0; a < q; ++a) {
+            xL[a] += t1[a];
+            xR[a] += t2[a];
+          }
+          std::vector<double> u1 = mv(AIL, xL, nI, q), u2 = mv(AIR, xR, nI, q);
+          for (int i = 0; i < nI; ++i) u1[i] += u2[i];
+          std::vector<double> u3 = mv(Ainv, u1, nI, nI);
+          std::vector<double> xI(nI);
+          for (int i = 0; i < nI; ++i) xI[i] = y[i] - u3[i];
+          std::vector<double> c1 = mv(B21L, xL, q, q), c2 = mv(B21I, xI, q, nI), c3 = mv(B21R, xR, q, q);
+          for (int a = 0; a < q; ++a) Sc[(size_t)a * q + j] -= c1[a] + c2[a] + c3[a];
+        }
+        if (!invert(Sc, q)) return fail(SEM_E_INVAL, "singular wall Schur complement");
+        Mat Q = matmul(Ainv, B12I, nI, nI, q);                // nI x q
+        Mat PhiL = B12L, PhiR = B12R;
+        {
+          Mat LQ = matmul(ALI, Q, q, nI, q), RQ = matmul(ARI, Q, q, nI, q);
+          for (size_t t = 0; t < PhiL.size(); ++t) {
+            PhiL[t] -= LQ[t];
+            PhiR[t] -= RQ[t];
           }
         }
+        // uploads, column-major so that threads over the output rows read consecutive words
+        H.Wv.assign((size_t)q * q, 0.0);
+        for (int a = 0; a < q; ++a)
+          for (int b = 0; b < q; ++b) H.Wv[(size_t)b * q + a] = Sc[(size_t)a * q + b];
+        H.Qm.assign((size_t)q * nI, 0.0);
+        for (int i = 0; i < nI; ++i)
+          for (int a = 0; a < q; ++a) H.Qm[(size_t)a * nI + i] = Q[(size_t)i * q + a];
+        const int np = 2 * q + nI;
+        H.Bt.assign((size_t)np * q, 0.0);
+        for (int a = 0; a < q; ++a) {
+          for (int b = 0; b < q; ++b) {
+            H.Bt[(size_t)b * q + a] = B21L[(size_t)a * q + b];
+            H.Bt[(size_t)(q + nI + b) * q + a] = B21R[(size_t)a * q + b];
+          }
+          for (int i = 0; i < nI; ++i) H.Bt[(size_t)(q + i) * q + a] = B21I[(size_t)a * nI + i];
+        }
+        H.Crm.assign((size_t)2 * q * nI, 0.0);
+        for (int i = 0; i < nI; ++i)
+          for (int pp = 0; pp < 2 * q; ++pp) H.Crm[(size_t)pp * nI + i] = W[(size_t)i * 2 * q + pp];
+        // H_k = S^_k^-1 (e^{i th_k} Phi_L + Phi_R), column-major per mode
+        H.Hm.assign((size_t)nx * q * q * 2, 0.0);
+        parallel_for(nx, [&](int k) {
+          double th = 2.0 * M_PI * k / nx;
+          cd e1(std::cos(th), std::sin(th));
+          for (int i = 0; i < q; ++i)
+            for (int a = 0; a < q; ++a) {
+              cd t = 0;
+              for (int b = 0; b < q; ++b)
+                t += sinv(k, i, b) * (e1 * PhiL[(size_t)b * q + a] + PhiR[(size_t)b * q + a]);
+              H.Hm[(((size_t)k * q + a) * q + i) * 2] = t.real();
+              H.Hm[(((size_t)k * q + a) * q + i) * 2 + 1] = t.imag();
+            }
+        });
       }
     }
     twid.resize((size_t)2 * nx);
@@ -492,6 +676,12 @@ static sem_status build_mesh(sem_mesh* M) {
   for (int w = 0; w < 2; ++w) {
     M->sd_nI[w] = sdh[w].nI;
     M->sd_q[w] = sdh[w].q;
+    M->sd_M1[w] = sdh[w].M1;
+    M->sd_nMT1[w] = sdh[w].nMT1;
+    M->sd_KS1[w] = sdh[w].KS1;
+    M->sd_nMT3[w] = sdh[w].nMT3;
+    M->sd_KS3[w] = sdh[w].KS3;
+    M->sd_wall[w] = sdh[w].wall;
   }
   // ---- 1D operators
   const int P1 = P + 1;
@@ -643,8 +833,7 @@ static sem_status build_mesh(sem_mesh* M) {
     std::string p = w == 0 ? "sd0_" : "sd1_";
     SDHost& H = sdh[w];
     put(M, (p + "I_idx").c_str(), H.I_idx);
-    // A_II^{-1} and the per-mode inverses are uploaded column-major
-    H.AinvII = transpose(H.AinvII, H.nI, H.nI);
+    // the per-mode inverses are uploaded column-major
     {
       std::vector<double> St(H.Shat.size());
       const size_t qq = (size_t)H.q * H.q;
@@ -655,14 +844,18 @@ static sem_status build_mesh(sem_mesh* M) {
               St[((k * qq) + (size_t)b * H.q + a) * 2 + ri] = H.Shat[((k * qq) + (size_t)a * H.q + b) * 2 + ri];
       H.Shat.swap(St);
     }
-    put(M, (p + "AinvII").c_str(), H.AinvII);
-    put(M, (p + "ALI").c_str(), H.ALI);
-    put(M, (p + "ARI").c_str(), H.ARI);
+    put(M, (p + "A1").c_str(), H.A1);
+    put(M, (p + "C3").c_str(), H.C3);
     put(M, (p + "Shat").c_str(), H.Shat);
-    put(M, (p + "AinvII32").c_str(), tof(H.AinvII));
-    put(M, (p + "ALI32").c_str(), tof(H.ALI));
-    put(M, (p + "ARI32").c_str(), tof(H.ARI));
+    put(M, (p + "A1_32").c_str(), tof(H.A1));
+    put(M, (p + "C3_32").c_str(), tof(H.C3));
     put(M, (p + "Shat32").c_str(), tof(H.Shat));
+    put(M, (p + "Wv").c_str(), H.Wv);
+    put(M, (p + "Hm").c_str(), H.Hm);
+    put(M, (p + "Qm").c_str(), H.Qm);
+    put(M, (p + "Bt").c_str(), H.Bt);
+    put(M, (p + "Crm").c_str(), H.Crm);
+    reserve(M, (p + "vbuf").c_str(), (size_t)std::max(1, H.q) * sizeof(double));
     reserve(M, (p + "yI").c_str(), (size_t)nx * std::max(1, H.nI) * sizeof(double));
     reserve(M, (p + "TL").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
     reserve(M, (p + "TR").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
@@ -853,18 +1046,28 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     sd.q = M->sd_q[w];
     sd.zero_surface = w == 0 ? 1 : 0;
     sd.I_idx = at<int32_t>(M, (p + "I_idx").c_str());
-    sd.AinvII = at<double>(M, (p + "AinvII").c_str());
-    sd.ALI = at<double>(M, (p + "ALI").c_str());
-    sd.ARI = at<double>(M, (p + "ARI").c_str());
+    sd.M1 = M->sd_M1[w];
+    sd.nMT1 = M->sd_nMT1[w];
+    sd.KS1 = M->sd_KS1[w];
+    sd.nMT3 = M->sd_nMT3[w];
+    sd.KS3 = M->sd_KS3[w];
+    sd.A1 = at<double>(M, (p + "A1").c_str());
+    sd.C3 = at<double>(M, (p + "C3").c_str());
     sd.Shat = at<double>(M, (p + "Shat").c_str());
-    sd.AinvII32 = at<float>(M, (p + "AinvII32").c_str());
-    sd.ALI32 = at<float>(M, (p + "ALI32").c_str());
-    sd.ARI32 = at<float>(M, (p + "ARI32").c_str());
+    sd.A1_32 = at<float>(M, (p + "A1_32").c_str());
+    sd.C3_32 = at<float>(M, (p + "C3_32").c_str());
     sd.Shat32 = at<float>(M, (p + "Shat32").c_str());
     sd.yI = at<double>(M, (p + "yI").c_str());
     sd.TL = at<double>(M, (p + "TL").c_str());
     sd.TR = at<double>(M, (p + "TR").c_str());
     sd.XH = at<double>(M, (p + "XH").c_str());
+    sd.wall = M->sd_wall[w];
+    sd.Wv = at<double>(M, (p + "Wv").c_str());
+    sd.Hm = at<double>(M, (p + "Hm").c_str());
+    sd.Qm = at<double>(M, (p + "Qm").c_str());
+    sd.Bt = at<double>(M, (p + "Bt").c_str());
+    sd.Crm = at<double>(M, (p + "Crm").c_str());
+    sd.vbuf = at<double>(M, (p + "vbuf").c_str());
   }
   h.M1 = at<double>(M, "M1");
   h.S1 = at<double>(M, "S1");
@@ -908,7 +1111,8 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
                         h.pre_mass, h.pre_lap32, h.M1, h.S1, h.Ifine, h.Mfine, h.Filt, h.pre1d, h.h, h.hx, h.G,
                         h.G32, h.G16, h.invd, h.status, h.ks, h.H, h.part, h.V, h.Zb, h.w, h.b, h.tmp, h.xs,
                         h.wmass, h.side, h.s1d, h.V32, h.Z32, h.w32, h.x32, h.b32, h.twid, h.Brow, h.Rrow,
-                        h.sd[0].yI, h.sd[1].yI, M->rk, M->scal};
+                        h.sd[0].yI, h.sd[1].yI, h.sd[0].A1, h.sd[1].A1, h.sd[0].C3, h.sd[1].C3, h.sd[0].XH,
+                        h.sd[1].XH, M->rk, M->scal};
   for (size_t i = 0; i < sizeof(need) / sizeof(need[0]); ++i)
     if (!need[i]) return fail(SEM_E_INVAL, "internal: workspace layout incomplete (" + std::to_string(i) + ")");
   for (const Upload& u : M->uploads)

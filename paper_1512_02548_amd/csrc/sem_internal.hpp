@@ -35,23 +35,35 @@ struct KrylovState {
 
 // Exact inverse of a column-coupled operator on a periodic tank: the interior
 // nodes of every column are condensed onto the vertical lines, the resulting
-// block-circulant line system is diagonalised by a DFT along x.
+// block-circulant line system is diagonalised by a DFT along x.  Dense
+// factors are stored in MFMA fragment order: element (M-tile mt, K-step s,
+// lane l) is A[16 mt + l%16][4 s + l/16], zero padded.
 struct SDData {
   int32_t nI, q;                  // interior unknowns per column, unknowns per line
-  int32_t zero_surface, pad;      // 1: surface nodes are Dirichlet (set to 0)
+  int32_t zero_surface;           // 1: surface nodes are Dirichlet (set to 0)
+  int32_t M1;                     // nI + 2q rows of the condensation factor
+  int32_t nMT1, KS1;              // its M-tiles and K-steps
+  int32_t nMT3, KS3;              // of the back-substitution factor
   const int32_t* I_idx;           // [nI] column-local indices of the interior unknowns
-  const double* AinvII;           // [nI][nI] column-major
-  const double* ALI;              // [q][nI] coupling of the left line to the interior
-  const double* ARI;              // [q][nI] coupling of the right line to the interior
+  const double* A1;               // fragments of [A_II^-1; A_LI A_II^-1; A_RI A_II^-1]  (M1 x nI)
+  const double* C3;               // fragments of A_II^-1 [A_IL | A_IR]                    (nI x 2q)
   const double* Shat;             // [nx][q][q][2] inverse line symbol per Fourier mode, column-major
-  const float* AinvII32;
-  const float* ALI32;
-  const float* ARI32;
+  const float* A1_32;
+  const float* C3_32;
   const float* Shat32;
   double* yI;                     // [nx][nI] interior solves
   double* TL;                     // [nx][q]
   double* TR;                     // [nx][q]
   double* XH;                     // [nx][q][2] modal line solution
+  // tanks with walls: correction for the jump v between the wall line nx and
+  // line 0 of the periodic solve (Schur complement on the wall line)
+  int32_t wall, pad2;
+  const double* Wv;               // [q][q] inverse Schur complement, column-major
+  const double* Hm;               // [nx][q][q][2] modal response to v, column-major per mode
+  const double* Qm;               // [q][nI] interior response of the last column, column-major
+  const double* Bt;               // [2q + nI][q] wall-line row of the last column, column-major
+  const double* Crm;              // [2q][nI] back-substitution factor, column-major
+  double* vbuf;                   // [q] v
 };
 
 // Everything a kernel needs about one tank; lives in device memory at the
