@@ -25,14 +25,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stiff_mfma_stream_series_64x4_P6.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1512_02548_amd", "csrc", "kernels_mfma.hip")
 
 
-def stiffness_bytes_per_elem(P, word=8):
+def measured_traffic():
+    """HBM bytes per launch of the stiffness kernel from the committed PMC
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading),
+    or None when the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if kv.get("source_sha256") != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def stiffness_bytes_per_elem(P, word=8, gword=None):
     """Algorithmic HBM bytes of one matrix-free stiffness application per
-    element: the geometric-factor stream (3 values per node) plus reading and
-    writing each degree of freedom once (P^2/2 owned nodes per element)."""
+    element: the geometric-factor stream (3 values per node, gword bytes
+    each) plus reading and writing each degree of freedom once (P^2/2 owned
+    nodes per element, word bytes each)."""
     Np = (P + 1) * (P + 2) // 2
-    return 3 * Np * word + 2 * (P * P / 2.0) * word
+    gword = word if gword is None else gword
+    return 3 * Np * gword + 2 * (P * P / 2.0) * word
 
 
 def stiffness_flops_per_elem(P):
@@ -69,6 +92,60 @@ def cpu_baseline(spec, budget_s=15.0):
                        f"{nfree} free DOF each, {el:.1f} s, BLAS limited to 1 thread")
 
 
+def large_tank(lib, wl, torch, reps=3):
+    """The 2048x8, P=6 walled tank over a trapezoidal bar with irregular
+    waves: one Laplace solve of its initial state to rtol 1e-10 in FP64 and
+    with FP32 / bfloat16-factor inner solves inside FP64 refinement, plus the
+    stiffness apply at this size (HBM-sized factors)."""
+    spec = wl.bar_irregular_spec()
+    ns = spec.ns
+    probe = lib.mesh_from_spec(spec, np.ones(ns), np.zeros(ns), bind=False)
+    eta0, phi0, h, hx = wl.bar_irregular_state(probe.surface_x(), spec)
+    m = lib.mesh_from_spec(spec, h, hx)
+    dev = torch.device("cuda:0")
+    eta = torch.tensor(eta0, device=dev)
+    phis = torch.tensor(phi0, device=dev)
+    etax = torch.zeros_like(eta)
+    m.gradient_recover(lib.SEM_RECOVER_DX, eta, None, etax)
+    out = {"workload": spec.name, "n_free": int(m.info.n_free), "elements": int(m.info.n_elem), "rtol": 1e-10}
+    ref = None
+    for name, prec in (("fp64", lib.SEM_PREC_FP64), ("fp32_ir", lib.SEM_PREC_FP32_IR),
+                       ("bf16_ir", lib.SEM_PREC_BF16_IR)):
+        o = lib.default_opts(rtol=1e-10, max_iter=20000, prec=prec, inner_rtol=1e-2)
+        phi = torch.zeros(m.n, dtype=torch.float64, device=dev)
+        best, st = None, None
+        for _ in range(reps):
+            phi.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = m.laplace_solve(eta, etax, phis, phi, o)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+        if ref is None:
+            ref = phi.clone()
+        dev_rel = float((phi - ref).abs().max() / ref.abs().max())
+        out[name] = {"gdof_s": m.info.n_free / best / 1e9, "solve_ms": best * 1e3, "iters": st["iters"],
+                     "refinements": st["refinements"], "rel_residual": st["rel_residual"],
+                     "max_rel_diff_vs_fp64": dev_rel}
+    u = torch.randn(m.n, dtype=torch.float64, device=dev)
+    y = torch.empty_like(u)
+    E = m.info.n_elem
+    for name, prec, word, dt in (("fp64", 0, 8, torch.float64), ("fp32", 1, 4, torch.float32),
+                                 ("bf16_factors", 2, None, torch.float32)):
+        uu = u.to(dt)
+        yy = torch.empty_like(uu)
+        ms = m.apply_timed(lib.SEM_OP_STIFFNESS, uu, yy, 200, prec)
+        if word is None:
+            b = stiffness_bytes_per_elem(spec.P, 4, gword=2) * E
+        else:
+            b = stiffness_bytes_per_elem(spec.P, word) * E
+        out.setdefault("stiffness", {})[name] = {"mean_launch_ms": ms, "bytes_per_launch": b,
+                                                 "achieved_gbs": b / (ms * 1e-3) / 1e9,
+                                                 "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +154,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-large", action="store_true", help="skip the 2048x8 bar-tank section")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -116,12 +196,17 @@ def main():
     tsolve, iters, nsolve = run(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the stiffness kernel timed live with HIP events around each of its
+    # launches on the solve's stream, over further steps of the same run (the
+    # event records themselves slow the steps, so they stay out of `value`)
+    m.kernel_timing(True)
+    run(min(args.steps, 50))
+    torch.cuda.synchronize()
+    nlaunch, kms = m.kernel_timing_read()
+    m.kernel_timing(False)
+    ms = kms / max(nlaunch, 1)
 
     # dominant kernel: the matrix-free stiffness apply on this tank's factors
-    u = torch.randn(m.n, dtype=torch.float64, device=dev)
-    y = torch.empty_like(u)
-    reps = 200
-    ms = m.apply_timed(lib.SEM_OP_STIFFNESS, u, y, reps)
     E = m.info.n_elem
     bytes_launch = stiffness_bytes_per_elem(spec.P) * E
     achieved = bytes_launch / (ms * 1e-3) / 1e9
@@ -143,12 +228,21 @@ def main():
                    "n_free": int(n_free), "elements": int(E), "rtol": args.rtol, "precision": "fp64",
                    "solves": nsolve, "mean_iters": iters / max(nsolve, 1),
                    "solve_time_fraction": tsolve / wall},
-        "roofline": {"bound": "hbm", "kernel": "stiffness apply (k_gather STIFF)", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "stiffness apply (k_stiff_mfma)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "mean_launch_ms": ms,
+                     "traffic": measured_traffic(), "mean_launch_ms": ms, "launches": nlaunch,
                      "bytes_per_launch": bytes_launch,
                      "flops_per_launch": stiffness_flops_per_elem(spec.P) * E},
     }
+    if args.copy_probe:
+        a = torch.empty(32 << 20, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = {"read": a.numel() * 8, "write": a.numel() * 8}
+    if not args.no_large:
+        out["large_tank"] = large_tank(lib, wl, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
     print(json.dumps(out))

@@ -200,6 +200,19 @@ void sem_batch_destroy(sem_batch* batch);
  * doubles, may be NULL) receives lane*4+v for FP64 then for FP32. */
 sem_status sem_selftest_mfma(sem_mesh* mesh, double* max_err_host, double* raw_host, void* stream);
 
+/* Live timing of the stiffness-apply kernel inside the Krylov iterations
+ * (the operator of Secs. 3.1.2 and 3.2): while enabled, every stiffness
+ * launch of the GMRES iterations of sem_laplace_solve / sem_rk4_step (and the
+ * batch step), in whatever precision the iterations run, is bracketed by HIP
+ * events on the solve's stream; launches queued after convergence, which
+ * return at once, are not counted.  enable = 1 starts (and clears) the
+ * accumulation, 0 stops it.  sem_kernel_timing_read returns the number of
+ * counted launches and their summed duration in milliseconds (HOST
+ * pointers).  Timing adds event records to the stream; leave it off in
+ * production. */
+sem_status sem_kernel_timing(sem_mesh* mesh, int32_t enable);
+sem_status sem_kernel_timing_read(const sem_mesh* mesh, int64_t* launches_host, double* total_ms_host);
+
 const char* sem_last_error(void);
 
 #ifdef __cplusplus

@@ -1107,7 +1107,15 @@ static void gather_full(const TankDev& h, const TankDev* d, int op, const T* u, 
   }
   if (op == OP_STIFF && h.use_mfma) stiff_mfma(h, d, u, y, side, flags, sizeof(GS) == 1 ? 2 : 1, st);
   else gather_kernel<T, GS>(h, d, op, u, y, side, flags, st);
-  hipLaunchKernelGGL(k_fixup<T>, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side, flags);
+  if (!(flags & F_NOFIX))
+    hipLaunchKernelGGL(k_fixup<T>, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side, flags);
+}
+
+void launch_fixup(const TankDev& h, const TankDev* d, double* y, double* side, int flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_fixup<double>, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side, flags);
+}
+void launch_fixup(const TankDev& h, const TankDev* d, float* y, float* side, int flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_fixup<float>, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side, flags);
 }
 
 void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side,

@@ -30,6 +30,8 @@ namespace {
 constexpr int kWaves = kBlockThreads / 64;
 constexpr int kMtw = 2;   // M-tiles per wave in the condensation product
 
+__host__ __device__ inline int sd_part_words(int q) { return max(kWaves * 16 * 16 * 2, 32 * q); }
+
 __device__ inline double wsum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -113,9 +115,9 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
   extern __shared__ double sh[];
-  double* part = sh;                      // [kWaves][16][16][2]
-  double* gh = sh + kWaves * 16 * 16 * 2; // [16][q][2]
   const int q = sd.q, nx = d.nx, nc = d.nc;
+  double* part = sh;                      // [kWaves][16][16][2], later x^ of the block's modes [16][q][2]
+  double* gh = sh + sd_part_words(q);     // [16][q][2]
   const int nNT = (q + 15) / 16, KS = (nx + 3) / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   const int k0 = blockIdx.x * 16;
@@ -192,6 +194,30 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
     }
     sd.XH[((size_t)k * q + i) * 2] = xr;
     sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
+    if (sd.wall) {
+      part[t * 2] = xr;   // the reduction area is free again: x^ of this block's modes
+      part[t * 2 + 1] = xi;
+    }
+  }
+  if (!sd.wall) return;
+  // walls: this block's share of lines nx-1 and 0 of the inverse transform
+  __syncthreads();
+  const int a0 = nx - 1;
+  for (int t = threadIdx.x; t < 2 * q; t += blockDim.x) {
+    const int ln = t / q, j = t - ln * q;
+    double acc = 0;
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = k0 + kk;
+      if (k >= nx) break;
+      const double hr = part[(kk * q + j) * 2], hi = part[(kk * q + j) * 2 + 1];
+      if (ln == 0) {
+        const int mm = (int)(((int64_t)k * a0) % nx);
+        acc += hr * d.twid[2 * mm] + hi * d.twid[2 * mm + 1];
+      } else {
+        acc += hr;
+      }
+    }
+    sd.WP[((size_t)blockIdx.x * 2 + ln) * q + j] = acc;
   }
 }
 
@@ -290,32 +316,44 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
     for (int j = threadIdx.x; j < q; j += blockDim.x) z[(int64_t)nx * nc + j] = T(xl[j] + sd.vbuf[j]);
     if (sd.zero_surface && threadIdx.x == 0) z[(int64_t)nx * nc + d.nl - 1] = T(0);
   }
-  // z_I = Y - C [x_L,c; x_L,c+1]: one M-tile per wave
-  const int mt = blockIdx.y * kWaves + wv;
-  if (mt >= sd.nMT3) return;
+  // z_I = Y - C [x_L,c; x_L,c+1]: kMtw M-tiles per wave
+  const int mt0 = (blockIdx.y * kWaves + wv) * kMtw;
+  const int nMT = sd.nMT3;
+  if (mt0 >= nMT) return;
   const T* C = SdMat<T>::C3(sd);
   const int KS3 = sd.KS3;
-  V4 acc = V4{0, 0, 0, 0};
+  V4 acc[kMtw];
+#pragma unroll
+  for (int u = 0; u < kMtw; ++u) acc[u] = V4{0, 0, 0, 0};
 #pragma unroll 4
   for (int s = 0; s < KS3; ++s) {
     const int kk = 4 * s + grp;
     T b = T(0);
     if (kk < q) b = T(xl[col * q + kk]);
     else if (kk < 2 * q) b = T(xl[(col + 1) * q + kk - q]);
-    acc = MF::op(C[((size_t)mt * KS3 + s) * 64 + lane], b, acc);
+#pragma unroll
+    for (int u = 0; u < kMtw; ++u) {
+      const int mt = min(mt0 + u, nMT - 1);   // a clamped tile is computed, never stored
+      acc[u] = MF::op(C[((size_t)mt * KS3 + s) * 64 + lane], b, acc[u]);
+    }
   }
   const int c = c0 + col;
   if (c >= nx) return;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = 16 * mt + MF::row(v, grp);
-    if (row < nI) z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - (double)acc[v]);
+  for (int u = 0; u < kMtw; ++u) {
+    const int mt = mt0 + u;
+    if (mt >= nMT) break;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * mt + MF::row(v, grp);
+      if (row < nI) z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - (double)acc[u][v]);
+    }
   }
 }
 
-// Wall correction (one workgroup): the first solve's values on the last
-// column and line 0, the jump v = Sc^-1 (r_wall - B21 y), and the last
-// column's interior update y_I -= Q v.
+// Wall correction (one workgroup): lines nx-1 and 0 of the first solve
+// (sums of the per-block partials), then v = W [r_wall; x_{nx-1}; x_0; y_I]
+// with one wavefront per component of v.
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
@@ -324,98 +362,61 @@ k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   const SDData& sd = d.sd[which];
   extern __shared__ double sh[];
   const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc;
-  const int np = 2 * q + nI;
-  double* part = sh;              // [kWaves][2][64]
-  double* yg = part + kWaves * 2 * 64;   // [np]: line nx-1, interior of column nx-1, line 0
-  double* t = yg + np;            // [q]
-  double* v = t + q;              // [q]
+  const int np = 3 * q + nI;
+  const int nb2 = (nx + 15) / 16;
+  double* in = sh;   // [np]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int a0 = nx - 1;
   const double inx = 1.0 / nx;
-  // lines nx-1 and 0 of the first solve from its modes
-  const int step = (int)(((int64_t)kWaves * a0) % nx);
-  for (int j0 = 0; j0 < q; j0 += 64) {
-    const int j = j0 + lane;
-    double s0 = 0, s1 = 0;
-    if (j < q) {
-      int mm = (int)(((int64_t)a0 * wv) % nx);
-#pragma unroll 4
-      for (int k = wv; k < nx; k += kWaves) {
-        const double hr = sd.XH[((size_t)k * q + j) * 2], hi = sd.XH[((size_t)k * q + j) * 2 + 1];
-        s0 += hr * d.twid[2 * mm] + hi * d.twid[2 * mm + 1];
-        s1 += hr;                 // line 0: e^{0} = 1
-        mm += step;
-        if (mm >= nx) mm -= nx;
-      }
-    }
-    part[(wv * 2 + 0) * 64 + lane] = s0;
-    part[(wv * 2 + 1) * 64 + lane] = s1;
-    __syncthreads();
-    if (threadIdx.x < 64 && j0 + threadIdx.x < q) {
-      double x0 = 0, x1 = 0;
-      for (int w = 0; w < kWaves; ++w) {
-        x0 += part[(w * 2 + 0) * 64 + threadIdx.x];
-        x1 += part[(w * 2 + 1) * 64 + threadIdx.x];
-      }
-      yg[j0 + threadIdx.x] = x0 * inx;
-      yg[q + nI + j0 + threadIdx.x] = x1 * inx;
-    }
-    __syncthreads();
+  for (int t = threadIdx.x; t < 2 * q; t += blockDim.x) {
+    const int ln = t / q, j = t - ln * q;
+    double acc = 0;
+#pragma unroll 8
+    for (int b = 0; b < nb2; ++b) acc += sd.WP[((size_t)b * 2 + ln) * q + j];
+    in[q + ln * q + j] = acc * inx;
   }
-  // interior of column nx-1: y_I - C [x_{nx-1}; x_0]
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    double acc = sd.yI[(size_t)a0 * nI + i];
-#pragma unroll 4
-    for (int p = 0; p < q; ++p) acc -= sd.Crm[(size_t)p * nI + i] * yg[p];
-#pragma unroll 4
-    for (int p = 0; p < q; ++p) acc -= sd.Crm[(size_t)(q + p) * nI + i] * yg[q + nI + p];
-    yg[q + i] = acc;
-  }
+  for (int a = threadIdx.x; a < q; a += blockDim.x) in[a] = (double)r[(int64_t)nx * nc + a];
+  for (int i = threadIdx.x; i < nI; i += blockDim.x) in[3 * q + i] = sd.yI[(size_t)(nx - 1) * nI + i];
   __syncthreads();
-  for (int a = threadIdx.x; a < q; a += blockDim.x) {
-    double acc = (double)r[(int64_t)nx * nc + a];
-#pragma unroll 4
-    for (int p = 0; p < np; ++p) acc -= sd.Bt[(size_t)p * q + a] * yg[p];
-    t[a] = acc;
-  }
-  __syncthreads();
-  for (int a = threadIdx.x; a < q; a += blockDim.x) {
+  for (int a = wv; a < q; a += kWaves) {
+    const double* row = sd.Wv + (size_t)a * np;
     double acc = 0;
 #pragma unroll 4
-    for (int b = 0; b < q; ++b) acc += sd.Wv[(size_t)b * q + a] * t[b];
-    v[a] = acc;
-    sd.vbuf[a] = acc;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) {
-    double acc = 0;
-#pragma unroll 4
-    for (int a = 0; a < q; ++a) acc += sd.Qm[(size_t)a * nI + i] * v[a];
-    sd.yI[(size_t)a0 * nI + i] -= acc;
+    for (int p = lane; p < np; p += 64) acc += row[p] * in[p];
+    acc = wsum(acc);
+    if (lane == 0) sd.vbuf[a] = acc;
   }
 }
 
-// x^_k -= H_k v for every mode (thread per mode and line unknown)
+// x^_k -= H_k v for every mode (thread per mode and line unknown); the
+// last column's interior solve y_I -= Q v (threads past nx q)
 __global__ void __launch_bounds__(kBlockThreads)
 k_sd_wall_modes(const TankDev* __restrict__ td, int which, int gate) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
   const SDData& sd = d.sd[which];
-  const int q = sd.q;
+  const int q = sd.q, nI = sd.nI;
+  const int64_t nm = (int64_t)d.nx * q;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)d.nx * q) return;
-  const int64_t k = t / q;
-  const int i = (int)(t - k * q);
-  const double* Hk = sd.Hm + (size_t)k * q * q * 2;
-  double xr = 0, xi = 0;
+  if (t < nm) {
+    const int64_t k = t / q;
+    const int i = (int)(t - k * q);
+    const double* Hk = sd.Hm + (size_t)k * q * q * 2;
+    double xr = 0, xi = 0;
 #pragma unroll 4
-  for (int a = 0; a < q; ++a) {
-    const double va = sd.vbuf[a];
-    xr += Hk[((size_t)a * q + i) * 2] * va;
-    xi += Hk[((size_t)a * q + i) * 2 + 1] * va;
+    for (int a = 0; a < q; ++a) {
+      const double va = sd.vbuf[a];
+      xr += Hk[((size_t)a * q + i) * 2] * va;
+      xi += Hk[((size_t)a * q + i) * 2 + 1] * va;
+    }
+    sd.XH[((size_t)k * q + i) * 2] -= xr;
+    sd.XH[((size_t)k * q + i) * 2 + 1] -= xi;
+  } else if (t < nm + nI) {
+    const int i = (int)(t - nm);
+    double acc = 0;
+#pragma unroll 4
+    for (int a = 0; a < q; ++a) acc += sd.Qm[(size_t)a * nI + i] * sd.vbuf[a];
+    sd.yI[(size_t)(d.nx - 1) * nI + i] -= acc;
   }
-  sd.XH[((size_t)k * q + i) * 2] -= xr;
-  sd.XH[((size_t)k * q + i) * 2 + 1] -= xi;
 }
 
 template <typename T>
@@ -423,16 +424,16 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
   const SDData& sd = h.sd[which];
   const unsigned ct = (unsigned)((h.nx + 15) / 16);
   const size_t l1 = sizeof(T) * 4 * (size_t)sd.KS1 * 16;
-  const size_t l2 = sizeof(double) * (kWaves * 16 * 16 * 2 + 16 * (size_t)sd.q * 2);
+  const size_t l2 = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
   const size_t l3 = sizeof(double) * (kWaves * 16 * 16 + 17 * (size_t)sd.q);
   const unsigned g1 = (unsigned)((sd.nMT1 + kWaves * kMtw - 1) / (kWaves * kMtw));
-  const unsigned g3 = (unsigned)((sd.nMT3 + kWaves - 1) / kWaves);
+  const unsigned g3 = (unsigned)((sd.nMT3 + kWaves * kMtw - 1) / (kWaves * kMtw));
   hipLaunchKernelGGL(k_sd_cond<T>, dim3(ct, g1), dim3(kBlockThreads), l1, st, d, which, u, gate);
   hipLaunchKernelGGL(k_sd_modes<T>, dim3(ct), dim3(kBlockThreads), l2, st, d, which, u, gate);
   if (sd.wall) {
-    const size_t lw = sizeof(double) * (kWaves * 2 * 64 + 2 * (size_t)sd.q + sd.nI + 2 * (size_t)sd.q);
+    const size_t lw = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
     hipLaunchKernelGGL(k_sd_wall<T>, dim3(1), dim3(kBlockThreads), lw, st, d, which, u, gate);
-    const int64_t nm = (int64_t)h.nx * sd.q;
+    const int64_t nm = (int64_t)h.nx * sd.q + sd.nI;
     hipLaunchKernelGGL(k_sd_wall_modes, dim3((unsigned)((nm + kBlockThreads - 1) / kBlockThreads)),
                        dim3(kBlockThreads), 0, st, d, which, gate);
   }

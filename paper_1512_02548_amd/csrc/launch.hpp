@@ -9,7 +9,7 @@ namespace sem {
 enum { OP_STIFF = 0, OP_MASS = 1, OP_PRE_LAP = 2, OP_PRE_MASS = 3, OP_SZ = 4 };
 // gather flags: mask the surface rows, negate, skip the launch once the
 // tank's Krylov cycle is done (kernels queued ahead of a convergence test)
-enum { F_MASK_SURF = 1, F_NEG = 2, F_GATE = 4 };
+enum { F_MASK_SURF = 1, F_NEG = 2, F_GATE = 4, F_NOFIX = 8 };   // F_NOFIX: element kernel only
 // progress word mirrored to host memory by the Krylov kernels
 enum { PROG_STEPS = 0xffff, PROG_DONE = 1 << 16, PROG_CONV = 1 << 17 };
 
@@ -26,6 +26,8 @@ void launch_stiff_mfma(const TankDev& h, const TankDev* d, const double* u, doub
 void launch_stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
                        int gstore, hipStream_t st);
 void launch_mfma_probe(double* out64, float* out32, hipStream_t st);
+void launch_fixup(const TankDev& h, const TankDev* d, double* y, double* side, int flags, hipStream_t st);
+void launch_fixup(const TankDev& h, const TankDev* d, float* y, float* side, int flags, hipStream_t st);
 void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st);
 void launch_sd(const TankDev& h, const TankDev* d, int which, const float* u, float* y, int gate, hipStream_t st);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);

@@ -77,8 +77,18 @@ struct sem_mesh {
   // by the device, read by the host while it queues steps)
   int32_t* prog_host = nullptr;
   int32_t* prog_dev = nullptr;
+  // live timing of the stiffness kernel (event pairs of the running cycle)
+  bool kt_on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> kt_ev;
+  size_t kt_used = 0;
+  int64_t kt_count = 0;
+  double kt_ms = 0;
   ~sem_mesh() {
     if (prog_host) (void)hipHostFree(prog_host);
+    for (auto& e : kt_ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
   }
 };
 
@@ -403,7 +413,7 @@ static sem_status build_mesh(sem_mesh* M) {
     int nI = 0, q = 0, M1 = 0, nMT1 = 0, KS1 = 0, nMT3 = 0, KS3 = 0, wall = 0;
     std::vector<int32_t> I_idx;
     std::vector<double> A1, C3, Shat;   // fragment-ordered factors, per-mode inverses
-    std::vector<double> Wv, Hm, Qm, Bt, Crm;   // wall-line correction (tanks with walls)
+    std::vector<double> Wv, Hm, Qm;   // wall-line correction (tanks with walls)
   } sdh[2];
   // MFMA fragment order of a rows x cols row-major matrix: [M-tile][K-step][lane]
   auto fragments = [](const Mat& A, int rows, int cols, int* nmt, int* ks) {
@@ -632,25 +642,38 @@ static sem_status build_mesh(sem_mesh* M) {
             PhiR[t] -= RQ[t];
           }
         }
-        // uploads, column-major so that threads over the output rows read consecutive words
-        H.Wv.assign((size_t)q * q, 0.0);
-        for (int a = 0; a < q; ++a)
-          for (int b = 0; b < q; ++b) H.Wv[(size_t)b * q + a] = Sc[(size_t)a * q + b];
+        // v = Sc^-1 (r_w - B21 y) with y on the last column from the first
+        // solve: lines nx-1 and 0 (x_a, x_b) and interior y_I - C_L x_a - C_R x_b.
+        // Folded into one row-major q x (3q + nI) matrix acting on
+        // [r_w; x_a; x_b; y_I]:  [Sc^-1 | -Sc^-1 (B21L - B21I C_L) | -Sc^-1 (B21R - B21I C_R) | -Sc^-1 B21I]
+        {
+          Mat CL((size_t)nI * q), CR((size_t)nI * q);
+          for (int i = 0; i < nI; ++i)
+            for (int a = 0; a < q; ++a) {
+              CL[(size_t)i * q + a] = W[(size_t)i * 2 * q + a];
+              CR[(size_t)i * q + a] = W[(size_t)i * 2 * q + q + a];
+            }
+          Mat BL = matmul(B21I, CL, q, nI, q), BR = matmul(B21I, CR, q, nI, q);
+          for (size_t t = 0; t < BL.size(); ++t) {
+            BL[t] = B21L[t] - BL[t];
+            BR[t] = B21R[t] - BR[t];
+          }
+          Mat V2 = matmul(Sc, BL, q, q, q), V3 = matmul(Sc, BR, q, q, q), V4 = matmul(Sc, B21I, q, q, nI);
+          const int np = 3 * q + nI;
+          H.Wv.assign((size_t)q * np, 0.0);
+          for (int a = 0; a < q; ++a) {
+            for (int b = 0; b < q; ++b) {
+              H.Wv[(size_t)a * np + b] = Sc[(size_t)a * q + b];
+              H.Wv[(size_t)a * np + q + b] = -V2[(size_t)a * q + b];
+              H.Wv[(size_t)a * np + 2 * q + b] = -V3[(size_t)a * q + b];
+            }
+            for (int i = 0; i < nI; ++i) H.Wv[(size_t)a * np + 3 * q + i] = -V4[(size_t)a * nI + i];
+          }
+        }
+        // y_I of the last column -= Q v  (column-major: threads over the interior rows)
         H.Qm.assign((size_t)q * nI, 0.0);
         for (int i = 0; i < nI; ++i)
           for (int a = 0; a < q; ++a) H.Qm[(size_t)a * nI + i] = Q[(size_t)i * q + a];
-        const int np = 2 * q + nI;
-        H.Bt.assign((size_t)np * q, 0.0);
-        for (int a = 0; a < q; ++a) {
-          for (int b = 0; b < q; ++b) {
-            H.Bt[(size_t)b * q + a] = B21L[(size_t)a * q + b];
-            H.Bt[(size_t)(q + nI + b) * q + a] = B21R[(size_t)a * q + b];
-          }
-          for (int i = 0; i < nI; ++i) H.Bt[(size_t)(q + i) * q + a] = B21I[(size_t)a * nI + i];
-        }
-        H.Crm.assign((size_t)2 * q * nI, 0.0);
-        for (int i = 0; i < nI; ++i)
-          for (int pp = 0; pp < 2 * q; ++pp) H.Crm[(size_t)pp * nI + i] = W[(size_t)i * 2 * q + pp];
         // H_k = S^_k^-1 (e^{i th_k} Phi_L + Phi_R), column-major per mode
         H.Hm.assign((size_t)nx * q * q * 2, 0.0);
         parallel_for(nx, [&](int k) {
@@ -853,9 +876,8 @@ static sem_status build_mesh(sem_mesh* M) {
     put(M, (p + "Wv").c_str(), H.Wv);
     put(M, (p + "Hm").c_str(), H.Hm);
     put(M, (p + "Qm").c_str(), H.Qm);
-    put(M, (p + "Bt").c_str(), H.Bt);
-    put(M, (p + "Crm").c_str(), H.Crm);
     reserve(M, (p + "vbuf").c_str(), (size_t)std::max(1, H.q) * sizeof(double));
+    reserve(M, (p + "WP").c_str(), (size_t)((nx + 15) / 16) * 2 * std::max(1, H.q) * sizeof(double));
     reserve(M, (p + "yI").c_str(), (size_t)nx * std::max(1, H.nI) * sizeof(double));
     reserve(M, (p + "TL").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
     reserve(M, (p + "TR").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
@@ -1065,9 +1087,8 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     sd.Wv = at<double>(M, (p + "Wv").c_str());
     sd.Hm = at<double>(M, (p + "Hm").c_str());
     sd.Qm = at<double>(M, (p + "Qm").c_str());
-    sd.Bt = at<double>(M, (p + "Bt").c_str());
-    sd.Crm = at<double>(M, (p + "Crm").c_str());
     sd.vbuf = at<double>(M, (p + "vbuf").c_str());
+    sd.WP = at<double>(M, (p + "WP").c_str());
   }
   h.M1 = at<double>(M, "M1");
   h.S1 = at<double>(M, "S1");
@@ -1181,6 +1202,43 @@ static void gather_t(sem_mesh* M, const GmresCfg& c, int op, const float* u, flo
   launch_gather(M->hd, M->dtank, op, u, y, side, flags, c.gstore, st);
 }
 
+// Stiffness application inside the Krylov loop, bracketed by timing events
+// when enabled (the fix-up of shared lines runs after the end event).
+template <typename T>
+static sem_status stiff_timed(sem_mesh* M, const GmresCfg& cfg, const T* u, T* y, T* side, int flags,
+                              hipStream_t st) {
+  if (!M->kt_on || cfg.op != OP_STIFF) {
+    gather_t(M, cfg, cfg.op, u, y, side, flags, st);
+    return SEM_OK;
+  }
+  if (M->kt_used == M->kt_ev.size()) {
+    std::pair<hipEvent_t, hipEvent_t> e;
+    HIPCHK(hipEventCreate(&e.first));
+    HIPCHK(hipEventCreate(&e.second));
+    M->kt_ev.push_back(e);
+  }
+  auto& e = M->kt_ev[M->kt_used++];
+  HIPCHK(hipEventRecord(e.first, st));
+  gather_t(M, cfg, cfg.op, u, y, side, flags | F_NOFIX, st);
+  HIPCHK(hipEventRecord(e.second, st));
+  launch_fixup(M->hd, M->dtank, y, side, flags, st);
+  return SEM_OK;
+}
+
+// Adds the first `real` recorded launches (the stream has been synchronised)
+static sem_status stiff_harvest(sem_mesh* M, size_t real) {
+  if (!M->kt_on) return SEM_OK;
+  real = std::min(real, M->kt_used);
+  for (size_t i = 0; i < real; ++i) {
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, M->kt_ev[i].first, M->kt_ev[i].second));
+    M->kt_ms += t;
+    M->kt_count += 1;
+  }
+  M->kt_used = 0;
+  return SEM_OK;
+}
+
 // Restarted right-preconditioned GMRES (classical Gram-Schmidt, Givens
 // rotations) on device vectors of type T: x (in: guess, out: solution), b.
 // Inner products, the Hessenberg matrix and the rotations are FP64.
@@ -1203,6 +1261,7 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
   const int gflags = flags | F_GATE;
   const int ahead = std::max(1, cfg.ahead);
   volatile int32_t* prog = M->prog_host;
+  M->kt_used = 0;
   KrylovState ks0{};
   ks0.rtol = cfg.rtol;
   HIPCHK(hipMemcpyAsync(h.ks, &ks0, sizeof(ks0), hipMemcpyHostToDevice, st));
@@ -1214,7 +1273,10 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
   while (true) {
     *prog = 0;
     // r = b - A x
-    gather_t(M, cfg, cfg.op, x, B.w, B.side, flags, st);
+    {
+      sem_status e = stiff_timed(M, cfg, x, B.w, B.side, flags, st);
+      if (e) return e;
+    }
     launch_residual(h, d, n, b, B.w, B.V, cfg.mask ? 1 : 0, st);
     launch_dots(n, 1, B.V, 0, B.V, h.part, ldp, scal + 0, cnt, nullptr, st);
     launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, B.V, M->prog_dev, st);
@@ -1223,7 +1285,10 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       T* Vj = B.V + (size_t)j * n;
       T* Zj = B.Z + (size_t)j * n;
       gather_t(M, cfg, cfg.pre, Vj, Zj, B.side, gflags, st);
-      gather_t(M, cfg, cfg.op, Zj, B.w, B.side, gflags, st);
+      {
+        sem_status e = stiff_timed(M, cfg, Zj, B.w, B.side, gflags, st);
+        if (e) return e;
+      }
       double* Hcol = h.H + (size_t)j * (m + 1);
       launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st);
       launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
@@ -1250,6 +1315,11 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
     launch_solve_update(n, B.Z, h.H, m, h.ks, x, st);
     HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    {
+      // the cycle's residual apply plus its executed steps; later ones were gated
+      sem_status e = stiff_harvest(M, 1 + (size_t)std::max(0, hks.j));
+      if (e) return e;
+    }
     total = hks.iters;
     if (hks.status || hks.converged || total >= cfg.max_iter) break;
   }
@@ -1294,6 +1364,24 @@ extern "C" sem_status sem_set_surface(sem_mesh* M, const double* eta, const doub
   HIPCHK(hipMemsetAsync(M->hd.status, 0, sizeof(int32_t), st));
   launch_coef(M->hd, M->dtank, eta, eta_x, 3, st);
   return read_status(M, st, nullptr);
+}
+
+extern "C" sem_status sem_kernel_timing(sem_mesh* M, int32_t enable) {
+  if (!M) return fail(SEM_E_INVAL, "null mesh");
+  M->kt_on = enable != 0;
+  M->kt_used = 0;
+  if (M->kt_on) {
+    M->kt_count = 0;
+    M->kt_ms = 0;
+  }
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_kernel_timing_read(const sem_mesh* M, int64_t* launches, double* total_ms) {
+  if (!M || !launches || !total_ms) return fail(SEM_E_INVAL, "null argument");
+  *launches = M->kt_count;
+  *total_ms = M->kt_ms;
+  return SEM_OK;
 }
 
 extern "C" sem_status sem_apply(sem_mesh* M, sem_operator op, const double* u, double* y, void* stream) {

@@ -58,12 +58,11 @@ struct SDData {
   // tanks with walls: correction for the jump v between the wall line nx and
   // line 0 of the periodic solve (Schur complement on the wall line)
   int32_t wall, pad2;
-  const double* Wv;               // [q][q] inverse Schur complement, column-major
+  const double* Wv;               // [q][3q + nI] v from [r_wall; x_{nx-1}; x_0; y_I(nx-1)], row-major
   const double* Hm;               // [nx][q][q][2] modal response to v, column-major per mode
   const double* Qm;               // [q][nI] interior response of the last column, column-major
-  const double* Bt;               // [2q + nI][q] wall-line row of the last column, column-major
-  const double* Crm;              // [2q][nI] back-substitution factor, column-major
   double* vbuf;                   // [q] v
+  double* WP;                     // [nx/16][2][q] per-block partial sums of lines nx-1 and 0
 };
 
 // Everything a kernel needs about one tank; lives in device memory at the

@@ -84,6 +84,8 @@ _SIGS = {
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
     "sem_batch_destroy": (None, [_P]),
     "sem_selftest_mfma": (C.c_int, [_P, C.POINTER(C.c_double), _D, _P]),
+    "sem_kernel_timing": (C.c_int, [_P, C.c_int32]),
+    "sem_kernel_timing_read": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "sem_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -183,6 +185,15 @@ class Mesh:
         check(sem_apply_timed(self.handle, op, prec, _ptr(u), _ptr(y), int(reps), C.byref(ms), _stream(stream)),
               "sem_apply_timed")
         return ms.value
+
+    def kernel_timing(self, enable):
+        check(sem_kernel_timing(self.handle, 1 if enable else 0), "sem_kernel_timing")
+
+    def kernel_timing_read(self):
+        n = C.c_int64()
+        ms = C.c_double()
+        check(sem_kernel_timing_read(self.handle, C.byref(n), C.byref(ms)), "sem_kernel_timing_read")
+        return n.value, ms.value
 
     def laplace_solve(self, eta, etax, phis, phi, opts=None, stream=None):
         st = sem_solve_stats()
