@@ -146,6 +146,93 @@ def large_tank(lib, wl, torch, reps=3):
     return out
 
 
+def build_meshes(lib, specs, state_fn, threads=8):
+    """Host-side mesh construction in parallel (the C calls release the GIL),
+    then device binding; returns meshes and device states."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+
+    def probe(spec):
+        return lib.mesh_from_spec(spec, np.ones(spec.ns), np.zeros(spec.ns), bind=False)
+
+    with ThreadPoolExecutor(threads) as ex:
+        probes = list(ex.map(probe, specs))
+    states = [state_fn(p.surface_x(), sp) for p, sp in zip(probes, specs)]
+    need = [i for i, (e, ph, h, hx) in enumerate(states) if not (np.all(h == 1.0) and np.all(hx == 0.0))]
+
+    def rebuild(i):
+        e, ph, h, hx = states[i]
+        return lib.mesh_from_spec(specs[i], h, hx, bind=False)
+
+    with ThreadPoolExecutor(threads) as ex:
+        for i, m in zip(need, ex.map(rebuild, need)):
+            probes[i] = m
+    dev = torch.device("cuda:0")
+    out = []
+    for m, (e, ph, h, hx) in zip(probes, states):
+        m.bind("cuda:0")
+        out.append(dict(mesh=m, eta=torch.tensor(e, device=dev), phi=torch.tensor(ph, device=dev),
+                        ws=torch.zeros(m.n, dtype=torch.float64, device=dev)))
+    return out
+
+
+def batch_workload(args):
+    """256 periodic tanks of random size and order (seeded): RK4 steps of all
+    tanks through the batch call with FP32 inner solves inside FP64
+    refinement, against a per-tank sequential FP64 loop on the same GPU."""
+    import torch
+
+    from paper_1512_02548_amd import lib
+    from paper_1512_02548_amd import workloads as wl
+    specs = wl.batch_tank_specs(count=args.tanks, rtol=1e-10)
+    t0 = time.perf_counter()
+    tanks = build_meshes(lib, specs, wl.batch_tank_state)
+    t_build = time.perf_counter() - t0
+    nfree = sum(int(t["mesh"].info.n_free) for t in tanks)
+    dts = [sp.dt for sp in specs]
+    res = {"workload": f"batch_tanks_{args.tanks}", "tanks": args.tanks, "sum_n_free": nfree,
+           "host_build_s": t_build, "steps": args.batch_steps}
+    save = [(t["eta"].clone(), t["phi"].clone()) for t in tanks]
+
+    def restore():
+        for t, (e, p) in zip(tanks, save):
+            t["eta"].copy_(e)
+            t["phi"].copy_(p)
+            t["ws"].zero_()
+
+    mixed = lib.default_opts(rtol=1e-10, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-2, max_iter=20000)
+    b = lib.Batch([t["mesh"] for t in tanks], args.streams)
+    restore()
+    b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks], [t["ws"] for t in tanks], dts, opts=mixed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        code, st, it = b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks],
+                                  [t["ws"] for t in tanks], dts, opts=mixed)
+        if code != 0:
+            raise RuntimeError(f"batch step failed: {[lib.STATUS_NAMES.get(x, x) for x in st if x]}")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    res["batched_mixed"] = {"tank_steps_per_s": args.tanks * args.batch_steps / tb,
+                            "gdof_s": 4 * nfree * args.batch_steps / tb / 1e9, "seconds": tb,
+                            "streams": args.streams}
+    fp64 = lib.default_opts(rtol=1e-10, warm_start=1, max_iter=20000)
+    restore()
+    for t, dt in zip(tanks, dts):
+        t["mesh"].rk4_step(t["eta"], t["phi"], t["ws"], dt, fp64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        for t, dt in zip(tanks, dts):
+            t["mesh"].rk4_step(t["eta"], t["phi"], t["ws"], dt, fp64)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    res["sequential_fp64"] = {"tank_steps_per_s": args.tanks * args.batch_steps / ts,
+                              "gdof_s": 4 * nfree * args.batch_steps / ts / 1e9, "seconds": ts}
+    res["speedup"] = ts / tb
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,11 +244,20 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 2048x8 bar-tank section")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--workload", choices=["stream_series", "batch"], default="stream_series",
+                    help="batch: the 256-tank batching comparison (one JSON object, not the bench line)")
+    ap.add_argument("--tanks", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--streams", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "batch":
+        print(json.dumps(batch_workload(args)))
+        return
 
     import torch
 

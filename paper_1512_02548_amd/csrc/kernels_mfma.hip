@@ -13,6 +13,7 @@
 // U is gathered from the LDS-staged input region, G streams from HBM in the
 // matching tile order, Y goes to LDS for the deterministic per-node sums
 // shared with the reference kernel.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -244,6 +245,26 @@ void launch_stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float
   } else {
     SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, float, float>), dim3(h.nb), dim3(kBlockThreads), lds, st,
                                           d, u, y, side, flags));
+  }
+}
+
+// Same launches with start/stop events taken from the dispatch itself (no
+// marker packets around the kernel): used to time the kernel inside solves.
+void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, int flags,
+                             hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+  size_t lds = stiff_mfma_lds_bytes(h, sizeof(double));
+  SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, double, double>), dim3(h.nb), dim3(kBlockThreads), lds,
+                                           st, e0, e1, 0, d, u, y, side, flags));
+}
+void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
+                             int gstore, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+  size_t lds = stiff_mfma_lds_bytes(h, sizeof(float));
+  if (gstore == 2) {
+    SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, float, BF16m>), dim3(h.nb), dim3(kBlockThreads), lds,
+                                             st, e0, e1, 0, d, u, y, side, flags));
+  } else {
+    SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, float, float>), dim3(h.nb), dim3(kBlockThreads), lds,
+                                             st, e0, e1, 0, d, u, y, side, flags));
   }
 }
 

@@ -25,6 +25,10 @@ void launch_stiff_mfma(const TankDev& h, const TankDev* d, const double* u, doub
                        hipStream_t st);
 void launch_stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
                        int gstore, hipStream_t st);
+void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, int flags,
+                             hipEvent_t e0, hipEvent_t e1, hipStream_t st);
+void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
+                             int gstore, hipEvent_t e0, hipEvent_t e1, hipStream_t st);
 void launch_mfma_probe(double* out64, float* out32, hipStream_t st);
 void launch_fixup(const TankDev& h, const TankDev* d, double* y, double* side, int flags, hipStream_t st);
 void launch_fixup(const TankDev& h, const TankDev* d, float* y, float* side, int flags, hipStream_t st);

@@ -1202,6 +1202,15 @@ static void gather_t(sem_mesh* M, const GmresCfg& c, int op, const float* u, flo
   launch_gather(M->hd, M->dtank, op, u, y, side, flags, c.gstore, st);
 }
 
+static void stiff_timed_launch(sem_mesh* M, const GmresCfg&, const double* u, double* y, double* side, int flags,
+                               hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+  launch_stiff_mfma_timed(M->hd, M->dtank, u, y, side, flags, e0, e1, st);
+}
+static void stiff_timed_launch(sem_mesh* M, const GmresCfg& c, const float* u, float* y, float* side, int flags,
+                               hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+  launch_stiff_mfma_timed(M->hd, M->dtank, u, y, side, flags, c.gstore, e0, e1, st);
+}
+
 // Stiffness application inside the Krylov loop, bracketed by timing events
 // when enabled (the fix-up of shared lines runs after the end event).
 template <typename T>
@@ -1218,9 +1227,14 @@ static sem_status stiff_timed(sem_mesh* M, const GmresCfg& cfg, const T* u, T* y
     M->kt_ev.push_back(e);
   }
   auto& e = M->kt_ev[M->kt_used++];
-  HIPCHK(hipEventRecord(e.first, st));
-  gather_t(M, cfg, cfg.op, u, y, side, flags | F_NOFIX, st);
-  HIPCHK(hipEventRecord(e.second, st));
+  if (M->hd.use_mfma) {
+    // events stamped by the kernel's own dispatch
+    stiff_timed_launch(M, cfg, u, y, side, flags, e.first, e.second, st);
+  } else {
+    HIPCHK(hipEventRecord(e.first, st));
+    gather_t(M, cfg, cfg.op, u, y, side, flags | F_NOFIX, st);
+    HIPCHK(hipEventRecord(e.second, st));
+  }
   launch_fixup(M->hd, M->dtank, y, side, flags, st);
   return SEM_OK;
 }

@@ -17,6 +17,7 @@ GPU.
 """
 import argparse
 import json
+import sys
 import time
 from dataclasses import dataclass, field
 
@@ -108,7 +109,7 @@ class GpuBackend:
 
 
 class Server:
-    def __init__(self, backend, state_fn, memory_budget=64 << 30, max_slots=64, clock=None):
+    def __init__(self, backend, state_fn, memory_budget=64 << 30, max_slots=64, clock=None, log=None):
         self.backend = backend
         self.state_fn = state_fn
         self.memory_budget = int(memory_budget)
@@ -118,6 +119,7 @@ class Server:
         self.in_use = 0
         self.tank_steps = 0
         self.ticks = 0
+        self.log = log          # optional callable(str): one line per retired request
 
     def submit(self, req):
         req.footprint, req.probe = self.backend.footprint(req.spec)
@@ -155,6 +157,8 @@ class Server:
         self.in_use -= r.footprint
         self.running.remove(r)
         self.finished.append(r)
+        if self.log:
+            self.log(f"request {r.rid} {r.status} at {now:.2f}s, latency {r.latency:.2f}s {r.error}")
 
     def run(self, requests, t0=None, realtime=True):
         """Serve requests whose `arrival` times are relative to the start."""
@@ -221,20 +225,20 @@ def main():
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--streams", type=int, default=8)
     ap.add_argument("--max-nx", type=int, default=None)
+    ap.add_argument("--quiet", action="store_true", help="no per-request lines on stderr")
     ap.add_argument("--sequential-fp64", action="store_true",
                     help="baseline: one tank at a time, plain FP64, arrivals ignored")
     a = ap.parse_args()
     from . import lib
     from . import workloads as wl
     reqs = make_requests(a.requests, a.rate, a.steps, max_nx=a.max_nx)
+    log = None if a.quiet else (lambda line: print(line, file=sys.stderr, flush=True))
     if a.sequential_fp64:
         be = GpuBackend(nstreams=1, opts=lib.default_opts(rtol=1e-8, warm_start=1, lookahead=3))
-        srv = Server(be, wl.batch_tank_state, max_slots=1)
-        for r in reqs:
-            r.arrival = 0.0
+        srv = Server(be, wl.batch_tank_state, max_slots=1, log=log)
     else:
         be = GpuBackend(nstreams=a.streams)
-        srv = Server(be, wl.batch_tank_state, max_slots=a.slots)
+        srv = Server(be, wl.batch_tank_state, max_slots=a.slots, log=log)
     rep = srv.run(reqs)
     rep.update(mode="sequential_fp64" if a.sequential_fp64 else "batched_mixed", rate=a.rate, steps=a.steps)
     print(json.dumps(rep))

@@ -205,9 +205,9 @@ def bar_irregular_state(xs, spec):
 
 
 # ------------------------------------------------------------ batches
-def batch_tank_specs(count=256, seed=SEED_BASE + 4, steps=200, rtol=1e-10, bar_fraction=0.0):
+def batch_tank_specs(count=256, seed=SEED_BASE + 4, steps=200, rtol=1e-10, bar_fraction=0.0, max_frac=0.9):
     """Random periodic tanks: nx ~ U{16..1024}, nz ~ U{2,4,8}, P ~ U{4,6,8},
-    kh ~ U[0.5, 3], H/L ~ U[0.01, 0.9] of the limiting steepness, about 8
+    kh ~ U[0.5, 3], H/L ~ U[0.01, max_frac] of the limiting steepness, about 8
     elements per wavelength (L = m 2 pi / k, m = max(1, nx // 8))."""
     rng = np.random.default_rng(seed)
     specs = []
@@ -216,7 +216,7 @@ def batch_tank_specs(count=256, seed=SEED_BASE + 4, steps=200, rtol=1e-10, bar_f
         nz = int(rng.choice([2, 4, 8]))
         P = int(rng.choice([4, 6, 8]))
         kh = float(rng.uniform(0.5, 3.0))
-        frac = float(rng.uniform(0.01, 0.9))
+        frac = float(rng.uniform(0.01, max_frac))
         bar = bool(rng.uniform() < bar_fraction)
         crest = float(rng.uniform(0.3, 0.6))
         h = 1.0
