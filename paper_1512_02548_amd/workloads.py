@@ -205,10 +205,12 @@ def bar_irregular_state(xs, spec):
 
 
 # ------------------------------------------------------------ batches
-def batch_tank_specs(count=256, seed=SEED_BASE + 4, steps=200, rtol=1e-10, bar_fraction=0.0, max_frac=0.9):
+def batch_tank_specs(count=256, seed=SEED_BASE + 4, steps=200, rtol=1e-10, bar_fraction=0.0, max_frac=0.9,
+                     filter_modes=2, filter_sigma=0.995):
     """Random periodic tanks: nx ~ U{16..1024}, nz ~ U{2,4,8}, P ~ U{4,6,8},
     kh ~ U[0.5, 3], H/L ~ U[0.01, max_frac] of the limiting steepness, about 8
-    elements per wavelength (L = m 2 pi / k, m = max(1, nx // 8))."""
+    elements per wavelength (L = m 2 pi / k, m = max(1, nx // 8)); the modal
+    filter scales the top `filter_modes` modes by `filter_sigma` once per step."""
     rng = np.random.default_rng(seed)
     specs = []
     for i in range(count):
@@ -225,7 +227,7 @@ def batch_tank_specs(count=256, seed=SEED_BASE + 4, steps=200, rtol=1e-10, bar_f
         L = mwav * 2 * np.pi / k
         c = omega_linear(k, h) / k
         specs.append(TankSpec(nx=nx, nz=nz, P=P, length=L, periodic=True,
-                              Pf=int(np.ceil(1.5 * P)), filter_ic=P - 1, filter_sigma=0.995,
+                              Pf=int(np.ceil(1.5 * P)), filter_ic=P + 1 - filter_modes, filter_sigma=filter_sigma,
                               dt=courant_dt(L, nx, P, c), steps=steps, rtol=rtol,
                               name=f"tank{i}_{nx}x{nz}_P{P}",
                               params=dict(k=k, h=h, HL=frac * limiting_steepness(kh), modes=8,
