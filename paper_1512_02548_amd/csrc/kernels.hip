@@ -408,13 +408,31 @@ __device__ inline bool last_block(int32_t* counter) {
 
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, const T* __restrict__ w,
+k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, T* __restrict__ w,
              double* __restrict__ part, int ldp, double* __restrict__ out, int64_t chunk,
-             int32_t* __restrict__ counter, const KrylovState* __restrict__ gate) {
+             int32_t* __restrict__ counter, const KrylovState* __restrict__ gate,
+             const TankDev* __restrict__ fixd, const T* __restrict__ side) {
   __shared__ double red[4][kMaxVec];
   if (gate && gate->done) return;
   const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (fixd) {
+    // w is an operator output whose shared-line contributions are still in
+    // the side buffer (the fix-up pass, done here for the elements this
+    // workgroup owns)
+    const TankDev& d = *fixd;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const int64_t c = i / d.nc;
+      const int ql = (int)(i - c * d.nc);
+      if (ql >= d.nl) continue;
+      if (c == d.nx) {
+        w[i] = side[(size_t)(d.nb - 1) * d.nl + ql];   // the wall line has one contribution
+      } else if (c % d.cb == 0) {
+        const int bl = c > 0 ? (int)(c / d.cb) - 1 : (d.periodic ? d.nb - 1 : -1);
+        if (bl >= 0) w[i] += side[(size_t)bl * d.nl + ql];
+      }
+    }
+  }
   // eight vectors per pass, their loads issued together (clamped indices,
   // zero weights past nvec keep the loads unconditional)
   for (int k0 = 0; k0 < nvec; k0 += 8) {
@@ -1174,20 +1192,22 @@ void dot_layout(int64_t n, int* nchunk, int64_t* chunk) {
 
 template <typename T>
 static void dots_t(int64_t n, int nvec, const T* X, int64_t ldx, const T* w, double* part, int ldp, double* out,
-                   int32_t* counter, const KrylovState* gate, hipStream_t st) {
+                   int32_t* counter, const KrylovState* gate, const TankDev* fixd, const T* side, hipStream_t st) {
   int nc;
   int64_t chunk;
   dot_layout(n, &nc, &chunk);
-  hipLaunchKernelGGL(k_dots_fused<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, nvec, X, ldx, w, part, ldp, out,
-                     chunk, counter, gate);
+  hipLaunchKernelGGL(k_dots_fused<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, nvec, X, ldx, const_cast<T*>(w), part,
+                     ldp, out, chunk, counter, gate, fixd, side);
 }
 void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
-                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st) {
-  dots_t<double>(n, nvec, X, ldx, w, part, ldp, out, counter, gate, st);
+                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st, const TankDev* fixd,
+                 const double* side) {
+  dots_t<double>(n, nvec, X, ldx, w, part, ldp, out, counter, gate, fixd, side, st);
 }
 void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
-                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st) {
-  dots_t<float>(n, nvec, X, ldx, w, part, ldp, out, counter, gate, st);
+                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st, const TankDev* fixd,
+                 const float* side) {
+  dots_t<float>(n, nvec, X, ldx, w, part, ldp, out, counter, gate, fixd, side, st);
 }
 
 template <typename T>

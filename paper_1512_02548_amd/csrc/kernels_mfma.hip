@@ -16,110 +16,193 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "launch.hpp"
 #include "mfma.hpp"
 
 namespace sem {
 
+// Global-address-space views: pointers read from the argument block are
+// otherwise accessed through flat instructions.
+#define SEM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ inline const SEM_GLOBAL T* gview(const T* p) {
+  return (const SEM_GLOBAL T*)p;
+}
+
 template <typename T, typename GS>
-__device__ inline T load_g(const TankDev& d, int64_t i);
+struct GLoad;
 template <>
-__device__ inline double load_g<double, double>(const TankDev& d, int64_t i) { return d.G[i]; }
+struct GLoad<double, double> {
+  __device__ static double at(const void* G, int64_t i) { return gview((const double*)G)[i]; }
+};
 template <>
-__device__ inline float load_g<float, float>(const TankDev& d, int64_t i) { return d.G32[i]; }
+struct GLoad<float, float> {
+  __device__ static float at(const void* G, int64_t i) { return gview((const float*)G)[i]; }
+};
 struct BF16m {};
 template <>
-__device__ inline float load_g<float, BF16m>(const TankDev& d, int64_t i) {
-  return __uint_as_float(((uint32_t)d.G16[i]) << 16);
-}
+struct GLoad<float, BF16m> {
+  __device__ static float at(const void* G, int64_t i) {
+    return __uint_as_float(((uint32_t)gview((const uint16_t*)G)[i]) << 16);
+  }
+};
+
+// Everything the stiffness kernel reads, passed by value (the kernel-argument
+// segment) so that no argument costs a dependent load.
+template <typename T>
+struct StiffArgs {
+  const void* G;                  // factor copy in tile layout (T, or bfloat16 bits)
+  const T* opf;                   // operators in MFMA fragment order: stage 1 then stage 2
+  const int32_t* elem_loc;        // [2nz][NpP]
+  const int32_t* acc_cnt;         // [nc]
+  const int32_t* acc_ent;         // [nc][kMaxContrib]
+  const int32_t* is_surf_loc;     // [nc + nl]
+  const KrylovState* ks;          // cycle state (launches gated on done)
+  int32_t nx, nz, nc, nl, cb, tiles, periodic, pad;
+};
 
 template <typename T>
-__device__ inline const T* opmat(const TankDev& d, int which);
-template <>
-__device__ inline const double* opmat<double>(const TankDev& d, int w) {
-  return w == 0 ? d.Dr : w == 1 ? d.Ds : w == 2 ? d.MDr : d.MDs;
-}
-template <>
-__device__ inline const float* opmat<float>(const TankDev& d, int w) {
-  return w == 0 ? d.Dr32 : w == 1 ? d.Ds32 : w == 2 ? d.MDr32 : d.MDs32;
+static StiffArgs<T> stiff_args(const TankDev& h, const void* G, const T* opf, int ops_in_lds) {
+  StiffArgs<T> a;
+  a.G = G;
+  a.opf = opf;
+  a.elem_loc = h.elem_loc;
+  a.acc_cnt = h.acc_cnt;
+  a.acc_ent = h.acc_ent;
+  a.is_surf_loc = h.is_surf_loc;
+  a.ks = h.ks;
+  a.nx = h.nx;
+  a.nz = h.nz;
+  a.nc = h.nc;
+  a.nl = h.nl;
+  a.cb = h.cb;
+  a.tiles = h.T;
+  a.periodic = h.periodic;
+  a.pad = ops_in_lds;
+  return a;
 }
 
-template <int P, typename T, typename GS>
+// LDS: [operators 4 NpP^2 (if they fit)] [elem_loc 2nz NpP ints] [u region cb nc + nl]
+// [element outputs T 16 (NpP + 1): rows padded against bank conflicts]
+template <typename T>
+static size_t stiff_lds_layout(const TankDev& h, int ops_in_lds, size_t* o_loc, size_t* o_u, size_t* o_st) {
+  size_t off = ops_in_lds ? 4 * (size_t)h.NpP * h.NpP * sizeof(T) : 0;
+  *o_loc = off;
+  off += (size_t)2 * h.nz * h.NpP * sizeof(int32_t);
+  off = (off + 15) / 16 * 16;
+  *o_u = off;
+  off += ((size_t)h.cb * h.nc + h.nl) * sizeof(T);
+  off = (off + 15) / 16 * 16;
+  *o_st = off;
+  off += (size_t)h.T * 16 * (h.NpP + 1) * sizeof(T);
+  return off;
+}
+
+template <int P, typename T, typename GS, bool OPS_LDS>
 __global__ void __launch_bounds__(kBlockThreads)
-k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict__ y, T* __restrict__ side,
-             int flags) {
+k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T* __restrict__ side, int flags,
+             uint32_t o_loc, uint32_t o_u, uint32_t o_st) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
-  const TankDev& d = *td;
-  if ((flags & F_GATE) && d.ks->done) return;
   constexpr int Np = (P + 1) * (P + 2) / 2;
   constexpr int NpP = (Np + 15) / 16 * 16;
   constexpr int MT = NpP / 16;      // M-tiles per operator block
   constexpr int KS = NpP / 4;       // K-steps of stage 1
+  if ((flags & F_GATE) && gview(a.ks)->done) return;
   extern __shared__ unsigned char lds_raw[];
-  T* lds = reinterpret_cast<T*>(lds_raw);
+  T* lop = reinterpret_cast<T*>(lds_raw);                        // [4][NpP][NpP]
+  int32_t* lloc = reinterpret_cast<int32_t*>(lds_raw + o_loc);   // [2nz][NpP]
+  T* ureg = reinterpret_cast<T*>(lds_raw + o_u);                 // [cb nc + nl]
+  T* st3 = reinterpret_cast<T*>(lds_raw + o_st);                 // [T 16][NpP]
   const int b = blockIdx.x;
-  const int c0 = b * d.cb;
-  const int cbb = min(d.cb, d.nx - c0);
-  const int nc = d.nc, nl = d.nl, nz2 = 2 * d.nz;
+  const int c0 = b * a.cb;
+  const int cbb = min(a.cb, a.nx - c0);
+  const int nc = a.nc, nl = a.nl, nz2 = 2 * a.nz;
   const int nreg = cbb * nc + nl;
   const int EBb = cbb * nz2;
-  T* ureg = lds;                          // [cb*nc + nl]
-  T* st3 = ureg + (d.cb * nc + nl);       // [T*16][NpP]
-#pragma unroll 4
-  for (int q = threadIdx.x; q < nreg; q += blockDim.x) {
-    int lc = q / nc, ql = q - lc * nc;
-    int64_t gi;
-    if (lc < cbb) gi = (int64_t)(c0 + lc) * nc + ql;
-    else gi = (ql < nl) ? ((c0 + cbb < d.nx) ? (int64_t)(c0 + cbb) * nc : (d.periodic ? 0 : (int64_t)d.nx * nc)) + ql : -1;
-    ureg[q] = gi >= 0 ? u[gi] : T(0);
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int ntile = (EBb + 15) >> 4;
-  const T* Dr = opmat<T>(d, 0);
-  const T* Ds = opmat<T>(d, 1);
-  const T* MDr = opmat<T>(d, 2);
-  const T* MDs = opmat<T>(d, 3);
+  // geometric factors of this wave's first tile, requested before anything
+  // else (tile layout: one (component, M-tile, v) group is 64 consecutive values)
+  T g[3][MT][4];
+  auto load_g = [&](int t) {
+    const int64_t gbase = (((int64_t)b * a.tiles + t) * 3) * (int64_t)NpP * 16;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          g[c][mt][v] = GLoad<T, GS>::at(a.G, gbase + (int64_t)c * NpP * 16 + (mt * 16 + v * 4) * 16 + lane);
+  };
+  // prefetching holds the factors live across stage 1; FP64 with three
+  // M-tiles (P = 8) would run out of registers, it loads them after stage 1
+  constexpr bool kPrefetch = MT <= 2 || sizeof(T) == sizeof(float);
+  if (kPrefetch && wave < ntile) load_g(wave);
+  // stage operators, element tables and the input region in LDS
+  if constexpr (OPS_LDS) {
+    // 16-byte loads; 4 NpP^2 is a multiple of 16 values
+    constexpr int kVec = 16 / sizeof(T);
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    using V = typename std::conditional<sizeof(T) == 8, dv2, f4>::type;
+    const SEM_GLOBAL V* src = (const SEM_GLOBAL V*)gview(a.opf);
+    V* dst = reinterpret_cast<V*>(lop);
+#pragma unroll
+    for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
+  }
+  for (int i = threadIdx.x; i < nz2 * NpP; i += blockDim.x) lloc[i] = gview(a.elem_loc)[i];
+  const int64_t rbase = (c0 + cbb < a.nx) ? (int64_t)(c0 + cbb) * nc : (a.periodic ? 0 : (int64_t)a.nx * nc);
+#pragma unroll 4
+  for (int q = threadIdx.x; q < nreg; q += blockDim.x) {
+    const int lc = q / nc, ql = q - lc * nc;
+    const int64_t gi = (lc < cbb) ? (int64_t)(c0 + lc) * nc + ql : rbase + ql;
+    ureg[q] = (lc < cbb || ql < nl) ? gview(u)[gi] : T(0);
+  }
+  __syncthreads();
+  // operator fragments: LDS copies, or global memory when they do not fit
+  auto opv = [&](int i) -> T {
+    if constexpr (OPS_LDS) return lop[i];
+    else return gview(a.opf)[i];
+  };
+  constexpr int kS2 = 2 * NpP * NpP;   // start of the stage-2 fragments
+  constexpr int NS = NpP + 1;          // padded row stride of the element outputs
   for (int t = wave; t < ntile; t += kBlockThreads / 64) {
     const int eb = t * 16 + col;
     const bool valid = eb < EBb;
     const int lc = valid ? eb / nz2 : 0;
     const int jt = valid ? eb - lc * nz2 : 0;
-    const int32_t* loc = d.elem_loc + jt * NpP;
-    // stage 1
+    const int32_t* loc = lloc + jt * NpP;
+    // stage 1: [Dr; Ds] U
     V4 acc[2 * MT];
 #pragma unroll
     for (int i = 0; i < 2 * MT; ++i) acc[i] = V4{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int k = 4 * s + grp;
-      T bval = (valid && k < Np) ? ureg[lc * nc + loc[k]] : T(0);
+      const T bval = (valid && k < Np) ? ureg[lc * nc + loc[k]] : T(0);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        const int row = 16 * mt + col;
-        acc[mt] = MF::op(Dr[row * NpP + k], bval, acc[mt]);
-        acc[MT + mt] = MF::op(Ds[row * NpP + k], bval, acc[MT + mt]);
+        const int f = ((mt * KS + s) * 2) * 64 + lane;
+        acc[mt] = MF::op(opv(f), bval, acc[mt]);
+        acc[MT + mt] = MF::op(opv(f + 64), bval, acc[MT + mt]);
       }
     }
-    // pointwise mixing with the geometric factors (tile layout: contiguous per (comp, mt, v))
-    const int64_t gbase = (((int64_t)b * d.T + t) * 3) * (int64_t)NpP * 16;
+    if (!kPrefetch) load_g(t);
+    // pointwise mixing with the geometric factors
     T fr[MT][4], fs[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        // FP64 copy: natural rows, node 16mt+4v+g at row 16mt+4v+g -> contiguous in lane
-        // FP32 copies: perm rows, node 16mt+4g+v at row 16mt+4v+g -> contiguous in lane
-        const int64_t o = (int64_t)(mt * 16 + v * 4) * 16 + lane;
-        T grr = load_g<T, GS>(d, gbase + o);
-        T grs = load_g<T, GS>(d, gbase + (int64_t)NpP * 16 + o);
-        T gss = load_g<T, GS>(d, gbase + 2 * (int64_t)NpP * 16 + o);
-        T tr = acc[mt][v], ts = acc[MT + mt][v];
-        fr[mt][v] = grr * tr + grs * ts;
-        fs[mt][v] = grs * tr + gss * ts;
+        const T tr = acc[mt][v], ts = acc[MT + mt][v];
+        fr[mt][v] = g[0][mt][v] * tr + g[1][mt][v] * ts;
+        fs[mt][v] = g[1][mt][v] * tr + g[2][mt][v] * ts;
       }
+    // the next tile's factors stream in during stage 2
+    if (kPrefetch && t + kBlockThreads / 64 < ntile) load_g(t + kBlockThreads / 64);
     // stage 2: K index (blk, mt, v, grp) -> operator row 16 mt + row(v, grp)
     V4 out[MT];
 #pragma unroll
@@ -128,70 +211,62 @@ k_stiff_mfma(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restr
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int krow = 16 * mt + MF::row(v, grp);
 #pragma unroll
         for (int mo = 0; mo < MT; ++mo) {
-          const int icol = 16 * mo + col;
-          out[mo] = MF::op(MDr[krow * NpP + icol], fr[mt][v], out[mo]);
-          out[mo] = MF::op(MDs[krow * NpP + icol], fs[mt][v], out[mo]);
+          const int f = kS2 + (((mt * 4 + v) * MT + mo) * 2) * 64 + lane;
+          out[mo] = MF::op(opv(f), fr[mt][v], out[mo]);
+          out[mo] = MF::op(opv(f + 64), fs[mt][v], out[mo]);
         }
       }
     if (valid) {
 #pragma unroll
       for (int mo = 0; mo < MT; ++mo)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 16 * mo + MF::row(v, grp);
-          st3[eb * NpP + i] = out[mo][v];
-        }
+        for (int v = 0; v < 4; ++v) st3[eb * NS + 16 * mo + MF::row(v, grp)] = out[mo][v];
     }
   }
   __syncthreads();
   // node sums in a fixed order (same table as the reference kernel)
   const T sgn = (flags & F_NEG) ? T(-1) : T(1);
   const int nown = cbb * nc;
+  // unrolled so that the table loads of several nodes are in flight together
+#pragma unroll 4
   for (int q = threadIdx.x; q < nown + nl; q += blockDim.x) {
-    int lc = q / nc, ql = q - lc * nc;
-    T a = 0;
+    const int lc = q / nc, ql = q - lc * nc;
+    if (lc >= cbb && ql >= nl) continue;
+    // the node's contributions: count and up to kMaxContrib entries (two 16-byte loads)
+    const int cnt = gview(a.acc_cnt)[ql];
+    int ent[kMaxContrib];
+#pragma unroll
+    for (int k = 0; k < kMaxContrib; ++k) ent[k] = gview(a.acc_ent)[(size_t)ql * kMaxContrib + k];
+    const bool masked = (flags & F_MASK_SURF) && gview(a.is_surf_loc)[ql];
+    T acc = 0;
     if (lc < cbb) {
-      // the node's contributions: count and up to kMaxContrib table entries,
-      // loaded together (two 16-byte loads)
-      const int cnt = d.acc_cnt[ql];
-      const int4* e4 = reinterpret_cast<const int4*>(d.acc_ent + (size_t)ql * kMaxContrib);
-      const int4 ea = e4[0], eb = e4[1];
-      const int ent[kMaxContrib] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
 #pragma unroll
       for (int k = 0; k < kMaxContrib; ++k) {
         if (k >= cnt) break;
         const int e = ent[k];
-        const int prev = (e >> 30) & 1;
-        const int off = e & 0x3fffffff;
-        if (prev) {
+        const int off = e & 0x3fffffff;             // element-in-column * NpP + node
+        const int pos = (off / NpP) * NS + off % NpP;
+        if ((e >> 30) & 1) {
           if (lc == 0) continue;  // previous column belongs to the left block
-          a += st3[(lc - 1) * nz2 * NpP + off];
+          acc += st3[(lc - 1) * nz2 * NS + pos];
         } else {
-          a += st3[lc * nz2 * NpP + off];
+          acc += st3[lc * nz2 * NS + pos];
         }
       }
-      a *= sgn;
-      if ((flags & F_MASK_SURF) && d.is_surf_loc[ql]) a = T(0);
-      y[(int64_t)(c0 + lc) * nc + ql] = a;
+      y[(int64_t)(c0 + lc) * nc + ql] = masked ? T(0) : acc * sgn;
     } else {
-      if (ql >= nl) continue;
-      const int cnt = d.acc_cnt[ql];
-      const int4* e4 = reinterpret_cast<const int4*>(d.acc_ent + (size_t)ql * kMaxContrib);
-      const int4 ea = e4[0], eb = e4[1];
-      const int ent[kMaxContrib] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+      // right line: contributions of the block's last column
 #pragma unroll
       for (int k = 0; k < kMaxContrib; ++k) {
         if (k >= cnt) break;
         const int e = ent[k];
         if (((e >> 30) & 1) == 0) continue;
-        a += st3[(cbb - 1) * nz2 * NpP + (e & 0x3fffffff)];
+        const int off = e & 0x3fffffff;
+        acc += st3[(cbb - 1) * nz2 * NS + (off / NpP) * NS + off % NpP];
       }
-      a *= sgn;
-      if ((flags & F_MASK_SURF) && d.is_surf_loc[ql]) a = T(0);
-      side[(size_t)b * nl + ql] = a;
+      side[(size_t)b * nl + ql] = masked ? T(0) : acc * sgn;
     }
   }
 }
@@ -214,8 +289,16 @@ __global__ void k_mfma_probe(double* out64, float* out32) {
   }
 }
 
+// operators go to LDS unless they would take more than 40 KiB
+template <typename T>
+static int stiff_ops_in_lds(const TankDev& h) {
+  return 4 * (size_t)h.NpP * h.NpP * sizeof(T) <= 40 * 1024 ? 1 : 0;
+}
+
 size_t stiff_mfma_lds_bytes(const TankDev& h, size_t word) {
-  return word * ((size_t)h.cb * h.nc + h.nl + (size_t)h.T * 16 * h.NpP);
+  size_t a, b, c;
+  return word == sizeof(double) ? stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c)
+                                : stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c);
 }
 
 #define SEM_MP_CASE(V, ...) \
@@ -230,42 +313,60 @@ size_t stiff_mfma_lds_bytes(const TankDev& h, size_t word) {
     SEM_MP_CASE(7, __VA_ARGS__) SEM_MP_CASE(8, __VA_ARGS__) default : break;                               \
   }
 
+// gstore: 0 = FP64 factors (T = double), 1 = FP32, 2 = bfloat16
+template <typename T, typename GS>
+static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T* side, int flags, hipEvent_t e0,
+                         hipEvent_t e1, hipStream_t st) {
+  const int inl = stiff_ops_in_lds<T>(h);
+  size_t ol, ou, os;
+  const size_t lds = stiff_lds_layout<T>(h, inl, &ol, &ou, &os);
+  const void* G;
+  const T* opf;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    G = h.G;
+    opf = h.opf;
+  } else {
+    G = sizeof(GS) == sizeof(float) ? (const void*)h.G32 : (const void*)h.G16;
+    opf = h.opf32;
+  }
+  const StiffArgs<T> a = stiff_args<T>(h, G, opf, inl);
+#define SEM_SL(INL)                                                                                           \
+  if (e0) {                                                                                                  \
+    SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL>), dim3(h.nb), dim3(kBlockThreads),  \
+                                             (uint32_t)lds, st, e0, e1, 0, a, u, y, side, flags, (uint32_t)ol, \
+                                             (uint32_t)ou, (uint32_t)os));                                     \
+  } else {                                                                                                   \
+    SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL>), dim3(h.nb), dim3(kBlockThreads), lds, \
+                                          st, a, u, y, side, flags, (uint32_t)ol, (uint32_t)ou, (uint32_t)os)); \
+  }
+  if (inl) {
+    SEM_SL(true)
+  } else {
+    SEM_SL(false)
+  }
+#undef SEM_SL
+}
+
 void launch_stiff_mfma(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, int flags,
                        hipStream_t st) {
-  size_t lds = stiff_mfma_lds_bytes(h, sizeof(double));
-  SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, double, double>), dim3(h.nb), dim3(kBlockThreads), lds, st,
-                                        d, u, y, side, flags));
+  stiff_launch<double, double>(h, d, u, y, side, flags, nullptr, nullptr, st);
 }
 void launch_stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
                        int gstore, hipStream_t st) {
-  size_t lds = stiff_mfma_lds_bytes(h, sizeof(float));
-  if (gstore == 2) {
-    SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, float, BF16m>), dim3(h.nb), dim3(kBlockThreads), lds, st,
-                                          d, u, y, side, flags));
-  } else {
-    SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, float, float>), dim3(h.nb), dim3(kBlockThreads), lds, st,
-                                          d, u, y, side, flags));
-  }
+  if (gstore == 2) stiff_launch<float, BF16m>(h, d, u, y, side, flags, nullptr, nullptr, st);
+  else stiff_launch<float, float>(h, d, u, y, side, flags, nullptr, nullptr, st);
 }
 
 // Same launches with start/stop events taken from the dispatch itself (no
 // marker packets around the kernel): used to time the kernel inside solves.
 void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, int flags,
                              hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
-  size_t lds = stiff_mfma_lds_bytes(h, sizeof(double));
-  SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, double, double>), dim3(h.nb), dim3(kBlockThreads), lds,
-                                           st, e0, e1, 0, d, u, y, side, flags));
+  stiff_launch<double, double>(h, d, u, y, side, flags, e0, e1, st);
 }
 void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
                              int gstore, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
-  size_t lds = stiff_mfma_lds_bytes(h, sizeof(float));
-  if (gstore == 2) {
-    SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, float, BF16m>), dim3(h.nb), dim3(kBlockThreads), lds,
-                                             st, e0, e1, 0, d, u, y, side, flags));
-  } else {
-    SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, float, float>), dim3(h.nb), dim3(kBlockThreads), lds,
-                                             st, e0, e1, 0, d, u, y, side, flags));
-  }
+  if (gstore == 2) stiff_launch<float, BF16m>(h, d, u, y, side, flags, e0, e1, st);
+  else stiff_launch<float, float>(h, d, u, y, side, flags, e0, e1, st);
 }
 
 void launch_mfma_probe(double* out64, float* out32, hipStream_t st) {

@@ -42,10 +42,15 @@ void launch_scatter_surface(const TankDev& h, const TankDev* d, const double* ph
                             hipStream_t st);
 void launch_gather_surface(const TankDev& h, const TankDev* d, const double* u, double* out, hipStream_t st);
 void dot_layout(int64_t n, int* nchunk, int64_t* chunk);
+// With fixd (the tank) and side: w is an operator output whose shared-line
+// contributions are still in `side`; the kernel adds them (and stores w)
+// before the products.
 void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double* w, double* part, int ldp,
-                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st);
+                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st,
+                 const TankDev* fixd = nullptr, const double* side = nullptr);
 void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
-                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st);
+                 double* out, int32_t* counter, const KrylovState* gate, hipStream_t st,
+                 const TankDev* fixd = nullptr, const float* side = nullptr);
 void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
                         KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st);
 void launch_orth_givens(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,

@@ -303,9 +303,30 @@ static sem_status build_mesh(sem_mesh* M) {
       Mat I = r1.interp_to({2.0 * nodeq[((size_t)t * NpP + k) * 2] - 1.0});
       for (int q = 0; q <= P; ++q) colw[((size_t)t * NpP + k) * (P + 1) + q] = I[q];
     }
-  // block decomposition
-  M->cb = std::max(1, (32 + 2 * nz - 1) / (2 * nz));
-  M->cb = std::min(M->cb, nx);
+  // block decomposition: a workgroup takes cb whole columns.  Up to four
+  // 16-element MFMA tiles per workgroup (one per wavefront) while the tank
+  // still gives at least 512 workgroups (two per CU); small tanks use one
+  // tile per workgroup for parallelism.  Both element kernels must fit their
+  // LDS (64 KiB): the reference kernel stages three element buffers, the
+  // matrix-core kernel the operators (FP64, when they fit in 40 KiB), the
+  // element table and one output buffer.
+  {
+    const int per_col = 2 * nz;
+    const double tiles_total = (double)nx * per_col / 16.0;
+    const int tt = std::max(1, std::min(4, (int)(tiles_total / 512.0)));
+    auto lds_ok = [&](int cb) {
+      const size_t EB = (size_t)cb * per_col, T = (EB + 15) / 16;
+      const size_t region = (size_t)cb * nc + nl;
+      const size_t ref = (region + 3 * EB * NpP) * sizeof(double);
+      const size_t ops = 4 * (size_t)NpP * NpP * sizeof(double);
+      const size_t mfma = (ops <= 40 * 1024 ? ops : 0) + (size_t)per_col * NpP * 4 + 32 + region * sizeof(double) +
+                          T * 16 * (NpP + 1) * sizeof(double);
+      return ref <= 65536 && mfma <= 65536;
+    };
+    int cb = std::max(1, (16 * tt) / per_col);
+    while (cb > 1 && !lds_ok(cb)) --cb;
+    M->cb = std::min(cb, nx);
+  }
   M->nb = (nx + M->cb - 1) / M->cb;
   M->EB = M->cb * 2 * nz;
   M->T = (M->EB + 15) / 16;
@@ -830,6 +851,36 @@ static sem_status build_mesh(sem_mesh* M) {
   put(M, "MDr32", tof(MDrp));
   put(M, "MDs32", tof(MDsp));
   put(M, "M32", tof(Mp));
+  // Operators of the matrix-core stiffness kernel in MFMA fragment order.
+  // Stage 1 (A = [Dr; Ds], 16x4 A tiles): [mt][s][op][lane] holds
+  // D_op[16 mt + l%16][4 s + l/16].  Stage 2 (A = (M D_op)^T): [mt][v][mo][op][lane]
+  // holds (M D_op)[16 mt + row(v, l/16)][16 mo + l%16], with the accumulator
+  // row map of the instruction: 4v + g for FP64, 4g + v for FP32.
+  {
+    const int MTt = NpP / 16, KSt = NpP / 4;
+    auto frag = [&](bool fp64) {
+      std::vector<double> f((size_t)4 * NpP * NpP, 0.0);
+      const std::vector<double>* D1[2] = {&Drp, &Dsp};
+      const std::vector<double>* D2[2] = {&MDrp, &MDsp};
+      size_t o = 0;
+      for (int mt = 0; mt < MTt; ++mt)
+        for (int st = 0; st < KSt; ++st)
+          for (int w = 0; w < 2; ++w)
+            for (int l = 0; l < 64; ++l) f[o++] = (*D1[w])[(size_t)(16 * mt + l % 16) * NpP + 4 * st + l / 16];
+      for (int mt = 0; mt < MTt; ++mt)
+        for (int v = 0; v < 4; ++v)
+          for (int mo = 0; mo < MTt; ++mo)
+            for (int w = 0; w < 2; ++w)
+              for (int l = 0; l < 64; ++l) {
+                const int g = l / 16;
+                const int row = fp64 ? 4 * v + g : 4 * g + v;
+                f[o++] = (*D2[w])[(size_t)(16 * mt + row) * NpP + 16 * mo + l % 16];
+              }
+      return f;
+    };
+    put(M, "opf", frag(true));
+    put(M, "opf32", tof(frag(false)));
+  }
   put(M, "elem_loc", M->elem_loc);
   put(M, "acc_cnt", M->acc_cnt);
   put(M, "acc_ent", M->acc_ent);
@@ -1043,6 +1094,8 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.Ds = at<double>(M, "Ds");
   h.MDr = at<double>(M, "MDr");
   h.MDs = at<double>(M, "MDs");
+  h.opf = at<double>(M, "opf");
+  h.opf32 = at<float>(M, "opf32");
   h.Mref = at<double>(M, "M");
   h.Dr32 = at<float>(M, "Dr32");
   h.Ds32 = at<float>(M, "Ds32");
@@ -1127,7 +1180,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   M->scal = at<double>(M, "scal");
   M->dtank = at<TankDev>(M, "tank");
   // every device array the kernels use must have been laid out
-  const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,
+  const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.opf, h.opf32, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,
                         h.acc_cnt, h.acc_ent, h.surf_loc, h.is_surf_loc, h.lay, h.nodeq, h.colw, h.pre_lap,
                         h.pre_mass, h.pre_lap32, h.M1, h.S1, h.Ifine, h.Mfine, h.Filt, h.pre1d, h.h, h.hx, h.G,
                         h.G32, h.G16, h.invd, h.status, h.ks, h.H, h.part, h.V, h.Zb, h.w, h.b, h.tmp, h.xs,
@@ -1216,6 +1269,7 @@ static void stiff_timed_launch(sem_mesh* M, const GmresCfg& c, const float* u, f
 template <typename T>
 static sem_status stiff_timed(sem_mesh* M, const GmresCfg& cfg, const T* u, T* y, T* side, int flags,
                               hipStream_t st) {
+  const bool nofix = (flags & F_NOFIX) != 0;   // the caller adds the side buffer itself
   if (!M->kt_on || cfg.op != OP_STIFF) {
     gather_t(M, cfg, cfg.op, u, y, side, flags, st);
     return SEM_OK;
@@ -1235,7 +1289,7 @@ static sem_status stiff_timed(sem_mesh* M, const GmresCfg& cfg, const T* u, T* y
     gather_t(M, cfg, cfg.op, u, y, side, flags | F_NOFIX, st);
     HIPCHK(hipEventRecord(e.second, st));
   }
-  launch_fixup(M->hd, M->dtank, y, side, flags, st);
+  if (!nofix) launch_fixup(M->hd, M->dtank, y, side, flags, st);
   return SEM_OK;
 }
 
@@ -1300,11 +1354,12 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       T* Zj = B.Z + (size_t)j * n;
       gather_t(M, cfg, cfg.pre, Vj, Zj, B.side, gflags, st);
       {
-        sem_status e = stiff_timed(M, cfg, Zj, B.w, B.side, gflags, st);
+        // the operator's shared-line fix-up is done inside the products below
+        sem_status e = stiff_timed(M, cfg, Zj, B.w, B.side, gflags | F_NOFIX, st);
         if (e) return e;
       }
       double* Hcol = h.H + (size_t)j * (m + 1);
-      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st);
+      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st, d, B.side);
       launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
       launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
       // wait while the device is more than `ahead` steps behind

@@ -85,6 +85,8 @@ struct TankDev {
   const float* MDr32;
   const float* MDs32;
   const float* Mref32;
+  const double* opf;              // [4 NpP^2] stiffness operators in MFMA fragment order (FP64 rows)
+  const float* opf32;             // the same for the FP32 accumulator row map
   // mesh tables
   const int32_t* elem_loc;        // [2nz][NpP] column-local node (< nc + nl), -1 = padding
   const int32_t* acc_cnt;         // [nc] number of contributions
