@@ -21,6 +21,8 @@
 // consecutive words.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "launch.hpp"
 #include "mfma.hpp"
 
@@ -238,6 +240,14 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   const int c0 = blockIdx.x * 16;
   const double inx = 1.0 / nx;
+  if (sd.fft_n1) {
+    // lines c0 .. c0+16 (wrapping) were transformed back by the FFT passes
+    for (int t = threadIdx.x; t < 17 * q; t += blockDim.x) {
+      const int cc = t / q, j = t - cc * q;
+      xl[t] = sd.XL[(size_t)((c0 + cc) % nx) * q + j];
+    }
+    __syncthreads();
+  } else {
   // inverse DFT for lines c0 .. c0+15: A[c][kk] = twiddle part (kk & 1) of mode
   // kk / 2 at line c, B[kk][j] = part (kk & 1) of x^_{kk/2}[j]
   {
@@ -297,6 +307,7 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
       }
       __syncthreads();
     }
+  }
   }
   // line values of the block's columns
   if (blockIdx.y == 0) {
@@ -363,7 +374,7 @@ k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   extern __shared__ double sh[];
   const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc;
   const int np = 3 * q + nI;
-  const int nb2 = (nx + 15) / 16;
+  const int nb2 = sd.nwp;
   double* in = sh;   // [np]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double inx = 1.0 / nx;
@@ -419,6 +430,269 @@ k_sd_wall_modes(const TankDev* __restrict__ td, int which, int gate) {
   }
 }
 
+// ------------------------------------------------------------ four-step transforms
+// nx = n1 n2, column c = n2 c1 + c2, mode k = k1 + n1 k2, w_N = e^{-2 pi i/N}:
+//   g^_k = sum_c2 w_n2^{k2 c2} [ w_nx^{k1 c2} sum_c1 w_n1^{k1 c1} g_{n2 c1 + c2} ]
+//   x_c  = Re sum_k1 conj(w_n1)^{k1 c1} [ conj(w_nx)^{k1 c2} sum_k2 conj(w_n2)^{k2 c2} x^_k ] / nx
+// Each bracket is a batch of small products on MFMA (16x16x4, real operands,
+// complex values as pairs); twiddles come from the nx-point table.
+
+__device__ inline int sd_mod(int64_t a, int n) { return (int)(a % n); }
+
+// pass A (block per c2): FT[k1][c2][j] = w_nx^{k1 c2} sum_c1 w_n1^{k1 c1} g[n2 c1 + c2][j]
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sdf_a(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  const SDData& sd = d.sd[which];
+  extern __shared__ double sh[];
+  const int q = sd.q, nx = d.nx, nc = d.nc, n1 = sd.fft_n1, n2 = sd.fft_n2;
+  const int c2 = blockIdx.x;
+  const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16, nNT = (q + 15) / 16;
+  double* gl = sh;   // [4 KS][q] line right sides of columns n2 c1 + c2
+  for (int t = threadIdx.x; t < 4 * KS * q; t += blockDim.x) {
+    const int c1 = t / q, j = t - c1 * q;
+    double v = 0;
+    if (c1 < n1) {
+      const int c = n2 * c1 + c2, cm = c == 0 ? nx - 1 : c - 1;
+      v = (double)r[(int64_t)c * nc + j];
+      if (sd.wall && c == 0) v += (double)r[(int64_t)nx * nc + j];
+      v -= sd.TL[(size_t)c * q + j] + sd.TR[(size_t)cm * q + j];
+    }
+    gl[t] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  for (int pr = wv; pr < nMT * nNT; pr += kWaves) {
+    const int mt = pr / nNT, nt = pr - mt * nNT;
+    const int k1 = 16 * mt + col, j = 16 * nt + col;
+    V4 ar = V4{0, 0, 0, 0}, ai = V4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int s = 0; s < KS; ++s) {
+      const int c1 = 4 * s + grp;
+      T wr = T(0), wi = T(0);
+      if (k1 < n1 && c1 < n1) {
+        const int m = sd_mod((int64_t)k1 * c1, n1) * n2;
+        wr = T(d.twid[2 * m]);
+        wi = T(d.twid[2 * m + 1]);
+      }
+      const T b = j < q ? T(gl[c1 * q + j]) : T(0);
+      ar = MF::op(wr, b, ar);
+      ai = MF::op(wi, b, ai);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k1o = 16 * mt + MF::row(v, grp);
+      if (k1o >= n1 || j >= q) continue;
+      const int m = sd_mod((int64_t)k1o * c2, nx);
+      const double tr = d.twid[2 * m], ti = d.twid[2 * m + 1];
+      const double yr = (double)ar[v], yi = (double)ai[v];
+      const size_t o = (((size_t)k1o * n2 + c2) * q + j) * 2;
+      sd.FT[o] = yr * tr - yi * ti;
+      sd.FT[o + 1] = yr * ti + yi * tr;
+    }
+  }
+}
+
+// pass B (block per k1): FG[k1 + n1 k2][j] = sum_c2 w_n2^{k2 c2} FT[k1][c2][j]
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sdf_b(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  const SDData& sd = d.sd[which];
+  const int q = sd.q, n1 = sd.fft_n1, n2 = sd.fft_n2;
+  const int k1 = blockIdx.x;
+  const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16, nNT = (q + 15) / 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const double* ft = sd.FT + (size_t)k1 * n2 * q * 2;
+  for (int pr = wv; pr < nMT * nNT; pr += kWaves) {
+    const int mt = pr / nNT, nt = pr - mt * nNT;
+    const int k2 = 16 * mt + col, j = 16 * nt + col;
+    V4 gr = V4{0, 0, 0, 0}, gi = V4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int s = 0; s < KS; ++s) {
+      const int c2 = 4 * s + grp;
+      T wr = T(0), wi = T(0);
+      if (k2 < n2 && c2 < n2) {
+        const int m = sd_mod((int64_t)k2 * c2, n2) * n1;
+        wr = T(d.twid[2 * m]);
+        wi = T(d.twid[2 * m + 1]);
+      }
+      T br = T(0), bi = T(0);
+      if (c2 < n2 && j < q) {
+        br = T(ft[((size_t)c2 * q + j) * 2]);
+        bi = T(ft[((size_t)c2 * q + j) * 2 + 1]);
+      }
+      gr = MF::op(wr, br, gr);
+      gr = MF::op(-wi, bi, gr);
+      gi = MF::op(wr, bi, gi);
+      gi = MF::op(wi, br, gi);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k2o = 16 * mt + MF::row(v, grp);
+      if (k2o >= n2 || j >= q) continue;
+      const size_t o = (((size_t)k1 + (size_t)n1 * k2o) * q + j) * 2;
+      sd.FG[o] = (double)gr[v];
+      sd.FG[o + 1] = (double)gi[v];
+    }
+  }
+}
+
+// per-mode solves x^_k = S^_k^{-1} g^_k (thread per mode and row; each block
+// holds 256 / q whole modes and, for walls, adds its share of lines nx-1 and 0)
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sdf_solve(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  const SDData& sd = d.sd[which];
+  extern __shared__ double sh[];
+  const int q = sd.q, nx = d.nx;
+  const int ml = max(1, kBlockThreads / q);
+  const int t = threadIdx.x;
+  const int kk = t / q, i = t - kk * q;
+  const int k = blockIdx.x * ml + kk;
+  double xr = 0, xi = 0;
+  const bool live = kk < ml && k < nx;
+  if (live) {
+    const T* S = SdMat<T>::Shat(sd) + (size_t)k * q * q * 2;
+    const double* g = sd.FG + (size_t)k * q * 2;
+#pragma unroll 8
+    for (int j = 0; j < q; ++j) {
+      const double sr = (double)S[((size_t)j * q + i) * 2], si = (double)S[((size_t)j * q + i) * 2 + 1];
+      const double gr = g[2 * j], gi = g[2 * j + 1];
+      xr += sr * gr - si * gi;
+      xi += sr * gi + si * gr;
+    }
+    sd.XH[((size_t)k * q + i) * 2] = xr;
+    sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
+  }
+  if (!sd.wall) return;
+  sh[2 * t] = live ? xr : 0.0;
+  sh[2 * t + 1] = live ? xi : 0.0;
+  __syncthreads();
+  const int a0 = nx - 1;
+  for (int u = threadIdx.x; u < 2 * q; u += blockDim.x) {
+    const int ln = u / q, j = u - ln * q;
+    double acc = 0;
+    for (int m2 = 0; m2 < ml; ++m2) {
+      const int km = blockIdx.x * ml + m2;
+      if (km >= nx) break;
+      const double hr = sh[2 * (m2 * q + j)], hi = sh[2 * (m2 * q + j) + 1];
+      if (ln == 0) {
+        const int mm = sd_mod((int64_t)km * a0, nx);
+        acc += hr * d.twid[2 * mm] + hi * d.twid[2 * mm + 1];
+      } else {
+        acc += hr;
+      }
+    }
+    sd.WP[((size_t)blockIdx.x * 2 + ln) * q + j] = acc;
+  }
+}
+
+// pass C (block per k1): FT[c2][k1][j] = conj(w_nx)^{k1 c2} sum_k2 conj(w_n2)^{k2 c2} x^[k1 + n1 k2][j]
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sdf_c(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  const SDData& sd = d.sd[which];
+  const int q = sd.q, nx = d.nx, n1 = sd.fft_n1, n2 = sd.fft_n2;
+  const int k1 = blockIdx.x;
+  const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16, nNT = (q + 15) / 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  for (int pr = wv; pr < nMT * nNT; pr += kWaves) {
+    const int mt = pr / nNT, nt = pr - mt * nNT;
+    const int c2 = 16 * mt + col, j = 16 * nt + col;
+    V4 ur = V4{0, 0, 0, 0}, ui = V4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int s = 0; s < KS; ++s) {
+      const int k2 = 4 * s + grp;
+      T wr = T(0), wi = T(0);   // conj(w_n2)^{k2 c2} = (twr, -twi)
+      if (c2 < n2 && k2 < n2) {
+        const int m = sd_mod((int64_t)k2 * c2, n2) * n1;
+        wr = T(d.twid[2 * m]);
+        wi = T(-d.twid[2 * m + 1]);
+      }
+      T br = T(0), bi = T(0);
+      if (k2 < n2 && j < q) {
+        const size_t o = (((size_t)k1 + (size_t)n1 * k2) * q + j) * 2;
+        br = T(sd.XH[o]);
+        bi = T(sd.XH[o + 1]);
+      }
+      ur = MF::op(wr, br, ur);
+      ur = MF::op(-wi, bi, ur);
+      ui = MF::op(wr, bi, ui);
+      ui = MF::op(wi, br, ui);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c2o = 16 * mt + MF::row(v, grp);
+      if (c2o >= n2 || j >= q) continue;
+      const int m = sd_mod((int64_t)k1 * c2o, nx);
+      const double tr = d.twid[2 * m], ti = -d.twid[2 * m + 1];   // conj(w_nx)^{k1 c2}
+      const double a = (double)ur[v], b = (double)ui[v];
+      const size_t o = (((size_t)c2o * n1 + k1) * q + j) * 2;
+      sd.FT[o] = a * tr - b * ti;
+      sd.FT[o + 1] = a * ti + b * tr;
+    }
+  }
+}
+
+// pass D (block per c2): XL[n2 c1 + c2][j] = Re sum_k1 conj(w_n1)^{k1 c1} FT[c2][k1][j] / nx
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sdf_d(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  const SDData& sd = d.sd[which];
+  const int q = sd.q, nx = d.nx, n1 = sd.fft_n1, n2 = sd.fft_n2;
+  const int c2 = blockIdx.x;
+  const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16, nNT = (q + 15) / 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const double* ft = sd.FT + (size_t)c2 * n1 * q * 2;
+  const double inx = 1.0 / nx;
+  for (int pr = wv; pr < nMT * nNT; pr += kWaves) {
+    const int mt = pr / nNT, nt = pr - mt * nNT;
+    const int c1 = 16 * mt + col, j = 16 * nt + col;
+    V4 acc = V4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int s = 0; s < KS; ++s) {
+      const int k1 = 4 * s + grp;
+      T wr = T(0), wi = T(0);   // Re(conj(w) u) = twr ur + twi ui
+      if (c1 < n1 && k1 < n1) {
+        const int m = sd_mod((int64_t)k1 * c1, n1) * n2;
+        wr = T(d.twid[2 * m]);
+        wi = T(d.twid[2 * m + 1]);
+      }
+      T br = T(0), bi = T(0);
+      if (k1 < n1 && j < q) {
+        br = T(ft[((size_t)k1 * q + j) * 2]);
+        bi = T(ft[((size_t)k1 * q + j) * 2 + 1]);
+      }
+      acc = MF::op(wr, br, acc);
+      acc = MF::op(wi, bi, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c1o = 16 * mt + MF::row(v, grp);
+      if (c1o >= n1 || j >= q) continue;
+      sd.XL[((size_t)n2 * c1o + c2) * q + j] = (double)acc[v] * inx;
+    }
+  }
+}
+
 template <typename T>
 static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y, int gate, hipStream_t st) {
   const SDData& sd = h.sd[which];
@@ -429,13 +703,27 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
   const unsigned g1 = (unsigned)((sd.nMT1 + kWaves * kMtw - 1) / (kWaves * kMtw));
   const unsigned g3 = (unsigned)((sd.nMT3 + kWaves * kMtw - 1) / (kWaves * kMtw));
   hipLaunchKernelGGL(k_sd_cond<T>, dim3(ct, g1), dim3(kBlockThreads), l1, st, d, which, u, gate);
-  hipLaunchKernelGGL(k_sd_modes<T>, dim3(ct), dim3(kBlockThreads), l2, st, d, which, u, gate);
+  const int n1 = sd.fft_n1, n2 = sd.fft_n2;
+  if (n1) {
+    const size_t la = sizeof(double) * 4 * (size_t)((n1 + 3) / 4) * sd.q;
+    hipLaunchKernelGGL(k_sdf_a<T>, dim3(n2), dim3(kBlockThreads), la, st, d, which, u, gate);
+    hipLaunchKernelGGL(k_sdf_b<T>, dim3(n1), dim3(kBlockThreads), 0, st, d, which, gate);
+    const int ml = std::max(1, kBlockThreads / sd.q);
+    hipLaunchKernelGGL(k_sdf_solve<T>, dim3((h.nx + ml - 1) / ml), dim3(kBlockThreads),
+                       sizeof(double) * 2 * kBlockThreads, st, d, which, gate);
+  } else {
+    hipLaunchKernelGGL(k_sd_modes<T>, dim3(ct), dim3(kBlockThreads), l2, st, d, which, u, gate);
+  }
   if (sd.wall) {
     const size_t lw = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
     hipLaunchKernelGGL(k_sd_wall<T>, dim3(1), dim3(kBlockThreads), lw, st, d, which, u, gate);
     const int64_t nm = (int64_t)h.nx * sd.q + sd.nI;
     hipLaunchKernelGGL(k_sd_wall_modes, dim3((unsigned)((nm + kBlockThreads - 1) / kBlockThreads)),
                        dim3(kBlockThreads), 0, st, d, which, gate);
+  }
+  if (n1) {
+    hipLaunchKernelGGL(k_sdf_c<T>, dim3(n1), dim3(kBlockThreads), 0, st, d, which, gate);
+    hipLaunchKernelGGL(k_sdf_d<T>, dim3(n2), dim3(kBlockThreads), 0, st, d, which, gate);
   }
   hipLaunchKernelGGL(k_sd_back<T>, dim3(ct, g3), dim3(kBlockThreads), l3, st, d, which, y, gate);
 }

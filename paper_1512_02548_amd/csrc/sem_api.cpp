@@ -55,6 +55,7 @@ struct sem_mesh {
   int sd_nI[2] = {0, 0}, sd_q[2] = {0, 0};
   int sd_M1[2] = {0, 0}, sd_nMT1[2] = {0, 0}, sd_KS1[2] = {0, 0}, sd_nMT3[2] = {0, 0}, sd_KS3[2] = {0, 0};
   int sd_wall[2] = {0, 0};
+  int fft_n1 = 0, fft_n2 = 0;   // four-step transforms along x (0: direct)
   int circ1d = 0;
   int64_t n = 0, ns = 0, E = 0;
   // host tables
@@ -711,6 +712,17 @@ static sem_status build_mesh(sem_mesh* M) {
         });
       }
     }
+    // long tanks: transforms along x as two passes of n1- and n2-point
+    // products (nx = n1 n2, n1 the largest divisor with 8 <= n1 <= sqrt(nx))
+    M->fft_n1 = M->fft_n2 = 0;
+    if (nx >= 256) {
+      for (int a = (int)std::sqrt((double)nx); a >= 8; --a)
+        if (nx % a == 0) {
+          M->fft_n1 = a;
+          M->fft_n2 = nx / a;
+          break;
+        }
+    }
     twid.resize((size_t)2 * nx);
     for (int mm = 0; mm < nx; ++mm) {
       twid[2 * mm] = std::cos(2.0 * M_PI * mm / nx);
@@ -928,7 +940,11 @@ static sem_status build_mesh(sem_mesh* M) {
     put(M, (p + "Hm").c_str(), H.Hm);
     put(M, (p + "Qm").c_str(), H.Qm);
     reserve(M, (p + "vbuf").c_str(), (size_t)std::max(1, H.q) * sizeof(double));
-    reserve(M, (p + "WP").c_str(), (size_t)((nx + 15) / 16) * 2 * std::max(1, H.q) * sizeof(double));
+    reserve(M, (p + "WP").c_str(), (size_t)nx * 2 * std::max(1, H.q) * sizeof(double));
+    const size_t fbytes = M->fft_n1 ? (size_t)nx * std::max(1, H.q) * sizeof(double) : 8;
+    reserve(M, (p + "FT").c_str(), 2 * fbytes);
+    reserve(M, (p + "FG").c_str(), 2 * fbytes);
+    reserve(M, (p + "XL").c_str(), fbytes);
     reserve(M, (p + "yI").c_str(), (size_t)nx * std::max(1, H.nI) * sizeof(double));
     reserve(M, (p + "TL").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
     reserve(M, (p + "TR").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
@@ -1142,6 +1158,15 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     sd.Qm = at<double>(M, (p + "Qm").c_str());
     sd.vbuf = at<double>(M, (p + "vbuf").c_str());
     sd.WP = at<double>(M, (p + "WP").c_str());
+    sd.fft_n1 = M->fft_n1;
+    sd.fft_n2 = M->fft_n2;
+    // partial line sums: one per block of the modes kernel (16 modes), or
+    // per block of the FFT path's mode solve (256 / q modes)
+    sd.nwp = M->fft_n1 ? (M->nx + std::max(1, 256 / std::max(1, sd.q)) - 1) / std::max(1, 256 / std::max(1, sd.q))
+                       : (M->nx + 15) / 16;
+    sd.FT = at<double>(M, (p + "FT").c_str());
+    sd.FG = at<double>(M, (p + "FG").c_str());
+    sd.XL = at<double>(M, (p + "XL").c_str());
   }
   h.M1 = at<double>(M, "M1");
   h.S1 = at<double>(M, "S1");

@@ -62,7 +62,14 @@ struct SDData {
   const double* Hm;               // [nx][q][q][2] modal response to v, column-major per mode
   const double* Qm;               // [q][nI] interior response of the last column, column-major
   double* vbuf;                   // [q] v
-  double* WP;                     // [nx/16][2][q] per-block partial sums of lines nx-1 and 0
+  double* WP;                     // [nwp][2][q] per-block partial sums of lines nx-1 and 0
+  int32_t nwp;                    // number of those partials
+  // long tanks: the transforms along x as four-step FFTs, nx = n1 n2
+  int32_t fft_n1, fft_n2;         // 0: direct DFT products
+  int32_t pad3;
+  double* FT;                     // [nx][q][2] intermediate of the two-step transforms
+  double* FG;                     // [nx][q][2] transformed line right sides
+  double* XL;                     // [nx][q] line solution
 };
 
 // Everything a kernel needs about one tank; lives in device memory at the

@@ -82,6 +82,34 @@ def test_apply_operators(case, bar, variant):
     assert rel_err(pair.to_oracle(host(y)), ref) < 1e-11
 
 
+@pytest.mark.parametrize("case", [
+    (256, 2, 3, 2 * np.pi, True, 0.1),    # nx = 16 x 16: transforms along x in two passes
+    (300, 2, 3, 30.0, False, 0.1),        # walls, nx = 15 x 20: partial MFMA tiles
+])
+def test_exact_inverses_two_pass_transforms(case):
+    """Long tanks transform along x in two passes (nx = n1 n2); the still-water
+    preconditioner and the 2D mass inverse stay exact there."""
+    import scipy.sparse.linalg as spla
+    pair, eta, phi = make_pair(case, bar=True)
+    m, lib, om = pair.m, pair.lib, pair.om
+    rng = np.random.default_rng(11)
+    u_or = rng.standard_normal(om.n)
+    u_or[om.surf] = 0.0
+    y = cuda(np.zeros(m.n))
+    m.apply(lib.SEM_OP_PRECOND, cuda(pair.to_lib(u_or)), y)
+    A0 = olap.stiffness(om, olap.still_water_G(om, np.mean(pair.h)))
+    F = om.free
+    ref = np.zeros(om.n)
+    ref[F] = spla.spsolve(A0.tocsr()[F][:, F].tocsc(), u_or[F])
+    assert rel_err(pair.to_oracle(host(y)), ref) < 1e-10
+    # w recovery uses the exact 2D mass inverse
+    of = oracle_fields(pair, eta, phi)
+    out = cuda(np.zeros(m.ns))
+    m.gradient_recover(lib.SEM_RECOVER_W, cuda(pair.to_lib(of["Phi"])), cuda(eta), out)
+    w_ref = osrf.recover_w(om, of["Phi"], of["d"], osrf.mass2d(om))[om.surf]
+    assert rel_err(host(out), w_ref) < 1e-10
+
+
 @pytest.mark.parametrize("case", CASES)
 def test_gradient_recovery_dx(case):
     pair, eta, phi = make_pair(case)
