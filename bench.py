@@ -274,7 +274,7 @@ def main():
     eta = torch.tensor(eta0, dtype=torch.float64, device=dev)
     phi = torch.tensor(phi0, dtype=torch.float64, device=dev)
     ws = torch.zeros(m.n, dtype=torch.float64, device=dev)
-    opts = lib.default_opts(rtol=args.rtol, warm_start=1, lookahead=3)
+    opts = lib.default_opts(rtol=args.rtol, warm_start=1, lookahead=1)
     n_free = m.info.n_free
 
     eta_init, phi_init = eta.clone(), phi.clone()

@@ -55,7 +55,9 @@ struct SdMat<float> {
 };
 }  // namespace
 
-// condense: grid (column tiles, M-tile groups)
+// condense: grid (column tiles, M-tiles); the K-steps of each product are
+// split over the four wavefronts (each issues a quarter of the factor loads)
+// and the partial tiles are added in LDS in wave order
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
@@ -65,9 +67,11 @@ k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
   extern __shared__ unsigned char lds_raw[];
+  const int nI = sd.nI, q = sd.q, nx = d.nx, KS = sd.KS1;
   T* Rt = reinterpret_cast<T*>(lds_raw);   // [4 KS][16] interior right sides of 16 columns
-  const int nI = sd.nI, q = sd.q, nx = d.nx, KS = sd.KS1, nMT = sd.nMT1;
+  double* red = reinterpret_cast<double*>(lds_raw);   // [kWaves][256], reuses Rt after the products
   const int c0 = blockIdx.x * 16;
+  const int mt = blockIdx.y;
 #pragma unroll 8
   for (int t = threadIdx.x; t < 4 * KS * 16; t += blockDim.x) {
     const int k = t >> 4, c = c0 + (t & 15);
@@ -75,36 +79,22 @@ k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const int mt0 = (blockIdx.y * kWaves + wv) * kMtw;
-  if (mt0 >= nMT) return;
-  const T* A = SdMat<T>::A1(sd);
-  V4 acc[kMtw];
+  const T* A = SdMat<T>::A1(sd) + (size_t)mt * KS * 64;
+  V4 acc = V4{0, 0, 0, 0};
+#pragma unroll 8
+  for (int s = wv; s < KS; s += kWaves) acc = MF::op(A[(size_t)s * 64 + lane], Rt[(4 * s + grp) * 16 + col], acc);
+  __syncthreads();
 #pragma unroll
-  for (int u = 0; u < kMtw; ++u) acc[u] = V4{0, 0, 0, 0};
-#pragma unroll 4
-  for (int s = 0; s < KS; ++s) {
-    const T b = Rt[(4 * s + grp) * 16 + col];
-#pragma unroll
-    for (int u = 0; u < kMtw; ++u) {
-      const int mt = min(mt0 + u, nMT - 1);   // a clamped tile is computed, never stored
-      acc[u] = MF::op(A[((size_t)mt * KS + s) * 64 + lane], b, acc[u]);
-    }
-  }
-  const int c = c0 + col;
+  for (int v = 0; v < 4; ++v) red[wv * 256 + MF::row(v, grp) * 16 + col] = (double)acc[v];
+  __syncthreads();
+  const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
+  const int row = 16 * mt + rr, c = c0 + cc;
   if (c >= nx) return;
-#pragma unroll
-  for (int u = 0; u < kMtw; ++u) {
-    const int mt = mt0 + u;
-    if (mt >= nMT) break;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 16 * mt + MF::row(v, grp);
-      const double val = (double)acc[u][v];
-      if (row < nI) sd.yI[(size_t)c * nI + row] = val;
-      else if (row < nI + q) sd.TL[(size_t)c * q + row - nI] = val;
-      else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
-    }
-  }
+  double val = 0;
+  for (int w = 0; w < kWaves; ++w) val += red[w * 256 + threadIdx.x];
+  if (row < nI) sd.yI[(size_t)c * nI + row] = val;
+  else if (row < nI + q) sd.TL[(size_t)c * q + row - nI] = val;
+  else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
 }
 
 // modes: one block per 16 Fourier modes; waves split the sum over columns
@@ -697,10 +687,10 @@ template <typename T>
 static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y, int gate, hipStream_t st) {
   const SDData& sd = h.sd[which];
   const unsigned ct = (unsigned)((h.nx + 15) / 16);
-  const size_t l1 = sizeof(T) * 4 * (size_t)sd.KS1 * 16;
+  const size_t l1 = std::max(sizeof(T) * 4 * (size_t)sd.KS1 * 16, sizeof(double) * kWaves * 256);
   const size_t l2 = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
   const size_t l3 = sizeof(double) * (kWaves * 16 * 16 + 17 * (size_t)sd.q);
-  const unsigned g1 = (unsigned)((sd.nMT1 + kWaves * kMtw - 1) / (kWaves * kMtw));
+  const unsigned g1 = (unsigned)sd.nMT1;
   const unsigned g3 = (unsigned)((sd.nMT3 + kWaves * kMtw - 1) / (kWaves * kMtw));
   hipLaunchKernelGGL(k_sd_cond<T>, dim3(ct, g1), dim3(kBlockThreads), l1, st, d, which, u, gate);
   const int n1 = sd.fft_n1, n2 = sd.fft_n2;

@@ -1387,8 +1387,11 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st, d, B.side);
       launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
       launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
-      // wait while the device is more than `ahead` steps behind
+      // wait while the device is more than `ahead` steps behind: spin on the
+      // progress word; ask the runtime whether the queue drained only every
+      // 100 us (a drained queue means the word is final)
       bool stop = false;
+      auto tq = std::chrono::steady_clock::now();
       while (true) {
         int32_t v = *prog;
         if (v & PROG_DONE) {
@@ -1396,13 +1399,17 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
           break;
         }
         if (j + 1 - (v & PROG_STEPS) <= ahead) break;
-        hipError_t q = hipStreamQuery(st);
-        if (q == hipSuccess) {          // queue drained: the word is final
-          stop = (*prog & PROG_DONE) != 0;
-          break;
+        auto now = std::chrono::steady_clock::now();
+        if (now - tq > std::chrono::microseconds(100)) {
+          tq = now;
+          hipError_t q = hipStreamQuery(st);
+          if (q == hipSuccess) {
+            stop = (*prog & PROG_DONE) != 0;
+            break;
+          }
+          if (q != hipErrorNotReady) HIPCHK(q);
         }
-        if (q != hipErrorNotReady) HIPCHK(q);
-        std::this_thread::yield();
+        __builtin_ia32_pause();
       }
       if (stop) break;
     }
@@ -1446,7 +1453,7 @@ static void default_opts(sem_solve_opts* o) {
   o->inner_rtol = 1e-4;
   o->max_refine = 30;
   o->warm_start = 0;
-  o->lookahead = 3;
+  o->lookahead = 2;
 }
 
 // ------------------------------------------------------------ public calls
