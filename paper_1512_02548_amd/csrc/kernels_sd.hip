@@ -30,7 +30,7 @@ namespace sem {
 
 namespace {
 constexpr int kWaves = kBlockThreads / 64;
-constexpr int kMtw = 2;   // M-tiles per wave in the condensation product
+constexpr int kModesPB = 8;  // Fourier modes per workgroup in the direct modes kernel
 
 __host__ __device__ inline int sd_part_words(int q) { return max(kWaves * 16 * 16 * 2, 32 * q); }
 
@@ -112,8 +112,8 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
   double* gh = sh + sd_part_words(q);     // [16][q][2]
   const int nNT = (q + 15) / 16, KS = (nx + 3) / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const int k0 = blockIdx.x * 16;
-  const int kmode = k0 + col;              // A row of this lane
+  const int k0 = blockIdx.x * kModesPB;
+  const int kmode = k0 + col;              // A row of this lane (rows past the block's modes are discarded)
   const bool kval = kmode < nx;
   const int kr = kval ? kmode : 0;
   // twiddle index (kmode * c) mod nx for c = 4 s + grp, s = wv, wv + 4, ...
@@ -172,7 +172,7 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
     }
   }
   // x^_k = S^_k^{-1} g^_k (column-major: thread per (mode, row))
-  for (int t = threadIdx.x; t < 16 * q; t += blockDim.x) {
+  for (int t = threadIdx.x; t < kModesPB * q; t += blockDim.x) {
     const int kk = t / q, i = t - kk * q, k = k0 + kk;
     if (k >= nx) continue;
     const T* S = SdMat<T>::Shat(sd) + (size_t)k * q * q * 2;
@@ -198,7 +198,7 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
   for (int t = threadIdx.x; t < 2 * q; t += blockDim.x) {
     const int ln = t / q, j = t - ln * q;
     double acc = 0;
-    for (int kk = 0; kk < 16; ++kk) {
+    for (int kk = 0; kk < kModesPB; ++kk) {
       const int k = k0 + kk;
       if (k >= nx) break;
       const double hr = part[(kk * q + j) * 2], hi = part[(kk * q + j) * 2 + 1];
@@ -213,7 +213,53 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
   }
 }
 
-// back: grid (column tiles, M-tile groups of the back-substitution)
+// inverse transform of the line solution (direct products, small nx): grid
+// (16-line tiles, 16-wide tiles of line unknowns); the K range (modes x
+// re/im) is split over the wavefronts and the partial tiles added in LDS
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  const SDData& sd = d.sd[which];
+  __shared__ double red[kWaves][256];
+  const int q = sd.q, nx = d.nx;
+  const int KS = (2 * nx + 3) / 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const int c0 = blockIdx.x * 16, nt = blockIdx.y;
+  // A[c][kk] = twiddle part (kk & 1) of mode kk / 2 at line c; B[kk][j] = that part of x^_{kk/2}[j]
+  const int cr = (c0 + col) % nx;
+  const int pr = grp & 1;
+  const int j = 16 * nt + col;
+  const int step = (int)(((int64_t)2 * kWaves * cr) % nx);   // the mode advances by 8 per pass
+  int mm = (int)(((int64_t)cr * (2 * wv + (grp >> 1))) % nx);
+  V4 acc = V4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int s = wv; s < KS; s += kWaves) {
+    const int k = 2 * s + (grp >> 1);
+    const bool kv = k < nx;
+    const T a = kv ? T(d.twid[2 * mm + pr]) : T(0);
+    const T b = (kv && j < q) ? T(sd.XH[((size_t)k * q + j) * 2 + pr]) : T(0);
+    acc = MF::op(a, b, acc);
+    mm += step;
+    if (mm >= nx) mm -= nx;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wv][MF::row(v, grp) * 16 + col] = (double)acc[v];
+  __syncthreads();
+  const int row = threadIdx.x >> 4, jc = threadIdx.x & 15;
+  const int c = c0 + row, jj = 16 * nt + jc;
+  if (c >= nx || jj >= q) return;
+  double v = 0;
+  for (int w = 0; w < kWaves; ++w) v += red[w][threadIdx.x];
+  sd.XL[(size_t)c * q + jj] = v / nx;
+}
+
+// back-substitution: grid (column tiles, M-tiles of A_II^-1 [A_IL | A_IR]);
+// the lines of 16 + 1 columns come from XL, the K range is split over the
+// wavefronts.  Block row 0 also writes the line values (and the wall line).
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate) {
@@ -223,83 +269,17 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
   extern __shared__ double sh[];
-  double* part = sh;                     // [kWaves][16][16]
-  double* xl = sh + kWaves * 16 * 16;    // [17][q] line solutions of columns c0 .. c0+16
   const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc;
-  const int nNT = (q + 15) / 16, KS = (2 * nx + 3) / 4;
+  double* xl = sh;                         // [17][q] line solutions of columns c0 .. c0+16
+  double* red = sh + 17 * q;               // [kWaves][256]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   const int c0 = blockIdx.x * 16;
-  const double inx = 1.0 / nx;
-  if (sd.fft_n1) {
-    // lines c0 .. c0+16 (wrapping) were transformed back by the FFT passes
-    for (int t = threadIdx.x; t < 17 * q; t += blockDim.x) {
-      const int cc = t / q, j = t - cc * q;
-      xl[t] = sd.XL[(size_t)((c0 + cc) % nx) * q + j];
-    }
-    __syncthreads();
-  } else {
-  // inverse DFT for lines c0 .. c0+15: A[c][kk] = twiddle part (kk & 1) of mode
-  // kk / 2 at line c, B[kk][j] = part (kk & 1) of x^_{kk/2}[j]
-  {
-    // rows past the last column wrap: row nx - c0 is the right neighbour
-    // (line 0) of the last column of a partial tile
-    const int cr = (c0 + col) % nx;
-    const int kfirst = 2 * wv + (grp >> 1), pr = grp & 1;
-    const int step = (int)(((int64_t)8 * cr) % nx);   // mode advances by 8 per pass
-    for (int nt = 0; nt < nNT; ++nt) {
-      V4 acc = V4{0, 0, 0, 0};
-      int mm = (int)(((int64_t)cr * kfirst) % nx);
-#pragma unroll 4
-      for (int s = wv; s < KS; s += kWaves) {
-        const int k = 2 * s + (grp >> 1);
-        const bool kv = k < nx;
-        const T a = kv ? T(d.twid[2 * mm + pr]) : T(0);
-        const int j = 16 * nt + col;
-        const T b = (kv && j < q) ? T(sd.XH[((size_t)k * q + j) * 2 + pr]) : T(0);
-        acc = MF::op(a, b, acc);
-        mm += step;
-        if (mm >= nx) mm -= nx;
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) part[(wv * 16 + MF::row(v, grp)) * 16 + col] = (double)acc[v];
-      __syncthreads();
-      {
-        const int row = threadIdx.x >> 4, jc = threadIdx.x & 15, j = 16 * nt + jc;
-        double sacc = 0;
-        for (int w = 0; w < kWaves; ++w) sacc += part[(w * 16 + row) * 16 + jc];
-        if (j < q) xl[row * q + j] = sacc * inx;
-      }
-      __syncthreads();
-    }
+  const int mt = blockIdx.y;
+  for (int t = threadIdx.x; t < 17 * q; t += blockDim.x) {
+    const int cc = t / q, j = t - cc * q;
+    xl[t] = sd.XL[(size_t)((c0 + cc) % nx) * q + j];
   }
-  // line c0+16 (wraps): lanes over j, waves over modes, fixed-order sums
-  {
-    const int c16 = (c0 + 16) % nx;
-    const int step = (int)(((int64_t)kWaves * c16) % nx);
-    for (int j0 = 0; j0 < q; j0 += 64) {
-      const int j = j0 + lane;
-      double acc = 0;
-      if (j < q) {
-        int mm = (int)(((int64_t)c16 * wv) % nx);
-#pragma unroll 4
-        for (int k = wv; k < nx; k += kWaves) {
-          acc += sd.XH[((size_t)k * q + j) * 2] * d.twid[2 * mm] + sd.XH[((size_t)k * q + j) * 2 + 1] * d.twid[2 * mm + 1];
-          mm += step;
-          if (mm >= nx) mm -= nx;
-        }
-      }
-      part[wv * 64 + lane] = acc;
-      __syncthreads();
-      if (threadIdx.x < 64 && j0 + threadIdx.x < q) {
-        double sacc = 0;
-        for (int w = 0; w < kWaves; ++w) sacc += part[w * 64 + threadIdx.x];
-        xl[16 * q + j0 + threadIdx.x] = sacc * inx;
-      }
-      __syncthreads();
-    }
-  }
-  }
-  // line values of the block's columns
+  __syncthreads();
   if (blockIdx.y == 0) {
     for (int t = threadIdx.x; t < 16 * q; t += blockDim.x) {
       const int cc = t / q, j = t - cc * q, c = c0 + cc;
@@ -311,45 +291,33 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
         if (c < nx) z[(int64_t)c * nc + (k == 0 ? d.nl - 1 : d.surf_loc[k])] = T(0);
       }
     }
+    if (sd.wall && blockIdx.x == 0) {
+      // wall line = line 0 + v
+      for (int j = threadIdx.x; j < q; j += blockDim.x) z[(int64_t)nx * nc + j] = T(xl[j] + sd.vbuf[j]);
+      if (sd.zero_surface && threadIdx.x == 0) z[(int64_t)nx * nc + d.nl - 1] = T(0);
+    }
   }
-  // wall line = line 0 + v
-  if (sd.wall && blockIdx.x == 0 && blockIdx.y == 0) {
-    for (int j = threadIdx.x; j < q; j += blockDim.x) z[(int64_t)nx * nc + j] = T(xl[j] + sd.vbuf[j]);
-    if (sd.zero_surface && threadIdx.x == 0) z[(int64_t)nx * nc + d.nl - 1] = T(0);
-  }
-  // z_I = Y - C [x_L,c; x_L,c+1]: kMtw M-tiles per wave
-  const int mt0 = (blockIdx.y * kWaves + wv) * kMtw;
-  const int nMT = sd.nMT3;
-  if (mt0 >= nMT) return;
-  const T* C = SdMat<T>::C3(sd);
+  // z_I = Y - C [x_L,c; x_L,c+1]
+  const T* C = SdMat<T>::C3(sd) + (size_t)mt * sd.KS3 * 64;
   const int KS3 = sd.KS3;
-  V4 acc[kMtw];
-#pragma unroll
-  for (int u = 0; u < kMtw; ++u) acc[u] = V4{0, 0, 0, 0};
+  V4 acc = V4{0, 0, 0, 0};
 #pragma unroll 4
-  for (int s = 0; s < KS3; ++s) {
+  for (int s = wv; s < KS3; s += kWaves) {
     const int kk = 4 * s + grp;
     T b = T(0);
     if (kk < q) b = T(xl[col * q + kk]);
     else if (kk < 2 * q) b = T(xl[(col + 1) * q + kk - q]);
-#pragma unroll
-    for (int u = 0; u < kMtw; ++u) {
-      const int mt = min(mt0 + u, nMT - 1);   // a clamped tile is computed, never stored
-      acc[u] = MF::op(C[((size_t)mt * KS3 + s) * 64 + lane], b, acc[u]);
-    }
+    acc = MF::op(C[(size_t)s * 64 + lane], b, acc);
   }
-  const int c = c0 + col;
-  if (c >= nx) return;
 #pragma unroll
-  for (int u = 0; u < kMtw; ++u) {
-    const int mt = mt0 + u;
-    if (mt >= nMT) break;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 16 * mt + MF::row(v, grp);
-      if (row < nI) z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - (double)acc[u][v]);
-    }
-  }
+  for (int v = 0; v < 4; ++v) red[wv * 256 + MF::row(v, grp) * 16 + col] = (double)acc[v];
+  __syncthreads();
+  const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
+  const int row = 16 * mt + rr, c = c0 + cc;
+  if (row >= nI || c >= nx) return;
+  double v = 0;
+  for (int w = 0; w < kWaves; ++w) v += red[w * 256 + threadIdx.x];
+  z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - v);
 }
 
 // Wall correction (one workgroup): lines nx-1 and 0 of the first solve
@@ -689,9 +657,8 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
   const unsigned ct = (unsigned)((h.nx + 15) / 16);
   const size_t l1 = std::max(sizeof(T) * 4 * (size_t)sd.KS1 * 16, sizeof(double) * kWaves * 256);
   const size_t l2 = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
-  const size_t l3 = sizeof(double) * (kWaves * 16 * 16 + 17 * (size_t)sd.q);
+  const size_t l3 = sizeof(double) * (kWaves * 256 + 17 * (size_t)sd.q);
   const unsigned g1 = (unsigned)sd.nMT1;
-  const unsigned g3 = (unsigned)((sd.nMT3 + kWaves * kMtw - 1) / (kWaves * kMtw));
   hipLaunchKernelGGL(k_sd_cond<T>, dim3(ct, g1), dim3(kBlockThreads), l1, st, d, which, u, gate);
   const int n1 = sd.fft_n1, n2 = sd.fft_n2;
   if (n1) {
@@ -702,7 +669,8 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
     hipLaunchKernelGGL(k_sdf_solve<T>, dim3((h.nx + ml - 1) / ml), dim3(kBlockThreads),
                        sizeof(double) * 2 * kBlockThreads, st, d, which, gate);
   } else {
-    hipLaunchKernelGGL(k_sd_modes<T>, dim3(ct), dim3(kBlockThreads), l2, st, d, which, u, gate);
+    hipLaunchKernelGGL(k_sd_modes<T>, dim3((h.nx + kModesPB - 1) / kModesPB), dim3(kBlockThreads), l2, st, d, which,
+                       u, gate);
   }
   if (sd.wall) {
     const size_t lw = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
@@ -714,8 +682,10 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
   if (n1) {
     hipLaunchKernelGGL(k_sdf_c<T>, dim3(n1), dim3(kBlockThreads), 0, st, d, which, gate);
     hipLaunchKernelGGL(k_sdf_d<T>, dim3(n2), dim3(kBlockThreads), 0, st, d, which, gate);
+  } else {
+    hipLaunchKernelGGL(k_sd_idft<T>, dim3(ct, (sd.q + 15) / 16), dim3(kBlockThreads), 0, st, d, which, gate);
   }
-  hipLaunchKernelGGL(k_sd_back<T>, dim3(ct, g3), dim3(kBlockThreads), l3, st, d, which, y, gate);
+  hipLaunchKernelGGL(k_sd_back<T>, dim3(ct, sd.nMT3), dim3(kBlockThreads), l3, st, d, which, y, gate);
 }
 
 void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st) {

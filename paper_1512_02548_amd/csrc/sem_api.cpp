@@ -941,10 +941,11 @@ static sem_status build_mesh(sem_mesh* M) {
     put(M, (p + "Qm").c_str(), H.Qm);
     reserve(M, (p + "vbuf").c_str(), (size_t)std::max(1, H.q) * sizeof(double));
     reserve(M, (p + "WP").c_str(), (size_t)nx * 2 * std::max(1, H.q) * sizeof(double));
-    const size_t fbytes = M->fft_n1 ? (size_t)nx * std::max(1, H.q) * sizeof(double) : 8;
+    const size_t lbytes = (size_t)nx * std::max(1, H.q) * sizeof(double);
+    const size_t fbytes = M->fft_n1 ? lbytes : 8;
     reserve(M, (p + "FT").c_str(), 2 * fbytes);
     reserve(M, (p + "FG").c_str(), 2 * fbytes);
-    reserve(M, (p + "XL").c_str(), fbytes);
+    reserve(M, (p + "XL").c_str(), lbytes);
     reserve(M, (p + "yI").c_str(), (size_t)nx * std::max(1, H.nI) * sizeof(double));
     reserve(M, (p + "TL").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
     reserve(M, (p + "TR").c_str(), (size_t)nx * std::max(1, H.q) * sizeof(double));
@@ -1163,7 +1164,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     // partial line sums: one per block of the modes kernel (16 modes), or
     // per block of the FFT path's mode solve (256 / q modes)
     sd.nwp = M->fft_n1 ? (M->nx + std::max(1, 256 / std::max(1, sd.q)) - 1) / std::max(1, 256 / std::max(1, sd.q))
-                       : (M->nx + 15) / 16;
+                       : (M->nx + 7) / 8;
     sd.FT = at<double>(M, (p + "FT").c_str());
     sd.FG = at<double>(M, (p + "FG").c_str());
     sd.XL = at<double>(M, (p + "XL").c_str());
