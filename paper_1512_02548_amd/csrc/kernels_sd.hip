@@ -34,6 +34,14 @@ constexpr int kModesPB = 8;  // Fourier modes per workgroup in the direct modes 
 
 __host__ __device__ inline int sd_part_words(int q) { return max(kWaves * 16 * 16 * 2, 32 * q); }
 
+// Reading the input r / hn (the unnormalised next Krylov vector and its norm)
+// instead of r: 1/hn, 0 when hn is not positive, 1 without a scale.
+__device__ inline double sd_in_scale(const double* nscale) {
+  if (!nscale) return 1.0;
+  const double hn = *nscale;
+  return hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
 __device__ inline double wsum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -60,7 +68,8 @@ struct SdMat<float> {
 // and the partial tiles are added in LDS in wave order
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
+k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
+          const double* __restrict__ nscale, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
   using MF = Mfma<T>;
@@ -72,10 +81,17 @@ k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   double* red = reinterpret_cast<double*>(lds_raw);   // [kWaves][256], reuses Rt after the products
   const int c0 = blockIdx.x * 16;
   const int mt = blockIdx.y;
+  const double rs = sd_in_scale(nscale);
 #pragma unroll 8
   for (int t = threadIdx.x; t < 4 * KS * 16; t += blockDim.x) {
     const int k = t >> 4, c = c0 + (t & 15);
-    Rt[t] = (k < nI && c < nx) ? r[(int64_t)c * d.nc + sd.I_idx[k]] : T(0);
+    T v = T(0);
+    if (k < nI && c < nx) {
+      const int64_t gi = (int64_t)c * d.nc + sd.I_idx[k];
+      v = nscale ? T((double)r[gi] * rs) : r[gi];
+      if (vout && blockIdx.y == 0) vout[gi] = v;
+    }
+    Rt[t] = v;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
@@ -100,7 +116,8 @@ k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
 // modes: one block per 16 Fourier modes; waves split the sum over columns
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
+k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
+           const double* __restrict__ nscale, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
   using MF = Mfma<T>;
@@ -113,6 +130,7 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
   const int nNT = (q + 15) / 16, KS = (nx + 3) / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   const int k0 = blockIdx.x * kModesPB;
+  const double rs = sd_in_scale(nscale);
   const int kmode = k0 + col;              // A row of this lane (rows past the block's modes are discarded)
   const bool kval = kmode < nx;
   const int kr = kval ? kmode : 0;
@@ -137,8 +155,13 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
         const int j = 16 * (nt0 + u) + col;
         T gv = T(0);
         if (cv && j < q) {
-          double rv = (double)r[(int64_t)c * nc + j];
-          if (sd.wall && c == 0) rv += (double)r[(int64_t)nx * nc + j];   // wall line folded onto line 0
+          double rv = (double)r[(int64_t)c * nc + j] * rs;
+          if (vout && blockIdx.x == 0) vout[(int64_t)c * nc + j] = T(rv);
+          if (sd.wall && c == 0) {   // wall line folded onto line 0
+            const double rw = (double)r[(int64_t)nx * nc + j] * rs;
+            if (vout && blockIdx.x == 0) vout[(int64_t)nx * nc + j] = T(rw);
+            rv += rw;
+          }
           gv = T(rv - sd.TL[(size_t)c * q + j] - sd.TR[(size_t)cm * q + j]);
         }
         are[u] = MF::op(fre, gv, are[u]);
@@ -262,7 +285,7 @@ k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
 // wavefronts.  Block row 0 also writes the line values (and the wall line).
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate) {
+k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
   using MF = Mfma<T>;
@@ -288,13 +311,20 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
     if (sd.zero_surface) {
       for (int t = threadIdx.x; t < 16 * d.P; t += blockDim.x) {
         const int cc = t / d.P, k = t - cc * d.P, c = c0 + cc;
-        if (c < nx) z[(int64_t)c * nc + (k == 0 ? d.nl - 1 : d.surf_loc[k])] = T(0);
+        if (c < nx) {
+          const int64_t gi = (int64_t)c * nc + (k == 0 ? d.nl - 1 : d.surf_loc[k]);
+          z[gi] = T(0);
+          if (vout) vout[gi] = T(0);   // the normalised Krylov vector vanishes at the surface
+        }
       }
     }
     if (sd.wall && blockIdx.x == 0) {
       // wall line = line 0 + v
       for (int j = threadIdx.x; j < q; j += blockDim.x) z[(int64_t)nx * nc + j] = T(xl[j] + sd.vbuf[j]);
-      if (sd.zero_surface && threadIdx.x == 0) z[(int64_t)nx * nc + d.nl - 1] = T(0);
+      if (sd.zero_surface && threadIdx.x == 0) {
+        z[(int64_t)nx * nc + d.nl - 1] = T(0);
+        if (vout) vout[(int64_t)nx * nc + d.nl - 1] = T(0);
+      }
     }
   }
   // z_I = Y - C [x_L,c; x_L,c+1]
@@ -325,7 +355,8 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
 // with one wavefront per component of v.
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
+k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
+          const double* __restrict__ nscale) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
   const SDData& sd = d.sd[which];
@@ -343,7 +374,8 @@ k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
     for (int b = 0; b < nb2; ++b) acc += sd.WP[((size_t)b * 2 + ln) * q + j];
     in[q + ln * q + j] = acc * inx;
   }
-  for (int a = threadIdx.x; a < q; a += blockDim.x) in[a] = (double)r[(int64_t)nx * nc + a];
+  const double rs = sd_in_scale(nscale);
+  for (int a = threadIdx.x; a < q; a += blockDim.x) in[a] = (double)r[(int64_t)nx * nc + a] * rs;
   for (int i = threadIdx.x; i < nI; i += blockDim.x) in[3 * q + i] = sd.yI[(size_t)(nx - 1) * nI + i];
   __syncthreads();
   for (int a = wv; a < q; a += kWaves) {
@@ -400,7 +432,8 @@ __device__ inline int sd_mod(int64_t a, int n) { return (int)(a % n); }
 // pass A (block per c2): FT[k1][c2][j] = w_nx^{k1 c2} sum_c1 w_n1^{k1 c1} g[n2 c1 + c2][j]
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sdf_a(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate) {
+k_sdf_a(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
+        const double* __restrict__ nscale, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
   using MF = Mfma<T>;
@@ -410,14 +443,20 @@ k_sdf_a(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int 
   const int q = sd.q, nx = d.nx, nc = d.nc, n1 = sd.fft_n1, n2 = sd.fft_n2;
   const int c2 = blockIdx.x;
   const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16, nNT = (q + 15) / 16;
+  const double rs = sd_in_scale(nscale);
   double* gl = sh;   // [4 KS][q] line right sides of columns n2 c1 + c2
   for (int t = threadIdx.x; t < 4 * KS * q; t += blockDim.x) {
     const int c1 = t / q, j = t - c1 * q;
     double v = 0;
     if (c1 < n1) {
       const int c = n2 * c1 + c2, cm = c == 0 ? nx - 1 : c - 1;
-      v = (double)r[(int64_t)c * nc + j];
-      if (sd.wall && c == 0) v += (double)r[(int64_t)nx * nc + j];
+      v = (double)r[(int64_t)c * nc + j] * rs;
+      if (vout) vout[(int64_t)c * nc + j] = T(v);
+      if (sd.wall && c == 0) {
+        const double rw = (double)r[(int64_t)nx * nc + j] * rs;
+        if (vout) vout[(int64_t)nx * nc + j] = T(rw);
+        v += rw;
+      }
       v -= sd.TL[(size_t)c * q + j] + sd.TR[(size_t)cm * q + j];
     }
     gl[t] = v;
@@ -652,29 +691,30 @@ k_sdf_d(const TankDev* __restrict__ td, int which, int gate) {
 }
 
 template <typename T>
-static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y, int gate, hipStream_t st) {
+static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y, int gate, const double* nscale,
+                 T* vout, hipStream_t st) {
   const SDData& sd = h.sd[which];
   const unsigned ct = (unsigned)((h.nx + 15) / 16);
   const size_t l1 = std::max(sizeof(T) * 4 * (size_t)sd.KS1 * 16, sizeof(double) * kWaves * 256);
   const size_t l2 = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
   const size_t l3 = sizeof(double) * (kWaves * 256 + 17 * (size_t)sd.q);
   const unsigned g1 = (unsigned)sd.nMT1;
-  hipLaunchKernelGGL(k_sd_cond<T>, dim3(ct, g1), dim3(kBlockThreads), l1, st, d, which, u, gate);
+  hipLaunchKernelGGL(k_sd_cond<T>, dim3(ct, g1), dim3(kBlockThreads), l1, st, d, which, u, gate, nscale, vout);
   const int n1 = sd.fft_n1, n2 = sd.fft_n2;
   if (n1) {
     const size_t la = sizeof(double) * 4 * (size_t)((n1 + 3) / 4) * sd.q;
-    hipLaunchKernelGGL(k_sdf_a<T>, dim3(n2), dim3(kBlockThreads), la, st, d, which, u, gate);
+    hipLaunchKernelGGL(k_sdf_a<T>, dim3(n2), dim3(kBlockThreads), la, st, d, which, u, gate, nscale, vout);
     hipLaunchKernelGGL(k_sdf_b<T>, dim3(n1), dim3(kBlockThreads), 0, st, d, which, gate);
     const int ml = std::max(1, kBlockThreads / sd.q);
     hipLaunchKernelGGL(k_sdf_solve<T>, dim3((h.nx + ml - 1) / ml), dim3(kBlockThreads),
                        sizeof(double) * 2 * kBlockThreads, st, d, which, gate);
   } else {
     hipLaunchKernelGGL(k_sd_modes<T>, dim3((h.nx + kModesPB - 1) / kModesPB), dim3(kBlockThreads), l2, st, d, which,
-                       u, gate);
+                       u, gate, nscale, vout);
   }
   if (sd.wall) {
     const size_t lw = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
-    hipLaunchKernelGGL(k_sd_wall<T>, dim3(1), dim3(kBlockThreads), lw, st, d, which, u, gate);
+    hipLaunchKernelGGL(k_sd_wall<T>, dim3(1), dim3(kBlockThreads), lw, st, d, which, u, gate, nscale);
     const int64_t nm = (int64_t)h.nx * sd.q + sd.nI;
     hipLaunchKernelGGL(k_sd_wall_modes, dim3((unsigned)((nm + kBlockThreads - 1) / kBlockThreads)),
                        dim3(kBlockThreads), 0, st, d, which, gate);
@@ -685,14 +725,16 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
   } else {
     hipLaunchKernelGGL(k_sd_idft<T>, dim3(ct, (sd.q + 15) / 16), dim3(kBlockThreads), 0, st, d, which, gate);
   }
-  hipLaunchKernelGGL(k_sd_back<T>, dim3(ct, sd.nMT3), dim3(kBlockThreads), l3, st, d, which, y, gate);
+  hipLaunchKernelGGL(k_sd_back<T>, dim3(ct, sd.nMT3), dim3(kBlockThreads), l3, st, d, which, y, gate, vout);
 }
 
-void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st) {
-  sd_t<double>(h, d, which, u, y, gate, st);
+void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st,
+               const double* nscale, double* vout) {
+  sd_t<double>(h, d, which, u, y, gate, nscale, vout, st);
 }
-void launch_sd(const TankDev& h, const TankDev* d, int which, const float* u, float* y, int gate, hipStream_t st) {
-  sd_t<float>(h, d, which, u, y, gate, st);
+void launch_sd(const TankDev& h, const TankDev* d, int which, const float* u, float* y, int gate, hipStream_t st,
+               const double* nscale, float* vout) {
+  sd_t<float>(h, d, which, u, y, gate, nscale, vout, st);
 }
 
 }  // namespace sem

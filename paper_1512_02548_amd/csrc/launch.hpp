@@ -32,8 +32,13 @@ void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const float* u,
 void launch_mfma_probe(double* out64, float* out32, hipStream_t st);
 void launch_fixup(const TankDev& h, const TankDev* d, double* y, double* side, int flags, hipStream_t st);
 void launch_fixup(const TankDev& h, const TankDev* d, float* y, float* side, int flags, hipStream_t st);
-void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st);
-void launch_sd(const TankDev& h, const TankDev* d, int which, const float* u, float* y, int gate, hipStream_t st);
+// Exact still-water inverse (which 0) or 2D mass inverse (which 1): y = A^{-1} u.
+// With nscale, the input is u / *nscale (0 when *nscale <= 0) and, with vout,
+// that scaled input is also stored to vout (the normalised Krylov vector).
+void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st,
+               const double* nscale = nullptr, double* vout = nullptr);
+void launch_sd(const TankDev& h, const TankDev* d, int which, const float* u, float* y, int gate, hipStream_t st,
+               const double* nscale = nullptr, float* vout = nullptr);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
 void launch_fill(int64_t n, double v, double* y, hipStream_t st);
 void launch_fill_f(int64_t n, float* y, hipStream_t st);

@@ -1375,10 +1375,15 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
     launch_dots(n, 1, B.V, 0, B.V, h.part, ldp, scal + 0, cnt, nullptr, st);
     launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, B.V, M->prog_dev, st);
     first = false;
+    // with the exact still-water inverse, V_j = w / h_{j,j-1} is formed while
+    // the preconditioner reads w (no separate scaling launch)
+    const bool fused = cfg.pre == OP_PRE_LAP && h.pre_kind == 1;
+    const double* hnorm = h.H + (size_t)(m + 1) * m + 2 * m + (m + 1);   // norms of V_1.. (scratch of the Givens update)
     for (int j = 0; j < m && total + j < cfg.max_iter; ++j) {
       T* Vj = B.V + (size_t)j * n;
       T* Zj = B.Z + (size_t)j * n;
-      gather_t(M, cfg, cfg.pre, Vj, Zj, B.side, gflags, st);
+      if (fused && j > 0) launch_sd(h, d, 0, B.w, Zj, 1, st, hnorm + (j - 1), Vj);
+      else gather_t(M, cfg, cfg.pre, Vj, Zj, B.side, gflags, st);
       {
         // the operator's shared-line fix-up is done inside the products below
         sem_status e = stiff_timed(M, cfg, Zj, B.w, B.side, gflags | F_NOFIX, st);
@@ -1387,7 +1392,7 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       double* Hcol = h.H + (size_t)j * (m + 1);
       launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st, d, B.side);
       launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
-      launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
+      if (!fused) launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
       // wait while the device is more than `ahead` steps behind: spin on the
       // progress word; ask the runtime whether the queue drained only every
       // 100 us (a drained queue means the word is final)
