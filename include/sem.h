@@ -177,20 +177,42 @@ sem_status sem_rk4_step(sem_mesh* mesh, double* eta, double* phi_s, double* phi_
                         const sem_solve_opts* opts, sem_solve_stats* stats, void* stream);
 
 /* Batching: many independent tanks (each bound to its own workspace)
- * advanced by one call.  The tanks are spread over `nstreams` worker
+ * advanced by one call.  A tank's results do not depend on which other tanks
+ * are in the batch.  per_tank_status / per_tank_iters: HOST arrays of `count`
+ * (may be NULL); active_host (may be NULL = all) selects the tanks of a call.
+ * Each tank step is transactional as in sem_rk4_step; the call returns the
+ * first failing status.
+ *
+ * nstreams = 0, lockstep (Secs. 3.1.1-3.1.3 for every tank at once): the
+ * Laplace solves of all tanks run as one restarted GMRES in lockstep; every
+ * kernel launch of an Arnoldi step covers the workgroups of all tanks, and a
+ * tank whose cycle has ended leaves the launches at once.  Each tank keeps
+ * its own Krylov scalars, so its arithmetic is the single-tank solve's.
+ * Needs periodic or walled tanks with nx >= 2 (exact still-water inverse)
+ * and the matrix-core stiffness kernel; FP64 solves.  sem_batch_create
+ * allocates the work-item tables (device) and the progress words (pinned
+ * host) and uploads them on `stream`.  The meshes must stay bound, unchanged,
+ * while the batch exists.  All work is ordered on the caller's `stream`.
+ *
+ * nstreams >= 1, concurrent: the tanks are spread over `nstreams` worker
  * threads, each driving its own HIP stream (created here, default priority),
- * so the kernels of different tanks overlap on the device.  Work recorded on
- * the caller's `stream` before the call is visible to the workers and the
- * caller's stream waits for all of them.  A tank's results do not depend on
- * which other tanks are in the batch.  per_tank_status / per_tank_iters: HOST
- * arrays of `count` (may be NULL).  Each tank step is transactional as in
- * sem_rk4_step; the call returns the first failing status. */
-sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, int32_t nstreams, sem_batch** out);
+ * each tank running sem_rk4_step.  Work recorded on the caller's `stream`
+ * before the call is visible to the workers and the caller's stream waits
+ * for all of them. */
+sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, int32_t nstreams, void* stream,
+                            sem_batch** out);
 sem_status sem_batch_rk4_step(sem_batch* batch, double* const* eta, double* const* phi_s,
                               double* const* phi_ws, const double* dt_host,
                               const uint8_t* active_host, const sem_solve_opts* opts,
                               int32_t* per_tank_status_host, int32_t* per_tank_iters_host,
                               void* stream);
+/* Lockstep batches only: the Laplace problem of every active tank, as
+ * sem_laplace_solve (phi[t] holds the start vector when opts->warm_start). */
+sem_status sem_batch_laplace_solve(sem_batch* batch, const double* const* eta,
+                                   const double* const* eta_x, const double* const* phi_s,
+                                   double* const* phi, const uint8_t* active_host,
+                                   const sem_solve_opts* opts, int32_t* per_tank_status_host,
+                                   int32_t* per_tank_iters_host, void* stream);
 void sem_batch_destroy(sem_batch* batch);
 
 /* Self-test of the matrix-core instructions' lane layout: runs one 16x16x4

@@ -1,0 +1,546 @@
+// Batches of independent tanks (sem_batch_*).
+//
+// Lockstep mode (nstreams = 0): the Laplace solves of all tanks run as one
+// restarted GMRES in lockstep.  Every launch of an Arnoldi step covers the
+// workgroups of all tanks (a work-item table per launch: tank, block), each
+// tank keeps its own Krylov scalars and leaves the step launches as soon as
+// its own cycle is done, so a tank's arithmetic is exactly the single-tank
+// solve's.  Kernels of one tank therefore overlap with those of all others,
+// and a step costs one launch per kernel for the whole batch.
+//
+// Concurrent mode (nstreams >= 1): each tank runs its own single-tank step;
+// the tanks are spread over worker threads with one HIP stream each.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "launch.hpp"
+#include "mesh.hpp"
+#include "sem_internal.hpp"
+
+using namespace sem;
+
+namespace {
+// pointer tables handed to the batched kernels, each [count]
+enum { PT_PHIS = 0, PT_WS = 1, PT_YP = 2, PT_COUNT = 3 };
+// staging copies of the live flags: a copy is reused only after the stream
+// has drained, so an earlier asynchronous upload never reads a later set
+constexpr int kLiveSlots = 16;
+}  // namespace
+
+struct sem_batch {
+  std::vector<sem_mesh*> meshes;
+  int nstreams = 0;
+  // concurrent mode
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  hipEvent_t start = nullptr;
+  // lockstep mode
+  std::vector<TankDev> tanks;   // host copies of the descriptors (progress words redirected)
+  char* dmem = nullptr;         // device: descriptors, live flags, work items, pointer tables
+  TankDev* dtanks = nullptr;
+  int32_t* dlive = nullptr;
+  const double** dptr = nullptr;
+  char* hpin = nullptr;         // pinned host memory, mapped
+  int32_t* prog_host = nullptr;
+  int32_t* prog_dev = nullptr;
+  KrylovState* ks_host = nullptr;
+  KrylovState* ks_dev = nullptr;
+  int32_t* st_host = nullptr;
+  int32_t* st_dev = nullptr;
+  int32_t* live_host = nullptr;   // kLiveSlots staging copies of the live flags
+  int live_slot = 0, live_pending = 0;
+  const double** ptr_host = nullptr;
+  BatchStage vec, dots, fixup, per_tank;
+  BatchStage stiff[kMaxOrder + 1];
+  BatchSD sdlap;
+  std::vector<int> orders;
+  int mmax = 0;
+  ~sem_batch() {
+    for (auto s : streams) (void)hipStreamDestroy(s);
+    for (auto e : events) (void)hipEventDestroy(e);
+    if (start) (void)hipEventDestroy(start);
+    if (dmem) (void)hipFree(dmem);
+    if (hpin) (void)hipHostFree(hpin);
+  }
+};
+
+// ------------------------------------------------------------ set-up
+static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
+  const int count = (int)B->meshes.size();
+  for (int t = 0; t < count; ++t) {
+    const sem_mesh* M = B->meshes[t];
+    if (M->hd.pre_kind != 1 || !M->hd.use_mfma)
+      return fail(SEM_E_INVAL, "lockstep batches need tanks with the exact still-water inverse and the matrix-core "
+                               "stiffness kernel (variant 0); use nstreams >= 1 for the others");
+  }
+  // pinned host area: progress words, Krylov states, status words, live flags, pointer tables
+  const size_t o_prog = 0;
+  const size_t o_ks = (o_prog + count * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t o_st = (o_ks + count * sizeof(KrylovState) + 255) / 256 * 256;
+  const size_t o_live = (o_st + count * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t o_ptr = (o_live + (size_t)kLiveSlots * count * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t hbytes = o_ptr + (size_t)PT_COUNT * count * sizeof(double*);
+  void* hp = nullptr;
+  HIPCHK(hipHostMalloc(&hp, hbytes, hipHostMallocMapped | hipHostMallocCoherent));
+  B->hpin = (char*)hp;
+  std::memset(hp, 0, hbytes);
+  void* dp = nullptr;
+  HIPCHK(hipHostGetDevicePointer(&dp, hp, 0));
+  char* hd = (char*)dp;
+  B->prog_host = (int32_t*)(B->hpin + o_prog);
+  B->prog_dev = (int32_t*)(hd + o_prog);
+  B->ks_host = (KrylovState*)(B->hpin + o_ks);
+  B->ks_dev = (KrylovState*)(hd + o_ks);
+  B->st_host = (int32_t*)(B->hpin + o_st);
+  B->st_dev = (int32_t*)(hd + o_st);
+  B->live_host = (int32_t*)(B->hpin + o_live);
+  B->ptr_host = (const double**)(B->hpin + o_ptr);
+  // descriptors with the progress words redirected to the batch's array
+  B->tanks.resize(count);
+  std::vector<int> ids(count);
+  for (int t = 0; t < count; ++t) {
+    B->tanks[t] = B->meshes[t]->hd;
+    B->tanks[t].prog = B->prog_dev + t;
+    B->mmax = std::max(B->mmax, B->tanks[t].m);
+    ids[t] = t;
+  }
+  // work-item tables
+  for (int t = 0; t < count; ++t) {
+    const TankDev& h = B->tanks[t];
+    const int nv = (int)((h.n + kBlockThreads - 1) / kBlockThreads);
+    for (int x = 0; x < nv; ++x) B->vec.items.push_back(BatchItem{t, x, 0, nv});
+    const int nd = dot_nchunk(h.n);
+    for (int x = 0; x < nd; ++x) B->dots.items.push_back(BatchItem{t, x, 0, nd});
+    const int nf = (h.nb * h.nl + kBlockThreads - 1) / kBlockThreads;
+    for (int x = 0; x < nf; ++x) B->fixup.items.push_back(BatchItem{t, x, 0, nf});
+    B->per_tank.items.push_back(BatchItem{t, 0, 0, 1});
+  }
+  for (int P = 1; P <= kMaxOrder; ++P) {
+    plan_stiff(B->tanks, ids, P, 0, &B->stiff[P]);
+    if (!B->stiff[P].items.empty()) B->orders.push_back(P);
+  }
+  plan_sd(B->tanks, ids, 0, 0, &B->sdlap);
+  std::vector<BatchStage*> stages = {&B->vec, &B->dots, &B->fixup, &B->per_tank};
+  for (int P : B->orders) stages.push_back(&B->stiff[P]);
+  for (BatchStage* s : {&B->sdlap.cond, &B->sdlap.modes, &B->sdlap.fa, &B->sdlap.fb, &B->sdlap.fsolve,
+                        &B->sdlap.wall, &B->sdlap.wmodes, &B->sdlap.fc, &B->sdlap.fd, &B->sdlap.idft,
+                        &B->sdlap.back})
+    stages.push_back(s);
+  // one device buffer: descriptors | live flags | pointer tables | item tables
+  size_t off = (size_t)count * sizeof(TankDev);
+  const size_t o_live_d = (off + 255) / 256 * 256;
+  off = o_live_d + count * sizeof(int32_t);
+  const size_t o_ptr_d = (off + 255) / 256 * 256;
+  off = o_ptr_d + (size_t)PT_COUNT * count * sizeof(double*);
+  std::vector<size_t> o_items;
+  for (BatchStage* s : stages) {
+    off = (off + 255) / 256 * 256;
+    o_items.push_back(off);
+    off += s->items.size() * sizeof(BatchItem);
+  }
+  void* dm = nullptr;
+  HIPCHK(hipMalloc(&dm, off));
+  B->dmem = (char*)dm;
+  B->dtanks = (TankDev*)B->dmem;
+  B->dlive = (int32_t*)(B->dmem + o_live_d);
+  B->dptr = (const double**)(B->dmem + o_ptr_d);
+  HIPCHK(hipMemcpyAsync(B->dtanks, B->tanks.data(), count * sizeof(TankDev), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(B->dlive, 0, count * sizeof(int32_t), st));
+  for (size_t i = 0; i < stages.size(); ++i) {
+    BatchStage* s = stages[i];
+    s->dev = (const BatchItem*)(B->dmem + o_items[i]);
+    if (!s->items.empty())
+      HIPCHK(hipMemcpyAsync(B->dmem + o_items[i], s->items.data(), s->items.size() * sizeof(BatchItem),
+                            hipMemcpyHostToDevice, st));
+  }
+  // the stage potentials of the RK4 steps (table PT_YP) never move
+  for (int t = 0; t < count; ++t) B->ptr_host[PT_YP * count + t] = B->meshes[t]->rk + B->meshes[t]->ns;
+  HIPCHK(hipMemcpyAsync(B->dptr + (size_t)PT_YP * count, B->ptr_host + (size_t)PT_YP * count,
+                        count * sizeof(double*), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SEM_OK;
+}
+
+static sem_status drain(sem_batch* B, hipStream_t st) {
+  HIPCHK(hipStreamSynchronize(st));
+  B->live_pending = 0;
+  return SEM_OK;
+}
+
+// live flags of the tanks that take part in the next launches
+static sem_status set_live(sem_batch* B, const std::vector<int>& live, hipStream_t st) {
+  const int count = (int)B->meshes.size();
+  if (B->live_pending == kLiveSlots) {
+    sem_status s = drain(B, st);
+    if (s) return s;
+  }
+  int32_t* h = B->live_host + (size_t)B->live_slot * count;
+  B->live_slot = (B->live_slot + 1) % kLiveSlots;
+  B->live_pending++;
+  std::fill(h, h + count, 0);
+  for (int t : live) h[t] = 1;
+  HIPCHK(hipMemcpyAsync(B->dlive, h, count * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  return SEM_OK;
+}
+
+static sem_status put_pointers(sem_batch* B, int which, const double* const* p, hipStream_t st) {
+  const int count = (int)B->meshes.size();
+  for (int t = 0; t < count; ++t) B->ptr_host[which * count + t] = p ? p[t] : nullptr;
+  HIPCHK(hipMemcpyAsync(B->dptr + (size_t)which * count, B->ptr_host + (size_t)which * count,
+                        count * sizeof(double*), hipMemcpyHostToDevice, st));
+  return SEM_OK;
+}
+
+// ------------------------------------------------------------ lockstep GMRES
+// Restarted right-preconditioned GMRES on every tank in `act`, b and the
+// start vector xs already in each tank's workspace.  iters[t] accumulates.
+// Tanks whose status word is set leave `act`.
+static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rtol, int max_iter, int ahead,
+                                 std::vector<int32_t>& iters, hipStream_t st) {
+  if (act.empty()) return SEM_OK;
+  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  volatile int32_t* prog = B->prog_host;
+  ahead = std::max(1, ahead);
+  sem_status s = set_live(B, act, st);
+  if (s) return s;
+  launch_ks_init_b(a, B->per_tank, rtol, st);
+  launch_dots_b(a, B->dots, 1, VSel{BV_B, 0}, VSel{BV_B, 0}, -1, 1, 0, 0, 0, st);
+  std::vector<int> live = act;
+  bool first = true;
+  while (true) {
+    for (int t : live) prog[t] = 0;
+    // r = b - A x
+    for (int P : B->orders) launch_stiff_b(a, B->stiff[P], P, VSel{BV_XS, 0}, VSel{BV_W, 0}, F_MASK_SURF, 0, st);
+    launch_fixup_b(a, B->fixup, VSel{BV_W, 0}, F_MASK_SURF, 0, st);
+    launch_residual_b(a, B->vec, VSel{BV_B, 0}, VSel{BV_W, 0}, VSel{BV_V, 0}, 0, st);
+    launch_dots_b(a, B->dots, 1, VSel{BV_V, 0}, VSel{BV_V, 0}, -1, 0, 0, 0, 0, st);
+    launch_cycle_start_b(a, B->per_tank, B->vec, first ? 1 : 0, 0, st);
+    first = false;
+    for (int j = 0; j < B->mmax; ++j) {
+      // z_j = M^-1 v_j; for j > 0 v_j = w / ||w|| is formed on the way
+      launch_sd_b(a, B->sdlap, 0, j == 0 ? VSel{BV_V, 0} : VSel{BV_W, 0}, VSel{BV_Z, j}, j, 1, 0, st);
+      for (int P : B->orders)
+        launch_stiff_b(a, B->stiff[P], P, VSel{BV_Z, j}, VSel{BV_W, 0}, F_MASK_SURF | F_GATE | F_NOFIX, 0, st);
+      launch_dots_b(a, B->dots, j + 1, VSel{BV_V, 0}, VSel{BV_W, 0}, j, 0, 1, 1, 0, st);
+      launch_orth_b(a, B->dots, j, 0, st);
+      // queue at most `ahead` steps in front of the slowest running tank
+      bool stop = false;
+      auto tq = std::chrono::steady_clock::now();
+      while (true) {
+        bool all_done = true;
+        int minsteps = INT_MAX;
+        for (int t : live) {
+          const int32_t v = prog[t];
+          if (!(v & PROG_DONE)) {
+            all_done = false;
+            minsteps = std::min(minsteps, v & PROG_STEPS);
+          }
+        }
+        if (all_done) {
+          stop = true;
+          break;
+        }
+        if (j + 1 - minsteps <= ahead) break;
+        auto now = std::chrono::steady_clock::now();
+        if (now - tq > std::chrono::microseconds(100)) {
+          tq = now;
+          hipError_t q = hipStreamQuery(st);
+          if (q == hipSuccess) break;   // drained: the words are final, re-read them next step
+          if (q != hipErrorNotReady) HIPCHK(q);
+        }
+        __builtin_ia32_pause();
+      }
+      if (stop) break;
+    }
+    launch_solve_update_b(a, B->per_tank, B->vec, VSel{BV_XS, 0}, 0, st);
+    launch_state_out_b(a, B->per_tank, B->ks_dev, B->st_dev, 0, st);
+    s = drain(B, st);
+    if (s) return s;
+    std::vector<int> next;
+    for (int t : live) {
+      const KrylovState& k = B->ks_host[t];
+      if (B->st_host[t] || k.status || k.converged || k.iters >= max_iter) continue;
+      next.push_back(t);
+    }
+    if (next.empty()) break;
+    live.swap(next);
+    s = set_live(B, live, st);
+    if (s) return s;
+  }
+  // final states of every tank of the solve; unconverged ones are marked
+  s = set_live(B, act, st);
+  if (s) return s;
+  launch_state_out_b(a, B->per_tank, B->ks_dev, B->st_dev, 1, st);
+  s = drain(B, st);
+  if (s) return s;
+  std::vector<int> keep;
+  for (int t : act) {
+    iters[t] += B->ks_host[t].iters;
+    if (!B->st_host[t]) keep.push_back(t);
+  }
+  act.swap(keep);
+  return SEM_OK;
+}
+
+// Laplace solves of the tanks in `act` with their factors current: lift from
+// the surface potentials (pointer table PT_PHIS or PT_YP), GMRES, Phi out to
+// the PT_WS table's vectors (which hold the start vectors on entry when warm).
+static sem_status lockstep_laplace(sem_batch* B, std::vector<int>& act, int phis_table, int warm,
+                                   const sem_solve_opts& o, std::vector<int32_t>& iters, hipStream_t st) {
+  const int count = (int)B->meshes.size();
+  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  sem_status s = set_live(B, act, st);
+  if (s) return s;
+  const double* const* phis = B->dptr + (size_t)phis_table * count;
+  launch_lift_in_b(a, B->vec, phis, warm ? B->dptr + (size_t)PT_WS * count : nullptr, st);
+  for (int P : B->orders)
+    launch_stiff_b(a, B->stiff[P], P, VSel{BV_TMP, 0}, VSel{BV_B, 0}, F_MASK_SURF | F_NEG, 0, st);
+  launch_fixup_b(a, B->fixup, VSel{BV_B, 0}, F_MASK_SURF | F_NEG, 0, st);
+  std::vector<int> solved = act;
+  s = lockstep_gmres(B, act, o.rtol, o.max_iter, o.lookahead, iters, st);
+  if (s) return s;
+  s = set_live(B, solved, st);
+  if (s) return s;
+  launch_solution_out_b(a, B->vec, phis, const_cast<double* const*>(B->dptr + (size_t)PT_WS * count), st);
+  return SEM_OK;
+}
+
+static sem_status check_opts(const sem_solve_opts* opts, sem_solve_opts* o) {
+  if (opts) *o = *opts;
+  else default_opts(o);
+  if (!(o->rtol > 0) || o->max_iter < 1) return fail(SEM_E_INVAL, "rtol > 0 and max_iter >= 1 required");
+  if (o->prec != SEM_PREC_FP64) return fail(SEM_E_INVAL, "lockstep batches solve in FP64");
+  return SEM_OK;
+}
+
+static sem_status lockstep_solve(sem_batch* B, const double* const* eta, const double* const* eta_x,
+                                 const double* const* phi_s, double* const* phi, const uint8_t* active,
+                                 const sem_solve_opts* opts, int32_t* per_status, int32_t* per_iters,
+                                 hipStream_t st) {
+  const int count = (int)B->meshes.size();
+  sem_solve_opts o;
+  sem_status s = check_opts(opts, &o);
+  if (s) return s;
+  std::vector<int> act;
+  for (int t = 0; t < count; ++t) {
+    if (active && !active[t]) continue;
+    if (!eta[t] || !eta_x[t] || !phi_s[t] || !phi[t]) return fail(SEM_E_INVAL, "null per-tank argument");
+    act.push_back(t);
+  }
+  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  s = put_pointers(B, PT_PHIS, phi_s, st);
+  if (!s) s = put_pointers(B, PT_WS, (const double* const*)phi, st);
+  if (s) return s;
+  std::vector<int> all = act;
+  s = set_live(B, act, st);
+  if (s) return s;
+  launch_status_clear_b(a, B->per_tank, st);
+  for (int t : act) launch_coef(B->meshes[t]->hd, B->meshes[t]->dtank, eta[t], eta_x[t], 3, st);
+  std::vector<int32_t> iters(count, 0);
+  s = lockstep_laplace(B, act, PT_PHIS, o.warm_start, o, iters, st);
+  if (s) return s;
+  s = set_live(B, all, st);
+  if (s) return s;
+  launch_state_out_b(a, B->per_tank, B->ks_dev, B->st_dev, 0, st);
+  s = drain(B, st);
+  if (s) return s;
+  sem_status worst = SEM_OK;
+  for (int t = 0; t < count; ++t) {
+    const bool on = !active || active[t];
+    const sem_status ts = on ? status_from_word(B->st_host[t]) : SEM_OK;
+    if (per_status) per_status[t] = ts;
+    if (per_iters) per_iters[t] = on ? iters[t] : 0;
+    if (ts != SEM_OK && worst == SEM_OK) worst = ts;
+  }
+  if (worst != SEM_OK) return fail(worst, "at least one tank failed; see per_tank_status");
+  return SEM_OK;
+}
+
+static sem_status lockstep_rk4(sem_batch* B, double* const* eta, double* const* phi_s, double* const* phi_ws,
+                               const double* dt, const uint8_t* active, const sem_solve_opts* opts,
+                               int32_t* per_status, int32_t* per_iters, hipStream_t st) {
+  const int count = (int)B->meshes.size();
+  sem_solve_opts o;
+  sem_status s = check_opts(opts, &o);
+  if (s) return s;
+  std::vector<int> act;
+  for (int t = 0; t < count; ++t)
+    if (!active || active[t]) act.push_back(t);
+  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  s = put_pointers(B, PT_PHIS, (const double* const*)phi_s, st);
+  if (!s) s = put_pointers(B, PT_WS, (const double* const*)phi_ws, st);
+  if (s) return s;
+  const std::vector<int> all = act;
+  s = set_live(B, act, st);
+  if (s) return s;
+  launch_status_clear_b(a, B->per_tank, st);
+  std::vector<int32_t> iters(count, 0);
+  const double cnode[4] = {0.0, 0.5, 0.5, 1.0};
+  const double wts[4] = {1.0 / 6, 2.0 / 6, 2.0 / 6, 1.0 / 6};
+  for (int sidx = 0; sidx < 4 && !act.empty(); ++sidx) {
+    for (int t : act) {
+      sem_mesh* M = B->meshes[t];
+      const int ns = (int)M->ns;
+      double* rk = M->rk;
+      const double* se = sidx == 0 ? eta[t] : rk;
+      const double* sp = sidx == 0 ? phi_s[t] : rk + ns;
+      launch_recover_dx(M->hd, M->dtank, se, rk + 2 * ns, sp, rk + 3 * ns, st);
+      launch_coef(M->hd, M->dtank, se, rk + 2 * ns, 3, st);
+    }
+    s = lockstep_laplace(B, act, sidx == 0 ? PT_PHIS : PT_YP, 1, o, iters, st);
+    if (s) return s;
+    for (int t : act) {
+      sem_mesh* M = B->meshes[t];
+      const int ns = (int)M->ns;
+      double* rk = M->rk;
+      const double* se = sidx == 0 ? eta[t] : rk;
+      s = recover_w_core(M, phi_ws[t], rk + 4 * ns, st);
+      if (s) return s;
+      launch_fs_rhs(M->hd, M->dtank, se, rk + 2 * ns, rk + 3 * ns, rk + 4 * ns, rk + 5 * ns, rk + 6 * ns, st);
+      if (sidx < 3)
+        launch_rk4_stage(ns, cnode[sidx + 1] * dt[t], wts[sidx], sidx == 0, eta[t], phi_s[t], rk + 5 * ns,
+                         rk + 6 * ns, rk, rk + ns, rk + 7 * ns, rk + 8 * ns, st);
+      else
+        launch_rk4_stage(ns, 0.0, wts[sidx], 0, eta[t], phi_s[t], rk + 5 * ns, rk + 6 * ns, rk, rk + ns,
+                         rk + 7 * ns, rk + 8 * ns, st);
+    }
+  }
+  for (int t : act) {
+    sem_mesh* M = B->meshes[t];
+    const int ns = (int)M->ns;
+    launch_rk4_final(M->hd, M->dtank, dt[t], M->rk + 7 * ns, M->rk + 8 * ns, eta[t], phi_s[t], M->sf != 1.0 ? 1 : 0,
+                     st);
+  }
+  s = set_live(B, all, st);
+  if (s) return s;
+  launch_state_out_b(a, B->per_tank, B->ks_dev, B->st_dev, 0, st);
+  s = drain(B, st);
+  if (s) return s;
+  sem_status worst = SEM_OK;
+  for (int t = 0; t < count; ++t) {
+    const bool on = !active || active[t];
+    const sem_status ts = on ? status_from_word(B->st_host[t]) : SEM_OK;
+    if (per_status) per_status[t] = ts;
+    if (per_iters) per_iters[t] = on ? iters[t] : 0;
+    if (ts != SEM_OK && worst == SEM_OK) worst = ts;
+  }
+  if (worst != SEM_OK) return fail(worst, "at least one tank failed; see per_tank_status");
+  return SEM_OK;
+}
+
+// ------------------------------------------------------------ concurrent mode
+static sem_status concurrent_rk4(sem_batch* B, double* const* eta, double* const* phi_s, double* const* phi_ws,
+                                 const double* dt, const uint8_t* active, const sem_solve_opts* opts,
+                                 int32_t* per_status, int32_t* per_iters, hipStream_t cst) {
+  const int count = (int)B->meshes.size();
+  // inputs written on the caller's stream must be visible to the workers
+  HIPCHK(hipEventRecord(B->start, cst));
+  const int W = (int)B->streams.size();
+  for (int w = 0; w < W; ++w) HIPCHK(hipStreamWaitEvent(B->streams[w], B->start, 0));
+  // largest tanks first, dealt to the least-loaded worker
+  std::vector<int> order;
+  for (int i = 0; i < count; ++i)
+    if (!active || active[i]) order.push_back(i);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return B->meshes[a]->n > B->meshes[b]->n; });
+  std::vector<std::vector<int>> work(W);
+  std::vector<double> load(W, 0.0);
+  for (int i : order) {
+    int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    work[w].push_back(i);
+    load[w] += (double)B->meshes[i]->n;
+  }
+  std::vector<sem_status> res(count, SEM_OK);
+  std::vector<int32_t> its(count, 0);
+  auto run = [&](int w) {
+    for (int i : work[w]) {
+      sem_solve_stats st4[4] = {};
+      res[i] = sem_rk4_step(B->meshes[i], eta[i], phi_s[i], phi_ws[i], dt[i], opts, st4, B->streams[w]);
+      its[i] = st4[0].iters + st4[1].iters + st4[2].iters + st4[3].iters;
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < W; ++w) th.emplace_back(run, w);
+  run(0);
+  for (auto& t : th) t.join();
+  for (int w = 0; w < W; ++w) {
+    HIPCHK(hipEventRecord(B->events[w], B->streams[w]));
+    HIPCHK(hipStreamWaitEvent(cst, B->events[w], 0));
+  }
+  sem_status worst = SEM_OK;
+  for (int i = 0; i < count; ++i) {
+    if (per_status) per_status[i] = (active && !active[i]) ? SEM_OK : res[i];
+    if (per_iters) per_iters[i] = its[i];
+    if (res[i] != SEM_OK && worst == SEM_OK) worst = res[i];
+  }
+  if (worst != SEM_OK) return fail(worst, "at least one tank failed; see per_tank_status");
+  return SEM_OK;
+}
+
+// ------------------------------------------------------------ public calls
+extern "C" sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, int32_t nstreams, void* stream,
+                                       sem_batch** out) {
+  if (!meshes || count < 1 || !out) return fail(SEM_E_INVAL, "bad batch arguments");
+  if (nstreams < 0 || nstreams > 64) return fail(SEM_E_INVAL, "nstreams must be in 0..64");
+  for (int i = 0; i < count; ++i)
+    if (!meshes[i] || !meshes[i]->bound) return fail(SEM_E_INVAL, "every mesh must be bound");
+  for (int i = 0; i < count; ++i)
+    for (int j = i + 1; j < count; ++j)
+      if (meshes[i] == meshes[j]) return fail(SEM_E_INVAL, "a mesh appears twice in the batch");
+  std::unique_ptr<sem_batch> B(new (std::nothrow) sem_batch());
+  if (!B) return fail(SEM_E_NOMEM, "host allocation failed");
+  B->meshes.assign(meshes, meshes + count);
+  B->nstreams = nstreams;
+  if (nstreams == 0) {
+    sem_status s = setup_lockstep(B.get(), (hipStream_t)stream);
+    if (s) return s;
+  } else {
+    int ns = std::min<int>(nstreams, count);
+    for (int i = 0; i < ns; ++i) {
+      hipStream_t st;
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      B->streams.push_back(st);
+      hipEvent_t ev;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      B->events.push_back(ev);
+    }
+    HIPCHK(hipEventCreateWithFlags(&B->start, hipEventDisableTiming));
+  }
+  *out = B.release();
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_batch_rk4_step(sem_batch* B, double* const* eta, double* const* phi_s,
+                                         double* const* phi_ws, const double* dt, const uint8_t* active,
+                                         const sem_solve_opts* opts, int32_t* per_status, int32_t* per_iters,
+                                         void* stream) {
+  if (!B || !eta || !phi_s || !phi_ws || !dt) return fail(SEM_E_INVAL, "null argument");
+  const int count = (int)B->meshes.size();
+  for (int i = 0; i < count; ++i) {
+    if (active && !active[i]) continue;
+    if (!eta[i] || !phi_s[i] || !phi_ws[i] || !(dt[i] > 0) || !std::isfinite(dt[i]))
+      return fail(SEM_E_INVAL, "bad per-tank argument");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (B->nstreams == 0) return lockstep_rk4(B, eta, phi_s, phi_ws, dt, active, opts, per_status, per_iters, st);
+  return concurrent_rk4(B, eta, phi_s, phi_ws, dt, active, opts, per_status, per_iters, st);
+}
+
+extern "C" sem_status sem_batch_laplace_solve(sem_batch* B, const double* const* eta, const double* const* eta_x,
+                                              const double* const* phi_s, double* const* phi, const uint8_t* active,
+                                              const sem_solve_opts* opts, int32_t* per_status, int32_t* per_iters,
+                                              void* stream) {
+  if (!B || !eta || !eta_x || !phi_s || !phi) return fail(SEM_E_INVAL, "null argument");
+  if (B->nstreams != 0) return fail(SEM_E_INVAL, "batched Laplace solves need a lockstep batch (nstreams = 0)");
+  return lockstep_solve(B, eta, eta_x, phi_s, phi, active, opts, per_status, per_iters, (hipStream_t)stream);
+}
+
+extern "C" void sem_batch_destroy(sem_batch* B) { delete B; }

@@ -304,10 +304,8 @@ k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict_
 
 // adds the right-line contributions of each block to the stored left lines
 template <typename T>
-__global__ void k_fixup(const TankDev* __restrict__ td, T* __restrict__ y, const T* __restrict__ side, int flags) {
-  const TankDev& d = *td;
-  if ((flags & F_GATE) && d.ks->done) return;
-  int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fixup_body(const TankDev& d, T* __restrict__ y, const T* __restrict__ side, int bx) {
+  int gid = bx * blockDim.x + threadIdx.x;
   if (gid >= d.nb * d.nl) return;
   int b = gid / d.nl, ql = gid - b * d.nl;
   // side[b] belongs to the line at x_{c0 + cbb}
@@ -321,6 +319,13 @@ __global__ void k_fixup(const TankDev* __restrict__ td, T* __restrict__ y, const
   } else {
     y[(int64_t)d.nx * d.nc + ql] = v;   // the wall line has one contribution
   }
+}
+
+template <typename T>
+__global__ void k_fixup(const TankDev* __restrict__ td, T* __restrict__ y, const T* __restrict__ side, int flags) {
+  const TankDev& d = *td;
+  if ((flags & F_GATE) && d.ks->done) return;
+  fixup_body<T>(d, y, side, blockIdx.x);
 }
 
 // ------------------------------------------------------------ vector kernels
@@ -396,25 +401,27 @@ __device__ inline void publish_progress(const KrylovState* ks, int32_t* mirror) 
 }
 
 
-__device__ inline bool last_block(int32_t* counter) {
+// nblk: the workgroups taking part (the tank's own grid in a batched launch)
+__device__ inline bool last_block(int32_t* counter, int nblk) {
   __shared__ int is_last;
   __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
+  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1) == nblk - 1);
   __syncthreads();
   if (is_last) __threadfence();
   return is_last != 0;
 }
 
+// Workgroup bx of nblk: partial products of its chunk, the last workgroup
+// adds the partials.  Shared by the single-tank and the batched kernels.
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, T* __restrict__ w,
-             double* __restrict__ part, int ldp, double* __restrict__ out, int64_t chunk,
-             int32_t* __restrict__ counter, const KrylovState* __restrict__ gate,
-             const TankDev* __restrict__ fixd, const T* __restrict__ side) {
+__device__ __forceinline__ void dots_body(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx,
+                                          T* __restrict__ w, double* __restrict__ part, int ldp,
+                                          double* __restrict__ out, int64_t chunk, int32_t* __restrict__ counter,
+                                          const TankDev* __restrict__ fixd, const T* __restrict__ side, int bx,
+                                          int nblk) {
   __shared__ double red[4][kMaxVec];
-  if (gate && gate->done) return;
-  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
+  const int64_t lo = (int64_t)bx * chunk, hi = min(lo + chunk, n);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (fixd) {
     // w is an operator output whose shared-line contributions are still in
@@ -455,29 +462,39 @@ k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, T* __res
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nvec; k += blockDim.x)
-    part[(size_t)blockIdx.x * ldp + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-  if (!last_block(counter)) return;
+    part[(size_t)bx * ldp + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  if (!last_block(counter, nblk)) return;
   // final sums: wave w takes vectors w, w+4, ...; lanes stride over the
   // workgroup partials in a fixed order, then a butterfly
   for (int k = wv; k < nvec; k += kBlockThreads / 64) {
     double t = 0;
-    for (int b2 = lane; b2 < (int)gridDim.x; b2 += 64) t += part[(size_t)b2 * ldp + k];
+    for (int b2 = lane; b2 < nblk; b2 += 64) t += part[(size_t)b2 * ldp + k];
     t = wave_sum(t);
     if (lane == 0) out[k] = t;
   }
   if (threadIdx.x == 0) *counter = 0;
 }
 
-// w' = w - sum_{i<=j} h_i V_i; ||w'||^2 reduced; Givens update of column j
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase, int m, T* __restrict__ w,
-             double* __restrict__ part, int ldp, int64_t chunk, KrylovState* __restrict__ ks,
-             int32_t* __restrict__ counter, int32_t* __restrict__ status, int32_t* __restrict__ mirror) {
+k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, T* __restrict__ w,
+             double* __restrict__ part, int ldp, double* __restrict__ out, int64_t chunk,
+             int32_t* __restrict__ counter, const KrylovState* __restrict__ gate,
+             const TankDev* __restrict__ fixd, const T* __restrict__ side) {
+  if (gate && gate->done) return;
+  dots_body<T>(n, nvec, X, ldx, w, part, ldp, out, chunk, counter, fixd, side, blockIdx.x, gridDim.x);
+}
+
+// w' = w - sum_{i<=j} h_i V_i; ||w'||^2 reduced; Givens update of column j
+template <typename T>
+__device__ __forceinline__ void orth_body(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase,
+                                          int m, T* __restrict__ w, double* __restrict__ part, int ldp,
+                                          int64_t chunk, KrylovState* __restrict__ ks, int32_t* __restrict__ counter,
+                                          int32_t* __restrict__ status, int32_t* __restrict__ mirror, int bx,
+                                          int nblk) {
   __shared__ double red[4];
-  if (ks->done) return;
   const double* hcol = Hbase + (size_t)j * (m + 1);
-  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
+  const int64_t lo = (int64_t)bx * chunk, hi = min(lo + chunk, n);
   double sacc = 0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     double v = w[i];
@@ -496,11 +513,11 @@ k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hba
   sacc = wave_sum(sacc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sacc;
   __syncthreads();
-  if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp] = ((red[0] + red[1]) + red[2]) + red[3];
-  if (!last_block(counter)) return;
+  if (threadIdx.x == 0) part[(size_t)bx * ldp] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (!last_block(counter, nblk)) return;
   if (threadIdx.x < 64) {
     double t = 0;
-    for (int b2 = threadIdx.x; b2 < (int)gridDim.x; b2 += 64) t += part[(size_t)b2 * ldp];
+    for (int b2 = threadIdx.x; b2 < nblk; b2 += 64) t += part[(size_t)b2 * ldp];
     t = wave_sum(t);
     if (threadIdx.x == 0) {
       givens_update(ks, Hbase, m, j, t, status);
@@ -508,6 +525,15 @@ k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hba
       publish_progress(ks, mirror);
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase, int m, T* __restrict__ w,
+             double* __restrict__ part, int ldp, int64_t chunk, KrylovState* __restrict__ ks,
+             int32_t* __restrict__ counter, int32_t* __restrict__ status, int32_t* __restrict__ mirror) {
+  if (ks->done) return;
+  orth_body<T>(n, j, V, Hbase, m, w, part, ldp, chunk, ks, counter, status, mirror, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------ GMRES pieces
@@ -668,6 +694,176 @@ __global__ void k_to_float(int64_t n, const double* __restrict__ r, double scale
 __global__ void k_add_float(int64_t n, const float* __restrict__ x32, double scale, double* __restrict__ x) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] += scale * (double)x32[i];
+}
+
+// ------------------------------------------------------------ batched Krylov steps
+// products of nvec vectors (from X, stride n) with w; out = H column hcol,
+// or the tank's scalars from index sidx when hcol < 0
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_dots_b(BatchArgs ba, int nvec, VSel X, VSel w, int hcol, int sidx, int fix, int gate) {
+  SEM_BATCH_TANK(ba)
+  if (gate && d.ks->done) return;
+  double* out = hcol >= 0 ? d.H + (size_t)hcol * (d.m + 1) : d.scal + sidx;
+  dots_body<T>(d.n, nvec, bvec<T>(d, X), d.n, bvec<T>(d, w), d.part, d.m + 2, out, dot_chunk(d.n), &d.ks->pad[0],
+               fix ? &d : nullptr, fix ? reinterpret_cast<const T*>(d.side) : nullptr, it_.bx, it_.nbx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_orth_b(BatchArgs ba, int j) {
+  SEM_BATCH_TANK(ba)
+  if (d.ks->done) return;
+  orth_body<T>(d.n, j, bvec<T>(d, VSel{BV_V, 0}), d.H, d.m, bvec<T>(d, VSel{BV_W, 0}), d.part, d.m + 2,
+               dot_chunk(d.n), d.ks, &d.ks->pad[0], d.status, d.prog, it_.bx, it_.nbx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_fixup_b(BatchArgs ba, VSel y, int flags) {
+  SEM_BATCH_TANK(ba)
+  if ((flags & F_GATE) && d.ks->done) return;
+  fixup_body<T>(d, bvec<T>(d, y), reinterpret_cast<const T*>(d.side), it_.bx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_residual_b(BatchArgs ba, VSel bsel, VSel ysel, VSel rsel) {
+  SEM_BATCH_TANK(ba)
+  const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const T* bv = bvec<T>(d, bsel);
+  const T* y = bvec<T>(d, ysel);
+  T v = bv[i] - y[i];
+  if (is_surface_node(d, i)) v = T(0);
+  bvec<T>(d, rsel)[i] = v;
+}
+
+// a tank whose status word is already set (e.g. a non-positive water column
+// found by the coefficient update) ends its solve at once
+__global__ void k_cycle_start_b(BatchArgs ba, int first) {
+  SEM_BATCH_TANK(ba)
+  if (threadIdx.x != 0) return;
+  if (*d.status) {
+    d.ks->done = 1;
+    d.ks->converged = 0;
+    d.ks->status |= *d.status;
+  } else {
+    cycle_start(d.ks, d.H, d.m, d.scal, first, d.status);
+  }
+  publish_progress(d.ks, d.prog);
+}
+
+// fresh Krylov state (including the reductions' completion counter)
+__global__ void k_ks_init_b(BatchArgs ba, double rtol) {
+  SEM_BATCH_TANK(ba)
+  if (threadIdx.x != 0) return;
+  KrylovState k{};
+  k.rtol = rtol;
+  *d.ks = k;
+}
+
+__global__ void k_status_clear_b(BatchArgs ba, int) {
+  SEM_BATCH_TANK(ba)
+  if (threadIdx.x == 0) *d.status = 0;
+}
+
+// end of a solve: unconverged tanks get the no-convergence bit; the Krylov
+// states and status words are copied to host-visible memory
+__global__ void k_state_out_b(BatchArgs ba, KrylovState* __restrict__ ks_out, int32_t* __restrict__ st_out,
+                              int mark_noconv) {
+  SEM_BATCH_TANK(ba)
+  if (threadIdx.x != 0) return;
+  const KrylovState k = *d.ks;
+  int32_t w = *d.status;
+  if (mark_noconv && !k.converged && !w) {
+    w |= ST_NOCONV;
+    *d.status = w;
+  }
+  ks_out[it_.tank] = k;
+  st_out[it_.tank] = w;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_scale_v0_b(BatchArgs ba, int) {
+  SEM_BATCH_TANK(ba)
+  const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
+  if (i >= d.n || d.ks->done) return;
+  T* V = bvec<T>(d, VSel{BV_V, 0});
+  V[i] = T((double)V[i] / d.ks->beta);
+}
+
+__global__ void k_solve_y_b(BatchArgs ba, int) {
+  SEM_BATCH_TANK(ba)
+  if (threadIdx.x != 0) return;
+  const int m = d.m;
+  const int jn = d.ks->j;
+  const double* H = d.H;
+  const double* g = d.H + (m + 1) * m + 2 * m;
+  double* y = d.H + (m + 1) * m + 2 * m + (m + 1) + m;
+  for (int i = jn - 1; i >= 0; --i) {
+    double sacc = g[i];
+    for (int k = i + 1; k < jn; ++k) sacc -= H[(size_t)k * (m + 1) + i] * y[k];
+    y[i] = sacc / H[(size_t)i * (m + 1) + i];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_update_x_b(BatchArgs ba, VSel xsel) {
+  SEM_BATCH_TANK(ba)
+  const int64_t n = d.n;
+  const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = d.m;
+  const double* y = d.H + (m + 1) * m + 2 * m + (m + 1) + m;
+  const T* Z = bvec<T>(d, VSel{BV_Z, 0});
+  T* x = bvec<T>(d, xsel);
+  const int jn = d.ks->j;
+  double v = x[i];
+  for (int k0 = 0; k0 < jn; k0 += 8) {
+    T zz[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) zz[u] = Z[(int64_t)min(k0 + u, jn - 1) * n + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < jn) v += y[k0 + u] * (double)zz[u];
+  }
+  x[i] = T(v);
+}
+
+// surface value of node i (x-ordered surface array phis), or -1 when i is
+// not a surface node
+__device__ inline int64_t surface_slot(const TankDev& d, int64_t i) {
+  const int64_t c = i / d.nc;
+  const int ql = (int)(i - c * d.nc);
+  if (!d.is_surf_loc[ql]) return -1;
+  int m = 0;
+  if (ql != d.nl - 1) {
+    for (int k = 1; k < d.P; ++k)
+      if (d.surf_loc[k] == ql) m = k;
+  }
+  return c * d.P + m;
+}
+
+// u = [0; phi~] (the lift's input) in the tank's tmp vector, and the start
+// vector xs = guess (masked at the surface) or 0
+__global__ void __launch_bounds__(kBlockThreads)
+k_lift_in_b(BatchArgs ba, const double* const* __restrict__ phis, const double* const* __restrict__ guess) {
+  SEM_BATCH_TANK(ba)
+  const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const int64_t sl = surface_slot(d, i);
+  const double* ps = phis[it_.tank];
+  const double* gs = guess ? guess[it_.tank] : nullptr;
+  d.tmp[i] = sl >= 0 ? ps[sl] : 0.0;
+  d.xs[i] = (sl >= 0 || !gs) ? 0.0 : gs[i];
+}
+
+// Phi = xs with the surface values put back
+__global__ void __launch_bounds__(kBlockThreads)
+k_solution_out_b(BatchArgs ba, const double* const* __restrict__ phis, double* const* __restrict__ phi) {
+  SEM_BATCH_TANK(ba)
+  const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const int64_t sl = surface_slot(d, i);
+  phi[it_.tank][i] = sl >= 0 ? phis[it_.tank][sl] : d.xs[i];
 }
 
 // ------------------------------------------------------------ 1D surface work
@@ -1264,6 +1460,69 @@ void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const float*
                      int mask, hipStream_t st) {
   hipLaunchKernelGGL(k_residual<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, d, n, b, y, r, mask);
 }
+// ------------------------------------------------------------ batched launchers
+static bool batch_args(const BatchArgs& a0, const BatchStage& p, BatchArgs* a) {
+  if (p.items.empty()) return false;
+  *a = a0;
+  a->items = p.dev;
+  return true;
+}
+#define SEM_BLAUNCH(P, KERN, ...)                                                                              \
+  do {                                                                                                       \
+    BatchArgs a_;                                                                                            \
+    if (batch_args(a0, P, &a_))                                                                              \
+      hipLaunchKernelGGL(KERN, dim3((unsigned)(P).items.size()), dim3(kBlockThreads), 0, st, a_, __VA_ARGS__); \
+  } while (0)
+
+void launch_dots_b(const BatchArgs& a0, const BatchStage& p, int nvec, VSel X, VSel w, int hcol, int sidx, int fix,
+                   int gate, int f32, hipStream_t st) {
+  if (f32) SEM_BLAUNCH(p, k_dots_b<float>, nvec, X, w, hcol, sidx, fix, gate);
+  else SEM_BLAUNCH(p, k_dots_b<double>, nvec, X, w, hcol, sidx, fix, gate);
+}
+void launch_orth_b(const BatchArgs& a0, const BatchStage& p, int j, int f32, hipStream_t st) {
+  if (f32) SEM_BLAUNCH(p, k_orth_b<float>, j);
+  else SEM_BLAUNCH(p, k_orth_b<double>, j);
+}
+void launch_fixup_b(const BatchArgs& a0, const BatchStage& p, VSel y, int flags, int f32, hipStream_t st) {
+  if (f32) SEM_BLAUNCH(p, k_fixup_b<float>, y, flags);
+  else SEM_BLAUNCH(p, k_fixup_b<double>, y, flags);
+}
+void launch_residual_b(const BatchArgs& a0, const BatchStage& p, VSel b, VSel y, VSel r, int f32, hipStream_t st) {
+  if (f32) SEM_BLAUNCH(p, k_residual_b<float>, b, y, r);
+  else SEM_BLAUNCH(p, k_residual_b<double>, b, y, r);
+}
+void launch_cycle_start_b(const BatchArgs& a0, const BatchStage& per_tank, const BatchStage& vec, int first, int f32,
+                          hipStream_t st) {
+  SEM_BLAUNCH(per_tank, k_cycle_start_b, first);
+  if (f32) SEM_BLAUNCH(vec, k_scale_v0_b<float>, 0);
+  else SEM_BLAUNCH(vec, k_scale_v0_b<double>, 0);
+}
+void launch_solve_update_b(const BatchArgs& a0, const BatchStage& per_tank, const BatchStage& vec, VSel x, int f32,
+                           hipStream_t st) {
+  SEM_BLAUNCH(per_tank, k_solve_y_b, 0);
+  if (f32) SEM_BLAUNCH(vec, k_update_x_b<float>, x);
+  else SEM_BLAUNCH(vec, k_update_x_b<double>, x);
+}
+void launch_ks_init_b(const BatchArgs& a0, const BatchStage& per_tank, double rtol, hipStream_t st) {
+  SEM_BLAUNCH(per_tank, k_ks_init_b, rtol);
+}
+void launch_status_clear_b(const BatchArgs& a0, const BatchStage& per_tank, hipStream_t st) {
+  SEM_BLAUNCH(per_tank, k_status_clear_b, 0);
+}
+void launch_state_out_b(const BatchArgs& a0, const BatchStage& per_tank, KrylovState* ks_out, int32_t* st_out,
+                        int mark_noconv, hipStream_t st) {
+  SEM_BLAUNCH(per_tank, k_state_out_b, ks_out, st_out, mark_noconv);
+}
+void launch_lift_in_b(const BatchArgs& a0, const BatchStage& vec, const double* const* phis,
+                      const double* const* guess, hipStream_t st) {
+  SEM_BLAUNCH(vec, k_lift_in_b, phis, guess);
+}
+void launch_solution_out_b(const BatchArgs& a0, const BatchStage& vec, const double* const* phis, double* const* phi,
+                           hipStream_t st) {
+  SEM_BLAUNCH(vec, k_solution_out_b, phis, phi);
+}
+#undef SEM_BLAUNCH
+
 void launch_to_float(int64_t n, const double* r, double scale, float* r32, hipStream_t st) {
   hipLaunchKernelGGL(k_to_float, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, r, scale, r32);
 }

@@ -16,6 +16,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "launch.hpp"
@@ -64,7 +65,7 @@ struct StiffArgs {
 };
 
 template <typename T>
-static StiffArgs<T> stiff_args(const TankDev& h, const void* G, const T* opf, int ops_in_lds) {
+__host__ __device__ inline StiffArgs<T> stiff_args(const TankDev& h, const void* G, const T* opf, int ops_in_lds) {
   StiffArgs<T> a;
   a.G = G;
   a.opf = opf;
@@ -87,7 +88,8 @@ static StiffArgs<T> stiff_args(const TankDev& h, const void* G, const T* opf, in
 // LDS: [operators 4 NpP^2 (if they fit)] [elem_loc 2nz NpP ints] [u region cb nc + nl]
 // [element outputs T 16 (NpP + 1): rows padded against bank conflicts]
 template <typename T>
-static size_t stiff_lds_layout(const TankDev& h, int ops_in_lds, size_t* o_loc, size_t* o_u, size_t* o_st) {
+__host__ __device__ inline size_t stiff_lds_layout(const TankDev& h, int ops_in_lds, size_t* o_loc, size_t* o_u,
+                                                   size_t* o_st) {
   size_t off = ops_in_lds ? 4 * (size_t)h.NpP * h.NpP * sizeof(T) : 0;
   *o_loc = off;
   off += (size_t)2 * h.nz * h.NpP * sizeof(int32_t);
@@ -100,23 +102,22 @@ static size_t stiff_lds_layout(const TankDev& h, int ops_in_lds, size_t* o_loc, 
   return off;
 }
 
+// Workgroup b of the tank's grid (columns b cb .. b cb + cb - 1).
 template <int P, typename T, typename GS, bool OPS_LDS>
-__global__ void __launch_bounds__(kBlockThreads)
-k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T* __restrict__ side, int flags,
-             uint32_t o_loc, uint32_t o_u, uint32_t o_st) {
+__device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __restrict__ u, T* __restrict__ y,
+                                           T* __restrict__ side, int flags, uint32_t o_loc, uint32_t o_u,
+                                           uint32_t o_st, int b) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   constexpr int Np = (P + 1) * (P + 2) / 2;
   constexpr int NpP = (Np + 15) / 16 * 16;
   constexpr int MT = NpP / 16;      // M-tiles per operator block
   constexpr int KS = NpP / 4;       // K-steps of stage 1
-  if ((flags & F_GATE) && gview(a.ks)->done) return;
   extern __shared__ unsigned char lds_raw[];
   T* lop = reinterpret_cast<T*>(lds_raw);                        // [4][NpP][NpP]
   int32_t* lloc = reinterpret_cast<int32_t*>(lds_raw + o_loc);   // [2nz][NpP]
   T* ureg = reinterpret_cast<T*>(lds_raw + o_u);                 // [cb nc + nl]
   T* st3 = reinterpret_cast<T*>(lds_raw + o_st);                 // [T 16][NpP]
-  const int b = blockIdx.x;
   const int c0 = b * a.cb;
   const int cbb = min(a.cb, a.nx - c0);
   const int nc = a.nc, nl = a.nl, nz2 = 2 * a.nz;
@@ -271,6 +272,38 @@ k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T
   }
 }
 
+template <int P, typename T, typename GS, bool OPS_LDS>
+__global__ void __launch_bounds__(kBlockThreads)
+k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T* __restrict__ side, int flags,
+             uint32_t o_loc, uint32_t o_u, uint32_t o_st) {
+  if ((flags & F_GATE) && gview(a.ks)->done) return;
+  stiff_body<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, blockIdx.x);
+}
+
+template <typename T, typename GS>
+__device__ inline const void* stiff_factors(const TankDev& d) {
+  if constexpr (sizeof(T) == sizeof(double)) return d.G;
+  else if constexpr (sizeof(GS) == sizeof(float)) return d.G32;
+  else return d.G16;
+}
+template <typename T>
+__device__ inline const T* stiff_ops(const TankDev& d) {
+  if constexpr (sizeof(T) == sizeof(double)) return d.opf;
+  else return d.opf32;
+}
+
+// batched: the tank's arguments and LDS offsets come from its descriptor
+template <int P, typename T, typename GS, bool OPS_LDS>
+__global__ void __launch_bounds__(kBlockThreads) k_stiff_mfma_b(BatchArgs ba, VSel u, VSel y, int flags) {
+  SEM_BATCH_TANK(ba)
+  if ((flags & F_GATE) && d.ks->done) return;
+  const StiffArgs<T> a = stiff_args<T>(d, stiff_factors<T, GS>(d), stiff_ops<T>(d), OPS_LDS ? 1 : 0);
+  size_t ol, ou, os;
+  stiff_lds_layout<T>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os);
+  stiff_body<P, T, GS, OPS_LDS>(a, bvec<T>(d, u), bvec<T>(d, y), reinterpret_cast<T*>(d.side), flags, (uint32_t)ol,
+                                (uint32_t)ou, (uint32_t)os, it_.bx);
+}
+
 // Lane-layout self-test of the two MFMA builtins: D = A B with known A, B;
 // each lane writes its four accumulator values to out[lane*4 + v].
 __global__ void k_mfma_probe(double* out64, float* out32) {
@@ -291,7 +324,7 @@ __global__ void k_mfma_probe(double* out64, float* out32) {
 
 // operators go to LDS unless they would take more than 40 KiB
 template <typename T>
-static int stiff_ops_in_lds(const TankDev& h) {
+__host__ __device__ inline int stiff_ops_in_lds(const TankDev& h) {
   return 4 * (size_t)h.NpP * h.NpP * sizeof(T) <= 40 * 1024 ? 1 : 0;
 }
 
@@ -367,6 +400,45 @@ void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const float* u,
                              int gstore, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
   if (gstore == 2) stiff_launch<float, BF16m>(h, d, u, y, side, flags, e0, e1, st);
   else stiff_launch<float, float>(h, d, u, y, side, flags, e0, e1, st);
+}
+
+void plan_stiff(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int P, int f32, BatchStage* out) {
+  *out = BatchStage{};
+  for (int t : ids) {
+    const TankDev& h = tanks[t];
+    if (h.P != P) continue;
+    size_t a, b, c;
+    const size_t lds = f32 ? stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c)
+                           : stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c);
+    for (int x = 0; x < h.nb; ++x) out->items.push_back(BatchItem{t, x, 0, h.nb});
+    out->lds = std::max(out->lds, lds);
+  }
+}
+
+template <typename T, typename GS>
+static void stiff_b_t(const BatchArgs& a0, const BatchStage& p, int P, VSel u, VSel y, int flags, hipStream_t st) {
+  if (p.items.empty()) return;
+  BatchArgs a = a0;
+  a.items = p.dev;
+  // whether the operators fit in LDS depends on P and the word size only
+  TankDev probe{};
+  probe.NpP = ((P + 1) * (P + 2) / 2 + 15) / 16 * 16;
+  const int inl = stiff_ops_in_lds<T>(probe);
+  const dim3 grid((unsigned)p.items.size());
+  if (inl) {
+    SEM_MP_SWITCH(P, hipLaunchKernelGGL((k_stiff_mfma_b<PP, T, GS, true>), grid, dim3(kBlockThreads), p.lds, st, a,
+                                        u, y, flags));
+  } else {
+    SEM_MP_SWITCH(P, hipLaunchKernelGGL((k_stiff_mfma_b<PP, T, GS, false>), grid, dim3(kBlockThreads), p.lds, st, a,
+                                        u, y, flags));
+  }
+}
+
+void launch_stiff_b(const BatchArgs& a, const BatchStage& p, int P, VSel u, VSel y, int flags, int gstore,
+                    hipStream_t st) {
+  if (gstore == 0) stiff_b_t<double, double>(a, p, P, u, y, flags, st);
+  else if (gstore == 1) stiff_b_t<float, float>(a, p, P, u, y, flags, st);
+  else stiff_b_t<float, BF16m>(a, p, P, u, y, flags, st);
 }
 
 void launch_mfma_probe(double* out64, float* out32, hipStream_t st) {

@@ -67,11 +67,7 @@ struct SdMat<float> {
 // split over the four wavefronts (each issues a quarter of the factor loads)
 // and the partial tiles are added in LDS in wave order
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
-          const double* __restrict__ nscale, T* __restrict__ vout) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
+__device__ __forceinline__ void sd_cond_body(const TankDev& d, int which, const T* __restrict__ r, const double* __restrict__ nscale, T* __restrict__ vout, int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
@@ -79,8 +75,8 @@ k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   const int nI = sd.nI, q = sd.q, nx = d.nx, KS = sd.KS1;
   T* Rt = reinterpret_cast<T*>(lds_raw);   // [4 KS][16] interior right sides of 16 columns
   double* red = reinterpret_cast<double*>(lds_raw);   // [kWaves][256], reuses Rt after the products
-  const int c0 = blockIdx.x * 16;
-  const int mt = blockIdx.y;
+  const int c0 = bx * 16;
+  const int mt = by;
   const double rs = sd_in_scale(nscale);
 #pragma unroll 8
   for (int t = threadIdx.x; t < 4 * KS * 16; t += blockDim.x) {
@@ -89,7 +85,7 @@ k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
     if (k < nI && c < nx) {
       const int64_t gi = (int64_t)c * d.nc + sd.I_idx[k];
       v = nscale ? T((double)r[gi] * rs) : r[gi];
-      if (vout && blockIdx.y == 0) vout[gi] = v;
+      if (vout && by == 0) vout[gi] = v;
     }
     Rt[t] = v;
   }
@@ -113,13 +109,18 @@ k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
 }
 
-// modes: one block per 16 Fourier modes; waves split the sum over columns
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
-           const double* __restrict__ nscale, T* __restrict__ vout) {
+k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
+          const double* __restrict__ nscale, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
+  sd_cond_body<T>(d, which, r, nscale, vout, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+// modes: one block per 16 Fourier modes; waves split the sum over columns
+template <typename T>
+__device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const T* __restrict__ r, const double* __restrict__ nscale, T* __restrict__ vout, int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
@@ -129,7 +130,7 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
   double* gh = sh + sd_part_words(q);     // [16][q][2]
   const int nNT = (q + 15) / 16, KS = (nx + 3) / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const int k0 = blockIdx.x * kModesPB;
+  const int k0 = bx * kModesPB;
   const double rs = sd_in_scale(nscale);
   const int kmode = k0 + col;              // A row of this lane (rows past the block's modes are discarded)
   const bool kval = kmode < nx;
@@ -156,10 +157,10 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
         T gv = T(0);
         if (cv && j < q) {
           double rv = (double)r[(int64_t)c * nc + j] * rs;
-          if (vout && blockIdx.x == 0) vout[(int64_t)c * nc + j] = T(rv);
+          if (vout && bx == 0) vout[(int64_t)c * nc + j] = T(rv);
           if (sd.wall && c == 0) {   // wall line folded onto line 0
             const double rw = (double)r[(int64_t)nx * nc + j] * rs;
-            if (vout && blockIdx.x == 0) vout[(int64_t)nx * nc + j] = T(rw);
+            if (vout && bx == 0) vout[(int64_t)nx * nc + j] = T(rw);
             rv += rw;
           }
           gv = T(rv - sd.TL[(size_t)c * q + j] - sd.TR[(size_t)cm * q + j]);
@@ -232,18 +233,24 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
         acc += hr;
       }
     }
-    sd.WP[((size_t)blockIdx.x * 2 + ln) * q + j] = acc;
+    sd.WP[((size_t)bx * 2 + ln) * q + j] = acc;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
+           const double* __restrict__ nscale, T* __restrict__ vout) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  sd_modes_body<T>(d, which, r, nscale, vout, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // inverse transform of the line solution (direct products, small nx): grid
 // (16-line tiles, 16-wide tiles of line unknowns); the K range (modes x
 // re/im) is split over the wavefronts and the partial tiles added in LDS
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
+__device__ __forceinline__ void sd_idft_body(const TankDev& d, int which, int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
@@ -251,7 +258,7 @@ k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
   const int q = sd.q, nx = d.nx;
   const int KS = (2 * nx + 3) / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const int c0 = blockIdx.x * 16, nt = blockIdx.y;
+  const int c0 = bx * 16, nt = by;
   // A[c][kk] = twiddle part (kk & 1) of mode kk / 2 at line c; B[kk][j] = that part of x^_{kk/2}[j]
   const int cr = (c0 + col) % nx;
   const int pr = grp & 1;
@@ -280,14 +287,19 @@ k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
   sd.XL[(size_t)c * q + jj] = v / nx;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  sd_idft_body<T>(d, which, (int)blockIdx.x, (int)blockIdx.y);
+}
+
 // back-substitution: grid (column tiles, M-tiles of A_II^-1 [A_IL | A_IR]);
 // the lines of 16 + 1 columns come from XL, the K range is split over the
 // wavefronts.  Block row 0 also writes the line values (and the wall line).
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate, T* __restrict__ vout) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
+__device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __restrict__ z, T* __restrict__ vout, int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
@@ -296,14 +308,14 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
   double* xl = sh;                         // [17][q] line solutions of columns c0 .. c0+16
   double* red = sh + 17 * q;               // [kWaves][256]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const int c0 = blockIdx.x * 16;
-  const int mt = blockIdx.y;
+  const int c0 = bx * 16;
+  const int mt = by;
   for (int t = threadIdx.x; t < 17 * q; t += blockDim.x) {
     const int cc = t / q, j = t - cc * q;
     xl[t] = sd.XL[(size_t)((c0 + cc) % nx) * q + j];
   }
   __syncthreads();
-  if (blockIdx.y == 0) {
+  if (by == 0) {
     for (int t = threadIdx.x; t < 16 * q; t += blockDim.x) {
       const int cc = t / q, j = t - cc * q, c = c0 + cc;
       if (c < nx) z[(int64_t)c * nc + j] = T(xl[cc * q + j]);
@@ -318,7 +330,7 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
         }
       }
     }
-    if (sd.wall && blockIdx.x == 0) {
+    if (sd.wall && bx == 0) {
       // wall line = line 0 + v
       for (int j = threadIdx.x; j < q; j += blockDim.x) z[(int64_t)nx * nc + j] = T(xl[j] + sd.vbuf[j]);
       if (sd.zero_surface && threadIdx.x == 0) {
@@ -350,15 +362,19 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
   z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - v);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate, T* __restrict__ vout) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  sd_back_body<T>(d, which, z, vout, (int)blockIdx.x, (int)blockIdx.y);
+}
+
 // Wall correction (one workgroup): lines nx-1 and 0 of the first solve
 // (sums of the per-block partials), then v = W [r_wall; x_{nx-1}; x_0; y_I]
 // with one wavefront per component of v.
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
-          const double* __restrict__ nscale) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
+__device__ __forceinline__ void sd_wall_body(const TankDev& d, int which, const T* __restrict__ r, const double* __restrict__ nscale, int bx, int by) {
   const SDData& sd = d.sd[which];
   extern __shared__ double sh[];
   const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc;
@@ -388,16 +404,22 @@ k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   }
 }
 
-// x^_k -= H_k v for every mode (thread per mode and line unknown); the
-// last column's interior solve y_I -= Q v (threads past nx q)
+template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sd_wall_modes(const TankDev* __restrict__ td, int which, int gate) {
+k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
+          const double* __restrict__ nscale) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
+  sd_wall_body<T>(d, which, r, nscale, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+// x^_k -= H_k v for every mode (thread per mode and line unknown); the
+// last column's interior solve y_I -= Q v (threads past nx q)
+__device__ __forceinline__ void sd_wall_modes_body(const TankDev& d, int which, int bx, int by) {
   const SDData& sd = d.sd[which];
   const int q = sd.q, nI = sd.nI;
   const int64_t nm = (int64_t)d.nx * q;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   if (t < nm) {
     const int64_t k = t / q;
     const int i = (int)(t - k * q);
@@ -420,6 +442,13 @@ k_sd_wall_modes(const TankDev* __restrict__ td, int which, int gate) {
   }
 }
 
+__global__ void __launch_bounds__(kBlockThreads)
+k_sd_wall_modes(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  sd_wall_modes_body(d, which, (int)blockIdx.x, (int)blockIdx.y);
+}
+
 // ------------------------------------------------------------ four-step transforms
 // nx = n1 n2, column c = n2 c1 + c2, mode k = k1 + n1 k2, w_N = e^{-2 pi i/N}:
 //   g^_k = sum_c2 w_n2^{k2 c2} [ w_nx^{k1 c2} sum_c1 w_n1^{k1 c1} g_{n2 c1 + c2} ]
@@ -431,17 +460,13 @@ __device__ inline int sd_mod(int64_t a, int n) { return (int)(a % n); }
 
 // pass A (block per c2): FT[k1][c2][j] = w_nx^{k1 c2} sum_c1 w_n1^{k1 c1} g[n2 c1 + c2][j]
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sdf_a(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
-        const double* __restrict__ nscale, T* __restrict__ vout) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
+__device__ __forceinline__ void sdf_a_body(const TankDev& d, int which, const T* __restrict__ r, const double* __restrict__ nscale, T* __restrict__ vout, int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
   extern __shared__ double sh[];
   const int q = sd.q, nx = d.nx, nc = d.nc, n1 = sd.fft_n1, n2 = sd.fft_n2;
-  const int c2 = blockIdx.x;
+  const int c2 = bx;
   const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16, nNT = (q + 15) / 16;
   const double rs = sd_in_scale(nscale);
   double* gl = sh;   // [4 KS][q] line right sides of columns n2 c1 + c2
@@ -494,17 +519,23 @@ k_sdf_a(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int 
   }
 }
 
-// pass B (block per k1): FG[k1 + n1 k2][j] = sum_c2 w_n2^{k2 c2} FT[k1][c2][j]
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sdf_b(const TankDev* __restrict__ td, int which, int gate) {
+k_sdf_a(const TankDev* __restrict__ td, int which, const T* __restrict__ r, int gate,
+        const double* __restrict__ nscale, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
+  sdf_a_body<T>(d, which, r, nscale, vout, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+// pass B (block per k1): FG[k1 + n1 k2][j] = sum_c2 w_n2^{k2 c2} FT[k1][c2][j]
+template <typename T>
+__device__ __forceinline__ void sdf_b_body(const TankDev& d, int which, int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
   const int q = sd.q, n1 = sd.fft_n1, n2 = sd.fft_n2;
-  const int k1 = blockIdx.x;
+  const int k1 = bx;
   const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16, nNT = (q + 15) / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   const double* ft = sd.FT + (size_t)k1 * n2 * q * 2;
@@ -542,20 +573,25 @@ k_sdf_b(const TankDev* __restrict__ td, int which, int gate) {
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sdf_b(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  sdf_b_body<T>(d, which, (int)blockIdx.x, (int)blockIdx.y);
+}
+
 // per-mode solves x^_k = S^_k^{-1} g^_k (thread per mode and row; each block
 // holds 256 / q whole modes and, for walls, adds its share of lines nx-1 and 0)
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sdf_solve(const TankDev* __restrict__ td, int which, int gate) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
+__device__ __forceinline__ void sdf_solve_body(const TankDev& d, int which, int bx, int by) {
   const SDData& sd = d.sd[which];
   extern __shared__ double sh[];
   const int q = sd.q, nx = d.nx;
   const int ml = max(1, kBlockThreads / q);
   const int t = threadIdx.x;
   const int kk = t / q, i = t - kk * q;
-  const int k = blockIdx.x * ml + kk;
+  const int k = bx * ml + kk;
   double xr = 0, xi = 0;
   const bool live = kk < ml && k < nx;
   if (live) {
@@ -580,7 +616,7 @@ k_sdf_solve(const TankDev* __restrict__ td, int which, int gate) {
     const int ln = u / q, j = u - ln * q;
     double acc = 0;
     for (int m2 = 0; m2 < ml; ++m2) {
-      const int km = blockIdx.x * ml + m2;
+      const int km = bx * ml + m2;
       if (km >= nx) break;
       const double hr = sh[2 * (m2 * q + j)], hi = sh[2 * (m2 * q + j) + 1];
       if (ln == 0) {
@@ -590,21 +626,26 @@ k_sdf_solve(const TankDev* __restrict__ td, int which, int gate) {
         acc += hr;
       }
     }
-    sd.WP[((size_t)blockIdx.x * 2 + ln) * q + j] = acc;
+    sd.WP[((size_t)bx * 2 + ln) * q + j] = acc;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sdf_solve(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  sdf_solve_body<T>(d, which, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // pass C (block per k1): FT[c2][k1][j] = conj(w_nx)^{k1 c2} sum_k2 conj(w_n2)^{k2 c2} x^[k1 + n1 k2][j]
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_sdf_c(const TankDev* __restrict__ td, int which, int gate) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
+__device__ __forceinline__ void sdf_c_body(const TankDev& d, int which, int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
   const int q = sd.q, nx = d.nx, n1 = sd.fft_n1, n2 = sd.fft_n2;
-  const int k1 = blockIdx.x;
+  const int k1 = bx;
   const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16, nNT = (q + 15) / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   for (int pr = wv; pr < nMT * nNT; pr += kWaves) {
@@ -645,17 +686,22 @@ k_sdf_c(const TankDev* __restrict__ td, int which, int gate) {
   }
 }
 
-// pass D (block per c2): XL[n2 c1 + c2][j] = Re sum_k1 conj(w_n1)^{k1 c1} FT[c2][k1][j] / nx
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_sdf_d(const TankDev* __restrict__ td, int which, int gate) {
+k_sdf_c(const TankDev* __restrict__ td, int which, int gate) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
+  sdf_c_body<T>(d, which, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+// pass D (block per c2): XL[n2 c1 + c2][j] = Re sum_k1 conj(w_n1)^{k1 c1} FT[c2][k1][j] / nx
+template <typename T>
+__device__ __forceinline__ void sdf_d_body(const TankDev& d, int which, int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
   const int q = sd.q, nx = d.nx, n1 = sd.fft_n1, n2 = sd.fft_n2;
-  const int c2 = blockIdx.x;
+  const int c2 = bx;
   const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16, nNT = (q + 15) / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   const double* ft = sd.FT + (size_t)c2 * n1 * q * 2;
@@ -688,6 +734,150 @@ k_sdf_d(const TankDev* __restrict__ td, int which, int gate) {
       sd.XL[((size_t)n2 * c1o + c2) * q + j] = (double)acc[v] * inx;
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sdf_d(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  sdf_d_body<T>(d, which, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+// ------------------------------------------------------------ batched chain
+// The same kernels over many tanks (one work item per workgroup of a tank's
+// own grid).  Input rin; with jn > 0 it is read as w / ||w|| and that
+// normalised vector is stored as V_jn on the way.
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_sd_cond_b(BatchArgs ba, int which, VSel rin, int jn, int gate) {
+  SEM_BATCH_TANK(ba)
+  if (gate && d.ks->done) return;
+  sd_cond_body<T>(d, which, bvec<T>(d, rin), jn > 0 ? krylov_norm(d, jn) : nullptr,
+                  jn > 0 ? bvec<T>(d, VSel{BV_V, jn}) : nullptr, it_.bx, it_.by);
+}
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_sd_modes_b(BatchArgs ba, int which, VSel rin, int jn, int gate) {
+  SEM_BATCH_TANK(ba)
+  if (gate && d.ks->done) return;
+  sd_modes_body<T>(d, which, bvec<T>(d, rin), jn > 0 ? krylov_norm(d, jn) : nullptr,
+                   jn > 0 ? bvec<T>(d, VSel{BV_V, jn}) : nullptr, it_.bx, it_.by);
+}
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_sdf_a_b(BatchArgs ba, int which, VSel rin, int jn, int gate) {
+  SEM_BATCH_TANK(ba)
+  if (gate && d.ks->done) return;
+  sdf_a_body<T>(d, which, bvec<T>(d, rin), jn > 0 ? krylov_norm(d, jn) : nullptr,
+                jn > 0 ? bvec<T>(d, VSel{BV_V, jn}) : nullptr, it_.bx, it_.by);
+}
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_sd_wall_b(BatchArgs ba, int which, VSel rin, int jn, int gate) {
+  SEM_BATCH_TANK(ba)
+  if (gate && d.ks->done) return;
+  sd_wall_body<T>(d, which, bvec<T>(d, rin), jn > 0 ? krylov_norm(d, jn) : nullptr, it_.bx, it_.by);
+}
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_sd_back_b(BatchArgs ba, int which, VSel zout, int jn, int gate) {
+  SEM_BATCH_TANK(ba)
+  if (gate && d.ks->done) return;
+  sd_back_body<T>(d, which, bvec<T>(d, zout), jn > 0 ? bvec<T>(d, VSel{BV_V, jn}) : nullptr, it_.bx, it_.by);
+}
+#define SEM_SD_PLAIN_B(NAME, BODY)                                                          \
+  template <typename T>                                                                     \
+  __global__ void __launch_bounds__(kBlockThreads) NAME(BatchArgs ba, int which, int gate) { \
+    SEM_BATCH_TANK(ba)                                                                      \
+    if (gate && d.ks->done) return;                                                         \
+    BODY<T>(d, which, it_.bx, it_.by);                                                      \
+  }
+SEM_SD_PLAIN_B(k_sd_idft_b, sd_idft_body)
+SEM_SD_PLAIN_B(k_sdf_b_b, sdf_b_body)
+SEM_SD_PLAIN_B(k_sdf_solve_b, sdf_solve_body)
+SEM_SD_PLAIN_B(k_sdf_c_b, sdf_c_body)
+SEM_SD_PLAIN_B(k_sdf_d_b, sdf_d_body)
+#undef SEM_SD_PLAIN_B
+__global__ void __launch_bounds__(kBlockThreads) k_sd_wall_modes_b(BatchArgs ba, int which, int gate) {
+  SEM_BATCH_TANK(ba)
+  if (gate && d.ks->done) return;
+  sd_wall_modes_body(d, which, it_.bx, it_.by);
+}
+
+namespace {
+// dynamic LDS of the chain's kernels for one tank
+struct SdLds {
+  size_t cond, modes, back, fa, fsolve, wall;
+};
+SdLds sd_lds(const SDData& sd, size_t word) {
+  SdLds l;
+  l.cond = std::max(word * 4 * (size_t)sd.KS1 * 16, sizeof(double) * kWaves * 256);
+  l.modes = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
+  l.back = sizeof(double) * (kWaves * 256 + 17 * (size_t)sd.q);
+  l.fa = sd.fft_n1 ? sizeof(double) * 4 * (size_t)((sd.fft_n1 + 3) / 4) * sd.q : 0;
+  l.fsolve = sizeof(double) * 2 * kBlockThreads;
+  l.wall = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
+  return l;
+}
+void add_grid(BatchStage& st, int tank, int gx, int gy, size_t lds) {
+  for (int y = 0; y < gy; ++y)
+    for (int x = 0; x < gx; ++x) st.items.push_back(BatchItem{tank, x, y, gx});
+  st.lds = std::max(st.lds, lds);
+}
+}  // namespace
+
+void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int which, int f32, BatchSD* out) {
+  *out = BatchSD{};
+  for (int t : ids) {
+    const TankDev& h = tanks[t];
+    const SDData& sd = h.sd[which];
+    const SdLds l = sd_lds(sd, f32 ? sizeof(float) : sizeof(double));
+    const int ct = (h.nx + 15) / 16;
+    add_grid(out->cond, t, ct, sd.nMT1, l.cond);
+    if (sd.fft_n1) {
+      add_grid(out->fa, t, sd.fft_n2, 1, l.fa);
+      add_grid(out->fb, t, sd.fft_n1, 1, 0);
+      const int ml = std::max(1, kBlockThreads / sd.q);
+      add_grid(out->fsolve, t, (h.nx + ml - 1) / ml, 1, l.fsolve);
+      add_grid(out->fc, t, sd.fft_n1, 1, 0);
+      add_grid(out->fd, t, sd.fft_n2, 1, 0);
+    } else {
+      add_grid(out->modes, t, (h.nx + kModesPB - 1) / kModesPB, 1, l.modes);
+      add_grid(out->idft, t, ct, (sd.q + 15) / 16, 0);
+    }
+    if (sd.wall) {
+      add_grid(out->wall, t, 1, 1, l.wall);
+      const int64_t nm = (int64_t)h.nx * sd.q + sd.nI;
+      add_grid(out->wmodes, t, (int)((nm + kBlockThreads - 1) / kBlockThreads), 1, 0);
+    }
+    add_grid(out->back, t, ct, sd.nMT3, l.back);
+  }
+}
+
+template <typename T>
+static void sd_b_t(const BatchArgs& a0, const BatchSD& p, int which, VSel rin, VSel zout, int jn, int gate,
+                   hipStream_t st) {
+  auto go = [&](const BatchStage& s, auto kern, auto... args) {
+    if (s.items.empty()) return;
+    BatchArgs a = a0;
+    a.items = s.dev;
+    hipLaunchKernelGGL(kern, dim3((unsigned)s.items.size()), dim3(kBlockThreads), s.lds, st, a, args...);
+  };
+  // the wall correction needs the modes of the periodic solve; the inverse
+  // transforms of the direct and the four-step tanks are independent
+  go(p.cond, k_sd_cond_b<T>, which, rin, jn, gate);
+  go(p.fa, k_sdf_a_b<T>, which, rin, jn, gate);
+  go(p.fb, k_sdf_b_b<T>, which, gate);
+  go(p.fsolve, k_sdf_solve_b<T>, which, gate);
+  go(p.modes, k_sd_modes_b<T>, which, rin, jn, gate);
+  go(p.wall, k_sd_wall_b<T>, which, rin, jn, gate);
+  go(p.wmodes, k_sd_wall_modes_b, which, gate);
+  go(p.fc, k_sdf_c_b<T>, which, gate);
+  go(p.fd, k_sdf_d_b<T>, which, gate);
+  go(p.idft, k_sd_idft_b<T>, which, gate);
+  go(p.back, k_sd_back_b<T>, which, zout, jn, gate);
+}
+
+void launch_sd_b(const BatchArgs& a, const BatchSD& p, int which, VSel rin, VSel zout, int jn, int gate, int f32,
+                 hipStream_t st) {
+  if (f32) sd_b_t<float>(a, p, which, rin, zout, jn, gate, st);
+  else sd_b_t<double>(a, p, which, rin, zout, jn, gate, st);
 }
 
 template <typename T>

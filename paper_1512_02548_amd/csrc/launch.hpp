@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "sem_internal.hpp"
 
 namespace sem {
@@ -85,4 +87,44 @@ void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y
                       hipStream_t st);
 void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const double* acce, const double* accp,
                       double* eta, double* phi, int use_filter, hipStream_t st);
+
+// ------------------------------------------------------------ batched launches
+// One launch over many tanks: its work items (one per workgroup; the device
+// copy is placed by the batch) and the dynamic LDS it needs (the most any of
+// its tanks needs).  A stage without items is not launched.
+struct BatchStage {
+  std::vector<BatchItem> items;
+  size_t lds = 0;
+  const BatchItem* dev = nullptr;
+};
+// the exact-inverse chain of one operator (which) and precision
+struct BatchSD {
+  BatchStage cond, modes, fa, fb, fsolve, wall, wmodes, fc, fd, idft, back;
+};
+void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int which, int f32, BatchSD* out);
+void plan_stiff(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int P, int f32, BatchStage* out);
+// input rin -> output zout; jn > 0: the input is w / ||w|| and V_jn is stored
+void launch_sd_b(const BatchArgs& a, const BatchSD& p, int which, VSel rin, VSel zout, int jn, int gate, int f32,
+                 hipStream_t st);
+// gstore as for the single-tank kernel (0 FP64, 1 FP32, 2 bfloat16 factors)
+void launch_stiff_b(const BatchArgs& a, const BatchStage& p, int P, VSel u, VSel y, int flags, int gstore,
+                    hipStream_t st);
+void launch_dots_b(const BatchArgs& a, const BatchStage& p, int nvec, VSel X, VSel w, int hcol, int sidx, int fix,
+                   int gate, int f32, hipStream_t st);
+void launch_orth_b(const BatchArgs& a, const BatchStage& p, int j, int f32, hipStream_t st);
+void launch_fixup_b(const BatchArgs& a, const BatchStage& p, VSel y, int flags, int f32, hipStream_t st);
+void launch_residual_b(const BatchArgs& a, const BatchStage& p, VSel b, VSel y, VSel r, int f32, hipStream_t st);
+void launch_cycle_start_b(const BatchArgs& a, const BatchStage& per_tank, const BatchStage& vec, int first, int f32,
+                          hipStream_t st);
+void launch_solve_update_b(const BatchArgs& a, const BatchStage& per_tank, const BatchStage& vec, VSel x, int f32,
+                           hipStream_t st);
+void launch_ks_init_b(const BatchArgs& a, const BatchStage& per_tank, double rtol, hipStream_t st);
+void launch_status_clear_b(const BatchArgs& a, const BatchStage& per_tank, hipStream_t st);
+// ks_out / st_out: host-visible arrays indexed by tank
+void launch_state_out_b(const BatchArgs& a, const BatchStage& per_tank, KrylovState* ks_out, int32_t* st_out,
+                        int mark_noconv, hipStream_t st);
+void launch_lift_in_b(const BatchArgs& a, const BatchStage& vec, const double* const* phis,
+                      const double* const* guess, hipStream_t st);
+void launch_solution_out_b(const BatchArgs& a, const BatchStage& vec, const double* const* phis, double* const* phi,
+                           hipStream_t st);
 }  // namespace sem

@@ -18,80 +18,19 @@
 
 #include "../../include/sem.h"
 #include "host_refelem.hpp"
-#include "sem_internal.hpp"
-
 #include "launch.hpp"
+#include "mesh.hpp"
+#include "sem_internal.hpp"
 
 using namespace sem;
 
 // ------------------------------------------------------------ error state
 static thread_local std::string g_err;
-static sem_status fail(sem_status s, const std::string& msg) {
+sem_status sem::fail(sem_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
 extern "C" const char* sem_last_error(void) { return g_err.c_str(); }
-
-#define HIPCHK(x)                                                                     \
-  do {                                                                                \
-    hipError_t e_ = (x);                                                              \
-    if (e_ != hipSuccess) return fail(SEM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-// ------------------------------------------------------------ mesh object
-struct Upload {
-  size_t off;
-  std::vector<char> data;
-};
-
-struct sem_mesh {
-  // description
-  int nx = 0, nz = 0, P = 0, periodic = 1, Pf = 0, ic = 2, m = 30;
-  double L = 0, g = 9.81, sf = 1.0;
-  std::vector<double> h, hx, slev;
-  // derived sizes
-  int Np = 0, NpP = 0, nl = 0, nc = 0, cb = 1, nb = 1, T = 1, EB = 0, nclass_col = 1;
-  int pre_kind = 0, variant = 0;
-  int sd_nI[2] = {0, 0}, sd_q[2] = {0, 0};
-  int sd_M1[2] = {0, 0}, sd_nMT1[2] = {0, 0}, sd_KS1[2] = {0, 0}, sd_nMT3[2] = {0, 0}, sd_KS3[2] = {0, 0};
-  int sd_wall[2] = {0, 0};
-  int fft_n1 = 0, fft_n2 = 0;   // four-step transforms along x (0: direct)
-  int circ1d = 0;
-  int64_t n = 0, ns = 0, E = 0;
-  // host tables
-  std::vector<int32_t> elem_loc, acc_cnt, acc_ent, surf_loc, is_surf_loc;
-  std::vector<double> node_x, node_sig;
-  std::vector<int64_t> surf_nodes;
-  // layout
-  size_t ws_bytes = 0;
-  std::vector<Upload> uploads;
-  TankDev hd{};             // device pointers filled at bind (offsets before)
-  char* ws = nullptr;
-  TankDev* dtank = nullptr;
-  double* scal = nullptr;   // small device scalars
-  bool bound = false;
-  // offsets of dynamic arrays
-  std::map<std::string, size_t> off;
-  // RK4 scratch (surface arrays)
-  double *rk = nullptr;
-  // progress word of the running Krylov cycle in pinned host memory (written
-  // by the device, read by the host while it queues steps)
-  int32_t* prog_host = nullptr;
-  int32_t* prog_dev = nullptr;
-  // live timing of the stiffness kernel (event pairs of the running cycle)
-  bool kt_on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> kt_ev;
-  size_t kt_used = 0;
-  int64_t kt_count = 0;
-  double kt_ms = 0;
-  ~sem_mesh() {
-    if (prog_host) (void)hipHostFree(prog_host);
-    for (auto& e : kt_ev) {
-      (void)hipEventDestroy(e.first);
-      (void)hipEventDestroy(e.second);
-    }
-  }
-};
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -1204,6 +1143,8 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.b32 = at<float>(M, "b32");
   M->rk = at<double>(M, "rk");
   M->scal = at<double>(M, "scal");
+  h.scal = M->scal;
+  h.prog = M->prog_dev;
   M->dtank = at<TankDev>(M, "tank");
   // every device array the kernels use must have been laid out
   const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.opf, h.opf32, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,
@@ -1232,13 +1173,13 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
 }
 
 // ------------------------------------------------------------ helpers
-static sem_status check_bound(sem_mesh* M) {
+sem_status sem::check_bound(sem_mesh* M) {
   if (!M) return fail(SEM_E_INVAL, "null mesh");
   if (!M->bound) return fail(SEM_E_INVAL, "mesh not bound to a workspace");
   return SEM_OK;
 }
 
-static sem_status status_from_word(int32_t w) {
+sem_status sem::status_from_word(int32_t w) {
   if (w & ST_NONFINITE) return SEM_E_NONFINITE;
   if (w & ST_DOMAIN) return SEM_E_DOMAIN;
   if (w & ST_BREAKDOWN) return SEM_E_BREAKDOWN;
@@ -1452,7 +1393,7 @@ static KrylovBufF buf32(sem_mesh* M) {
   return KrylovBufF{M->hd.V32, M->hd.Z32, M->hd.w32, reinterpret_cast<float*>(M->hd.side)};
 }
 
-static void default_opts(sem_solve_opts* o) {
+void sem::default_opts(sem_solve_opts* o) {
   o->rtol = 1e-12;
   o->max_iter = 5000;
   o->prec = SEM_PREC_FP64;
@@ -1685,8 +1626,7 @@ extern "C" sem_status sem_laplace_solve(sem_mesh* M, const double* eta, const do
   return laplace_core(M, phi_s, phi, &o, stats, st);
 }
 
-// w~ from M w = S_z Phi (factors 1/d must be current); out [ns]
-static sem_status recover_w_core(sem_mesh* M, const double* Phi, double* out, hipStream_t st) {
+sem_status sem::recover_w_core(sem_mesh* M, const double* Phi, double* out, hipStream_t st) {
   const TankDev& h = M->hd;
   const TankDev* d = M->dtank;
   launch_gather(h, d, OP_SZ, Phi, h.b, h.side, 0, st);
@@ -1800,101 +1740,3 @@ extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, doub
   return read_status(M, st, nullptr);
 }
 
-// ------------------------------------------------------------ batches
-// A batch advances many independent tanks per call.  The tanks are spread
-// over worker threads, each driving its own HIP stream, so that the kernels
-// of different tanks run concurrently on the device.  Every tank runs exactly
-// the kernels it would run alone (results do not depend on the batch).
-struct sem_batch {
-  std::vector<sem_mesh*> meshes;
-  std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> events;
-  hipEvent_t start = nullptr;
-};
-
-extern "C" sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, int32_t nstreams, sem_batch** out) {
-  if (!meshes || count < 1 || !out) return fail(SEM_E_INVAL, "bad batch arguments");
-  if (nstreams < 1 || nstreams > 64) return fail(SEM_E_INVAL, "nstreams must be in 1..64");
-  for (int i = 0; i < count; ++i)
-    if (!meshes[i] || !meshes[i]->bound) return fail(SEM_E_INVAL, "every mesh must be bound");
-  for (int i = 0; i < count; ++i)
-    for (int j = i + 1; j < count; ++j)
-      if (meshes[i] == meshes[j]) return fail(SEM_E_INVAL, "a mesh appears twice in the batch");
-  std::unique_ptr<sem_batch> B(new (std::nothrow) sem_batch());
-  if (!B) return fail(SEM_E_NOMEM, "host allocation failed");
-  B->meshes.assign(meshes, meshes + count);
-  int ns = std::min<int>(nstreams, count);
-  for (int i = 0; i < ns; ++i) {
-    hipStream_t st;
-    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    B->streams.push_back(st);
-    hipEvent_t ev;
-    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    B->events.push_back(ev);
-  }
-  HIPCHK(hipEventCreateWithFlags(&B->start, hipEventDisableTiming));
-  *out = B.release();
-  return SEM_OK;
-}
-
-extern "C" sem_status sem_batch_rk4_step(sem_batch* B, double* const* eta, double* const* phi_s,
-                                         double* const* phi_ws, const double* dt, const uint8_t* active,
-                                         const sem_solve_opts* opts, int32_t* per_status, int32_t* per_iters,
-                                         void* stream) {
-  if (!B || !eta || !phi_s || !phi_ws || !dt) return fail(SEM_E_INVAL, "null argument");
-  const int count = (int)B->meshes.size();
-  for (int i = 0; i < count; ++i) {
-    if (active && !active[i]) continue;
-    if (!eta[i] || !phi_s[i] || !phi_ws[i] || !(dt[i] > 0)) return fail(SEM_E_INVAL, "bad per-tank argument");
-  }
-  hipStream_t cst = (hipStream_t)stream;
-  // inputs written on the caller's stream must be visible to the workers
-  HIPCHK(hipEventRecord(B->start, cst));
-  const int W = (int)B->streams.size();
-  for (int w = 0; w < W; ++w) HIPCHK(hipStreamWaitEvent(B->streams[w], B->start, 0));
-  // largest tanks first, dealt to the least-loaded worker
-  std::vector<int> order;
-  for (int i = 0; i < count; ++i)
-    if (!active || active[i]) order.push_back(i);
-  std::sort(order.begin(), order.end(), [&](int a, int b) { return B->meshes[a]->n > B->meshes[b]->n; });
-  std::vector<std::vector<int>> work(W);
-  std::vector<double> load(W, 0.0);
-  for (int i : order) {
-    int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    work[w].push_back(i);
-    load[w] += (double)B->meshes[i]->n;
-  }
-  std::vector<sem_status> res(count, SEM_OK);
-  std::vector<int32_t> its(count, 0);
-  auto run = [&](int w) {
-    for (int i : work[w]) {
-      sem_solve_stats st4[4] = {};
-      res[i] = sem_rk4_step(B->meshes[i], eta[i], phi_s[i], phi_ws[i], dt[i], opts, st4, B->streams[w]);
-      its[i] = st4[0].iters + st4[1].iters + st4[2].iters + st4[3].iters;
-    }
-  };
-  std::vector<std::thread> th;
-  for (int w = 1; w < W; ++w) th.emplace_back(run, w);
-  run(0);
-  for (auto& t : th) t.join();
-  for (int w = 0; w < W; ++w) {
-    HIPCHK(hipEventRecord(B->events[w], B->streams[w]));
-    HIPCHK(hipStreamWaitEvent(cst, B->events[w], 0));
-  }
-  sem_status worst = SEM_OK;
-  for (int i = 0; i < count; ++i) {
-    if (per_status) per_status[i] = (active && !active[i]) ? SEM_OK : res[i];
-    if (per_iters) per_iters[i] = its[i];
-    if (res[i] != SEM_OK && worst == SEM_OK) worst = res[i];
-  }
-  if (worst != SEM_OK) g_err = "at least one tank failed; see per_tank_status";
-  return worst;
-}
-
-extern "C" void sem_batch_destroy(sem_batch* B) {
-  if (!B) return;
-  for (auto s : B->streams) hipStreamDestroy(s);
-  for (auto e : B->events) hipEventDestroy(e);
-  if (B->start) hipEventDestroy(B->start);
-  delete B;
-}

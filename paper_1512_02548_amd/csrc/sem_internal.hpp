@@ -1,5 +1,7 @@
 // Internal data structures shared by the host driver and the HIP kernels.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstddef>
 #include <cstdint>
 
@@ -150,7 +152,83 @@ struct TankDev {
   float* w32;
   float* x32;
   float* b32;
+  double* scal;                   // [64] small scalars (norms of the current solve)
+  int32_t* prog;                  // progress word of the running Krylov cycle (host-visible), or null
 };
+
+// ------------------------------------------------------------ batched launches
+// Many tanks advance together: every launch of a batched Krylov step covers
+// the workgroups of all tanks, listed in a table.  A work item names the tank
+// and the block coordinates inside that tank's own grid, plus the x extent of
+// that grid (the completion counters of the fused reductions count to it).
+struct BatchItem {
+  int32_t tank, bx, by, nbx;
+};
+
+// Arguments common to every batched launch.
+struct BatchArgs {
+  const TankDev* tanks;     // [count] copies of the tanks' descriptors
+  const int32_t* live;      // [count] 1 while the tank takes part in the current solve
+  const BatchItem* items;   // the launch's work items, one per workgroup
+};
+
+// Start of every batched kernel: the workgroup reads its work item, returns
+// unless its tank takes part in the solve, and then runs the single-tank code
+// on that tank's own workspace (d).
+#define SEM_BATCH_TANK(ba)                        \
+  const BatchItem it_ = (ba).items[blockIdx.x];  \
+  if (!(ba).live[it_.tank]) return;              \
+  const TankDev& d = (ba).tanks[it_.tank];
+
+// A vector of a tank's own workspace, named per launch.
+enum : int32_t { BV_NONE = 0, BV_V, BV_Z, BV_W, BV_B, BV_XS, BV_TMP, BV_WMASS };
+struct VSel {
+  int32_t kind, col;        // col: column of V or Z
+};
+
+template <typename T>
+__host__ __device__ inline T* bvec(const TankDev& d, VSel s);
+template <>
+__host__ __device__ inline double* bvec<double>(const TankDev& d, VSel s) {
+  switch (s.kind) {
+    case BV_V: return d.V + (int64_t)s.col * d.n;
+    case BV_Z: return d.Zb + (int64_t)s.col * d.n;
+    case BV_W: return d.w;
+    case BV_B: return d.b;
+    case BV_XS: return d.xs;
+    case BV_TMP: return d.tmp;
+    case BV_WMASS: return d.wmass;
+    default: return nullptr;
+  }
+}
+template <>
+__host__ __device__ inline float* bvec<float>(const TankDev& d, VSel s) {
+  switch (s.kind) {
+    case BV_V: return d.V32 + (int64_t)s.col * d.n;
+    case BV_Z: return d.Z32 + (int64_t)s.col * d.n;
+    case BV_W: return d.w32;
+    case BV_B: return d.b32;
+    case BV_XS: return d.x32;
+    default: return nullptr;
+  }
+}
+
+// The norm of the Krylov vector V_j (j >= 1), kept in the scratch area after
+// the Givens rotations and the right side of the tank's least-squares problem.
+__host__ __device__ inline double* krylov_norm(const TankDev& d, int j) {
+  const int m = d.m;
+  return d.H + (size_t)(m + 1) * m + 2 * m + (m + 1) + (j - 1);
+}
+
+// Chunking of the fused reductions: at most 256 workgroups of >= 512 entries.
+__host__ __device__ inline int64_t dot_chunk(int64_t n) {
+  const int64_t c = (n + 255) / 256;
+  return c < 512 ? 512 : c;
+}
+__host__ __device__ inline int dot_nchunk(int64_t n) {
+  const int64_t k = (n + dot_chunk(n) - 1) / dot_chunk(n);
+  return k < 1 ? 1 : (int)k;
+}
 
 // Index of the element-node value of component c in the MFMA tile layout.
 // FP32 copies: row order perm(m) = 16(m/16) + 4(m%4) + (m%16)/4 (the FP32

@@ -78,7 +78,10 @@ _SIGS = {
     "sem_free_surface_rhs": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "sem_rk4_step": (C.c_int, [_P, _P, _P, _P, C.c_double, C.POINTER(sem_solve_opts),
                                C.POINTER(sem_solve_stats), _P]),
-    "sem_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "sem_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
+    "sem_batch_laplace_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
+                                          C.POINTER(C.c_uint8), C.POINTER(sem_solve_opts),
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
     "sem_batch_rk4_step": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), _D,
                                      C.POINTER(C.c_uint8), C.POINTER(sem_solve_opts),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
@@ -228,26 +231,44 @@ class Mesh:
 
 
 class Batch:
-    """sem_batch_*: advance several bound meshes per call on concurrent streams."""
+    """sem_batch_*: advance several bound meshes per call.
 
-    def __init__(self, meshes, nstreams=8):
+    nstreams = 0: lockstep (one batched GMRES over all tanks); nstreams >= 1:
+    each tank's own step on that many concurrent streams."""
+
+    def __init__(self, meshes, nstreams=0, stream=None):
         self.meshes = list(meshes)
+        self.nstreams = int(nstreams)
         arr = (C.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
         self.handle = C.c_void_p()
-        check(sem_batch_create(arr, len(self.meshes), int(nstreams), C.byref(self.handle)), "sem_batch_create")
+        check(sem_batch_create(arr, len(self.meshes), self.nstreams, _stream(stream), C.byref(self.handle)),
+              "sem_batch_create")
+
+    def _ptrs(self, tensors):
+        return (C.c_void_p * len(self.meshes))(*[t.data_ptr() for t in tensors])
+
+    def _active(self, active):
+        n = len(self.meshes)
+        return None if active is None else (C.c_uint8 * n)(*[1 if a else 0 for a in active])
 
     def rk4_step(self, etas, phis, phiws, dts, active=None, opts=None, stream=None):
         n = len(self.meshes)
-        P = C.c_void_p * n
-        e = P(*[t.data_ptr() for t in etas])
-        p = P(*[t.data_ptr() for t in phis])
-        w = P(*[t.data_ptr() for t in phiws])
         dt = (C.c_double * n)(*[float(v) for v in dts])
-        act = None if active is None else (C.c_uint8 * n)(*[1 if a else 0 for a in active])
         st = (C.c_int32 * n)()
         it = (C.c_int32 * n)()
         o = opts if opts is not None else default_opts(warm_start=1)
-        code = sem_batch_rk4_step(self.handle, e, p, w, dt, act, C.byref(o), st, it, _stream(stream))
+        code = sem_batch_rk4_step(self.handle, self._ptrs(etas), self._ptrs(phis), self._ptrs(phiws), dt,
+                                  self._active(active), C.byref(o), st, it, _stream(stream))
+        return code, list(st), list(it)
+
+    def laplace_solve(self, etas, etaxs, phiss, phis_out, active=None, opts=None, stream=None):
+        n = len(self.meshes)
+        st = (C.c_int32 * n)()
+        it = (C.c_int32 * n)()
+        o = opts if opts is not None else default_opts()
+        code = sem_batch_laplace_solve(self.handle, self._ptrs(etas), self._ptrs(etaxs), self._ptrs(phiss),
+                                       self._ptrs(phis_out), self._active(active), C.byref(o), st, it,
+                                       _stream(stream))
         return code, list(st), list(it)
 
     def __del__(self):

@@ -1,0 +1,148 @@
+"""GPU tests of the lockstep batch: every Laplace solve and RK4 step of a
+tank in the batch is bitwise the single-tank result (each tank's arithmetic
+runs in the same kernels in the same order; only the launches are shared)."""
+import numpy as np
+import pytest
+
+from paper_1512_02548_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_specs():
+    """Mixed orders, layers and lengths, flat and bar beds, one tank long
+    enough for the four-step transforms (nx = 256)."""
+    specs = wl.batch_tank_specs(count=7, steps=3, bar_fraction=0.5, seed=4242)
+    sizes = [16, 20, 40, 24, 33, 17, 256]
+    for s, nx in zip(specs, sizes):
+        s.nx = nx
+        s.params["mwav"] = max(1, nx // 8)
+        s.length = s.params["mwav"] * 2 * np.pi / s.params["k"]
+    specs[-1].nz, specs[-1].P = 2, 4           # keep the long tank small
+    return specs
+
+
+def make_tank(spec):
+    import torch
+    from paper_1512_02548_amd import lib
+    probe = lib.Mesh(spec.nx, spec.nz, spec.P, spec.length, True, np.ones(spec.ns), np.zeros(spec.ns),
+                     filter_ic=spec.filter_ic, filter_sigma=spec.filter_sigma, overint=spec.Pf, bind=False)
+    eta, phi, h, hx = wl.batch_tank_state(probe.surface_x(), spec)
+    m = lib.mesh_from_spec(spec, h, hx)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    return dict(mesh=m, spec=spec, eta=t(eta), phi=t(phi), ws=torch.zeros(m.n, dtype=torch.float64, device="cuda"))
+
+
+def walled_tank():
+    """A tank between walls over a sloping bed (the wall correction of the exact inverse)."""
+    import torch
+    from paper_1512_02548_amd import lib
+    nx, nz, P, L = 12, 2, 6, 6.0
+    ns = nx * P + 1
+    probe = lib.Mesh(nx, nz, P, L, False, np.ones(ns), np.zeros(ns), bind=False)
+    xs = probe.surface_x()
+    h = 1.0 - 0.2 * np.exp(-((xs - 3.0) / 1.0) ** 2)
+    hx = 0.4 * (xs - 3.0) * np.exp(-((xs - 3.0) / 1.0) ** 2)
+    m = lib.Mesh(nx, nz, P, L, False, h, hx)
+    eta = 0.01 * np.cos(np.pi * xs / L)
+    phi = 0.02 * np.sin(np.pi * xs / L)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    return dict(mesh=m, spec=None, eta=t(eta), phi=t(phi), ws=torch.zeros(m.n, dtype=torch.float64, device="cuda"))
+
+
+def surface_gradient(tank):
+    import torch
+    from paper_1512_02548_amd import lib
+    ex = torch.zeros_like(tank["eta"])
+    tank["mesh"].gradient_recover(lib.SEM_RECOVER_DX, tank["eta"], None, ex)
+    return ex
+
+
+def test_lockstep_laplace_equals_single():
+    import torch
+    from paper_1512_02548_amd import lib
+    tanks = [make_tank(s) for s in mixed_specs()] + [walled_tank()]
+    opts = lib.default_opts(rtol=1e-10, max_iter=2000)
+    exs = [surface_gradient(t) for t in tanks]
+    single, its = [], []
+    for t, ex in zip(tanks, exs):
+        phi = torch.zeros(t["mesh"].n, dtype=torch.float64, device="cuda")
+        st = t["mesh"].laplace_solve(t["eta"], ex, t["phi"], phi, opts)
+        single.append(phi.cpu().numpy())
+        its.append(st["iters"])
+    outs = [torch.full((t["mesh"].n,), np.nan, dtype=torch.float64, device="cuda") for t in tanks]
+    b = lib.Batch([t["mesh"] for t in tanks], 0)
+    code, status, iters = b.laplace_solve([t["eta"] for t in tanks], exs, [t["phi"] for t in tanks], outs,
+                                          opts=opts)
+    torch.cuda.synchronize()
+    assert code == 0 and all(s == 0 for s in status), (code, status)
+    assert iters == its
+    for o, s in zip(outs, single):
+        assert np.array_equal(o.cpu().numpy(), s)
+    # a second call with a subset of the tanks and a warm start
+    act = [i % 2 == 0 for i in range(len(tanks))]
+    wopts = lib.default_opts(rtol=1e-12, max_iter=2000, warm_start=1)
+    ref = []
+    for t, ex, a, s in zip(tanks, exs, act, single):
+        phi = torch.tensor(s, device="cuda")
+        if a:
+            t["mesh"].laplace_solve(t["eta"], ex, t["phi"], phi, wopts)
+        ref.append(phi.cpu().numpy())
+    outs = [torch.tensor(s, device="cuda") for s in single]
+    code, status, _ = b.laplace_solve([t["eta"] for t in tanks], exs, [t["phi"] for t in tanks], outs,
+                                      active=act, opts=wopts)
+    torch.cuda.synchronize()
+    assert code == 0
+    for o, r in zip(outs, ref):
+        assert np.array_equal(o.cpu().numpy(), r)
+
+
+def test_lockstep_rk4_equals_single():
+    import torch
+    from paper_1512_02548_amd import lib
+    opts = lib.default_opts(rtol=1e-10, warm_start=1)
+    specs = mixed_specs()[:5]
+    steps = 3
+    alone = []
+    for s in specs:
+        t = make_tank(s)
+        for _ in range(steps):
+            t["mesh"].rk4_step(t["eta"], t["phi"], t["ws"], s.dt, opts)
+        alone.append((t["eta"].cpu().numpy(), t["phi"].cpu().numpy()))
+    tanks = [make_tank(s) for s in specs]
+    b = lib.Batch([t["mesh"] for t in tanks], 0)
+    for _ in range(steps):
+        code, status, iters = b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks],
+                                         [t["ws"] for t in tanks], [s.dt for s in specs], opts=opts)
+        assert code == 0, status
+        assert all(i > 0 for i in iters)
+    torch.cuda.synchronize()
+    for (e, p), t in zip(alone, tanks):
+        assert np.array_equal(t["eta"].cpu().numpy(), e)
+        assert np.array_equal(t["phi"].cpu().numpy(), p)
+
+
+def test_lockstep_failed_tank_is_isolated():
+    """A tank whose water column vanishes fails alone; the others advance as alone."""
+    import torch
+    from paper_1512_02548_amd import lib
+    opts = lib.default_opts(rtol=1e-10, warm_start=1)
+    specs = mixed_specs()[:3]
+    tanks = [make_tank(s) for s in specs]
+    ref = []
+    for s in specs:
+        t = make_tank(s)
+        t["mesh"].rk4_step(t["eta"], t["phi"], t["ws"], s.dt, opts)
+        ref.append(t["eta"].cpu().numpy())
+    bad_eta = tanks[1]["eta"].clone()
+    tanks[1]["eta"].fill_(-2.0)                # d = eta + h < 0 everywhere
+    b = lib.Batch([t["mesh"] for t in tanks], 0)
+    code, status, _ = b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks],
+                                 [t["ws"] for t in tanks], [s.dt for s in specs], opts=opts)
+    torch.cuda.synchronize()
+    assert code != 0
+    assert status[0] == 0 and status[2] == 0 and status[1] == lib.SEM_E_DOMAIN
+    assert np.all(tanks[1]["eta"].cpu().numpy() == -2.0)   # transactional
+    assert np.array_equal(tanks[0]["eta"].cpu().numpy(), ref[0])
+    assert np.array_equal(tanks[2]["eta"].cpu().numpy(), ref[2])
+    del bad_eta
