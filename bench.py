@@ -201,22 +201,32 @@ def batch_workload(args):
             t["phi"].copy_(p)
             t["ws"].zero_()
 
+    def batched(name, nstreams, opts):
+        b = lib.Batch([t["mesh"] for t in tanks], nstreams)
+        restore()
+        b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks], [t["ws"] for t in tanks], dts, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for _ in range(args.batch_steps):
+            code, st, it = b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks],
+                                      [t["ws"] for t in tanks], dts, opts=opts)
+            if code != 0:
+                raise RuntimeError(f"batch step failed: {[lib.STATUS_NAMES.get(x, x) for x in st if x]}")
+            iters += sum(it)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        res[name] = {"tank_steps_per_s": args.tanks * args.batch_steps / tb,
+                     "gdof_s": 4 * nfree * args.batch_steps / tb / 1e9, "seconds": tb,
+                     "streams": nstreams, "mean_iters_per_solve": iters / (4 * args.tanks * args.batch_steps)}
+        print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
+        del b
+        return tb
+
+    fp64 = lib.default_opts(rtol=1e-10, warm_start=1, max_iter=20000)
     mixed = lib.default_opts(rtol=1e-10, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-2, max_iter=20000)
-    b = lib.Batch([t["mesh"] for t in tanks], args.streams)
-    restore()
-    b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks], [t["ws"] for t in tanks], dts, opts=mixed)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.batch_steps):
-        code, st, it = b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks],
-                                  [t["ws"] for t in tanks], dts, opts=mixed)
-        if code != 0:
-            raise RuntimeError(f"batch step failed: {[lib.STATUS_NAMES.get(x, x) for x in st if x]}")
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    res["batched_mixed"] = {"tank_steps_per_s": args.tanks * args.batch_steps / tb,
-                            "gdof_s": 4 * nfree * args.batch_steps / tb / 1e9, "seconds": tb,
-                            "streams": args.streams}
+    tl = batched("lockstep_fp64", 0, fp64)
+    tc = batched("concurrent_mixed", args.streams, mixed)
     fp64 = lib.default_opts(rtol=1e-10, warm_start=1, max_iter=20000)
     restore()
     for t, dt in zip(tanks, dts):
@@ -230,7 +240,8 @@ def batch_workload(args):
     ts = time.perf_counter() - t0
     res["sequential_fp64"] = {"tank_steps_per_s": args.tanks * args.batch_steps / ts,
                               "gdof_s": 4 * nfree * args.batch_steps / ts / 1e9, "seconds": ts}
-    res["speedup"] = ts / tb
+    res["speedup_lockstep"] = ts / tl
+    res["speedup_concurrent"] = ts / tc
     return res
 
 

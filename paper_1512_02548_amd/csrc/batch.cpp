@@ -213,7 +213,7 @@ static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rto
   sem_status s = set_live(B, act, st);
   if (s) return s;
   launch_ks_init_b(a, B->per_tank, rtol, st);
-  launch_dots_b(a, B->dots, 1, VSel{BV_B, 0}, VSel{BV_B, 0}, -1, 1, 0, 0, 0, st);
+  launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_B, 0}, VSel{BV_B, 0}, -1, 1, 0, 0, 0, st);
   std::vector<int> live = act;
   bool first = true;
   while (true) {
@@ -222,7 +222,7 @@ static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rto
     for (int P : B->orders) launch_stiff_b(a, B->stiff[P], P, VSel{BV_XS, 0}, VSel{BV_W, 0}, F_MASK_SURF, 0, st);
     launch_fixup_b(a, B->fixup, VSel{BV_W, 0}, F_MASK_SURF, 0, st);
     launch_residual_b(a, B->vec, VSel{BV_B, 0}, VSel{BV_W, 0}, VSel{BV_V, 0}, 0, st);
-    launch_dots_b(a, B->dots, 1, VSel{BV_V, 0}, VSel{BV_V, 0}, -1, 0, 0, 0, 0, st);
+    launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_V, 0}, VSel{BV_V, 0}, -1, 0, 0, 0, 0, st);
     launch_cycle_start_b(a, B->per_tank, B->vec, first ? 1 : 0, 0, st);
     first = false;
     for (int j = 0; j < B->mmax; ++j) {
@@ -230,8 +230,8 @@ static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rto
       launch_sd_b(a, B->sdlap, 0, j == 0 ? VSel{BV_V, 0} : VSel{BV_W, 0}, VSel{BV_Z, j}, j, 1, 0, st);
       for (int P : B->orders)
         launch_stiff_b(a, B->stiff[P], P, VSel{BV_Z, j}, VSel{BV_W, 0}, F_MASK_SURF | F_GATE | F_NOFIX, 0, st);
-      launch_dots_b(a, B->dots, j + 1, VSel{BV_V, 0}, VSel{BV_W, 0}, j, 0, 1, 1, 0, st);
-      launch_orth_b(a, B->dots, j, 0, st);
+      launch_dots_b(a, B->dots, B->per_tank, j + 1, VSel{BV_V, 0}, VSel{BV_W, 0}, j, 0, 1, 1, 0, st);
+      launch_orth_b(a, B->dots, B->per_tank, j, 0, st);
       // queue at most `ahead` steps in front of the slowest running tank
       bool stop = false;
       auto tq = std::chrono::steady_clock::now();

@@ -412,14 +412,14 @@ __device__ inline bool last_block(int32_t* counter, int nblk) {
   return is_last != 0;
 }
 
-// Workgroup bx of nblk: partial products of its chunk, the last workgroup
-// adds the partials.  Shared by the single-tank and the batched kernels.
+// Workgroup bx: partial products of its chunk into part[bx].  Shared by the
+// single-tank kernel (the last workgroup then adds the partials) and the
+// batched kernels (a second launch adds them: one device-wide release per
+// workgroup is cheap for a few hundred workgroups, not for tens of thousands).
 template <typename T>
-__device__ __forceinline__ void dots_body(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx,
-                                          T* __restrict__ w, double* __restrict__ part, int ldp,
-                                          double* __restrict__ out, int64_t chunk, int32_t* __restrict__ counter,
-                                          const TankDev* __restrict__ fixd, const T* __restrict__ side, int bx,
-                                          int nblk) {
+__device__ __forceinline__ void dots_partial(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx,
+                                             T* __restrict__ w, double* __restrict__ part, int ldp, int64_t chunk,
+                                             const TankDev* __restrict__ fixd, const T* __restrict__ side, int bx) {
   __shared__ double red[4][kMaxVec];
   const int64_t lo = (int64_t)bx * chunk, hi = min(lo + chunk, n);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -463,16 +463,19 @@ __device__ __forceinline__ void dots_body(int64_t n, int nvec, const T* __restri
   __syncthreads();
   for (int k = threadIdx.x; k < nvec; k += blockDim.x)
     part[(size_t)bx * ldp + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-  if (!last_block(counter, nblk)) return;
-  // final sums: wave w takes vectors w, w+4, ...; lanes stride over the
-  // workgroup partials in a fixed order, then a butterfly
+}
+
+// final sums of nblk partials: wave w takes vectors w, w+4, ...; lanes stride
+// over the workgroup partials in a fixed order, then a butterfly
+__device__ __forceinline__ void dots_reduce(int nvec, const double* __restrict__ part, int ldp,
+                                            double* __restrict__ out, int nblk) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int k = wv; k < nvec; k += kBlockThreads / 64) {
     double t = 0;
     for (int b2 = lane; b2 < nblk; b2 += 64) t += part[(size_t)b2 * ldp + k];
     t = wave_sum(t);
     if (lane == 0) out[k] = t;
   }
-  if (threadIdx.x == 0) *counter = 0;
 }
 
 template <typename T>
@@ -482,16 +485,17 @@ k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, T* __res
              int32_t* __restrict__ counter, const KrylovState* __restrict__ gate,
              const TankDev* __restrict__ fixd, const T* __restrict__ side) {
   if (gate && gate->done) return;
-  dots_body<T>(n, nvec, X, ldx, w, part, ldp, out, chunk, counter, fixd, side, blockIdx.x, gridDim.x);
+  dots_partial<T>(n, nvec, X, ldx, w, part, ldp, chunk, fixd, side, blockIdx.x);
+  if (!last_block(counter, gridDim.x)) return;
+  dots_reduce(nvec, part, ldp, out, gridDim.x);
+  if (threadIdx.x == 0) *counter = 0;
 }
 
-// w' = w - sum_{i<=j} h_i V_i; ||w'||^2 reduced; Givens update of column j
+// w' = w - sum_{i<=j} h_i V_i, and this workgroup's part of ||w'||^2
 template <typename T>
-__device__ __forceinline__ void orth_body(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase,
-                                          int m, T* __restrict__ w, double* __restrict__ part, int ldp,
-                                          int64_t chunk, KrylovState* __restrict__ ks, int32_t* __restrict__ counter,
-                                          int32_t* __restrict__ status, int32_t* __restrict__ mirror, int bx,
-                                          int nblk) {
+__device__ __forceinline__ void orth_partial(int64_t n, int j, const T* __restrict__ V,
+                                             const double* __restrict__ Hbase, int m, T* __restrict__ w,
+                                             double* __restrict__ part, int ldp, int64_t chunk, int bx) {
   __shared__ double red[4];
   const double* hcol = Hbase + (size_t)j * (m + 1);
   const int64_t lo = (int64_t)bx * chunk, hi = min(lo + chunk, n);
@@ -514,26 +518,34 @@ __device__ __forceinline__ void orth_body(int64_t n, int j, const T* __restrict_
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sacc;
   __syncthreads();
   if (threadIdx.x == 0) part[(size_t)bx * ldp] = ((red[0] + red[1]) + red[2]) + red[3];
-  if (!last_block(counter, nblk)) return;
+}
+
+// ||w'||^2 from nblk partials (first wave), then the Givens update of column j
+__device__ __forceinline__ void orth_reduce(int j, const double* __restrict__ part, int ldp, int nblk,
+                                            KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
+                                            int32_t* __restrict__ status, int32_t* __restrict__ mirror) {
   if (threadIdx.x < 64) {
     double t = 0;
     for (int b2 = threadIdx.x; b2 < nblk; b2 += 64) t += part[(size_t)b2 * ldp];
     t = wave_sum(t);
     if (threadIdx.x == 0) {
       givens_update(ks, Hbase, m, j, t, status);
-      *counter = 0;
       publish_progress(ks, mirror);
     }
   }
 }
 
+// w' = w - sum_{i<=j} h_i V_i; ||w'||^2 reduced; Givens update of column j
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase, int m, T* __restrict__ w,
              double* __restrict__ part, int ldp, int64_t chunk, KrylovState* __restrict__ ks,
              int32_t* __restrict__ counter, int32_t* __restrict__ status, int32_t* __restrict__ mirror) {
   if (ks->done) return;
-  orth_body<T>(n, j, V, Hbase, m, w, part, ldp, chunk, ks, counter, status, mirror, blockIdx.x, gridDim.x);
+  orth_partial<T>(n, j, V, Hbase, m, w, part, ldp, chunk, blockIdx.x);
+  if (!last_block(counter, gridDim.x)) return;
+  if (threadIdx.x == 0) *counter = 0;
+  orth_reduce(j, part, ldp, gridDim.x, ks, Hbase, m, status, mirror);
 }
 
 // ------------------------------------------------------------ GMRES pieces
@@ -701,20 +713,33 @@ __global__ void k_add_float(int64_t n, const float* __restrict__ x32, double sca
 // or the tank's scalars from index sidx when hcol < 0
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_dots_b(BatchArgs ba, int nvec, VSel X, VSel w, int hcol, int sidx, int fix, int gate) {
+k_dots_b(BatchArgs ba, int nvec, VSel X, VSel w, int fix, int gate) {
+  SEM_BATCH_TANK(ba)
+  if (gate && d.ks->done) return;
+  dots_partial<T>(d.n, nvec, bvec<T>(d, X), d.n, bvec<T>(d, w), d.part, d.m + 2, dot_chunk(d.n),
+                  fix ? &d : nullptr, fix ? reinterpret_cast<const T*>(d.side) : nullptr, it_.bx);
+}
+
+// one workgroup per tank: out = H column hcol, or the scalars from sidx when hcol < 0
+__global__ void __launch_bounds__(kBlockThreads) k_dots_sum_b(BatchArgs ba, int nvec, int hcol, int sidx, int gate) {
   SEM_BATCH_TANK(ba)
   if (gate && d.ks->done) return;
   double* out = hcol >= 0 ? d.H + (size_t)hcol * (d.m + 1) : d.scal + sidx;
-  dots_body<T>(d.n, nvec, bvec<T>(d, X), d.n, bvec<T>(d, w), d.part, d.m + 2, out, dot_chunk(d.n), &d.ks->pad[0],
-               fix ? &d : nullptr, fix ? reinterpret_cast<const T*>(d.side) : nullptr, it_.bx, it_.nbx);
+  dots_reduce(nvec, d.part, d.m + 2, out, dot_nchunk(d.n));
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads) k_orth_b(BatchArgs ba, int j) {
   SEM_BATCH_TANK(ba)
   if (d.ks->done) return;
-  orth_body<T>(d.n, j, bvec<T>(d, VSel{BV_V, 0}), d.H, d.m, bvec<T>(d, VSel{BV_W, 0}), d.part, d.m + 2,
-               dot_chunk(d.n), d.ks, &d.ks->pad[0], d.status, d.prog, it_.bx, it_.nbx);
+  orth_partial<T>(d.n, j, bvec<T>(d, VSel{BV_V, 0}), d.H, d.m, bvec<T>(d, VSel{BV_W, 0}), d.part, d.m + 2,
+                  dot_chunk(d.n), it_.bx);
+}
+
+__global__ void __launch_bounds__(kBlockThreads) k_orth_sum_b(BatchArgs ba, int j) {
+  SEM_BATCH_TANK(ba)
+  if (d.ks->done) return;
+  orth_reduce(j, d.part, d.m + 2, dot_nchunk(d.n), d.ks, d.H, d.m, d.status, d.prog);
 }
 
 template <typename T>
@@ -1474,14 +1499,17 @@ static bool batch_args(const BatchArgs& a0, const BatchStage& p, BatchArgs* a) {
       hipLaunchKernelGGL(KERN, dim3((unsigned)(P).items.size()), dim3(kBlockThreads), 0, st, a_, __VA_ARGS__); \
   } while (0)
 
-void launch_dots_b(const BatchArgs& a0, const BatchStage& p, int nvec, VSel X, VSel w, int hcol, int sidx, int fix,
-                   int gate, int f32, hipStream_t st) {
-  if (f32) SEM_BLAUNCH(p, k_dots_b<float>, nvec, X, w, hcol, sidx, fix, gate);
-  else SEM_BLAUNCH(p, k_dots_b<double>, nvec, X, w, hcol, sidx, fix, gate);
+void launch_dots_b(const BatchArgs& a0, const BatchStage& p, const BatchStage& per_tank, int nvec, VSel X, VSel w,
+                   int hcol, int sidx, int fix, int gate, int f32, hipStream_t st) {
+  if (f32) SEM_BLAUNCH(p, k_dots_b<float>, nvec, X, w, fix, gate);
+  else SEM_BLAUNCH(p, k_dots_b<double>, nvec, X, w, fix, gate);
+  SEM_BLAUNCH(per_tank, k_dots_sum_b, nvec, hcol, sidx, gate);
 }
-void launch_orth_b(const BatchArgs& a0, const BatchStage& p, int j, int f32, hipStream_t st) {
+void launch_orth_b(const BatchArgs& a0, const BatchStage& p, const BatchStage& per_tank, int j, int f32,
+                   hipStream_t st) {
   if (f32) SEM_BLAUNCH(p, k_orth_b<float>, j);
   else SEM_BLAUNCH(p, k_orth_b<double>, j);
+  SEM_BLAUNCH(per_tank, k_orth_sum_b, j);
 }
 void launch_fixup_b(const BatchArgs& a0, const BatchStage& p, VSel y, int flags, int f32, hipStream_t st) {
   if (f32) SEM_BLAUNCH(p, k_fixup_b<float>, y, flags);

@@ -109,9 +109,11 @@ void launch_sd_b(const BatchArgs& a, const BatchSD& p, int which, VSel rin, VSel
 // gstore as for the single-tank kernel (0 FP64, 1 FP32, 2 bfloat16 factors)
 void launch_stiff_b(const BatchArgs& a, const BatchStage& p, int P, VSel u, VSel y, int flags, int gstore,
                     hipStream_t st);
-void launch_dots_b(const BatchArgs& a, const BatchStage& p, int nvec, VSel X, VSel w, int hcol, int sidx, int fix,
-                   int gate, int f32, hipStream_t st);
-void launch_orth_b(const BatchArgs& a, const BatchStage& p, int j, int f32, hipStream_t st);
+// partial products over p's work items, then their sums in one workgroup per tank
+void launch_dots_b(const BatchArgs& a, const BatchStage& p, const BatchStage& per_tank, int nvec, VSel X, VSel w,
+                   int hcol, int sidx, int fix, int gate, int f32, hipStream_t st);
+void launch_orth_b(const BatchArgs& a, const BatchStage& p, const BatchStage& per_tank, int j, int f32,
+                   hipStream_t st);
 void launch_fixup_b(const BatchArgs& a, const BatchStage& p, VSel y, int flags, int f32, hipStream_t st);
 void launch_residual_b(const BatchArgs& a, const BatchStage& p, VSel b, VSel y, VSel r, int f32, hipStream_t st);
 void launch_cycle_start_b(const BatchArgs& a, const BatchStage& per_tank, const BatchStage& vec, int first, int f32,
