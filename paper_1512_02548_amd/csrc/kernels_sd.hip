@@ -63,50 +63,142 @@ struct SdMat<float> {
 };
 }  // namespace
 
-// condense: grid (column tiles, M-tiles); the K-steps of each product are
-// split over the four wavefronts (each issues a quarter of the factor loads)
-// and the partial tiles are added in LDS in wave order
+// Launch shape of the condensation and back-substitution products of a
+// tank (nMT M-tiles): ntw N-tiles of 16 columns per workgroup (wider groups
+// reuse each factor fragment over more columns) and four M-tiles, one per
+// wave; or, for small tanks (split = 1), one M-tile per workgroup with its K
+// range split over the four waves (more workgroups, shorter chains).  A
+// function of the tank alone, so a tank gets the same launch shape alone and
+// in a batch.
+struct SdShape {
+  int ntw, split;
+};
+__host__ __device__ inline SdShape sd_shape(int nx, int nMT) {
+  const int ct = (nx + 15) / 16, mg = (nMT + 3) / 4;
+  if (((ct + 3) / 4) * mg >= 256) return SdShape{4, 0};
+  if (((ct + 1) / 2) * mg >= 256) return SdShape{2, 0};
+  if (ct * mg >= 256) return SdShape{1, 0};
+  return SdShape{1, 1};
+}
+constexpr int kNTMax = 4;    // N-tiles per wave at most
+constexpr int kKC = 24;      // K-steps of the right-hand factor staged in LDS at a time (LDS < 64 KiB)
+// LDS of the condensation's staging area (and, split, of its wave partials),
+// before the interior index table
+__host__ __device__ inline size_t sd_cond_stage_bytes(int ntw, size_t word, int split) {
+  const size_t st = word * 4 * kKC * (16 * (size_t)ntw + 1);
+  const size_t red = split ? sizeof(double) * kWaves * ntw * 256 : 0;
+  return ((st > red ? st : red) + 15) / 16 * 16;
+}
+
+// condense, as the product [Y; T_L; T_R] = A1 R over the tank's columns:
+// workgroup (column group bx, M-tiles 4 by .. 4 by + 3), one M-tile per wave
+// and all N-tiles of the group, the full K range in order (so an output does
+// not depend on the grouping); R is staged in LDS in chunks of kKC K-steps.
 template <typename T>
-__device__ __forceinline__ void sd_cond_body(const TankDev& d, int which, const T* __restrict__ r, const double* __restrict__ nscale, T* __restrict__ vout, int bx, int by) {
+__device__ __forceinline__ void sd_cond_body(const TankDev& d, int which, const T* __restrict__ r,
+                                             const double* __restrict__ nscale, T* __restrict__ vout, int bx,
+                                             int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
   extern __shared__ unsigned char lds_raw[];
-  const int nI = sd.nI, q = sd.q, nx = d.nx, KS = sd.KS1;
-  T* Rt = reinterpret_cast<T*>(lds_raw);   // [4 KS][16] interior right sides of 16 columns
-  double* red = reinterpret_cast<double*>(lds_raw);   // [kWaves][256], reuses Rt after the products
-  const int c0 = bx * 16;
-  const int mt = by;
-  const double rs = sd_in_scale(nscale);
-#pragma unroll 8
-  for (int t = threadIdx.x; t < 4 * KS * 16; t += blockDim.x) {
-    const int k = t >> 4, c = c0 + (t & 15);
-    T v = T(0);
-    if (k < nI && c < nx) {
-      const int64_t gi = (int64_t)c * d.nc + sd.I_idx[k];
-      v = nscale ? T((double)r[gi] * rs) : r[gi];
-      if (vout && by == 0) vout[gi] = v;
-    }
-    Rt[t] = v;
-  }
-  __syncthreads();
+  const int nI = sd.nI, q = sd.q, nx = d.nx, KS = sd.KS1, nMT = sd.nMT1;
+  const SdShape sh = sd_shape(nx, nMT);
+  const int ntw = sh.ntw;
+  const int ldr = 16 * ntw + 1;                          // odd stride: conflict-free staging
+  T* Rs = reinterpret_cast<T*>(lds_raw);                 // [4 kKC][ldr]
+  int32_t* lidx = reinterpret_cast<int32_t*>(lds_raw + sd_cond_stage_bytes(ntw, sizeof(T), sh.split));   // [nI]
+  const int c0 = bx * 16 * ntw;
+  for (int k = threadIdx.x; k < nI; k += blockDim.x) lidx[k] = sd.I_idx[k];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const T* A = SdMat<T>::A1(sd) + (size_t)mt * KS * 64;
-  V4 acc = V4{0, 0, 0, 0};
-#pragma unroll 8
-  for (int s = wv; s < KS; s += kWaves) acc = MF::op(A[(size_t)s * 64 + lane], Rt[(4 * s + grp) * 16 + col], acc);
-  __syncthreads();
+  const int mt = sh.split ? by : 4 * by + wv;
+  const int s_first = sh.split ? wv : 0, s_step = sh.split ? kWaves : 1;
+  const double rs = sd_in_scale(nscale);
+  const T* A = SdMat<T>::A1(sd) + (size_t)min(mt, nMT - 1) * KS * 64;
+  V4 acc[kNTMax];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) red[wv * 256 + MF::row(v, grp) * 16 + col] = (double)acc[v];
-  __syncthreads();
-  const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
-  const int row = 16 * mt + rr, c = c0 + cc;
-  if (c >= nx) return;
-  double val = 0;
-  for (int w = 0; w < kWaves; ++w) val += red[w * 256 + threadIdx.x];
-  if (row < nI) sd.yI[(size_t)c * nI + row] = val;
-  else if (row < nI + q) sd.TL[(size_t)c * q + row - nI] = val;
-  else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
+  for (int u = 0; u < kNTMax; ++u) acc[u] = V4{0, 0, 0, 0};
+  for (int s0 = 0; s0 < KS; s0 += kKC) {
+    const int kc = min(kKC, KS - s0);
+    const int nk = 4 * kc;
+    __syncthreads();
+    // K fastest: consecutive threads read consecutive interior unknowns of a
+    // column; unrolled so that the loads of several entries are in flight
+#pragma unroll 8
+    for (int t = threadIdx.x; t < nk * 16 * ntw; t += blockDim.x) {
+      const int cc = t / nk, kk = t - cc * nk;
+      const int k = 4 * s0 + kk, c = c0 + cc;
+      T v = T(0);
+      if (k < nI && c < nx) {
+        const int64_t gi = (int64_t)c * d.nc + lidx[k];
+        v = nscale ? T((double)r[gi] * rs) : r[gi];
+        if (vout && by == 0) vout[gi] = v;
+      }
+      Rs[kk * ldr + cc] = v;
+    }
+    __syncthreads();
+    if (mt < nMT) {
+      // split: wave w takes the chunk's K-steps w, w + 4, ... (the chunk
+      // length is a multiple of 4, so the assignment is global).  The factor
+      // fragments of kPre K-steps are loaded together, ahead of their MFMAs.
+      constexpr int kPre = 8;
+      for (int s = s_first; s < kc; s += kPre * s_step) {
+        T ab[kPre];
+#pragma unroll
+        for (int p2 = 0; p2 < kPre; ++p2) {
+          const int ss = s + p2 * s_step;
+          ab[p2] = ss < kc ? A[(size_t)(s0 + ss) * 64 + lane] : T(0);
+        }
+#pragma unroll
+        for (int p2 = 0; p2 < kPre; ++p2) {
+          const int ss = s + p2 * s_step;
+          if (ss >= kc) break;
+          const T* brow = Rs + (4 * ss + grp) * ldr + col;
+#pragma unroll
+          for (int u = 0; u < kNTMax; ++u)
+            if (u < ntw) acc[u] = MF::op(ab[p2], brow[16 * u], acc[u]);
+        }
+      }
+    }
+  }
+  if (sh.split) {
+    // partial tiles added in wave order (the staging area is free again)
+    double* red = reinterpret_cast<double*>(lds_raw);   // [kWaves][ntw][256]
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kNTMax; ++u) {
+      if (u >= ntw) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(wv * ntw + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[u][v];
+    }
+    __syncthreads();
+    const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
+    const int row = 16 * mt + rr;
+    for (int u = 0; u < ntw; ++u) {
+      const int c = c0 + 16 * u + cc;
+      if (c >= nx) continue;
+      double val = 0;
+      for (int w = 0; w < kWaves; ++w) val += red[(w * ntw + u) * 256 + threadIdx.x];
+      if (row < nI) sd.yI[(size_t)c * nI + row] = val;
+      else if (row < nI + q) sd.TL[(size_t)c * q + row - nI] = val;
+      else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
+    }
+    return;
+  }
+  if (mt >= nMT) return;
+#pragma unroll
+  for (int u = 0; u < kNTMax; ++u) {
+    const int c = c0 + 16 * u + col;
+    if (u >= ntw || c >= nx) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * mt + MF::row(v, grp);
+      const double val = (double)acc[u][v];
+      if (row < nI) sd.yI[(size_t)c * nI + row] = val;
+      else if (row < nI + q) sd.TL[(size_t)c * q + row - nI] = val;
+      else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
+    }
+  }
 }
 
 template <typename T>
@@ -199,11 +291,13 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
   for (int t = threadIdx.x; t < kModesPB * q; t += blockDim.x) {
     const int kk = t / q, i = t - kk * q, k = k0 + kk;
     if (k >= nx) continue;
-    const T* S = SdMat<T>::Shat(sd) + (size_t)k * q * q * 2;
+    const bool cj = 2 * k > nx;   // stored as the conjugate of mode nx - k
+    const T* S = SdMat<T>::Shat(sd) + (size_t)(cj ? nx - k : k) * q * q * 2;
+    const double sgn = cj ? -1.0 : 1.0;
     double xr = 0, xi = 0;
 #pragma unroll 8
     for (int j = 0; j < q; ++j) {
-      const double sr = (double)S[((size_t)j * q + i) * 2], si = (double)S[((size_t)j * q + i) * 2 + 1];
+      const double sr = (double)S[((size_t)j * q + i) * 2], si = sgn * (double)S[((size_t)j * q + i) * 2 + 1];
       const double gr = gh[(kk * q + j) * 2], gi = gh[(kk * q + j) * 2 + 1];
       xr += sr * gr - si * gi;
       xi += sr * gi + si * gr;
@@ -295,33 +389,41 @@ k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
   sd_idft_body<T>(d, which, (int)blockIdx.x, (int)blockIdx.y);
 }
 
-// back-substitution: grid (column tiles, M-tiles of A_II^-1 [A_IL | A_IR]);
-// the lines of 16 + 1 columns come from XL, the K range is split over the
-// wavefronts.  Block row 0 also writes the line values (and the wall line).
+// back-substitution z_I = Y - A_II^-1 [A_IL | A_IR] [x_L,c; x_L,c+1] as a
+// tiled product: workgroup (column group bx, M-tiles 4 by .. 4 by + 3), one
+// M-tile per wave, the full K range (2q) in order; the lines of the group's
+// columns and the next one come from XL through LDS.  Workgroups of row 0
+// also write the line values (and the wall line).
 template <typename T>
-__device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __restrict__ z, T* __restrict__ vout, int bx, int by) {
+__device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __restrict__ z, T* __restrict__ vout,
+                                             int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const SDData& sd = d.sd[which];
   extern __shared__ double sh[];
-  const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc;
-  double* xl = sh;                         // [17][q] line solutions of columns c0 .. c0+16
-  double* red = sh + 17 * q;               // [kWaves][256]
+  const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc, nMT = sd.nMT3, KS3 = sd.KS3;
+  const SdShape shp = sd_shape(nx, nMT);
+  const int ntw = shp.ntw;
+  const int ncol = 16 * ntw;
+  const int qp = q + 1;                      // odd stride: conflict-free reads across columns
+  double* xl = sh;                           // [ncol + 1][qp] line solutions of columns c0 .. c0 + ncol
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const int c0 = bx * 16;
-  const int mt = by;
-  for (int t = threadIdx.x; t < 17 * q; t += blockDim.x) {
+  const int c0 = bx * ncol;
+  const int mt = shp.split ? by : 4 * by + wv;
+  const int s_first = shp.split ? wv : 0, s_step = shp.split ? kWaves : 1;
+#pragma unroll 4
+  for (int t = threadIdx.x; t < (ncol + 1) * q; t += blockDim.x) {
     const int cc = t / q, j = t - cc * q;
-    xl[t] = sd.XL[(size_t)((c0 + cc) % nx) * q + j];
+    xl[cc * qp + j] = sd.XL[(size_t)((c0 + cc) % nx) * q + j];
   }
   __syncthreads();
   if (by == 0) {
-    for (int t = threadIdx.x; t < 16 * q; t += blockDim.x) {
+    for (int t = threadIdx.x; t < ncol * q; t += blockDim.x) {
       const int cc = t / q, j = t - cc * q, c = c0 + cc;
-      if (c < nx) z[(int64_t)c * nc + j] = T(xl[cc * q + j]);
+      if (c < nx) z[(int64_t)c * nc + j] = T(xl[cc * qp + j]);
     }
     if (sd.zero_surface) {
-      for (int t = threadIdx.x; t < 16 * d.P; t += blockDim.x) {
+      for (int t = threadIdx.x; t < ncol * d.P; t += blockDim.x) {
         const int cc = t / d.P, k = t - cc * d.P, c = c0 + cc;
         if (c < nx) {
           const int64_t gi = (int64_t)c * nc + (k == 0 ? d.nl - 1 : d.surf_loc[k]);
@@ -339,27 +441,65 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
       }
     }
   }
-  // z_I = Y - C [x_L,c; x_L,c+1]
-  const T* C = SdMat<T>::C3(sd) + (size_t)mt * sd.KS3 * 64;
-  const int KS3 = sd.KS3;
-  V4 acc = V4{0, 0, 0, 0};
-#pragma unroll 4
-  for (int s = wv; s < KS3; s += kWaves) {
-    const int kk = 4 * s + grp;
-    T b = T(0);
-    if (kk < q) b = T(xl[col * q + kk]);
-    else if (kk < 2 * q) b = T(xl[(col + 1) * q + kk - q]);
-    acc = MF::op(C[(size_t)s * 64 + lane], b, acc);
+  if (mt >= nMT) return;   // (uniform over the workgroup in split mode)
+  const T* C = SdMat<T>::C3(sd) + (size_t)mt * KS3 * 64;
+  V4 acc[kNTMax];
+#pragma unroll
+  for (int u = 0; u < kNTMax; ++u) acc[u] = V4{0, 0, 0, 0};
+  constexpr int kPre = 8;   // factor fragments loaded together, ahead of their MFMAs
+  for (int s = s_first; s < KS3; s += kPre * s_step) {
+    T ab[kPre];
+#pragma unroll
+    for (int p2 = 0; p2 < kPre; ++p2) {
+      const int ss = s + p2 * s_step;
+      ab[p2] = ss < KS3 ? C[(size_t)ss * 64 + lane] : T(0);
+    }
+#pragma unroll
+    for (int p2 = 0; p2 < kPre; ++p2) {
+      const int ss = s + p2 * s_step;
+      if (ss >= KS3) break;
+      const int kk = 4 * ss + grp;
+      // B[kk][col] = x_L of column col (kk < q) or of the next column
+      const int off = kk < q ? kk : (kk < 2 * q ? qp + kk - q : -1);
+#pragma unroll
+      for (int u = 0; u < kNTMax; ++u) {
+        if (u >= ntw) continue;
+        const T b = off >= 0 ? T(xl[(16 * u + col) * qp + off]) : T(0);
+        acc[u] = MF::op(ab[p2], b, acc[u]);
+      }
+    }
+  }
+  if (shp.split) {
+    // partial tiles added in wave order
+    double* red = xl + (ncol + 1) * qp;   // [kWaves][ntw][256]
+#pragma unroll
+    for (int u = 0; u < kNTMax; ++u) {
+      if (u >= ntw) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(wv * ntw + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[u][v];
+    }
+    __syncthreads();
+    const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
+    const int row = 16 * mt + rr;
+    for (int u = 0; u < ntw; ++u) {
+      const int c = c0 + 16 * u + cc;
+      if (c >= nx || row >= nI) continue;
+      double sacc = 0;
+      for (int w = 0; w < kWaves; ++w) sacc += red[(w * ntw + u) * 256 + threadIdx.x];
+      z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - sacc);
+    }
+    return;
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) red[wv * 256 + MF::row(v, grp) * 16 + col] = (double)acc[v];
-  __syncthreads();
-  const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
-  const int row = 16 * mt + rr, c = c0 + cc;
-  if (row >= nI || c >= nx) return;
-  double v = 0;
-  for (int w = 0; w < kWaves; ++w) v += red[w * 256 + threadIdx.x];
-  z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - v);
+  for (int u = 0; u < kNTMax; ++u) {
+    const int c = c0 + 16 * u + col;
+    if (u >= ntw || c >= nx) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * mt + MF::row(v, grp);
+      if (row < nI) z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - (double)acc[u][v]);
+    }
+  }
 }
 
 template <typename T>
@@ -383,12 +523,14 @@ __device__ __forceinline__ void sd_wall_body(const TankDev& d, int which, const 
   double* in = sh;   // [np]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double inx = 1.0 / nx;
-  for (int t = threadIdx.x; t < 2 * q; t += blockDim.x) {
+  // lines nx-1 and 0: one wavefront per value, lanes over the partials
+  for (int t = wv; t < 2 * q; t += kWaves) {
     const int ln = t / q, j = t - ln * q;
     double acc = 0;
-#pragma unroll 8
-    for (int b = 0; b < nb2; ++b) acc += sd.WP[((size_t)b * 2 + ln) * q + j];
-    in[q + ln * q + j] = acc * inx;
+#pragma unroll 4
+    for (int b = lane; b < nb2; b += 64) acc += sd.WP[((size_t)b * 2 + ln) * q + j];
+    acc = wsum(acc);
+    if (lane == 0) in[q + ln * q + j] = acc * inx;
   }
   const double rs = sd_in_scale(nscale);
   for (int a = threadIdx.x; a < q; a += blockDim.x) in[a] = (double)r[(int64_t)nx * nc + a] * rs;
@@ -595,11 +737,13 @@ __device__ __forceinline__ void sdf_solve_body(const TankDev& d, int which, int 
   double xr = 0, xi = 0;
   const bool live = kk < ml && k < nx;
   if (live) {
-    const T* S = SdMat<T>::Shat(sd) + (size_t)k * q * q * 2;
+    const bool cj = 2 * k > nx;   // stored as the conjugate of mode nx - k
+    const T* S = SdMat<T>::Shat(sd) + (size_t)(cj ? nx - k : k) * q * q * 2;
+    const double sgn = cj ? -1.0 : 1.0;
     const double* g = sd.FG + (size_t)k * q * 2;
 #pragma unroll 8
     for (int j = 0; j < q; ++j) {
-      const double sr = (double)S[((size_t)j * q + i) * 2], si = (double)S[((size_t)j * q + i) * 2 + 1];
+      const double sr = (double)S[((size_t)j * q + i) * 2], si = sgn * (double)S[((size_t)j * q + i) * 2 + 1];
       const double gr = g[2 * j], gi = g[2 * j + 1];
       xr += sr * gr - si * gi;
       xi += sr * gi + si * gr;
@@ -744,6 +888,34 @@ k_sdf_d(const TankDev* __restrict__ td, int which, int gate) {
   sdf_d_body<T>(d, which, (int)blockIdx.x, (int)blockIdx.y);
 }
 
+namespace {
+// dynamic LDS of the chain's kernels for one tank
+struct SdLds {
+  size_t cond, modes, back, fa, fsolve, wall;
+};
+SdLds sd_lds(const TankDev& h, const SDData& sd, size_t word) {
+  const SdShape s1 = sd_shape(h.nx, sd.nMT1), s3 = sd_shape(h.nx, sd.nMT3);
+  SdLds l;
+  l.cond = sd_cond_stage_bytes(s1.ntw, word, s1.split) + sizeof(int32_t) * sd.nI;
+  l.modes = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
+  l.back = sizeof(double) * ((16 * (size_t)s3.ntw + 1) * (sd.q + 1) + (s3.split ? kWaves * s3.ntw * 256 : 0));
+  l.fa = sd.fft_n1 ? sizeof(double) * 4 * (size_t)((sd.fft_n1 + 3) / 4) * sd.q : 0;
+  l.fsolve = sizeof(double) * 2 * kBlockThreads;
+  l.wall = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
+  return l;
+}
+struct SdGrid {
+  int cx, cy, bx, by;
+};
+// grids of the condensation (cx, cy) and back-substitution (bx, by) products
+SdGrid sd_grid(const TankDev& h, const SDData& sd) {
+  const SdShape s1 = sd_shape(h.nx, sd.nMT1), s3 = sd_shape(h.nx, sd.nMT3);
+  const int ct = (h.nx + 15) / 16;
+  return SdGrid{(ct + s1.ntw - 1) / s1.ntw, s1.split ? sd.nMT1 : (sd.nMT1 + 3) / 4, (ct + s3.ntw - 1) / s3.ntw,
+                s3.split ? sd.nMT3 : (sd.nMT3 + 3) / 4};
+}
+}  // namespace
+
 // ------------------------------------------------------------ batched chain
 // The same kernels over many tanks (one work item per workgroup of a tank's
 // own grid).  Input rin; with jn > 0 it is read as w / ||w|| and that
@@ -801,20 +973,6 @@ __global__ void __launch_bounds__(kBlockThreads) k_sd_wall_modes_b(BatchArgs ba,
 }
 
 namespace {
-// dynamic LDS of the chain's kernels for one tank
-struct SdLds {
-  size_t cond, modes, back, fa, fsolve, wall;
-};
-SdLds sd_lds(const SDData& sd, size_t word) {
-  SdLds l;
-  l.cond = std::max(word * 4 * (size_t)sd.KS1 * 16, sizeof(double) * kWaves * 256);
-  l.modes = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
-  l.back = sizeof(double) * (kWaves * 256 + 17 * (size_t)sd.q);
-  l.fa = sd.fft_n1 ? sizeof(double) * 4 * (size_t)((sd.fft_n1 + 3) / 4) * sd.q : 0;
-  l.fsolve = sizeof(double) * 2 * kBlockThreads;
-  l.wall = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
-  return l;
-}
 void add_grid(BatchStage& st, int tank, int gx, int gy, size_t lds) {
   for (int y = 0; y < gy; ++y)
     for (int x = 0; x < gx; ++x) st.items.push_back(BatchItem{tank, x, y, gx});
@@ -827,9 +985,10 @@ void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int
   for (int t : ids) {
     const TankDev& h = tanks[t];
     const SDData& sd = h.sd[which];
-    const SdLds l = sd_lds(sd, f32 ? sizeof(float) : sizeof(double));
+    const SdLds l = sd_lds(h, sd, f32 ? sizeof(float) : sizeof(double));
+    const SdGrid g = sd_grid(h, sd);
     const int ct = (h.nx + 15) / 16;
-    add_grid(out->cond, t, ct, sd.nMT1, l.cond);
+    add_grid(out->cond, t, g.cx, g.cy, l.cond);
     if (sd.fft_n1) {
       add_grid(out->fa, t, sd.fft_n2, 1, l.fa);
       add_grid(out->fb, t, sd.fft_n1, 1, 0);
@@ -846,7 +1005,7 @@ void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int
       const int64_t nm = (int64_t)h.nx * sd.q + sd.nI;
       add_grid(out->wmodes, t, (int)((nm + kBlockThreads - 1) / kBlockThreads), 1, 0);
     }
-    add_grid(out->back, t, ct, sd.nMT3, l.back);
+    add_grid(out->back, t, g.bx, g.by, l.back);
   }
 }
 
@@ -885,11 +1044,11 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
                  T* vout, hipStream_t st) {
   const SDData& sd = h.sd[which];
   const unsigned ct = (unsigned)((h.nx + 15) / 16);
-  const size_t l1 = std::max(sizeof(T) * 4 * (size_t)sd.KS1 * 16, sizeof(double) * kWaves * 256);
-  const size_t l2 = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
-  const size_t l3 = sizeof(double) * (kWaves * 256 + 17 * (size_t)sd.q);
-  const unsigned g1 = (unsigned)sd.nMT1;
-  hipLaunchKernelGGL(k_sd_cond<T>, dim3(ct, g1), dim3(kBlockThreads), l1, st, d, which, u, gate, nscale, vout);
+  const SdLds lds = sd_lds(h, sd, sizeof(T));
+  const SdGrid g = sd_grid(h, sd);
+  const size_t l2 = lds.modes;
+  hipLaunchKernelGGL(k_sd_cond<T>, dim3(g.cx, g.cy), dim3(kBlockThreads), lds.cond, st, d, which, u, gate, nscale,
+                     vout);
   const int n1 = sd.fft_n1, n2 = sd.fft_n2;
   if (n1) {
     const size_t la = sizeof(double) * 4 * (size_t)((n1 + 3) / 4) * sd.q;
@@ -915,7 +1074,7 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
   } else {
     hipLaunchKernelGGL(k_sd_idft<T>, dim3(ct, (sd.q + 15) / 16), dim3(kBlockThreads), 0, st, d, which, gate);
   }
-  hipLaunchKernelGGL(k_sd_back<T>, dim3(ct, sd.nMT3), dim3(kBlockThreads), l3, st, d, which, y, gate, vout);
+  hipLaunchKernelGGL(k_sd_back<T>, dim3(g.bx, g.by), dim3(kBlockThreads), lds.back, st, d, which, y, gate, vout);
 }
 
 void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st,

@@ -498,8 +498,9 @@ static sem_status build_mesh(sem_mesh* M) {
         if (k < nk) return Sinv[((size_t)k * q + a) * q + b];
         return std::conj(Sinv[((size_t)(nx - k) * q + a) * q + b]);
       };
-      H.Shat.assign((size_t)nx * q * q * 2, 0.0);
-      for (int k = 0; k < nx; ++k)
+      // modes k > nx/2 are the conjugates of modes nx - k: only 0..nx/2 are kept
+      H.Shat.assign((size_t)nk * q * q * 2, 0.0);
+      for (int k = 0; k < nk; ++k)
         for (int a = 0; a < q; ++a)
           for (int b = 0; b < q; ++b) {
             cd v = sinv(k, a, b);
@@ -862,7 +863,8 @@ static sem_status build_mesh(sem_mesh* M) {
     {
       std::vector<double> St(H.Shat.size());
       const size_t qq = (size_t)H.q * H.q;
-      for (int k = 0; k < nx; ++k)
+      const size_t nks = H.Shat.size() / (2 * std::max<size_t>(qq, 1));
+      for (size_t k = 0; k < nks; ++k)
         for (int a = 0; a < H.q; ++a)
           for (int b = 0; b < H.q; ++b)
             for (int ri = 0; ri < 2; ++ri)

@@ -49,7 +49,8 @@ struct SDData {
   const int32_t* I_idx;           // [nI] column-local indices of the interior unknowns
   const double* A1;               // fragments of [A_II^-1; A_LI A_II^-1; A_RI A_II^-1]  (M1 x nI)
   const double* C3;               // fragments of A_II^-1 [A_IL | A_IR]                    (nI x 2q)
-  const double* Shat;             // [nx][q][q][2] inverse line symbol per Fourier mode, column-major
+  const double* Shat;             // [nx/2+1][q][q][2] inverse line symbol per Fourier mode k <= nx/2,
+                                  // column-major (mode nx - k is the conjugate of mode k)
   const float* A1_32;
   const float* C3_32;
   const float* Shat32;
