@@ -31,9 +31,10 @@ using namespace sem;
 namespace {
 // pointer tables handed to the batched kernels, each [count]
 enum { PT_PHIS = 0, PT_WS = 1, PT_YP = 2, PT_COUNT = 3 };
-// staging copies of the live flags: a copy is reused only after the stream
-// has drained, so an earlier asynchronous upload never reads a later set
-constexpr int kLiveSlots = 16;
+// pinned staging copies of small uploads (live flags, per-tank scales): a
+// slot is reused only after the stream has drained, so an asynchronous
+// upload never reads a later value
+constexpr int kStageSlots = 16;
 }  // namespace
 
 struct sem_batch {
@@ -56,12 +57,15 @@ struct sem_batch {
   KrylovState* ks_dev = nullptr;
   int32_t* st_host = nullptr;
   int32_t* st_dev = nullptr;
-  int32_t* live_host = nullptr;   // kLiveSlots staging copies of the live flags
-  int live_slot = 0, live_pending = 0;
+  char* stage_host = nullptr;     // kStageSlots staging slots of count doubles
+  int stage_slot = 0, stage_pending = 0;
+  double* scal_host = nullptr;    // [count] tank scalars read back
+  double* scal_dev = nullptr;
+  double* dscale = nullptr;       // device [count] per-tank factors of the refinement
   const double** ptr_host = nullptr;
   BatchStage vec, dots, fixup, per_tank;
-  BatchStage stiff[kMaxOrder + 1];
-  BatchSD sdlap;
+  BatchStage stiff[kMaxOrder + 1], stiff32[kMaxOrder + 1];   // FP64, FP32 (LDS sized per word)
+  BatchSD sdlap, sdlap32;
   std::vector<int> orders;
   int mmax = 0;
   ~sem_batch() {
@@ -86,8 +90,9 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   const size_t o_prog = 0;
   const size_t o_ks = (o_prog + count * sizeof(int32_t) + 255) / 256 * 256;
   const size_t o_st = (o_ks + count * sizeof(KrylovState) + 255) / 256 * 256;
-  const size_t o_live = (o_st + count * sizeof(int32_t) + 255) / 256 * 256;
-  const size_t o_ptr = (o_live + (size_t)kLiveSlots * count * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t o_scal = (o_st + count * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t o_stage = (o_scal + count * sizeof(double) + 255) / 256 * 256;
+  const size_t o_ptr = (o_stage + (size_t)kStageSlots * count * sizeof(double) + 255) / 256 * 256;
   const size_t hbytes = o_ptr + (size_t)PT_COUNT * count * sizeof(double*);
   void* hp = nullptr;
   HIPCHK(hipHostMalloc(&hp, hbytes, hipHostMallocMapped | hipHostMallocCoherent));
@@ -102,7 +107,9 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   B->ks_dev = (KrylovState*)(hd + o_ks);
   B->st_host = (int32_t*)(B->hpin + o_st);
   B->st_dev = (int32_t*)(hd + o_st);
-  B->live_host = (int32_t*)(B->hpin + o_live);
+  B->scal_host = (double*)(B->hpin + o_scal);
+  B->scal_dev = (double*)(hd + o_scal);
+  B->stage_host = B->hpin + o_stage;
   B->ptr_host = (const double**)(B->hpin + o_ptr);
   // descriptors with the progress words redirected to the batch's array
   B->tanks.resize(count);
@@ -126,19 +133,26 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   }
   for (int P = 1; P <= kMaxOrder; ++P) {
     plan_stiff(B->tanks, ids, P, 0, &B->stiff[P]);
+    plan_stiff(B->tanks, ids, P, 1, &B->stiff32[P]);
     if (!B->stiff[P].items.empty()) B->orders.push_back(P);
   }
   plan_sd(B->tanks, ids, 0, 0, &B->sdlap);
+  plan_sd(B->tanks, ids, 0, 1, &B->sdlap32);
   std::vector<BatchStage*> stages = {&B->vec, &B->dots, &B->fixup, &B->per_tank};
-  for (int P : B->orders) stages.push_back(&B->stiff[P]);
-  for (BatchStage* s : {&B->sdlap.cond, &B->sdlap.modes, &B->sdlap.fa, &B->sdlap.fb, &B->sdlap.fsolve,
-                        &B->sdlap.wall, &B->sdlap.wmodes, &B->sdlap.fc, &B->sdlap.fd, &B->sdlap.idft,
-                        &B->sdlap.back})
-    stages.push_back(s);
-  // one device buffer: descriptors | live flags | pointer tables | item tables
+  for (int P : B->orders) {
+    stages.push_back(&B->stiff[P]);
+    stages.push_back(&B->stiff32[P]);
+  }
+  for (BatchSD* p : {&B->sdlap, &B->sdlap32})
+    for (BatchStage* s : {&p->cond, &p->modes, &p->fa, &p->fb, &p->fsolve, &p->wall, &p->wmodes, &p->fc, &p->fd,
+                          &p->idft, &p->back})
+      stages.push_back(s);
+  // one device buffer: descriptors | live flags | scales | pointer tables | item tables
   size_t off = (size_t)count * sizeof(TankDev);
   const size_t o_live_d = (off + 255) / 256 * 256;
   off = o_live_d + count * sizeof(int32_t);
+  const size_t o_scale_d = (off + 255) / 256 * 256;
+  off = o_scale_d + count * sizeof(double);
   const size_t o_ptr_d = (off + 255) / 256 * 256;
   off = o_ptr_d + (size_t)PT_COUNT * count * sizeof(double*);
   std::vector<size_t> o_items;
@@ -152,6 +166,7 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   B->dmem = (char*)dm;
   B->dtanks = (TankDev*)B->dmem;
   B->dlive = (int32_t*)(B->dmem + o_live_d);
+  B->dscale = (double*)(B->dmem + o_scale_d);
   B->dptr = (const double**)(B->dmem + o_ptr_d);
   HIPCHK(hipMemcpyAsync(B->dtanks, B->tanks.data(), count * sizeof(TankDev), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(B->dlive, 0, count * sizeof(int32_t), st));
@@ -172,24 +187,29 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
 
 static sem_status drain(sem_batch* B, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
-  B->live_pending = 0;
+  B->stage_pending = 0;
+  return SEM_OK;
+}
+
+// asynchronous upload of at most count doubles through a staging slot
+static sem_status upload(sem_batch* B, void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (B->stage_pending == kStageSlots) {
+    sem_status s = drain(B, st);
+    if (s) return s;
+  }
+  char* h = B->stage_host + (size_t)B->stage_slot * B->meshes.size() * sizeof(double);
+  B->stage_slot = (B->stage_slot + 1) % kStageSlots;
+  B->stage_pending++;
+  std::memcpy(h, src, bytes);
+  HIPCHK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st));
   return SEM_OK;
 }
 
 // live flags of the tanks that take part in the next launches
 static sem_status set_live(sem_batch* B, const std::vector<int>& live, hipStream_t st) {
-  const int count = (int)B->meshes.size();
-  if (B->live_pending == kLiveSlots) {
-    sem_status s = drain(B, st);
-    if (s) return s;
-  }
-  int32_t* h = B->live_host + (size_t)B->live_slot * count;
-  B->live_slot = (B->live_slot + 1) % kLiveSlots;
-  B->live_pending++;
-  std::fill(h, h + count, 0);
-  for (int t : live) h[t] = 1;
-  HIPCHK(hipMemcpyAsync(B->dlive, h, count * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  return SEM_OK;
+  std::vector<int32_t> f(B->meshes.size(), 0);
+  for (int t : live) f[t] = 1;
+  return upload(B, B->dlive, f.data(), f.size() * sizeof(int32_t), st);
 }
 
 static sem_status put_pointers(sem_batch* B, int which, const double* const* p, hipStream_t st) {
@@ -202,36 +222,40 @@ static sem_status put_pointers(sem_batch* B, int which, const double* const* p, 
 
 // ------------------------------------------------------------ lockstep GMRES
 // Restarted right-preconditioned GMRES on every tank in `act`, b and the
-// start vector xs already in each tank's workspace.  iters[t] accumulates.
-// Tanks whose status word is set leave `act`.
-static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rtol, int max_iter, int ahead,
-                                 std::vector<int32_t>& iters, hipStream_t st) {
+// start vector x already in each tank's workspace (FP64 b, xs; or, f32, the
+// FP32 copies b32, x32 with FP32 (gstore 1) or bfloat16 (gstore 2) factors).
+// iters[t] accumulates.  Tanks whose status word is set leave `act`; with
+// mark_noconv, unconverged tanks get the no-convergence bit (and leave too).
+static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rtol, int max_iter, int ahead, int f32,
+                                 int gstore, int mark_noconv, std::vector<int32_t>& iters, hipStream_t st) {
   if (act.empty()) return SEM_OK;
   const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  const BatchStage* stiff = f32 ? B->stiff32 : B->stiff;
+  const BatchSD& sdp = f32 ? B->sdlap32 : B->sdlap;
   volatile int32_t* prog = B->prog_host;
   ahead = std::max(1, ahead);
   sem_status s = set_live(B, act, st);
   if (s) return s;
   launch_ks_init_b(a, B->per_tank, rtol, st);
-  launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_B, 0}, VSel{BV_B, 0}, -1, 1, 0, 0, 0, st);
+  launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_B, 0}, VSel{BV_B, 0}, -1, 1, 0, 0, f32, st);
   std::vector<int> live = act;
   bool first = true;
   while (true) {
     for (int t : live) prog[t] = 0;
     // r = b - A x
-    for (int P : B->orders) launch_stiff_b(a, B->stiff[P], P, VSel{BV_XS, 0}, VSel{BV_W, 0}, F_MASK_SURF, 0, st);
-    launch_fixup_b(a, B->fixup, VSel{BV_W, 0}, F_MASK_SURF, 0, st);
-    launch_residual_b(a, B->vec, VSel{BV_B, 0}, VSel{BV_W, 0}, VSel{BV_V, 0}, 0, st);
-    launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_V, 0}, VSel{BV_V, 0}, -1, 0, 0, 0, 0, st);
-    launch_cycle_start_b(a, B->per_tank, B->vec, first ? 1 : 0, 0, st);
+    for (int P : B->orders) launch_stiff_b(a, stiff[P], P, VSel{BV_XS, 0}, VSel{BV_W, 0}, F_MASK_SURF, gstore, st);
+    launch_fixup_b(a, B->fixup, VSel{BV_W, 0}, F_MASK_SURF, f32, st);
+    launch_residual_b(a, B->vec, VSel{BV_B, 0}, VSel{BV_W, 0}, VSel{BV_V, 0}, f32, st);
+    launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_V, 0}, VSel{BV_V, 0}, -1, 0, 0, 0, f32, st);
+    launch_cycle_start_b(a, B->per_tank, B->vec, first ? 1 : 0, f32, st);
     first = false;
     for (int j = 0; j < B->mmax; ++j) {
       // z_j = M^-1 v_j; for j > 0 v_j = w / ||w|| is formed on the way
-      launch_sd_b(a, B->sdlap, 0, j == 0 ? VSel{BV_V, 0} : VSel{BV_W, 0}, VSel{BV_Z, j}, j, 1, 0, st);
+      launch_sd_b(a, sdp, 0, j == 0 ? VSel{BV_V, 0} : VSel{BV_W, 0}, VSel{BV_Z, j}, j, 1, f32, st);
       for (int P : B->orders)
-        launch_stiff_b(a, B->stiff[P], P, VSel{BV_Z, j}, VSel{BV_W, 0}, F_MASK_SURF | F_GATE | F_NOFIX, 0, st);
-      launch_dots_b(a, B->dots, B->per_tank, j + 1, VSel{BV_V, 0}, VSel{BV_W, 0}, j, 0, 1, 1, 0, st);
-      launch_orth_b(a, B->dots, B->per_tank, j, 0, st);
+        launch_stiff_b(a, stiff[P], P, VSel{BV_Z, j}, VSel{BV_W, 0}, F_MASK_SURF | F_GATE | F_NOFIX, gstore, st);
+      launch_dots_b(a, B->dots, B->per_tank, j + 1, VSel{BV_V, 0}, VSel{BV_W, 0}, j, 0, 1, 1, f32, st);
+      launch_orth_b(a, B->dots, B->per_tank, j, f32, st);
       // queue at most `ahead` steps in front of the slowest running tank
       bool stop = false;
       auto tq = std::chrono::steady_clock::now();
@@ -261,7 +285,7 @@ static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rto
       }
       if (stop) break;
     }
-    launch_solve_update_b(a, B->per_tank, B->vec, VSel{BV_XS, 0}, 0, st);
+    launch_solve_update_b(a, B->per_tank, B->vec, VSel{BV_XS, 0}, f32, st);
     launch_state_out_b(a, B->per_tank, B->ks_dev, B->st_dev, 0, st);
     s = drain(B, st);
     if (s) return s;
@@ -276,10 +300,10 @@ static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rto
     s = set_live(B, live, st);
     if (s) return s;
   }
-  // final states of every tank of the solve; unconverged ones are marked
+  // final states of every tank of the solve
   s = set_live(B, act, st);
   if (s) return s;
-  launch_state_out_b(a, B->per_tank, B->ks_dev, B->st_dev, 1, st);
+  launch_state_out_b(a, B->per_tank, B->ks_dev, B->st_dev, mark_noconv, st);
   s = drain(B, st);
   if (s) return s;
   std::vector<int> keep;
@@ -291,9 +315,90 @@ static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rto
   return SEM_OK;
 }
 
+// FP64 iterative refinement around FP32 lockstep GMRES (the single-tank
+// solve's steps, every tank in `act` at once): r = b - A x in FP64, then the
+// correction from the inner solve of A d = r / ||r||, x += ||r|| d.  Tanks
+// that fail leave `act` with their status bit set.
+static sem_status lockstep_ir(sem_batch* B, std::vector<int>& act, const sem_solve_opts& o,
+                              std::vector<int32_t>& iters, hipStream_t st) {
+  const int count = (int)B->meshes.size();
+  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  const int gstore = o.prec == SEM_PREC_BF16_IR ? 2 : 1;
+  sem_status s = set_live(B, act, st);
+  if (s) return s;
+  launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_B, 0}, VSel{BV_B, 0}, -1, 4, 0, 0, 0, st);
+  launch_scal_out_b(a, B->per_tank, 4, B->scal_dev, st);
+  s = drain(B, st);
+  if (s) return s;
+  std::vector<double> bnorm(count, 0.0), rn(count, 0.0), scale(count, 0.0);
+  for (int t : act) bnorm[t] = std::sqrt(B->scal_host[t]);
+  std::vector<int> cur = act, noconv, nonfinite;
+  for (int k = 0; k <= o.max_refine && !cur.empty(); ++k) {
+    s = set_live(B, cur, st);
+    if (s) return s;
+    for (int P : B->orders) launch_stiff_b(a, B->stiff[P], P, VSel{BV_XS, 0}, VSel{BV_W, 0}, F_MASK_SURF, 0, st);
+    launch_fixup_b(a, B->fixup, VSel{BV_W, 0}, F_MASK_SURF, 0, st);
+    launch_residual_b(a, B->vec, VSel{BV_B, 0}, VSel{BV_W, 0}, VSel{BV_TMP, 0}, 0, st);
+    launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_TMP, 0}, VSel{BV_TMP, 0}, -1, 4, 0, 0, 0, st);
+    launch_scal_out_b(a, B->per_tank, 4, B->scal_dev, st);
+    s = drain(B, st);
+    if (s) return s;
+    std::vector<int> next;
+    int min_iters = INT_MAX;
+    for (int t : cur) {
+      rn[t] = std::sqrt(B->scal_host[t]);
+      if (!std::isfinite(rn[t])) {
+        nonfinite.push_back(t);
+        continue;
+      }
+      if (rn[t] <= o.rtol * bnorm[t] || rn[t] == 0.0) continue;   // converged
+      if (k == o.max_refine || iters[t] >= o.max_iter) {
+        noconv.push_back(t);
+        continue;
+      }
+      next.push_back(t);
+      min_iters = std::min(min_iters, (int)iters[t]);
+    }
+    if (next.empty()) break;
+    for (int t : next) scale[t] = 1.0 / rn[t];
+    s = set_live(B, next, st);
+    if (!s) s = upload(B, B->dscale, scale.data(), count * sizeof(double), st);
+    if (s) return s;
+    launch_to_float_b(a, B->vec, B->dscale, st);
+    std::vector<int> inner = next;
+    s = lockstep_gmres(B, inner, o.inner_rtol, o.max_iter - min_iters, o.lookahead, 1, gstore, 0, iters, st);
+    if (s) return s;
+    s = set_live(B, inner, st);
+    if (!s) s = upload(B, B->dscale, rn.data(), count * sizeof(double), st);
+    if (s) return s;
+    launch_add_float_b(a, B->vec, B->dscale, st);
+    cur.swap(inner);
+  }
+  if (!noconv.empty()) {
+    s = set_live(B, noconv, st);
+    if (s) return s;
+    launch_status_or_b(a, B->per_tank, ST_NOCONV, st);
+  }
+  if (!nonfinite.empty()) {
+    s = set_live(B, nonfinite, st);
+    if (s) return s;
+    launch_status_or_b(a, B->per_tank, ST_NONFINITE, st);
+  }
+  s = set_live(B, act, st);
+  if (s) return s;
+  launch_state_out_b(a, B->per_tank, B->ks_dev, B->st_dev, 0, st);
+  s = drain(B, st);
+  if (s) return s;
+  std::vector<int> keep;
+  for (int t : act)
+    if (!B->st_host[t]) keep.push_back(t);
+  act.swap(keep);
+  return SEM_OK;
+}
+
 // Laplace solves of the tanks in `act` with their factors current: lift from
-// the surface potentials (pointer table PT_PHIS or PT_YP), GMRES, Phi out to
-// the PT_WS table's vectors (which hold the start vectors on entry when warm).
+// the surface potentials (pointer table PT_PHIS or PT_YP), the solve, Phi out
+// to the PT_WS table's vectors (which hold the start vectors on entry when warm).
 static sem_status lockstep_laplace(sem_batch* B, std::vector<int>& act, int phis_table, int warm,
                                    const sem_solve_opts& o, std::vector<int32_t>& iters, hipStream_t st) {
   const int count = (int)B->meshes.size();
@@ -306,7 +411,8 @@ static sem_status lockstep_laplace(sem_batch* B, std::vector<int>& act, int phis
     launch_stiff_b(a, B->stiff[P], P, VSel{BV_TMP, 0}, VSel{BV_B, 0}, F_MASK_SURF | F_NEG, 0, st);
   launch_fixup_b(a, B->fixup, VSel{BV_B, 0}, F_MASK_SURF | F_NEG, 0, st);
   std::vector<int> solved = act;
-  s = lockstep_gmres(B, act, o.rtol, o.max_iter, o.lookahead, iters, st);
+  if (o.prec == SEM_PREC_FP64) s = lockstep_gmres(B, act, o.rtol, o.max_iter, o.lookahead, 0, 0, 1, iters, st);
+  else s = lockstep_ir(B, act, o, iters, st);
   if (s) return s;
   s = set_live(B, solved, st);
   if (s) return s;
@@ -318,7 +424,9 @@ static sem_status check_opts(const sem_solve_opts* opts, sem_solve_opts* o) {
   if (opts) *o = *opts;
   else default_opts(o);
   if (!(o->rtol > 0) || o->max_iter < 1) return fail(SEM_E_INVAL, "rtol > 0 and max_iter >= 1 required");
-  if (o->prec != SEM_PREC_FP64) return fail(SEM_E_INVAL, "lockstep batches solve in FP64");
+  if (o->prec < 0 || o->prec > 2) return fail(SEM_E_INVAL, "unknown precision");
+  if (o->prec != SEM_PREC_FP64 && !(o->inner_rtol > 0 && o->inner_rtol < 1))
+    return fail(SEM_E_INVAL, "inner_rtol must lie in (0, 1)");
   return SEM_OK;
 }
 

@@ -853,6 +853,34 @@ __global__ void __launch_bounds__(kBlockThreads) k_update_x_b(BatchArgs ba, VSel
   x[i] = T(v);
 }
 
+// the tank's scalar idx to host-visible memory
+__global__ void k_scal_out_b(BatchArgs ba, int idx, double* __restrict__ out) {
+  SEM_BATCH_TANK(ba)
+  if (threadIdx.x == 0) out[it_.tank] = d.scal[idx];
+}
+
+// refinement: b32 = (float)(tmp * scale[tank]), x32 = 0
+__global__ void __launch_bounds__(kBlockThreads) k_to_float_b(BatchArgs ba, const double* __restrict__ scale) {
+  SEM_BATCH_TANK(ba)
+  const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  d.b32[i] = (float)(d.tmp[i] * scale[it_.tank]);
+  d.x32[i] = 0.0f;
+}
+
+// refinement: xs += scale[tank] * x32
+__global__ void __launch_bounds__(kBlockThreads) k_add_float_b(BatchArgs ba, const double* __restrict__ scale) {
+  SEM_BATCH_TANK(ba)
+  const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  d.xs[i] += scale[it_.tank] * (double)d.x32[i];
+}
+
+__global__ void k_status_or_b(BatchArgs ba, int bits) {
+  SEM_BATCH_TANK(ba)
+  if (threadIdx.x == 0) atomicOr(d.status, bits);
+}
+
 // surface value of node i (x-ordered surface array phis), or -1 when i is
 // not a surface node
 __device__ inline int64_t surface_slot(const TankDev& d, int64_t i) {
@@ -1540,6 +1568,18 @@ void launch_status_clear_b(const BatchArgs& a0, const BatchStage& per_tank, hipS
 void launch_state_out_b(const BatchArgs& a0, const BatchStage& per_tank, KrylovState* ks_out, int32_t* st_out,
                         int mark_noconv, hipStream_t st) {
   SEM_BLAUNCH(per_tank, k_state_out_b, ks_out, st_out, mark_noconv);
+}
+void launch_scal_out_b(const BatchArgs& a0, const BatchStage& per_tank, int idx, double* out, hipStream_t st) {
+  SEM_BLAUNCH(per_tank, k_scal_out_b, idx, out);
+}
+void launch_to_float_b(const BatchArgs& a0, const BatchStage& vec, const double* scale, hipStream_t st) {
+  SEM_BLAUNCH(vec, k_to_float_b, scale);
+}
+void launch_add_float_b(const BatchArgs& a0, const BatchStage& vec, const double* scale, hipStream_t st) {
+  SEM_BLAUNCH(vec, k_add_float_b, scale);
+}
+void launch_status_or_b(const BatchArgs& a0, const BatchStage& per_tank, int bits, hipStream_t st) {
+  SEM_BLAUNCH(per_tank, k_status_or_b, bits);
 }
 void launch_lift_in_b(const BatchArgs& a0, const BatchStage& vec, const double* const* phis,
                       const double* const* guess, hipStream_t st) {

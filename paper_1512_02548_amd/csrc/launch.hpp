@@ -125,6 +125,12 @@ void launch_status_clear_b(const BatchArgs& a, const BatchStage& per_tank, hipSt
 // ks_out / st_out: host-visible arrays indexed by tank
 void launch_state_out_b(const BatchArgs& a, const BatchStage& per_tank, KrylovState* ks_out, int32_t* st_out,
                         int mark_noconv, hipStream_t st);
+// scalar idx of every tank to out[tank] (host-visible)
+void launch_scal_out_b(const BatchArgs& a, const BatchStage& per_tank, int idx, double* out, hipStream_t st);
+// iterative refinement: b32 = tmp * scale[t], x32 = 0; then xs += scale[t] * x32
+void launch_to_float_b(const BatchArgs& a, const BatchStage& vec, const double* scale, hipStream_t st);
+void launch_add_float_b(const BatchArgs& a, const BatchStage& vec, const double* scale, hipStream_t st);
+void launch_status_or_b(const BatchArgs& a, const BatchStage& per_tank, int bits, hipStream_t st);
 void launch_lift_in_b(const BatchArgs& a, const BatchStage& vec, const double* const* phis,
                       const double* const* guess, hipStream_t st);
 void launch_solution_out_b(const BatchArgs& a, const BatchStage& vec, const double* const* phis, double* const* phi,
