@@ -226,6 +226,7 @@ def batch_workload(args):
     fp64 = lib.default_opts(rtol=1e-10, warm_start=1, max_iter=20000)
     mixed = lib.default_opts(rtol=1e-10, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-2, max_iter=20000)
     tl = batched("lockstep_fp64", 0, fp64)
+    batched("lockstep_mixed", 0, mixed)
     tc = batched("concurrent_mixed", args.streams, mixed)
     fp64 = lib.default_opts(rtol=1e-10, warm_start=1, max_iter=20000)
     restore()

@@ -7,7 +7,8 @@ be advanced a given number of RK4 steps.  The server
   (workspace + state) fits in the memory budget, in arrival order;
 * keeps every admitted tank's mesh, workspace and state resident;
 * advances all admitted tanks together, one RK4 step per tick, through the
-  library's batch call (their kernels overlap on the device);
+  library's batch call (lockstep by default: the stage solves of all
+  in-flight tanks run as one batched GMRES, every launch covering all tanks);
 * admits new tanks and retires finished (or failed) ones only between ticks;
 * records per-request latency (arrival to completion) and throughput.
 
@@ -48,7 +49,7 @@ class Request:
 class GpuBackend:
     """Tanks on the GPU through the C ABI; steps are batched across tanks."""
 
-    def __init__(self, nstreams=8, opts=None, device="cuda"):
+    def __init__(self, nstreams=0, opts=None, device="cuda"):
         import torch
 
         from . import lib
@@ -228,7 +229,8 @@ def main():
     ap.add_argument("--rate", type=float, default=4.0, help="arrivals per second")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--slots", type=int, default=32)
-    ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--streams", type=int, default=0,
+                    help="0: lockstep batch (default); >= 1: per-tank steps on that many streams")
     ap.add_argument("--max-nx", type=int, default=None)
     ap.add_argument("--quiet", action="store_true", help="no per-request lines on stderr")
     ap.add_argument("--sequential-fp64", action="store_true",

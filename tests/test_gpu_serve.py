@@ -29,15 +29,15 @@ def run_alone(spec, steps, opts):
     return be.result(t)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_batch_equals_alone(prec):
+@pytest.mark.parametrize("prec,nstreams", [(0, 0), (1, 0), (0, 4), (1, 4)])
+def test_batch_equals_alone(prec, nstreams):
     from paper_1512_02548_amd import lib
     from paper_1512_02548_amd.serve import GpuBackend
     opts = lib.default_opts(rtol=1e-10, warm_start=1, prec=prec, inner_rtol=1e-3)
     specs = small_specs()
     steps = 3
     alone = [run_alone(s, steps, opts) for s in specs]
-    be = GpuBackend(nstreams=4, opts=opts)
+    be = GpuBackend(nstreams=nstreams, opts=opts)
     tanks = [be.create(s, wl.batch_tank_state) for s in specs]
     for _ in range(steps):
         ok, msg = be.step(tanks)
@@ -47,13 +47,14 @@ def test_batch_equals_alone(prec):
         assert np.array_equal(r["eta"], a["eta"]) and np.array_equal(r["phi"], a["phi"])
 
 
-def test_server_mix_matches_alone():
+@pytest.mark.parametrize("nstreams", [0, 4])
+def test_server_mix_matches_alone(nstreams):
     from paper_1512_02548_amd import lib
     from paper_1512_02548_amd.serve import GpuBackend, Request, Server
     opts = lib.default_opts(rtol=1e-8, warm_start=1, prec=1, inner_rtol=1e-3)
     specs = small_specs()
     reqs = [Request(i, s, arrival=0.02 * i, steps=2 + (i % 3)) for i, s in enumerate(specs)]
-    srv = Server(GpuBackend(nstreams=4, opts=opts), wl.batch_tank_state, max_slots=4)
+    srv = Server(GpuBackend(nstreams=nstreams, opts=opts), wl.batch_tank_state, max_slots=4)
     rep = srv.run(reqs)
     assert rep["done"] == len(specs)
     for r in srv.finished:
