@@ -30,7 +30,7 @@ using namespace sem;
 
 namespace {
 // pointer tables handed to the batched kernels, each [count]
-enum { PT_PHIS = 0, PT_WS = 1, PT_YP = 2, PT_COUNT = 3 };
+enum { PT_PHIS = 0, PT_WS = 1, PT_YP = 2, PT_ETA = 3, PT_ETAX = 4, PT_COUNT = 5 };
 // pinned staging copies of small uploads (live flags, per-tank scales): a
 // slot is reused only after the stream has drained, so an asynchronous
 // upload never reads a later value
@@ -62,10 +62,14 @@ struct sem_batch {
   double* scal_host = nullptr;    // [count] tank scalars read back
   double* scal_dev = nullptr;
   double* dscale = nullptr;       // device [count] per-tank factors of the refinement
+  double* ddt = nullptr;          // device [count] time steps of the RK4 call
   const double** ptr_host = nullptr;
   BatchStage vec, dots, fixup, per_tank;
   BatchStage stiff[kMaxOrder + 1], stiff32[kMaxOrder + 1];   // FP64, FP32 (LDS sized per word)
   BatchSD sdlap, sdlap32;
+  BatchSD sdmass;                 // exact inverse of the 2D mass matrix (w recovery)
+  BatchStagePlan stage;           // the RK4 stage work around the solves
+  std::vector<int> walled;        // tanks whose 1D operators run as single-tank kernels
   std::vector<int> orders;
   int mmax = 0;
   ~sem_batch() {
@@ -138,12 +142,19 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   }
   plan_sd(B->tanks, ids, 0, 0, &B->sdlap);
   plan_sd(B->tanks, ids, 0, 1, &B->sdlap32);
+  plan_sd(B->tanks, ids, 1, 0, &B->sdmass);
+  plan_stage(B->tanks, ids, &B->stage);
+  for (int t = 0; t < count; ++t)
+    if (!B->tanks[t].circ1d) B->walled.push_back(t);
   std::vector<BatchStage*> stages = {&B->vec, &B->dots, &B->fixup, &B->per_tank};
   for (int P : B->orders) {
     stages.push_back(&B->stiff[P]);
     stages.push_back(&B->stiff32[P]);
   }
-  for (BatchSD* p : {&B->sdlap, &B->sdlap32})
+  for (int P = 1; P <= kMaxOrder; ++P)
+    for (BatchStage* st2 : {&B->stage.coef[P], &B->stage.sz[P], &B->stage.final_[P]}) stages.push_back(st2);
+  for (BatchStage* st2 : {&B->stage.surf, &B->stage.circ, &B->stage.fsl, &B->stage.fsg}) stages.push_back(st2);
+  for (BatchSD* p : {&B->sdlap, &B->sdlap32, &B->sdmass})
     for (BatchStage* s : {&p->cond, &p->modes, &p->fa, &p->fb, &p->fsolve, &p->wall, &p->wmodes, &p->fc, &p->fd,
                           &p->idft, &p->back})
       stages.push_back(s);
@@ -152,7 +163,7 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   const size_t o_live_d = (off + 255) / 256 * 256;
   off = o_live_d + count * sizeof(int32_t);
   const size_t o_scale_d = (off + 255) / 256 * 256;
-  off = o_scale_d + count * sizeof(double);
+  off = o_scale_d + 2 * count * sizeof(double);
   const size_t o_ptr_d = (off + 255) / 256 * 256;
   off = o_ptr_d + (size_t)PT_COUNT * count * sizeof(double*);
   std::vector<size_t> o_items;
@@ -167,6 +178,7 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   B->dtanks = (TankDev*)B->dmem;
   B->dlive = (int32_t*)(B->dmem + o_live_d);
   B->dscale = (double*)(B->dmem + o_scale_d);
+  B->ddt = B->dscale + count;
   B->dptr = (const double**)(B->dmem + o_ptr_d);
   HIPCHK(hipMemcpyAsync(B->dtanks, B->tanks.data(), count * sizeof(TankDev), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(B->dlive, 0, count * sizeof(int32_t), st));
@@ -183,6 +195,16 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
                         count * sizeof(double*), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   return SEM_OK;
+}
+
+static BatchArgs args(const sem_batch* B) {
+  BatchArgs a{};
+  a.tanks = B->dtanks;
+  a.live = B->dlive;
+  a.items = nullptr;
+  a.ptrs = B->dptr;
+  a.count = (int32_t)B->meshes.size();
+  return a;
 }
 
 static sem_status drain(sem_batch* B, hipStream_t st) {
@@ -229,7 +251,7 @@ static sem_status put_pointers(sem_batch* B, int which, const double* const* p, 
 static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rtol, int max_iter, int ahead, int f32,
                                  int gstore, int mark_noconv, std::vector<int32_t>& iters, hipStream_t st) {
   if (act.empty()) return SEM_OK;
-  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  const BatchArgs a = args(B);
   const BatchStage* stiff = f32 ? B->stiff32 : B->stiff;
   const BatchSD& sdp = f32 ? B->sdlap32 : B->sdlap;
   volatile int32_t* prog = B->prog_host;
@@ -322,7 +344,7 @@ static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rto
 static sem_status lockstep_ir(sem_batch* B, std::vector<int>& act, const sem_solve_opts& o,
                               std::vector<int32_t>& iters, hipStream_t st) {
   const int count = (int)B->meshes.size();
-  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  const BatchArgs a = args(B);
   const int gstore = o.prec == SEM_PREC_BF16_IR ? 2 : 1;
   sem_status s = set_live(B, act, st);
   if (s) return s;
@@ -402,7 +424,7 @@ static sem_status lockstep_ir(sem_batch* B, std::vector<int>& act, const sem_sol
 static sem_status lockstep_laplace(sem_batch* B, std::vector<int>& act, int phis_table, int warm,
                                    const sem_solve_opts& o, std::vector<int32_t>& iters, hipStream_t st) {
   const int count = (int)B->meshes.size();
-  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  const BatchArgs a = args(B);
   sem_status s = set_live(B, act, st);
   if (s) return s;
   const double* const* phis = B->dptr + (size_t)phis_table * count;
@@ -444,15 +466,17 @@ static sem_status lockstep_solve(sem_batch* B, const double* const* eta, const d
     if (!eta[t] || !eta_x[t] || !phi_s[t] || !phi[t]) return fail(SEM_E_INVAL, "null per-tank argument");
     act.push_back(t);
   }
-  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  const BatchArgs a = args(B);
   s = put_pointers(B, PT_PHIS, phi_s, st);
   if (!s) s = put_pointers(B, PT_WS, (const double* const*)phi, st);
+  if (!s) s = put_pointers(B, PT_ETA, eta, st);
+  if (!s) s = put_pointers(B, PT_ETAX, eta_x, st);
   if (s) return s;
   std::vector<int> all = act;
   s = set_live(B, act, st);
   if (s) return s;
   launch_status_clear_b(a, B->per_tank, st);
-  for (int t : act) launch_coef(B->meshes[t]->hd, B->meshes[t]->dtank, eta[t], eta_x[t], 3, st);
+  launch_coef_b(a, B->stage, SSel{SS_PT, PT_ETA}, SSel{SS_PT, PT_ETAX}, 3, st);
   std::vector<int32_t> iters(count, 0);
   s = lockstep_laplace(B, act, PT_PHIS, o.warm_start, o, iters, st);
   if (s) return s;
@@ -473,6 +497,11 @@ static sem_status lockstep_solve(sem_batch* B, const double* const* eta, const d
   return SEM_OK;
 }
 
+// One RK4 step of every active tank; the same steps as the single-tank call
+// (gradient recovery, coefficients, Laplace solve, w recovery, free-surface
+// right side, stage update; filter and transactional write-back at the end),
+// each as one launch over all tanks.  Tanks with walls take their 1D
+// operators from the single-tank kernels.
 static sem_status lockstep_rk4(sem_batch* B, double* const* eta, double* const* phi_s, double* const* phi_ws,
                                const double* dt, const uint8_t* active, const sem_solve_opts* opts,
                                int32_t* per_status, int32_t* per_iters, hipStream_t st) {
@@ -483,9 +512,11 @@ static sem_status lockstep_rk4(sem_batch* B, double* const* eta, double* const* 
   std::vector<int> act;
   for (int t = 0; t < count; ++t)
     if (!active || active[t]) act.push_back(t);
-  const BatchArgs a{B->dtanks, B->dlive, nullptr};
+  const BatchArgs a = args(B);
   s = put_pointers(B, PT_PHIS, (const double* const*)phi_s, st);
   if (!s) s = put_pointers(B, PT_WS, (const double* const*)phi_ws, st);
+  if (!s) s = put_pointers(B, PT_ETA, (const double* const*)eta, st);
+  if (!s) s = upload(B, B->ddt, dt, count * sizeof(double), st);
   if (s) return s;
   const std::vector<int> all = act;
   s = set_live(B, act, st);
@@ -494,39 +525,49 @@ static sem_status lockstep_rk4(sem_batch* B, double* const* eta, double* const* 
   std::vector<int32_t> iters(count, 0);
   const double cnode[4] = {0.0, 0.5, 0.5, 1.0};
   const double wts[4] = {1.0 / 6, 2.0 / 6, 2.0 / 6, 1.0 / 6};
+  const SSel RK[9] = {{SS_RK, 0}, {SS_RK, 1}, {SS_RK, 2}, {SS_RK, 3}, {SS_RK, 4},
+                      {SS_RK, 5}, {SS_RK, 6}, {SS_RK, 7}, {SS_RK, 8}};
+  auto in_act = [&](int t) { return std::find(act.begin(), act.end(), t) != act.end(); };
   for (int sidx = 0; sidx < 4 && !act.empty(); ++sidx) {
-    for (int t : act) {
+    const SSel se = sidx == 0 ? SSel{SS_PT, PT_ETA} : RK[0];
+    const SSel sp = sidx == 0 ? SSel{SS_PT, PT_PHIS} : RK[1];
+    s = set_live(B, act, st);
+    if (s) return s;
+    launch_recover_dx_b(a, B->stage, se, RK[2], sp, RK[3], st);
+    for (int t : B->walled) {
+      if (!in_act(t)) continue;
       sem_mesh* M = B->meshes[t];
-      const int ns = (int)M->ns;
-      double* rk = M->rk;
-      const double* se = sidx == 0 ? eta[t] : rk;
-      const double* sp = sidx == 0 ? phi_s[t] : rk + ns;
-      launch_recover_dx(M->hd, M->dtank, se, rk + 2 * ns, sp, rk + 3 * ns, st);
-      launch_coef(M->hd, M->dtank, se, rk + 2 * ns, 3, st);
+      const size_t ns = M->ns;
+      launch_recover_dx(M->hd, M->dtank, sidx == 0 ? eta[t] : M->rk, M->rk + 2 * ns,
+                        sidx == 0 ? phi_s[t] : M->rk + ns, M->rk + 3 * ns, st);
     }
+    launch_coef_b(a, B->stage, se, RK[2], 3, st);
     s = lockstep_laplace(B, act, sidx == 0 ? PT_PHIS : PT_YP, 1, o, iters, st);
     if (s) return s;
-    for (int t : act) {
+    if (act.empty()) break;
+    s = set_live(B, act, st);
+    if (s) return s;
+    // w~: M w = S_z Phi, w~ = w at the surface
+    launch_sz_b(a, B->stage, SSel{SS_PT, PT_WS}, st);
+    launch_fixup_b(a, B->fixup, VSel{BV_B, 0}, 0, 0, st);
+    launch_sd_b(a, B->sdmass, 1, VSel{BV_B, 0}, VSel{BV_WMASS, 0}, 0, 0, 0, st);
+    launch_gather_surface_b(a, B->stage, VSel{BV_WMASS, 0}, RK[4], st);
+    launch_fs_rhs_b(a, B->stage, se, RK[2], RK[3], RK[4], RK[5], RK[6], st);
+    for (int t : B->walled) {
+      if (!in_act(t)) continue;
       sem_mesh* M = B->meshes[t];
-      const int ns = (int)M->ns;
+      const size_t ns = M->ns;
       double* rk = M->rk;
-      const double* se = sidx == 0 ? eta[t] : rk;
-      s = recover_w_core(M, phi_ws[t], rk + 4 * ns, st);
-      if (s) return s;
-      launch_fs_rhs(M->hd, M->dtank, se, rk + 2 * ns, rk + 3 * ns, rk + 4 * ns, rk + 5 * ns, rk + 6 * ns, st);
-      if (sidx < 3)
-        launch_rk4_stage(ns, cnode[sidx + 1] * dt[t], wts[sidx], sidx == 0, eta[t], phi_s[t], rk + 5 * ns,
-                         rk + 6 * ns, rk, rk + ns, rk + 7 * ns, rk + 8 * ns, st);
-      else
-        launch_rk4_stage(ns, 0.0, wts[sidx], 0, eta[t], phi_s[t], rk + 5 * ns, rk + 6 * ns, rk, rk + ns,
-                         rk + 7 * ns, rk + 8 * ns, st);
+      launch_fs_rhs(M->hd, M->dtank, sidx == 0 ? eta[t] : rk, rk + 2 * ns, rk + 3 * ns, rk + 4 * ns, rk + 5 * ns,
+                    rk + 6 * ns, st);
     }
+    launch_rk4_stage_b(a, B->stage, B->ddt, sidx < 3 ? cnode[sidx + 1] : 0.0, wts[sidx], sidx == 0 ? 1 : 0,
+                       SSel{SS_PT, PT_ETA}, SSel{SS_PT, PT_PHIS}, st);
   }
-  for (int t : act) {
-    sem_mesh* M = B->meshes[t];
-    const int ns = (int)M->ns;
-    launch_rk4_final(M->hd, M->dtank, dt[t], M->rk + 7 * ns, M->rk + 8 * ns, eta[t], phi_s[t], M->sf != 1.0 ? 1 : 0,
-                     st);
+  if (!act.empty()) {
+    s = set_live(B, act, st);
+    if (s) return s;
+    launch_rk4_final_b(a, B->stage, B->ddt, SSel{SS_PT, PT_ETA}, SSel{SS_PT, PT_PHIS}, st);
   }
   s = set_live(B, all, st);
   if (s) return s;

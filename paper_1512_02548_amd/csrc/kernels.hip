@@ -96,11 +96,10 @@ struct Prec<float, BF16> : Prec<float, float> {
 // ------------------------------------------------------------ coefficients
 // G = |J| Lam K Lam^T and 1/d at every element node (paper Sec. 2).
 template <int P>
-__global__ void k_coef(const TankDev* __restrict__ td, const double* __restrict__ eta,
-                       const double* __restrict__ etax, int what) {
-  const TankDev& d = *td;
+__device__ __forceinline__ void coef_body(const TankDev& d, const double* __restrict__ eta,
+                                          const double* __restrict__ etax, int what, int bx) {
   constexpr int Np = (P + 1) * (P + 2) / 2;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)bx * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)d.nx * 2 * d.nz * Np;
   if (gid >= total) return;
   int m = gid % Np;
@@ -147,22 +146,24 @@ __global__ void k_coef(const TankDev* __restrict__ td, const double* __restrict_
   d.G16[tile_index(d.T, d.NpP, b, eb, m, 3, 2)] = float_to_bf16((float)Gss);
 }
 
+template <int P>
+__global__ void k_coef(const TankDev* __restrict__ td, const double* __restrict__ eta,
+                       const double* __restrict__ etax, int what) {
+  coef_body<P>(*td, eta, etax, what, blockIdx.x);
+}
+
 // ------------------------------------------------------------ gather kernels
 
 // Per block: y_owned = sum over the block's elements of op_e(u_e).
 // LDS: region of the input (cb*nc + nl), per-element stage buffers.
 template <int P, int OP, typename T = double, typename GS = double>
-__global__ void __launch_bounds__(kBlockThreads)
-k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict__ y,
-         T* __restrict__ side, int flags) {
-  const TankDev& d = *td;
-  if ((flags & F_GATE) && d.ks->done) return;
+__device__ __forceinline__ void gather_body(const TankDev& d, const T* __restrict__ u, T* __restrict__ y,
+                                            T* __restrict__ side, int flags, int b) {
   using PR = Prec<T, GS>;
   constexpr int Np = (P + 1) * (P + 2) / 2;
   constexpr int NpP = (Np + 15) / 16 * 16;
   extern __shared__ unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
-  const int b = blockIdx.x;
   const int c0 = b * d.cb;
   const int cbb = min(d.cb, d.nx - c0);
   const int nc = d.nc, nl = d.nl;
@@ -302,6 +303,15 @@ k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict_
   }
 }
 
+template <int P, int OP, typename T = double, typename GS = double>
+__global__ void __launch_bounds__(kBlockThreads)
+k_gather(const TankDev* __restrict__ td, const T* __restrict__ u, T* __restrict__ y,
+         T* __restrict__ side, int flags) {
+  const TankDev& d = *td;
+  if ((flags & F_GATE) && d.ks->done) return;
+  gather_body<P, OP, T, GS>(d, u, y, side, flags, blockIdx.x);
+}
+
 // adds the right-line contributions of each block to the stored left lines
 template <typename T>
 __device__ __forceinline__ void fixup_body(const TankDev& d, T* __restrict__ y, const T* __restrict__ side, int bx) {
@@ -375,13 +385,17 @@ __global__ void k_scatter_surface(const TankDev* __restrict__ td, const double* 
   }
 }
 
-__global__ void k_gather_surface(const TankDev* __restrict__ td, const double* __restrict__ u,
-                                 double* __restrict__ out) {
-  const TankDev& d = *td;
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gather_surface_body(const TankDev& d, const double* __restrict__ u,
+                                                    double* __restrict__ out, int bx) {
+  int s = bx * blockDim.x + threadIdx.x;
   if (s >= d.ns) return;
   int c = s / d.P, m = s - c * d.P;
   out[s] = u[(int64_t)c * d.nc + d.surf_loc[m]];
+}
+
+__global__ void k_gather_surface(const TankDev* __restrict__ td, const double* __restrict__ u,
+                                 double* __restrict__ out) {
+  gather_surface_body(*td, u, out, blockIdx.x);
 }
 
 // ------------------------------------------------------------ fused reductions
@@ -1128,11 +1142,10 @@ k_fs_rhs(const TankDev* __restrict__ td, const double* __restrict__ eta, const d
 // y[eP + a] = sum_j row[a][j] x[(eP + j) mod ns].  One wavefront per output
 // node: lanes stride over j, then a butterfly sum (fixed order).  x1/y1, when
 // given, is a second vector with the same operator.
-__global__ void __launch_bounds__(kBlockThreads)
-k_circ_apply(const TankDev* __restrict__ td, int which, const double* __restrict__ x0, double* __restrict__ y0,
-             const double* __restrict__ x1, double* __restrict__ y1) {
-  const TankDev& d = *td;
-  const int s = blockIdx.x * (kBlockThreads / 64) + (threadIdx.x >> 6);
+__device__ __forceinline__ void circ_body(const TankDev& d, int which, const double* __restrict__ x0,
+                                          double* __restrict__ y0, const double* __restrict__ x1,
+                                          double* __restrict__ y1, int bx) {
+  const int s = bx * (kBlockThreads / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (s >= d.ns) return;
   const int P = d.P, ns = d.ns;
@@ -1155,19 +1168,24 @@ k_circ_apply(const TankDev* __restrict__ td, int which, const double* __restrict
   }
 }
 
+__global__ void __launch_bounds__(kBlockThreads)
+k_circ_apply(const TankDev* __restrict__ td, int which, const double* __restrict__ x0, double* __restrict__ y0,
+             const double* __restrict__ x1, double* __restrict__ y1) {
+  circ_body(*td, which, x0, y0, x1, y1, blockIdx.x);
+}
+
 // Over-integrated element right-hand sides (Secs. 3.1.1, 3.3): loc[e][i][2]
 // = J_e (I^T M_f F)_i for F_eta and F_phi.  One wavefront per element: the
 // fluxes at the P_f+1 fine nodes, their mass-weighted sums, then the
 // projection back onto the P+1 element nodes.
-__global__ void __launch_bounds__(kBlockThreads)
-k_fs_local(const TankDev* __restrict__ td, const double* __restrict__ eta, const double* __restrict__ etax,
-           const double* __restrict__ phix, const double* __restrict__ ws, double* __restrict__ loc) {
-  const TankDev& d = *td;
+__device__ __forceinline__ void fs_local_body(const TankDev& d, const double* __restrict__ eta,
+                                              const double* __restrict__ etax, const double* __restrict__ phix,
+                                              const double* __restrict__ ws, double* __restrict__ loc, int bx) {
   constexpr int kW = kBlockThreads / 64;
   __shared__ double fl[kW][2][64];
   __shared__ double mf[kW][2][64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int e = blockIdx.x * kW + wv;
+  const int e = bx * kW + wv;
   const bool live = e < d.nx;
   const int P = d.P, nf = d.Pf + 1;
   if (live && lane < nf) {
@@ -1210,11 +1228,16 @@ k_fs_local(const TankDev* __restrict__ td, const double* __restrict__ eta, const
   }
 }
 
+__global__ void __launch_bounds__(kBlockThreads)
+k_fs_local(const TankDev* __restrict__ td, const double* __restrict__ eta, const double* __restrict__ etax,
+           const double* __restrict__ phix, const double* __restrict__ ws, double* __restrict__ loc) {
+  fs_local_body(*td, eta, etax, phix, ws, loc, blockIdx.x);
+}
+
 // node sums of the element right-hand sides (left element first)
-__global__ void k_fs_gather(const TankDev* __restrict__ td, const double* __restrict__ loc,
-                            double* __restrict__ re, double* __restrict__ rp) {
-  const TankDev& d = *td;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fs_gather_body(const TankDev& d, const double* __restrict__ loc,
+                                               double* __restrict__ re, double* __restrict__ rp, int bx) {
+  const int s = bx * blockDim.x + threadIdx.x;
   if (s >= d.ns) return;
   const int P = d.P;
   const int e = s / P, k = s - e * P;
@@ -1235,6 +1258,11 @@ __global__ void k_fs_gather(const TankDev* __restrict__ td, const double* __rest
   rp[s] = ap;
 }
 
+__global__ void k_fs_gather(const TankDev* __restrict__ td, const double* __restrict__ loc,
+                            double* __restrict__ re, double* __restrict__ rp) {
+  fs_gather_body(*td, loc, re, rp, blockIdx.x);
+}
+
 // ------------------------------------------------------------ RK4 + filter
 // stage: ye = y0e + a*dt*ke, yp = y0p + a*dt*kp ; acc += w * k
 __global__ void k_rk4_stage(int ns, double adt, double wgt, int first, const double* __restrict__ y0e,
@@ -1253,11 +1281,9 @@ __global__ void k_rk4_stage(int ns, double adt, double wgt, int first, const dou
 // y = y0 + dt*acc, then the element filter on interior nodes; writes the
 // caller's arrays only when the status word is clean (transactional step).
 template <int P>
-__global__ void __launch_bounds__(kBlockThreads)
-k_rk4_final(const TankDev* __restrict__ td, double dt, const double* __restrict__ acce,
-            const double* __restrict__ accp, double* __restrict__ eta, double* __restrict__ phi,
-            int use_filter) {
-  const TankDev& d = *td;
+__device__ __forceinline__ void rk4_final_body(const TankDev& d, double dt, const double* __restrict__ acce,
+                                               const double* __restrict__ accp, double* __restrict__ eta,
+                                               double* __restrict__ phi, int use_filter) {
   double* ne = d.s1d + 13 * (size_t)d.ns;
   double* np_ = d.s1d + 14 * (size_t)d.ns;
   for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
@@ -1297,6 +1323,90 @@ k_rk4_final(const TankDev* __restrict__ td, double dt, const double* __restrict_
     eta[s] = fe[s];
     phi[s] = fp[s];
   }
+}
+
+template <int P>
+__global__ void __launch_bounds__(kBlockThreads)
+k_rk4_final(const TankDev* __restrict__ td, double dt, const double* __restrict__ acce,
+            const double* __restrict__ accp, double* __restrict__ eta, double* __restrict__ phi,
+            int use_filter) {
+  rk4_final_body<P>(*td, dt, acce, accp, eta, phi, use_filter);
+}
+
+// ------------------------------------------------------------ batched stage kernels
+// The per-stage work of the RK4 step around the Laplace solve, over many
+// tanks per launch (the single-tank bodies on each tank's own data).
+__global__ void __launch_bounds__(kBlockThreads)
+k_circ_apply_b(BatchArgs ba, int which, SSel x0, SSel y0, SSel x1, SSel y1) {
+  SEM_BATCH_TANK(ba)
+  circ_body(d, which, svec(ba, d, it_.tank, x0), svec(ba, d, it_.tank, y0), svec(ba, d, it_.tank, x1),
+            svec(ba, d, it_.tank, y1), it_.bx);
+}
+
+// M'^-1 applied to the free-surface node sums kept in s1d rows 11 and 12
+__global__ void __launch_bounds__(kBlockThreads) k_circ_apply_s1d_b(BatchArgs ba, SSel y0, SSel y1) {
+  SEM_BATCH_TANK(ba)
+  circ_body(d, 1, d.s1d + 11 * (size_t)d.ns, svec(ba, d, it_.tank, y0), d.s1d + 12 * (size_t)d.ns,
+            svec(ba, d, it_.tank, y1), it_.bx);
+}
+
+template <int P>
+__global__ void __launch_bounds__(kBlockThreads) k_coef_b(BatchArgs ba, SSel eta, SSel etax, int what) {
+  SEM_BATCH_TANK(ba)
+  coef_body<P>(d, svec(ba, d, it_.tank, eta), svec(ba, d, it_.tank, etax), what, it_.bx);
+}
+
+// S_z Phi (element kernel of the reference gather; Phi from a pointer table)
+template <int P>
+__global__ void __launch_bounds__(kBlockThreads) k_sz_b(BatchArgs ba, SSel u) {
+  SEM_BATCH_TANK(ba)
+  gather_body<P, OP_SZ, double, double>(d, svec(ba, d, it_.tank, u), d.b, d.side, 0, it_.bx);
+}
+
+__global__ void __launch_bounds__(kBlockThreads) k_gather_surface_b(BatchArgs ba, VSel u, SSel out) {
+  SEM_BATCH_TANK(ba)
+  gather_surface_body(d, bvec<double>(d, u), svec(ba, d, it_.tank, out), it_.bx);
+}
+
+// element right sides into s1d (the single-tank kernels' scratch)
+__global__ void __launch_bounds__(kBlockThreads)
+k_fs_local_b(BatchArgs ba, SSel eta, SSel etax, SSel phix, SSel ws) {
+  SEM_BATCH_TANK(ba)
+  fs_local_body(d, svec(ba, d, it_.tank, eta), svec(ba, d, it_.tank, etax), svec(ba, d, it_.tank, phix),
+                svec(ba, d, it_.tank, ws), d.s1d + 5 * (size_t)d.ns, it_.bx);
+}
+
+__global__ void __launch_bounds__(kBlockThreads) k_fs_gather_b(BatchArgs ba, int) {
+  SEM_BATCH_TANK(ba)
+  fs_gather_body(d, d.s1d + 5 * (size_t)d.ns, d.s1d + 11 * (size_t)d.ns, d.s1d + 12 * (size_t)d.ns, it_.bx);
+}
+
+// stage update with each tank's own step: ye = y0e + c dt ke, ... (as k_rk4_stage)
+__global__ void __launch_bounds__(kBlockThreads)
+k_rk4_stage_b(BatchArgs ba, const double* __restrict__ dt, double c, double wgt, int first, SSel y0e, SSel y0p) {
+  SEM_BATCH_TANK(ba)
+  const int s = it_.bx * blockDim.x + threadIdx.x;
+  if (s >= d.ns) return;
+  const size_t ns = d.ns;
+  const double adt = c * dt[it_.tank];
+  const double* ke = d.rk + 5 * ns;
+  const double* kp = d.rk + 6 * ns;
+  double* acce = d.rk + 7 * ns;
+  double* accp = d.rk + 8 * ns;
+  const double a = ke[s], bq = kp[s];
+  acce[s] = (first ? 0.0 : acce[s]) + wgt * a;
+  accp[s] = (first ? 0.0 : accp[s]) + wgt * bq;
+  d.rk[s] = svec(ba, d, it_.tank, y0e)[s] + adt * a;
+  d.rk[ns + s] = svec(ba, d, it_.tank, y0p)[s] + adt * bq;
+}
+
+template <int P>
+__global__ void __launch_bounds__(kBlockThreads)
+k_rk4_final_b(BatchArgs ba, const double* __restrict__ dt, SSel eta, SSel phi) {
+  SEM_BATCH_TANK(ba)
+  const size_t ns = d.ns;
+  rk4_final_body<P>(d, dt[it_.tank], d.rk + 7 * ns, d.rk + 8 * ns, svec(ba, d, it_.tank, eta),
+                    svec(ba, d, it_.tank, phi), d.use_filter);
 }
 
 // ------------------------------------------------------------ launchers
@@ -1633,5 +1743,64 @@ void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const doubl
                       double* eta, double* phi, int use_filter, hipStream_t st) {
   SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_rk4_final<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, dt, acce, accp, eta, phi, use_filter));
 }
+
+// ------------------------------------------------------------ batched stage launchers
+void plan_stage(const std::vector<TankDev>& tanks, const std::vector<int>& ids, BatchStagePlan* out) {
+  *out = BatchStagePlan{};
+  for (int t : ids) {
+    const TankDev& h = tanks[t];
+    auto add = [&](BatchStage& s, int gx, size_t lds) {
+      for (int x = 0; x < gx; ++x) s.items.push_back(BatchItem{t, x, 0, gx});
+      s.lds = std::max(s.lds, lds);
+    };
+    const int P = h.P;
+    add(out->coef[P], (int)nblk((int64_t)h.nx * 2 * h.nz * h.Np), 0);
+    add(out->sz[P], h.nb, gather_lds_bytes(h, sizeof(double)));
+    add(out->final_[P], 1, 0);
+    add(out->surf, (int)nblk(h.ns), 0);
+    if (h.circ1d) {
+      add(out->circ, (int)nblk(h.ns, kBlockThreads / 64), 0);
+      add(out->fsl, (int)nblk(h.nx, kBlockThreads / 64), 0);
+      add(out->fsg, (int)nblk(h.ns), 0);
+    }
+  }
+}
+
+#define SEM_BL(ST, KERN, ...)                                                                                   \
+  do {                                                                                                        \
+    BatchArgs a_;                                                                                             \
+    if (batch_args(a0, ST, &a_))                                                                              \
+      hipLaunchKernelGGL(KERN, dim3((unsigned)(ST).items.size()), dim3(kBlockThreads), (ST).lds, st, a_,       \
+                         __VA_ARGS__);                                                                         \
+  } while (0)
+
+void launch_recover_dx_b(const BatchArgs& a0, const BatchStagePlan& p, SSel in0, SSel out0, SSel in1, SSel out1,
+                         hipStream_t st) {
+  SEM_BL(p.circ, k_circ_apply_b, 0, in0, out0, in1, out1);
+}
+void launch_coef_b(const BatchArgs& a0, const BatchStagePlan& p, SSel eta, SSel etax, int what, hipStream_t st) {
+  for (int P = 1; P <= kMaxOrder; ++P) SEM_P_SWITCH(P, SEM_BL(p.coef[PP], k_coef_b<PP>, eta, etax, what));
+}
+void launch_sz_b(const BatchArgs& a0, const BatchStagePlan& p, SSel u, hipStream_t st) {
+  for (int P = 1; P <= kMaxOrder; ++P) SEM_P_SWITCH(P, SEM_BL(p.sz[PP], k_sz_b<PP>, u));
+}
+void launch_gather_surface_b(const BatchArgs& a0, const BatchStagePlan& p, VSel u, SSel out, hipStream_t st) {
+  SEM_BL(p.surf, k_gather_surface_b, u, out);
+}
+void launch_fs_rhs_b(const BatchArgs& a0, const BatchStagePlan& p, SSel eta, SSel etax, SSel phix, SSel ws,
+                     SSel et, SSel pt, hipStream_t st) {
+  SEM_BL(p.fsl, k_fs_local_b, eta, etax, phix, ws);
+  SEM_BL(p.fsg, k_fs_gather_b, 0);
+  SEM_BL(p.circ, k_circ_apply_s1d_b, et, pt);   // M'^-1 of the node sums
+}
+void launch_rk4_stage_b(const BatchArgs& a0, const BatchStagePlan& p, const double* dt, double c, double wgt,
+                        int first, SSel y0e, SSel y0p, hipStream_t st) {
+  SEM_BL(p.surf, k_rk4_stage_b, dt, c, wgt, first, y0e, y0p);
+}
+void launch_rk4_final_b(const BatchArgs& a0, const BatchStagePlan& p, const double* dt, SSel eta, SSel phi,
+                        hipStream_t st) {
+  for (int P = 1; P <= kMaxOrder; ++P) SEM_P_SWITCH(P, SEM_BL(p.final_[PP], k_rk4_final_b<PP>, dt, eta, phi));
+}
+#undef SEM_BL
 
 }  // namespace sem

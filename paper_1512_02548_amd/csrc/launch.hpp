@@ -131,6 +131,26 @@ void launch_scal_out_b(const BatchArgs& a, const BatchStage& per_tank, int idx, 
 void launch_to_float_b(const BatchArgs& a, const BatchStage& vec, const double* scale, hipStream_t st);
 void launch_add_float_b(const BatchArgs& a, const BatchStage& vec, const double* scale, hipStream_t st);
 void launch_status_or_b(const BatchArgs& a, const BatchStage& per_tank, int bits, hipStream_t st);
+// the RK4 stage work around the Laplace solve, per launch over many tanks
+struct BatchStagePlan {
+  BatchStage coef[kMaxOrder + 1], sz[kMaxOrder + 1], final_[kMaxOrder + 1];   // per order
+  BatchStage surf;            // elementwise over the surface nodes
+  BatchStage circ, fsl, fsg;  // periodic 1D operators (tanks with walls use the single-tank kernels)
+};
+void plan_stage(const std::vector<TankDev>& tanks, const std::vector<int>& ids, BatchStagePlan* out);
+void launch_recover_dx_b(const BatchArgs& a, const BatchStagePlan& p, SSel in0, SSel out0, SSel in1, SSel out1,
+                         hipStream_t st);
+void launch_coef_b(const BatchArgs& a, const BatchStagePlan& p, SSel eta, SSel etax, int what, hipStream_t st);
+// S_z u into each tank's b (element kernel; the line fix-up follows separately)
+void launch_sz_b(const BatchArgs& a, const BatchStagePlan& p, SSel u, hipStream_t st);
+void launch_gather_surface_b(const BatchArgs& a, const BatchStagePlan& p, VSel u, SSel out, hipStream_t st);
+void launch_fs_rhs_b(const BatchArgs& a, const BatchStagePlan& p, SSel eta, SSel etax, SSel phix, SSel ws,
+                     SSel et, SSel pt, hipStream_t st);
+// dt: device [count]; ye, yp = stage arrays 0, 1 of each tank
+void launch_rk4_stage_b(const BatchArgs& a, const BatchStagePlan& p, const double* dt, double c, double wgt,
+                        int first, SSel y0e, SSel y0p, hipStream_t st);
+void launch_rk4_final_b(const BatchArgs& a, const BatchStagePlan& p, const double* dt, SSel eta, SSel phi,
+                        hipStream_t st);
 void launch_lift_in_b(const BatchArgs& a, const BatchStage& vec, const double* const* phis,
                       const double* const* guess, hipStream_t st);
 void launch_solution_out_b(const BatchArgs& a, const BatchStage& vec, const double* const* phis, double* const* phi,

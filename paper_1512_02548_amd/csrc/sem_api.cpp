@@ -1147,6 +1147,8 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   M->scal = at<double>(M, "scal");
   h.scal = M->scal;
   h.prog = M->prog_dev;
+  h.rk = M->rk;
+  h.use_filter = M->sf != 1.0 ? 1 : 0;
   M->dtank = at<TankDev>(M, "tank");
   // every device array the kernels use must have been laid out
   const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.opf, h.opf32, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,

@@ -155,6 +155,9 @@ struct TankDev {
   float* b32;
   double* scal;                   // [64] small scalars (norms of the current solve)
   int32_t* prog;                  // progress word of the running Krylov cycle (host-visible), or null
+  double* rk;                     // [9][ns] RK4 stage arrays: eta, phi, eta_x, phi_x, w~, slopes (2), sums (2)
+  int32_t use_filter;             // the modal filter is on
+  int32_t pad4;
 };
 
 // ------------------------------------------------------------ batched launches
@@ -171,7 +174,20 @@ struct BatchArgs {
   const TankDev* tanks;     // [count] copies of the tanks' descriptors
   const int32_t* live;      // [count] 1 while the tank takes part in the current solve
   const BatchItem* items;   // the launch's work items, one per workgroup
+  const double* const* ptrs;   // [tables][count] the caller's per-tank surface and volume arrays
+  int32_t count;
+  int32_t pad;
 };
+
+// A surface array of a tank: one of its RK4 stage arrays (rk + k ns), or the
+// caller's array from pointer table k.
+enum : int32_t { SS_RK = 0, SS_PT = 1 };
+struct SSel {
+  int32_t kind, k;
+};
+__host__ __device__ inline double* svec(const BatchArgs& ba, const TankDev& d, int tank, SSel s) {
+  return s.kind == SS_RK ? d.rk + (size_t)s.k * d.ns : const_cast<double*>(ba.ptrs[(size_t)s.k * ba.count + tank]);
+}
 
 // Start of every batched kernel: the workgroup reads its work item, returns
 // unless its tank takes part in the solve, and then runs the single-tank code
