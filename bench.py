@@ -147,14 +147,18 @@ def large_tank(lib, wl, torch, reps=3):
     return out
 
 
-def build_meshes(lib, specs, state_fn, threads=8):
+def build_meshes(lib, specs, state_fn, threads=8, tiles=None):
     """Host-side mesh construction in parallel (the C calls release the GIL),
-    then device binding; returns meshes and device states."""
+    then device binding; returns meshes and device states.  tiles: an
+    autotuner table ((P, nz) -> stiffness tiles per workgroup) or None."""
     import torch
     from concurrent.futures import ThreadPoolExecutor
 
+    from paper_1512_02548_amd import tune
+
     def probe(spec):
-        return lib.mesh_from_spec(spec, np.ones(spec.ns), np.zeros(spec.ns), bind=False)
+        return lib.mesh_from_spec(spec, np.ones(spec.ns), np.zeros(spec.ns), bind=False,
+                                  tiles_per_block=tune.tiles_for(tiles, spec))
 
     with ThreadPoolExecutor(threads) as ex:
         probes = list(ex.map(probe, specs))
@@ -163,7 +167,7 @@ def build_meshes(lib, specs, state_fn, threads=8):
 
     def rebuild(i):
         e, ph, h, hx = states[i]
-        return lib.mesh_from_spec(specs[i], h, hx, bind=False)
+        return lib.mesh_from_spec(specs[i], h, hx, bind=False, tiles_per_block=tune.tiles_for(tiles, specs[i]))
 
     with ThreadPoolExecutor(threads) as ex:
         for i, m in zip(need, ex.map(rebuild, need)):
@@ -185,14 +189,18 @@ def batch_workload(args):
 
     from paper_1512_02548_amd import lib
     from paper_1512_02548_amd import workloads as wl
+    from paper_1512_02548_amd import tune
     specs = wl.batch_tank_specs(count=args.tanks, rtol=1e-10)
+    # element tiles of the stiffness kernel from the autotuner, per (P, nz) class
+    table, trep = tune.tune(specs)
+    print(f"# autotune: {trep}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    tanks = build_meshes(lib, specs, wl.batch_tank_state)
+    tanks = build_meshes(lib, specs, wl.batch_tank_state, tiles=table)
     t_build = time.perf_counter() - t0
     nfree = sum(int(t["mesh"].info.n_free) for t in tanks)
     dts = [sp.dt for sp in specs]
     res = {"workload": f"batch_tanks_{args.tanks}", "tanks": args.tanks, "sum_n_free": nfree,
-           "host_build_s": t_build, "steps": args.batch_steps}
+           "host_build_s": t_build, "steps": args.batch_steps, "autotune": trep}
     save = [(t["eta"].clone(), t["phi"].clone()) for t in tanks]
 
     def restore():

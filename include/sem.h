@@ -89,6 +89,8 @@ typedef struct {
   int32_t overint_order;       /* Pf >= P: GLL(Pf) fine grid for the FS right side; Pf == P: none */
   int32_t restart;             /* GMRES restart length, 0 = default (30)            */
   int32_t variant;             /* stiffness kernel: 0 = matrix cores (MFMA), 1 = reference vector-ALU kernel */
+  int32_t tiles_per_block;     /* element tile of the stiffness kernel: 16-element MFMA tiles per workgroup
+                                  (1..4; the columns per workgroup follow), 0 = chosen from the tank size */
 } sem_mesh_desc;
 
 typedef struct {

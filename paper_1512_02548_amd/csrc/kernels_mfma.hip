@@ -322,10 +322,19 @@ __global__ void k_mfma_probe(double* out64, float* out32) {
   }
 }
 
-// operators go to LDS unless they would take more than 40 KiB
+// operators go to LDS unless they would take more than 40 KiB.  (A workgroup
+// may hold up to 160 KiB of LDS on this chip, but the 72 KiB eighth-order
+// FP64 operators leave room for one workgroup per CU, which measured slower
+// than reading their fragments through the caches with more workgroups.)
 template <typename T>
 __host__ __device__ inline int stiff_ops_in_lds(const TankDev& h) {
   return 4 * (size_t)h.NpP * h.NpP * sizeof(T) <= 40 * 1024 ? 1 : 0;
+}
+
+// kernels whose dynamic LDS exceeds the default 64 KiB are allowed more once
+template <typename K>
+static void allow_lds(K kern, size_t bytes) {
+  if (bytes > 64 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 size_t stiff_mfma_lds_bytes(const TankDev& h, size_t word) {
@@ -364,6 +373,7 @@ static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T
   }
   const StiffArgs<T> a = stiff_args<T>(h, G, opf, inl);
 #define SEM_SL(INL)                                                                                           \
+  SEM_MP_SWITCH(h.P, allow_lds(k_stiff_mfma<PP, T, GS, INL>, lds));                                          \
   if (e0) {                                                                                                  \
     SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL>), dim3(h.nb), dim3(kBlockThreads),  \
                                              (uint32_t)lds, st, e0, e1, 0, a, u, y, side, flags, (uint32_t)ol, \
@@ -426,9 +436,11 @@ static void stiff_b_t(const BatchArgs& a0, const BatchStage& p, int P, VSel u, V
   const int inl = stiff_ops_in_lds<T>(probe);
   const dim3 grid((unsigned)p.items.size());
   if (inl) {
+    SEM_MP_SWITCH(P, allow_lds(k_stiff_mfma_b<PP, T, GS, true>, p.lds));
     SEM_MP_SWITCH(P, hipLaunchKernelGGL((k_stiff_mfma_b<PP, T, GS, true>), grid, dim3(kBlockThreads), p.lds, st, a,
                                         u, y, flags));
   } else {
+    SEM_MP_SWITCH(P, allow_lds(k_stiff_mfma_b<PP, T, GS, false>, p.lds));
     SEM_MP_SWITCH(P, hipLaunchKernelGGL((k_stiff_mfma_b<PP, T, GS, false>), grid, dim3(kBlockThreads), p.lds, st, a,
                                         u, y, flags));
   }

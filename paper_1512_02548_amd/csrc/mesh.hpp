@@ -39,6 +39,7 @@ struct sem_mesh {
   // derived sizes
   int Np = 0, NpP = 0, nl = 0, nc = 0, cb = 1, nb = 1, T = 1, EB = 0, nclass_col = 1;
   int pre_kind = 0, variant = 0;
+  int tiles_req = 0;        // requested 16-element tiles per stiffness workgroup (0 = from the size)
   int sd_nI[2] = {0, 0}, sd_q[2] = {0, 0};
   int sd_M1[2] = {0, 0}, sd_nMT1[2] = {0, 0}, sd_KS1[2] = {0, 0}, sd_nMT3[2] = {0, 0}, sd_KS3[2] = {0, 0};
   int sd_wall[2] = {0, 0};

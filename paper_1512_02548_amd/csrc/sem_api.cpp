@@ -248,12 +248,12 @@ static sem_status build_mesh(sem_mesh* M) {
   // still gives at least 512 workgroups (two per CU); small tanks use one
   // tile per workgroup for parallelism.  Both element kernels must fit their
   // LDS (64 KiB): the reference kernel stages three element buffers, the
-  // matrix-core kernel the operators (FP64, when they fit in 40 KiB), the
-  // element table and one output buffer.
+  // matrix-core kernel the operators (when they fit in 40 KiB), the element
+  // table and one output buffer.
   {
     const int per_col = 2 * nz;
     const double tiles_total = (double)nx * per_col / 16.0;
-    const int tt = std::max(1, std::min(4, (int)(tiles_total / 512.0)));
+    const int tt = M->tiles_req > 0 ? M->tiles_req : std::max(1, std::min(4, (int)(tiles_total / 512.0)));
     auto lds_ok = [&](int cb) {
       const size_t EB = (size_t)cb * per_col, T = (EB + 15) / 16;
       const size_t region = (size_t)cb * nc + nl;
@@ -953,6 +953,8 @@ extern "C" sem_status sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out)
   M->m = desc->restart > 0 ? desc->restart : 30;
   if (desc->variant < 0 || desc->variant > 1) return fail(SEM_E_INVAL, "variant must be 0 or 1");
   M->variant = desc->variant;
+  if (desc->tiles_per_block < 0 || desc->tiles_per_block > 4) return fail(SEM_E_INVAL, "tiles_per_block must be in 0..4");
+  M->tiles_req = desc->tiles_per_block;
   if (M->m > kMaxRestart) return fail(SEM_E_INVAL, "restart must be <= 64");
   int64_t ns = (int64_t)M->nx * M->P + (M->periodic ? 0 : 1);
   M->h.assign(desc->h, desc->h + ns);

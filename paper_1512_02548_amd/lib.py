@@ -37,7 +37,8 @@ class sem_mesh_desc(C.Structure):
                 ("h", C.POINTER(C.c_double)), ("h_x", C.POINTER(C.c_double)),
                 ("sigma_levels", C.POINTER(C.c_double)),
                 ("filter_ic", C.c_int32), ("filter_sigma", C.c_double),
-                ("overint_order", C.c_int32), ("restart", C.c_int32), ("variant", C.c_int32)]
+                ("overint_order", C.c_int32), ("restart", C.c_int32), ("variant", C.c_int32),
+                ("tiles_per_block", C.c_int32)]
 
 
 class sem_mesh_info(C.Structure):
@@ -129,14 +130,14 @@ class Mesh:
     """A tank on the device: mesh_create + query + a torch-allocated workspace + bind."""
 
     def __init__(self, nx, nz, P, length, periodic, h, hx, g=9.81, sigma_levels=None, filter_ic=None,
-                 filter_sigma=1.0, overint=None, restart=30, variant=0, device="cuda", bind=True):
+                 filter_sigma=1.0, overint=None, restart=30, variant=0, tiles_per_block=0, device="cuda", bind=True):
         self.h = np.ascontiguousarray(h, dtype=np.float64)
         self.hx = np.ascontiguousarray(hx, dtype=np.float64)
         self._sl = None if sigma_levels is None else np.ascontiguousarray(sigma_levels, dtype=np.float64)
         dp = lambda a: a.ctypes.data_as(_D) if a is not None else None
         desc = sem_mesh_desc(nx, nz, P, 1 if periodic else 0, float(length), float(g), dp(self.h), dp(self.hx),
                              dp(self._sl), P + 1 if filter_ic is None else filter_ic, float(filter_sigma),
-                             P if overint is None else overint, restart, variant)
+                             P if overint is None else overint, restart, variant, int(tiles_per_block))
         self.handle = C.c_void_p()
         check(sem_mesh_create(C.byref(desc), C.byref(self.handle)), "sem_mesh_create")
         self.info = sem_mesh_info()

@@ -49,7 +49,7 @@ class Request:
 class GpuBackend:
     """Tanks on the GPU through the C ABI; steps are batched across tanks."""
 
-    def __init__(self, nstreams=0, opts=None, device="cuda"):
+    def __init__(self, nstreams=0, opts=None, device="cuda", tiles=None):
         import torch
 
         from . import lib
@@ -61,11 +61,17 @@ class GpuBackend:
             rtol=1e-8, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-3, lookahead=3)
         self._batch = None
         self._batch_key = None
+        self.tiles = tiles        # autotuner table (P, nz) -> stiffness tiles per workgroup, or None
+
+    def _tiles(self, spec):
+        from . import tune
+        return tune.tiles_for(self.tiles, spec)
 
     def footprint(self, spec):
         ns = spec.ns
         m = self.lib.Mesh(spec.nx, spec.nz, spec.P, spec.length, spec.periodic, np.ones(ns), np.zeros(ns),
-                          filter_ic=spec.filter_ic, filter_sigma=spec.filter_sigma, overint=spec.Pf, bind=False)
+                          filter_ic=spec.filter_ic, filter_sigma=spec.filter_sigma, overint=spec.Pf, bind=False,
+                          tiles_per_block=self._tiles(spec))
         return int(m.info.workspace_bytes) + 8 * (2 * ns + int(m.n)), m
 
     def create(self, spec, state_fn, probe=None):
@@ -76,14 +82,14 @@ class GpuBackend:
         if probe is None:
             probe = self.lib.Mesh(spec.nx, spec.nz, spec.P, spec.length, spec.periodic, np.ones(ns),
                                   np.zeros(ns), filter_ic=spec.filter_ic, filter_sigma=spec.filter_sigma,
-                                  overint=spec.Pf, bind=False)
+                                  overint=spec.Pf, bind=False, tiles_per_block=self._tiles(spec))
         xs = probe.surface_x()
         eta, phi, h, hx = state_fn(xs, spec)
         if np.all(h == 1.0) and np.all(hx == 0.0):
             m = probe
             m.bind(self.device)
         else:
-            m = self.lib.mesh_from_spec(spec, h, hx, device=self.device)
+            m = self.lib.mesh_from_spec(spec, h, hx, device=self.device, tiles_per_block=self._tiles(spec))
         dev = torch.device(self.device)
         tank = dict(mesh=m, spec=spec,
                     eta=torch.tensor(eta, dtype=torch.float64, device=dev),
@@ -233,6 +239,8 @@ def main():
                     help="0: lockstep batch (default); >= 1: per-tank steps on that many streams")
     ap.add_argument("--max-nx", type=int, default=None)
     ap.add_argument("--quiet", action="store_true", help="no per-request lines on stderr")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose the stiffness element tiles with the autotuner first (not timed)")
     ap.add_argument("--sequential-fp64", action="store_true",
                     help="baseline: one tank at a time, plain FP64, arrivals ignored")
     a = ap.parse_args()
@@ -244,10 +252,17 @@ def main():
         be = GpuBackend(nstreams=1, opts=lib.default_opts(rtol=1e-8, warm_start=1, lookahead=3))
         srv = Server(be, wl.batch_tank_state, max_slots=1, log=log)
     else:
-        be = GpuBackend(nstreams=a.streams)
+        tiles, trep = None, None
+        if a.tune:
+            from . import tune
+            tiles, trep = tune.tune([r.spec for r in reqs])
+        be = GpuBackend(nstreams=a.streams, tiles=tiles)
         srv = Server(be, wl.batch_tank_state, max_slots=a.slots, log=log)
     rep = srv.run(reqs)
-    rep.update(mode="sequential_fp64" if a.sequential_fp64 else "batched_mixed", rate=a.rate, steps=a.steps)
+    rep.update(mode="sequential_fp64" if a.sequential_fp64 else ("lockstep_mixed" if a.streams == 0 else
+                                                                  "concurrent_mixed"), rate=a.rate, steps=a.steps)
+    if not a.sequential_fp64 and a.tune:
+        rep["autotune"] = trep
     print(json.dumps(rep))
 
 
