@@ -181,7 +181,7 @@ def build_meshes(lib, specs, state_fn, threads=8, tiles=None):
     return out
 
 
-def batch_workload(args):
+def batch_workload(args, modes=("lockstep_fp64", "lockstep_mixed", "concurrent_mixed", "sequential_fp64")):
     """256 periodic tanks of random size and order (seeded): RK4 steps of all
     tanks through the batch call with FP32 inner solves inside FP64
     refinement, against a per-tank sequential FP64 loop on the same GPU."""
@@ -233,9 +233,12 @@ def batch_workload(args):
 
     fp64 = lib.default_opts(rtol=1e-10, warm_start=1, max_iter=20000)
     mixed = lib.default_opts(rtol=1e-10, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-2, max_iter=20000)
-    tl = batched("lockstep_fp64", 0, fp64)
-    batched("lockstep_mixed", 0, mixed)
-    tc = batched("concurrent_mixed", args.streams, mixed)
+    tl = batched("lockstep_fp64", 0, fp64) if "lockstep_fp64" in modes else None
+    if "lockstep_mixed" in modes:
+        batched("lockstep_mixed", 0, mixed)
+    tc = batched("concurrent_mixed", args.streams, mixed) if "concurrent_mixed" in modes else None
+    if "sequential_fp64" not in modes:
+        return res
     fp64 = lib.default_opts(rtol=1e-10, warm_start=1, max_iter=20000)
     restore()
     for t, dt in zip(tanks, dts):
@@ -249,8 +252,10 @@ def batch_workload(args):
     ts = time.perf_counter() - t0
     res["sequential_fp64"] = {"tank_steps_per_s": args.tanks * args.batch_steps / ts,
                               "gdof_s": 4 * nfree * args.batch_steps / ts / 1e9, "seconds": ts}
-    res["speedup_lockstep"] = ts / tl
-    res["speedup_concurrent"] = ts / tc
+    if tl:
+        res["speedup_lockstep"] = ts / tl
+    if tc:
+        res["speedup_concurrent"] = ts / tc
     return res
 
 
@@ -263,11 +268,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-large", action="store_true", help="skip the 2048x8 bar-tank section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-tank lockstep batch section")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", choices=["stream_series", "batch"], default="stream_series",
                     help="batch: the 256-tank batching comparison (one JSON object, not the bench line)")
     ap.add_argument("--tanks", type=int, default=256)
+    ap.add_argument("--batch-modes", default="lockstep_fp64,lockstep_mixed,concurrent_mixed,sequential_fp64",
+                    help="comma-separated subset of the batch workload's modes")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--streams", type=int, default=8)
     args = ap.parse_args()
@@ -277,7 +285,7 @@ def main():
         sys.exit(2)
 
     if args.workload == "batch":
-        print(json.dumps(batch_workload(args)))
+        print(json.dumps(batch_workload(args, modes=tuple(args.batch_modes.split(",")))))
         return
 
     import torch
@@ -372,6 +380,13 @@ def main():
         out["copy_probe_bytes"] = {"read": a.numel() * 8, "write": a.numel() * 8}
     if not args.no_large:
         out["large_tank"] = large_tank(lib, wl, torch)
+    if not args.no_batch:
+        # 256 tanks of mixed size and order in one lockstep batch, one RK4 step
+        # each way, against the per-tank sequential FP64 loop
+        del m
+        torch.cuda.empty_cache()
+        bargs = argparse.Namespace(tanks=256, batch_steps=1, streams=8)
+        out["batch_256"] = batch_workload(bargs, modes=("lockstep_fp64", "lockstep_mixed", "sequential_fp64"))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
     print(json.dumps(out))
