@@ -30,7 +30,7 @@ namespace sem {
 
 namespace {
 constexpr int kWaves = kBlockThreads / 64;
-constexpr int kModesPB = 8;  // Fourier modes per workgroup in the direct modes kernel
+constexpr int kModesPB = kModesPerBlock;
 
 __host__ __device__ inline int sd_part_words(int q) { return max(kWaves * 16 * 16 * 2, 32 * q); }
 

@@ -1107,7 +1107,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     // partial line sums: one per block of the modes kernel (16 modes), or
     // per block of the FFT path's mode solve (256 / q modes)
     sd.nwp = M->fft_n1 ? (M->nx + std::max(1, 256 / std::max(1, sd.q)) - 1) / std::max(1, 256 / std::max(1, sd.q))
-                       : (M->nx + 7) / 8;
+                       : (M->nx + kModesPerBlock - 1) / kModesPerBlock;
     sd.FT = at<double>(M, (p + "FT").c_str());
     sd.FG = at<double>(M, (p + "FG").c_str());
     sd.XL = at<double>(M, (p + "XL").c_str());

@@ -12,6 +12,7 @@ constexpr int kMaxContrib = 8;      // element contributions to one column-local
 constexpr int kBlockThreads = 256;
 constexpr int kMaxRestart = 64;     // GMRES restart length limit
 constexpr int kMaxVec = kMaxRestart + 1;
+constexpr int kModesPerBlock = 8;   // Fourier modes per workgroup of the direct (small-nx) mode solves
 
 // status bits accumulated on the device
 enum : int32_t {
