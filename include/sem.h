@@ -194,7 +194,9 @@ sem_status sem_rk4_step(sem_mesh* mesh, double* eta, double* phi_s, double* phi_
  * and the matrix-core stiffness kernel; FP64 solves.  sem_batch_create
  * allocates the work-item tables (device) and the progress words (pinned
  * host) and uploads them on `stream`.  The meshes must stay bound, unchanged,
- * while the batch exists.  All work is ordered on the caller's `stream`.
+ * while the batch exists.  The batch runs on a stream of its own (default
+ * priority), ordered after the caller's `stream` on entry; the caller's
+ * stream waits for it on return.
  *
  * nstreams >= 1, concurrent: the tanks are spread over `nstreams` worker
  * threads, each driving its own HIP stream (created here, default priority),
@@ -215,6 +217,13 @@ sem_status sem_batch_laplace_solve(sem_batch* batch, const double* const* eta,
                                    double* const* phi, const uint8_t* active_host,
                                    const sem_solve_opts* opts, int32_t* per_tank_status_host,
                                    int32_t* per_tank_iters_host, void* stream);
+/* Lockstep batches: issue each Arnoldi step as one HIP graph launch (1, the
+ * default; captured on first use per step and precision) or as direct kernel
+ * launches (0).  Results are the same either way. */
+sem_status sem_batch_graphs(sem_batch* batch, int32_t enable);
+/* Number of Arnoldi steps captured as graphs so far (0 when capture is not
+ * possible and the steps run as direct launches). */
+sem_status sem_batch_graph_count(const sem_batch* batch, int32_t* captured_host);
 void sem_batch_destroy(sem_batch* batch);
 
 /* Self-test of the matrix-core instructions' lane layout: runs one 16x16x4

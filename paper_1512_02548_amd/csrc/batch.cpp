@@ -44,7 +44,10 @@ struct sem_batch {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
   hipEvent_t start = nullptr;
-  // lockstep mode
+  // lockstep mode: the batch's own stream (graph capture needs one that is
+  // not the null stream), ordered after and before the caller's stream
+  hipStream_t lstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<TankDev> tanks;   // host copies of the descriptors (progress words redirected)
   char* dmem = nullptr;         // device: descriptors, live flags, work items, pointer tables
   TankDev* dtanks = nullptr;
@@ -72,10 +75,21 @@ struct sem_batch {
   std::vector<int> walled;        // tanks whose 1D operators run as single-tank kernels
   std::vector<int> orders;
   int mmax = 0;
+  // Arnoldi steps captured as HIP graphs, per step j and precision (FP64,
+  // FP32 factors, bfloat16 factors): one launch per step instead of ~20
+  bool use_graphs = true;
+  bool graphs_failed = false;
+  std::vector<hipGraphExec_t> steps[3];
   ~sem_batch() {
+    for (auto& v : steps)
+      for (auto g : v)
+        if (g) (void)hipGraphExecDestroy(g);
     for (auto s : streams) (void)hipStreamDestroy(s);
     for (auto e : events) (void)hipEventDestroy(e);
     if (start) (void)hipEventDestroy(start);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (lstream) (void)hipStreamDestroy(lstream);
     if (dmem) (void)hipFree(dmem);
     if (hpin) (void)hipHostFree(hpin);
   }
@@ -243,6 +257,54 @@ static sem_status put_pointers(sem_batch* B, int which, const double* const* p, 
 }
 
 // ------------------------------------------------------------ lockstep GMRES
+// Kernels of Arnoldi step j over all tanks: z_j = M^-1 v_j (for j > 0,
+// v_j = w / ||w|| is formed on the way), w = A z_j, the products with
+// V_0..V_j, the orthogonalisation and Givens update.  Every launch returns at
+// once for a tank whose cycle is done.
+static void issue_step(sem_batch* B, int j, int f32, int gstore, hipStream_t st) {
+  const BatchArgs a = args(B);
+  const BatchStage* stiff = f32 ? B->stiff32 : B->stiff;
+  const BatchSD& sdp = f32 ? B->sdlap32 : B->sdlap;
+  launch_sd_b(a, sdp, 0, j == 0 ? VSel{BV_V, 0} : VSel{BV_W, 0}, VSel{BV_Z, j}, j, 1, f32, st);
+  for (int P : B->orders)
+    launch_stiff_b(a, stiff[P], P, VSel{BV_Z, j}, VSel{BV_W, 0}, F_MASK_SURF | F_GATE | F_NOFIX, gstore, st);
+  launch_dots_b(a, B->dots, B->per_tank, j + 1, VSel{BV_V, 0}, VSel{BV_W, 0}, j, 0, 1, 1, f32, st);
+  launch_orth_b(a, B->dots, B->per_tank, j, f32, st);
+}
+
+// The step as a graph launch: captured from the stream on first use (the
+// launches only read device-resident tables and flags, so one capture per
+// step and precision serves every later cycle and call).  Falls back to
+// direct launches if capture is not possible.
+static sem_status arnoldi_step(sem_batch* B, int j, int f32, int gstore, hipStream_t st) {
+  if (!B->use_graphs || B->graphs_failed) {
+    issue_step(B, j, f32, gstore, st);
+    return SEM_OK;
+  }
+  auto& g = B->steps[f32 ? gstore : 0];
+  if ((int)g.size() < B->mmax) g.resize(B->mmax, nullptr);
+  if (!g[j]) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      issue_step(B, j, f32, gstore, st);
+      ok = hipStreamEndCapture(st, &graph) == hipSuccess && graph;
+    }
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!ok) {
+      (void)hipGetLastError();
+      B->graphs_failed = true;
+      issue_step(B, j, f32, gstore, st);
+      return SEM_OK;
+    }
+    g[j] = exec;
+  }
+  HIPCHK(hipGraphLaunch(g[j], st));
+  return SEM_OK;
+}
+
 // Restarted right-preconditioned GMRES on every tank in `act`, b and the
 // start vector x already in each tank's workspace (FP64 b, xs; or, f32, the
 // FP32 copies b32, x32 with FP32 (gstore 1) or bfloat16 (gstore 2) factors).
@@ -272,12 +334,8 @@ static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rto
     launch_cycle_start_b(a, B->per_tank, B->vec, first ? 1 : 0, f32, st);
     first = false;
     for (int j = 0; j < B->mmax; ++j) {
-      // z_j = M^-1 v_j; for j > 0 v_j = w / ||w|| is formed on the way
-      launch_sd_b(a, sdp, 0, j == 0 ? VSel{BV_V, 0} : VSel{BV_W, 0}, VSel{BV_Z, j}, j, 1, f32, st);
-      for (int P : B->orders)
-        launch_stiff_b(a, stiff[P], P, VSel{BV_Z, j}, VSel{BV_W, 0}, F_MASK_SURF | F_GATE | F_NOFIX, gstore, st);
-      launch_dots_b(a, B->dots, B->per_tank, j + 1, VSel{BV_V, 0}, VSel{BV_W, 0}, j, 0, 1, 1, f32, st);
-      launch_orth_b(a, B->dots, B->per_tank, j, f32, st);
+      s = arnoldi_step(B, j, f32, gstore, st);
+      if (s) return s;
       // queue at most `ahead` steps in front of the slowest running tank
       bool stop = false;
       auto tq = std::chrono::steady_clock::now();
@@ -634,6 +692,19 @@ static sem_status concurrent_rk4(sem_batch* B, double* const* eta, double* const
   return SEM_OK;
 }
 
+// work on the batch's stream follows the caller's earlier work, and the
+// caller's stream waits for the batch's
+static sem_status enter(sem_batch* B, hipStream_t caller) {
+  HIPCHK(hipEventRecord(B->ev_in, caller));
+  HIPCHK(hipStreamWaitEvent(B->lstream, B->ev_in, 0));
+  return SEM_OK;
+}
+static sem_status leave(sem_batch* B, hipStream_t caller) {
+  HIPCHK(hipEventRecord(B->ev_out, B->lstream));
+  HIPCHK(hipStreamWaitEvent(caller, B->ev_out, 0));
+  return SEM_OK;
+}
+
 // ------------------------------------------------------------ public calls
 extern "C" sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, int32_t nstreams, void* stream,
                                        sem_batch** out) {
@@ -651,6 +722,9 @@ extern "C" sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, i
   if (nstreams == 0) {
     sem_status s = setup_lockstep(B.get(), (hipStream_t)stream);
     if (s) return s;
+    HIPCHK(hipStreamCreateWithFlags(&B->lstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
   } else {
     int ns = std::min<int>(nstreams, count);
     for (int i = 0; i < ns; ++i) {
@@ -679,7 +753,13 @@ extern "C" sem_status sem_batch_rk4_step(sem_batch* B, double* const* eta, doubl
       return fail(SEM_E_INVAL, "bad per-tank argument");
   }
   hipStream_t st = (hipStream_t)stream;
-  if (B->nstreams == 0) return lockstep_rk4(B, eta, phi_s, phi_ws, dt, active, opts, per_status, per_iters, st);
+  if (B->nstreams == 0) {
+    sem_status s = enter(B, st);
+    if (s) return s;
+    s = lockstep_rk4(B, eta, phi_s, phi_ws, dt, active, opts, per_status, per_iters, B->lstream);
+    sem_status s2 = leave(B, st);
+    return s ? s : s2;
+  }
   return concurrent_rk4(B, eta, phi_s, phi_ws, dt, active, opts, per_status, per_iters, st);
 }
 
@@ -689,7 +769,27 @@ extern "C" sem_status sem_batch_laplace_solve(sem_batch* B, const double* const*
                                               void* stream) {
   if (!B || !eta || !eta_x || !phi_s || !phi) return fail(SEM_E_INVAL, "null argument");
   if (B->nstreams != 0) return fail(SEM_E_INVAL, "batched Laplace solves need a lockstep batch (nstreams = 0)");
-  return lockstep_solve(B, eta, eta_x, phi_s, phi, active, opts, per_status, per_iters, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  sem_status s = enter(B, st);
+  if (s) return s;
+  s = lockstep_solve(B, eta, eta_x, phi_s, phi, active, opts, per_status, per_iters, B->lstream);
+  sem_status s2 = leave(B, st);
+  return s ? s : s2;
+}
+
+extern "C" sem_status sem_batch_graphs(sem_batch* B, int32_t enable) {
+  if (!B) return fail(SEM_E_INVAL, "null batch");
+  B->use_graphs = enable != 0;
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_batch_graph_count(const sem_batch* B, int32_t* captured) {
+  if (!B || !captured) return fail(SEM_E_INVAL, "null argument");
+  int32_t c = 0;
+  for (const auto& v : B->steps)
+    for (auto g : v) c += g != nullptr;
+  *captured = c;
+  return SEM_OK;
 }
 
 extern "C" void sem_batch_destroy(sem_batch* B) { delete B; }

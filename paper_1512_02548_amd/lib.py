@@ -87,6 +87,8 @@ _SIGS = {
                                      C.POINTER(C.c_uint8), C.POINTER(sem_solve_opts),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
     "sem_batch_destroy": (None, [_P]),
+    "sem_batch_graphs": (C.c_int, [_P, C.c_int32]),
+    "sem_batch_graph_count": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "sem_selftest_mfma": (C.c_int, [_P, C.POINTER(C.c_double), _D, _P]),
     "sem_kernel_timing": (C.c_int, [_P, C.c_int32]),
     "sem_kernel_timing_read": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -244,6 +246,15 @@ class Batch:
         self.handle = C.c_void_p()
         check(sem_batch_create(arr, len(self.meshes), self.nstreams, _stream(stream), C.byref(self.handle)),
               "sem_batch_create")
+
+    def graphs(self, enable):
+        """Lockstep Arnoldi steps as HIP graph launches (default) or direct launches."""
+        check(sem_batch_graphs(self.handle, 1 if enable else 0), "sem_batch_graphs")
+
+    def graph_count(self):
+        c = C.c_int32()
+        check(sem_batch_graph_count(self.handle, C.byref(c)), "sem_batch_graph_count")
+        return c.value
 
     def _ptrs(self, tensors):
         return (C.c_void_p * len(self.meshes))(*[t.data_ptr() for t in tensors])

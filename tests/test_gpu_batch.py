@@ -159,3 +159,30 @@ def test_lockstep_failed_tank_is_isolated():
     assert np.array_equal(tanks[0]["eta"].cpu().numpy(), ref[0])
     assert np.array_equal(tanks[2]["eta"].cpu().numpy(), ref[2])
     del bad_eta
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lockstep_graphs_match_direct_launches(prec):
+    """Arnoldi steps replayed from captured HIP graphs give the same bits as
+    direct launches, call after call (eager work and synchronisations in
+    between every replay)."""
+    import torch
+    from paper_1512_02548_amd import lib
+    opts = lib.default_opts(rtol=1e-10, warm_start=1, prec=prec, inner_rtol=1e-2)
+    specs = mixed_specs()[:4]
+    results = []
+    for graphs in (False, True):
+        tanks = [make_tank(s) for s in specs]
+        b = lib.Batch([t["mesh"] for t in tanks], 0)
+        b.graphs(graphs)
+        for _ in range(3):
+            code, status, _ = b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks],
+                                         [t["ws"] for t in tanks], [s.dt for s in specs], opts=opts)
+            assert code == 0, status
+            torch.cuda.synchronize()
+            snap = [t["eta"].clone() for t in tanks]   # eager work between the replays
+            del snap
+        assert (b.graph_count() > 0) == graphs
+        results.append([(t["eta"].cpu().numpy(), t["phi"].cpu().numpy()) for t in tanks])
+    for (e0, p0), (e1, p1) in zip(*results):
+        assert np.array_equal(e0, e1) and np.array_equal(p0, p1)
