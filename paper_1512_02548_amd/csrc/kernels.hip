@@ -1139,7 +1139,8 @@ k_fs_rhs(const TankDev* __restrict__ td, const double* __restrict__ eta, const d
 
 // ------------------------------------------------------------ 1D periodic direct solves
 // y = A x for a block-circulant A given by its first block-row [P][ns]:
-// y[eP + a] = sum_j row[a][j] x[(eP + j) mod ns].  One wavefront per output
+// y[eP + a] = sum_j row[a][j] x[(eP + j) mod ns], j within the row's decay
+// band (circ_band elements each side, below rounding beyond).  One wavefront per output
 // node: lanes stride over j, then a butterfly sum (fixed order).  x1/y1, when
 // given, is a second vector with the same operator.
 __device__ __forceinline__ void circ_body(const TankDev& d, int which, const double* __restrict__ x0,
@@ -1152,8 +1153,14 @@ __device__ __forceinline__ void circ_body(const TankDev& d, int which, const dou
   const int e = s / P, a = s - e * P;
   const double* row = (which == 0 ? d.Rrow : d.Brow) + (size_t)a * ns;
   const int base = e * P;
+  // the row's band: elements nx - band .. nx - 1, 0 .. band (or the whole row)
+  const bool all = 2 * d.circ_band + 1 >= d.nx;
+  const int span = all ? ns : (2 * d.circ_band + 1) * P;
+  const int j0 = all ? 0 : (d.nx - d.circ_band) * P;
   double acc0 = 0, acc1 = 0;
-  for (int j = lane; j < ns; j += 64) {
+  for (int t = lane; t < span; t += 64) {
+    int j = j0 + t;
+    if (j >= ns) j -= ns;
     int src = base + j;
     if (src >= ns) src -= ns;
     double r = row[j];

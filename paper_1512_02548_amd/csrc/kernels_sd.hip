@@ -222,10 +222,11 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
   double* gh = sh + sd_part_words(q);     // [16][q][2]
   const int nNT = (q + 15) / 16, KS = (nx + 3) / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const int k0 = bx * kModesPB;
+  constexpr int kPairs = kModesPB / 2;
   const double rs = sd_in_scale(nscale);
-  const int kmode = k0 + col;              // A row of this lane (rows past the block's modes are discarded)
-  const bool kval = kmode < nx;
+  // A row of this lane: the mode of slot `col` (rows past the block's slots are discarded)
+  const int kmode = col < kModesPB ? paired_mode(bx, col, kPairs, nx) : -1;
+  const bool kval = kmode >= 0;
   const int kr = kval ? kmode : 0;
   // twiddle index (kmode * c) mod nx for c = 4 s + grp, s = wv, wv + 4, ...
   const int step = (int)(((int64_t)16 * kr) % nx);
@@ -289,8 +290,11 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
   }
   // x^_k = S^_k^{-1} g^_k (column-major: thread per (mode, row))
   for (int t = threadIdx.x; t < kModesPB * q; t += blockDim.x) {
-    const int kk = t / q, i = t - kk * q, k = k0 + kk;
-    if (k >= nx) continue;
+    const int kk = t / q, i = t - kk * q, k = paired_mode(bx, kk, kPairs, nx);
+    if (k < 0) {
+      if (sd.wall) part[t * 2] = part[t * 2 + 1] = 0.0;
+      continue;
+    }
     const bool cj = 2 * k > nx;   // stored as the conjugate of mode nx - k
     const T* S = SdMat<T>::Shat(sd) + (size_t)(cj ? nx - k : k) * q * q * 2;
     const double sgn = cj ? -1.0 : 1.0;
@@ -317,8 +321,8 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
     const int ln = t / q, j = t - ln * q;
     double acc = 0;
     for (int kk = 0; kk < kModesPB; ++kk) {
-      const int k = k0 + kk;
-      if (k >= nx) break;
+      const int k = paired_mode(bx, kk, kPairs, nx);
+      if (k < 0) continue;
       const double hr = part[(kk * q + j) * 2], hi = part[(kk * q + j) * 2 + 1];
       if (ln == 0) {
         const int mm = (int)(((int64_t)k * a0) % nx);
@@ -728,40 +732,42 @@ k_sdf_b(const TankDev* __restrict__ td, int which, int gate) {
 template <typename T>
 __device__ __forceinline__ void sdf_solve_body(const TankDev& d, int which, int bx, int by) {
   const SDData& sd = d.sd[which];
-  extern __shared__ double sh[];
+  extern __shared__ double sh[];   // [slots][q][2] x^ of this block's modes (walls)
   const int q = sd.q, nx = d.nx;
-  const int ml = max(1, kBlockThreads / q);
-  const int t = threadIdx.x;
-  const int kk = t / q, i = t - kk * q;
-  const int k = bx * ml + kk;
-  double xr = 0, xi = 0;
-  const bool live = kk < ml && k < nx;
-  if (live) {
-    const bool cj = 2 * k > nx;   // stored as the conjugate of mode nx - k
-    const T* S = SdMat<T>::Shat(sd) + (size_t)(cj ? nx - k : k) * q * q * 2;
-    const double sgn = cj ? -1.0 : 1.0;
-    const double* g = sd.FG + (size_t)k * q * 2;
+  const int ml = fft_modes_per_block(q), ns = fft_slots(ml);
+  for (int t = threadIdx.x; t < ns * q; t += blockDim.x) {
+    const int kk = t / q, i = t - kk * q;
+    const int k = fft_mode(bx, kk, ml, nx);
+    double xr = 0, xi = 0;
+    if (k >= 0) {
+      const bool cj = 2 * k > nx;   // stored as the conjugate of mode nx - k
+      const T* S = SdMat<T>::Shat(sd) + (size_t)(cj ? nx - k : k) * q * q * 2;
+      const double sgn = cj ? -1.0 : 1.0;
+      const double* g = sd.FG + (size_t)k * q * 2;
 #pragma unroll 8
-    for (int j = 0; j < q; ++j) {
-      const double sr = (double)S[((size_t)j * q + i) * 2], si = sgn * (double)S[((size_t)j * q + i) * 2 + 1];
-      const double gr = g[2 * j], gi = g[2 * j + 1];
-      xr += sr * gr - si * gi;
-      xi += sr * gi + si * gr;
+      for (int j = 0; j < q; ++j) {
+        const double sr = (double)S[((size_t)j * q + i) * 2], si = sgn * (double)S[((size_t)j * q + i) * 2 + 1];
+        const double gr = g[2 * j], gi = g[2 * j + 1];
+        xr += sr * gr - si * gi;
+        xi += sr * gi + si * gr;
+      }
+      sd.XH[((size_t)k * q + i) * 2] = xr;
+      sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
     }
-    sd.XH[((size_t)k * q + i) * 2] = xr;
-    sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
+    if (sd.wall) {
+      sh[2 * t] = xr;
+      sh[2 * t + 1] = xi;
+    }
   }
   if (!sd.wall) return;
-  sh[2 * t] = live ? xr : 0.0;
-  sh[2 * t + 1] = live ? xi : 0.0;
   __syncthreads();
   const int a0 = nx - 1;
   for (int u = threadIdx.x; u < 2 * q; u += blockDim.x) {
     const int ln = u / q, j = u - ln * q;
     double acc = 0;
-    for (int m2 = 0; m2 < ml; ++m2) {
-      const int km = bx * ml + m2;
-      if (km >= nx) break;
+    for (int m2 = 0; m2 < ns; ++m2) {
+      const int km = fft_mode(bx, m2, ml, nx);
+      if (km < 0) continue;
       const double hr = sh[2 * (m2 * q + j)], hi = sh[2 * (m2 * q + j) + 1];
       if (ln == 0) {
         const int mm = sd_mod((int64_t)km * a0, nx);
@@ -900,7 +906,7 @@ SdLds sd_lds(const TankDev& h, const SDData& sd, size_t word) {
   l.modes = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
   l.back = sizeof(double) * ((16 * (size_t)s3.ntw + 1) * (sd.q + 1) + (s3.split ? kWaves * s3.ntw * 256 : 0));
   l.fa = sd.fft_n1 ? sizeof(double) * 4 * (size_t)((sd.fft_n1 + 3) / 4) * sd.q : 0;
-  l.fsolve = sizeof(double) * 2 * kBlockThreads;
+  l.fsolve = sizeof(double) * 2 * (size_t)fft_slots(fft_modes_per_block(sd.q)) * sd.q;
   l.wall = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
   return l;
 }
@@ -992,12 +998,11 @@ void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int
     if (sd.fft_n1) {
       add_grid(out->fa, t, sd.fft_n2, 1, l.fa);
       add_grid(out->fb, t, sd.fft_n1, 1, 0);
-      const int ml = std::max(1, kBlockThreads / sd.q);
-      add_grid(out->fsolve, t, (h.nx + ml - 1) / ml, 1, l.fsolve);
+      add_grid(out->fsolve, t, fft_mode_blocks(h.nx, fft_modes_per_block(sd.q)), 1, l.fsolve);
       add_grid(out->fc, t, sd.fft_n1, 1, 0);
       add_grid(out->fd, t, sd.fft_n2, 1, 0);
     } else {
-      add_grid(out->modes, t, (h.nx + kModesPB - 1) / kModesPB, 1, l.modes);
+      add_grid(out->modes, t, paired_blocks(h.nx, kModesPB / 2), 1, l.modes);
       add_grid(out->idft, t, ct, (sd.q + 15) / 16, 0);
     }
     if (sd.wall) {
@@ -1054,11 +1059,11 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
     const size_t la = sizeof(double) * 4 * (size_t)((n1 + 3) / 4) * sd.q;
     hipLaunchKernelGGL(k_sdf_a<T>, dim3(n2), dim3(kBlockThreads), la, st, d, which, u, gate, nscale, vout);
     hipLaunchKernelGGL(k_sdf_b<T>, dim3(n1), dim3(kBlockThreads), 0, st, d, which, gate);
-    const int ml = std::max(1, kBlockThreads / sd.q);
-    hipLaunchKernelGGL(k_sdf_solve<T>, dim3((h.nx + ml - 1) / ml), dim3(kBlockThreads),
-                       sizeof(double) * 2 * kBlockThreads, st, d, which, gate);
+    const int ml = fft_modes_per_block(sd.q);
+    hipLaunchKernelGGL(k_sdf_solve<T>, dim3(fft_mode_blocks(h.nx, ml)), dim3(kBlockThreads), lds.fsolve, st, d,
+                       which, gate);
   } else {
-    hipLaunchKernelGGL(k_sd_modes<T>, dim3((h.nx + kModesPB - 1) / kModesPB), dim3(kBlockThreads), l2, st, d, which,
+    hipLaunchKernelGGL(k_sd_modes<T>, dim3(paired_blocks(h.nx, kModesPB / 2)), dim3(kBlockThreads), l2, st, d, which,
                        u, gate, nscale, vout);
   }
   if (sd.wall) {

@@ -45,6 +45,7 @@ struct sem_mesh {
   int sd_wall[2] = {0, 0};
   int fft_n1 = 0, fft_n2 = 0;   // four-step transforms along x (0: direct)
   int circ1d = 0;
+  int circ_band = 0;        // elements on each side kept by the periodic 1D applies
   int64_t n = 0, ns = 0, E = 0;
   // host tables
   std::vector<int32_t> elem_loc, acc_cnt, acc_ent, surf_loc, is_surf_loc;

@@ -784,6 +784,22 @@ static sem_status build_mesh(sem_mesh* M) {
           Brow[(size_t)a * ns1 + dd * P + b] = sb.real() / nx;
           Rrow[(size_t)a * ns1 + dd * P + b] = sr.real() / nx;
         }
+    // The rows decay geometrically away from the diagonal (about a decade per
+    // element): the applies skip the elements farther than `circ_band`, where
+    // every entry is below 1e-15 of its row's largest and the first skipped
+    // ones, four elements further out, below ~1e-19 (under the rounding of
+    // the sums themselves).  Short tanks keep every element.
+    int reach = 0;
+    for (const std::vector<double>* R : {&Brow, &Rrow})
+      for (int a = 0; a < P; ++a) {
+        double mx = 0;
+        for (int j = 0; j < ns1; ++j) mx = std::max(mx, std::fabs((*R)[(size_t)a * ns1 + j]));
+        for (int j = 0; j < ns1; ++j) {
+          const int dd = j / P, dist = std::min(dd, nx - dd);
+          if (std::fabs((*R)[(size_t)a * ns1 + j]) > 1e-15 * mx) reach = std::max(reach, dist);
+        }
+      }
+    M->circ_band = std::min(reach + 4, nx);   // elements on each side; 2 band + 1 >= nx: all
   }
 
   // ---- workspace layout: constants
@@ -1104,10 +1120,9 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     sd.WP = at<double>(M, (p + "WP").c_str());
     sd.fft_n1 = M->fft_n1;
     sd.fft_n2 = M->fft_n2;
-    // partial line sums: one per block of the modes kernel (16 modes), or
-    // per block of the FFT path's mode solve (256 / q modes)
-    sd.nwp = M->fft_n1 ? (M->nx + std::max(1, 256 / std::max(1, sd.q)) - 1) / std::max(1, 256 / std::max(1, sd.q))
-                       : (M->nx + kModesPerBlock - 1) / kModesPerBlock;
+    // partial line sums: one per workgroup of the mode solves (pairs of
+    // conjugate modes per workgroup)
+    sd.nwp = M->fft_n1 ? fft_mode_blocks(M->nx, fft_modes_per_block(sd.q)) : paired_blocks(M->nx, kModesPerBlock / 2);
     sd.FT = at<double>(M, (p + "FT").c_str());
     sd.FG = at<double>(M, (p + "FG").c_str());
     sd.XL = at<double>(M, (p + "XL").c_str());
@@ -1119,6 +1134,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.Filt = at<double>(M, "Filt");
   h.pre1d = at<double>(M, "pre1d");
   h.circ1d = M->circ1d;
+  h.circ_band = M->circ_band;
   h.Brow = at<double>(M, "Brow");
   h.Rrow = at<double>(M, "Rrow");
   h.h = at<double>(M, "h");

@@ -14,6 +14,28 @@ constexpr int kMaxRestart = 64;     // GMRES restart length limit
 constexpr int kMaxVec = kMaxRestart + 1;
 constexpr int kModesPerBlock = 8;   // Fourier modes per workgroup of the direct (small-nx) mode solves
 
+// Mode solves take mode k together with its conjugate partner nx - k (both
+// use the one stored inverse symbol): a workgroup of `pairs` pairs has
+// k = pairs bx + h in slot h and nx - k in slot pairs + h (-1: empty slot;
+// modes 0 and nx/2 have no partner).
+__host__ __device__ inline int paired_mode(int bx, int slot, int pairs, int nx) {
+  const int h = slot < pairs ? slot : slot - pairs;
+  const int k = pairs * bx + h;
+  if (2 * k > nx) return -1;
+  if (slot < pairs) return k;
+  return (k == 0 || 2 * k == nx) ? -1 : nx - k;
+}
+__host__ __device__ inline int paired_blocks(int nx, int pairs) { return (nx / 2) / pairs + 1; }
+// the four-step path's mode solve: up to ml = 256 / q modes per workgroup
+// (paired when ml >= 2, one mode per workgroup otherwise)
+__host__ __device__ inline int fft_modes_per_block(int q) { return q >= 256 ? 1 : 256 / q; }
+__host__ __device__ inline int fft_slots(int ml) { return ml < 2 ? 1 : 2 * (ml / 2); }
+__host__ __device__ inline int fft_mode(int bx, int slot, int ml, int nx) {
+  if (ml < 2) return bx < nx ? bx : -1;
+  return paired_mode(bx, slot, ml / 2, nx);
+}
+__host__ __device__ inline int fft_mode_blocks(int nx, int ml) { return ml < 2 ? nx : paired_blocks(nx, ml / 2); }
+
 // status bits accumulated on the device
 enum : int32_t {
   ST_DOMAIN = 1,
@@ -125,7 +147,8 @@ struct TankDev {
   const double* Mfine;            // (Pf+1) x (Pf+1)
   const double* Filt;             // (P+1) x (P+1)
   const double* pre1d;            // [3][(P+1)^2] W C^{-1} W for the 1D mass (classes: first, interior, last)
-  int32_t circ1d, pad2;           // periodic: M'^{-1} and M'^{-1} S_x applied as block-circulant rows
+  int32_t circ1d;                 // periodic: M'^{-1} and M'^{-1} S_x applied as block-circulant rows
+  int32_t circ_band;              // ... over the elements within this distance of the diagonal (all if 2 band + 1 >= nx)
   const double* Brow;             // [P][ns] first block-row of M'^{-1}
   const double* Rrow;             // [P][ns] first block-row of M'^{-1} S_x
   const double* h;                // [ns]
