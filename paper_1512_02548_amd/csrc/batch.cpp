@@ -169,8 +169,8 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
     for (BatchStage* st2 : {&B->stage.coef[P], &B->stage.sz[P], &B->stage.final_[P]}) stages.push_back(st2);
   for (BatchStage* st2 : {&B->stage.surf, &B->stage.circ, &B->stage.fsl, &B->stage.fsg}) stages.push_back(st2);
   for (BatchSD* p : {&B->sdlap, &B->sdlap32, &B->sdmass})
-    for (BatchStage* s : {&p->cond, &p->modes, &p->fa, &p->fb, &p->fsolve, &p->wall, &p->wmodes, &p->fc, &p->fd,
-                          &p->idft, &p->back})
+    for (BatchStage* s : {&p->cond, &p->modes, &p->fa, &p->fb, &p->fsolve, &p->wlines, &p->wall, &p->wmodes,
+                          &p->fc, &p->fd, &p->idft, &p->back})
       stages.push_back(s);
   // one device buffer: descriptors | live flags | scales | pointer tables | item tables
   size_t off = (size_t)count * sizeof(TankDev);

@@ -291,10 +291,7 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
   // x^_k = S^_k^{-1} g^_k (column-major: thread per (mode, row))
   for (int t = threadIdx.x; t < kModesPB * q; t += blockDim.x) {
     const int kk = t / q, i = t - kk * q, k = paired_mode(bx, kk, kPairs, nx);
-    if (k < 0) {
-      if (sd.wall) part[t * 2] = part[t * 2 + 1] = 0.0;
-      continue;
-    }
+    if (k < 0) continue;
     const bool cj = 2 * k > nx;   // stored as the conjugate of mode nx - k
     const T* S = SdMat<T>::Shat(sd) + (size_t)(cj ? nx - k : k) * q * q * 2;
     const double sgn = cj ? -1.0 : 1.0;
@@ -308,30 +305,6 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
     }
     sd.XH[((size_t)k * q + i) * 2] = xr;
     sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
-    if (sd.wall) {
-      part[t * 2] = xr;   // the reduction area is free again: x^ of this block's modes
-      part[t * 2 + 1] = xi;
-    }
-  }
-  if (!sd.wall) return;
-  // walls: this block's share of lines nx-1 and 0 of the inverse transform
-  __syncthreads();
-  const int a0 = nx - 1;
-  for (int t = threadIdx.x; t < 2 * q; t += blockDim.x) {
-    const int ln = t / q, j = t - ln * q;
-    double acc = 0;
-    for (int kk = 0; kk < kModesPB; ++kk) {
-      const int k = paired_mode(bx, kk, kPairs, nx);
-      if (k < 0) continue;
-      const double hr = part[(kk * q + j) * 2], hi = part[(kk * q + j) * 2 + 1];
-      if (ln == 0) {
-        const int mm = (int)(((int64_t)k * a0) % nx);
-        acc += hr * d.twid[2 * mm] + hi * d.twid[2 * mm + 1];
-      } else {
-        acc += hr;
-      }
-    }
-    sd.WP[((size_t)bx * 2 + ln) * q + j] = acc;
   }
 }
 
@@ -514,40 +487,55 @@ k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate
   sd_back_body<T>(d, which, z, vout, (int)blockIdx.x, (int)blockIdx.y);
 }
 
-// Wall correction (one workgroup): lines nx-1 and 0 of the first solve
-// (sums of the per-block partials), then v = W [r_wall; x_{nx-1}; x_0; y_I]
-// with one wavefront per component of v.
-template <typename T>
-__device__ __forceinline__ void sd_wall_body(const TankDev& d, int which, const T* __restrict__ r, const double* __restrict__ nscale, int bx, int by) {
+// Sum of a workgroup's values in a fixed order (wave butterflies, then the
+// four wave totals in order); the result is valid in every thread.
+__device__ inline double block_total(double v) {
+  __shared__ double wt[kWaves];
+  v = wsum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) wt[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((wt[0] + wt[1]) + wt[2]) + wt[3];
+}
+
+// Wall correction, first part (a workgroup per value): lines nx-1 and 0 of
+// the periodic solve straight from the modal solution,
+// x_c = Re sum_k e^{2 pi i k c / nx} x^_k / nx, into WP = [x_{nx-1}; x_0].
+__device__ __forceinline__ void sd_wall_lines_body(const TankDev& d, int which, int bx, int by) {
   const SDData& sd = d.sd[which];
-  extern __shared__ double sh[];
+  const int q = sd.q, nx = d.nx;
+  const int ln = bx / q, j = bx - ln * q;
+  const int c = ln == 0 ? nx - 1 : 0;
+  double acc = 0;
+  for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+    const int mm = (int)(((int64_t)k * c) % nx);
+    const double hr = sd.XH[((size_t)k * q + j) * 2], hi = sd.XH[((size_t)k * q + j) * 2 + 1];
+    acc += hr * d.twid[2 * mm] + hi * d.twid[2 * mm + 1];
+  }
+  acc = block_total(acc);
+  if (threadIdx.x == 0) sd.WP[bx] = acc / nx;
+}
+
+// Wall correction, second part (a workgroup per component a of v):
+// v_a = W_a . [r_wall; x_{nx-1}; x_0; y_I(nx-1)]
+template <typename T>
+__device__ __forceinline__ void sd_wall_body(const TankDev& d, int which, const T* __restrict__ r,
+                                             const double* __restrict__ nscale, int bx, int by) {
+  const SDData& sd = d.sd[which];
   const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc;
   const int np = 3 * q + nI;
-  const int nb2 = sd.nwp;
-  double* in = sh;   // [np]
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double inx = 1.0 / nx;
-  // lines nx-1 and 0: one wavefront per value, lanes over the partials
-  for (int t = wv; t < 2 * q; t += kWaves) {
-    const int ln = t / q, j = t - ln * q;
-    double acc = 0;
-#pragma unroll 4
-    for (int b = lane; b < nb2; b += 64) acc += sd.WP[((size_t)b * 2 + ln) * q + j];
-    acc = wsum(acc);
-    if (lane == 0) in[q + ln * q + j] = acc * inx;
-  }
   const double rs = sd_in_scale(nscale);
-  for (int a = threadIdx.x; a < q; a += blockDim.x) in[a] = (double)r[(int64_t)nx * nc + a] * rs;
-  for (int i = threadIdx.x; i < nI; i += blockDim.x) in[3 * q + i] = sd.yI[(size_t)(nx - 1) * nI + i];
-  __syncthreads();
-  for (int a = wv; a < q; a += kWaves) {
-    const double* row = sd.Wv + (size_t)a * np;
-    double acc = 0;
-#pragma unroll 4
-    for (int p = lane; p < np; p += 64) acc += row[p] * in[p];
-    acc = wsum(acc);
-    if (lane == 0) sd.vbuf[a] = acc;
+  const double* row = sd.Wv + (size_t)bx * np;
+  double acc = 0;
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    double in;
+    if (p < q) in = (double)r[(int64_t)nx * nc + p] * rs;
+    else if (p < 3 * q) in = sd.WP[p - q];
+    else in = sd.yI[(size_t)(nx - 1) * nI + p - 3 * q];
+    acc += row[p] * in;
   }
+  acc = block_total(acc);
+  if (threadIdx.x == 0) sd.vbuf[bx] = acc;
 }
 
 template <typename T>
@@ -557,6 +545,12 @@ k_sd_wall(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
   sd_wall_body<T>(d, which, r, nscale, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+__global__ void __launch_bounds__(kBlockThreads) k_sd_wall_lines(const TankDev* __restrict__ td, int which, int gate) {
+  const TankDev& d = *td;
+  if (gate && d.ks->done) return;
+  sd_wall_lines_body(d, which, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // x^_k -= H_k v for every mode (thread per mode and line unknown); the
@@ -569,13 +563,15 @@ __device__ __forceinline__ void sd_wall_modes_body(const TankDev& d, int which, 
   if (t < nm) {
     const int64_t k = t / q;
     const int i = (int)(t - k * q);
-    const double* Hk = sd.Hm + (size_t)k * q * q * 2;
+    const bool cj = 2 * k > d.nx;   // stored as the conjugate of mode nx - k
+    const double* Hk = sd.Hm + (size_t)(cj ? d.nx - k : k) * q * q * 2;
+    const double sgn = cj ? -1.0 : 1.0;
     double xr = 0, xi = 0;
 #pragma unroll 4
     for (int a = 0; a < q; ++a) {
       const double va = sd.vbuf[a];
       xr += Hk[((size_t)a * q + i) * 2] * va;
-      xi += Hk[((size_t)a * q + i) * 2 + 1] * va;
+      xi += sgn * Hk[((size_t)a * q + i) * 2 + 1] * va;
     }
     sd.XH[((size_t)k * q + i) * 2] -= xr;
     sd.XH[((size_t)k * q + i) * 2 + 1] -= xi;
@@ -732,7 +728,6 @@ k_sdf_b(const TankDev* __restrict__ td, int which, int gate) {
 template <typename T>
 __device__ __forceinline__ void sdf_solve_body(const TankDev& d, int which, int bx, int by) {
   const SDData& sd = d.sd[which];
-  extern __shared__ double sh[];   // [slots][q][2] x^ of this block's modes (walls)
   const int q = sd.q, nx = d.nx;
   const int ml = fft_modes_per_block(q), ns = fft_slots(ml);
   for (int t = threadIdx.x; t < ns * q; t += blockDim.x) {
@@ -754,29 +749,6 @@ __device__ __forceinline__ void sdf_solve_body(const TankDev& d, int which, int 
       sd.XH[((size_t)k * q + i) * 2] = xr;
       sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
     }
-    if (sd.wall) {
-      sh[2 * t] = xr;
-      sh[2 * t + 1] = xi;
-    }
-  }
-  if (!sd.wall) return;
-  __syncthreads();
-  const int a0 = nx - 1;
-  for (int u = threadIdx.x; u < 2 * q; u += blockDim.x) {
-    const int ln = u / q, j = u - ln * q;
-    double acc = 0;
-    for (int m2 = 0; m2 < ns; ++m2) {
-      const int km = fft_mode(bx, m2, ml, nx);
-      if (km < 0) continue;
-      const double hr = sh[2 * (m2 * q + j)], hi = sh[2 * (m2 * q + j) + 1];
-      if (ln == 0) {
-        const int mm = sd_mod((int64_t)km * a0, nx);
-        acc += hr * d.twid[2 * mm] + hi * d.twid[2 * mm + 1];
-      } else {
-        acc += hr;
-      }
-    }
-    sd.WP[((size_t)bx * 2 + ln) * q + j] = acc;
   }
 }
 
@@ -906,8 +878,8 @@ SdLds sd_lds(const TankDev& h, const SDData& sd, size_t word) {
   l.modes = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
   l.back = sizeof(double) * ((16 * (size_t)s3.ntw + 1) * (sd.q + 1) + (s3.split ? kWaves * s3.ntw * 256 : 0));
   l.fa = sd.fft_n1 ? sizeof(double) * 4 * (size_t)((sd.fft_n1 + 3) / 4) * sd.q : 0;
-  l.fsolve = sizeof(double) * 2 * (size_t)fft_slots(fft_modes_per_block(sd.q)) * sd.q;
-  l.wall = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
+  l.fsolve = 0;
+  l.wall = 0;
   return l;
 }
 struct SdGrid {
@@ -972,6 +944,11 @@ SEM_SD_PLAIN_B(k_sdf_solve_b, sdf_solve_body)
 SEM_SD_PLAIN_B(k_sdf_c_b, sdf_c_body)
 SEM_SD_PLAIN_B(k_sdf_d_b, sdf_d_body)
 #undef SEM_SD_PLAIN_B
+__global__ void __launch_bounds__(kBlockThreads) k_sd_wall_lines_b(BatchArgs ba, int which, int gate) {
+  SEM_BATCH_TANK(ba)
+  if (gate && d.ks->done) return;
+  sd_wall_lines_body(d, which, it_.bx, it_.by);
+}
 __global__ void __launch_bounds__(kBlockThreads) k_sd_wall_modes_b(BatchArgs ba, int which, int gate) {
   SEM_BATCH_TANK(ba)
   if (gate && d.ks->done) return;
@@ -1006,7 +983,8 @@ void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int
       add_grid(out->idft, t, ct, (sd.q + 15) / 16, 0);
     }
     if (sd.wall) {
-      add_grid(out->wall, t, 1, 1, l.wall);
+      add_grid(out->wlines, t, 2 * sd.q, 1, 0);
+      add_grid(out->wall, t, sd.q, 1, l.wall);
       const int64_t nm = (int64_t)h.nx * sd.q + sd.nI;
       add_grid(out->wmodes, t, (int)((nm + kBlockThreads - 1) / kBlockThreads), 1, 0);
     }
@@ -1030,6 +1008,7 @@ static void sd_b_t(const BatchArgs& a0, const BatchSD& p, int which, VSel rin, V
   go(p.fb, k_sdf_b_b<T>, which, gate);
   go(p.fsolve, k_sdf_solve_b<T>, which, gate);
   go(p.modes, k_sd_modes_b<T>, which, rin, jn, gate);
+  go(p.wlines, k_sd_wall_lines_b, which, gate);
   go(p.wall, k_sd_wall_b<T>, which, rin, jn, gate);
   go(p.wmodes, k_sd_wall_modes_b, which, gate);
   go(p.fc, k_sdf_c_b<T>, which, gate);
@@ -1067,8 +1046,8 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
                        u, gate, nscale, vout);
   }
   if (sd.wall) {
-    const size_t lw = sizeof(double) * (3 * (size_t)sd.q + sd.nI);
-    hipLaunchKernelGGL(k_sd_wall<T>, dim3(1), dim3(kBlockThreads), lw, st, d, which, u, gate, nscale);
+    hipLaunchKernelGGL(k_sd_wall_lines, dim3(2 * sd.q), dim3(kBlockThreads), 0, st, d, which, gate);
+    hipLaunchKernelGGL(k_sd_wall<T>, dim3(sd.q), dim3(kBlockThreads), 0, st, d, which, u, gate, nscale);
     const int64_t nm = (int64_t)h.nx * sd.q + sd.nI;
     hipLaunchKernelGGL(k_sd_wall_modes, dim3((unsigned)((nm + kBlockThreads - 1) / kBlockThreads)),
                        dim3(kBlockThreads), 0, st, d, which, gate);

@@ -99,7 +99,7 @@ struct BatchStage {
 };
 // the exact-inverse chain of one operator (which) and precision
 struct BatchSD {
-  BatchStage cond, modes, fa, fb, fsolve, wall, wmodes, fc, fd, idft, back;
+  BatchStage cond, modes, fa, fb, fsolve, wlines, wall, wmodes, fc, fd, idft, back;
 };
 void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int which, int f32, BatchSD* out);
 void plan_stiff(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int P, int f32, BatchStage* out);

@@ -637,8 +637,9 @@ static sem_status build_mesh(sem_mesh* M) {
         for (int i = 0; i < nI; ++i)
           for (int a = 0; a < q; ++a) H.Qm[(size_t)a * nI + i] = Q[(size_t)i * q + a];
         // H_k = S^_k^-1 (e^{i th_k} Phi_L + Phi_R), column-major per mode
-        H.Hm.assign((size_t)nx * q * q * 2, 0.0);
-        parallel_for(nx, [&](int k) {
+        // modes k > nx/2 are the conjugates of modes nx - k: only 0..nx/2 are kept
+        H.Hm.assign((size_t)nk * q * q * 2, 0.0);
+        parallel_for(nk, [&](int k) {
           double th = 2.0 * M_PI * k / nx;
           cd e1(std::cos(th), std::sin(th));
           for (int i = 0; i < q; ++i)
@@ -897,7 +898,7 @@ static sem_status build_mesh(sem_mesh* M) {
     put(M, (p + "Hm").c_str(), H.Hm);
     put(M, (p + "Qm").c_str(), H.Qm);
     reserve(M, (p + "vbuf").c_str(), (size_t)std::max(1, H.q) * sizeof(double));
-    reserve(M, (p + "WP").c_str(), (size_t)nx * 2 * std::max(1, H.q) * sizeof(double));
+    reserve(M, (p + "WP").c_str(), (size_t)2 * std::max(1, H.q) * sizeof(double));
     const size_t lbytes = (size_t)nx * std::max(1, H.q) * sizeof(double);
     const size_t fbytes = M->fft_n1 ? lbytes : 8;
     reserve(M, (p + "FT").c_str(), 2 * fbytes);
@@ -1120,9 +1121,6 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     sd.WP = at<double>(M, (p + "WP").c_str());
     sd.fft_n1 = M->fft_n1;
     sd.fft_n2 = M->fft_n2;
-    // partial line sums: one per workgroup of the mode solves (pairs of
-    // conjugate modes per workgroup)
-    sd.nwp = M->fft_n1 ? fft_mode_blocks(M->nx, fft_modes_per_block(sd.q)) : paired_blocks(M->nx, kModesPerBlock / 2);
     sd.FT = at<double>(M, (p + "FT").c_str());
     sd.FG = at<double>(M, (p + "FG").c_str());
     sd.XL = at<double>(M, (p + "XL").c_str());

@@ -85,11 +85,12 @@ struct SDData {
   // line 0 of the periodic solve (Schur complement on the wall line)
   int32_t wall, pad2;
   const double* Wv;               // [q][3q + nI] v from [r_wall; x_{nx-1}; x_0; y_I(nx-1)], row-major
-  const double* Hm;               // [nx][q][q][2] modal response to v, column-major per mode
+  const double* Hm;               // [nx/2+1][q][q][2] modal response to v, column-major per mode
+                                  // (mode nx - k is the conjugate of mode k)
   const double* Qm;               // [q][nI] interior response of the last column, column-major
   double* vbuf;                   // [q] v
-  double* WP;                     // [nwp][2][q] per-block partial sums of lines nx-1 and 0
-  int32_t nwp;                    // number of those partials
+  double* WP;                     // [2][q] lines nx-1 and 0 of the periodic solve
+  int32_t pad5;
   // long tanks: the transforms along x as four-step FFTs, nx = n1 n2
   int32_t fft_n1, fft_n2;         // 0: direct DFT products
   int32_t pad3;
