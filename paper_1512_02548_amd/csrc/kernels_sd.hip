@@ -609,13 +609,14 @@ __device__ __forceinline__ void sdf_a_body(const TankDev& d, int which, const T*
   extern __shared__ double sh[];
   const int q = sd.q, nx = d.nx, nc = d.nc, n1 = sd.fft_n1, n2 = sd.fft_n2;
   const int c2 = bx;
-  const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16, nNT = (q + 15) / 16;
+  const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16;
   const double rs = sd_in_scale(nscale);
-  double* gl = sh;   // [4 KS][q] line right sides of columns n2 c1 + c2
-  for (int t = threadIdx.x; t < 4 * KS * q; t += blockDim.x) {
-    const int c1 = t / q, j = t - c1 * q;
+  const int nt = by;   // this workgroup's 16 line unknowns
+  double* gl = sh;   // [4 KS][16] line right sides of columns n2 c1 + c2, unknowns 16 nt ..
+  for (int t = threadIdx.x; t < 4 * KS * 16; t += blockDim.x) {
+    const int c1 = t >> 4, j = 16 * nt + (t & 15);
     double v = 0;
-    if (c1 < n1) {
+    if (c1 < n1 && j < q) {
       const int c = n2 * c1 + c2, cm = c == 0 ? nx - 1 : c - 1;
       v = (double)r[(int64_t)c * nc + j] * rs;
       if (vout) vout[(int64_t)c * nc + j] = T(v);
@@ -630,8 +631,7 @@ __device__ __forceinline__ void sdf_a_body(const TankDev& d, int which, const T*
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  for (int pr = wv; pr < nMT * nNT; pr += kWaves) {
-    const int mt = pr / nNT, nt = pr - mt * nNT;
+  for (int mt = wv; mt < nMT; mt += kWaves) {
     const int k1 = 16 * mt + col, j = 16 * nt + col;
     V4 ar = V4{0, 0, 0, 0}, ai = V4{0, 0, 0, 0};
 #pragma unroll 4
@@ -643,7 +643,7 @@ __device__ __forceinline__ void sdf_a_body(const TankDev& d, int which, const T*
         wr = T(d.twid[2 * m]);
         wi = T(d.twid[2 * m + 1]);
       }
-      const T b = j < q ? T(gl[c1 * q + j]) : T(0);
+      const T b = T(gl[c1 * 16 + col]);
       ar = MF::op(wr, b, ar);
       ai = MF::op(wi, b, ai);
     }
@@ -678,11 +678,11 @@ __device__ __forceinline__ void sdf_b_body(const TankDev& d, int which, int bx, 
   const SDData& sd = d.sd[which];
   const int q = sd.q, n1 = sd.fft_n1, n2 = sd.fft_n2;
   const int k1 = bx;
-  const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16, nNT = (q + 15) / 16;
+  const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   const double* ft = sd.FT + (size_t)k1 * n2 * q * 2;
-  for (int pr = wv; pr < nMT * nNT; pr += kWaves) {
-    const int mt = pr / nNT, nt = pr - mt * nNT;
+  const int nt = by;   // this workgroup's 16 line unknowns
+  for (int mt = wv; mt < nMT; mt += kWaves) {
     const int k2 = 16 * mt + col, j = 16 * nt + col;
     V4 gr = V4{0, 0, 0, 0}, gi = V4{0, 0, 0, 0};
 #pragma unroll 4
@@ -768,10 +768,10 @@ __device__ __forceinline__ void sdf_c_body(const TankDev& d, int which, int bx, 
   const SDData& sd = d.sd[which];
   const int q = sd.q, nx = d.nx, n1 = sd.fft_n1, n2 = sd.fft_n2;
   const int k1 = bx;
-  const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16, nNT = (q + 15) / 16;
+  const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  for (int pr = wv; pr < nMT * nNT; pr += kWaves) {
-    const int mt = pr / nNT, nt = pr - mt * nNT;
+  const int nt = by;   // this workgroup's 16 line unknowns
+  for (int mt = wv; mt < nMT; mt += kWaves) {
     const int c2 = 16 * mt + col, j = 16 * nt + col;
     V4 ur = V4{0, 0, 0, 0}, ui = V4{0, 0, 0, 0};
 #pragma unroll 4
@@ -824,12 +824,12 @@ __device__ __forceinline__ void sdf_d_body(const TankDev& d, int which, int bx, 
   const SDData& sd = d.sd[which];
   const int q = sd.q, nx = d.nx, n1 = sd.fft_n1, n2 = sd.fft_n2;
   const int c2 = bx;
-  const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16, nNT = (q + 15) / 16;
+  const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
   const double* ft = sd.FT + (size_t)c2 * n1 * q * 2;
   const double inx = 1.0 / nx;
-  for (int pr = wv; pr < nMT * nNT; pr += kWaves) {
-    const int mt = pr / nNT, nt = pr - mt * nNT;
+  const int nt = by;   // this workgroup's 16 line unknowns
+  for (int mt = wv; mt < nMT; mt += kWaves) {
     const int c1 = 16 * mt + col, j = 16 * nt + col;
     V4 acc = V4{0, 0, 0, 0};
 #pragma unroll 4
@@ -877,7 +877,7 @@ SdLds sd_lds(const TankDev& h, const SDData& sd, size_t word) {
   l.cond = sd_cond_stage_bytes(s1.ntw, word, s1.split) + sizeof(int32_t) * sd.nI;
   l.modes = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
   l.back = sizeof(double) * ((16 * (size_t)s3.ntw + 1) * (sd.q + 1) + (s3.split ? kWaves * s3.ntw * 256 : 0));
-  l.fa = sd.fft_n1 ? sizeof(double) * 4 * (size_t)((sd.fft_n1 + 3) / 4) * sd.q : 0;
+  l.fa = sd.fft_n1 ? sizeof(double) * 4 * (size_t)((sd.fft_n1 + 3) / 4) * 16 : 0;
   l.fsolve = 0;
   l.wall = 0;
   return l;
@@ -973,11 +973,12 @@ void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int
     const int ct = (h.nx + 15) / 16;
     add_grid(out->cond, t, g.cx, g.cy, l.cond);
     if (sd.fft_n1) {
-      add_grid(out->fa, t, sd.fft_n2, 1, l.fa);
-      add_grid(out->fb, t, sd.fft_n1, 1, 0);
+      const int nnt = (sd.q + 15) / 16;
+      add_grid(out->fa, t, sd.fft_n2, nnt, l.fa);
+      add_grid(out->fb, t, sd.fft_n1, nnt, 0);
       add_grid(out->fsolve, t, fft_mode_blocks(h.nx, fft_modes_per_block(sd.q)), 1, l.fsolve);
-      add_grid(out->fc, t, sd.fft_n1, 1, 0);
-      add_grid(out->fd, t, sd.fft_n2, 1, 0);
+      add_grid(out->fc, t, sd.fft_n1, nnt, 0);
+      add_grid(out->fd, t, sd.fft_n2, nnt, 0);
     } else {
       add_grid(out->modes, t, paired_blocks(h.nx, kModesPB / 2), 1, l.modes);
       add_grid(out->idft, t, ct, (sd.q + 15) / 16, 0);
@@ -1035,9 +1036,10 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
                      vout);
   const int n1 = sd.fft_n1, n2 = sd.fft_n2;
   if (n1) {
-    const size_t la = sizeof(double) * 4 * (size_t)((n1 + 3) / 4) * sd.q;
-    hipLaunchKernelGGL(k_sdf_a<T>, dim3(n2), dim3(kBlockThreads), la, st, d, which, u, gate, nscale, vout);
-    hipLaunchKernelGGL(k_sdf_b<T>, dim3(n1), dim3(kBlockThreads), 0, st, d, which, gate);
+    const size_t la = sizeof(double) * 4 * (size_t)((n1 + 3) / 4) * 16;
+    const unsigned nnt = (unsigned)((sd.q + 15) / 16);
+    hipLaunchKernelGGL(k_sdf_a<T>, dim3(n2, nnt), dim3(kBlockThreads), la, st, d, which, u, gate, nscale, vout);
+    hipLaunchKernelGGL(k_sdf_b<T>, dim3(n1, nnt), dim3(kBlockThreads), 0, st, d, which, gate);
     const int ml = fft_modes_per_block(sd.q);
     hipLaunchKernelGGL(k_sdf_solve<T>, dim3(fft_mode_blocks(h.nx, ml)), dim3(kBlockThreads), lds.fsolve, st, d,
                        which, gate);
@@ -1053,8 +1055,9 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
                        dim3(kBlockThreads), 0, st, d, which, gate);
   }
   if (n1) {
-    hipLaunchKernelGGL(k_sdf_c<T>, dim3(n1), dim3(kBlockThreads), 0, st, d, which, gate);
-    hipLaunchKernelGGL(k_sdf_d<T>, dim3(n2), dim3(kBlockThreads), 0, st, d, which, gate);
+    const unsigned nnt = (unsigned)((sd.q + 15) / 16);
+    hipLaunchKernelGGL(k_sdf_c<T>, dim3(n1, nnt), dim3(kBlockThreads), 0, st, d, which, gate);
+    hipLaunchKernelGGL(k_sdf_d<T>, dim3(n2, nnt), dim3(kBlockThreads), 0, st, d, which, gate);
   } else {
     hipLaunchKernelGGL(k_sd_idft<T>, dim3(ct, (sd.q + 15) / 16), dim3(kBlockThreads), 0, st, d, which, gate);
   }
