@@ -208,6 +208,7 @@ def batch_workload(args, modes=("lockstep_fp64", "lockstep_mixed", "concurrent_m
             t["eta"].copy_(e)
             t["phi"].copy_(p)
             t["ws"].zero_()
+            t["mesh"].reset_history()
 
     def batched(name, nstreams, opts):
         b = lib.Batch([t["mesh"] for t in tanks], nstreams)
@@ -265,6 +266,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rtol", type=float, default=1e-12)
+    ap.add_argument("--predict", type=int, default=3,
+                    help="past steps extrapolated into each stage solve's start vector (0..3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-large", action="store_true", help="skip the 2048x8 bar-tank section")
@@ -302,7 +305,7 @@ def main():
     eta = torch.tensor(eta0, dtype=torch.float64, device=dev)
     phi = torch.tensor(phi0, dtype=torch.float64, device=dev)
     ws = torch.zeros(m.n, dtype=torch.float64, device=dev)
-    opts = lib.default_opts(rtol=args.rtol, warm_start=1, lookahead=1)
+    opts = lib.default_opts(rtol=args.rtol, warm_start=1, lookahead=1, predict=args.predict)
     n_free = m.info.n_free
 
     eta_init, phi_init = eta.clone(), phi.clone()
@@ -318,6 +321,7 @@ def main():
                 eta.copy_(eta_init)
                 phi.copy_(phi_init)
                 ws.zero_()
+                m.reset_history()
                 state["since"] = 0
             state["since"] += 1
             code, st = m.rk4_step(eta, phi, ws, spec.dt, opts)
@@ -363,7 +367,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "nx": spec.nx, "nz": spec.nz, "P": spec.P, "Pf": spec.Pf,
                    "n_free": int(n_free), "elements": int(E), "rtol": args.rtol, "precision": "fp64",
-                   "solves": nsolve, "mean_iters": iters / max(nsolve, 1),
+                   "solves": nsolve, "mean_iters": iters / max(nsolve, 1), "predict": args.predict,
                    "solve_time_fraction": tsolve / wall},
         "roofline": {"bound": "hbm", "kernel": "stiffness apply (k_stiff_mfma)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

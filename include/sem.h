@@ -107,7 +107,8 @@ typedef struct {
   int32_t max_refine;   /* IR: maximum outer refinements                           */
   int32_t warm_start;   /* 1: phi holds the initial guess on entry                 */
   int32_t lookahead;    /* Krylov steps the host may queue ahead of the device (>=1) */
-  int32_t reserved;
+  int32_t predict;      /* RK4 steps only: 0..3 past steps extrapolated into each
+                           stage solve's start vector (0: the previous stage's Phi) */
 } sem_solve_opts;
 
 typedef struct {
@@ -174,9 +175,22 @@ sem_status sem_free_surface_rhs(sem_mesh* mesh, const double* eta, const double*
 /* One classical RK4 step of (eta, phi~) [ns] followed by the modal filter
  * (Secs. 3.1.1, 3.4).  phi_ws [n] carries the warm start of the Laplace
  * solves across calls.  Transactional: on error eta and phi_s are left
- * unchanged.  stats: HOST array of 4 (one per stage) or NULL. */
+ * unchanged.  stats: HOST array of 4 (one per stage) or NULL.
+ *
+ * Stage start vectors: each stage solve starts from the previous stage's
+ * Phi (in phi_ws) plus the change from the previous stage to this one,
+ * extrapolated over the same stage of the last opts->predict completed steps
+ * of this mesh (linear, quadratic or cubic in the step index).  The mesh's
+ * workspace keeps that record; it restarts when dt changes and after
+ * sem_rk4_reset_history.  The start vector never changes the stopping test,
+ * only the iteration count. */
 sem_status sem_rk4_step(sem_mesh* mesh, double* eta, double* phi_s, double* phi_ws, double dt,
                         const sem_solve_opts* opts, sem_solve_stats* stats, void* stream);
+
+/* Forget the recorded stage solutions of `mesh` (ordered on `stream`): call
+ * when the state passed to the next step was not reached by the previous
+ * steps on this mesh (a new initial condition). */
+sem_status sem_rk4_reset_history(sem_mesh* mesh, void* stream);
 
 /* Batching: many independent tanks (each bound to its own workspace)
  * advanced by one call.  A tank's results do not depend on which other tanks

@@ -507,6 +507,7 @@ static sem_status check_opts(const sem_solve_opts* opts, sem_solve_opts* o) {
   if (o->prec < 0 || o->prec > 2) return fail(SEM_E_INVAL, "unknown precision");
   if (o->prec != SEM_PREC_FP64 && !(o->inner_rtol > 0 && o->inner_rtol < 1))
     return fail(SEM_E_INVAL, "inner_rtol must lie in (0, 1)");
+  if (o->predict < 0 || o->predict > kHistSteps) return fail(SEM_E_INVAL, "predict must be in 0..3");
   return SEM_OK;
 }
 
@@ -600,11 +601,13 @@ static sem_status lockstep_rk4(sem_batch* B, double* const* eta, double* const* 
                         sidx == 0 ? phi_s[t] : M->rk + ns, M->rk + 3 * ns, st);
     }
     launch_coef_b(a, B->stage, se, RK[2], 3, st);
+    launch_predict_b(a, B->vec, sidx, o.predict, B->ddt, PT_WS, st);
     s = lockstep_laplace(B, act, sidx == 0 ? PT_PHIS : PT_YP, 1, o, iters, st);
     if (s) return s;
     if (act.empty()) break;
     s = set_live(B, act, st);
     if (s) return s;
+    launch_history_b(a, B->vec, sidx, PT_WS, st);
     // w~: M w = S_z Phi, w~ = w at the surface
     launch_sz_b(a, B->stage, SSel{SS_PT, PT_WS}, st);
     launch_fixup_b(a, B->fixup, VSel{BV_B, 0}, 0, 0, st);

@@ -933,6 +933,77 @@ k_solution_out_b(BatchArgs ba, const double* const* __restrict__ phis, double* c
   phi[it_.tank][i] = sl >= 0 ? phis[it_.tank][sl] : d.xs[i];
 }
 
+// ------------------------------------------------------------ stage predictor
+// Initial guess of RK4 stage k's Laplace solve.  The solve starts from the
+// previous stage's solution p; the guess adds the change from the previous
+// stage to stage k, extrapolated over the last steps (the same stage of
+// steps n-1, n-2, n-3: D1, D2, D3) by the polynomial of the available
+// depth: D1, 2 D1 - D2, or 3 D1 - 3 D2 + D3.  Stage 0's change in a step
+// needs the last stage of the step before, so its record starts one step
+// later.  Only the starting vector changes; the solve's stopping test does
+// not.
+__device__ inline int predict_depth(const StageHistory& hs, int stage, int maxdepth, double dt) {
+  if (hs.dt != dt) return 0;
+  const int dep = stage == 0 ? hs.valid - 1 : hs.valid;
+  return max(0, min(dep, maxdepth));
+}
+// the record of stage k, `back` steps before the current one (0: the current step's slot)
+__device__ inline const double* hist_slot(const TankDev& d, int stage, const StageHistory& hs, int back) {
+  const int r = (hs.slot - back + kHistSteps) % kHistSteps;
+  return d.hist + ((size_t)stage * kHistSteps + (size_t)r) * d.n;
+}
+
+__device__ __forceinline__ void predict_body(const TankDev& d, int stage, int maxdepth, double dt,
+                                             double* __restrict__ ws, int64_t i) {
+  const StageHistory hs = *d.hs;
+  const int dep = predict_depth(hs, stage, maxdepth, dt);
+  const double p = ws[i];
+  d.pv[i] = p;
+  if (dep == 0) return;
+  const double d1 = hist_slot(d, stage, hs, 1)[i];
+  double e = d1;
+  if (dep >= 2) {
+    const double d2 = hist_slot(d, stage, hs, 2)[i];
+    e = dep == 2 ? 2.0 * d1 - d2 : (3.0 * d1 - 3.0 * d2) + hist_slot(d, stage, hs, 3)[i];
+  }
+  ws[i] = p + e;
+}
+
+// after stage k's solve: its change from the starting vector, into this step's slot
+__device__ __forceinline__ void history_body(const TankDev& d, int stage, const double* __restrict__ ws, int64_t i) {
+  double* slot = const_cast<double*>(hist_slot(d, stage, *d.hs, 0));
+  slot[i] = ws[i] - d.pv[i];
+}
+
+__global__ void __launch_bounds__(kBlockThreads)
+k_predict(const TankDev* __restrict__ td, int stage, int maxdepth, double dt, double* __restrict__ ws) {
+  const TankDev& d = *td;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.n) predict_body(d, stage, maxdepth, dt, ws, i);
+}
+
+__global__ void __launch_bounds__(kBlockThreads)
+k_history(const TankDev* __restrict__ td, int stage, const double* __restrict__ ws) {
+  const TankDev& d = *td;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.n) history_body(d, stage, ws, i);
+}
+
+__global__ void __launch_bounds__(kBlockThreads)
+k_predict_b(BatchArgs ba, int stage, int maxdepth, const double* __restrict__ dt, int table) {
+  SEM_BATCH_TANK(ba)
+  const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  predict_body(d, stage, maxdepth, dt[it_.tank], const_cast<double*>(ba.ptrs[(size_t)table * ba.count + it_.tank]), i);
+}
+
+__global__ void __launch_bounds__(kBlockThreads) k_history_b(BatchArgs ba, int stage, int table) {
+  SEM_BATCH_TANK(ba)
+  const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  history_body(d, stage, ba.ptrs[(size_t)table * ba.count + it_.tank], i);
+}
+
 // ------------------------------------------------------------ 1D surface work
 // One workgroup per tank.  1D element e (column) holds surface nodes
 // e*P + k, k = 0..P (wrapped when periodic).
@@ -1330,6 +1401,12 @@ __device__ __forceinline__ void rk4_final_body(const TankDev& d, double dt, cons
     eta[s] = fe[s];
     phi[s] = fp[s];
   }
+  if (threadIdx.x == 0) {   // the step is complete: its stage record counts
+    StageHistory& hs = *d.hs;
+    hs.valid = hs.dt == dt ? min(hs.valid + 1, 64) : 1;
+    hs.slot = (hs.slot + 1) % kHistSteps;
+    hs.dt = dt;
+  }
 }
 
 template <int P>
@@ -1536,6 +1613,13 @@ void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hip
 void launch_fill(int64_t n, double v, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, v, y);
 }
+void launch_predict(const TankDev& h, const TankDev* d, int stage, int maxdepth, double dt, double* ws,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_predict, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, stage, maxdepth, dt, ws);
+}
+void launch_history(const TankDev& h, const TankDev* d, int stage, const double* ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_history, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, stage, ws);
+}
 void launch_mask_surface(const TankDev& h, const TankDev* d, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_mask_surface, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, y);
 }
@@ -1659,6 +1743,13 @@ void launch_orth_b(const BatchArgs& a0, const BatchStage& p, const BatchStage& p
 void launch_fixup_b(const BatchArgs& a0, const BatchStage& p, VSel y, int flags, int f32, hipStream_t st) {
   if (f32) SEM_BLAUNCH(p, k_fixup_b<float>, y, flags);
   else SEM_BLAUNCH(p, k_fixup_b<double>, y, flags);
+}
+void launch_predict_b(const BatchArgs& a0, const BatchStage& vec, int stage, int maxdepth, const double* dt, int table,
+                      hipStream_t st) {
+  SEM_BLAUNCH(vec, k_predict_b, stage, maxdepth, dt, table);
+}
+void launch_history_b(const BatchArgs& a0, const BatchStage& vec, int stage, int table, hipStream_t st) {
+  SEM_BLAUNCH(vec, k_history_b, stage, table);
 }
 void launch_residual_b(const BatchArgs& a0, const BatchStage& p, VSel b, VSel y, VSel r, int f32, hipStream_t st) {
   if (f32) SEM_BLAUNCH(p, k_residual_b<float>, b, y, r);

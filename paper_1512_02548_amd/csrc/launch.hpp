@@ -85,6 +85,9 @@ void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const 
 void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,
                       const double* ke, const double* kp, double* ye, double* yp, double* acce, double* accp,
                       hipStream_t st);
+void launch_predict(const TankDev& h, const TankDev* d, int stage, int maxdepth, double dt, double* ws,
+                    hipStream_t st);
+void launch_history(const TankDev& h, const TankDev* d, int stage, const double* ws, hipStream_t st);
 void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const double* acce, const double* accp,
                       double* eta, double* phi, int use_filter, hipStream_t st);
 
@@ -128,6 +131,9 @@ void launch_state_out_b(const BatchArgs& a, const BatchStage& per_tank, KrylovSt
 // scalar idx of every tank to out[tank] (host-visible)
 void launch_scal_out_b(const BatchArgs& a, const BatchStage& per_tank, int idx, double* out, hipStream_t st);
 // iterative refinement: b32 = tmp * scale[t], x32 = 0; then xs += scale[t] * x32
+void launch_predict_b(const BatchArgs& a, const BatchStage& vec, int stage, int maxdepth, const double* dt, int table,
+                      hipStream_t st);
+void launch_history_b(const BatchArgs& a, const BatchStage& vec, int stage, int table, hipStream_t st);
 void launch_to_float_b(const BatchArgs& a, const BatchStage& vec, const double* scale, hipStream_t st);
 void launch_add_float_b(const BatchArgs& a, const BatchStage& vec, const double* scale, hipStream_t st);
 void launch_status_or_b(const BatchArgs& a, const BatchStage& per_tank, int bits, hipStream_t st);

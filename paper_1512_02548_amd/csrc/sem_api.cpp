@@ -936,6 +936,9 @@ static sem_status build_mesh(sem_mesh* M) {
   reserve(M, "side", (size_t)4 * M->nb * nl * sizeof(double));
   reserve(M, "s1d", 16 * ns1 * sizeof(double));
   reserve(M, "rk", 16 * ns1 * sizeof(double));
+  reserve(M, "hist", (size_t)4 * kHistSteps * n * sizeof(double));
+  reserve(M, "pv", n * sizeof(double));
+  reserve(M, "hs", sizeof(StageHistory));
   reserve(M, "V32", (size_t)(m + 1) * n * sizeof(float));
   reserve(M, "Z32", (size_t)m * n * sizeof(float));
   reserve(M, "w32", n * sizeof(float));
@@ -1165,6 +1168,9 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.prog = M->prog_dev;
   h.rk = M->rk;
   h.use_filter = M->sf != 1.0 ? 1 : 0;
+  h.hist = at<double>(M, "hist");
+  h.pv = at<double>(M, "pv");
+  h.hs = at<StageHistory>(M, "hs");
   M->dtank = at<TankDev>(M, "tank");
   // every device array the kernels use must have been laid out
   const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.opf, h.opf32, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,
@@ -1173,7 +1179,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
                         h.G32, h.G16, h.invd, h.status, h.ks, h.H, h.part, h.V, h.Zb, h.w, h.b, h.tmp, h.xs,
                         h.wmass, h.side, h.s1d, h.V32, h.Z32, h.w32, h.x32, h.b32, h.twid, h.Brow, h.Rrow,
                         h.sd[0].yI, h.sd[1].yI, h.sd[0].A1, h.sd[1].A1, h.sd[0].C3, h.sd[1].C3, h.sd[0].XH,
-                        h.sd[1].XH, M->rk, M->scal};
+                        h.sd[1].XH, M->rk, M->scal, h.hist, h.pv, h.hs};
   for (size_t i = 0; i < sizeof(need) / sizeof(need[0]); ++i)
     if (!need[i]) return fail(SEM_E_INVAL, "internal: workspace layout incomplete (" + std::to_string(i) + ")");
   for (const Upload& u : M->uploads)
@@ -1182,6 +1188,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   HIPCHK(hipMemsetAsync(h.status, 0, 64, st));
   // Krylov state, including the completion counter of the fused reductions
   HIPCHK(hipMemsetAsync(h.ks, 0, sizeof(KrylovState), st));
+  HIPCHK(hipMemsetAsync(h.hs, 0, sizeof(StageHistory), st));
   HIPCHK(hipMemsetAsync(h.wmass, 0, M->n * sizeof(double), st));
   HIPCHK(hipMemsetAsync(h.G, 0, M->off.at("G32") - M->off.at("G"), st));
   HIPCHK(hipMemsetAsync(h.G32, 0, M->off.at("G16") - M->off.at("G32"), st));
@@ -1421,6 +1428,7 @@ void sem::default_opts(sem_solve_opts* o) {
   o->max_refine = 30;
   o->warm_start = 0;
   o->lookahead = 2;
+  o->predict = 3;
 }
 
 // ------------------------------------------------------------ public calls
@@ -1544,12 +1552,21 @@ extern "C" sem_status sem_selftest_mfma(sem_mesh* M, double* max_err, double* ra
 // FP64: GMRES on A_FF x = b.  FP32_IR / BF16_IR: FP64 iterative refinement,
 // each correction from an FP32 GMRES solve (FP32 vectors and operators, FP32
 // or bfloat16 geometric factors, FP64 inner products) scaled by ||r||.
+// RK4 stage solves: the stage index, the extrapolation depth and dt of the
+// start-vector predictor (the predictor and the record of the stage's
+// change run inside the solve's timed span).
+struct StagePredict {
+  int stage, depth;
+  double dt;
+};
+
 static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, const sem_solve_opts* o,
-                               sem_solve_stats* stats, hipStream_t st) {
+                               sem_solve_stats* stats, hipStream_t st, const StagePredict* pred = nullptr) {
   const TankDev& h = M->hd;
   const TankDev* d = M->dtank;
   const int64_t n = M->n;
   auto t0 = std::chrono::steady_clock::now();
+  if (pred) launch_predict(h, d, pred->stage, pred->depth, pred->dt, phi, st);
   // b = -(A [0; phi~])_F
   launch_scatter_surface(h, d, phi_s, h.tmp, 1, st);
   launch_gather(h, d, OP_STIFF, h.tmp, h.b, h.side, F_MASK_SURF | F_NEG, st);
@@ -1614,6 +1631,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   // Phi = x_F + lift
   HIPCHK(hipMemcpyAsync(phi, h.xs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   launch_scatter_surface(h, d, phi_s, phi, 0, st);
+  if (pred) launch_history(h, d, pred->stage, phi, st);
   HIPCHK(hipStreamSynchronize(st));
   if (stats) {
     stats->iters = iters;
@@ -1697,6 +1715,13 @@ extern "C" sem_status sem_free_surface_rhs(sem_mesh* M, const double* eta, const
   return read_status(M, st, nullptr);
 }
 
+extern "C" sem_status sem_rk4_reset_history(sem_mesh* M, void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  HIPCHK(hipMemsetAsync(M->hd.hs, 0, sizeof(StageHistory), (hipStream_t)stream));
+  return SEM_OK;
+}
+
 extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, double* phi_ws, double dt,
                                    const sem_solve_opts* opts, sem_solve_stats* stats, void* stream) {
   sem_status s = check_bound(M);
@@ -1706,6 +1731,7 @@ extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, doub
   sem_solve_opts o;
   if (opts) o = *opts;
   else default_opts(&o);
+  if (o.predict < 0 || o.predict > kHistSteps) return fail(SEM_E_INVAL, "predict must be in 0..3");
   hipStream_t st = (hipStream_t)stream;
   const TankDev& h = M->hd;
   const TankDev* d = M->dtank;
@@ -1738,7 +1764,8 @@ extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, doub
       break;
     }
     sem_solve_stats ls{};
-    s = laplace_core(M, sp, phi_ws, &lo, &ls, st);
+    const StagePredict pred{sidx, o.predict, dt};
+    s = laplace_core(M, sp, phi_ws, &lo, &ls, st, &pred);
     if (stats) stats[sidx] = ls;
     if (s) {
       first_err = s;

@@ -45,6 +45,17 @@ enum : int32_t {
 };
 
 // Krylov state of one solve, resident in the workspace.
+// Record of the RK4 stepper's stage solutions, for the initial guesses of
+// the stage Laplace solves: the ring slot of the next step, the number of
+// consecutive completed steps with step size dt since the last reset (a
+// different step size starts the record again).
+struct StageHistory {
+  int32_t slot;
+  int32_t valid;
+  double dt;
+};
+constexpr int kHistSteps = 3;       // past steps kept per stage
+
 struct KrylovState {
   double bnorm;       // ||b||
   double beta;        // ||r0|| of the current cycle
@@ -183,6 +194,9 @@ struct TankDev {
   double* rk;                     // [9][ns] RK4 stage arrays: eta, phi, eta_x, phi_x, w~, slopes (2), sums (2)
   int32_t use_filter;             // the modal filter is on
   int32_t pad4;
+  double* hist;                   // [4 stages][kHistSteps][n] stage-solution differences
+  double* pv;                     // n: a stage's starting vector before extrapolation
+  StageHistory* hs;
 };
 
 // ------------------------------------------------------------ batched launches

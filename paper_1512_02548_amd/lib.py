@@ -49,7 +49,7 @@ class sem_mesh_info(C.Structure):
 class sem_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32),
                 ("inner_rtol", C.c_double), ("max_refine", C.c_int32), ("warm_start", C.c_int32),
-                ("lookahead", C.c_int32), ("reserved", C.c_int32)]
+                ("lookahead", C.c_int32), ("predict", C.c_int32)]
 
 
 class sem_solve_stats(C.Structure):
@@ -79,6 +79,7 @@ _SIGS = {
     "sem_free_surface_rhs": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "sem_rk4_step": (C.c_int, [_P, _P, _P, _P, C.c_double, C.POINTER(sem_solve_opts),
                                C.POINTER(sem_solve_stats), _P]),
+    "sem_rk4_reset_history": (C.c_int, [_P, _P]),
     "sem_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
     "sem_batch_laplace_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
                                           C.POINTER(C.c_uint8), C.POINTER(sem_solve_opts),
@@ -124,8 +125,8 @@ def _stream(stream=None):
 
 
 def default_opts(rtol=1e-12, max_iter=5000, prec=SEM_PREC_FP64, inner_rtol=1e-4, max_refine=30,
-                 warm_start=0, lookahead=2):
-    return sem_solve_opts(rtol, max_iter, prec, inner_rtol, max_refine, warm_start, lookahead, 0)
+                 warm_start=0, lookahead=2, predict=3):
+    return sem_solve_opts(rtol, max_iter, prec, inner_rtol, max_refine, warm_start, lookahead, predict)
 
 
 class Mesh:
@@ -225,6 +226,10 @@ class Mesh:
         if raise_on_error:
             check(code, "sem_rk4_step")
         return code, [s.as_dict() for s in st]
+
+    def reset_history(self, stream=None):
+        """Forget the recorded stage solutions (a new initial condition follows)."""
+        check(sem_rk4_reset_history(self.handle, _stream(stream)), "sem_rk4_reset_history")
 
     def __del__(self):
         h = getattr(self, "handle", None)

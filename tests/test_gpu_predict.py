@@ -1,0 +1,85 @@
+"""GPU tests of the RK4 stage predictor: the start vector of each stage solve
+extrapolated from the recorded stage changes of past steps.  The start vector
+does not change what the solve converges to (same stopping test), only how
+many iterations it takes; a reset or a new step size starts the record
+again, which makes the next step identical to one on a fresh mesh."""
+import numpy as np
+import pytest
+
+from paper_1512_02548_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def stream_tank(nx=16, nz=2, P=6):
+    import torch
+    from paper_1512_02548_amd import lib
+    spec = wl.stream_series_spec(nx=nx, nz=nz, P=P)
+    m = lib.mesh_from_spec(spec, np.ones(spec.ns), np.zeros(spec.ns))
+    eta, phi, h, hx = wl.stream_series_state(m.surface_x(), spec)
+    m = lib.mesh_from_spec(spec, h, hx)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    return spec, m, t(eta), t(phi), torch.zeros(m.n, dtype=torch.float64, device="cuda")
+
+
+def run(m, eta, phi, ws, dt, steps, opts):
+    its = []
+    for _ in range(steps):
+        _, st = m.rk4_step(eta, phi, ws, dt, opts)
+        its.append([s["iters"] for s in st])
+    return its
+
+
+def test_predictor_fewer_iterations_same_solution():
+    from paper_1512_02548_amd import lib
+    steps = 10
+    res = {}
+    for depth in (0, 1, 2, 3):
+        spec, m, eta, phi, ws = stream_tank()
+        opts = lib.default_opts(rtol=1e-13, warm_start=1, predict=depth)
+        its = run(m, eta, phi, ws, spec.dt, steps, opts)
+        res[depth] = (eta.cpu().numpy(), phi.cpu().numpy(), its)
+    e0, p0, i0 = res[0]
+    scale = max(np.abs(e0).max(), 1e-30), max(np.abs(p0).max(), 1e-30)
+    for depth in (1, 2, 3):
+        e, p, _ = res[depth]
+        assert np.abs(e - e0).max() / scale[0] < 1e-10
+        assert np.abs(p - p0).max() / scale[1] < 1e-10
+    # once the record is full (step 5 on), every deeper predictor needs fewer
+    # iterations per step than the previous stage's solution alone
+    tail = lambda d: sum(sum(s) for s in res[d][2][4:])
+    assert tail(3) < tail(1) < tail(0), {d: tail(d) for d in res}
+    assert tail(2) < tail(0)
+
+
+def test_reset_and_new_step_size_restart_the_record():
+    """After a reset (or with a new dt) the next step is bitwise the step of a
+    fresh mesh from the same state and start vector."""
+    import torch
+    from paper_1512_02548_amd import lib
+    opts = lib.default_opts(rtol=1e-12, warm_start=1, predict=3)
+    spec, m, eta, phi, ws = stream_tank()
+    run(m, eta, phi, ws, spec.dt, 5, opts)
+    for mode in ("reset", "dt"):
+        dt = spec.dt if mode == "reset" else 0.5 * spec.dt
+        _, m2, e2, p2, w2 = stream_tank()
+        e2.copy_(eta), p2.copy_(phi), w2.copy_(ws)
+        if mode == "reset":
+            m.reset_history()
+        ia = run(m, eta, phi, ws, dt, 1, opts)
+        ib = run(m2, e2, p2, w2, dt, 1, opts)
+        torch.cuda.synchronize()
+        assert ia == ib
+        assert torch.equal(eta, e2) and torch.equal(phi, p2) and torch.equal(ws, w2)
+        # and the record builds up again: the next steps match too
+        ia = run(m, eta, phi, ws, dt, 4, opts)
+        ib = run(m2, e2, p2, w2, dt, 4, opts)
+        assert ia == ib
+        assert torch.equal(eta, e2) and torch.equal(phi, p2)
+
+
+def test_predict_out_of_range_is_rejected():
+    from paper_1512_02548_amd import lib
+    spec, m, eta, phi, ws = stream_tank(nx=8, nz=1, P=4)
+    code, _ = m.rk4_step(eta, phi, ws, spec.dt, lib.default_opts(warm_start=1, predict=4), raise_on_error=False)
+    assert code == lib.SEM_E_INVAL
