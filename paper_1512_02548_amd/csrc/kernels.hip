@@ -407,11 +407,23 @@ __device__ void givens_update(KrylovState* __restrict__ ks, double* __restrict__
 
 // Progress of the current Krylov cycle written to host-visible memory
 // (steps done, cycle done, converged) so the host can stop queueing steps
-// without synchronising the stream.
-__device__ inline void publish_progress(const KrylovState* ks, int32_t* mirror) {
+// without synchronising the stream.  A single tank's block also takes the
+// scalars the host reports once the solve has converged (scal: residual
+// estimate, ||b||, total iterations), written before the word is released.
+__device__ inline void publish_progress(const KrylovState* ks, int32_t* mirror, double* scal = nullptr) {
   if (!mirror) return;
+  if (scal) {
+    scal[0] = ks->resid;
+    scal[1] = ks->bnorm;
+    scal[2] = (double)ks->iters;
+  }
   int32_t v = (ks->j & PROG_STEPS) | (ks->done ? PROG_DONE : 0) | (ks->converged ? PROG_CONV : 0);
   __hip_atomic_store(mirror, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// the scalars of a single tank's progress block (the word, then three doubles)
+__device__ inline double* progress_scalars(int32_t* mirror) {
+  return mirror ? reinterpret_cast<double*>(mirror) + 1 : nullptr;
 }
 
 
@@ -537,14 +549,15 @@ __device__ __forceinline__ void orth_partial(int64_t n, int j, const T* __restri
 // ||w'||^2 from nblk partials (first wave), then the Givens update of column j
 __device__ __forceinline__ void orth_reduce(int j, const double* __restrict__ part, int ldp, int nblk,
                                             KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
-                                            int32_t* __restrict__ status, int32_t* __restrict__ mirror) {
+                                            int32_t* __restrict__ status, int32_t* __restrict__ mirror,
+                                            double* __restrict__ smirror = nullptr) {
   if (threadIdx.x < 64) {
     double t = 0;
     for (int b2 = threadIdx.x; b2 < nblk; b2 += 64) t += part[(size_t)b2 * ldp];
     t = wave_sum(t);
     if (threadIdx.x == 0) {
       givens_update(ks, Hbase, m, j, t, status);
-      publish_progress(ks, mirror);
+      publish_progress(ks, mirror, smirror);
     }
   }
 }
@@ -559,7 +572,60 @@ k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hba
   orth_partial<T>(n, j, V, Hbase, m, w, part, ldp, chunk, blockIdx.x);
   if (!last_block(counter, gridDim.x)) return;
   if (threadIdx.x == 0) *counter = 0;
-  orth_reduce(j, part, ldp, gridDim.x, ks, Hbase, m, status, mirror);
+  orth_reduce(j, part, ldp, gridDim.x, ks, Hbase, m, status, mirror, progress_scalars(mirror));
+}
+
+// One Arnoldi step's orthogonalisation in one launch: h = V^T w (the
+// fix-up of w's shared lines folded in), then w' = w - V h, ||w'||^2 and the
+// Givens update, with the arithmetic of the two separate kernels.  The
+// workgroups meet once in between: the last to finish its inner products
+// adds the partials, writes h and advances the epoch word; the others wait
+// for the epoch.  The grid (at most 256 workgroups of 256 threads, little
+// LDS) is resident at once on an otherwise idle device; the wait is bounded,
+// and a wait that runs out marks the solve failed (ST_STALLED) and leaves
+// the kernel instead of waiting on.
+constexpr int kWaitPolls = 1 << 21;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_arnoldi_orth(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase, int m, T* __restrict__ w,
+               double* __restrict__ part, int ldp, int64_t chunk, KrylovState* __restrict__ ks,
+               int32_t* __restrict__ counter, int32_t* __restrict__ epoch, int32_t* __restrict__ status,
+               int32_t* __restrict__ mirror, const TankDev* __restrict__ fixd, const T* __restrict__ side) {
+  __shared__ int go;
+  if (ks->done) return;
+  const int32_t e0 = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double* hcol = Hbase + (size_t)j * (m + 1);
+  dots_partial<T>(n, j + 1, V, n, w, part, ldp, chunk, fixd, side, blockIdx.x);
+  if (last_block(counter, gridDim.x)) {
+    dots_reduce(j + 1, part, ldp, hcol, gridDim.x);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      *counter = 0;
+      __threadfence();
+      __hip_atomic_store(epoch, e0 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else {
+    if (threadIdx.x == 0) {
+      int ok = 0;
+      for (int p = 0; p < kWaitPolls; ++p) {
+        if (__hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e0) {
+          ok = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (!ok) atomicOr(status, ST_STALLED);
+      go = ok;
+    }
+    __syncthreads();
+    if (!go) return;
+    __threadfence();   // acquire: h as the last workgroup wrote it
+  }
+  orth_partial<T>(n, j, V, Hbase, m, w, part, ldp, chunk, blockIdx.x);
+  if (!last_block(counter, gridDim.x)) return;
+  if (threadIdx.x == 0) *counter = 0;
+  orth_reduce(j, part, ldp, gridDim.x, ks, Hbase, m, status, mirror, progress_scalars(mirror));
 }
 
 // ------------------------------------------------------------ GMRES pieces
@@ -661,7 +727,7 @@ __global__ void k_cycle_start(KrylovState* __restrict__ ks, double* __restrict__
                               int32_t* __restrict__ mirror) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   cycle_start(ks, Hbase, m, rr, first, status);
-  publish_progress(ks, mirror);
+  publish_progress(ks, mirror, progress_scalars(mirror));
 }
 
 __device__ void cycle_start(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
@@ -707,6 +773,35 @@ __global__ void k_residual(const TankDev* __restrict__ td, int64_t n, const T* _
   if (i >= n) return;
   T v = bvec[i] - y[i];
   if (mask && is_surface_node(*td, i)) v = T(0);
+  r[i] = v;
+}
+
+// y[i] of an element-kernel output with its shared-line contribution from
+// the side buffer added (the fix-up pass, done by the consumer; the same
+// addition as the separate pass)
+template <typename T>
+__device__ inline T fixed_value(const TankDev& d, const T* __restrict__ y, const T* __restrict__ side, int64_t i) {
+  const int64_t c = i / d.nc;
+  const int ql = (int)(i - c * d.nc);
+  T v = y[i];
+  if (ql >= d.nl) return v;
+  if (c == d.nx) return side[(size_t)(d.nb - 1) * d.nl + ql];   // the wall line has one contribution
+  if (c % d.cb == 0) {
+    const int bl = c > 0 ? (int)(c / d.cb) - 1 : (d.periodic ? d.nb - 1 : -1);
+    if (bl >= 0) v += side[(size_t)bl * d.nl + ql];
+  }
+  return v;
+}
+
+// r = b - y with y's fix-up folded in (masked at the surface)
+template <typename T>
+__global__ void k_residual_fix(const TankDev* __restrict__ td, int64_t n, const T* __restrict__ bvec,
+                               const T* __restrict__ y, const T* __restrict__ side, T* __restrict__ r, int mask) {
+  const TankDev& d = *td;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T v = bvec[i] - fixed_value<T>(d, y, side, i);
+  if (mask && is_surface_node(d, i)) v = T(0);
   r[i] = v;
 }
 
@@ -953,20 +1048,21 @@ __device__ inline const double* hist_slot(const TankDev& d, int stage, const Sta
   return d.hist + ((size_t)stage * kHistSteps + (size_t)r) * d.n;
 }
 
+// the extrapolated change at node i for depth dep >= 1
+__device__ inline double predict_increment(const TankDev& d, const StageHistory& hs, int stage, int dep, int64_t i) {
+  const double d1 = hist_slot(d, stage, hs, 1)[i];
+  if (dep == 1) return d1;
+  const double d2 = hist_slot(d, stage, hs, 2)[i];
+  return dep == 2 ? 2.0 * d1 - d2 : (3.0 * d1 - 3.0 * d2) + hist_slot(d, stage, hs, 3)[i];
+}
+
 __device__ __forceinline__ void predict_body(const TankDev& d, int stage, int maxdepth, double dt,
                                              double* __restrict__ ws, int64_t i) {
   const StageHistory hs = *d.hs;
   const int dep = predict_depth(hs, stage, maxdepth, dt);
   const double p = ws[i];
   d.pv[i] = p;
-  if (dep == 0) return;
-  const double d1 = hist_slot(d, stage, hs, 1)[i];
-  double e = d1;
-  if (dep >= 2) {
-    const double d2 = hist_slot(d, stage, hs, 2)[i];
-    e = dep == 2 ? 2.0 * d1 - d2 : (3.0 * d1 - 3.0 * d2) + hist_slot(d, stage, hs, 3)[i];
-  }
-  ws[i] = p + e;
+  if (dep > 0) ws[i] = p + predict_increment(d, hs, stage, dep, i);
 }
 
 // after stage k's solve: its change from the starting vector, into this step's slot
@@ -975,18 +1071,50 @@ __device__ __forceinline__ void history_body(const TankDev& d, int stage, const 
   slot[i] = ws[i] - d.pv[i];
 }
 
+// Start of a single-tank Laplace solve, one pass: u = [0; phi~] (the lift's
+// input); the start vector xs = 0 at the surface and elsewhere the warm-start
+// vector ws (none: 0), plus the extrapolated change when stage >= 0 (ws
+// itself is kept as the stage's starting vector); the Krylov state reset
+// (init_ks).  Values as the separate passes give them.
 __global__ void __launch_bounds__(kBlockThreads)
-k_predict(const TankDev* __restrict__ td, int stage, int maxdepth, double dt, double* __restrict__ ws) {
+k_solve_begin(const TankDev* __restrict__ td, const double* __restrict__ phis, double* __restrict__ u,
+              const double* __restrict__ ws, int stage, int maxdepth, double dt, double rtol, int init_ks) {
   const TankDev& d = *td;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < d.n) predict_body(d, stage, maxdepth, dt, ws, i);
+  if (init_ks && i == 0) {
+    KrylovState k0{};
+    k0.rtol = rtol;
+    *d.ks = k0;
+  }
+  if (i >= d.n) return;
+  const int64_t sl = surface_slot(d, i);
+  u[i] = sl >= 0 ? phis[sl] : 0.0;
+  double g = 0.0;
+  if (ws) {
+    const double p = ws[i];
+    g = p;
+    if (stage >= 0) {
+      const StageHistory hs = *d.hs;
+      const int dep = predict_depth(hs, stage, maxdepth, dt);
+      d.pv[i] = p;
+      if (dep > 0) g = p + predict_increment(d, hs, stage, dep, i);
+    }
+  }
+  d.xs[i] = sl >= 0 ? 0.0 : g;
 }
 
+// End of a single-tank Laplace solve: Phi = xs with the surface values put
+// back; for a stage solve (stage >= 0) the change from the stage's starting
+// vector into this step's record.
 __global__ void __launch_bounds__(kBlockThreads)
-k_history(const TankDev* __restrict__ td, int stage, const double* __restrict__ ws) {
+k_solve_end(const TankDev* __restrict__ td, const double* __restrict__ phis, double* __restrict__ phi, int stage) {
   const TankDev& d = *td;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < d.n) history_body(d, stage, ws, i);
+  if (i >= d.n) return;
+  const int64_t sl = surface_slot(d, i);
+  const double v = sl >= 0 ? phis[sl] : d.xs[i];
+  phi[i] = v;
+  if (stage >= 0) const_cast<double*>(hist_slot(d, stage, *d.hs, 0))[i] = v - d.pv[i];
 }
 
 __global__ void __launch_bounds__(kBlockThreads)
@@ -1613,12 +1741,13 @@ void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hip
 void launch_fill(int64_t n, double v, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, v, y);
 }
-void launch_predict(const TankDev& h, const TankDev* d, int stage, int maxdepth, double dt, double* ws,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(k_predict, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, stage, maxdepth, dt, ws);
+void launch_solve_begin(const TankDev& h, const TankDev* d, const double* phis, double* u, const double* ws,
+                        int stage, int maxdepth, double dt, double rtol, int init_ks, hipStream_t st) {
+  hipLaunchKernelGGL(k_solve_begin, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, phis, u, ws, stage, maxdepth, dt,
+                     rtol, init_ks);
 }
-void launch_history(const TankDev& h, const TankDev* d, int stage, const double* ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_history, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, stage, ws);
+void launch_solve_end(const TankDev& h, const TankDev* d, const double* phis, double* phi, int stage, hipStream_t st) {
+  hipLaunchKernelGGL(k_solve_end, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, phis, phi, stage);
 }
 void launch_mask_surface(const TankDev& h, const TankDev* d, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_mask_surface, dim3(nblk(h.n)), dim3(kBlockThreads), 0, st, d, y);
@@ -1669,6 +1798,26 @@ static void orth_t(int64_t n, int j, const T* V, double* H, int m, T* w, double*
   hipLaunchKernelGGL(k_orth_fused<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, H, m, w, part, ldp, chunk, ks,
                      counter, status, mirror);
 }
+template <typename T>
+static void arnoldi_orth_t(int64_t n, int j, const T* V, double* H, int m, T* w, double* part, int ldp,
+                           KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const T* side,
+                           hipStream_t st) {
+  int nc;
+  int64_t chunk;
+  dot_layout(n, &nc, &chunk);
+  hipLaunchKernelGGL(k_arnoldi_orth<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, H, m, w, part, ldp, chunk, ks,
+                     &ks->pad[0], &ks->pad[1], status, mirror, fixd, side);
+}
+void launch_arnoldi_orth(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
+                         KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const double* side,
+                         hipStream_t st) {
+  arnoldi_orth_t<double>(n, j, V, H, m, w, part, ldp, ks, status, mirror, fixd, side, st);
+}
+void launch_arnoldi_orth(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
+                         KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const float* side,
+                         hipStream_t st) {
+  arnoldi_orth_t<float>(n, j, V, H, m, w, part, ldp, ks, status, mirror, fixd, side, st);
+}
 void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
                         KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st) {
   orth_t<double>(n, j, V, H, m, w, part, ldp, ks, counter, status, mirror, st);
@@ -1705,6 +1854,14 @@ void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int
                         int64_t n, float* V, int32_t* mirror, hipStream_t st) {
   hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status, mirror);
   hipLaunchKernelGGL(k_scale_v0<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, V, ks);
+}
+void launch_residual_fix(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y,
+                         const double* side, double* r, int mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_fix<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, d, n, b, y, side, r, mask);
+}
+void launch_residual_fix(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y,
+                         const float* side, float* r, int mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_fix<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, d, n, b, y, side, r, mask);
 }
 void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
                      int mask, hipStream_t st) {

@@ -58,6 +58,13 @@ void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double
 void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
                  double* out, int32_t* counter, const KrylovState* gate, hipStream_t st,
                  const TankDev* fixd = nullptr, const float* side = nullptr);
+// h = V^T w, w' = w - V h, ||w'||, Givens: one launch (a bounded in-kernel wait)
+void launch_arnoldi_orth(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
+                         KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const double* side,
+                         hipStream_t st);
+void launch_arnoldi_orth(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
+                         KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const float* side,
+                         hipStream_t st);
 void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
                         KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st);
 void launch_orth_givens(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
@@ -85,9 +92,13 @@ void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const 
 void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,
                       const double* ke, const double* kp, double* ye, double* yp, double* acce, double* accp,
                       hipStream_t st);
-void launch_predict(const TankDev& h, const TankDev* d, int stage, int maxdepth, double dt, double* ws,
-                    hipStream_t st);
-void launch_history(const TankDev& h, const TankDev* d, int stage, const double* ws, hipStream_t st);
+void launch_solve_begin(const TankDev& h, const TankDev* d, const double* phis, double* u, const double* ws,
+                        int stage, int maxdepth, double dt, double rtol, int init_ks, hipStream_t st);
+void launch_solve_end(const TankDev& h, const TankDev* d, const double* phis, double* phi, int stage, hipStream_t st);
+void launch_residual_fix(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y,
+                         const double* side, double* r, int mask, hipStream_t st);
+void launch_residual_fix(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y,
+                         const float* side, float* r, int mask, hipStream_t st);
 void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const double* acce, const double* accp,
                       double* eta, double* phi, int use_filter, hipStream_t st);
 

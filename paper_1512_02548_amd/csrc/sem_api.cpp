@@ -1211,6 +1211,7 @@ sem_status sem::status_from_word(int32_t w) {
   if (w & ST_DOMAIN) return SEM_E_DOMAIN;
   if (w & ST_BREAKDOWN) return SEM_E_BREAKDOWN;
   if (w & ST_NOCONV) return SEM_E_NOCONV;
+  if (w & ST_STALLED) return SEM_E_DEVICE;
   return SEM_OK;
 }
 
@@ -1231,6 +1232,7 @@ struct GmresCfg {
   int max_iter;
   int ahead;   // Krylov steps queued ahead of the device
   int gstore;   // FP32 path: 1 = FP32 factors, 2 = bfloat16 factors
+  int ks_ready;   // the Krylov state was reset by the solve's first kernel
 };
 
 struct KrylovBuf {
@@ -1326,7 +1328,7 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
   M->kt_used = 0;
   KrylovState ks0{};
   ks0.rtol = cfg.rtol;
-  HIPCHK(hipMemcpyAsync(h.ks, &ks0, sizeof(ks0), hipMemcpyHostToDevice, st));
+  if (!cfg.ks_ready) HIPCHK(hipMemcpyAsync(h.ks, &ks0, sizeof(ks0), hipMemcpyHostToDevice, st));
   int32_t* cnt = &h.ks->pad[0];
   launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, cnt, nullptr, st);
   int total = 0;
@@ -1334,18 +1336,21 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
   bool first = true;
   while (true) {
     *prog = 0;
-    // r = b - A x
+    // r = b - A x (the operator's shared-line fix-up folded into the residual)
     {
-      sem_status e = stiff_timed(M, cfg, x, B.w, B.side, flags, st);
+      sem_status e = stiff_timed(M, cfg, x, B.w, B.side, flags | F_NOFIX, st);
       if (e) return e;
     }
-    launch_residual(h, d, n, b, B.w, B.V, cfg.mask ? 1 : 0, st);
+    launch_residual_fix(h, d, n, b, B.w, B.side, B.V, cfg.mask ? 1 : 0, st);
     launch_dots(n, 1, B.V, 0, B.V, h.part, ldp, scal + 0, cnt, nullptr, st);
     launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, B.V, M->prog_dev, st);
     first = false;
+    int32_t seen = 0;   // the progress word that ended the cycle
     // with the exact still-water inverse, V_j = w / h_{j,j-1} is formed while
     // the preconditioner reads w (no separate scaling launch)
     const bool fused = cfg.pre == OP_PRE_LAP && h.pre_kind == 1;
+  // small tanks: h = V^T w and the orthogonalisation in one launch
+  const bool fused_orth = dot_nchunk(n) <= kFusedOrthMaxBlocks && !in_concurrent_batch;
     const double* hnorm = h.H + (size_t)(m + 1) * m + 2 * m + (m + 1);   // norms of V_1.. (scratch of the Givens update)
     for (int j = 0; j < m && total + j < cfg.max_iter; ++j) {
       T* Vj = B.V + (size_t)j * n;
@@ -1357,9 +1362,13 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
         sem_status e = stiff_timed(M, cfg, Zj, B.w, B.side, gflags | F_NOFIX, st);
         if (e) return e;
       }
-      double* Hcol = h.H + (size_t)j * (m + 1);
-      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st, d, B.side);
-      launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
+      if (fused_orth) {
+        launch_arnoldi_orth(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, h.status, M->prog_dev, d, B.side, st);
+      } else {
+        double* Hcol = h.H + (size_t)j * (m + 1);
+        launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st, d, B.side);
+        launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
+      }
       if (!fused) launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
       // wait while the device is more than `ahead` steps behind: spin on the
       // progress word; ask the runtime whether the queue drained only every
@@ -1370,6 +1379,7 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
         int32_t v = *prog;
         if (v & PROG_DONE) {
           stop = true;
+          seen = v;
           break;
         }
         if (j + 1 - (v & PROG_STEPS) <= ahead) break;
@@ -1378,7 +1388,8 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
           tq = now;
           hipError_t q = hipStreamQuery(st);
           if (q == hipSuccess) {
-            stop = (*prog & PROG_DONE) != 0;
+            seen = *prog;
+            stop = (seen & PROG_DONE) != 0;
             break;
           }
           if (q != hipErrorNotReady) HIPCHK(q);
@@ -1388,6 +1399,19 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       if (stop) break;
     }
     launch_solve_update(n, B.Z, h.H, m, h.ks, x, st);
+    if ((seen & PROG_CONV) && !M->kt_on) {
+      // converged: the progress block carries the final scalars (released
+      // with the word), so no readback; the caller's synchronisation at the
+      // end of the solve covers the queued update
+      const volatile double* sc = reinterpret_cast<const volatile double*>(M->prog_host) + 1;
+      hks = KrylovState{};
+      hks.resid = sc[0];
+      hks.bnorm = sc[1];
+      hks.iters = (int32_t)sc[2];
+      hks.j = seen & PROG_STEPS;
+      hks.done = hks.converged = 1;
+      break;
+    }
     HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     {
@@ -1419,6 +1443,8 @@ static KrylovBuf buf64(sem_mesh* M) { return KrylovBuf{M->hd.V, M->hd.Zb, M->hd.
 static KrylovBufF buf32(sem_mesh* M) {
   return KrylovBufF{M->hd.V32, M->hd.Z32, M->hd.w32, reinterpret_cast<float*>(M->hd.side)};
 }
+
+thread_local bool sem::in_concurrent_batch = false;
 
 void sem::default_opts(sem_solve_opts* o) {
   o->rtol = 1e-12;
@@ -1566,21 +1592,17 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   const TankDev* d = M->dtank;
   const int64_t n = M->n;
   auto t0 = std::chrono::steady_clock::now();
-  if (pred) launch_predict(h, d, pred->stage, pred->depth, pred->dt, phi, st);
-  // b = -(A [0; phi~])_F
-  launch_scatter_surface(h, d, phi_s, h.tmp, 1, st);
+  const bool fp64 = o->prec == SEM_PREC_FP64;
+  // u = [0; phi~], the start vector xs (warm start, stage predictor), the
+  // Krylov state; then b = -(A u)_F
+  launch_solve_begin(h, d, phi_s, h.tmp, o->warm_start ? phi : nullptr, pred ? pred->stage : -1,
+                     pred ? pred->depth : 0, pred ? pred->dt : 0.0, o->rtol, fp64 ? 1 : 0, st);
   launch_gather(h, d, OP_STIFF, h.tmp, h.b, h.side, F_MASK_SURF | F_NEG, st);
-  if (o->warm_start) {
-    HIPCHK(hipMemcpyAsync(h.xs, phi, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    launch_mask_surface(h, d, h.xs, st);
-  } else {
-    launch_fill(n, 0.0, h.xs, st);
-  }
   int iters = 0, refinements = 0;
   double rel = 0;
   sem_status s = SEM_OK;
-  if (o->prec == SEM_PREC_FP64) {
-    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->rtol, o->max_iter, o->lookahead, 0};
+  if (fp64) {
+    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->rtol, o->max_iter, o->lookahead, 0, 1};
     s = gmres(M, cfg, buf64(M), h.xs, h.b, &iters, &rel, st);
   } else {
     const int ldp = M->m + 2;
@@ -1628,10 +1650,8 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
     }
   }
   if (s == SEM_E_NOCONV) set_status_bits(M, ST_NOCONV, st);
-  // Phi = x_F + lift
-  HIPCHK(hipMemcpyAsync(phi, h.xs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  launch_scatter_surface(h, d, phi_s, phi, 0, st);
-  if (pred) launch_history(h, d, pred->stage, phi, st);
+  // Phi = x_F + lift; a stage solve's change into the record
+  launch_solve_end(h, d, phi_s, phi, pred ? pred->stage : -1, st);
   HIPCHK(hipStreamSynchronize(st));
   if (stats) {
     stats->iters = iters;
