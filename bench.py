@@ -266,8 +266,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rtol", type=float, default=1e-12)
-    ap.add_argument("--predict", type=int, default=3,
-                    help="past steps extrapolated into each stage solve's start vector (0..3)")
+    ap.add_argument("--predict", type=int, default=5,
+                    help="past steps extrapolated into each stage solve's start vector (0..6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-large", action="store_true", help="skip the 2048x8 bar-tank section")

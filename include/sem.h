@@ -107,7 +107,7 @@ typedef struct {
   int32_t max_refine;   /* IR: maximum outer refinements                           */
   int32_t warm_start;   /* 1: phi holds the initial guess on entry                 */
   int32_t lookahead;    /* Krylov steps the host may queue ahead of the device (>=1) */
-  int32_t predict;      /* RK4 steps only: 0..3 past steps extrapolated into each
+  int32_t predict;      /* RK4 steps only: 0..6 past steps extrapolated into each
                            stage solve's start vector (0: the previous stage's Phi) */
 } sem_solve_opts;
 
@@ -184,7 +184,7 @@ sem_status sem_free_surface_rhs(sem_mesh* mesh, const double* eta, const double*
  * Stage start vectors: each stage solve starts from the previous stage's
  * Phi (in phi_ws) plus the change from the previous stage to this one,
  * extrapolated over the same stage of the last opts->predict completed steps
- * of this mesh (linear, quadratic or cubic in the step index).  The mesh's
+ * of this mesh (a polynomial in the step index of that degree).  The mesh's
  * workspace keeps that record; it restarts when dt changes and after
  * sem_rk4_reset_history.  The start vector never changes the stopping test,
  * only the iteration count. */

@@ -507,7 +507,7 @@ static sem_status check_opts(const sem_solve_opts* opts, sem_solve_opts* o) {
   if (o->prec < 0 || o->prec > 2) return fail(SEM_E_INVAL, "unknown precision");
   if (o->prec != SEM_PREC_FP64 && !(o->inner_rtol > 0 && o->inner_rtol < 1))
     return fail(SEM_E_INVAL, "inner_rtol must lie in (0, 1)");
-  if (o->predict < 0 || o->predict > kHistSteps) return fail(SEM_E_INVAL, "predict must be in 0..3");
+  if (o->predict < 0 || o->predict > kHistSteps) return fail(SEM_E_INVAL, "predict must be in 0..6");
   return SEM_OK;
 }
 

@@ -1032,11 +1032,11 @@ k_solution_out_b(BatchArgs ba, const double* const* __restrict__ phis, double* c
 // Initial guess of RK4 stage k's Laplace solve.  The solve starts from the
 // previous stage's solution p; the guess adds the change from the previous
 // stage to stage k, extrapolated over the last steps (the same stage of
-// steps n-1, n-2, n-3: D1, D2, D3) by the polynomial of the available
-// depth: D1, 2 D1 - D2, or 3 D1 - 3 D2 + D3.  Stage 0's change in a step
-// needs the last stage of the step before, so its record starts one step
-// later.  Only the starting vector changes; the solve's stopping test does
-// not.
+// steps n-1, n-2, ...: D1, D2, ...) by the polynomial through the available
+// depth q: sum_m (-1)^(m+1) C(q, m) D_m (D1; 2 D1 - D2; 3 D1 - 3 D2 + D3;
+// ...).  Stage 0's change in a step needs the last stage of the step before,
+// so its record starts one step later.  Only the starting vector changes;
+// the solve's stopping test does not.
 __device__ inline int predict_depth(const StageHistory& hs, int stage, int maxdepth, double dt) {
   if (hs.dt != dt) return 0;
   const int dep = stage == 0 ? hs.valid - 1 : hs.valid;
@@ -1048,12 +1048,21 @@ __device__ inline const double* hist_slot(const TankDev& d, int stage, const Sta
   return d.hist + ((size_t)stage * kHistSteps + (size_t)r) * d.n;
 }
 
-// the extrapolated change at node i for depth dep >= 1
+// the extrapolated change at node i for depth dep >= 1 (terms added in the
+// order m = 1, 2, ...; the records are loaded together)
 __device__ inline double predict_increment(const TankDev& d, const StageHistory& hs, int stage, int dep, int64_t i) {
-  const double d1 = hist_slot(d, stage, hs, 1)[i];
-  if (dep == 1) return d1;
-  const double d2 = hist_slot(d, stage, hs, 2)[i];
-  return dep == 2 ? 2.0 * d1 - d2 : (3.0 * d1 - 3.0 * d2) + hist_slot(d, stage, hs, 3)[i];
+  // signed binomial weights (-1)^(m+1) C(q, m), row q - 1
+  constexpr double kW[kHistSteps][kHistSteps] = {{1, 0, 0, 0, 0, 0},         {2, -1, 0, 0, 0, 0},
+                                                  {3, -3, 1, 0, 0, 0},        {4, -6, 4, -1, 0, 0},
+                                                  {5, -10, 10, -5, 1, 0},     {6, -15, 20, -15, 6, -1}};
+  double dm[kHistSteps];
+#pragma unroll
+  for (int m = 0; m < kHistSteps; ++m) dm[m] = m < dep ? hist_slot(d, stage, hs, m + 1)[i] : 0.0;
+  double e = dm[0] * kW[dep - 1][0];
+#pragma unroll
+  for (int m = 1; m < kHistSteps; ++m)
+    if (m < dep) e += kW[dep - 1][m] * dm[m];
+  return e;
 }
 
 __device__ __forceinline__ void predict_body(const TankDev& d, int stage, int maxdepth, double dt,

@@ -1454,7 +1454,7 @@ void sem::default_opts(sem_solve_opts* o) {
   o->max_refine = 30;
   o->warm_start = 0;
   o->lookahead = 2;
-  o->predict = 3;
+  o->predict = 5;
 }
 
 // ------------------------------------------------------------ public calls
@@ -1751,7 +1751,7 @@ extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, doub
   sem_solve_opts o;
   if (opts) o = *opts;
   else default_opts(&o);
-  if (o.predict < 0 || o.predict > kHistSteps) return fail(SEM_E_INVAL, "predict must be in 0..3");
+  if (o.predict < 0 || o.predict > kHistSteps) return fail(SEM_E_INVAL, "predict must be in 0..6");
   hipStream_t st = (hipStream_t)stream;
   const TankDev& h = M->hd;
   const TankDev* d = M->dtank;

@@ -55,7 +55,7 @@ struct StageHistory {
   int32_t valid;
   double dt;
 };
-constexpr int kHistSteps = 3;       // past steps kept per stage
+constexpr int kHistSteps = 6;       // past steps kept per stage
 
 struct KrylovState {
   double bnorm;       // ||b||

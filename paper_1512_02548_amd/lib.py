@@ -125,7 +125,7 @@ def _stream(stream=None):
 
 
 def default_opts(rtol=1e-12, max_iter=5000, prec=SEM_PREC_FP64, inner_rtol=1e-4, max_refine=30,
-                 warm_start=0, lookahead=2, predict=3):
+                 warm_start=0, lookahead=2, predict=5):
     return sem_solve_opts(rtol, max_iter, prec, inner_rtol, max_refine, warm_start, lookahead, predict)
 
 

@@ -113,9 +113,9 @@ def test_lockstep_laplace_equals_single(prec, rtol):
 def test_lockstep_rk4_equals_single(prec):
     import torch
     from paper_1512_02548_amd import lib
-    opts = lib.default_opts(rtol=1e-10, warm_start=1, prec=prec, inner_rtol=1e-2)
+    opts = lib.default_opts(rtol=1e-10, warm_start=1, prec=prec, inner_rtol=1e-2, predict=6)
     specs = mixed_specs()[:5]
-    steps = 5                       # the stage predictor reaches its full depth
+    steps = 8                       # the stage predictor reaches its full depth
     alone = []
     for s in specs:
         t = make_tank(s)
