@@ -491,6 +491,26 @@ __device__ __forceinline__ void dots_partial(int64_t n, int nvec, const T* __res
     part[(size_t)bx * ldp + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
 }
 
+// Workgroup bx's part of sum_i v_i^2 over its chunk for values the caller
+// forms per node (value(i), which may also store them), in the order of
+// dots_partial with X = w: thread-strided sums, wave butterflies, the four
+// wave totals in order.
+template <typename F>
+__device__ __forceinline__ void self_dot_partial(int64_t n, int64_t chunk, int bx, double* __restrict__ part, int ldp,
+                                                 F value) {
+  __shared__ double red[4];
+  const int64_t lo = (int64_t)bx * chunk, hi = min(lo + chunk, n);
+  double sacc = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const double v = value(i);
+    sacc += v * v;
+  }
+  sacc = wave_sum(sacc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sacc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)bx * ldp] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 // final sums of nblk partials: wave w takes vectors w, w+4, ...; lanes stride
 // over the workgroup partials in a fixed order, then a butterfly
 __device__ __forceinline__ void dots_reduce(int nvec, const double* __restrict__ part, int ldp,
@@ -685,50 +705,9 @@ __global__ void k_scale_next(int64_t n, int j, const T* __restrict__ w, T* __res
   if (j + 1 < m + 1) V[(int64_t)(j + 1) * n + i] = (hn > 0.0) ? T(wi / hn) : T(0);
 }
 
-// solve the triangular system for y (single thread) then x += Z y (all threads)
-__global__ void k_solve_y(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int jn = ks->j;
-  double* H = Hbase;
-  double* g = Hbase + (m + 1) * m + 2 * m;
-  double* y = g + (m + 1) + m;     // after the norm scratch
-  for (int i = jn - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int k = i + 1; k < jn; ++k) s -= H[(size_t)k * (m + 1) + i] * y[k];
-    y[i] = s / H[(size_t)i * (m + 1) + i];
-  }
-}
-
-template <typename T>
-__global__ void k_update_x(int64_t n, const T* __restrict__ Z, const double* __restrict__ Hbase,
-                           int m, const KrylovState* __restrict__ ks, T* __restrict__ x) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double* g = Hbase + (m + 1) * m + 2 * m;
-  const double* y = g + (m + 1) + m;
-  int jn = ks->j;
-  double v = x[i];
-  for (int k0 = 0; k0 < jn; k0 += 8) {
-    T zz[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) zz[u] = Z[(int64_t)min(k0 + u, jn - 1) * n + i];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (k0 + u < jn) v += y[k0 + u] * (double)zz[u];
-  }
-  x[i] = T(v);
-}
-
 // start of a cycle: r is in V_0 (masked); beta = sqrt(rr); V_0 = r/beta; g = (beta, 0, ...)
 __device__ void cycle_start(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
                             const double* __restrict__ rr, int first, int32_t* __restrict__ status);
-__global__ void k_cycle_start(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
-                              const double* __restrict__ rr, int first, int32_t* __restrict__ status,
-                              int32_t* __restrict__ mirror) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  cycle_start(ks, Hbase, m, rr, first, status);
-  publish_progress(ks, mirror, progress_scalars(mirror));
-}
 
 __device__ void cycle_start(KrylovState* __restrict__ ks, double* __restrict__ Hbase, int m,
                             const double* __restrict__ rr, int first, int32_t* __restrict__ status) {
@@ -793,16 +772,81 @@ __device__ inline T fixed_value(const TankDev& d, const T* __restrict__ y, const
   return v;
 }
 
-// r = b - y with y's fix-up folded in (masked at the surface)
-template <typename T>
-__global__ void k_residual_fix(const TankDev* __restrict__ td, int64_t n, const T* __restrict__ bvec,
-                               const T* __restrict__ y, const T* __restrict__ side, T* __restrict__ r, int mask) {
+// b's shared-line fix-up and ||b||^2 in one launch (out = ||b||^2): the
+// values of the fix-up pass followed by the fused inner product
+__global__ void __launch_bounds__(kBlockThreads)
+k_fix_norm(const TankDev* __restrict__ td, int64_t n, double* __restrict__ b, const double* __restrict__ side,
+           double* __restrict__ part, int ldp, double* __restrict__ out, int64_t chunk, int32_t* __restrict__ counter) {
   const TankDev& d = *td;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  self_dot_partial(n, chunk, blockIdx.x, part, ldp, [&](int64_t i) {
+    const double v = fixed_value<double>(d, b, side, i);
+    b[i] = v;
+    return v;
+  });
+  if (!last_block(counter, gridDim.x)) return;
+  dots_reduce(1, part, ldp, out, gridDim.x);
+  if (threadIdx.x == 0) *counter = 0;
+}
+
+// Start of a Krylov cycle in one launch: r = b - y (y's fix-up folded in,
+// masked at the surface) into V_0, ||r||^2 into rr[0], and in the last
+// workgroup the cycle start (beta, the Givens right side, convergence at
+// once) and its progress word.  The values of the separate residual, inner
+// product and cycle-start kernels.
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_residual_cycle(const TankDev* __restrict__ td, int64_t n, const T* __restrict__ bvec, const T* __restrict__ y,
+                 const T* __restrict__ side, T* __restrict__ r, int mask, double* __restrict__ part, int ldp,
+                 double* __restrict__ rr, int64_t chunk, int32_t* __restrict__ counter, KrylovState* __restrict__ ks,
+                 double* __restrict__ Hbase, int m, int first, int32_t* __restrict__ status,
+                 int32_t* __restrict__ mirror) {
+  const TankDev& d = *td;
+  self_dot_partial(n, chunk, blockIdx.x, part, ldp, [&](int64_t i) {
+    T v = bvec[i] - fixed_value<T>(d, y, side, i);
+    if (mask && is_surface_node(d, i)) v = T(0);
+    r[i] = v;
+    return (double)v;
+  });
+  if (!last_block(counter, gridDim.x)) return;
+  dots_reduce(1, part, ldp, rr, gridDim.x);
+  if (threadIdx.x == 0) {
+    *counter = 0;
+    cycle_start(ks, Hbase, m, rr, first, status);
+    publish_progress(ks, mirror, progress_scalars(mirror));
+  }
+}
+
+// End of a Krylov cycle in one launch: every workgroup solves the small
+// triangular system for y (one thread, the order of the separate solve) and
+// then updates its part of x += Z y.
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads)
+k_solve_update(int64_t n, const T* __restrict__ Z, const double* __restrict__ Hbase, int m,
+               const KrylovState* __restrict__ ks, T* __restrict__ x) {
+  __shared__ double ys[kMaxRestart];
+  const int jn = ks->j;
+  if (threadIdx.x == 0) {
+    const double* H = Hbase;
+    const double* g = Hbase + (m + 1) * m + 2 * m;
+    for (int i = jn - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int k = i + 1; k < jn; ++k) sacc -= H[(size_t)k * (m + 1) + i] * ys[k];
+      ys[i] = sacc / H[(size_t)i * (m + 1) + i];
+    }
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  T v = bvec[i] - fixed_value<T>(d, y, side, i);
-  if (mask && is_surface_node(d, i)) v = T(0);
-  r[i] = v;
+  double v = x[i];
+  for (int k0 = 0; k0 < jn; k0 += 8) {
+    T zz[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) zz[u] = Z[(int64_t)min(k0 + u, jn - 1) * n + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < jn) v += ys[k0 + u] * (double)zz[u];
+  }
+  x[i] = T(v);
 }
 
 // r32 = (float)(r * scale)
@@ -1844,33 +1888,43 @@ void launch_scale_next(int64_t n, int j, const float* w, float* V, const double*
                        const KrylovState* ks, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_next<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, j, w, V, H, m, ks);
 }
-void launch_solve_update(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, ks, H, m);
-  hipLaunchKernelGGL(k_update_x<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
+void launch_solve_update_fused(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_solve_update<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
 }
-void launch_solve_update(int64_t n, const float* Z, double* H, int m, KrylovState* ks, float* x,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, ks, H, m);
-  hipLaunchKernelGGL(k_update_x<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
+void launch_solve_update_fused(int64_t n, const float* Z, double* H, int m, KrylovState* ks, float* x,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_solve_update<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
 }
-void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status,
-                        int64_t n, double* V, int32_t* mirror, hipStream_t st) {
-  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status, mirror);
-  hipLaunchKernelGGL(k_scale_v0<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, V, ks);
+void launch_fix_norm(const TankDev& h, const TankDev* d, int64_t n, double* b, const double* side, double* part,
+                     int ldp, double* out, int32_t* counter, hipStream_t st) {
+  int nc;
+  int64_t chunk;
+  dot_layout(n, &nc, &chunk);
+  hipLaunchKernelGGL(k_fix_norm, dim3(nc), dim3(kBlockThreads), 0, st, d, n, b, side, part, ldp, out, chunk, counter);
 }
-void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status,
-                        int64_t n, float* V, int32_t* mirror, hipStream_t st) {
-  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, ks, H, m, rr, first, status, mirror);
-  hipLaunchKernelGGL(k_scale_v0<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, V, ks);
+template <typename T>
+static void residual_cycle_t(const TankDev* d, int64_t n, const T* b, const T* y, const T* side, T* r, int mask,
+                             double* part, int ldp, double* rr, int32_t* counter, KrylovState* ks, double* H, int m,
+                             int first, int32_t* status, int32_t* mirror, hipStream_t st) {
+  int nc;
+  int64_t chunk;
+  dot_layout(n, &nc, &chunk);
+  hipLaunchKernelGGL(k_residual_cycle<T>, dim3(nc), dim3(kBlockThreads), 0, st, d, n, b, y, side, r, mask, part, ldp,
+                     rr, chunk, counter, ks, H, m, first, status, mirror);
+  hipLaunchKernelGGL(k_scale_v0<T>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, r, ks);
 }
-void launch_residual_fix(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y,
-                         const double* side, double* r, int mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual_fix<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, d, n, b, y, side, r, mask);
+void launch_residual_cycle(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y,
+                           const double* side, double* r, int mask, double* part, int ldp, double* rr,
+                           int32_t* counter, KrylovState* ks, double* H, int m, int first, int32_t* status,
+                           int32_t* mirror, hipStream_t st) {
+  residual_cycle_t<double>(d, n, b, y, side, r, mask, part, ldp, rr, counter, ks, H, m, first, status, mirror, st);
 }
-void launch_residual_fix(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y,
-                         const float* side, float* r, int mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual_fix<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, d, n, b, y, side, r, mask);
+void launch_residual_cycle(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y,
+                           const float* side, float* r, int mask, double* part, int ldp, double* rr,
+                           int32_t* counter, KrylovState* ks, double* H, int m, int first, int32_t* status,
+                           int32_t* mirror, hipStream_t st) {
+  residual_cycle_t<float>(d, n, b, y, side, r, mask, part, ldp, rr, counter, ks, H, m, first, status, mirror, st);
 }
 void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
                      int mask, hipStream_t st) {

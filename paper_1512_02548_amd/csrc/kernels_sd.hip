@@ -81,6 +81,13 @@ __host__ __device__ inline SdShape sd_shape(int nx, int nMT) {
   return SdShape{1, 1};
 }
 constexpr int kNTMax = 4;    // N-tiles per wave at most
+// Small direct-transform tanks (nx <= 64, lines of at most 32 unknowns): the
+// back-substitution workgroups form the line values they need by the inverse
+// transform themselves (17 lines x 32 unknowns, one 16 x 16 tile per wave),
+// instead of a separate inverse-transform launch.
+__host__ __device__ inline bool sd_back_dft(int nx, int q, int fft_n1, int nMT3) {
+  return fft_n1 == 0 && nx <= 64 && q <= 32 && sd_shape(nx, nMT3).ntw == 1;
+}
 constexpr int kKC = 24;      // K-steps of the right-hand factor staged in LDS at a time (LDS < 64 KiB)
 // LDS of the condensation's staging area (and, split, of its wave partials),
 // before the interior index table
@@ -388,10 +395,43 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
   const int c0 = bx * ncol;
   const int mt = shp.split ? by : 4 * by + wv;
   const int s_first = shp.split ? wv : 0, s_step = shp.split ? kWaves : 1;
+  if (sd_back_dft(nx, q, sd.fft_n1, nMT)) {
+    // x_L,c = Re sum_k e^{2 pi i k c / nx} x^_k / nx for lines c0 .. c0 + 16:
+    // wave (line tile lt, unknown tile jt), the whole K range (modes x re/im)
+    // in order, operands loaded kD K-steps at a time
+    const int lt = wv >> 1, jt = wv & 1;
+    const int cr = (c0 + 16 * lt + col) % nx, pr = grp & 1, jb = 16 * jt + col;
+    const int KSd = (2 * nx + 3) / 4;
+    V4 acc = V4{0, 0, 0, 0};
+    constexpr int kD = 16;
+    // twiddle index (cr k) mod nx, k = 2 s + grp / 2: advances by 2 cr per K-step
+    const int step = (2 * cr) % nx;
+    int mm = (cr * (grp >> 1)) % nx;
+    for (int s0 = 0; s0 < KSd; s0 += kD) {
+      T av[kD], bv[kD];
+#pragma unroll
+      for (int u = 0; u < kD; ++u) {
+        const int k = 2 * (s0 + u) + (grp >> 1);
+        const bool kv = s0 + u < KSd && k < nx;
+        av[u] = kv ? T(d.twid[2 * mm + pr]) : T(0);
+        bv[u] = (kv && jb < q) ? T(sd.XH[((size_t)k * q + jb) * 2 + pr]) : T(0);
+        mm += step;
+        if (mm >= nx) mm -= nx;
+      }
+#pragma unroll
+      for (int u = 0; u < kD; ++u) acc = MF::op(av[u], bv[u], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int cc = 16 * lt + MF::row(v, grp);
+      if (cc <= ncol && jb < q) xl[cc * qp + jb] = (double)acc[v] / nx;
+    }
+  } else {
 #pragma unroll 4
-  for (int t = threadIdx.x; t < (ncol + 1) * q; t += blockDim.x) {
-    const int cc = t / q, j = t - cc * q;
-    xl[cc * qp + j] = sd.XL[(size_t)((c0 + cc) % nx) * q + j];
+    for (int t = threadIdx.x; t < (ncol + 1) * q; t += blockDim.x) {
+      const int cc = t / q, j = t - cc * q;
+      xl[cc * qp + j] = sd.XL[(size_t)((c0 + cc) % nx) * q + j];
+    }
   }
   __syncthreads();
   if (by == 0) {
@@ -981,7 +1021,7 @@ void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int
       add_grid(out->fd, t, sd.fft_n2, nnt, 0);
     } else {
       add_grid(out->modes, t, paired_blocks(h.nx, kModesPB / 2), 1, l.modes);
-      add_grid(out->idft, t, ct, (sd.q + 15) / 16, 0);
+      if (!sd_back_dft(h.nx, sd.q, sd.fft_n1, sd.nMT3)) add_grid(out->idft, t, ct, (sd.q + 15) / 16, 0);
     }
     if (sd.wall) {
       add_grid(out->wlines, t, 2 * sd.q, 1, 0);
@@ -1058,7 +1098,7 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
     const unsigned nnt = (unsigned)((sd.q + 15) / 16);
     hipLaunchKernelGGL(k_sdf_c<T>, dim3(n1, nnt), dim3(kBlockThreads), 0, st, d, which, gate);
     hipLaunchKernelGGL(k_sdf_d<T>, dim3(n2, nnt), dim3(kBlockThreads), 0, st, d, which, gate);
-  } else {
+  } else if (!sd_back_dft(h.nx, sd.q, sd.fft_n1, sd.nMT3)) {
     hipLaunchKernelGGL(k_sd_idft<T>, dim3(ct, (sd.q + 15) / 16), dim3(kBlockThreads), 0, st, d, which, gate);
   }
   hipLaunchKernelGGL(k_sd_back<T>, dim3(g.bx, g.by), dim3(kBlockThreads), lds.back, st, d, which, y, gate, vout);

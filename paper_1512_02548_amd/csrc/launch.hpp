@@ -73,12 +73,6 @@ void launch_scale_next(int64_t n, int j, const double* w, double* V, const doubl
                        hipStream_t st);
 void launch_scale_next(int64_t n, int j, const float* w, float* V, const double* H, int m, const KrylovState* ks,
                        hipStream_t st);
-void launch_solve_update(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x, hipStream_t st);
-void launch_solve_update(int64_t n, const float* Z, double* H, int m, KrylovState* ks, float* x, hipStream_t st);
-void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status, int64_t n,
-                        double* V, int32_t* mirror, hipStream_t st);
-void launch_cycle_start(KrylovState* ks, double* H, int m, const double* rr, int first, int32_t* status, int64_t n,
-                        float* V, int32_t* mirror, hipStream_t st);
 void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
                      int mask, hipStream_t st);
 void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y, float* r,
@@ -95,10 +89,23 @@ void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y
 void launch_solve_begin(const TankDev& h, const TankDev* d, const double* phis, double* u, const double* ws,
                         int stage, int maxdepth, double dt, double rtol, int init_ks, hipStream_t st);
 void launch_solve_end(const TankDev& h, const TankDev* d, const double* phis, double* phi, int stage, hipStream_t st);
-void launch_residual_fix(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y,
-                         const double* side, double* r, int mask, hipStream_t st);
-void launch_residual_fix(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y,
-                         const float* side, float* r, int mask, hipStream_t st);
+// b's fix-up and ||b||^2 (out) in one launch
+void launch_fix_norm(const TankDev& h, const TankDev* d, int64_t n, double* b, const double* side, double* part,
+                     int ldp, double* out, int32_t* counter, hipStream_t st);
+// r = b - y (fix-up folded in) into V_0, ||r||^2 into rr[0], the cycle start; then V_0 /= beta
+void launch_residual_cycle(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y,
+                           const double* side, double* r, int mask, double* part, int ldp, double* rr,
+                           int32_t* counter, KrylovState* ks, double* H, int m, int first, int32_t* status,
+                           int32_t* mirror, hipStream_t st);
+void launch_residual_cycle(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y,
+                           const float* side, float* r, int mask, double* part, int ldp, double* rr,
+                           int32_t* counter, KrylovState* ks, double* H, int m, int first, int32_t* status,
+                           int32_t* mirror, hipStream_t st);
+// y from the small triangular system and x += Z y, one launch
+void launch_solve_update_fused(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x,
+                               hipStream_t st);
+void launch_solve_update_fused(int64_t n, const float* Z, double* H, int m, KrylovState* ks, float* x,
+                               hipStream_t st);
 void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const double* acce, const double* accp,
                       double* eta, double* phi, int use_filter, hipStream_t st);
 

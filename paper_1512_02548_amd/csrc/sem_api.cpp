@@ -1233,6 +1233,7 @@ struct GmresCfg {
   int ahead;   // Krylov steps queued ahead of the device
   int gstore;   // FP32 path: 1 = FP32 factors, 2 = bfloat16 factors
   int ks_ready;   // the Krylov state was reset by the solve's first kernel
+  int bnorm_ready;   // ||b||^2 is already in scal[1] (b fixed up)
 };
 
 struct KrylovBuf {
@@ -1330,7 +1331,7 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
   ks0.rtol = cfg.rtol;
   if (!cfg.ks_ready) HIPCHK(hipMemcpyAsync(h.ks, &ks0, sizeof(ks0), hipMemcpyHostToDevice, st));
   int32_t* cnt = &h.ks->pad[0];
-  launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, cnt, nullptr, st);
+  if (!cfg.bnorm_ready) launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, cnt, nullptr, st);
   int total = 0;
   KrylovState hks{};
   bool first = true;
@@ -1341,9 +1342,8 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       sem_status e = stiff_timed(M, cfg, x, B.w, B.side, flags | F_NOFIX, st);
       if (e) return e;
     }
-    launch_residual_fix(h, d, n, b, B.w, B.side, B.V, cfg.mask ? 1 : 0, st);
-    launch_dots(n, 1, B.V, 0, B.V, h.part, ldp, scal + 0, cnt, nullptr, st);
-    launch_cycle_start(h.ks, h.H, m, scal, first ? 1 : 0, h.status, n, B.V, M->prog_dev, st);
+    launch_residual_cycle(h, d, n, b, B.w, B.side, B.V, cfg.mask ? 1 : 0, h.part, ldp, scal, cnt, h.ks, h.H, m,
+                          first ? 1 : 0, h.status, M->prog_dev, st);
     first = false;
     int32_t seen = 0;   // the progress word that ended the cycle
     // with the exact still-water inverse, V_j = w / h_{j,j-1} is formed while
@@ -1398,7 +1398,7 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       }
       if (stop) break;
     }
-    launch_solve_update(n, B.Z, h.H, m, h.ks, x, st);
+    launch_solve_update_fused(n, B.Z, h.H, m, h.ks, x, st);
     if ((seen & PROG_CONV) && !M->kt_on) {
       // converged: the progress block carries the final scalars (released
       // with the word), so no readback; the caller's synchronisation at the
@@ -1597,12 +1597,18 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   // Krylov state; then b = -(A u)_F
   launch_solve_begin(h, d, phi_s, h.tmp, o->warm_start ? phi : nullptr, pred ? pred->stage : -1,
                      pred ? pred->depth : 0, pred ? pred->dt : 0.0, o->rtol, fp64 ? 1 : 0, st);
-  launch_gather(h, d, OP_STIFF, h.tmp, h.b, h.side, F_MASK_SURF | F_NEG, st);
+  if (fp64) {
+    // the lift's shared-line fix-up and ||b||^2 in one launch
+    launch_gather(h, d, OP_STIFF, h.tmp, h.b, h.side, F_MASK_SURF | F_NEG | F_NOFIX, st);
+    launch_fix_norm(h, d, n, h.b, h.side, h.part, M->m + 2, M->scal + 1, &h.ks->pad[0], st);
+  } else {
+    launch_gather(h, d, OP_STIFF, h.tmp, h.b, h.side, F_MASK_SURF | F_NEG, st);
+  }
   int iters = 0, refinements = 0;
   double rel = 0;
   sem_status s = SEM_OK;
   if (fp64) {
-    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->rtol, o->max_iter, o->lookahead, 0, 1};
+    GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->rtol, o->max_iter, o->lookahead, 0, 1, 1};
     s = gmres(M, cfg, buf64(M), h.xs, h.b, &iters, &rel, st);
   } else {
     const int ldp = M->m + 2;
