@@ -155,11 +155,7 @@ sem_status sem_apply_timed(sem_mesh* mesh, sem_operator op, int32_t prec, const 
 /* Laplace problem of Sec. 3.1.2 for the surface state (eta, eta_x, phi~):
  * A_FF Phi_F = -A_FS phi~, Phi_S = phi~.  phi [n]: in = initial guess when
  * opts->warm_start, out = Phi including the surface values.  stats may be
- * NULL.  Tanks of up to 32768 unknowns run each Arnoldi step's
- * orthogonalisation as one launch of at most 64 workgroups that wait for
- * each other once; the wait is bounded, and one that runs out (the device
- * filled by other streams' waiting kernels) fails the solve with
- * SEM_E_DEVICE. */
+ * NULL. */
 sem_status sem_laplace_solve(sem_mesh* mesh, const double* eta, const double* eta_x,
                              const double* phi_s, double* phi, const sem_solve_opts* opts,
                              sem_solve_stats* stats, void* stream);

@@ -671,13 +671,11 @@ static sem_status concurrent_rk4(sem_batch* B, double* const* eta, double* const
   std::vector<sem_status> res(count, SEM_OK);
   std::vector<int32_t> its(count, 0);
   auto run = [&](int w) {
-    in_concurrent_batch = true;
     for (int i : work[w]) {
       sem_solve_stats st4[4] = {};
       res[i] = sem_rk4_step(B->meshes[i], eta[i], phi_s[i], phi_ws[i], dt[i], opts, st4, B->streams[w]);
       its[i] = st4[0].iters + st4[1].iters + st4[2].iters + st4[3].iters;
     }
-    in_concurrent_batch = false;
   };
   std::vector<std::thread> th;
   for (int w = 1; w < W; ++w) th.emplace_back(run, w);

@@ -595,59 +595,6 @@ k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hba
   orth_reduce(j, part, ldp, gridDim.x, ks, Hbase, m, status, mirror, progress_scalars(mirror));
 }
 
-// One Arnoldi step's orthogonalisation in one launch: h = V^T w (the
-// fix-up of w's shared lines folded in), then w' = w - V h, ||w'||^2 and the
-// Givens update, with the arithmetic of the two separate kernels.  The
-// workgroups meet once in between: the last to finish its inner products
-// adds the partials, writes h and advances the epoch word; the others wait
-// for the epoch.  The grid (at most 256 workgroups of 256 threads, little
-// LDS) is resident at once on an otherwise idle device; the wait is bounded,
-// and a wait that runs out marks the solve failed (ST_STALLED) and leaves
-// the kernel instead of waiting on.
-constexpr int kWaitPolls = 1 << 21;
-
-template <typename T>
-__global__ void __launch_bounds__(kBlockThreads)
-k_arnoldi_orth(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase, int m, T* __restrict__ w,
-               double* __restrict__ part, int ldp, int64_t chunk, KrylovState* __restrict__ ks,
-               int32_t* __restrict__ counter, int32_t* __restrict__ epoch, int32_t* __restrict__ status,
-               int32_t* __restrict__ mirror, const TankDev* __restrict__ fixd, const T* __restrict__ side) {
-  __shared__ int go;
-  if (ks->done) return;
-  const int32_t e0 = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  double* hcol = Hbase + (size_t)j * (m + 1);
-  dots_partial<T>(n, j + 1, V, n, w, part, ldp, chunk, fixd, side, blockIdx.x);
-  if (last_block(counter, gridDim.x)) {
-    dots_reduce(j + 1, part, ldp, hcol, gridDim.x);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      *counter = 0;
-      __threadfence();
-      __hip_atomic_store(epoch, e0 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else {
-    if (threadIdx.x == 0) {
-      int ok = 0;
-      for (int p = 0; p < kWaitPolls; ++p) {
-        if (__hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e0) {
-          ok = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-      if (!ok) atomicOr(status, ST_STALLED);
-      go = ok;
-    }
-    __syncthreads();
-    if (!go) return;
-    __threadfence();   // acquire: h as the last workgroup wrote it
-  }
-  orth_partial<T>(n, j, V, Hbase, m, w, part, ldp, chunk, blockIdx.x);
-  if (!last_block(counter, gridDim.x)) return;
-  if (threadIdx.x == 0) *counter = 0;
-  orth_reduce(j, part, ldp, gridDim.x, ks, Hbase, m, status, mirror, progress_scalars(mirror));
-}
-
 // ------------------------------------------------------------ GMRES pieces
 // Givens update of Hessenberg column j (one thread).  The column holds
 // h_{0..j}; hnorm2 = ||w'||^2.  Sets done/converged and the norm of V_{j+1}.
@@ -1850,26 +1797,6 @@ static void orth_t(int64_t n, int j, const T* V, double* H, int m, T* w, double*
   dot_layout(n, &nc, &chunk);
   hipLaunchKernelGGL(k_orth_fused<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, H, m, w, part, ldp, chunk, ks,
                      counter, status, mirror);
-}
-template <typename T>
-static void arnoldi_orth_t(int64_t n, int j, const T* V, double* H, int m, T* w, double* part, int ldp,
-                           KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const T* side,
-                           hipStream_t st) {
-  int nc;
-  int64_t chunk;
-  dot_layout(n, &nc, &chunk);
-  hipLaunchKernelGGL(k_arnoldi_orth<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, H, m, w, part, ldp, chunk, ks,
-                     &ks->pad[0], &ks->pad[1], status, mirror, fixd, side);
-}
-void launch_arnoldi_orth(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
-                         KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const double* side,
-                         hipStream_t st) {
-  arnoldi_orth_t<double>(n, j, V, H, m, w, part, ldp, ks, status, mirror, fixd, side, st);
-}
-void launch_arnoldi_orth(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
-                         KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const float* side,
-                         hipStream_t st) {
-  arnoldi_orth_t<float>(n, j, V, H, m, w, part, ldp, ks, status, mirror, fixd, side, st);
 }
 void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
                         KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st) {

@@ -8,6 +8,7 @@
 #include "sem_internal.hpp"
 
 namespace sem {
+
 enum { OP_STIFF = 0, OP_MASS = 1, OP_PRE_LAP = 2, OP_PRE_MASS = 3, OP_SZ = 4 };
 // gather flags: mask the surface rows, negate, skip the launch once the
 // tank's Krylov cycle is done (kernels queued ahead of a convergence test)
@@ -58,13 +59,6 @@ void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double
 void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
                  double* out, int32_t* counter, const KrylovState* gate, hipStream_t st,
                  const TankDev* fixd = nullptr, const float* side = nullptr);
-// h = V^T w, w' = w - V h, ||w'||, Givens: one launch (a bounded in-kernel wait)
-void launch_arnoldi_orth(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
-                         KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const double* side,
-                         hipStream_t st);
-void launch_arnoldi_orth(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
-                         KrylovState* ks, int32_t* status, int32_t* mirror, const TankDev* fixd, const float* side,
-                         hipStream_t st);
 void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
                         KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st);
 void launch_orth_givens(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,

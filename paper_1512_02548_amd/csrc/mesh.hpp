@@ -88,9 +88,5 @@ sem_status status_from_word(int32_t w);
 void default_opts(sem_solve_opts* o);
 // w~ from M w = S_z Phi with the factors 1/d current; out [ns]
 sem_status recover_w_core(sem_mesh* M, const double* Phi, double* out, hipStream_t st);
-// set on the worker threads of a concurrent batch: solves there keep the
-// two-launch orthogonalisation (no in-kernel wait while other streams fill the device)
-extern thread_local bool in_concurrent_batch;
-// the one-launch orthogonalisation (in-kernel wait) is used up to this many workgroups
-constexpr int kFusedOrthMaxBlocks = 64;
+
 }  // namespace sem

@@ -1211,7 +1211,6 @@ sem_status sem::status_from_word(int32_t w) {
   if (w & ST_DOMAIN) return SEM_E_DOMAIN;
   if (w & ST_BREAKDOWN) return SEM_E_BREAKDOWN;
   if (w & ST_NOCONV) return SEM_E_NOCONV;
-  if (w & ST_STALLED) return SEM_E_DEVICE;
   return SEM_OK;
 }
 
@@ -1349,8 +1348,6 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
     // with the exact still-water inverse, V_j = w / h_{j,j-1} is formed while
     // the preconditioner reads w (no separate scaling launch)
     const bool fused = cfg.pre == OP_PRE_LAP && h.pre_kind == 1;
-  // small tanks: h = V^T w and the orthogonalisation in one launch
-  const bool fused_orth = dot_nchunk(n) <= kFusedOrthMaxBlocks && !in_concurrent_batch;
     const double* hnorm = h.H + (size_t)(m + 1) * m + 2 * m + (m + 1);   // norms of V_1.. (scratch of the Givens update)
     for (int j = 0; j < m && total + j < cfg.max_iter; ++j) {
       T* Vj = B.V + (size_t)j * n;
@@ -1362,13 +1359,9 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
         sem_status e = stiff_timed(M, cfg, Zj, B.w, B.side, gflags | F_NOFIX, st);
         if (e) return e;
       }
-      if (fused_orth) {
-        launch_arnoldi_orth(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, h.status, M->prog_dev, d, B.side, st);
-      } else {
-        double* Hcol = h.H + (size_t)j * (m + 1);
-        launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st, d, B.side);
-        launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
-      }
+      double* Hcol = h.H + (size_t)j * (m + 1);
+      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st, d, B.side);
+      launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
       if (!fused) launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
       // wait while the device is more than `ahead` steps behind: spin on the
       // progress word; ask the runtime whether the queue drained only every
@@ -1443,8 +1436,6 @@ static KrylovBuf buf64(sem_mesh* M) { return KrylovBuf{M->hd.V, M->hd.Zb, M->hd.
 static KrylovBufF buf32(sem_mesh* M) {
   return KrylovBufF{M->hd.V32, M->hd.Z32, M->hd.w32, reinterpret_cast<float*>(M->hd.side)};
 }
-
-thread_local bool sem::in_concurrent_batch = false;
 
 void sem::default_opts(sem_solve_opts* o) {
   o->rtol = 1e-12;

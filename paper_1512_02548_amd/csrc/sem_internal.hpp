@@ -42,7 +42,6 @@ enum : int32_t {
   ST_NOCONV = 2,
   ST_BREAKDOWN = 4,
   ST_NONFINITE = 8,
-  ST_STALLED = 16,    // a bounded wait inside a kernel ran out (workgroups not all resident)
 };
 
 // Krylov state of one solve, resident in the workspace.
