@@ -438,6 +438,23 @@ __device__ inline bool last_block(int32_t* counter, int nblk) {
   return is_last != 0;
 }
 
+// y[i] of an element-kernel output with its shared-line contribution from
+// the side buffer added (the fix-up pass, done by the consumer; the same
+// addition as the separate pass)
+template <typename T>
+__device__ inline T fixed_value(const TankDev& d, const T* __restrict__ y, const T* __restrict__ side, int64_t i) {
+  const int64_t c = i / d.nc;
+  const int ql = (int)(i - c * d.nc);
+  T v = y[i];
+  if (ql >= d.nl) return v;
+  if (c == d.nx) return side[(size_t)(d.nb - 1) * d.nl + ql];   // the wall line has one contribution
+  if (c % d.cb == 0) {
+    const int bl = c > 0 ? (int)(c / d.cb) - 1 : (d.periodic ? d.nb - 1 : -1);
+    if (bl >= 0) v += side[(size_t)bl * d.nl + ql];
+  }
+  return v;
+}
+
 // Workgroup bx: partial products of its chunk into part[bx].  Shared by the
 // single-tank kernel (the last workgroup then adds the partials) and the
 // batched kernels (a second launch adds them: one device-wide release per
@@ -449,23 +466,6 @@ __device__ __forceinline__ void dots_partial(int64_t n, int nvec, const T* __res
   __shared__ double red[4][kMaxVec];
   const int64_t lo = (int64_t)bx * chunk, hi = min(lo + chunk, n);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (fixd) {
-    // w is an operator output whose shared-line contributions are still in
-    // the side buffer (the fix-up pass, done here for the elements this
-    // workgroup owns)
-    const TankDev& d = *fixd;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      const int64_t c = i / d.nc;
-      const int ql = (int)(i - c * d.nc);
-      if (ql >= d.nl) continue;
-      if (c == d.nx) {
-        w[i] = side[(size_t)(d.nb - 1) * d.nl + ql];   // the wall line has one contribution
-      } else if (c % d.cb == 0) {
-        const int bl = c > 0 ? (int)(c / d.cb) - 1 : (d.periodic ? d.nb - 1 : -1);
-        if (bl >= 0) w[i] += side[(size_t)bl * d.nl + ql];
-      }
-    }
-  }
   // eight vectors per pass, their loads issued together (clamped indices,
   // zero weights past nvec keep the loads unconditional)
   for (int k0 = 0; k0 < nvec; k0 += 8) {
@@ -473,7 +473,18 @@ __device__ __forceinline__ void dots_partial(int64_t n, int nvec, const T* __res
 #pragma unroll
     for (int u = 0; u < 8; ++u) sacc[u] = 0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      const double wi = (double)w[i];
+      T wt;
+      if (fixd && k0 == 0) {
+        // w is an operator output whose shared-line contributions are still
+        // in the side buffer: the fix-up of this node, kept for the later
+        // passes (same thread)
+        wt = fixed_value<T>(*fixd, w, side, i);
+        const int64_t c = i / fixd->nc;
+        if (i - c * fixd->nc < fixd->nl) w[i] = wt;
+      } else {
+        wt = w[i];
+      }
+      const double wi = (double)wt;
       T xv[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) xv[u] = X[(int64_t)min(k0 + u, nvec - 1) * ldx + i];
@@ -700,23 +711,6 @@ __global__ void k_residual(const TankDev* __restrict__ td, int64_t n, const T* _
   T v = bvec[i] - y[i];
   if (mask && is_surface_node(*td, i)) v = T(0);
   r[i] = v;
-}
-
-// y[i] of an element-kernel output with its shared-line contribution from
-// the side buffer added (the fix-up pass, done by the consumer; the same
-// addition as the separate pass)
-template <typename T>
-__device__ inline T fixed_value(const TankDev& d, const T* __restrict__ y, const T* __restrict__ side, int64_t i) {
-  const int64_t c = i / d.nc;
-  const int ql = (int)(i - c * d.nc);
-  T v = y[i];
-  if (ql >= d.nl) return v;
-  if (c == d.nx) return side[(size_t)(d.nb - 1) * d.nl + ql];   // the wall line has one contribution
-  if (c % d.cb == 0) {
-    const int bl = c > 0 ? (int)(c / d.cb) - 1 : (d.periodic ? d.nb - 1 : -1);
-    if (bl >= 0) v += side[(size_t)bl * d.nl + ql];
-  }
-  return v;
 }
 
 // b's shared-line fix-up and ||b||^2 in one launch (out = ||b||^2): the
