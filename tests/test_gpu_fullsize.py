@@ -1,0 +1,80 @@
+"""GPU parity at the benchmarked sizes, in the configurations bench.py times.
+
+* The 2048x8, P = 6 walled tank over the trapezoidal bar (589 872 free
+  unknowns): the Laplace solve of its initial state at rtol 1e-10 in FP64 and
+  with FP32 / bfloat16-factor inner solves inside FP64 refinement, against
+  the oracle's sparse direct solve of the same state, element by element.
+* The 64x4, P = 6 stream-series tank: eight RK4 steps at rtol 1e-12 with the
+  stage predictor at its default depth (full depth from the sixth step on),
+  against eight oracle steps (direct solves at every stage).
+
+Tolerances (relative max-norm): 1e-10 for FP64, at rtol 1e-10 (the bench's
+setting; measured 9.4e-11) and at rtol 1e-12; FP64 refinement around FP32
+inner solves 1e-10 (measured 2.5e-11) and around bfloat16-factor inner
+solves 1e-9 (measured 5.7e-10); the RK4 steps 1e-10."""
+import numpy as np
+import pytest
+
+from helpers import Pair, cuda, host, rel_err
+from oracle import laplace as olap
+from oracle import surface as osrf
+from paper_1512_02548_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bar_tank():
+    spec = wl.bar_irregular_spec()
+    from oracle.mesh import Mesh as OMesh
+    xs = OMesh(spec.nx, 1, spec.P, spec.length, spec.periodic).xs_surf
+    eta, phi, h, hx = wl.bar_irregular_state(xs, spec)
+    pair = Pair(spec.nx, spec.nz, spec.P, spec.length, spec.periodic, h, hx, filter_ic=spec.filter_ic,
+                filter_sigma=spec.filter_sigma, Pf=spec.Pf, g=spec.g)
+    print(f"bar tank {spec.nx}x{spec.nz} P={spec.P}: oracle solve", flush=True)
+    s1 = osrf.Surface1D(pair.om)
+    etax = s1.recover_dx(eta)
+    G, _ = olap.coefficients(pair.om, eta, etax, h, hx)
+    Phi = olap.solve_direct(pair.om, olap.stiffness(pair.om, G), phi)
+    return pair, eta, etax, phi, Phi
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-10), (2, 1e-9)])
+def test_bar_tank_solve_matches_oracle(bar_tank, prec, tol):
+    pair, eta, etax, phi, Phi = bar_tank
+    m = pair.m
+    out = cuda(np.zeros(m.n))
+    opts = pair.lib.default_opts(rtol=1e-10, max_iter=20000, prec=prec, inner_rtol=1e-2)
+    st = m.laplace_solve(cuda(eta), cuda(etax), cuda(phi), out, opts)
+    err = rel_err(pair.to_oracle(host(out)), Phi)
+    print(f"prec {prec}: {st['iters']} iterations, relative error {err:.2e}", flush=True)
+    assert err < tol, (err, st)
+
+
+def test_bar_tank_solve_tight_fp64(bar_tank):
+    pair, eta, etax, phi, Phi = bar_tank
+    m = pair.m
+    out = cuda(np.zeros(m.n))
+    st = m.laplace_solve(cuda(eta), cuda(etax), cuda(phi), out, pair.lib.default_opts(rtol=1e-12, max_iter=20000))
+    err = rel_err(pair.to_oracle(host(out)), Phi)
+    assert err < 1e-10, (err, st)
+
+
+def test_stream_series_steps_match_oracle():
+    from oracle.mesh import Mesh as OMesh
+    from oracle.stepper import Tank
+    spec = wl.stream_series_spec()
+    om = OMesh(spec.nx, spec.nz, spec.P, spec.length, True)
+    eta, phi, h, hx = wl.stream_series_state(om.xs_surf, spec)
+    pair = Pair(spec.nx, spec.nz, spec.P, spec.length, True, h, hx, filter_ic=spec.filter_ic,
+                filter_sigma=spec.filter_sigma, Pf=spec.Pf, g=spec.g)
+    tank = Tank(om, h, hx, g=spec.g, Pf=spec.Pf, filt=(spec.filter_ic, spec.filter_sigma))
+    e_t, p_t = cuda(eta), cuda(phi)
+    ws = cuda(np.zeros(pair.m.n))
+    opts = pair.lib.default_opts(rtol=1e-12, warm_start=1, lookahead=1)
+    e_o, p_o = eta.copy(), phi.copy()
+    for _ in range(8):
+        pair.m.rk4_step(e_t, p_t, ws, spec.dt, opts)
+        e_o, p_o = tank.step(e_o, p_o, spec.dt)
+    assert rel_err(host(e_t), e_o) < 1e-10
+    assert rel_err(host(p_t), p_o) < 1e-10
