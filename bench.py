@@ -263,9 +263,10 @@ def batch_workload(args, modes=("lockstep_fp64", "lockstep_mixed", "concurrent_m
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rtol", type=float, default=1e-12)
+    ap.add_argument("--lookahead", type=int, default=1, help="Krylov steps the host queues ahead of the device")
     ap.add_argument("--predict", type=int, default=5,
                     help="past steps extrapolated into each stage solve's start vector (0..6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -305,7 +306,7 @@ def main():
     eta = torch.tensor(eta0, dtype=torch.float64, device=dev)
     phi = torch.tensor(phi0, dtype=torch.float64, device=dev)
     ws = torch.zeros(m.n, dtype=torch.float64, device=dev)
-    opts = lib.default_opts(rtol=args.rtol, warm_start=1, lookahead=1, predict=args.predict)
+    opts = lib.default_opts(rtol=args.rtol, warm_start=1, lookahead=args.lookahead, predict=args.predict)
     n_free = m.info.n_free
 
     eta_init, phi_init = eta.clone(), phi.clone()
