@@ -166,7 +166,7 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
     stages.push_back(&B->stiff32[P]);
   }
   for (int P = 1; P <= kMaxOrder; ++P)
-    for (BatchStage* st2 : {&B->stage.coef[P], &B->stage.sz[P], &B->stage.final_[P]}) stages.push_back(st2);
+    for (BatchStage* st2 : {&B->stage.coef[P], &B->stage.final_[P]}) stages.push_back(st2);
   for (BatchStage* st2 : {&B->stage.surf, &B->stage.circ, &B->stage.fsl, &B->stage.fsg}) stages.push_back(st2);
   for (BatchSD* p : {&B->sdlap, &B->sdlap32, &B->sdmass})
     for (BatchStage* s : {&p->cond, &p->modes, &p->fa, &p->fb, &p->fsolve, &p->wlines, &p->wall, &p->wmodes,
@@ -609,7 +609,7 @@ static sem_status lockstep_rk4(sem_batch* B, double* const* eta, double* const* 
     if (s) return s;
     launch_history_b(a, B->vec, sidx, PT_WS, st);
     // w~: M w = S_z Phi, w~ = w at the surface
-    launch_sz_b(a, B->stage, SSel{SS_PT, PT_WS}, st);
+    for (int P = 1; P <= kMaxOrder; ++P) launch_sz_mfma_b(a, B->stiff[P], P, SSel{SS_PT, PT_WS}, st);
     launch_fixup_b(a, B->fixup, VSel{BV_B, 0}, 0, 0, st);
     launch_sd_b(a, B->sdmass, 1, VSel{BV_B, 0}, VSel{BV_WMASS, 0}, 0, 0, 0, st);
     launch_gather_surface_b(a, B->stage, VSel{BV_WMASS, 0}, RK[4], st);

@@ -1562,13 +1562,6 @@ __global__ void __launch_bounds__(kBlockThreads) k_coef_b(BatchArgs ba, SSel eta
   coef_body<P>(d, svec(ba, d, it_.tank, eta), svec(ba, d, it_.tank, etax), what, it_.bx);
 }
 
-// S_z Phi (element kernel of the reference gather; Phi from a pointer table)
-template <int P>
-__global__ void __launch_bounds__(kBlockThreads) k_sz_b(BatchArgs ba, SSel u) {
-  SEM_BATCH_TANK(ba)
-  gather_body<P, OP_SZ, double, double>(d, svec(ba, d, it_.tank, u), d.b, d.side, 0, it_.bx);
-}
-
 __global__ void __launch_bounds__(kBlockThreads) k_gather_surface_b(BatchArgs ba, VSel u, SSel out) {
   SEM_BATCH_TANK(ba)
   gather_surface_body(d, bvec<double>(d, u), svec(ba, d, it_.tank, out), it_.bx);
@@ -1688,8 +1681,19 @@ static void gather_full(const TankDev& h, const TankDev* d, int op, const T* u, 
       return;
     }
   }
-  if (op == OP_STIFF && h.use_mfma) stiff_mfma(h, d, u, y, side, flags, sizeof(GS) == 1 ? 2 : 1, st);
-  else gather_kernel<T, GS>(h, d, op, u, y, side, flags, st);
+  bool done = false;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    if (op == OP_SZ && h.use_mfma && flags == 0) {
+      launch_sz_mfma(h, d, u, y, side, st);
+      done = true;
+    }
+  }
+  if (done) {
+  } else if (op == OP_STIFF && h.use_mfma) {
+    stiff_mfma(h, d, u, y, side, flags, sizeof(GS) == 1 ? 2 : 1, st);
+  } else {
+    gather_kernel<T, GS>(h, d, op, u, y, side, flags, st);
+  }
   if (!(flags & F_NOFIX))
     hipLaunchKernelGGL(k_fixup<T>, dim3(nblk((int64_t)h.nb * h.nl)), dim3(kBlockThreads), 0, st, d, y, side, flags);
 }
@@ -1994,7 +1998,6 @@ void plan_stage(const std::vector<TankDev>& tanks, const std::vector<int>& ids, 
     };
     const int P = h.P;
     add(out->coef[P], (int)nblk((int64_t)h.nx * 2 * h.nz * h.Np), 0);
-    add(out->sz[P], h.nb, gather_lds_bytes(h, sizeof(double)));
     add(out->final_[P], 1, 0);
     add(out->surf, (int)nblk(h.ns), 0);
     if (h.circ1d) {
@@ -2019,9 +2022,6 @@ void launch_recover_dx_b(const BatchArgs& a0, const BatchStagePlan& p, SSel in0,
 }
 void launch_coef_b(const BatchArgs& a0, const BatchStagePlan& p, SSel eta, SSel etax, int what, hipStream_t st) {
   for (int P = 1; P <= kMaxOrder; ++P) SEM_P_SWITCH(P, SEM_BL(p.coef[PP], k_coef_b<PP>, eta, etax, what));
-}
-void launch_sz_b(const BatchArgs& a0, const BatchStagePlan& p, SSel u, hipStream_t st) {
-  for (int P = 1; P <= kMaxOrder; ++P) SEM_P_SWITCH(P, SEM_BL(p.sz[PP], k_sz_b<PP>, u));
 }
 void launch_gather_surface_b(const BatchArgs& a0, const BatchStagePlan& p, VSel u, SSel out, hipStream_t st) {
   SEM_BL(p.surf, k_gather_surface_b, u, out);

@@ -61,6 +61,8 @@ struct StiffArgs {
   const int32_t* acc_ent;         // [nc][kMaxContrib]
   const int32_t* is_surf_loc;     // [nc + nl]
   const KrylovState* ks;          // cycle state (launches gated on done)
+  const double* lay;              // [2nz][8] element constants (S_z: sigma derivatives and J)
+  const double* invd;             // 1/d at the element nodes, tile layout (S_z)
   int32_t nx, nz, nc, nl, cb, tiles, periodic, pad;
 };
 
@@ -74,6 +76,8 @@ __host__ __device__ inline StiffArgs<T> stiff_args(const TankDev& h, const void*
   a.acc_ent = h.acc_ent;
   a.is_surf_loc = h.is_surf_loc;
   a.ks = h.ks;
+  a.lay = h.lay;
+  a.invd = h.invd;
   a.nx = h.nx;
   a.nz = h.nz;
   a.nc = h.nc;
@@ -103,7 +107,11 @@ __host__ __device__ inline size_t stiff_lds_layout(const TankDev& h, int ops_in_
 }
 
 // Workgroup b of the tank's grid (columns b cb .. b cb + cb - 1).
-template <int P, typename T, typename GS, bool OPS_LDS>
+// SZ: the operator of the w~ recovery instead (paper Sec. 3.1.3),
+// y = J M diag(1/d) (r_sigma Dr + s_sigma Ds) u per element: the same stage 1,
+// the mixing F = (r_sigma T_r + s_sigma T_s) / d at the nodes, stage 2 with M
+// alone, and J per element (FP64 only).
+template <int P, typename T, typename GS, bool OPS_LDS, bool SZ = false>
 __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __restrict__ u, T* __restrict__ y,
                                            T* __restrict__ side, int flags, uint32_t o_loc, uint32_t o_u,
                                            uint32_t o_st, int b) {
@@ -128,16 +136,26 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
   const int ntile = (EBb + 15) >> 4;
   // geometric factors of this wave's first tile, requested before anything
   // else (tile layout: one (component, M-tile, v) group is 64 consecutive values)
-  T g[3][MT][4];
+  T g[SZ ? 1 : 3][MT][4];
   auto load_g = [&](int t) {
-    const int64_t gbase = (((int64_t)b * a.tiles + t) * 3) * (int64_t)NpP * 16;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
+    if constexpr (SZ) {
+      // 1/d of node 16 mt + 4 v + grp of element col (its tile-layout row is permuted)
+      const int64_t ibase = ((int64_t)b * a.tiles + t) * (int64_t)NpP * 16;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          g[c][mt][v] = GLoad<T, GS>::at(a.G, gbase + (int64_t)c * NpP * 16 + (mt * 16 + v * 4) * 16 + lane);
+          g[0][mt][v] = gview(a.invd)[ibase + (16 * mt + 4 * grp + v) * 16 + col];
+    } else {
+      const int64_t gbase = (((int64_t)b * a.tiles + t) * 3) * (int64_t)NpP * 16;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            g[c][mt][v] = GLoad<T, GS>::at(a.G, gbase + (int64_t)c * NpP * 16 + (mt * 16 + v * 4) * 16 + lane);
+    }
   };
   // prefetching holds the factors live across stage 1; FP64 with three
   // M-tiles (P = 8) would run out of registers, it loads them after stage 1
@@ -194,14 +212,29 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
     if (!kPrefetch) load_g(t);
     // pointwise mixing with the geometric factors
     T fr[MT][4], fs[MT][4];
+    T jel = T(1);
+    if constexpr (SZ) {
+      const SEM_GLOBAL double* lay = gview(a.lay) + jt * 8;
+      const T rsig = T(lay[1]), ssig = T(lay[3]);
+      jel = T(lay[4]);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const T tr = acc[mt][v], ts = acc[MT + mt][v];
-        fr[mt][v] = g[0][mt][v] * tr + g[1][mt][v] * ts;
-        fs[mt][v] = g[1][mt][v] * tr + g[2][mt][v] * ts;
-      }
+        for (int v = 0; v < 4; ++v) {
+          const T dsig = rsig * acc[mt][v] + ssig * acc[MT + mt][v];
+          fr[mt][v] = dsig * g[0][mt][v];
+          fs[mt][v] = T(0);
+        }
+    } else {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const T tr = acc[mt][v], ts = acc[MT + mt][v];
+          fr[mt][v] = g[0][mt][v] * tr + g[1][mt][v] * ts;
+          fs[mt][v] = g[1][mt][v] * tr + g[2][mt][v] * ts;
+        }
+    }
     // the next tile's factors stream in during stage 2
     if (kPrefetch && t + kBlockThreads / 64 < ntile) load_g(t + kBlockThreads / 64);
     // stage 2: K index (blk, mt, v, grp) -> operator row 16 mt + row(v, grp)
@@ -216,14 +249,15 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
         for (int mo = 0; mo < MT; ++mo) {
           const int f = kS2 + (((mt * 4 + v) * MT + mo) * 2) * 64 + lane;
           out[mo] = MF::op(opv(f), fr[mt][v], out[mo]);
-          out[mo] = MF::op(opv(f + 64), fs[mt][v], out[mo]);
+          if constexpr (!SZ) out[mo] = MF::op(opv(f + 64), fs[mt][v], out[mo]);
         }
       }
     if (valid) {
 #pragma unroll
       for (int mo = 0; mo < MT; ++mo)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) st3[eb * NS + 16 * mo + MF::row(v, grp)] = out[mo][v];
+        for (int v = 0; v < 4; ++v)
+          st3[eb * NS + 16 * mo + MF::row(v, grp)] = SZ ? T(out[mo][v] * jel) : out[mo][v];
     }
   }
   __syncthreads();
@@ -302,6 +336,23 @@ __global__ void __launch_bounds__(kBlockThreads) k_stiff_mfma_b(BatchArgs ba, VS
   stiff_lds_layout<T>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os);
   stiff_body<P, T, GS, OPS_LDS>(a, bvec<T>(d, u), bvec<T>(d, y), reinterpret_cast<T*>(d.side), flags, (uint32_t)ol,
                                 (uint32_t)ou, (uint32_t)os, it_.bx);
+}
+
+// S_z of the w~ recovery on the matrix cores (FP64), single tank and batched
+template <int P, bool OPS_LDS>
+__global__ void __launch_bounds__(kBlockThreads)
+k_sz_mfma(const StiffArgs<double> a, const double* __restrict__ u, double* __restrict__ y,
+          double* __restrict__ side, uint32_t o_loc, uint32_t o_u, uint32_t o_st) {
+  stiff_body<P, double, double, OPS_LDS, true>(a, u, y, side, 0, o_loc, o_u, o_st, blockIdx.x);
+}
+template <int P, bool OPS_LDS>
+__global__ void __launch_bounds__(kBlockThreads) k_sz_mfma_b(BatchArgs ba, SSel u) {
+  SEM_BATCH_TANK(ba)
+  const StiffArgs<double> a = stiff_args<double>(d, d.G, d.opf_sz, OPS_LDS ? 1 : 0);
+  size_t ol, ou, os;
+  stiff_lds_layout<double>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os);
+  stiff_body<P, double, double, OPS_LDS, true>(a, svec(ba, d, it_.tank, u), d.b, d.side, 0, (uint32_t)ol,
+                                               (uint32_t)ou, (uint32_t)os, it_.bx);
 }
 
 // Lane-layout self-test of the two MFMA builtins: D = A B with known A, B;
@@ -410,6 +461,38 @@ void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const float* u,
                              int gstore, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
   if (gstore == 2) stiff_launch<float, BF16m>(h, d, u, y, side, flags, e0, e1, st);
   else stiff_launch<float, float>(h, d, u, y, side, flags, e0, e1, st);
+}
+
+void launch_sz_mfma(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, hipStream_t st) {
+  const int inl = stiff_ops_in_lds<double>(h);
+  size_t ol, ou, os;
+  const size_t lds = stiff_lds_layout<double>(h, inl, &ol, &ou, &os);
+  const StiffArgs<double> a = stiff_args<double>(h, h.G, h.opf_sz, inl);
+  if (inl) {
+    SEM_MP_SWITCH(h.P, allow_lds(k_sz_mfma<PP, true>, lds));
+    SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_sz_mfma<PP, true>), dim3(h.nb), dim3(kBlockThreads), lds, st, a, u, y,
+                                          side, (uint32_t)ol, (uint32_t)ou, (uint32_t)os));
+  } else {
+    SEM_MP_SWITCH(h.P, allow_lds(k_sz_mfma<PP, false>, lds));
+    SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_sz_mfma<PP, false>), dim3(h.nb), dim3(kBlockThreads), lds, st, a, u, y,
+                                          side, (uint32_t)ol, (uint32_t)ou, (uint32_t)os));
+  }
+}
+
+void launch_sz_mfma_b(const BatchArgs& a0, const BatchStage& p, int P, SSel u, hipStream_t st) {
+  if (p.items.empty()) return;
+  BatchArgs a = a0;
+  a.items = p.dev;
+  TankDev probe{};
+  probe.NpP = ((P + 1) * (P + 2) / 2 + 15) / 16 * 16;
+  const dim3 grid((unsigned)p.items.size());
+  if (stiff_ops_in_lds<double>(probe)) {
+    SEM_MP_SWITCH(P, allow_lds(k_sz_mfma_b<PP, true>, p.lds));
+    SEM_MP_SWITCH(P, hipLaunchKernelGGL((k_sz_mfma_b<PP, true>), grid, dim3(kBlockThreads), p.lds, st, a, u));
+  } else {
+    SEM_MP_SWITCH(P, allow_lds(k_sz_mfma_b<PP, false>, p.lds));
+    SEM_MP_SWITCH(P, hipLaunchKernelGGL((k_sz_mfma_b<PP, false>), grid, dim3(kBlockThreads), p.lds, st, a, u));
+  }
 }
 
 void plan_stiff(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int P, int f32, BatchStage* out) {

@@ -151,7 +151,7 @@ void launch_add_float_b(const BatchArgs& a, const BatchStage& vec, const double*
 void launch_status_or_b(const BatchArgs& a, const BatchStage& per_tank, int bits, hipStream_t st);
 // the RK4 stage work around the Laplace solve, per launch over many tanks
 struct BatchStagePlan {
-  BatchStage coef[kMaxOrder + 1], sz[kMaxOrder + 1], final_[kMaxOrder + 1];   // per order
+  BatchStage coef[kMaxOrder + 1], final_[kMaxOrder + 1];   // per order
   BatchStage surf;            // elementwise over the surface nodes
   BatchStage circ, fsl, fsg;  // periodic 1D operators (tanks with walls use the single-tank kernels)
 };
@@ -160,7 +160,10 @@ void launch_recover_dx_b(const BatchArgs& a, const BatchStagePlan& p, SSel in0, 
                          hipStream_t st);
 void launch_coef_b(const BatchArgs& a, const BatchStagePlan& p, SSel eta, SSel etax, int what, hipStream_t st);
 // S_z u into each tank's b (element kernel; the line fix-up follows separately)
-void launch_sz_b(const BatchArgs& a, const BatchStagePlan& p, SSel u, hipStream_t st);
+// S_z of the w~ recovery on the matrix cores (FP64): b = S_z u (side buffer for the fix-up)
+void launch_sz_mfma(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, hipStream_t st);
+// batched, over the tanks of order P (the FP64 stiffness plan of that order): d.b = S_z u
+void launch_sz_mfma_b(const BatchArgs& a, const BatchStage& p, int P, SSel u, hipStream_t st);
 void launch_gather_surface_b(const BatchArgs& a, const BatchStagePlan& p, VSel u, SSel out, hipStream_t st);
 void launch_fs_rhs_b(const BatchArgs& a, const BatchStagePlan& p, SSel eta, SSel etax, SSel phix, SSel ws,
                      SSel et, SSel pt, hipStream_t st);

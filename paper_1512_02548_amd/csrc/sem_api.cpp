@@ -827,10 +827,11 @@ static sem_status build_mesh(sem_mesh* M) {
   // row map of the instruction: 4v + g for FP64, 4g + v for FP32.
   {
     const int MTt = NpP / 16, KSt = NpP / 4;
-    auto frag = [&](bool fp64) {
+    const std::vector<double> zero((size_t)NpP * NpP, 0.0);
+    auto frag = [&](bool fp64, bool sz = false) {
       std::vector<double> f((size_t)4 * NpP * NpP, 0.0);
       const std::vector<double>* D1[2] = {&Drp, &Dsp};
-      const std::vector<double>* D2[2] = {&MDrp, &MDsp};
+      const std::vector<double>* D2[2] = {sz ? &Mp : &MDrp, sz ? &zero : &MDsp};
       size_t o = 0;
       for (int mt = 0; mt < MTt; ++mt)
         for (int st = 0; st < KSt; ++st)
@@ -849,6 +850,8 @@ static sem_status build_mesh(sem_mesh* M) {
     };
     put(M, "opf", frag(true));
     put(M, "opf32", tof(frag(false)));
+    // S_z (w~ recovery): the same stage 1; stage 2 applies M (symmetric)
+    put(M, "opf_sz", frag(true, true));
   }
   put(M, "elem_loc", M->elem_loc);
   put(M, "acc_cnt", M->acc_cnt);
@@ -1076,6 +1079,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.MDs = at<double>(M, "MDs");
   h.opf = at<double>(M, "opf");
   h.opf32 = at<float>(M, "opf32");
+  h.opf_sz = at<double>(M, "opf_sz");
   h.Mref = at<double>(M, "M");
   h.Dr32 = at<float>(M, "Dr32");
   h.Ds32 = at<float>(M, "Ds32");
@@ -1173,7 +1177,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.hs = at<StageHistory>(M, "hs");
   M->dtank = at<TankDev>(M, "tank");
   // every device array the kernels use must have been laid out
-  const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.opf, h.opf32, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,
+  const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.opf, h.opf32, h.opf_sz, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,
                         h.acc_cnt, h.acc_ent, h.surf_loc, h.is_surf_loc, h.lay, h.nodeq, h.colw, h.pre_lap,
                         h.pre_mass, h.pre_lap32, h.M1, h.S1, h.Ifine, h.Mfine, h.Filt, h.pre1d, h.h, h.hx, h.G,
                         h.G32, h.G16, h.invd, h.status, h.ks, h.H, h.part, h.V, h.Zb, h.w, h.b, h.tmp, h.xs,

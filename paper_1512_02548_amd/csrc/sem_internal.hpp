@@ -132,6 +132,7 @@ struct TankDev {
   const float* Mref32;
   const double* opf;              // [4 NpP^2] stiffness operators in MFMA fragment order (FP64 rows)
   const float* opf32;             // the same for the FP32 accumulator row map
+  const double* opf_sz;           // [4 NpP^2] S_z operators: stage 1 as opf, stage 2 M (second block zero)
   // mesh tables
   const int32_t* elem_loc;        // [2nz][NpP] column-local node (< nc + nl), -1 = padding
   const int32_t* acc_cnt;         // [nc] number of contributions
