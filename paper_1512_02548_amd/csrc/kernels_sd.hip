@@ -30,7 +30,6 @@ namespace sem {
 
 namespace {
 constexpr int kWaves = kBlockThreads / 64;
-constexpr int kModesPB = kModesPerBlock;
 
 __host__ __device__ inline int sd_part_words(int q) { return max(kWaves * 16 * 16 * 2, 32 * q); }
 
@@ -229,7 +228,7 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
   double* gh = sh + sd_part_words(q);     // [16][q][2]
   const int nNT = (q + 15) / 16, KS = (nx + 3) / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  constexpr int kPairs = kModesPB / 2;
+  const int kModesPB = modes_per_block(nx), kPairs = kModesPB / 2;
   const double rs = sd_in_scale(nscale);
   // A row of this lane: the mode of slot `col` (rows past the block's slots are discarded)
   const int kmode = col < kModesPB ? paired_mode(bx, col, kPairs, nx) : -1;
@@ -915,7 +914,7 @@ SdLds sd_lds(const TankDev& h, const SDData& sd, size_t word) {
   const SdShape s1 = sd_shape(h.nx, sd.nMT1), s3 = sd_shape(h.nx, sd.nMT3);
   SdLds l;
   l.cond = sd_cond_stage_bytes(s1.ntw, word, s1.split) + sizeof(int32_t) * sd.nI;
-  l.modes = sizeof(double) * (sd_part_words(sd.q) + 16 * (size_t)sd.q * 2);
+  l.modes = sizeof(double) * (sd_part_words(sd.q) + kModesPerBlockMax * (size_t)sd.q * 2);
   l.back = sizeof(double) * ((16 * (size_t)s3.ntw + 1) * (sd.q + 1) + (s3.split ? kWaves * s3.ntw * 256 : 0));
   l.fa = sd.fft_n1 ? sizeof(double) * 4 * (size_t)((sd.fft_n1 + 3) / 4) * 16 : 0;
   l.fsolve = 0;
@@ -1020,7 +1019,7 @@ void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int
       add_grid(out->fc, t, sd.fft_n1, nnt, 0);
       add_grid(out->fd, t, sd.fft_n2, nnt, 0);
     } else {
-      add_grid(out->modes, t, paired_blocks(h.nx, kModesPB / 2), 1, l.modes);
+      add_grid(out->modes, t, paired_blocks(h.nx, modes_per_block(h.nx) / 2), 1, l.modes);
       if (!sd_back_dft(h.nx, sd.q, sd.fft_n1, sd.nMT3)) add_grid(out->idft, t, ct, (sd.q + 15) / 16, 0);
     }
     if (sd.wall) {
@@ -1084,7 +1083,7 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
     hipLaunchKernelGGL(k_sdf_solve<T>, dim3(fft_mode_blocks(h.nx, ml)), dim3(kBlockThreads), lds.fsolve, st, d,
                        which, gate);
   } else {
-    hipLaunchKernelGGL(k_sd_modes<T>, dim3(paired_blocks(h.nx, kModesPB / 2)), dim3(kBlockThreads), l2, st, d, which,
+    hipLaunchKernelGGL(k_sd_modes<T>, dim3(paired_blocks(h.nx, modes_per_block(h.nx) / 2)), dim3(kBlockThreads), l2, st, d, which,
                        u, gate, nscale, vout);
   }
   if (sd.wall) {

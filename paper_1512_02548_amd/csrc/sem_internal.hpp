@@ -12,7 +12,11 @@ constexpr int kMaxContrib = 8;      // element contributions to one column-local
 constexpr int kBlockThreads = 256;
 constexpr int kMaxRestart = 64;     // GMRES restart length limit
 constexpr int kMaxVec = kMaxRestart + 1;
-constexpr int kModesPerBlock = 8;   // Fourier modes per workgroup of the direct (small-nx) mode solves
+// Fourier modes per workgroup of the direct-transform mode solves: 8 for
+// short tanks (more workgroups), 16 from nx > 128 on (full 16-row MFMA tiles,
+// each workgroup's pass over the columns shared by more modes)
+constexpr int kModesPerBlockMax = 16;
+__host__ __device__ inline int modes_per_block(int nx) { return nx <= 128 ? 8 : 16; }
 
 // Mode solves take mode k together with its conjugate partner nx - k (both
 // use the one stored inverse symbol): a workgroup of `pairs` pairs has
