@@ -1134,208 +1134,14 @@ __device__ inline int s_index(const TankDev& d, int e, int k) {
   return s >= d.ns ? s - d.ns : s;
 }
 
-// y = sum_e R_e^T (scale * A_e) u_e with A_e one of the (P+1)^2 matrices,
-// gathered per node in a fixed order (the node's left element first).
-template <int P>
-__device__ void s_apply(const TankDev& d, const double* A, double scale, const double* u, double* y) {
-  for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
-    int e = s / P, k = s - e * P;
-    double acc = 0;
-    // element e with local index k (k < P), and for k == 0 element e-1 with local P
-    if (e < d.nx) {
-      for (int q = 0; q <= P; ++q) acc += A[k * (P + 1) + q] * u[s_index(d, e, q)];
-    }
-    if (k == 0) {
-      int ep = e - 1;
-      if (ep < 0 && d.periodic) ep = d.nx - 1;
-      if (ep >= 0) {
-        double a2 = 0;
-        for (int q = 0; q <= P; ++q) a2 += A[P * (P + 1) + q] * u[s_index(d, ep, q)];
-        acc += a2;
-      }
-    }
-    y[s] = scale * acc;
-  }
-}
-
-template <int P>
-__device__ void s_precond(const TankDev& d, const double* r, double* z) {
-  // element-block Jacobi of M': classes 0 first, 1 interior, 2 last (walls)
-  for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
-    int e = s / P, k = s - e * P;
-    double acc = 0;
-    auto cls = [&](int ee) {
-      if (d.periodic) return 1;
-      if (d.nx == 1) return 0;
-      return ee == 0 ? 0 : (ee == d.nx - 1 ? 2 : 1);
-    };
-    if (e < d.nx) {
-      const double* C = d.pre1d + cls(e) * (P + 1) * (P + 1);
-      for (int q = 0; q <= P; ++q) acc += C[k * (P + 1) + q] * r[s_index(d, e, q)];
-    }
-    if (k == 0) {
-      int ep = e - 1;
-      if (ep < 0 && d.periodic) ep = d.nx - 1;
-      if (ep >= 0) {
-        const double* C = d.pre1d + cls(ep) * (P + 1) * (P + 1);
-        double a2 = 0;
-        for (int q = 0; q <= P; ++q) a2 += C[P * (P + 1) + q] * r[s_index(d, ep, q)];
-        acc += a2;
-      }
-    }
-    z[s] = acc;
-  }
-}
-
-__device__ inline double s_dot(const TankDev& d, const double* a, const double* b, double* red) {
-  double s = 0;
-  for (int i = threadIdx.x; i < d.ns; i += blockDim.x) s += a[i] * b[i];
-  return block_sum(s, red);
-}
-
-// PCG for M' x = rhs (x holds the initial guess); work arrays r, z, p, q
-template <int P>
-__device__ int s_mass_solve(const TankDev& d, const double* rhs, double* x, double* r, double* z,
-                            double* p, double* q, double* red) {
-  const double J = 0.5 * d.dX;
-  s_apply<P>(d, d.M1, J, x, q);
-  __syncthreads();
-  for (int i = threadIdx.x; i < d.ns; i += blockDim.x) r[i] = rhs[i] - q[i];
-  __syncthreads();
-  double bn = sqrt(s_dot(d, rhs, rhs, red));
-  s_precond<P>(d, r, z);
-  __syncthreads();
-  for (int i = threadIdx.x; i < d.ns; i += blockDim.x) p[i] = z[i];
-  __syncthreads();
-  double rz = s_dot(d, r, z, red);
-  int it = 0;
-  const double tol = 1e-15 * (bn > 0 ? bn : 1.0);
-  for (; it < 500; ++it) {
-    double rn = sqrt(s_dot(d, r, r, red));
-    if (rn <= tol) break;
-    s_apply<P>(d, d.M1, J, p, q);
-    __syncthreads();
-    double alpha = rz / s_dot(d, p, q, red);
-    for (int i = threadIdx.x; i < d.ns; i += blockDim.x) {
-      x[i] += alpha * p[i];
-      r[i] -= alpha * q[i];
-    }
-    __syncthreads();
-    s_precond<P>(d, r, z);
-    __syncthreads();
-    double rzn = s_dot(d, r, z, red);
-    double beta = rzn / rz;
-    rz = rzn;
-    for (int i = threadIdx.x; i < d.ns; i += blockDim.x) p[i] = z[i] + beta * p[i];
-    __syncthreads();
-  }
-  return it;
-}
-
-// f_x from M' f_x = S_x f for up to two fields (in0 -> out0, in1 -> out1)
-template <int P>
-__global__ void __launch_bounds__(kBlockThreads)
-k_recover_dx(const TankDev* __restrict__ td, const double* __restrict__ in0, double* __restrict__ out0,
-             const double* __restrict__ in1, double* __restrict__ out1) {
-  const TankDev& d = *td;
-  __shared__ double red[kBlockThreads];
-  double* rhs = d.s1d;
-  double* r = d.s1d + 1 * (size_t)d.ns;
-  double* z = d.s1d + 2 * (size_t)d.ns;
-  double* p = d.s1d + 3 * (size_t)d.ns;
-  double* q = d.s1d + 4 * (size_t)d.ns;
-  for (int f = 0; f < 2; ++f) {
-    const double* in = f == 0 ? in0 : in1;
-    double* out = f == 0 ? out0 : out1;
-    if (!in) continue;
-    s_apply<P>(d, d.S1, 1.0, in, rhs);
-    __syncthreads();
-    for (int i = threadIdx.x; i < d.ns; i += blockDim.x) out[i] = 0.0;
-    __syncthreads();
-    s_mass_solve<P>(d, rhs, out, r, z, p, q, red);
-    __syncthreads();
-  }
-}
-
-// Over-integrated free-surface right-hand sides (Secs. 3.1.1, 3.3), then M' solves.
-template <int P>
-__global__ void __launch_bounds__(kBlockThreads)
-k_fs_rhs(const TankDev* __restrict__ td, const double* __restrict__ eta, const double* __restrict__ etax,
-         const double* __restrict__ phix, const double* __restrict__ ws, double* __restrict__ eta_t,
-         double* __restrict__ phi_t) {
-  const TankDev& d = *td;
-  __shared__ double red[kBlockThreads];
-  const int Pf = d.Pf, nf = Pf + 1;
-  double* loc = d.s1d + 5 * (size_t)d.ns;    // [nx][P+1][2] element contributions (needs 2(P+1)nx <= 6 ns)
-  double* rhs_e = d.s1d + 11 * (size_t)d.ns;
-  double* rhs_p = d.s1d + 12 * (size_t)d.ns;
-  double* r = d.s1d + 1 * (size_t)d.ns;
-  double* z = d.s1d + 2 * (size_t)d.ns;
-  double* p = d.s1d + 3 * (size_t)d.ns;
-  double* q = d.s1d + 4 * (size_t)d.ns;
-  const double J = 0.5 * d.dX;
-  // thread per (element, coarse node i): RHS_i = J sum_a I[a][i] sum_b Mf[a][b] F[b]
-  for (int it = threadIdx.x; it < d.nx * (P + 1); it += blockDim.x) {
-    int e = it / (P + 1), i = it - e * (P + 1);
-    double acc_e = 0, acc_p = 0;
-    for (int a = 0; a < nf; ++a) {
-      if (d.Ifine[a * (P + 1) + i] == 0.0) continue;
-      double se = 0, sp = 0;
-      for (int bq = 0; bq < nf; ++bq) {
-        double et = 0, ex = 0, px = 0, ww = 0;
-        for (int k = 0; k <= P; ++k) {
-          double Ik = d.Ifine[bq * (P + 1) + k];
-          int s = s_index(d, e, k);
-          et += Ik * eta[s];
-          ex += Ik * etax[s];
-          px += Ik * phix[s];
-          ww += Ik * ws[s];
-        }
-        double fe = -ex * px + ww * (1.0 + ex * ex);
-        double fp = -d.g * et - 0.5 * (px * px - ww * ww * (1.0 + ex * ex));
-        double mf = d.Mfine[a * nf + bq];
-        se += mf * fe;
-        sp += mf * fp;
-      }
-      acc_e += d.Ifine[a * (P + 1) + i] * se;
-      acc_p += d.Ifine[a * (P + 1) + i] * sp;
-    }
-    loc[(size_t)it * 2 + 0] = J * acc_e;
-    loc[(size_t)it * 2 + 1] = J * acc_p;
-  }
-  __syncthreads();
-  for (int s = threadIdx.x; s < d.ns; s += blockDim.x) {
-    int e = s / P, k = s - e * P;
-    double ae = 0, ap = 0;
-    if (e < d.nx) {
-      ae = loc[((size_t)e * (P + 1) + k) * 2 + 0];
-      ap = loc[((size_t)e * (P + 1) + k) * 2 + 1];
-    }
-    if (k == 0) {
-      int ep = e - 1;
-      if (ep < 0 && d.periodic) ep = d.nx - 1;
-      if (ep >= 0) {
-        ae += loc[((size_t)ep * (P + 1) + P) * 2 + 0];
-        ap += loc[((size_t)ep * (P + 1) + P) * 2 + 1];
-      }
-    }
-    rhs_e[s] = ae;
-    rhs_p[s] = ap;
-    eta_t[s] = 0.0;
-    phi_t[s] = 0.0;
-  }
-  __syncthreads();
-  s_mass_solve<P>(d, rhs_e, eta_t, r, z, p, q, red);
-  __syncthreads();
-  s_mass_solve<P>(d, rhs_p, phi_t, r, z, p, q, red);
-}
-
-// ------------------------------------------------------------ 1D periodic direct solves
-// y = A x for a block-circulant A given by its first block-row [P][ns]:
-// y[eP + a] = sum_j row[a][j] x[(eP + j) mod ns], j within the row's decay
-// band (circ_band elements each side, below rounding beyond).  One wavefront per output
-// node: lanes stride over j, then a butterfly sum (fixed order).  x1/y1, when
-// given, is a second vector with the same operator.
+// ------------------------------------------------------------ 1D projections as exact rows
+// y = A x for A = M'^{-1} S_x or M'^{-1}.  Periodic: A is block-circulant,
+// given by its first block-row [P][nx P]: y[eP + a] = sum_j row[a][j]
+// x[(eP + j) mod nx P], j within the row's decay band (circ_band elements
+// each side, below rounding beyond).  Walls: the same rows for the nodes
+// farther than the band from both walls, explicit rows for the others.  One
+// wavefront per output node: lanes stride over j, then a butterfly sum
+// (fixed order).  x1/y1, when given, is a second vector with the same operator.
 __device__ __forceinline__ void circ_body(const TankDev& d, int which, const double* __restrict__ x0,
                                           double* __restrict__ y0, const double* __restrict__ x1,
                                           double* __restrict__ y1, int bx) {
@@ -1344,21 +1150,42 @@ __device__ __forceinline__ void circ_body(const TankDev& d, int which, const dou
   if (s >= d.ns) return;
   const int P = d.P, ns = d.ns;
   const int e = s / P, a = s - e * P;
-  const double* row = (which == 0 ? d.Rrow : d.Brow) + (size_t)a * ns;
-  const int base = e * P;
-  // the row's band: elements nx - band .. nx - 1, 0 .. band (or the whole row)
-  const bool all = 2 * d.circ_band + 1 >= d.nx;
-  const int span = all ? ns : (2 * d.circ_band + 1) * P;
-  const int j0 = all ? 0 : (d.nx - d.circ_band) * P;
   double acc0 = 0, acc1 = 0;
-  for (int t = lane; t < span; t += 64) {
-    int j = j0 + t;
-    if (j >= ns) j -= ns;
-    int src = base + j;
-    if (src >= ns) src -= ns;
-    double r = row[j];
-    acc0 += r * x0[src];
-    if (x1) acc1 += r * x1[src];
+  int rr = -1, t0 = 0;   // walls: explicit row near a wall and its window start
+  if (!d.periodic) {
+    if (s < d.wall_nl) {
+      rr = s;
+    } else if (s >= ns - d.wall_nr) {
+      rr = d.wall_nl + (s - (ns - d.wall_nr));
+      t0 = ns - d.wall_wd;
+    }
+  }
+  if (rr >= 0) {
+    const double* row = d.wrows + ((size_t)(which == 0 ? 0 : 1) * (d.wall_nl + d.wall_nr) + rr) * d.wall_wd;
+    for (int t = lane; t < d.wall_wd; t += 64) {
+      const double r = row[t];
+      acc0 += r * x0[t0 + t];
+      if (x1) acc1 += r * x1[t0 + t];
+    }
+  } else {
+    // the periodic row (nodes per row: nxp = nx P); its band: elements
+    // nx - band .. nx - 1, 0 .. band (or the whole row).  With walls the
+    // node is at least band + 1 elements from both walls: no wrap.
+    const int nxp = d.nx * P;
+    const double* row = (which == 0 ? d.Rrow : d.Brow) + (size_t)a * ns;
+    const int base = e * P;
+    const bool all = 2 * d.circ_band + 1 >= d.nx;
+    const int span = all ? nxp : (2 * d.circ_band + 1) * P;
+    const int j0 = all ? 0 : (d.nx - d.circ_band) * P;
+    for (int t = lane; t < span; t += 64) {
+      int j = j0 + t;
+      if (j >= nxp) j -= nxp;
+      int src = d.periodic ? base + j : base - d.circ_band * P + t;
+      if (src >= nxp && d.periodic) src -= nxp;
+      double r = row[j];
+      acc0 += r * x0[src];
+      if (x1) acc1 += r * x1[src];
+    }
   }
   acc0 = wave_sum(acc0);
   if (x1) acc1 = wave_sum(acc1);
@@ -1954,27 +1781,19 @@ void launch_fill_f(int64_t n, float* y, hipStream_t st) { hipMemsetAsync(y, 0, n
 
 void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, double* out0, const double* in1,
                        double* out1, hipStream_t st) {
-  if (h.circ1d) {
-    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, 0, in0,
-                       out0, in1, out1);
-    return;
-  }
-  SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_recover_dx<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, in0, out0, in1, out1));
+  hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, 0, in0, out0,
+                     in1, out1);
 }
 void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const double* etax, const double* phix,
                    const double* ws, double* et, double* pt, hipStream_t st) {
-  if (h.circ1d) {
-    double* loc = h.s1d + 5 * (size_t)h.ns;
-    double* re = h.s1d + 11 * (size_t)h.ns;
-    double* rp = h.s1d + 12 * (size_t)h.ns;
-    hipLaunchKernelGGL(k_fs_local, dim3(nblk(h.nx, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, eta, etax,
-                       phix, ws, loc);
-    hipLaunchKernelGGL(k_fs_gather, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, loc, re, rp);
-    hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, 1, re, et,
-                       rp, pt);
-    return;
-  }
-  SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_fs_rhs<PP>, dim3(1), dim3(kBlockThreads), 0, st, d, eta, etax, phix, ws, et, pt));
+  double* loc = h.s1d + 5 * (size_t)h.ns;
+  double* re = h.s1d + 11 * (size_t)h.ns;
+  double* rp = h.s1d + 12 * (size_t)h.ns;
+  hipLaunchKernelGGL(k_fs_local, dim3(nblk(h.nx, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, eta, etax,
+                     phix, ws, loc);
+  hipLaunchKernelGGL(k_fs_gather, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, loc, re, rp);
+  hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, 1, re, et, rp,
+                     pt);
 }
 void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,
                       const double* ke, const double* kp, double* ye, double* yp, double* acce, double* accp,

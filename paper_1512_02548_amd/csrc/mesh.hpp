@@ -46,6 +46,7 @@ struct sem_mesh {
   int fft_n1 = 0, fft_n2 = 0;   // four-step transforms along x (0: direct)
   int circ1d = 0;
   int circ_band = 0;        // elements on each side kept by the periodic 1D applies
+  int wall_nl = 0, wall_nr = 0, wall_wd = 0;   // walls: explicit rows near each wall, their window
   int64_t n = 0, ns = 0, E = 0;
   // host tables
   std::vector<int32_t> elem_loc, acc_cnt, acc_ent, surf_loc, is_surf_loc;

@@ -686,28 +686,13 @@ static sem_status build_mesh(sem_mesh* M) {
   Ref1D rf(M->Pf);
   Mat If = r1.interp_to(rf.r);
   Mat Filt = filter_matrix(P, M->ic, M->sf);
-  // 1D block Jacobi of M' (classes: first, interior, last)
-  std::vector<double> pre1d((size_t)3 * P1 * P1, 0.0);
-  for (int cls = 0; cls < 3; ++cls) {
-    bool left_shared = M->periodic || cls != 0;
-    bool right_shared = M->periodic || cls != 2;
-    if (!M->periodic && nx == 1) left_shared = right_shared = false;
-    Mat C((size_t)P1 * P1);
-    for (int i = 0; i < P1 * P1; ++i) C[i] = 0.5 * dX * r1.M[i];
-    if (left_shared) C[0] += 0.5 * dX * r1.M[(size_t)P * P1 + P];
-    if (right_shared) C[(size_t)P * P1 + P] += 0.5 * dX * r1.M[0];
-    if (!invert(C, P1)) return fail(SEM_E_INVAL, "singular 1D block");
-    std::vector<double> w(P1, 1.0);
-    if (left_shared) w[0] = 1.0 / std::sqrt(2.0);
-    if (right_shared) w[P] = 1.0 / std::sqrt(2.0);
-    for (int a = 0; a < P1; ++a)
-      for (int b = 0; b < P1; ++b) pre1d[(size_t)cls * P1 * P1 + a * P1 + b] = w[a] * C[(size_t)a * P1 + b] * w[b];
-  }
-
-  // 1D periodic: first block-rows of M'^{-1} and M'^{-1} S_x from the block
-  // symbol (blocks of the P nodes e*P..e*P+P-1 of element e)
-  std::vector<double> Brow, Rrow;
-  M->circ1d = M->periodic ? 1 : 0;
+  // 1D projections applied as exact rows: first block-rows of M'^{-1} and
+  // M'^{-1} S_x from the block symbol of the periodic operators (blocks of
+  // the P nodes e*P..e*P+P-1 of element e).  With walls these are the rows of
+  // every node farther than the rows' decay band from both walls; the rows
+  // near the walls follow below from the walled M'.
+  std::vector<double> Brow, Rrow, wrows;
+  M->circ1d = 1;
   if (M->circ1d) {
     using cd = std::complex<double>;
     const int ns1 = (int)M->ns;
@@ -801,6 +786,68 @@ static sem_status build_mesh(sem_mesh* M) {
         }
       }
     M->circ_band = std::min(reach + 4, nx);   // elements on each side; 2 band + 1 >= nx: all
+    if (!M->periodic) {
+      // Walled M' (banded, half-bandwidth P) and S_x, assembled from the
+      // element matrices; rows of M'^{-1} from a banded Cholesky factor
+      // (M' e_s solves; M' is symmetric), rows of M'^{-1} S_x as S_x^T
+      // applied to them.  Rows of the nodes in the W elements next to each
+      // wall are kept explicitly over the window of nodes they reach.
+      const int band = M->circ_band, W = band + 2;
+      const bool all = 2 * W + 1 >= nx;
+      M->wall_nl = all ? ns1 : W * P;
+      M->wall_nr = all ? 0 : W * P + 1;
+      M->wall_wd = all ? ns1 : std::min(ns1, (W + band + 1) * P + 1);
+      const int hb = P;
+      std::vector<double> Mb((size_t)ns1 * (hb + 1), 0.0);   // Mb[i][k] = M'(i, i - k)
+      std::vector<double> Sd((size_t)ns1 * (2 * hb + 1), 0.0);   // Sd[i][hb + j - i] = S_x(i, j)
+      for (int e = 0; e < nx; ++e)
+        for (int a = 0; a <= P; ++a)
+          for (int b = 0; b <= P; ++b) {
+            const int i = e * P + a, j = e * P + b;
+            if (j <= i) Mb[(size_t)i * (hb + 1) + (i - j)] += Je * r1.M[(size_t)a * P1 + b];
+            Sd[(size_t)i * (2 * hb + 1) + hb + j - i] += S1[(size_t)a * P1 + b];
+          }
+      std::vector<double> Lb((size_t)ns1 * (hb + 1), 0.0);   // Cholesky factor, same band layout
+      for (int i = 0; i < ns1; ++i)
+        for (int j = std::max(0, i - hb); j <= i; ++j) {
+          double sum = Mb[(size_t)i * (hb + 1) + (i - j)];
+          for (int k = std::max(0, i - hb); k < j; ++k)
+            sum -= Lb[(size_t)i * (hb + 1) + (i - k)] * Lb[(size_t)j * (hb + 1) + (j - k)];
+          if (i == j) {
+            if (!(sum > 0)) return fail(SEM_E_INVAL, "internal: 1D mass matrix not positive definite");
+            Lb[(size_t)i * (hb + 1)] = std::sqrt(sum);
+          } else {
+            Lb[(size_t)i * (hb + 1) + (i - j)] = sum / Lb[(size_t)j * (hb + 1)];
+          }
+        }
+      const int nr = M->wall_nl + M->wall_nr, wd = M->wall_wd;
+      wrows.assign((size_t)2 * nr * wd, 0.0);
+      std::vector<double> z(ns1), y(ns1);
+      for (int rr = 0; rr < nr; ++rr) {
+        const int srow = rr < M->wall_nl ? rr : ns1 - M->wall_nr + (rr - M->wall_nl);
+        const int t0 = rr < M->wall_nl ? 0 : ns1 - wd;
+        // M' z = e_srow: L y = e, L^T z = y
+        for (int i = 0; i < ns1; ++i) {
+          double sum = i == srow ? 1.0 : 0.0;
+          for (int k = std::max(0, i - hb); k < i; ++k) sum -= Lb[(size_t)i * (hb + 1) + (i - k)] * y[k];
+          y[i] = sum / Lb[(size_t)i * (hb + 1)];
+        }
+        for (int i = ns1 - 1; i >= 0; --i) {
+          double sum = y[i];
+          for (int k = i + 1; k <= std::min(ns1 - 1, i + hb); ++k) sum -= Lb[(size_t)k * (hb + 1) + (k - i)] * z[k];
+          z[i] = sum / Lb[(size_t)i * (hb + 1)];
+        }
+        for (int t = 0; t < wd; ++t) {
+          const int j = t0 + t;
+          // (S_x^T z)_j = sum_i S_x(i, j) z_i over |i - j| <= hb
+          double r = 0;
+          for (int i = std::max(0, j - hb); i <= std::min(ns1 - 1, j + hb); ++i)
+            r += Sd[(size_t)i * (2 * hb + 1) + hb + j - i] * z[i];
+          wrows[((size_t)0 * nr + rr) * wd + t] = r;
+          wrows[((size_t)1 * nr + rr) * wd + t] = z[j];
+        }
+      }
+    }
   }
 
   // ---- workspace layout: constants
@@ -869,9 +916,10 @@ static sem_status build_mesh(sem_mesh* M) {
   put(M, "Ifine", If);
   put(M, "Mfine", rf.M);
   put(M, "Filt", Filt);
-  put(M, "pre1d", pre1d);
   put(M, "Brow", Brow);
   put(M, "Rrow", Rrow);
+  if (wrows.empty()) wrows.assign(1, 0.0);
+  put(M, "wrows", wrows);
   put(M, "h", M->h);
   put(M, "hx", M->hx);
   put(M, "twid", twid);
@@ -1137,11 +1185,14 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.Ifine = at<double>(M, "Ifine");
   h.Mfine = at<double>(M, "Mfine");
   h.Filt = at<double>(M, "Filt");
-  h.pre1d = at<double>(M, "pre1d");
   h.circ1d = M->circ1d;
   h.circ_band = M->circ_band;
   h.Brow = at<double>(M, "Brow");
   h.Rrow = at<double>(M, "Rrow");
+  h.wrows = at<double>(M, "wrows");
+  h.wall_nl = M->wall_nl;
+  h.wall_nr = M->wall_nr;
+  h.wall_wd = M->wall_wd;
   h.h = at<double>(M, "h");
   h.hx = at<double>(M, "hx");
   h.G = at<double>(M, "G");
@@ -1179,7 +1230,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   // every device array the kernels use must have been laid out
   const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.opf, h.opf32, h.opf_sz, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,
                         h.acc_cnt, h.acc_ent, h.surf_loc, h.is_surf_loc, h.lay, h.nodeq, h.colw, h.pre_lap,
-                        h.pre_mass, h.pre_lap32, h.M1, h.S1, h.Ifine, h.Mfine, h.Filt, h.pre1d, h.h, h.hx, h.G,
+                        h.pre_mass, h.pre_lap32, h.M1, h.S1, h.Ifine, h.Mfine, h.Filt, h.h, h.hx, h.G,
                         h.G32, h.G16, h.invd, h.status, h.ks, h.H, h.part, h.V, h.Zb, h.w, h.b, h.tmp, h.xs,
                         h.wmass, h.side, h.s1d, h.V32, h.Z32, h.w32, h.x32, h.b32, h.twid, h.Brow, h.Rrow,
                         h.sd[0].yI, h.sd[1].yI, h.sd[0].A1, h.sd[1].A1, h.sd[0].C3, h.sd[1].C3, h.sd[0].XH,

@@ -163,11 +163,16 @@ struct TankDev {
   const double* Ifine;            // (Pf+1) x (P+1)
   const double* Mfine;            // (Pf+1) x (Pf+1)
   const double* Filt;             // (P+1) x (P+1)
-  const double* pre1d;            // [3][(P+1)^2] W C^{-1} W for the 1D mass (classes: first, interior, last)
   int32_t circ1d;                 // periodic: M'^{-1} and M'^{-1} S_x applied as block-circulant rows
   int32_t circ_band;              // ... over the elements within this distance of the diagonal (all if 2 band + 1 >= nx)
   const double* Brow;             // [P][ns] first block-row of M'^{-1}
   const double* Rrow;             // [P][ns] first block-row of M'^{-1} S_x
+  // walls: rows of M'^{-1} S_x (table 0) and M'^{-1} (table 1) within a few
+  // decay lengths of the walls, exact, over a window of wall_wd nodes from
+  // the wall ([2][wall_nl + wall_nr][wall_wd]); the other rows are the
+  // periodic block-rows above
+  const double* wrows;
+  int32_t wall_nl, wall_nr, wall_wd, pad6;
   const double* h;                // [ns]
   const double* hx;               // [ns]
   // dynamic fields

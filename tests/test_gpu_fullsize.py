@@ -11,7 +11,8 @@
 Tolerances (relative max-norm): 1e-10 for FP64, at rtol 1e-10 (the bench's
 setting; measured 9.4e-11) and at rtol 1e-12; FP64 refinement around FP32
 inner solves 1e-10 (measured 2.5e-11) and around bfloat16-factor inner
-solves 1e-9 (measured 5.7e-10); the RK4 steps 1e-10."""
+solves 1e-9 (measured 5.7e-10); the RK4 steps and the walled tank's eta_x
+(the exact 1D projection rows) 1e-10."""
 import numpy as np
 import pytest
 
@@ -49,6 +50,17 @@ def test_bar_tank_solve_matches_oracle(bar_tank, prec, tol):
     err = rel_err(pair.to_oracle(host(out)), Phi)
     print(f"prec {prec}: {st['iters']} iterations, relative error {err:.2e}", flush=True)
     assert err < tol, (err, st)
+
+
+def test_bar_tank_gradient_recovery_matches_oracle(bar_tank):
+    """eta_x on the walled 2048-column tank: rows near the walls exact, the
+    others the translation-invariant band (walls farther than its reach)."""
+    pair, eta, etax, phi, Phi = bar_tank
+    out = cuda(np.zeros(pair.m.ns))
+    pair.m.gradient_recover(pair.lib.SEM_RECOVER_DX, cuda(eta), None, out)
+    err = rel_err(host(out), etax)
+    print(f"eta_x relative error {err:.2e}", flush=True)
+    assert err < 1e-10   # measured 4.0e-12
 
 
 def test_bar_tank_solve_tight_fp64(bar_tank):
