@@ -144,6 +144,26 @@ def large_tank(lib, wl, torch, reps=3):
         out.setdefault("stiffness", {})[name] = {"mean_launch_ms": ms, "bytes_per_launch": b,
                                                  "achieved_gbs": b / (ms * 1e-3) / 1e9,
                                                  "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    # time stepping from the snapshot (FP64, rtol 1e-10): the stage solves of
+    # a few RK4 steps, the later ones started by the stage predictor
+    eta_s, phi_s = eta.clone(), phis.clone()
+    ws = torch.zeros(m.n, dtype=torch.float64, device=dev)
+    o = lib.default_opts(rtol=1e-10, max_iter=20000, warm_start=1)
+    steps, t_step, t_solve, its = 8, [], 0.0, []
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = m.rk4_step(eta_s, phi_s, ws, spec.dt, o)
+        torch.cuda.synchronize()
+        t_step.append(time.perf_counter() - t0)
+        if k >= steps // 2:
+            t_solve += sum(x["seconds"] for x in st)
+            its += [x["iters"] for x in st]
+    tail = t_step[steps // 2:]
+    out["rk4"] = {"steps": steps, "dt": spec.dt, "ms_per_step_last_half": 1e3 * sum(tail) / len(tail),
+                  "mean_iters_per_solve_last_half": float(np.mean(its)),
+                  "solve_gdof_s_last_half": m.info.n_free * len(its) / t_solve / 1e9,
+                  "ms_first_step": 1e3 * t_step[0]}
     return out
 
 
