@@ -72,7 +72,6 @@ struct sem_batch {
   BatchSD sdlap, sdlap32;
   BatchSD sdmass;                 // exact inverse of the 2D mass matrix (w recovery)
   BatchStagePlan stage;           // the RK4 stage work around the solves
-  std::vector<int> walled;        // tanks whose 1D operators run as single-tank kernels
   std::vector<int> orders;
   int mmax = 0;
   // Arnoldi steps captured as HIP graphs, per step j and precision (FP64,
@@ -158,8 +157,6 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   plan_sd(B->tanks, ids, 0, 1, &B->sdlap32);
   plan_sd(B->tanks, ids, 1, 0, &B->sdmass);
   plan_stage(B->tanks, ids, &B->stage);
-  for (int t = 0; t < count; ++t)
-    if (!B->tanks[t].circ1d) B->walled.push_back(t);
   std::vector<BatchStage*> stages = {&B->vec, &B->dots, &B->fixup, &B->per_tank};
   for (int P : B->orders) {
     stages.push_back(&B->stiff[P]);
@@ -586,20 +583,12 @@ static sem_status lockstep_rk4(sem_batch* B, double* const* eta, double* const* 
   const double wts[4] = {1.0 / 6, 2.0 / 6, 2.0 / 6, 1.0 / 6};
   const SSel RK[9] = {{SS_RK, 0}, {SS_RK, 1}, {SS_RK, 2}, {SS_RK, 3}, {SS_RK, 4},
                       {SS_RK, 5}, {SS_RK, 6}, {SS_RK, 7}, {SS_RK, 8}};
-  auto in_act = [&](int t) { return std::find(act.begin(), act.end(), t) != act.end(); };
   for (int sidx = 0; sidx < 4 && !act.empty(); ++sidx) {
     const SSel se = sidx == 0 ? SSel{SS_PT, PT_ETA} : RK[0];
     const SSel sp = sidx == 0 ? SSel{SS_PT, PT_PHIS} : RK[1];
     s = set_live(B, act, st);
     if (s) return s;
     launch_recover_dx_b(a, B->stage, se, RK[2], sp, RK[3], st);
-    for (int t : B->walled) {
-      if (!in_act(t)) continue;
-      sem_mesh* M = B->meshes[t];
-      const size_t ns = M->ns;
-      launch_recover_dx(M->hd, M->dtank, sidx == 0 ? eta[t] : M->rk, M->rk + 2 * ns,
-                        sidx == 0 ? phi_s[t] : M->rk + ns, M->rk + 3 * ns, st);
-    }
     launch_coef_b(a, B->stage, se, RK[2], 3, st);
     launch_predict_b(a, B->vec, sidx, o.predict, B->ddt, PT_WS, st);
     s = lockstep_laplace(B, act, sidx == 0 ? PT_PHIS : PT_YP, 1, o, iters, st);
@@ -614,14 +603,6 @@ static sem_status lockstep_rk4(sem_batch* B, double* const* eta, double* const* 
     launch_sd_b(a, B->sdmass, 1, VSel{BV_B, 0}, VSel{BV_WMASS, 0}, 0, 0, 0, st);
     launch_gather_surface_b(a, B->stage, VSel{BV_WMASS, 0}, RK[4], st);
     launch_fs_rhs_b(a, B->stage, se, RK[2], RK[3], RK[4], RK[5], RK[6], st);
-    for (int t : B->walled) {
-      if (!in_act(t)) continue;
-      sem_mesh* M = B->meshes[t];
-      const size_t ns = M->ns;
-      double* rk = M->rk;
-      launch_fs_rhs(M->hd, M->dtank, sidx == 0 ? eta[t] : rk, rk + 2 * ns, rk + 3 * ns, rk + 4 * ns, rk + 5 * ns,
-                    rk + 6 * ns, st);
-    }
     launch_rk4_stage_b(a, B->stage, B->ddt, sidx < 3 ? cnode[sidx + 1] : 0.0, wts[sidx], sidx == 0 ? 1 : 0,
                        SSel{SS_PT, PT_ETA}, SSel{SS_PT, PT_PHIS}, st);
   }
