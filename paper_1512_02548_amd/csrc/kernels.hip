@@ -99,16 +99,22 @@ template <int P>
 __device__ __forceinline__ void coef_body(const TankDev& d, const double* __restrict__ eta,
                                           const double* __restrict__ etax, int what, int bx) {
   constexpr int Np = (P + 1) * (P + 2) / 2;
+  // Sixteen consecutive lanes take the sixteen elements of one tile at one
+  // node, the next sixteen the next node: every store below is then one
+  // contiguous run of the tile layout.  Grid: nb * T * Np * 16 threads.
   const int64_t gid = (int64_t)bx * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)d.nx * 2 * d.nz * Np;
-  if (gid >= total) return;
-  int m = gid % Np;
-  int64_t e = gid / Np;
-  int jt = e % (2 * d.nz);
-  int c = e / (2 * d.nz);
-  int t = jt & 1, j = jt >> 1;
-  int b = c / d.cb, lc = c % d.cb;
-  int eb = lc * 2 * d.nz + jt;
+  const int e16 = (int)(gid & 15);
+  const int64_t r = gid >> 4;
+  const int m = (int)(r % Np);
+  const int64_t g = r / Np;  // tile over the whole tank: b * T + tile
+  if (g >= (int64_t)d.nb * d.T) return;
+  const int b = (int)(g / d.T);
+  const int eb = (int)(g - (int64_t)b * d.T) * 16 + e16;
+  if (eb >= d.EB) return;
+  const int lc = eb / (2 * d.nz), jt = eb - lc * 2 * d.nz;
+  const int c = b * d.cb + lc;
+  if (c >= d.nx) return;
+  int t = jt & 1;
   const double* lay = d.lay + jt * 8;
   const double* w = d.colw + ((size_t)t * d.NpP + m) * (P + 1);
   double et = 0, ex = 0, hh = 0, hxx = 0;
@@ -1462,7 +1468,7 @@ size_t gather_lds_bytes(const TankDev& h, size_t word) {
 
 void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const double* etax, int what,
                  hipStream_t st) {
-  int64_t total = (int64_t)h.nx * 2 * h.nz * h.Np;
+  int64_t total = (int64_t)h.nb * h.T * h.Np * 16;
   SEM_P_SWITCH(h.P, hipLaunchKernelGGL(k_coef<PP>, dim3(nblk(total)), dim3(kBlockThreads), 0, st, d, eta, etax, what));
 }
 
@@ -1816,7 +1822,7 @@ void plan_stage(const std::vector<TankDev>& tanks, const std::vector<int>& ids, 
       s.lds = std::max(s.lds, lds);
     };
     const int P = h.P;
-    add(out->coef[P], (int)nblk((int64_t)h.nx * 2 * h.nz * h.Np), 0);
+    add(out->coef[P], (int)nblk((int64_t)h.nb * h.T * h.Np * 16), 0);
     add(out->final_[P], 1, 0);
     add(out->surf, (int)nblk(h.ns), 0);
     if (h.circ1d) {
