@@ -115,7 +115,11 @@ typedef struct {
   int32_t iters;        /* Krylov iterations (all inner iterations under IR)   */
   int32_t refinements;  /* outer IR steps (0 for FP64)                         */
   double rel_residual;  /* final ||r||/||b|| (FP64 true residual under IR)     */
-  double seconds;       /* wall time of the call (host clock, synchronised)    */
+  double seconds;       /* wall time of the call (host clock, synchronised);
+                           for the stage solves of sem_rk4_step, the device
+                           time between the solve's first and last launches
+                           (events on the stream: the step does not wait for
+                           the device around its stage solves)              */
   int32_t status;       /* sem_status of this solve                            */
   int32_t reserved;
 } sem_solve_stats;

@@ -758,7 +758,15 @@ k_residual_cycle(const TankDev* __restrict__ td, int64_t n, const T* __restrict_
   dots_reduce(1, part, ldp, rr, gridDim.x);
   if (threadIdx.x == 0) {
     *counter = 0;
-    cycle_start(ks, Hbase, m, rr, first, status);
+    if (*status) {
+      // a status set before the cycle (a non-positive water column found by
+      // the coefficient update, a non-finite value) ends the solve at once
+      ks->status |= *status;
+      ks->done = 1;
+      ks->converged = 0;
+    } else {
+      cycle_start(ks, Hbase, m, rr, first, status);
+    }
     publish_progress(ks, mirror, progress_scalars(mirror));
   }
 }

@@ -74,8 +74,14 @@ struct sem_mesh {
   size_t kt_used = 0;
   int64_t kt_count = 0;
   double kt_ms = 0;
+  // start and end events of the stage solves of one RK4 step (slot 0 also
+  // serves a single solve); created on first use
+  hipEvent_t solve_ev[4][2] = {};
   ~sem_mesh() {
     if (prog_host) (void)hipHostFree(prog_host);
+    for (auto& e : solve_ev)
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
     for (auto& e : kt_ev) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);

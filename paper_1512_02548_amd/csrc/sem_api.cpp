@@ -1632,12 +1632,28 @@ struct StagePredict {
   double dt;
 };
 
+// Device time between the two events of a solve (0 if they cannot be read).
+static double solve_seconds(hipEvent_t* ev) {
+  float ms = 0;
+  return (ev[0] && ev[1] && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) ? ms * 1e-3 : 0.0;
+}
+
+// A stage solve (pred set) neither waits for the device before it starts nor
+// after it ends: its seconds come from the events around its launches, read
+// by the RK4 step once the step has synchronised.  A single solve
+// synchronises at its end and reports the host clock.
 static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, const sem_solve_opts* o,
                                sem_solve_stats* stats, hipStream_t st, const StagePredict* pred = nullptr) {
   const TankDev& h = M->hd;
   const TankDev* d = M->dtank;
   const int64_t n = M->n;
   auto t0 = std::chrono::steady_clock::now();
+  hipEvent_t* ev = M->solve_ev[pred ? pred->stage : 0];
+  if (pred) {
+    if (!ev[0]) HIPCHK(hipEventCreate(&ev[0]));
+    if (!ev[1]) HIPCHK(hipEventCreate(&ev[1]));
+    HIPCHK(hipEventRecord(ev[0], st));
+  }
   const bool fp64 = o->prec == SEM_PREC_FP64;
   // u = [0; phi~], the start vector xs (warm start, stage predictor), the
   // Krylov state; then b = -(A u)_F
@@ -1704,12 +1720,16 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   if (s == SEM_E_NOCONV) set_status_bits(M, ST_NOCONV, st);
   // Phi = x_F + lift; a stage solve's change into the record
   launch_solve_end(h, d, phi_s, phi, pred ? pred->stage : -1, st);
-  HIPCHK(hipStreamSynchronize(st));
+  if (pred) {
+    HIPCHK(hipEventRecord(ev[1], st));
+  } else {
+    HIPCHK(hipStreamSynchronize(st));
+  }
   if (stats) {
     stats->iters = iters;
     stats->refinements = refinements;
     stats->rel_residual = rel;
-    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->seconds = pred ? 0.0 : std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     stats->status = s;
   }
   return s;
@@ -1824,20 +1844,19 @@ extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, doub
   sem_solve_opts lo = o;
   lo.warm_start = 1;
   sem_status first_err = SEM_OK;
+  int solved = 0;   // stage solves launched (their events are current)
   for (int sidx = 0; sidx < 4; ++sidx) {
     const double* se = sidx == 0 ? eta : ye;
     const double* sp = sidx == 0 ? phi_s : yp;
     launch_recover_dx(h, d, se, ex, sp, px, st);
+    // a non-positive water column found here ends the stage solve at its
+    // first cycle (the solve's kernels read the status word), so the step
+    // does not wait for the device before the solve
     launch_coef(h, d, se, ex, 3, st);
-    int32_t w = 0;
-    s = read_status(M, st, &w);
-    if (s) {
-      first_err = s;
-      break;
-    }
     sem_solve_stats ls{};
     const StagePredict pred{sidx, o.predict, dt};
     s = laplace_core(M, sp, phi_ws, &lo, &ls, st, &pred);
+    ++solved;
     if (stats) stats[sidx] = ls;
     if (s) {
       first_err = s;
@@ -1854,8 +1873,16 @@ extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, doub
     else
       launch_rk4_stage(ns, 0.0, wts[sidx], 0, eta, phi_s, ke, kp, ye, yp, ae, ap, st);
   }
-  if (first_err) return first_err;
+  if (first_err) {
+    (void)hipStreamSynchronize(st);
+    if (stats)
+      for (int k = 0; k < solved; ++k) stats[k].seconds = solve_seconds(M->solve_ev[k]);
+    return first_err;
+  }
   launch_rk4_final(h, d, dt, ae, ap, eta, phi_s, M->sf != 1.0 ? 1 : 0, st);
-  return read_status(M, st, nullptr);
+  s = read_status(M, st, nullptr);
+  if (stats)
+    for (int k = 0; k < solved; ++k) stats[k].seconds = solve_seconds(M->solve_ev[k]);
+  return s;
 }
 
