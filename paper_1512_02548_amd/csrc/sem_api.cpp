@@ -1449,8 +1449,8 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
     launch_solve_update_fused(n, B.Z, h.H, m, h.ks, x, st);
     if ((seen & PROG_CONV) && !M->kt_on) {
       // converged: the progress block carries the final scalars (released
-      // with the word), so no readback; the caller's synchronisation at the
-      // end of the solve covers the queued update
+      // with the word), so no readback; the queued update runs in stream
+      // order before anything that reads x
       const volatile double* sc = reinterpret_cast<const volatile double*>(M->prog_host) + 1;
       hks = KrylovState{};
       hks.resid = sc[0];

@@ -83,3 +83,22 @@ def test_predict_out_of_range_is_rejected():
     spec, m, eta, phi, ws = stream_tank(nx=8, nz=1, P=4)
     code, _ = m.rk4_step(eta, phi, ws, spec.dt, lib.default_opts(warm_start=1, predict=7), raise_on_error=False)
     assert code == lib.SEM_E_INVAL
+
+
+def test_stage_solve_times_from_device_events():
+    """The step does not wait for the device around its stage solves; each
+    stage solve reports the device time between its first and last launch:
+    positive, and together no longer than the step's wall time."""
+    import time
+    import torch
+    from paper_1512_02548_amd import lib
+    spec, m, eta, phi, ws = stream_tank()
+    opts = lib.default_opts(rtol=1e-12, warm_start=1)
+    m.rk4_step(eta, phi, ws, spec.dt, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = m.rk4_step(eta, phi, ws, spec.dt, opts)
+    wall = time.perf_counter() - t0
+    secs = [s["seconds"] for s in st]
+    assert len(secs) == 4 and all(s > 0 for s in secs), secs
+    assert sum(secs) <= wall, (secs, wall)
