@@ -226,6 +226,26 @@ def test_rk4_domain_error_is_transactional():
     assert np.array_equal(host(e_t), eta) and np.array_equal(host(p_t), phi)
 
 
+def test_rk4_nonfinite_surface_is_transactional():
+    """A NaN in the surface elevation: the coefficient update flags it, the
+    first stage solve ends at its first cycle, NONFINITE is returned and the
+    state is left untouched; the next step from a clean state succeeds."""
+    case = CASES[0]
+    pair, eta, phi = make_pair(case)
+    bad = eta.copy()
+    bad[5] = np.nan
+    e_t, p_t = cuda(bad), cuda(phi)
+    ws = cuda(np.zeros(pair.m.n))
+    code, st = pair.m.rk4_step(e_t, p_t, ws, 0.01, raise_on_error=False)
+    assert code == pair.lib.SEM_E_NONFINITE
+    assert np.array_equal(host(p_t), phi)
+    assert np.array_equal(np.isnan(host(e_t)), np.isnan(bad))
+    e_t, ws = cuda(eta), cuda(np.zeros(pair.m.n))
+    pair.m.reset_history()
+    code, _ = pair.m.rk4_step(e_t, p_t, ws, 0.01, raise_on_error=False)
+    assert code == pair.lib.SEM_OK
+
+
 @pytest.mark.parametrize("case", [CASES[1], CASES[2]])
 @pytest.mark.parametrize("prec", [1, 2])
 def test_laplace_solve_mixed_precision(case, prec):
