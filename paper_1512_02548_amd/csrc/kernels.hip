@@ -774,10 +774,16 @@ k_residual_cycle(const TankDev* __restrict__ td, int64_t n, const T* __restrict_
 // End of a Krylov cycle in one launch: every workgroup solves the small
 // triangular system for y (one thread, the order of the separate solve) and
 // then updates its part of x += Z y.
+__device__ inline const double* hist_slot(const TankDev& d, int stage, const StageHistory& hs, int back);
+__device__ inline int64_t surface_slot(const TankDev& d, int64_t i);
+
+// td set (FP64, the solve's last cycle): the end of the Laplace solve in the
+// same pass, the values of k_solve_end (x is the tank's xs)
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_solve_update(int64_t n, const T* __restrict__ Z, const double* __restrict__ Hbase, int m,
-               const KrylovState* __restrict__ ks, T* __restrict__ x) {
+               const KrylovState* __restrict__ ks, T* __restrict__ x, const TankDev* __restrict__ td,
+               const double* __restrict__ phis, double* __restrict__ phi, int stage) {
   __shared__ double ys[kMaxRestart];
   const int jn = ks->j;
   if (threadIdx.x == 0) {
@@ -802,6 +808,13 @@ k_solve_update(int64_t n, const T* __restrict__ Z, const double* __restrict__ Hb
       if (k0 + u < jn) v += ys[k0 + u] * (double)zz[u];
   }
   x[i] = T(v);
+  if (td) {
+    const TankDev& d = *td;
+    const int64_t sl = surface_slot(d, i);
+    const double pv = sl >= 0 ? phis[sl] : (double)T(v);
+    phi[i] = pv;
+    if (stage >= 0) const_cast<double*>(hist_slot(d, stage, *d.hs, 0))[i] = pv - d.pv[i];
+  }
 }
 
 // r32 = (float)(r * scale)
@@ -1655,12 +1668,14 @@ void launch_scale_next(int64_t n, int j, const float* w, float* V, const double*
   hipLaunchKernelGGL(k_scale_next<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, j, w, V, H, m, ks);
 }
 void launch_solve_update_fused(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_solve_update<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
+                               hipStream_t st, const TankDev* d, const double* phis, double* phi, int stage) {
+  hipLaunchKernelGGL(k_solve_update<double>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x, d, phis,
+                     phi, stage);
 }
 void launch_solve_update_fused(int64_t n, const float* Z, double* H, int m, KrylovState* ks, float* x,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_solve_update<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x);
+  hipLaunchKernelGGL(k_solve_update<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x,
+                     (const TankDev*)nullptr, (const double*)nullptr, (double*)nullptr, -1);
 }
 void launch_fix_norm(const TankDev& h, const TankDev* d, int64_t n, double* b, const double* side, double* part,
                      int ldp, double* out, int32_t* counter, hipStream_t st) {

@@ -97,7 +97,8 @@ void launch_residual_cycle(const TankDev& h, const TankDev* d, int64_t n, const 
                            int32_t* mirror, hipStream_t st);
 // y from the small triangular system and x += Z y, one launch
 void launch_solve_update_fused(int64_t n, const double* Z, double* H, int m, KrylovState* ks, double* x,
-                               hipStream_t st);
+                               hipStream_t st, const TankDev* d = nullptr, const double* phis = nullptr,
+                               double* phi = nullptr, int stage = -1);
 void launch_solve_update_fused(int64_t n, const float* Z, double* H, int m, KrylovState* ks, float* x,
                                hipStream_t st);
 void launch_rk4_final(const TankDev& h, const TankDev* d, double dt, const double* acce, const double* accp,

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <memory>
 #include <new>
 #include <set>
@@ -1288,6 +1289,14 @@ struct GmresCfg {
   int gstore;   // FP32 path: 1 = FP32 factors, 2 = bfloat16 factors
   int ks_ready;   // the Krylov state was reset by the solve's first kernel
   int bnorm_ready;   // ||b||^2 is already in scal[1] (b fixed up)
+  // FP64 Laplace solves: the end of the solve (Phi, the stage record) done by
+  // the last cycle's update; `done` says whether it was
+  struct End {
+    const double* phis;
+    double* phi;
+    int stage;
+    bool done;
+  }* end = nullptr;
 };
 
 struct KrylovBuf {
@@ -1446,8 +1455,18 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       }
       if (stop) break;
     }
-    launch_solve_update_fused(n, B.Z, h.H, m, h.ks, x, st);
-    if ((seen & PROG_CONV) && !M->kt_on) {
+    const bool last = (seen & PROG_CONV) && !M->kt_on;
+    if constexpr (std::is_same<T, double>::value) {
+      if (last && cfg.end) {
+        launch_solve_update_fused(n, B.Z, h.H, m, h.ks, x, st, d, cfg.end->phis, cfg.end->phi, cfg.end->stage);
+        cfg.end->done = true;
+      } else {
+        launch_solve_update_fused(n, B.Z, h.H, m, h.ks, x, st);
+      }
+    } else {
+      launch_solve_update_fused(n, B.Z, h.H, m, h.ks, x, st);
+    }
+    if (last) {
       // converged: the progress block carries the final scalars (released
       // with the word), so no readback; the queued update runs in stream
       // order before anything that reads x
@@ -1669,8 +1688,10 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   int iters = 0, refinements = 0;
   double rel = 0;
   sem_status s = SEM_OK;
+  GmresCfg::End end{phi_s, phi, pred ? pred->stage : -1, false};
   if (fp64) {
     GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->rtol, o->max_iter, o->lookahead, 0, 1, 1};
+    cfg.end = &end;
     s = gmres(M, cfg, buf64(M), h.xs, h.b, &iters, &rel, st);
   } else {
     const int ldp = M->m + 2;
@@ -1719,7 +1740,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   }
   if (s == SEM_E_NOCONV) set_status_bits(M, ST_NOCONV, st);
   // Phi = x_F + lift; a stage solve's change into the record
-  launch_solve_end(h, d, phi_s, phi, pred ? pred->stage : -1, st);
+  if (!end.done) launch_solve_end(h, d, phi_s, phi, pred ? pred->stage : -1, st);
   if (pred) {
     HIPCHK(hipEventRecord(ev[1], st));
   } else {
