@@ -719,22 +719,6 @@ __global__ void k_residual(const TankDev* __restrict__ td, int64_t n, const T* _
   r[i] = v;
 }
 
-// b's shared-line fix-up and ||b||^2 in one launch (out = ||b||^2): the
-// values of the fix-up pass followed by the fused inner product
-__global__ void __launch_bounds__(kBlockThreads)
-k_fix_norm(const TankDev* __restrict__ td, int64_t n, double* __restrict__ b, const double* __restrict__ side,
-           double* __restrict__ part, int ldp, double* __restrict__ out, int64_t chunk, int32_t* __restrict__ counter) {
-  const TankDev& d = *td;
-  self_dot_partial(n, chunk, blockIdx.x, part, ldp, [&](int64_t i) {
-    const double v = fixed_value<double>(d, b, side, i);
-    b[i] = v;
-    return v;
-  });
-  if (!last_block(counter, gridDim.x)) return;
-  dots_reduce(1, part, ldp, out, gridDim.x);
-  if (threadIdx.x == 0) *counter = 0;
-}
-
 // Start of a Krylov cycle in one launch: r = b - y (y's fix-up folded in,
 // masked at the surface) into V_0, ||r||^2 into rr[0], and in the last
 // workgroup the cycle start (beta, the Givens right side, convergence at
@@ -742,20 +726,51 @@ k_fix_norm(const TankDev* __restrict__ td, int64_t n, double* __restrict__ b, co
 // product and cycle-start kernels.
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
-k_residual_cycle(const TankDev* __restrict__ td, int64_t n, const T* __restrict__ bvec, const T* __restrict__ y,
+k_residual_cycle(const TankDev* __restrict__ td, int64_t n, T* __restrict__ bvec, const T* __restrict__ y,
                  const T* __restrict__ side, T* __restrict__ r, int mask, double* __restrict__ part, int ldp,
                  double* __restrict__ rr, int64_t chunk, int32_t* __restrict__ counter, KrylovState* __restrict__ ks,
                  double* __restrict__ Hbase, int m, int first, int32_t* __restrict__ status,
-                 int32_t* __restrict__ mirror) {
+                 int32_t* __restrict__ mirror, const T* __restrict__ bside) {
   const TankDev& d = *td;
-  self_dot_partial(n, chunk, blockIdx.x, part, ldp, [&](int64_t i) {
-    T v = bvec[i] - fixed_value<T>(d, y, side, i);
-    if (mask && is_surface_node(d, i)) v = T(0);
-    r[i] = v;
-    return (double)v;
-  });
+  if (bside) {
+    // b's own shared-line fix-up (its contributions in bside) in the same
+    // pass, kept in b, and ||b||^2 into rr[1] beside ||r||^2 (each sum in the
+    // order of the separate fix-up-and-norm kernel)
+    __shared__ double red2[2][4];
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(lo + chunk, n);
+    double s0 = 0, s1 = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const T bf = fixed_value<T>(d, bvec, bside, i);
+      bvec[i] = bf;
+      T v = bf - fixed_value<T>(d, y, side, i);
+      if (mask && is_surface_node(d, i)) v = T(0);
+      r[i] = v;
+      const double dv = (double)v, db = (double)bf;
+      s0 += dv * dv;
+      s1 += db * db;
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if ((threadIdx.x & 63) == 0) {
+      red2[0][threadIdx.x >> 6] = s0;
+      red2[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      part[(size_t)blockIdx.x * ldp] = ((red2[0][0] + red2[0][1]) + red2[0][2]) + red2[0][3];
+      part[(size_t)blockIdx.x * ldp + 1] = ((red2[1][0] + red2[1][1]) + red2[1][2]) + red2[1][3];
+    }
+  } else {
+    self_dot_partial(n, chunk, blockIdx.x, part, ldp, [&](int64_t i) {
+      T v = bvec[i] - fixed_value<T>(d, y, side, i);
+      if (mask && is_surface_node(d, i)) v = T(0);
+      r[i] = v;
+      return (double)v;
+    });
+  }
   if (!last_block(counter, gridDim.x)) return;
-  dots_reduce(1, part, ldp, rr, gridDim.x);
+  dots_reduce(bside ? 2 : 1, part, ldp, rr, gridDim.x);
+  if (bside) __syncthreads();   // rr[1] comes from the second wave
   if (threadIdx.x == 0) {
     *counter = 0;
     if (*status) {
@@ -1677,35 +1692,30 @@ void launch_solve_update_fused(int64_t n, const float* Z, double* H, int m, Kryl
   hipLaunchKernelGGL(k_solve_update<float>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, Z, H, m, ks, x,
                      (const TankDev*)nullptr, (const double*)nullptr, (double*)nullptr, -1);
 }
-void launch_fix_norm(const TankDev& h, const TankDev* d, int64_t n, double* b, const double* side, double* part,
-                     int ldp, double* out, int32_t* counter, hipStream_t st) {
-  int nc;
-  int64_t chunk;
-  dot_layout(n, &nc, &chunk);
-  hipLaunchKernelGGL(k_fix_norm, dim3(nc), dim3(kBlockThreads), 0, st, d, n, b, side, part, ldp, out, chunk, counter);
-}
 template <typename T>
 static void residual_cycle_t(const TankDev* d, int64_t n, const T* b, const T* y, const T* side, T* r, int mask,
                              double* part, int ldp, double* rr, int32_t* counter, KrylovState* ks, double* H, int m,
-                             int first, int32_t* status, int32_t* mirror, hipStream_t st) {
+                             int first, int32_t* status, int32_t* mirror, hipStream_t st, const T* bside) {
   int nc;
   int64_t chunk;
   dot_layout(n, &nc, &chunk);
-  hipLaunchKernelGGL(k_residual_cycle<T>, dim3(nc), dim3(kBlockThreads), 0, st, d, n, b, y, side, r, mask, part, ldp,
-                     rr, chunk, counter, ks, H, m, first, status, mirror);
+  hipLaunchKernelGGL(k_residual_cycle<T>, dim3(nc), dim3(kBlockThreads), 0, st, d, n, const_cast<T*>(b), y, side, r,
+                     mask, part, ldp, rr, chunk, counter, ks, H, m, first, status, mirror, bside);
   hipLaunchKernelGGL(k_scale_v0<T>, dim3(nblk(n)), dim3(kBlockThreads), 0, st, n, r, ks);
 }
 void launch_residual_cycle(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y,
                            const double* side, double* r, int mask, double* part, int ldp, double* rr,
                            int32_t* counter, KrylovState* ks, double* H, int m, int first, int32_t* status,
-                           int32_t* mirror, hipStream_t st) {
-  residual_cycle_t<double>(d, n, b, y, side, r, mask, part, ldp, rr, counter, ks, H, m, first, status, mirror, st);
+                           int32_t* mirror, hipStream_t st, const double* bside) {
+  residual_cycle_t<double>(d, n, b, y, side, r, mask, part, ldp, rr, counter, ks, H, m, first, status, mirror, st,
+                           bside);
 }
 void launch_residual_cycle(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y,
                            const float* side, float* r, int mask, double* part, int ldp, double* rr,
                            int32_t* counter, KrylovState* ks, double* H, int m, int first, int32_t* status,
                            int32_t* mirror, hipStream_t st) {
-  residual_cycle_t<float>(d, n, b, y, side, r, mask, part, ldp, rr, counter, ks, H, m, first, status, mirror, st);
+  residual_cycle_t<float>(d, n, b, y, side, r, mask, part, ldp, rr, counter, ks, H, m, first, status, mirror, st,
+                          (const float*)nullptr);
 }
 void launch_residual(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y, double* r,
                      int mask, hipStream_t st) {

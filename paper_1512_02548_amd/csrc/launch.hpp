@@ -83,14 +83,13 @@ void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y
 void launch_solve_begin(const TankDev& h, const TankDev* d, const double* phis, double* u, const double* ws,
                         int stage, int maxdepth, double dt, double rtol, int init_ks, hipStream_t st);
 void launch_solve_end(const TankDev& h, const TankDev* d, const double* phis, double* phi, int stage, hipStream_t st);
-// b's fix-up and ||b||^2 (out) in one launch
-void launch_fix_norm(const TankDev& h, const TankDev* d, int64_t n, double* b, const double* side, double* part,
-                     int ldp, double* out, int32_t* counter, hipStream_t st);
 // r = b - y (fix-up folded in) into V_0, ||r||^2 into rr[0], the cycle start; then V_0 /= beta
+// bside (FP64 Laplace solves, first cycle): b's shared-line contributions;
+// b is fixed up in place and ||b||^2 goes to rr[1]
 void launch_residual_cycle(const TankDev& h, const TankDev* d, int64_t n, const double* b, const double* y,
                            const double* side, double* r, int mask, double* part, int ldp, double* rr,
                            int32_t* counter, KrylovState* ks, double* H, int m, int first, int32_t* status,
-                           int32_t* mirror, hipStream_t st);
+                           int32_t* mirror, hipStream_t st, const double* bside = nullptr);
 void launch_residual_cycle(const TankDev& h, const TankDev* d, int64_t n, const float* b, const float* y,
                            const float* side, float* r, int mask, double* part, int ldp, double* rr,
                            int32_t* counter, KrylovState* ks, double* H, int m, int first, int32_t* status,

@@ -1288,7 +1288,8 @@ struct GmresCfg {
   int ahead;   // Krylov steps queued ahead of the device
   int gstore;   // FP32 path: 1 = FP32 factors, 2 = bfloat16 factors
   int ks_ready;   // the Krylov state was reset by the solve's first kernel
-  int bnorm_ready;   // ||b||^2 is already in scal[1] (b fixed up)
+  int bnorm_ready;   // ||b||^2 is already in scal[1] (b fixed up), or comes with the first residual
+  const double* bside = nullptr;   // FP64: b's shared-line contributions, fixed up by the first residual pass
   // FP64 Laplace solves: the end of the solve (Phi, the stage record) done by
   // the last cycle's update; `done` says whether it was
   struct End {
@@ -1405,8 +1406,13 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       sem_status e = stiff_timed(M, cfg, x, B.w, B.side, flags | F_NOFIX, st);
       if (e) return e;
     }
-    launch_residual_cycle(h, d, n, b, B.w, B.side, B.V, cfg.mask ? 1 : 0, h.part, ldp, scal, cnt, h.ks, h.H, m,
-                          first ? 1 : 0, h.status, M->prog_dev, st);
+    if constexpr (std::is_same<T, double>::value) {
+      launch_residual_cycle(h, d, n, b, B.w, B.side, B.V, cfg.mask ? 1 : 0, h.part, ldp, scal, cnt, h.ks, h.H, m,
+                            first ? 1 : 0, h.status, M->prog_dev, st, first ? cfg.bside : nullptr);
+    } else {
+      launch_residual_cycle(h, d, n, b, B.w, B.side, B.V, cfg.mask ? 1 : 0, h.part, ldp, scal, cnt, h.ks, h.H, m,
+                            first ? 1 : 0, h.status, M->prog_dev, st);
+    }
     first = false;
     int32_t seen = 0;   // the progress word that ended the cycle
     // with the exact still-water inverse, V_j = w / h_{j,j-1} is formed while
@@ -1678,10 +1684,12 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   // Krylov state; then b = -(A u)_F
   launch_solve_begin(h, d, phi_s, h.tmp, o->warm_start ? phi : nullptr, pred ? pred->stage : -1,
                      pred ? pred->depth : 0, pred ? pred->dt : 0.0, o->rtol, fp64 ? 1 : 0, st);
+  // FP64: the lift's shared-line contributions go to a second side buffer
+  // (the operator applies of the cycles use the first); the first residual
+  // pass fixes b up and forms ||b||^2
+  double* bside = h.side + 2 * (size_t)h.nb * h.nl;
   if (fp64) {
-    // the lift's shared-line fix-up and ||b||^2 in one launch
-    launch_gather(h, d, OP_STIFF, h.tmp, h.b, h.side, F_MASK_SURF | F_NEG | F_NOFIX, st);
-    launch_fix_norm(h, d, n, h.b, h.side, h.part, M->m + 2, M->scal + 1, &h.ks->pad[0], st);
+    launch_gather(h, d, OP_STIFF, h.tmp, h.b, bside, F_MASK_SURF | F_NEG | F_NOFIX, st);
   } else {
     launch_gather(h, d, OP_STIFF, h.tmp, h.b, h.side, F_MASK_SURF | F_NEG, st);
   }
@@ -1691,6 +1699,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   GmresCfg::End end{phi_s, phi, pred ? pred->stage : -1, false};
   if (fp64) {
     GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->rtol, o->max_iter, o->lookahead, 0, 1, 1};
+    cfg.bside = bside;
     cfg.end = &end;
     s = gmres(M, cfg, buf64(M), h.xs, h.b, &iters, &rel, st);
   } else {
