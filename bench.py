@@ -11,7 +11,7 @@ HBM.  A step is one RK4 step.
 
 value = Laplace-solve GDOF/s = sum over solves of n_free / sum of solve times.
 
-Prints one JSON line.  --gpus above 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 exits: the library runs on one GPU.
 """
 import argparse
 import json
@@ -304,7 +304,7 @@ def main():
     ap.add_argument("--streams", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the library runs on one GPU; runs on several GPUs are not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
