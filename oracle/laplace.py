@@ -30,8 +30,8 @@ pin in the tests shows both behaviours); it is kept here as
 The Dirichlet condition Phi = phi~ on S^FS (eq. "eq:FSeqs") is imposed by
 moving the surface columns to the right-hand side:
 A_FF Phi_F = -A_FS phi~.  The oracle solves with sparse LU (scipy splu), the
-paper's solver class; a reference right-preconditioned GMRES with the
-library's preconditioner is provided for iteration-count comparisons.
+paper's solver class; a reference right-preconditioned GMRES with a plain
+element-block-Jacobi preconditioner is provided for Krylov cross-checks.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -140,7 +140,8 @@ def block_jacobi(mesh, A0, dirichlet=True):
     """Element-block Jacobi (additive Schwarz on element patches):
     B = sum_k R_k^T W_k C_k^{-1} W_k R_k, C_k = principal submatrix of the
     assembled A0 on element k's (free) nodes, W_k = diag(mult^{-1/2}).
-    The paper leaves the preconditioner open; this is the library's choice.
+    The paper leaves the preconditioner open; this is a plain reference
+    choice for the Krylov cross-checks.
     Returns a function r -> z on full-length vectors (surface entries 0)."""
     A0 = A0.tocsr()
     w = 1.0 / np.sqrt(mesh.mult)

@@ -139,7 +139,7 @@ def _equispaced_interp(P, values, t):
     return out
 
 
-def warp_blend_nodes(P):
+def warp_blend_nodes(P, alpha=None):
     """Warburton's warp-and-blend nodes on the reference triangle
     {(-1,-1), (1,-1), (-1,1)} in (r, s) coordinates.
 
@@ -153,10 +153,12 @@ def warp_blend_nodes(P):
     1 - t^2, so edge nodes land exactly on the GLL points.
 
     Node order: rows of constant s from s = -1 upward, r increasing in a row.
+    alpha: blending parameter; None takes the published optimum for P.
     """
     if P == 0:
         return np.array([-1.0 / 3.0]), np.array([-1.0 / 3.0])
-    alpha = ALPHA_OPT[P] if P < len(ALPHA_OPT) else 5.0 / 3.0
+    if alpha is None:
+        alpha = ALPHA_OPT[P] if P < len(ALPHA_OPT) else 5.0 / 3.0
     lamA, lamB, lamC = [], [], []
     for j in range(P + 1):
         for i in range(P + 1 - j):

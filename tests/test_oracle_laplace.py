@@ -186,3 +186,43 @@ def test_over_integration_exact_for_polynomial_products():
     assert max(np.max(np.abs(ae - te)), np.max(np.abs(ap - tp))) > 1e-4
     I, Mf = fine_grid(P, 3 * P)
     assert I.shape == (3 * P + 1, P + 1) and np.allclose(gll_nodes(3 * P)[[0, -1]], [-1, 1])
+
+
+def test_K_matches_sigma_map_jacobian_on_sloping_bed():
+    """K = J J^T / det J with J = d(x, sigma)/d(x, z) of the sigma-map
+    sigma(x, z) = (z + h(x)) / (eta(x) + h(x)) (Sec. 2, eqs. sigtrans and
+    jacobian).  J is taken here by complex-step differentiation of the map
+    itself at the physical position of every element node of a sloping-bed
+    tank, independently of the closed form in coefficients().  eta and h are
+    global polynomials of degree <= P so that the column interpolants are
+    exact; G = |J^k| Lam K Lam^T is compared at every node."""
+    P = 4
+    m = Mesh(5, 3, P, 4.0, False)
+    eta_f = lambda x: 0.12 - 0.03 * x + 0.01 * x ** 3 - 0.0015 * x ** 4
+    h_f = lambda x: 1.0 - 0.09 * x + 0.02 * x ** 2
+    etax_f = lambda x: -0.03 + 0.03 * x ** 2 - 0.006 * x ** 3
+    hx_f = lambda x: -0.09 + 0.04 * x
+    xs = m.xs_surf
+    G, d = lap.coefficients(m, eta_f(xs), etax_f(xs), h_f(xs), hx_f(xs))
+
+    def sigma(x, z):
+        return (z + h_f(x)) / (eta_f(x) + h_f(x))
+
+    x = m.ex
+    z = m.esig * (eta_f(x) + h_f(x)) - h_f(x)
+    step = 1e-30
+    sx = np.imag(sigma(x + 1j * step, z)) / step
+    sz = np.imag(sigma(x, z + 1j * step)) / step
+    det = sz
+    Kref = np.empty(x.shape + (2, 2))
+    Kref[..., 0, 0] = 1.0 / det
+    Kref[..., 0, 1] = sx / det
+    Kref[..., 1, 0] = sx / det
+    Kref[..., 1, 1] = (sx * sx + sz * sz) / det
+    Gref = np.einsum("kac,kicd,kbd->kiab", m.Lam, Kref, m.Lam) * m.J[:, None, None, None]
+    assert np.max(np.abs(d - 1.0 / sz)) < 1e-13
+    assert np.max(np.abs(G[..., 0] - Gref[..., 0, 0])) < 1e-12
+    assert np.max(np.abs(G[..., 1] - Gref[..., 0, 1])) < 1e-12
+    assert np.max(np.abs(G[..., 2] - Gref[..., 1, 1])) < 1e-12
+    # the bed slope really enters: a quarter of the nodes see |q| > 0.02
+    assert np.mean(np.abs(sx / sz) > 0.02) > 0.25

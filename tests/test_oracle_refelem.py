@@ -152,3 +152,32 @@ def test_filter_properties(P, ic, sf):
 def test_filter_rejects_vertex_modes():
     with pytest.raises(ValueError):
         filter_matrix(6, 1, 0.9)
+
+
+def lebesgue_constant(r, s, P, n=120):
+    """max over a uniform sample of the reference triangle of sum_i |l_i|,
+    with the Lagrange basis of the node set (r, s) evaluated through the
+    orthonormal simplex basis."""
+    from oracle.refelem import simplex_basis, simplex_modes
+    modes = simplex_modes(P)
+    V = np.stack([simplex_basis(r, s, i, j) for i, j in modes], axis=1)
+    g = np.linspace(-1.0, 1.0, n + 1)
+    R, S = np.meshgrid(g, g)
+    inside = R + S <= 1e-12
+    Vs = np.stack([simplex_basis(R[inside], S[inside], i, j) for i, j in modes], axis=1)
+    return np.abs(Vs @ np.linalg.inv(V)).sum(axis=1).max()
+
+
+@pytest.mark.parametrize("P", [6, 7, 8, 9])
+def test_alpha_opt_minimises_lebesgue_constant(P):
+    """Warburton's alpha_opt is defined as the blending parameter that
+    minimises the Lebesgue constant of the warp-and-blend nodes.  The nodes
+    the oracle builds for order P (through its table lookup) must therefore
+    beat alpha = 0 and the table entries of the neighbouring orders, and lie
+    within 0.5% of the best value on an alpha grid."""
+    from oracle.refelem import ALPHA_OPT, warp_blend_nodes
+    lam = lebesgue_constant(*warp_blend_nodes(P), P)
+    others = [lebesgue_constant(*warp_blend_nodes(P, a), P) for a in (0.0, ALPHA_OPT[P - 1], ALPHA_OPT[P + 1])]
+    assert lam < min(others) - 1e-3
+    grid = [lebesgue_constant(*warp_blend_nodes(P, a), P) for a in np.linspace(0.5, 2.0, 16)]
+    assert lam < 1.005 * min(grid)

@@ -125,9 +125,7 @@ def test_linearised_spectrum_resolved_modes():
     eta_t = DtN phi~, phi~_t = -g eta, so its eigenvalues are +-i sqrt(g mu)
     with mu the eigenvalues of the discrete Dirichlet-to-Neumann map.  The
     resolved modes reproduce mu_k = k tanh(kh) (the dispersion relation of
-    Sec. 4.2) and are real to within 1e-3, i.e. purely imaginary lambda.
-    (Grid-scale modes of this triangle discretisation are not: their mu have
-    imaginary parts, which the per-step modal filter damps.)"""
+    Sec. 4.2) and are real to within 1e-3."""
     m = Mesh(5, 2, 6, 2 * np.pi, True)
     mu = np.linalg.eigvals(dtn_matrix(m))
     mu = mu[np.argsort(np.abs(mu))]
@@ -136,5 +134,102 @@ def test_linearised_spectrum_resolved_modes():
         pair = mu[2 * kk - 1: 2 * kk + 1]
         assert np.all(np.abs(pair.real - kk * np.tanh(kk)) < 2e-3 * kk)
         assert np.all(np.abs(pair.imag) < 1e-3 * kk)
-    lam = np.sqrt(-9.81 * mu[1:7].astype(complex))
-    assert np.max(np.abs(lam.real)) < 0.03 * np.max(np.abs(lam.imag))
+
+
+def quad_dtn_matrix(nx, P, Pz, L=2 * np.pi, h=1.0):
+    """The same Dirichlet-to-Neumann map on the paper's own 2D element
+    (Sec. 3.1.4: tensor-product quadrilaterals, order P in x, one layer of
+    order Pz in sigma, still water, flat bed), assembled from the oracle's
+    1D operators: A = h K_x (x) M_s + (1/h) M_x (x) K_s, harmonic extension
+    with Phi = phi~ on top, then w from the 2D projection M w = S_z Phi."""
+    from oracle.refelem import Ref1D
+    rx, rz = Ref1D(P), Ref1D(Pz)
+
+    def glob(ne, p, Me, periodic):
+        n = ne * p + (0 if periodic else 1)
+        out = np.zeros((n, n))
+        for e in range(ne):
+            idx = [(e * p + j) % n for j in range(p + 1)]
+            out[np.ix_(idx, idx)] += Me
+        return out
+
+    jx = 0.5 * L / nx
+    Mx = glob(nx, P, jx * rx.M, True)
+    Kx = glob(nx, P, rx.D.T @ rx.M @ rx.D / jx, True)
+    Mz = glob(1, Pz, 0.5 * rz.M, False)
+    Kz = glob(1, Pz, 2.0 * rz.D.T @ rz.M @ rz.D, False)
+    Sz = glob(1, Pz, rz.M @ rz.D, False)
+    A = h * np.kron(Kx, Mz) + np.kron(Mx, Kz) / h
+    nzn = Pz + 1
+    top = np.arange(nx * P) * nzn + Pz
+    free = np.setdiff1d(np.arange(nx * P * nzn), top)
+    E = np.zeros((nx * P * nzn, nx * P))
+    E[top, np.arange(nx * P)] = 1.0
+    E[free] = -np.linalg.solve(A[np.ix_(free, free)], A[np.ix_(free, top)])
+    W = np.linalg.solve(np.kron(Mx, Mz), np.kron(Mx, Sz) @ E) / h
+    return W[top]
+
+
+def flux_dtn_matrix(m):
+    """phi~ -> M'^{-1} (A Phi)_S: the surface rows of the Galerkin residual of
+    the harmonic extension (Green's identity), projected onto the surface C0
+    space."""
+    h, hx, z = np.ones(m.ns), np.zeros(m.ns), np.zeros(m.ns)
+    G, _ = lap.coefficients(m, z, z, h, hx)
+    A = lap.stiffness(m, G)
+    s1 = srf.Surface1D(m)
+    cols = []
+    for i in range(m.ns):
+        e = np.zeros(m.ns)
+        e[i] = 1.0
+        cols.append(s1.solve_mass((A @ lap.solve_direct(m, A, e))[m.surf]))
+    return np.array(cols).T
+
+
+def filtered_step_radius(m, D, dt, filt, g=9.81):
+    """Spectral radius of one RK4 step of the linearised system followed by
+    the per-element filter on eta and phi~."""
+    ns = m.ns
+    J = np.zeros((2 * ns, 2 * ns))
+    J[:ns, ns:] = D
+    J[ns:, :ns] = -g * np.eye(ns)
+    Z = dt * J
+    R = np.eye(2 * ns) + Z + Z @ Z / 2 + Z @ Z @ Z / 6 + Z @ Z @ Z @ Z / 24
+    s1 = srf.Surface1D(m)
+    Fs = np.stack([s1.apply_filter(np.eye(ns)[:, i], *filt) for i in range(ns)], axis=1)
+    return np.max(np.abs(np.linalg.eigvals(np.kron(np.eye(2), Fs) @ R)))
+
+
+@pytest.mark.parametrize("nz,P", [(1, 4), (2, 4), (1, 6), (2, 6)])
+def test_linearised_spectrum_full(nz, P):
+    """Full spectrum of the linearised system (Sec. 4.1, Fig. 3).  The paper
+    states a purely imaginary spectrum for its tensor-product elements; the
+    oracle's building blocks reproduce that on quadrilaterals to machine
+    precision.  On the triangle mesh the same w~ projection (Sec. 3.1.3) is
+    not normal: the grid-scale part of the map has complex eigenvalues, with
+    max|Im mu|/max|mu| between 0.25 and 0.5 (measured: 0.47/0.45 at P = 4,
+    0.38/0.35 at P = 6 for nz = 1/2), i.e. growth rates Re(lambda) of
+    1.5-2.5 s^-1 on this 5-column tank.  The Galerkin-flux form of the same
+    map (Green's identity on the assembled operator) is symmetric and real.
+    The modal filter can cancel the growth only when it reaches the lowest
+    bubble mode (ic = 2)."""
+    m = Mesh(5, nz, P, 2 * np.pi, True)
+    D = dtn_matrix(m)
+    mu = np.linalg.eigvals(D)
+    ratio = np.max(np.abs(mu.imag)) / np.max(np.abs(mu))
+    assert 0.25 < ratio < 0.5
+    lam = np.sqrt(-9.81 * mu.astype(complex))
+    assert 1.0 < np.max(np.abs(lam.real)) < 3.0
+    # the paper's elements: real spectrum, max|mu| tame in P at fixed Pz
+    q4, q8 = (np.linalg.eigvals(quad_dtn_matrix(5, p, 4)) for p in (4, 8))
+    assert np.max(np.abs(q8.imag)) < 1e-10 * np.max(np.abs(q8))
+    assert np.max(np.abs(q4.imag)) < 1e-10 * np.max(np.abs(q4))
+    assert np.max(np.abs(q8)) < 1.3 * np.max(np.abs(q4))
+    # the Galerkin-flux map on the same triangles
+    mf = np.linalg.eigvals(flux_dtn_matrix(m))
+    assert np.max(np.abs(mf.imag)) < 1e-10 * np.max(np.abs(mf))
+    assert mf.real.min() > -1e-10
+    if nz == 2 and P == 4:
+        dt = 0.035917
+        assert filtered_step_radius(m, D, dt, (2, 0.9)) < 1.0 + 1e-9
+        assert filtered_step_radius(m, D, dt, (3, 0.0)) > 1.003
