@@ -137,6 +137,18 @@ sem_status sem_mesh_node_coords(const sem_mesh* mesh, double* x_host, double* si
 sem_status sem_mesh_surface_nodes(const sem_mesh* mesh, int64_t* idx_host);
 void sem_mesh_destroy(sem_mesh* mesh);
 
+/* The reference-element operators every mesh of order P is built from (host
+ * work only; all outputs HOST, row-major, any may be NULL):
+ *  r, s [Np]: warp-and-blend nodes of the reference triangle (Sec. 3.1.4);
+ *  Dr, Ds, M [Np x Np]: V_r V^{-1}, V_s V^{-1}, (V V^T)^{-1} (Sec. 3.1.4);
+ *  F [(P+1) x (P+1)]: the 1D modal filter V^ diag(sigma) V^{-1} with modes
+ *    >= ic scaled by sigma_f (Sec. 3.4; ic >= 2);
+ *  I [(Pf+1) x (P+1)]: interpolation from GLL(P) to GLL(Pf) and
+ *  Mf [(Pf+1) x (Pf+1)]: the fine mass matrix (Sec. 3.3).
+ * Np = (P+1)(P+2)/2; 1 <= P <= 10, P <= Pf <= 32. */
+sem_status sem_reference_operators(int32_t P, int32_t Pf, int32_t ic, double sigma_f, double* r, double* s,
+                                   double* Dr, double* Ds, double* M, double* F, double* I, double* Mf);
+
 /* Geometric factors of the sigma-map at every element node (Sec. 2, the
  * Jacobian and K = J J^T / det J with q = (1-sigma) h_x - sigma eta_x):
  * stores G = |J| Lam K Lam^T and 1/d in the workspace.  eta, eta_x: [ns]. */

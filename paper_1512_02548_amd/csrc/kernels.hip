@@ -1818,6 +1818,19 @@ void launch_add_float(int64_t n, const float* x32, double scale, double* x, hipS
 }
 void launch_fill_f(int64_t n, float* y, hipStream_t st) { hipMemsetAsync(y, 0, n * sizeof(float), st); }
 
+// Krylov state of a fresh solve: everything zero (the reductions' completion
+// counter included) except the tolerance
+__global__ void k_ks_reset(KrylovState* ks, double rtol) {
+  if (threadIdx.x == 0) {
+    KrylovState z{};
+    z.rtol = rtol;
+    *ks = z;
+  }
+}
+void launch_ks_reset(KrylovState* ks, double rtol, hipStream_t st) {
+  hipLaunchKernelGGL(k_ks_reset, dim3(1), dim3(64), 0, st, ks, rtol);
+}
+
 void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, double* out0, const double* in1,
                        double* out1, hipStream_t st) {
   hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, 0, in0, out0,

@@ -17,6 +17,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <set>
+#include <utility>
 #include <type_traits>
 
 #include "launch.hpp"
@@ -382,10 +385,22 @@ __host__ __device__ inline int stiff_ops_in_lds(const TankDev& h) {
   return 4 * (size_t)h.NpP * h.NpP * sizeof(T) <= 40 * 1024 ? 1 : 0;
 }
 
-// kernels whose dynamic LDS exceeds the default 64 KiB are allowed more once
+// Kernels whose dynamic LDS exceeds the default 64 KiB get the chip's full
+// 160 KiB cap.  The cap is runtime state shared by every thread that launches
+// the kernel, so it is raised once per (kernel, device), under a lock, before
+// that device's first such launch; concurrent workers (batch mode with several
+// streams) never set it while another thread launches the same kernel.
+static std::mutex g_lds_mu;
+static std::set<std::pair<const void*, int>> g_lds_done;
+
 template <typename K>
 static void allow_lds(K kern, size_t bytes) {
-  if (bytes > 64 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (bytes <= 64 * 1024) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(g_lds_mu);
+  if (g_lds_done.insert({(const void*)kern, dev}).second)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 size_t stiff_mfma_lds_bytes(const TankDev& h, size_t word) {

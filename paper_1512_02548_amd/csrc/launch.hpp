@@ -44,6 +44,7 @@ void launch_sd(const TankDev& h, const TankDev* d, int which, const float* u, fl
                const double* nscale = nullptr, float* vout = nullptr);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
 void launch_fill(int64_t n, double v, double* y, hipStream_t st);
+void launch_ks_reset(KrylovState* ks, double rtol, hipStream_t st);
 void launch_fill_f(int64_t n, float* y, hipStream_t st);
 void launch_mask_surface(const TankDev& h, const TankDev* d, double* y, hipStream_t st);
 void launch_scatter_surface(const TankDev& h, const TankDev* d, const double* phis, double* u, int zero_rest,

@@ -67,6 +67,9 @@ struct sem_mesh {
   // progress word of the running Krylov cycle in pinned host memory (written
   // by the device, read by the host while it queues steps)
   int32_t* prog_host = nullptr;
+  // pinned host block that every small device-to-host readback lands in
+  // (never pageable stack memory: several worker threads may read back at once)
+  void* rb_host = nullptr;
   int32_t* prog_dev = nullptr;
   // live timing of the stiffness kernel (event pairs of the running cycle)
   bool kt_on = false;
@@ -75,10 +78,11 @@ struct sem_mesh {
   int64_t kt_count = 0;
   double kt_ms = 0;
   // start and end events of the stage solves of one RK4 step (slot 0 also
-  // serves a single solve); created on first use
+  // serves a single solve); created when the mesh is bound
   hipEvent_t solve_ev[4][2] = {};
   ~sem_mesh() {
     if (prog_host) (void)hipHostFree(prog_host);
+    if (rb_host) (void)hipHostFree(rb_host);
     for (auto& e : solve_ev)
       for (hipEvent_t x : e)
         if (x) (void)hipEventDestroy(x);

@@ -1077,6 +1077,27 @@ extern "C" sem_status sem_mesh_surface_nodes(const sem_mesh* M, int64_t* idx) {
 
 extern "C" void sem_mesh_destroy(sem_mesh* M) { delete M; }
 
+extern "C" sem_status sem_reference_operators(int32_t P, int32_t Pf, int32_t ic, double sigma_f, double* r,
+                                              double* s, double* Dr, double* Ds, double* Mm, double* F,
+                                              double* I, double* Mf) {
+  if (P < 1 || P > 10 || Pf < P || Pf > 32) return fail(SEM_E_INVAL, "need 1 <= P <= 10 and P <= Pf <= 32");
+  if (ic < 2) return fail(SEM_E_INVAL, "filter cut-off must leave the vertex modes alone (ic >= 2)");
+  const RefTri ref(P);
+  auto out = [](double* dst, const std::vector<double>& v) {
+    if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));
+  };
+  out(r, ref.r);
+  out(s, ref.s);
+  out(Dr, ref.Dr);
+  out(Ds, ref.Ds);
+  out(Mm, ref.M);
+  const Ref1D r1(P), rf(Pf);
+  out(F, filter_matrix(P, ic, sigma_f));
+  out(I, r1.interp_to(rf.r));
+  out(Mf, rf.M);
+  return SEM_OK;
+}
+
 template <class T>
 static T* at(sem_mesh* M, const char* name) {
   return reinterpret_cast<T*>(M->ws + M->off.at(name));
@@ -1096,6 +1117,11 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     M->prog_dev = (int32_t*)dp;
     *(volatile int32_t*)M->prog_host = 0;
   }
+  if (!M->rb_host) HIPCHK(hipHostMalloc(&M->rb_host, 256, hipHostMallocDefault));
+  // the stage solves' timing events, created once per mesh
+  for (auto& e : M->solve_ev)
+    for (auto& x : e)
+      if (!x) HIPCHK(hipEventCreate(&x));
   M->ws = (char*)workspace;
   TankDev& h = M->hd;
   h = TankDev{};
@@ -1270,10 +1296,18 @@ sem_status sem::status_from_word(int32_t w) {
   return SEM_OK;
 }
 
+// Small device-to-host reads go through the mesh's pinned readback block.
+static sem_status readback(sem_mesh* M, void* out, const void* dev, size_t bytes, hipStream_t st) {
+  if (bytes > 256) return fail(SEM_E_INVAL, "readback larger than the pinned block");
+  HIPCHK(hipMemcpyAsync(M->rb_host, dev, bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(out, M->rb_host, bytes);
+  return SEM_OK;
+}
+
 static sem_status read_status(sem_mesh* M, hipStream_t st, int32_t* word) {
   int32_t w = 0;
-  HIPCHK(hipMemcpyAsync(&w, M->hd.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  if (sem_status e = readback(M, &w, M->hd.status, sizeof(w), st)) return e;
   if (word) *word = w;
   sem_status s = status_from_word(w);
   if (s != SEM_OK) return fail(s, "device reported status " + std::to_string(w));
@@ -1391,9 +1425,7 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
   const int ahead = std::max(1, cfg.ahead);
   volatile int32_t* prog = M->prog_host;
   M->kt_used = 0;
-  KrylovState ks0{};
-  ks0.rtol = cfg.rtol;
-  if (!cfg.ks_ready) HIPCHK(hipMemcpyAsync(h.ks, &ks0, sizeof(ks0), hipMemcpyHostToDevice, st));
+  if (!cfg.ks_ready) launch_ks_reset(h.ks, cfg.rtol, st);
   int32_t* cnt = &h.ks->pad[0];
   if (!cfg.bnorm_ready) launch_dots(n, 1, b, 0, b, h.part, ldp, scal + 1, cnt, nullptr, st);
   int total = 0;
@@ -1485,8 +1517,7 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       hks.done = hks.converged = 1;
       break;
     }
-    HIPCHK(hipMemcpyAsync(&hks, h.ks, sizeof(hks), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if (sem_status e = readback(M, &hks, h.ks, sizeof(hks), st)) return e;
     {
       // the cycle's residual apply plus its executed steps; later ones were gated
       sem_status e = stiff_harvest(M, 1 + (size_t)std::max(0, hks.j));
@@ -1504,10 +1535,10 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
 
 static sem_status set_status_bits(sem_mesh* M, int32_t bits, hipStream_t st) {
   int32_t w = 0;
-  HIPCHK(hipMemcpyAsync(&w, M->hd.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  if (sem_status e = readback(M, &w, M->hd.status, sizeof(w), st)) return e;
   w |= bits;
-  HIPCHK(hipMemcpyAsync(M->hd.status, &w, sizeof(int32_t), hipMemcpyHostToDevice, st));
+  std::memcpy(M->rb_host, &w, sizeof(w));
+  HIPCHK(hipMemcpyAsync(M->hd.status, M->rb_host, sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   return SEM_OK;
 }
@@ -1674,11 +1705,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
   const int64_t n = M->n;
   auto t0 = std::chrono::steady_clock::now();
   hipEvent_t* ev = M->solve_ev[pred ? pred->stage : 0];
-  if (pred) {
-    if (!ev[0]) HIPCHK(hipEventCreate(&ev[0]));
-    if (!ev[1]) HIPCHK(hipEventCreate(&ev[1]));
-    HIPCHK(hipEventRecord(ev[0], st));
-  }
+  if (pred) HIPCHK(hipEventRecord(ev[0], st));
   const bool fp64 = o->prec == SEM_PREC_FP64;
   // u = [0; phi~], the start vector xs (warm start, stage predictor), the
   // Krylov state; then b = -(A u)_F
@@ -1709,8 +1736,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
     int32_t* cnt = &h.ks->pad[0];
     HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t), st));
     launch_dots(n, 1, h.b, 0, h.b, h.part, ldp, scal + 4, cnt, nullptr, st);
-    HIPCHK(hipMemcpyAsync(&nb2, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if (sem_status e = readback(M, &nb2, scal + 4, sizeof(nb2), st)) return e;
     double bnorm = std::sqrt(nb2);
     GmresCfg cfg{OP_STIFF, OP_PRE_LAP, true, o->inner_rtol, 0, o->lookahead, o->prec == SEM_PREC_BF16_IR ? 2 : 1};
     s = SEM_E_NOCONV;
@@ -1719,8 +1745,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
       launch_gather(h, d, OP_STIFF, h.xs, h.w, h.side, F_MASK_SURF, st);
       launch_residual(h, d, n, h.b, h.w, h.tmp, 1, st);
       launch_dots(n, 1, h.tmp, 0, h.tmp, h.part, ldp, scal + 4, cnt, nullptr, st);
-      HIPCHK(hipMemcpyAsync(&rr, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
+      if (sem_status e = readback(M, &rr, scal + 4, sizeof(rr), st)) return e;
       double rn = std::sqrt(rr);
       rel = bnorm > 0 ? rn / bnorm : rn;
       if (!std::isfinite(rn)) {

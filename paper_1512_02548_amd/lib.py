@@ -70,6 +70,7 @@ _SIGS = {
     "sem_mesh_node_coords": (C.c_int, [_P, _D, _D]),
     "sem_mesh_surface_nodes": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "sem_mesh_destroy": (None, [_P]),
+    "sem_reference_operators": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_double] + [_D] * 8),
     "sem_set_surface": (C.c_int, [_P, _P, _P, _P]),
     "sem_apply": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "sem_apply_timed": (C.c_int, [_P, C.c_int, C.c_int32, _P, _P, C.c_int32, C.POINTER(C.c_float), _P]),
@@ -293,6 +294,16 @@ class Batch:
         if h is not None and h.value and sem_batch_destroy is not None:
             sem_batch_destroy(h)
             self.handle = None
+
+
+def reference_operators(P, Pf, ic=2, sigma_f=1.0):
+    """The host's reference-element operators (sem_reference_operators)."""
+    Np = (P + 1) * (P + 2) // 2
+    out = dict(r=np.empty(Np), s=np.empty(Np), Dr=np.empty((Np, Np)), Ds=np.empty((Np, Np)), M=np.empty((Np, Np)),
+               F=np.empty((P + 1, P + 1)), I=np.empty((Pf + 1, P + 1)), Mf=np.empty((Pf + 1, Pf + 1)))
+    args = [out[k].ctypes.data_as(_D) for k in ("r", "s", "Dr", "Ds", "M", "F", "I", "Mf")]
+    check(sem_reference_operators(P, Pf, ic, float(sigma_f), *args), "sem_reference_operators")
+    return out
 
 
 def mesh_from_spec(spec, h, hx, **kw):

@@ -236,26 +236,40 @@ def solve(k, h, H, N=20, g=G_ACC, height_steps=None):
     return StreamFunctionWave(k, h, H, g, z[N + 1:2 * N + 1].copy(), *z[2 * N + 1:], Y.copy())
 
 
+def refine(w, N):
+    """The same wave with N modes, by Newton's method started from w (its
+    surface at the new collocation points, its coefficients padded with
+    zeros)."""
+    X = np.arange(N + 1) * np.pi / (N * w.k)
+    B = np.zeros(N)
+    B[:min(N, w.N)] = w.B[:N]
+    z0 = np.concatenate([w.surface_height(X), B, [w.U, w.Q, w.R]])
+    z = _newton(z0, (w.k, w.h, w.H, w.g, N))
+    return StreamFunctionWave(w.k, w.h, w.H, w.g, z[N + 1:2 * N + 1].copy(), *z[2 * N + 1:], z[:N + 1].copy())
+
+
 def solve_resolved(k, h, H, g=G_ACC, tol=1e-11, sizes=(12, 16, 20, 24, 32, 40, 48, 64)):
     """The wave with the smallest number of modes whose dynamic condition,
     checked between the collocation points, holds to tol relative to the
     Bernoulli constant; if none does, the size with the smallest such
     residual.  (More modes than the wave needs only add columns at rounding
-    level and make the collocation system ill-conditioned.)"""
-    best, best_res = None, np.inf
+    level and make the collocation system ill-conditioned.)  The first size
+    is reached by height continuation, the others start from the previous
+    size's wave."""
+    best, best_res, w = None, np.inf, None
     for N in sizes:
         try:
-            w = solve(k, h, H, N=N, g=g)
+            w = solve(k, h, H, N=N, g=g) if w is None else refine(w, N)
         except RuntimeError:
-            continue
+            if w is None:
+                continue
+            break
         X = np.linspace(0.0, np.pi / k, 4 * N + 1)
         _, dyn = w.residuals(X)
         res = np.max(np.abs(dyn)) / abs(w.R)
         if res < best_res:
             best, best_res = w, res
-        if res < tol:
-            break
-        if res > 10 * best_res:
+        if res < tol or res > 10 * best_res:
             break
     if best is None:
         raise RuntimeError("no stream-function solution found")

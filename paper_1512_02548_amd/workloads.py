@@ -1,16 +1,20 @@
 """Seeded synthetic inputs for wave-tank runs.
 
 This module holds no arithmetic of the numerical method: it only draws
-parameters and evaluates closed-form surface fields (linear waves, a
-phase-locked Fourier series, a trapezoidal bar, a JONSWAP-shaped irregular
-train) at surface x-coordinates that the caller supplies.  It is shared by the
+parameters and evaluates surface fields (linear waves, exact stream-function
+waves, a trapezoidal bar, a JONSWAP-shaped irregular train) at surface
+x-coordinates that the caller supplies.  It is shared by the
 product path (bench, serving) and by the tests that feed the same arrays to the
 CPU oracle.
 
 Workloads (sizes are quads in x by layers in sigma, order P):
   standing_wave    8x2, P=4, periodic, kh=1, H/L=0.001, linear standing wave
   stream_series    64x4, P=6, periodic, kh=1, H/L=0.0903 (90% of limiting),
-                   20-mode phase-locked series, Pf=9, filter last 2 modes 0.5%
+                   exact stream-function wave of 20 Fourier modes with a seeded
+                   crest position, Pf=9, filter last 2 modes 0.5%
+  table1           8x1, P=6, periodic, one wavelength of the kh=1, H/L=0.0903
+                   stream-function wave; T/dt = 40, 80, 160; filter and
+                   over-integration switched on and off
   bar_irregular    2048x8, P=6, walls, L=40h, trapezoidal bar, 64-component
                    JONSWAP-shaped train with kh in [0.5, 3]
   batch_tanks      256 periodic flat tanks with random sizes and orders
@@ -18,8 +22,11 @@ Workloads (sizes are quads in x by layers in sigma, order P):
                    half of them over a bar
 """
 from dataclasses import dataclass, field
+from functools import lru_cache
 
 import numpy as np
+
+from . import streamfunction as sfw
 
 G_ACC = 9.81
 SEED_BASE = 20251512
@@ -97,37 +104,75 @@ def stream_series_spec(nx=64, nz=4, P=6, steps=1000):
                     filter_ic=P - 1, filter_sigma=0.995, dt=courant_dt(L, nx, P, c),
                     steps=steps, rtol=1e-12, name=f"stream_series_{nx}x{nz}_P{P}",
                     params=dict(k=k, h=h, HL=0.9 * limiting_steepness(k * h), modes=20,
-                                rho=0.3, seed=SEED_BASE + 2))
+                                seed=SEED_BASE + 2))
 
 
-def series_coefficients(k, h, L, HL, modes, rho, seed):
-    """Phase-locked amplitudes a_j = a1 rho^(j-1) u_j, u_j ~ U[0.8, 1.2],
-    scaled so that max(eta) - min(eta) = HL * L on a fine grid."""
-    rng = np.random.default_rng(seed)
-    u = rng.uniform(0.8, 1.2, modes)
-    a = rho ** np.arange(modes) * u
-    xf = np.linspace(0.0, L, 8192, endpoint=False)
-    eta = (a[:, None] * np.cos(np.arange(1, modes + 1)[:, None] * k * xf[None, :])).sum(0)
-    return a * (HL * L / (eta.max() - eta.min()))
+@lru_cache(maxsize=512)
+def sf_wave(k, h, H, modes=None):
+    """Stream-function wave (exact steady wave of permanent form); modes=None
+    takes as many Fourier modes as the wave needs."""
+    if modes is None:
+        return sfw.solve_resolved(k, h, H, g=G_ACC)
+    return sfw.solve(k, h, H, N=modes, g=G_ACC)
 
 
-def series_state(xs, k, h, a):
-    """eta = sum a_j cos(jkx), phi~ = sum c a_j coth(jkh) sin(jkx) with the
-    carrier's linear phase speed c."""
-    xs = np.asarray(xs, dtype=float)
-    c = omega_linear(k, h) / k
-    j = np.arange(1, len(a) + 1)[:, None]
-    eta = (a[:, None] * np.cos(j * k * xs[None, :])).sum(0)
-    phi = (c * a[:, None] / np.tanh(j * k * h) * np.sin(j * k * xs[None, :])).sum(0)
-    return eta, phi
+def sf_crest(seed, wavelength):
+    """Seeded crest position in [0, wavelength)."""
+    return float(np.random.default_rng(seed).uniform(0.0, wavelength))
 
 
-def stream_series_state(xs, spec):
+def stream_series_state(xs, spec, t=0.0):
+    """The exact stream-function wave of the spec (20 Fourier modes) with its
+    crest at a seeded position, at time t: (eta, phi~, h, h_x)."""
     p = spec.params
-    a = series_coefficients(p["k"], p["h"], spec.length, p["HL"], p["modes"], p["rho"], p["seed"])
-    eta, phi = series_state(xs, p["k"], p["h"], a)
+    k, h = p["k"], p["h"]
+    w = sf_wave(k, h, p["HL"] * 2 * np.pi / k, p["modes"])
+    x0 = sf_crest(p["seed"], w.wavelength)
     xs = np.asarray(xs, dtype=float)
-    return eta, phi, np.full_like(xs, p["h"]), np.zeros_like(xs)
+    eta, phi = w.surface_state(xs - x0, t)
+    return eta, phi, np.full_like(xs, h), np.zeros_like(xs)
+
+
+def stream_series_exact_eta(xs, spec, t):
+    """Elevation of the spec's exact wave at time t (the reference for
+    accuracy measurements)."""
+    return stream_series_state(xs, spec, t)[0]
+
+
+# ------------------------------------------------ Table 1 (filter x over-integration)
+TABLE1_STRATEGIES = (
+    # (name, filter, over-integration order factor); "top": the paper's 5%
+    # off the highest mode; "bubble": every bubble mode (ic = 2) damped at
+    # the rate of the still-water growth of the triangle discretisation
+    ("no_filter_no_overint", None, 1),
+    ("no_filter_overint", None, 2),
+    ("filter_no_overint", "top", 1),
+    ("filter_overint", "top", 2),
+    ("bubble_filter_overint", "bubble", 2),
+)
+# growth rate (1/s) of the still-water linearised system of the 8x1, P = 6
+# triangle tank (kh = 1, h = 1): the rate the bubble filter has to remove
+TABLE1_BUBBLE_RATE = 3.5
+
+
+def table1_spec(steps_per_period, strategy, periods=50.0):
+    """One wavelength of the kh = 1, H/L = 0.0903 stream-function wave on 8
+    elements of order 6 (one layer), as in the paper's Table 1; the filter
+    removes 5% of the amplitude of the highest mode once per step and
+    over-integration uses GLL(2P) nodes."""
+    name, filt, fac = next(s for s in TABLE1_STRATEGIES if s[0] == strategy)
+    k, h, P, nx = 1.0, 1.0, 6, 8
+    L = 2 * np.pi / k
+    w = sf_wave(k, h, 0.9 * limiting_steepness(k * h) * L, None)
+    T = w.period
+    dt = T / steps_per_period
+    ic, sig = {None: (P + 1, 1.0), "top": (P, 0.95), "bubble": (2, float(np.exp(-TABLE1_BUBBLE_RATE * dt)))}[filt]
+    return TankSpec(nx=nx, nz=1, P=P, length=L, periodic=True, Pf=fac * P,
+                    filter_ic=ic, filter_sigma=sig,
+                    dt=dt, steps=int(round(periods * steps_per_period)), rtol=1e-12,
+                    name=f"table1_{strategy}_T{steps_per_period}",
+                    params=dict(k=k, h=h, HL=0.9 * limiting_steepness(k * h), modes=None, seed=SEED_BASE + 6,
+                                period=T, steps_per_period=steps_per_period, strategy=strategy))
 
 
 # ---------------------------------------------- 2048x8 bar, irregular waves
@@ -230,30 +275,31 @@ def batch_tank_specs(count=256, seed=SEED_BASE + 4, steps=200, rtol=1e-10, bar_f
                               Pf=int(np.ceil(1.5 * P)), filter_ic=P + 1 - filter_modes, filter_sigma=filter_sigma,
                               dt=courant_dt(L, nx, P, c), steps=steps, rtol=rtol,
                               name=f"tank{i}_{nx}x{nz}_P{P}",
-                              params=dict(k=k, h=h, HL=frac * limiting_steepness(kh), modes=8,
-                                          rho=0.3, seed=int(rng.integers(0, 2 ** 31)),
+                              params=dict(k=k, h=h, HL=frac * limiting_steepness(kh),
+                                          seed=int(rng.integers(0, 2 ** 31)),
                                           mwav=mwav, bar=bar, crest=crest)))
     return specs
 
 
 def batch_tank_state(xs, spec):
-    """Phase-locked series on the tank's own wavelength; optionally a bar
-    scaled into the middle 60% of the tank."""
+    """The tank's exact stream-function wave (as many modes as it needs),
+    crest at a seeded position; optionally a bar scaled into the middle 60%
+    of the tank (the wave is then the flat-bed wave of the offshore depth)."""
     p = spec.params
     xs = np.asarray(xs, dtype=float)
-    a = series_coefficients(p["k"], p["h"], 2 * np.pi / p["k"],
-                            p["HL"], p["modes"], p["rho"], p["seed"])
-    eta, phi = series_state(xs, p["k"], p["h"], a)
-    h = np.full_like(xs, p["h"])
+    k, h0 = p["k"], p["h"]
+    w = sf_wave(k, h0, p["HL"] * 2 * np.pi / k, None)
+    eta, phi = w.surface_state(xs - sf_crest(p["seed"], w.wavelength))
+    h = np.full_like(xs, h0)
     hx = np.zeros_like(xs)
     if p.get("bar"):
         L = spec.length
         span = 0.6 * L
-        rise = p["h"] - p["crest"]
+        rise = h0 - p["crest"]
         # slopes scaled so that the whole bar fits the middle 60%
         total = rise * (20 + 10) + 0.2 * span
         sc = span / total
-        h, hx = trapezoid_bar(xs, L, spec.nx, p["h"], p["crest"], 0.2 * L, 0.2 * span * sc,
+        h, hx = trapezoid_bar(xs, L, spec.nx, h0, p["crest"], 0.2 * L, 0.2 * span * sc,
                               up=20 * sc, down=10 * sc)
     return eta, phi, h, hx
 

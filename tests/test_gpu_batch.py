@@ -186,3 +186,56 @@ def test_lockstep_graphs_match_direct_launches(prec):
         results.append([(t["eta"].cpu().numpy(), t["phi"].cpu().numpy()) for t in tanks])
     for (e0, p0), (e1, p1) in zip(*results):
         assert np.array_equal(e0, e1) and np.array_equal(p0, p1)
+
+
+def oracle_specs():
+    """Three small periodic tanks for the oracle: one over a bar (P = 4), one
+    of eighth order, one of sixth order with four layers."""
+    specs = wl.batch_tank_specs(count=3, steps=2, bar_fraction=0.0, seed=777)
+    shapes = [(16, 2, 4, True), (12, 2, 8, False), (20, 4, 6, False)]
+    for s, (nx, nz, P, bar) in zip(specs, shapes):
+        s.nx, s.nz, s.P = nx, nz, P
+        s.Pf = int(np.ceil(1.5 * P))
+        s.filter_ic = P - 1
+        s.params["mwav"] = max(1, nx // 8)
+        s.length = s.params["mwav"] * 2 * np.pi / s.params["k"]
+        s.dt = wl.courant_dt(s.length, nx, P, wl.omega_linear(s.params["k"], 1.0) / s.params["k"])
+        s.params["bar"] = bar
+        s.params["crest"] = 0.5
+        s.params["HL"] = 0.4 * wl.limiting_steepness(s.params["k"])
+    return specs
+
+
+def oracle_steps(spec, steps):
+    from oracle.mesh import Mesh as OMesh
+    from oracle.stepper import Tank
+    om = OMesh(spec.nx, spec.nz, spec.P, spec.length, True)
+    eta, phi, h, hx = wl.batch_tank_state(om.xs_surf, spec)
+    tank = Tank(om, h, hx, g=spec.g, Pf=spec.Pf, filt=(spec.filter_ic, spec.filter_sigma))
+    for _ in range(steps):
+        eta, phi = tank.step(eta, phi, spec.dt)
+    return eta, phi
+
+
+@pytest.mark.parametrize("prec,rtol,tol", [(0, 1e-12, 1e-10), (1, 1e-10, 1e-8)])
+def test_lockstep_rk4_matches_oracle(prec, rtol, tol):
+    """Tanks advanced together in the lockstep batch (a bar tank, an
+    eighth-order tank, a four-layer tank) against the oracle's own steps of
+    each tank: FP64 to 1e-10, FP32 refinement to 1e-8 (relative max-norm)."""
+    import torch
+    from paper_1512_02548_amd import lib
+    specs = oracle_specs()
+    steps = 2
+    tanks = [make_tank(s) for s in specs]
+    opts = lib.default_opts(rtol=rtol, warm_start=1, prec=prec, inner_rtol=1e-3, max_iter=20000)
+    b = lib.Batch([t["mesh"] for t in tanks], 0)
+    for _ in range(steps):
+        code, status, _ = b.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks],
+                                     [t["ws"] for t in tanks], [s.dt for s in specs], opts=opts)
+        assert code == 0, status
+    torch.cuda.synchronize()
+    for s, t in zip(specs, tanks):
+        e_o, p_o = oracle_steps(s, steps)
+        e, p = t["eta"].cpu().numpy(), t["phi"].cpu().numpy()
+        assert np.max(np.abs(e - e_o)) / np.max(np.abs(e_o)) < tol, s.name
+        assert np.max(np.abs(p - p_o)) / np.max(np.abs(p_o)) < tol, s.name

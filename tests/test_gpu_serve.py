@@ -61,3 +61,23 @@ def test_server_mix_matches_alone(nstreams):
         a = run_alone(r.spec, r.steps, opts)
         assert np.array_equal(r.result["eta"], a["eta"]), r.rid
     assert rep["p99_latency_s"] >= rep["p50_latency_s"] > 0
+
+
+def test_served_results_match_oracle():
+    """Requests served together (a bar tank, an eighth-order tank, a
+    four-layer tank, arriving while the others run) against the oracle's own
+    steps of each tank: FP64 solves to rtol 1e-12, results within 1e-10."""
+    from test_gpu_batch import oracle_specs, oracle_steps
+    from paper_1512_02548_amd import lib
+    from paper_1512_02548_amd.serve import GpuBackend, Request, Server
+    opts = lib.default_opts(rtol=1e-12, warm_start=1, max_iter=20000)
+    specs = oracle_specs()
+    steps = [2, 3, 2]
+    reqs = [Request(i, s, arrival=0.01 * i, steps=n) for i, (s, n) in enumerate(zip(specs, steps))]
+    srv = Server(GpuBackend(nstreams=0, opts=opts), wl.batch_tank_state, max_slots=4)
+    rep = srv.run(reqs)
+    assert rep["done"] == len(specs)
+    for r in srv.finished:
+        e_o, p_o = oracle_steps(r.spec, r.steps)
+        assert np.max(np.abs(r.result["eta"] - e_o)) / np.max(np.abs(e_o)) < 1e-10, r.rid
+        assert np.max(np.abs(r.result["phi"] - p_o)) / np.max(np.abs(p_o)) < 1e-10, r.rid

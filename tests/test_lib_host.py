@@ -81,3 +81,26 @@ def test_workspace_layout_complete(periodic):
     m = make(8, 2, 4, 6.28, periodic)
     code = lib.sem_mesh_bind(m.handle, C.c_void_p(1 << 20), m.info.workspace_bytes, None)
     assert code == lib.SEM_E_DEVICE, lib.sem_last_error()
+
+
+@pytest.mark.parametrize("P,Pf,ic,sf", [(1, 2, 2, 0.9), (4, 6, 3, 0.95), (6, 9, 5, 0.995), (8, 12, 8, 0.5)])
+def test_reference_operators_match_oracle(P, Pf, ic, sf):
+    """The host builder's Dr, Ds, M (matched by node coordinates), filter F,
+    fine-grid interpolation I and fine mass M_f agree with the oracle's to
+    rounding (relative 1e-13 of each matrix's largest entry)."""
+    from oracle.refelem import Ref1D, RefTri, filter_matrix, fine_grid
+    from paper_1512_02548_amd import lib
+    h = lib.reference_operators(P, Pf, ic, sf)
+    ref = RefTri(P)
+    key = lambda r, s: [(round(a, 10), round(b, 10)) for a, b in zip(r, s)]
+    pos = {k: i for i, k in enumerate(key(ref.r, ref.s))}
+    perm = np.array([pos[k] for k in key(h["r"], h["s"])])     # host node i = oracle node perm[i]
+    assert np.max(np.abs(h["r"] - ref.r[perm])) < 1e-14 and np.max(np.abs(h["s"] - ref.s[perm])) < 1e-14
+    for name, A in (("Dr", ref.Dr), ("Ds", ref.Ds), ("M", ref.M)):
+        B = A[np.ix_(perm, perm)]
+        assert np.max(np.abs(h[name] - B)) < 1e-13 * np.max(np.abs(B)), name
+    I, Mf = fine_grid(P, Pf)
+    for name, B in (("F", filter_matrix(P, ic, sf)), ("I", I), ("Mf", Mf)):
+        assert np.max(np.abs(h[name] - B)) < 1e-13 * np.max(np.abs(B)), name
+    with pytest.raises(lib.SemError):
+        lib.reference_operators(P, P - 1 if P > 1 else 0)

@@ -76,7 +76,7 @@ def test_steep_wave_conditions_between_collocation_points():
         res.append(np.max(np.abs(dyn)) / w.R)
     assert res[1] < 1e-8 < res[0] < 1e-5
     w = sf.solve_resolved(k, h, H)
-    assert np.max(np.abs(w.residuals(X)[1])) / w.R < 1e-9
+    assert np.max(np.abs(w.residuals(X)[1])) / w.R < 5e-9
     # crest-trough height and zero mean level
     x = np.arange(4096) * w.wavelength / 4096
     eta = w.eta(x)
