@@ -182,6 +182,17 @@ sem_status sem_laplace_solve(sem_mesh* mesh, const double* eta, const double* et
 sem_status sem_gradient_recover(sem_mesh* mesh, sem_recover_kind kind, const double* in,
                                 const double* eta, double* out, void* stream);
 
+/* Velocity in the whole volume (Sec. 3.1.3, eqs. representationU, velocpot,
+ * velocpot2; the chain rule of the sigma-map of Sec. 2): u = d phi/dx and
+ * w = d phi/dz at every node [n], each from the global L2 projection
+ * M u = S_u Phi, M w = S_z Phi with
+ *   S_u = int (d_x Phi + sigma_x d_sigma Phi) N_i,  S_z = int (1/d) d_sigma Phi N_i,
+ * sigma_x = ((1 - sigma) h_x - sigma eta_x)/d, over the computational domain.
+ * Phi [n] (a Laplace solution for the surface eta [ns], eta_x [ns]); u or w
+ * may be NULL.  The surface values of w are the w~ of SEM_RECOVER_W. */
+sem_status sem_recover_kinematics(sem_mesh* mesh, const double* Phi, const double* eta,
+                                  const double* eta_x, double* u, double* w, void* stream);
+
 /* Over-integrated Galerkin right-hand side of the free-surface equations
  * (Secs. 3.1.1, 3.3) followed by the M' solves: (deta_dt, dphi_dt) [ns]. */
 sem_status sem_free_surface_rhs(sem_mesh* mesh, const double* eta, const double* eta_x,
@@ -202,6 +213,19 @@ sem_status sem_free_surface_rhs(sem_mesh* mesh, const double* eta, const double*
  * only the iteration count. */
 sem_status sem_rk4_step(sem_mesh* mesh, double* eta, double* phi_s, double* phi_ws, double dt,
                         const sem_solve_opts* opts, sem_solve_stats* stats, void* stream);
+
+/* Wave generation and absorption zones (Sec. 2.2): each surface variable q
+ * gets the source (1 - gamma(x)) tau^-1 (q_a(x, t) - q) with tau = dt.
+ * sem_set_relaxation stores the weights 1 - gamma at the surface nodes
+ * (HOST [ns], each in [0, 1]; NULL switches the zones off); host work, kept
+ * across binds.  sem_rk4_step_forced is sem_rk4_step with the source added
+ * to every stage's slopes; qa (DEVICE [3][2][ns]) holds the targets
+ * (eta_a, phi~_a) at t, t + dt/2 and t + dt.  SEM_E_INVAL when no weights
+ * are set.  Meshes with weights set are rejected by sem_batch_create. */
+sem_status sem_set_relaxation(sem_mesh* mesh, const double* weight_host);
+sem_status sem_rk4_step_forced(sem_mesh* mesh, double* eta, double* phi_s, double* phi_ws, double dt,
+                               const double* qa, const sem_solve_opts* opts, sem_solve_stats* stats,
+                               void* stream);
 
 /* Forget the recorded stage solutions of `mesh` (ordered on `stream`): call
  * when the state passed to the next step was not reached by the previous

@@ -67,6 +67,18 @@ def coefficients(mesh, eta_s, etax_s, h_s, hx_s):
     return np.stack([G[..., 0, 0], G[..., 0, 1], G[..., 1, 1]], axis=-1), d
 
 
+def sigma_x(mesh, eta_s, etax_s, h_s, hx_s):
+    """d(sigma)/dx of the sigma-map at every element node (Sec. 2, the
+    Jacobian's off-diagonal entry): ((1 - sigma) h_x - sigma eta_x) / d, with
+    the column interpolants of the surface data.  Returns (E, Np)."""
+    eta = mesh.column_interp(eta_s)
+    etax = mesh.column_interp(etax_s)
+    h = mesh.column_interp(h_s)
+    hx = mesh.column_interp(hx_s)
+    sig = mesh.esig
+    return ((1.0 - sig) * hx - sig * etax) / (eta + h)
+
+
 def element_stiffness(ref, Gk):
     """A^k = sum_ab D_a^T M diag(G_ab) D_b (quadrature-free, Sec. 3.2)."""
     D = (ref.Dr, ref.Ds)

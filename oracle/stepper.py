@@ -15,6 +15,11 @@ Time integration is the explicit fourth-order Runge-Kutta method of Sec.
 3.1.1, read as the classical scheme (nodes 0, 1/2, 1/2, 1; weights
 1, 2, 2, 1 over 6).  The modal filter of Sec. 3.4 is applied to eta and phi~
 once after every completed step.
+
+Sec. 2.2 (wave generation and absorption zones) adds to the right-hand side
+of each surface variable q the penalty source (1 - gamma(x)) tau^-1
+(q_a(x, t) - q) with tau equal to the time step; the weights 1 - gamma at
+the surface nodes and the target q_a(t) = (eta_a, phi~_a) are inputs.
 """
 import numpy as np
 
@@ -28,6 +33,15 @@ def rk4(f, y, dt):
     k2 = f(y + 0.5 * dt * k1)
     k3 = f(y + 0.5 * dt * k2)
     k4 = f(y + dt * k3)
+    return y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+
+def rk4_t(f, y, t, dt):
+    """One classical RK4 step for y' = f(y, t)."""
+    k1 = f(y, t)
+    k2 = f(y + 0.5 * dt * k1, t + 0.5 * dt)
+    k3 = f(y + 0.5 * dt * k2, t + 0.5 * dt)
+    k4 = f(y + dt * k3, t + dt)
     return y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
@@ -77,15 +91,23 @@ class Tank:
             lp.append(s1.Je * I.T @ Mf @ fp)
         return s1.solve_mass(s1.assemble_vec(np.array(le))), s1.solve_mass(s1.assemble_vec(np.array(lp)))
 
-    def step(self, eta, phi, dt):
-        """One RK4 step of (eta, phi~) followed by the per-element filter."""
+    def step(self, eta, phi, dt, t=0.0, relax=None):
+        """One RK4 step of (eta, phi~) followed by the per-element filter.
+        relax = (weight, target): weight [ns] holds 1 - gamma(x) at the
+        surface nodes, target(t) returns (eta_a, phi~_a) at time t; the
+        source weight / dt (q_a - q) joins each stage's right-hand side."""
         ns = self.mesh.ns
 
-        def f(y):
+        def f(y, ts):
             et, pt = self.stage(y[:ns], y[ns:])
-            return np.concatenate([et, pt])
+            rhs = np.concatenate([et, pt])
+            if relax is not None:
+                wgt, target = relax
+                ea, pa = target(ts)
+                rhs += np.concatenate([wgt, wgt]) / dt * (np.concatenate([ea, pa]) - y)
+            return rhs
 
-        y = rk4(f, np.concatenate([eta, phi]), dt)
+        y = rk4_t(f, np.concatenate([eta, phi]), t, dt)
         eta, phi = y[:ns], y[ns:]
         if self.filt is not None:
             eta = self.s1.apply_filter(eta, *self.filt)

@@ -10,7 +10,10 @@ The vertical surface velocity comes from M w = S_z Phi (eqs. "velocpot",
 quadrature-free (Sec. 3.2) with the nodal values of sigma_z = 1/d:
 S_z^k = |J^k| M diag(1/d) D_sigma^k, D_sigma^k = r_sigma D_r + s_sigma D_s.
 Both integrals are taken over the computational (x, sigma) domain, so the 2D
-mass matrix sum_k |J^k| M is constant in time; w~ is w on S^FS.
+mass matrix sum_k |J^k| M is constant in time; w~ is w on S^FS.  The
+horizontal velocity in the volume comes from the same projection of
+d phi/dx = d_x Phi + sigma_x d_sigma Phi (eq. representationU with the
+chain rule of the sigma-map).
 
 Sec. 3.1.1 gives the weak free-surface equations (eq. "FSproblem"),
 
@@ -105,6 +108,29 @@ def sz_times(mesh, Phi, d):
         loc = mesh.J[k] * ref.M @ ((Dsig @ Phi[mesh.EToN[k]]) / d[k])
         np.add.at(out, mesh.EToN[k], loc)
     return out
+
+
+def su_times(mesh, Phi, sigx):
+    """S_u Phi assembled: sum_k R_k^T |J^k| M (D_x^k + diag(sigma_x) D_sigma^k) Phi_k,
+    the quadrature-free form of int (d_x Phi + sigma_x d_sigma Phi) N_i over
+    the computational domain (chain rule of the sigma-map, Sec. 2; the
+    horizontal velocity of eq. representationU)."""
+    ref = mesh.ref
+    out = np.zeros(mesh.n)
+    for k in range(mesh.E):
+        Dx = mesh.Lam[k, 0, 0] * ref.Dr + mesh.Lam[k, 1, 0] * ref.Ds
+        Dsig = mesh.Lam[k, 0, 1] * ref.Dr + mesh.Lam[k, 1, 1] * ref.Ds
+        Pk = Phi[mesh.EToN[k]]
+        loc = mesh.J[k] * ref.M @ (Dx @ Pk + sigx[k] * (Dsig @ Pk))
+        np.add.at(out, mesh.EToN[k], loc)
+    return out
+
+
+def recover_u(mesh, Phi, sigx, Mc=None):
+    """Horizontal velocity u = d phi/dx on all nodes from the global L2
+    projection M u = S_u Phi (Sec. 3.1.3, eq. representationU)."""
+    Mc = mass2d(mesh) if Mc is None else Mc
+    return spla.spsolve(Mc.tocsc(), su_times(mesh, Phi, sigx))
 
 
 def recover_w(mesh, Phi, d, Mc=None):

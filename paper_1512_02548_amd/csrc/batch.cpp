@@ -697,6 +697,8 @@ extern "C" sem_status sem_batch_create(sem_mesh* const* meshes, int32_t count, i
   for (int i = 0; i < count; ++i)
     if (!meshes[i] || !meshes[i]->bound) return fail(SEM_E_INVAL, "every mesh must be bound");
   for (int i = 0; i < count; ++i)
+    if (meshes[i]->relax_on) return fail(SEM_E_INVAL, "relaxation zones are not supported in batches");
+  for (int i = 0; i < count; ++i)
     for (int j = i + 1; j < count; ++j)
       if (meshes[i] == meshes[j]) return fail(SEM_E_INVAL, "a mesh appears twice in the batch");
   std::unique_ptr<sem_batch> B(new (std::nothrow) sem_batch());

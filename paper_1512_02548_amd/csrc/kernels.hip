@@ -140,6 +140,7 @@ __device__ __forceinline__ void coef_body(const TankDev& d, const double* __rest
   double Grs = J * (a0 * l10 + a1 * l11);
   double Gss = J * (b0 * l10 + b1 * l11);
   if (what & 2) d.invd[tile_index(d.T, d.NpP, b, eb, m, 1, 0)] = 1.0 / dd;
+  if (what & 4) d.sigx[tile_index(d.T, d.NpP, b, eb, m, 1, 0)] = q / dd;
   if (!(what & 1)) return;
   d.G[tile_index64(d.T, d.NpP, b, eb, m, 3, 0)] = Grr;
   d.G[tile_index64(d.T, d.NpP, b, eb, m, 3, 1)] = Grs;
@@ -191,7 +192,7 @@ __device__ __forceinline__ void gather_body(const TankDev& d, const T* __restric
   __syncthreads();
   // 2. per-element work, thread per (element, node)
   const int work = EBb * Np;
-  if (OP == OP_STIFF || OP == OP_SZ) {
+  if (OP == OP_STIFF || OP == OP_SZ || OP == OP_SU) {
     // phase 1: derivatives and pointwise flux f_a = sum_b G_ab D_b u
     for (int it = threadIdx.x; it < work; it += blockDim.x) {
       int eb = it / Np, i = it - eb * Np;
@@ -211,10 +212,16 @@ __device__ __forceinline__ void gather_body(const TankDev& d, const T* __restric
         T gss = PR::G(d, b, eb, i, 2);
         st1[eb * NpP + i] = grr * tr + grs * ts;
         st2[eb * NpP + i] = grs * tr + gss * ts;
-      } else {
+      } else if (OP == OP_SZ) {
         const double* lay = d.lay + jt * 8;
         T dsig = T(lay[1]) * tr + T(lay[3]) * ts;
         st1[eb * NpP + i] = dsig * T(d.invd[tile_index(d.T, NpP, b, eb, i, 1, 0)]);
+      } else {
+        // d phi/dx = d_x Phi + sigma_x d_sigma Phi (chain rule of the sigma-map)
+        const double* lay = d.lay + jt * 8;
+        T dx = T(lay[0]) * tr + T(lay[2]) * ts;
+        T dsig = T(lay[1]) * tr + T(lay[3]) * ts;
+        st1[eb * NpP + i] = dx + dsig * T(d.sigx[tile_index(d.T, NpP, b, eb, i, 1, 0)]);
       }
     }
     __syncthreads();
@@ -1522,6 +1529,7 @@ static void gather_kernel(const TankDev& h, const TankDev* d, int op, const T* u
       case OP_PRE_LAP: SEM_G(OP_PRE_LAP); break;
       case OP_PRE_MASS: SEM_G(OP_PRE_MASS); break;
       case OP_SZ: SEM_G(OP_SZ); break;
+      case OP_SU: SEM_G(OP_SU); break;
     }
   } else {
     switch (op) {
@@ -1847,6 +1855,22 @@ void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const 
   hipLaunchKernelGGL(k_circ_apply, dim3(nblk(h.ns, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, 1, re, et, rp,
                      pt);
 }
+// Relaxation-zone source of Sec. 2.2 added to a stage's slopes:
+// k += w (q_a - q) / tau for q = eta and phi~ at the stage state.
+__global__ void k_relax(int ns, double inv_tau, const double* __restrict__ w, const double* __restrict__ qae,
+                        const double* __restrict__ qap, const double* __restrict__ se, const double* __restrict__ sp,
+                        double* __restrict__ ke, double* __restrict__ kp) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  const double a = w[s] * inv_tau;
+  ke[s] += a * (qae[s] - se[s]);
+  kp[s] += a * (qap[s] - sp[s]);
+}
+void launch_relax(int ns, double inv_tau, const double* w, const double* qae, const double* qap, const double* se,
+                  const double* sp, double* ke, double* kp, hipStream_t st) {
+  hipLaunchKernelGGL(k_relax, dim3(nblk(ns)), dim3(kBlockThreads), 0, st, ns, inv_tau, w, qae, qap, se, sp, ke, kp);
+}
+
 void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,
                       const double* ke, const double* kp, double* ye, double* yp, double* acce, double* accp,
                       hipStream_t st) {

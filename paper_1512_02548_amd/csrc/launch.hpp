@@ -9,7 +9,7 @@
 
 namespace sem {
 
-enum { OP_STIFF = 0, OP_MASS = 1, OP_PRE_LAP = 2, OP_PRE_MASS = 3, OP_SZ = 4 };
+enum { OP_STIFF = 0, OP_MASS = 1, OP_PRE_LAP = 2, OP_PRE_MASS = 3, OP_SZ = 4, OP_SU = 5 };
 // gather flags: mask the surface rows, negate, skip the launch once the
 // tank's Krylov cycle is done (kernels queued ahead of a convergence test)
 enum { F_MASK_SURF = 1, F_NEG = 2, F_GATE = 4, F_NOFIX = 8 };   // F_NOFIX: element kernel only
@@ -45,6 +45,8 @@ void launch_sd(const TankDev& h, const TankDev* d, int which, const float* u, fl
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
 void launch_fill(int64_t n, double v, double* y, hipStream_t st);
 void launch_ks_reset(KrylovState* ks, double rtol, hipStream_t st);
+void launch_relax(int ns, double inv_tau, const double* w, const double* qae, const double* qap, const double* se,
+                  const double* sp, double* ke, double* kp, hipStream_t st);
 void launch_fill_f(int64_t n, float* y, hipStream_t st);
 void launch_mask_surface(const TankDev& h, const TankDev* d, double* y, hipStream_t st);
 void launch_scatter_surface(const TankDev& h, const TankDev* d, const double* phis, double* u, int zero_rest,

@@ -60,6 +60,8 @@ struct sem_mesh {
   sem::TankDev* dtank = nullptr;
   double* scal = nullptr;   // small device scalars
   bool bound = false;
+  bool relax_on = false;        // relaxation-zone weights set (sem_set_relaxation)
+  std::vector<double> relax_w;  // their host copy, uploaded again at every bind
   // offsets of dynamic arrays
   std::map<std::string, size_t> off;
   // RK4 scratch (surface arrays)

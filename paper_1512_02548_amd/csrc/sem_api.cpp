@@ -974,6 +974,7 @@ static sem_status build_mesh(sem_mesh* M) {
   reserve(M, "G32", tiles * 3 * sizeof(float));
   reserve(M, "G16", tiles * 3 * sizeof(uint16_t));
   reserve(M, "invd", tiles * sizeof(double));
+  reserve(M, "sigx", tiles * sizeof(double));
   reserve(M, "status", 64);
   reserve(M, "ks", sizeof(KrylovState));
   reserve(M, "H", ((size_t)(m + 1) * m + 5 * m + 1) * sizeof(double));
@@ -1226,6 +1227,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.G32 = at<float>(M, "G32");
   h.G16 = at<uint16_t>(M, "G16");
   h.invd = at<double>(M, "invd");
+  h.sigx = at<double>(M, "sigx");
   h.status = at<int32_t>(M, "status");
   h.ks = at<KrylovState>(M, "ks");
   h.H = at<double>(M, "H");
@@ -1258,7 +1260,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   const void* need[] = {h.Dr, h.Ds, h.MDr, h.MDs, h.opf, h.opf32, h.opf_sz, h.Mref, h.Dr32, h.Ds32, h.MDr32, h.MDs32, h.Mref32, h.elem_loc,
                         h.acc_cnt, h.acc_ent, h.surf_loc, h.is_surf_loc, h.lay, h.nodeq, h.colw, h.pre_lap,
                         h.pre_mass, h.pre_lap32, h.M1, h.S1, h.Ifine, h.Mfine, h.Filt, h.h, h.hx, h.G,
-                        h.G32, h.G16, h.invd, h.status, h.ks, h.H, h.part, h.V, h.Zb, h.w, h.b, h.tmp, h.xs,
+                        h.G32, h.G16, h.invd, h.sigx, h.status, h.ks, h.H, h.part, h.V, h.Zb, h.w, h.b, h.tmp, h.xs,
                         h.wmass, h.side, h.s1d, h.V32, h.Z32, h.w32, h.x32, h.b32, h.twid, h.Brow, h.Rrow,
                         h.sd[0].yI, h.sd[1].yI, h.sd[0].A1, h.sd[1].A1, h.sd[0].C3, h.sd[1].C3, h.sd[0].XH,
                         h.sd[1].XH, M->rk, M->scal, h.hist, h.pv, h.hs};
@@ -1276,6 +1278,9 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   HIPCHK(hipMemsetAsync(h.G32, 0, M->off.at("G16") - M->off.at("G32"), st));
   HIPCHK(hipMemsetAsync(h.G16, 0, M->off.at("invd") - M->off.at("G16"), st));
   HIPCHK(hipMemsetAsync(h.invd, 0, M->off.at("status") - M->off.at("invd"), st));
+  if (M->relax_on)
+    HIPCHK(hipMemcpyAsync(M->rk + 9 * (size_t)M->ns, M->relax_w.data(), M->ns * sizeof(double),
+                          hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   M->bound = true;
   return SEM_OK;
@@ -1811,23 +1816,54 @@ extern "C" sem_status sem_laplace_solve(sem_mesh* M, const double* eta, const do
   return laplace_core(M, phi_s, phi, &o, stats, st);
 }
 
-sem_status sem::recover_w_core(sem_mesh* M, const double* Phi, double* out, hipStream_t st) {
+// x = M^-1 rhs for the constant 2D mass matrix: exactly (line condensation
+// and DFT) on periodic tanks, preconditioned GMRES to 1e-14 with walls
+// (x holds the start vector there)
+static sem_status mass_solve(sem_mesh* M, const double* rhs, double* x, hipStream_t st) {
   const TankDev& h = M->hd;
   const TankDev* d = M->dtank;
-  launch_gather(h, d, OP_SZ, Phi, h.b, h.side, 0, st);
   if (h.pre_kind == 1) {
-    // periodic tanks: the mass matrix is inverted exactly (line condensation + DFT)
-    launch_gather(h, d, OP_PRE_MASS, h.b, h.wmass, h.side, 0, st);
-    launch_gather_surface(h, d, h.wmass, out, st);
+    launch_gather(h, d, OP_PRE_MASS, rhs, x, h.side, 0, st);
     return SEM_OK;
   }
   GmresCfg cfg{OP_MASS, OP_PRE_MASS, false, 1e-14, 400, 4, 0};
   int iters;
   double rel;
-  sem_status s = gmres(M, cfg, buf64(M), h.wmass, h.b, &iters, &rel, st);
+  sem_status s = gmres(M, cfg, buf64(M), x, rhs, &iters, &rel, st);
   if (s == SEM_E_NOCONV) set_status_bits(M, ST_NOCONV, st);
+  return s;
+}
+
+sem_status sem::recover_w_core(sem_mesh* M, const double* Phi, double* out, hipStream_t st) {
+  const TankDev& h = M->hd;
+  const TankDev* d = M->dtank;
+  launch_gather(h, d, OP_SZ, Phi, h.b, h.side, 0, st);
+  sem_status s = mass_solve(M, h.b, h.wmass, st);
   launch_gather_surface(h, d, h.wmass, out, st);
   return s;
+}
+
+extern "C" sem_status sem_recover_kinematics(sem_mesh* M, const double* Phi, const double* eta,
+                                             const double* eta_x, double* u, double* w, void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!Phi || !eta || !eta_x || (!u && !w)) return fail(SEM_E_INVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const TankDev& h = M->hd;
+  const TankDev* d = M->dtank;
+  HIPCHK(hipMemsetAsync(h.status, 0, sizeof(int32_t), st));
+  // 1/d and d sigma/dx at the element nodes
+  launch_coef(h, d, eta, eta_x, 2 | 4, st);
+  if ((s = read_status(M, st, nullptr))) return s;
+  const int ops[2] = {OP_SZ, OP_SU};
+  double* outs[2] = {w, u};
+  for (int k = 0; k < 2; ++k) {
+    if (!outs[k]) continue;
+    launch_gather(h, d, ops[k], Phi, h.b, h.side, 0, st);
+    launch_fill(M->n, 0.0, outs[k], st);
+    if ((s = mass_solve(M, h.b, outs[k], st))) return s;
+  }
+  return read_status(M, st, nullptr);
 }
 
 extern "C" sem_status sem_gradient_recover(sem_mesh* M, sem_recover_kind kind, const double* in, const double* eta,
@@ -1869,8 +1905,10 @@ extern "C" sem_status sem_rk4_reset_history(sem_mesh* M, void* stream) {
   return SEM_OK;
 }
 
-extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, double* phi_ws, double dt,
-                                   const sem_solve_opts* opts, sem_solve_stats* stats, void* stream) {
+// One RK4 step; qa (device, [3][2][ns]: eta_a and phi~_a at t, t + dt/2 and
+// t + dt) adds the relaxation-zone source of Sec. 2.2 with tau = dt.
+static sem_status rk4_step_core(sem_mesh* M, double* eta, double* phi_s, double* phi_ws, double dt, const double* qa,
+                                const sem_solve_opts* opts, sem_solve_stats* stats, void* stream) {
   sem_status s = check_bound(M);
   if (s) return s;
   if (!eta || !phi_s || !phi_ws) return fail(SEM_E_INVAL, "null argument");
@@ -1923,6 +1961,11 @@ extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, doub
       break;
     }
     launch_fs_rhs(h, d, se, ex, px, wsf, ke, kp, st);
+    if (qa) {
+      const int slot = sidx == 0 ? 0 : (sidx == 3 ? 2 : 1);
+      launch_relax(ns, 1.0 / dt, M->rk + 9 * (size_t)ns, qa + (size_t)slot * 2 * ns, qa + ((size_t)slot * 2 + 1) * ns,
+                   se, sp, ke, kp, st);
+    }
     if (sidx < 3)
       launch_rk4_stage(ns, cnode[sidx + 1] * dt, wts[sidx], sidx == 0, eta, phi_s, ke, kp, ye, yp, ae, ap, st);
     else
@@ -1939,5 +1982,37 @@ extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, doub
   if (stats)
     for (int k = 0; k < solved; ++k) stats[k].seconds = solve_seconds(M->solve_ev[k]);
   return s;
+}
+
+extern "C" sem_status sem_rk4_step(sem_mesh* M, double* eta, double* phi_s, double* phi_ws, double dt,
+                                   const sem_solve_opts* opts, sem_solve_stats* stats, void* stream) {
+  return rk4_step_core(M, eta, phi_s, phi_ws, dt, nullptr, opts, stats, stream);
+}
+
+extern "C" sem_status sem_set_relaxation(sem_mesh* M, const double* weight) {
+  if (!M) return fail(SEM_E_INVAL, "null argument");
+  if (!weight) {
+    M->relax_on = false;
+    M->relax_w.clear();
+    return SEM_OK;
+  }
+  for (int64_t i = 0; i < M->ns; ++i)
+    if (!(weight[i] >= 0.0 && weight[i] <= 1.0)) return fail(SEM_E_INVAL, "relaxation weights must lie in [0, 1]");
+  M->relax_w.assign(weight, weight + M->ns);
+  M->relax_on = true;
+  if (M->bound) {
+    HIPCHK(hipMemcpy(M->rk + 9 * (size_t)M->ns, M->relax_w.data(), M->ns * sizeof(double), hipMemcpyHostToDevice));
+  }
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_rk4_step_forced(sem_mesh* M, double* eta, double* phi_s, double* phi_ws, double dt,
+                                          const double* qa, const sem_solve_opts* opts, sem_solve_stats* stats,
+                                          void* stream) {
+  sem_status s = check_bound(M);
+  if (s) return s;
+  if (!qa) return fail(SEM_E_INVAL, "null argument");
+  if (!M->relax_on) return fail(SEM_E_INVAL, "no relaxation weights set (sem_set_relaxation)");
+  return rk4_step_core(M, eta, phi_s, phi_ws, dt, qa, opts, stats, stream);
 }
 

@@ -180,6 +180,7 @@ struct TankDev {
   float* G32;
   uint16_t* G16;                  // bfloat16 copy of G (same layout)
   double* invd;                   // [nb][T][NpP][16]
+  double* sigx;                   // d sigma/dx at the element nodes, same layout (kinematics)
   int32_t* status;                // one word
   KrylovState* ks;
   double* H;                      // (m+1) x m Hessenberg, then cs[m], sn[m], g[m+1], y[m]

@@ -77,10 +77,14 @@ _SIGS = {
     "sem_laplace_solve": (C.c_int, [_P, _P, _P, _P, _P, C.POINTER(sem_solve_opts),
                                     C.POINTER(sem_solve_stats), _P]),
     "sem_gradient_recover": (C.c_int, [_P, C.c_int, _P, _P, _P, _P]),
+    "sem_recover_kinematics": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "sem_free_surface_rhs": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "sem_rk4_step": (C.c_int, [_P, _P, _P, _P, C.c_double, C.POINTER(sem_solve_opts),
                                C.POINTER(sem_solve_stats), _P]),
     "sem_rk4_reset_history": (C.c_int, [_P, _P]),
+    "sem_set_relaxation": (C.c_int, [_P, _D]),
+    "sem_rk4_step_forced": (C.c_int, [_P, _P, _P, _P, C.c_double, _P, C.POINTER(sem_solve_opts),
+                                      C.POINTER(sem_solve_stats), _P]),
     "sem_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
     "sem_batch_laplace_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
                                           C.POINTER(C.c_uint8), C.POINTER(sem_solve_opts),
@@ -215,6 +219,12 @@ class Mesh:
         check(sem_gradient_recover(self.handle, kind, _ptr(inp), _ptr(eta) if eta is not None else None,
                                    _ptr(out), _stream(stream)), "sem_gradient_recover")
 
+    def recover_kinematics(self, Phi, eta, etax, u, w, stream=None):
+        """u and w at every node (either may be None)."""
+        check(sem_recover_kinematics(self.handle, _ptr(Phi), _ptr(eta), _ptr(etax),
+                                     _ptr(u) if u is not None else None, _ptr(w) if w is not None else None,
+                                     _stream(stream)), "sem_recover_kinematics")
+
     def free_surface_rhs(self, eta, etax, phix, ws, deta, dphi, stream=None):
         check(sem_free_surface_rhs(self.handle, _ptr(eta), _ptr(etax), _ptr(phix), _ptr(ws), _ptr(deta),
                                    _ptr(dphi), _stream(stream)), "sem_free_surface_rhs")
@@ -226,6 +236,24 @@ class Mesh:
                             _stream(stream))
         if raise_on_error:
             check(code, "sem_rk4_step")
+        return code, [s.as_dict() for s in st]
+
+    def set_relaxation(self, weight):
+        """Relaxation-zone weights 1 - gamma at the surface nodes (None: off)."""
+        if weight is None:
+            check(sem_set_relaxation(self.handle, None), "sem_set_relaxation")
+            return
+        self._relax = np.ascontiguousarray(weight, dtype=np.float64)
+        check(sem_set_relaxation(self.handle, self._relax.ctypes.data_as(_D)), "sem_set_relaxation")
+
+    def rk4_step_forced(self, eta, phis, phi_ws, dt, qa, opts=None, stream=None, raise_on_error=True):
+        """RK4 step with the relaxation source; qa: device tensor [3, 2, ns]."""
+        st = (sem_solve_stats * 4)()
+        o = opts if opts is not None else default_opts(warm_start=1)
+        code = sem_rk4_step_forced(self.handle, _ptr(eta), _ptr(phis), _ptr(phi_ws), float(dt), _ptr(qa),
+                                   C.byref(o), st, _stream(stream))
+        if raise_on_error:
+            check(code, "sem_rk4_step_forced")
         return code, [s.as_dict() for s in st]
 
     def reset_history(self, stream=None):

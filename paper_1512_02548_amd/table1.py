@@ -12,9 +12,9 @@ step fails (non-finite values or a water column of non-positive height,
 the library's NONFINITE / DOMAIN statuses: the paper's "NaN").  Reported per
 run: the step and t/T of failure, the error max_i |eta_i - eta_exact(x_i, t)|
 / H against the exact wave translated by c t at the paper's reporting times
-t/T = 1, 1.8, 3.1, 10, 28.2, 50, and the mean wall time per step (the
-paper's cost per dt is the ratio to the no-filter, no-over-integration run
-at the same T/dt).
+t/T = 1, 1.8, 3.1, 10, 28.2, 50, and the wall time per step over the first
+30 steps (the paper's cost per dt is its ratio to the no-filter,
+no-over-integration run at the same T/dt).
 
 Usage: python -m paper_1512_02548_amd.table1 [--periods 50] [--out FILE]
 """
@@ -26,6 +26,7 @@ import time
 import numpy as np
 
 REPORT_TIMES = (1.0, 1.8, 3.1, 10.0, 28.2, 50.0)
+COST_STEPS = 30
 
 
 def run(strategy, steps_per_period, periods=50.0, rtol=1e-12, report_times=REPORT_TIMES, log=None):
@@ -53,8 +54,12 @@ def run(strategy, steps_per_period, periods=50.0, rtol=1e-12, report_times=REPOR
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     n = 0
+    t_first = None
     for n in range(1, spec.steps + 1):
         code, _ = m.rk4_step(eta, phi, ws, spec.dt, opts, raise_on_error=False)
+        if n == COST_STEPS:
+            torch.cuda.synchronize()
+            t_first = time.perf_counter() - t0
         if code != lib.SEM_OK:
             out["failed_step"] = n
             out["failed_t_over_T"] = n / steps_per_period
@@ -72,6 +77,9 @@ def run(strategy, steps_per_period, periods=50.0, rtol=1e-12, report_times=REPOR
     done = n if out["failed_step"] is None else n - 1
     out["steps_run"] = done
     out["ms_per_step"] = 1e3 * wall / max(n, 1)
+    # cost per step over the first steps from the exact wave, before any run
+    # has grown far from it (every strategy completes them)
+    out["ms_per_step_first"] = 1e3 * t_first / COST_STEPS if t_first is not None else None
     out["period"] = T
     return out
 
@@ -89,8 +97,8 @@ def main(argv=None):
         for strat, _, _ in wl.TABLE1_STRATEGIES:
             r = run(strat, spp, a.periods, log=sys.stderr)
             if base is None:
-                base = r["ms_per_step"]
-            r["cost_per_dt_rel"] = r["ms_per_step"] / base
+                base = r["ms_per_step_first"]
+            r["cost_per_dt_rel"] = r["ms_per_step_first"] / base if r["ms_per_step_first"] else None
             print(f"# {json.dumps(r)}", file=sys.stderr, flush=True)
             res.append(r)
     text = json.dumps({"table1": res})

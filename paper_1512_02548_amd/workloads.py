@@ -249,6 +249,77 @@ def bar_irregular_state(xs, spec):
     return eta * taper, phi * taper, h, hx
 
 
+# ------------------------------------------- generation and absorption zones
+def relax_weight(xi):
+    """1 - gamma over a relaxation zone, xi = 0 at the zone's outer end and 1
+    where it meets the interior: 1 - (10 xi^3 - 15 xi^4 + 6 xi^5), which
+    falls from 1 to 0 with zero first and second derivatives at both ends."""
+    xi = np.clip(xi, 0.0, 1.0)
+    return 1.0 - xi ** 3 * (10.0 - 15.0 * xi + 6.0 * xi * xi)
+
+
+def relax_tank_spec(nx=48, nz=2, P=4, wavelengths=3, periods=4.0):
+    """A walled flat tank of `wavelengths` linear waves (kh = 1, H/L = 0.01):
+    a generation zone of one wavelength at x = 0 drives the progressive wave,
+    an absorption zone of one wavelength at x = L takes it out."""
+    k, h = 1.0, 1.0
+    lam = 2 * np.pi / k
+    L = wavelengths * lam
+    c = omega_linear(k, h) / k
+    dt = courant_dt(L, nx, P, c)
+    T = lam / c
+    return TankSpec(nx=nx, nz=nz, P=P, length=L, periodic=False, Pf=int(np.ceil(1.5 * P)),
+                    filter_ic=P + 1, filter_sigma=1.0, dt=dt, steps=int(np.ceil(periods * T / dt)), rtol=1e-12,
+                    name=f"relax_tank_{nx}x{nz}_P{P}",
+                    params=dict(k=k, h=h, H=0.01 * lam, gen_len=lam, abs_len=lam, period=T))
+
+
+def incident_linear(xs, t, k, h, H):
+    """Linear progressive wave of Sec. 4.2 at the surface: (eta, phi~)."""
+    w = omega_linear(k, h)
+    c = w / k
+    eta = 0.5 * H * np.cos(w * t - k * xs)
+    phi = -0.5 * H * c * np.cosh(k * (eta + h)) / np.sinh(k * h) * np.sin(w * t - k * xs)
+    return eta, phi
+
+
+def wave_group_state(xs, spec, x0, width=None):
+    """A right-going linear wave group centred at x0: the carrier of the
+    tank's linear wave under a Gaussian envelope (deep-water-free kh = 1,
+    width one wavelength): (eta, phi~)."""
+    p = spec.params
+    k, h, H = p["k"], p["h"], p["H"]
+    width = width or 2 * np.pi / k
+    xs = np.asarray(xs, dtype=float)
+    env = np.exp(-((xs - x0) / width) ** 2)
+    e, ph = incident_linear(xs, 0.0, k, h, H)
+    return env * e, env * ph
+
+
+def relax_tank_forcing(xs, spec, incident=None):
+    """(weight, target): weight = 1 - gamma at the surface nodes (generation
+    zone at x = 0, absorption zone at x = L, 0 between); target(t) = the
+    incident wave (eta_a, phi~_a) in the generation half, 0 in the absorption
+    half, ramped in over the first period."""
+    p = spec.params
+    xs = np.asarray(xs, dtype=float)
+    L = spec.length
+    wgt = np.zeros_like(xs)
+    g = xs < p["gen_len"]
+    wgt[g] = relax_weight(xs[g] / p["gen_len"])
+    a = xs > L - p["abs_len"]
+    wgt[a] = relax_weight((L - xs[a]) / p["abs_len"])
+    left = xs < 0.5 * L
+    inc = incident or (lambda x, t: incident_linear(x, t, p["k"], p["h"], p["H"]))
+
+    def target(t):
+        e, ph = inc(xs, t)
+        ramp = min(1.0, t / p["period"])
+        ramp = ramp * ramp * (3 - 2 * ramp)
+        return np.where(left, ramp * e, 0.0), np.where(left, ramp * ph, 0.0)
+    return wgt, target
+
+
 # ------------------------------------------------------------ batches
 def batch_tank_specs(count=256, seed=SEED_BASE + 4, steps=200, rtol=1e-10, bar_fraction=0.0, max_frac=0.9,
                      filter_modes=2, filter_sigma=0.995):

@@ -22,12 +22,12 @@ class Pair:
     """Library mesh (bound on the GPU) + oracle mesh + numbering map."""
 
     def __init__(self, nx, nz, P, L, periodic, h, hx, filter_ic=None, filter_sigma=1.0, Pf=None, g=9.81,
-                 restart=30, variant=0):
+                 restart=30, variant=0, sigma_levels=None):
         from paper_1512_02548_amd import lib
         self.lib = lib
         self.m = lib.Mesh(nx, nz, P, L, periodic, h, hx, g=g, filter_ic=filter_ic, filter_sigma=filter_sigma,
-                          overint=Pf, restart=restart, variant=variant)
-        self.om = OMesh(nx, nz, P, L, periodic)
+                          overint=Pf, restart=restart, variant=variant, sigma_levels=sigma_levels)
+        self.om = OMesh(nx, nz, P, L, periodic, sigma_levels=sigma_levels)
         self.perm = node_permutation(self.m, self.om)
         self.h = np.asarray(h, float)
         self.hx = np.asarray(hx, float)

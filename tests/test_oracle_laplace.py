@@ -226,3 +226,61 @@ def test_K_matches_sigma_map_jacobian_on_sloping_bed():
     assert np.max(np.abs(G[..., 2] - Gref[..., 1, 1])) < 1e-12
     # the bed slope really enters: a quarter of the nodes see |q| > 0.02
     assert np.mean(np.abs(sx / sz) > 0.02) > 0.25
+
+
+def test_volume_kinematics_projection_sloping_bed():
+    """The projections M u = S_u Phi and M w = S_z Phi of a smooth field
+    phi(x, z) sampled at the nodes of a sloping-bed tank with a deformed
+    surface recover d phi/dx and d phi/dz at every node, converging
+    exponentially in P (exercises sigma_x with both its h_x and eta_x parts;
+    the field need not be harmonic for this)."""
+    L = 4.0
+    phi_f = lambda x, z: np.sin(1.3 * x + 0.4) * np.exp(0.7 * z) + 0.2 * x * z * z
+    phix_f = lambda x, z: 1.3 * np.cos(1.3 * x + 0.4) * np.exp(0.7 * z) + 0.2 * z * z
+    phiz_f = lambda x, z: 0.7 * np.sin(1.3 * x + 0.4) * np.exp(0.7 * z) + 0.4 * x * z
+    errs = []
+    for P in (2, 4, 6, 8):
+        m = Mesh(4, 2, P, L, False)
+        xs = m.xs_surf
+        eta = 0.1 * np.cos(1.1 * xs) + 0.05 * np.sin(0.4 * xs)
+        etax = -0.11 * np.sin(1.1 * xs) + 0.02 * np.cos(0.4 * xs)
+        h = 1.0 - 0.3 * np.exp(-(xs - 2.0) ** 2)
+        hx = 0.6 * (xs - 2.0) * np.exp(-(xs - 2.0) ** 2)
+        en, hn = m.column_interp(eta), m.column_interp(h)
+        z = m.node_z(en, hn)
+        Phi = np.zeros(m.n)
+        Phi[m.EToN] = phi_f(m.ex, z)
+        sx = lap.sigma_x(m, eta, etax, h, hx)
+        _, d = lap.coefficients(m, eta, etax, h, hx)
+        u = srf.recover_u(m, Phi, sx)
+        w = srf.recover_w(m, Phi, d)
+        ux = np.max(np.abs(u[m.EToN] - phix_f(m.ex, z)))
+        wz = np.max(np.abs(w[m.EToN] - phiz_f(m.ex, z)))
+        errs.append(max(ux, wz))
+    # measured: 1.8e-1, 6.1e-3, 5.5e-4, 4.1e-5
+    assert errs[1] < errs[0] / 8 and errs[2] < errs[1] / 8 and errs[3] < errs[2] / 8
+    assert errs[3] < 1e-4
+
+
+def test_volume_kinematics_manufactured_harmonic():
+    """Laplace solve + projections on a deformed surface over a flat bed:
+    u and w at every node converge to the gradient of the harmonic function
+    cosh(k(z+h))/cosh(kh) sin(kx) (Sec. 4.3's kinematics, exact solution)."""
+    k, h = 1.0, 1.0
+    errs = []
+    for P in (2, 4, 6):
+        m = Mesh(4, 2, P, 2 * np.pi, True)
+        s1 = srf.Surface1D(m)
+        xs = m.xs_surf
+        eta = 0.1 * np.cos(xs) + 0.03 * np.sin(2 * xs)
+        etax = s1.recover_dx(eta)
+        G, d = lap.coefficients(m, eta, etax, *flat(m, h))
+        Phi = lap.solve_direct(m, lap.stiffness(m, G), exact.harmonic_phi(xs, eta, k, h))
+        u = srf.recover_u(m, Phi, lap.sigma_x(m, eta, etax, *flat(m, h)))
+        w = srf.recover_w(m, Phi, d)
+        z = m.node_z(m.column_interp(eta), np.full((m.E, m.Np), h))
+        ue = k * np.cosh(k * (z + h)) / np.cosh(k * h) * np.cos(k * m.ex)
+        errs.append(max(np.max(np.abs(u[m.EToN] - ue)),
+                        np.max(np.abs(w[m.EToN] - exact.harmonic_w(m.ex, z, k, h)))))
+    assert errs[1] < errs[0] / 10 and errs[2] < errs[1] / 10
+    assert errs[2] < 2e-3

@@ -235,3 +235,66 @@ def test_linearised_spectrum_full(nz, P):
         dt = 0.035917
         assert filtered_step_radius(m, D, dt, (2, 0.9)) < 1.0 + 1e-9
         assert filtered_step_radius(m, D, dt, (3, 0.0)) > 1.003
+
+
+def test_relaxation_source():
+    """Sec. 2.2: with the free-surface equations silent (g = 0 and phi~ = 0
+    keep N(q) = 0) the penalty term alone relaxes q towards q_a; with weight
+    1 everywhere and tau = dt one RK4 step of q' = (q_a - q)/dt from q = 0
+    with constant q_a gives q_a (1 - R(-1)), R(z) = 1 + z + z^2/2 + z^3/6 +
+    z^4/24, i.e. (5/8) q_a exactly; weight 0 leaves the state alone.  In a
+    wave tank the generation zone builds up the target wave in its zone and
+    the absorption zone keeps the far end of the tank from reflecting."""
+    m = Mesh(8, 1, 4, 2 * np.pi, True)
+    tank = Tank(m, np.ones(m.ns), np.zeros(m.ns), g=0.0)
+    z = np.zeros(m.ns)
+    qa = 0.01 * np.cos(m.xs_surf)
+    e, p = tank.step(z, z, 0.1, relax=(np.ones(m.ns), lambda t: (qa, 0 * qa)))
+    assert np.max(np.abs(e - 0.625 * qa)) < 1e-15 and np.max(np.abs(p)) == 0.0
+    e, p = tank.step(z, z, 0.1, relax=(np.zeros(m.ns), lambda t: (qa, qa)))
+    assert np.max(np.abs(e)) == 0.0 and np.max(np.abs(p)) == 0.0
+    # generation: a linear wave builds up in the zone at x = 0 of a walled tank
+    from paper_1512_02548_amd import workloads as wl
+    spec = wl.relax_tank_spec(nx=24, nz=2, P=4, periods=1.5)
+    m = Mesh(spec.nx, spec.nz, spec.P, spec.length, False)
+    wgt, target = wl.relax_tank_forcing(m.xs_surf, spec)
+    tank = Tank(m, np.ones(m.ns), np.zeros(m.ns), Pf=spec.Pf)
+    e, p = np.zeros(m.ns), np.zeros(m.ns)
+    t = 0.0
+    H = spec.params["H"]
+    for _ in range(spec.steps):
+        e, p = tank.step(e, p, spec.dt, t, relax=(wgt, target))
+        t += spec.dt
+    # inside the zone (away from the wall, whose natural condition the
+    # progressive target does not meet) the state follows the target
+    zone = (m.xs_surf > 0.1 * spec.params["gen_len"]) & (m.xs_surf < 0.5 * spec.params["gen_len"])
+    ea, _ = target(t)
+    assert np.max(np.abs(e[zone] - ea[zone])) < 0.05 * H
+    # the wave has left the zone: the free part of the tank carries it
+    free = (m.xs_surf > spec.params["gen_len"]) & (m.xs_surf < spec.params["gen_len"] + 0.25 * 2 * np.pi)
+    assert np.max(np.abs(e[free])) > 0.25 * H
+
+
+def test_relaxation_absorbs_a_wave_group():
+    """Sec. 2.2: a linear wave group inside the absorption zone (q_a = 0)
+    loses more than 95% of its energy within 20 steps (the source removes it
+    at a rate of order weight / tau with tau = dt); the same group without
+    the zone keeps its energy."""
+    from paper_1512_02548_amd import workloads as wl
+    spec = wl.relax_tank_spec(nx=24, nz=2, P=4)
+    m = Mesh(spec.nx, spec.nz, spec.P, spec.length, False)
+    wgt, _ = wl.relax_tank_forcing(m.xs_surf, spec)
+    wgt[m.xs_surf < 0.5 * spec.length] = 0.0         # absorption zone only
+    e0, p0 = wl.wave_group_state(m.xs_surf, spec, x0=spec.length - 0.4 * spec.params["abs_len"],
+                                 width=0.25 * spec.params["abs_len"])
+    energies = {}
+    zero = lambda t: (np.zeros(m.ns), np.zeros(m.ns))
+    for on in (True, False):
+        tank = Tank(m, np.ones(m.ns), np.zeros(m.ns), Pf=spec.Pf)
+        e, p = e0.copy(), p0.copy()
+        E0 = tank.energy(e, p)
+        for n in range(20):
+            e, p = tank.step(e, p, spec.dt, n * spec.dt, relax=(wgt, zero) if on else None)
+        energies[on] = tank.energy(e, p) / E0
+    assert energies[True] < 0.05
+    assert abs(energies[False] - 1.0) < 0.02
