@@ -199,6 +199,23 @@ sem_status sem_free_surface_rhs(sem_mesh* mesh, const double* eta, const double*
                                 const double* phi_x, const double* w_s, double* deta_dt,
                                 double* dphi_dt, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * right-hand side as sem_free_surface_rhs, bitwise, with its scratch (the
+ * element right-hand sides and their node sums, 2 nx (P+1) + 2 ns doubles)
+ * in a static device array of SEM_NOALLOC_SCRATCH_BYTES per device instead
+ * of the mesh workspace.  Allocates nothing and never synchronises: the call
+ * only enqueues on `stream` and returns.  SEM_E_INVAL for a tank whose
+ * scratch exceeds the array or when the current device is not the one the
+ * mesh was bound on.  All calls on one device share the array, so calls
+ * that overlap on one device (concurrent streams or threads) race; order
+ * them on one stream.  The array keeps the last call's contents; every
+ * value is written before it is read. */
+#define SEM_NOALLOC_SCRATCH_BYTES (4u << 20)
+sem_status sem_free_surface_rhs_noalloc(sem_mesh* mesh, const double* eta, const double* eta_x,
+                                        const double* phi_x, const double* w_s, double* deta_dt,
+                                        double* dphi_dt, void* stream);
+
 /* One classical RK4 step of (eta, phi~) [ns] followed by the modal filter
  * (Secs. 3.1.1, 3.4).  phi_ws [n] carries the warm start of the Laplace
  * solves across calls.  Transactional: on error eta and phi_s are left

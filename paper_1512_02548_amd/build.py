@@ -22,7 +22,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-mcode-object
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
           "-Wno-unused-result", "-Wno-unused-command-line-argument"]
-SOURCES = ["host_refelem.cpp", "sem_api.cpp", "batch.cpp", "kernels.hip", "kernels_mfma.hip", "kernels_sd.hip"]
+SOURCES = ["host_refelem.cpp", "sem_api.cpp", "batch.cpp", "kernels.hip", "kernels_mfma.hip", "kernels_sd.hip", "noalloc.hip"]
 
 
 def _compile(src):

@@ -1846,9 +1846,12 @@ void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, do
 }
 void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const double* etax, const double* phix,
                    const double* ws, double* et, double* pt, hipStream_t st) {
-  double* loc = h.s1d + 5 * (size_t)h.ns;
-  double* re = h.s1d + 11 * (size_t)h.ns;
-  double* rp = h.s1d + 12 * (size_t)h.ns;
+  launch_fs_rhs_into(h, d, eta, etax, phix, ws, et, pt, h.s1d + 5 * (size_t)h.ns, h.s1d + 11 * (size_t)h.ns,
+                     h.s1d + 12 * (size_t)h.ns, st);
+}
+void launch_fs_rhs_into(const TankDev& h, const TankDev* d, const double* eta, const double* etax,
+                        const double* phix, const double* ws, double* et, double* pt, double* loc, double* re,
+                        double* rp, hipStream_t st) {
   hipLaunchKernelGGL(k_fs_local, dim3(nblk(h.nx, kBlockThreads / 64)), dim3(kBlockThreads), 0, st, d, eta, etax,
                      phix, ws, loc);
   hipLaunchKernelGGL(k_fs_gather, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, loc, re, rp);

@@ -80,6 +80,10 @@ void launch_recover_dx(const TankDev& h, const TankDev* d, const double* in0, do
                        double* out1, hipStream_t st);
 void launch_fs_rhs(const TankDev& h, const TankDev* d, const double* eta, const double* etax, const double* phix,
                    const double* ws, double* et, double* pt, hipStream_t st);
+// the same with caller-chosen scratch: loc [2 nx (P+1)], re and rp [ns]
+void launch_fs_rhs_into(const TankDev& h, const TankDev* d, const double* eta, const double* etax,
+                        const double* phix, const double* ws, double* et, double* pt, double* loc, double* re,
+                        double* rp, hipStream_t st);
 void launch_rk4_stage(int ns, double adt, double wgt, int first, const double* y0e, const double* y0p,
                       const double* ke, const double* kp, double* ye, double* yp, double* acce, double* accp,
                       hipStream_t st);

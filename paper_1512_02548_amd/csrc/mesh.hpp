@@ -73,6 +73,7 @@ struct sem_mesh {
   // (never pageable stack memory: several worker threads may read back at once)
   void* rb_host = nullptr;
   int32_t* prog_dev = nullptr;
+  int device = -1;               // the device the workspace was bound on
   // live timing of the stiffness kernel (event pairs of the running cycle)
   bool kt_on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> kt_ev;

@@ -1119,6 +1119,7 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
     *(volatile int32_t*)M->prog_host = 0;
   }
   if (!M->rb_host) HIPCHK(hipHostMalloc(&M->rb_host, 256, hipHostMallocDefault));
+  HIPCHK(hipGetDevice(&M->device));
   // the stage solves' timing events, created once per mesh
   for (auto& e : M->solve_ev)
     for (auto& x : e)

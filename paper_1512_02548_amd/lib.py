@@ -79,6 +79,7 @@ _SIGS = {
     "sem_gradient_recover": (C.c_int, [_P, C.c_int, _P, _P, _P, _P]),
     "sem_recover_kinematics": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "sem_free_surface_rhs": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "sem_free_surface_rhs_noalloc": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "sem_rk4_step": (C.c_int, [_P, _P, _P, _P, C.c_double, C.POINTER(sem_solve_opts),
                                C.POINTER(sem_solve_stats), _P]),
     "sem_rk4_reset_history": (C.c_int, [_P, _P]),
@@ -228,6 +229,12 @@ class Mesh:
     def free_surface_rhs(self, eta, etax, phix, ws, deta, dphi, stream=None):
         check(sem_free_surface_rhs(self.handle, _ptr(eta), _ptr(etax), _ptr(phix), _ptr(ws), _ptr(deta),
                                    _ptr(dphi), _stream(stream)), "sem_free_surface_rhs")
+
+    def free_surface_rhs_noalloc(self, eta, etax, phix, ws, deta, dphi, stream=None):
+        """sem_free_surface_rhs with its scratch in the library's static
+        device array (no allocation, no synchronisation)."""
+        check(sem_free_surface_rhs_noalloc(self.handle, _ptr(eta), _ptr(etax), _ptr(phix), _ptr(ws), _ptr(deta),
+                                           _ptr(dphi), _stream(stream)), "sem_free_surface_rhs_noalloc")
 
     def rk4_step(self, eta, phis, phi_ws, dt, opts=None, stream=None, raise_on_error=True):
         st = (sem_solve_stats * 4)()
