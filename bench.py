@@ -63,7 +63,7 @@ def stiffness_flops_per_elem(P):
     return 8 * Np * Np + 6 * Np
 
 
-def cpu_baseline(spec, budget_s=15.0):
+def cpu_baseline(spec, budget_s=15.0, threads=1):
     """The oracle (element matrices -> CSR -> sparse LU) timed on the host for
     a bounded sample of the same workload's Laplace solves."""
     from threadpoolctl import threadpool_limits
@@ -73,7 +73,7 @@ def cpu_baseline(spec, budget_s=15.0):
     from oracle.mesh import Mesh as OMesh
     from paper_1512_02548_amd import workloads as wl
 
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         om = OMesh(spec.nx, spec.nz, spec.P, spec.length, spec.periodic)
         eta, phi, h, hx = wl.stream_series_state(om.xs_surf, spec)
         s1 = osrf.Surface1D(om)
@@ -87,9 +87,10 @@ def cpu_baseline(spec, budget_s=15.0):
             if el > budget_s or count >= 200:
                 break
     nfree = om.n - om.ns
-    return dict(value=nfree * count / el / 1e9, unit="GDOF/s", cores=1, kind="oracle",
+    return dict(value=nfree * count / el / 1e9, unit="GDOF/s", cores=threads, kind="oracle",
                 sample=f"{count} Laplace solves (assembly + sparse LU) of the initial state, "
-                       f"{nfree} free DOF each, {el:.1f} s, BLAS limited to 1 thread")
+                       f"{nfree} free DOF each, {el:.1f} s, BLAS limited to {threads} thread(s); "
+                       "SciPy's sparse LU itself runs on one thread")
 
 
 def large_tank(lib, wl, torch, reps=3):
@@ -279,6 +280,55 @@ def batch_workload(args, modes=("lockstep_fp64", "lockstep_mixed", "concurrent_m
     return res
 
 
+def serving(args):
+    """Served tank-steps/s and p50/p99 request latency: a Poisson stream of
+    requests (tanks drawn like the 256-tank batch, half over a bar, exact
+    stream-function waves, 200 RK4 steps each) served by continuous batching
+    (lockstep batch, FP32 inner solves refined in FP64 to 1e-8) at a rate of
+    `rho` times the batch's measured capacity, against a sequential server
+    that runs one tank at a time in plain FP64 to the same tolerance."""
+    import torch
+
+    from paper_1512_02548_amd import lib, serve, tune
+    from paper_1512_02548_amd import workloads as wl
+    n, steps = args.serve_requests, args.serve_steps
+    reqs = serve.make_requests(n, 1.0, steps)
+    table, _ = tune.tune([r.spec for r in reqs])
+    # capacity: tank-steps/s of the lockstep batch over the first 32 requests
+    be = serve.GpuBackend(nstreams=0, tiles=table)
+    tanks = [be.create(r.spec, wl.batch_tank_state) for r in reqs[:32]]
+    be.step(tanks)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        be.step(tanks)
+    torch.cuda.synchronize()
+    cap = 3 * len(tanks) / (time.perf_counter() - t0)
+    del tanks, be
+    torch.cuda.empty_cache()
+    rate = args.serve_rho * cap / steps
+    arr = wl.poisson_arrivals(rate, n)
+    out = {"requests": n, "steps_per_request": steps, "rho": args.serve_rho, "capacity_tank_steps_s": cap,
+           "arrival_rate_per_s": rate, "filter": [2, 0.995], "tolerance": 1e-8, "bar_fraction": 0.5}
+    for mode in ("batched_mixed", "sequential_fp64"):
+        rs = [serve.Request(r.rid, r.spec, float(a), steps) for r, a in zip(reqs, arr)]
+        if mode == "batched_mixed":
+            backend = serve.GpuBackend(nstreams=0, tiles=table)
+            srv = serve.Server(backend, wl.batch_tank_state, max_slots=64)
+        else:
+            backend = serve.GpuBackend(nstreams=1, opts=lib.default_opts(rtol=1e-8, warm_start=1, lookahead=3))
+            srv = serve.Server(backend, wl.batch_tank_state, max_slots=1)
+        rep = srv.run(rs)
+        rep["batch_rebuilds"] = getattr(backend, "rebuilds", None)
+        out[mode] = rep
+        print(f"# serving {mode}: {rep}", file=sys.stderr, flush=True)
+        del srv, backend
+        torch.cuda.empty_cache()
+    b, s = out["batched_mixed"], out["sequential_fp64"]
+    out["speedup_tank_steps"] = b["tank_steps_per_s"] / s["tank_steps_per_s"] if s["tank_steps_per_s"] else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +351,10 @@ def main():
                     help="comma-separated subset of the batch workload's modes")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=200)
+    ap.add_argument("--serve-rho", type=float, default=0.8, help="arrival rate as a fraction of batched capacity")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "the library runs on one GPU; runs on several GPUs are not implemented",
@@ -414,8 +468,15 @@ def main():
         torch.cuda.empty_cache()
         bargs = argparse.Namespace(tanks=256, batch_steps=1, streams=8)
         out["batch_256"] = batch_workload(bargs, modes=("lockstep_fp64", "lockstep_mixed", "sequential_fp64"))
+    if not args.no_serve:
+        if args.no_batch:
+            del m
+            torch.cuda.empty_cache()
+        out["serving"] = serving(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
+        ncpu = len(os.sched_getaffinity(0))
+        out["cpu_baseline_all_threads"] = cpu_baseline(spec, args.cpu_budget / 2, threads=ncpu)
     print(json.dumps(out))
 
 

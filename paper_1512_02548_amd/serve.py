@@ -10,6 +10,9 @@ be advanced a given number of RK4 steps.  The server
   library's batch call (lockstep by default: the stage solves of all
   in-flight tanks run as one batched GMRES, every launch covering all tanks);
 * admits new tanks and retires finished (or failed) ones only between ticks;
+  a retired tank stays in the device batch, switched off by the batch's
+  active mask, until the next admission rebuilds the batch (so retirements
+  cost no rebuild, and each tick's arrivals share one);
 * records per-request latency (arrival to completion) and throughput.
 
 The backend is pluggable: ``GpuBackend`` drives libsem.so; tests substitute a
@@ -60,7 +63,9 @@ class GpuBackend:
         self.opts = opts if opts is not None else lib.default_opts(
             rtol=1e-8, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-3, lookahead=3)
         self._batch = None
-        self._batch_key = None
+        self._members = []        # tanks of the current device batch, in its order
+        self._retired = []        # retired members kept alive until the next rebuild
+        self.rebuilds = 0
         self.tiles = tiles        # autotuner table (P, nz) -> stiffness tiles per workgroup, or None
 
     def _tiles(self, spec):
@@ -98,21 +103,33 @@ class GpuBackend:
         return tank
 
     def step(self, tanks):
-        key = tuple(id(t["mesh"]) for t in tanks)
-        if key != self._batch_key:
+        pos = {id(t): i for i, t in enumerate(self._members)}
+        if self._batch is None or any(id(t) not in pos for t in tanks):
+            # a tank joined: one batch over the running tanks; retired ones go
             self._batch = self.lib.Batch([t["mesh"] for t in tanks], self.nstreams)
-            self._batch_key = key
-        code, st, it = self._batch.rk4_step([t["eta"] for t in tanks], [t["phi"] for t in tanks],
-                                            [t["ws"] for t in tanks], [t["spec"].dt for t in tanks],
-                                            opts=self.opts)
+            self._members = list(tanks)
+            for t in self._retired:
+                t.clear()
+            self._retired = []
+            self.rebuilds += 1
+            pos = {id(t): i for i, t in enumerate(self._members)}
+        mem = self._members
+        want = {id(t) for t in tanks}
+        active = [id(t) in want for t in mem]
+        code, st, it = self._batch.rk4_step([t["eta"] for t in mem], [t["phi"] for t in mem],
+                                            [t["ws"] for t in mem], [t["spec"].dt for t in mem],
+                                            active=active, opts=self.opts)
+        st = [st[pos[id(t)]] for t in tanks]
         return [s == 0 for s in st], [self.lib.STATUS_NAMES.get(s, str(s)) for s in st]
 
     def result(self, tank):
         return dict(eta=tank["eta"].cpu().numpy(), phi=tank["phi"].cpu().numpy())
 
     def release(self, tank):
-        tank.clear()
-        self._batch_key = None
+        if any(t is tank for t in self._members):
+            self._retired.append(tank)      # still referenced by the device batch
+        else:
+            tank.clear()
 
 
 class Server:
@@ -212,12 +229,10 @@ class Server:
                     ticks=self.ticks)
 
 
-def make_requests(count, rate, steps, seed=None, bar_fraction=0.5, max_nx=None, filter_modes=3, filter_sigma=0.8):
-    """Poisson stream of tanks drawn like the batch workload, half over a bar.
-    On these triangle meshes the grid-scale modes of the linearised system
-    grow (complex Dirichlet-to-Neumann eigenvalues) and the mild two-mode
-    filter does not hold them over 200 steps; requests therefore filter the
-    top three modes by 0.8 per step."""
+def make_requests(count, rate, steps, seed=None, bar_fraction=0.5, max_nx=None, filter_modes=2, filter_sigma=0.995):
+    """Poisson stream of tanks drawn like the batch workload (exact
+    stream-function waves), half over a bar, with the batch workload's mild
+    filter of the last two modes by 0.5% per step."""
     from . import workloads as wl
     kw = {} if seed is None else dict(seed=seed)
     specs = wl.batch_tank_specs(count=count, steps=steps, rtol=1e-8, bar_fraction=bar_fraction,
@@ -238,6 +253,8 @@ def main():
     ap.add_argument("--streams", type=int, default=0,
                     help="0: lockstep batch (default); >= 1: per-tank steps on that many streams")
     ap.add_argument("--max-nx", type=int, default=None)
+    ap.add_argument("--filter-modes", type=int, default=2)
+    ap.add_argument("--filter-sigma", type=float, default=0.995)
     ap.add_argument("--quiet", action="store_true", help="no per-request lines on stderr")
     ap.add_argument("--tune", action="store_true",
                     help="choose the stiffness element tiles with the autotuner first (not timed)")
@@ -246,7 +263,8 @@ def main():
     a = ap.parse_args()
     from . import lib
     from . import workloads as wl
-    reqs = make_requests(a.requests, a.rate, a.steps, max_nx=a.max_nx)
+    reqs = make_requests(a.requests, a.rate, a.steps, max_nx=a.max_nx, filter_modes=a.filter_modes,
+                         filter_sigma=a.filter_sigma)
     log = None if a.quiet else (lambda line: print(line, file=sys.stderr, flush=True))
     if a.sequential_fp64:
         be = GpuBackend(nstreams=1, opts=lib.default_opts(rtol=1e-8, warm_start=1, lookahead=3))
@@ -260,7 +278,8 @@ def main():
         srv = Server(be, wl.batch_tank_state, max_slots=a.slots, log=log)
     rep = srv.run(reqs)
     rep.update(mode="sequential_fp64" if a.sequential_fp64 else ("lockstep_mixed" if a.streams == 0 else
-                                                                  "concurrent_mixed"), rate=a.rate, steps=a.steps)
+                                                                  "concurrent_mixed"), rate=a.rate, steps=a.steps,
+               filter=[a.filter_modes, a.filter_sigma], batch_rebuilds=getattr(srv.backend, "rebuilds", None))
     if not a.sequential_fp64 and a.tune:
         rep["autotune"] = trep
     print(json.dumps(rep))
