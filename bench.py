@@ -309,7 +309,8 @@ def serving(args):
     rate = args.serve_rho * cap / steps
     arr = wl.poisson_arrivals(rate, n)
     out = {"requests": n, "steps_per_request": steps, "rho": args.serve_rho, "capacity_tank_steps_s": cap,
-           "arrival_rate_per_s": rate, "filter": [2, 0.995], "tolerance": 1e-8, "bar_fraction": 0.5}
+           "arrival_rate_per_s": rate, "filter": {"top_modes": 3, "sigma": 0.8}, "tolerance": 1e-8,
+           "bar_fraction": 0.5}
     for mode in ("batched_mixed", "sequential_fp64"):
         rs = [serve.Request(r.rid, r.spec, float(a), steps) for r, a in zip(reqs, arr)]
         if mode == "batched_mixed":
@@ -460,7 +461,14 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = {"read": a.numel() * 8, "write": a.numel() * 8}
     if not args.no_large:
-        out["large_tank"] = large_tank(lib, wl, torch)
+        out["large_tank"] = lt = large_tank(lib, wl, torch)
+        # the same kernel at a size that streams its factors from HBM (31 MB
+        # of FP64 factors and vectors per launch; 17 MB with FP32, 10 MB with
+        # bfloat16 factors), timed by events around 200 launches
+        out["roofline_large_tank"] = {
+            k: {"bound": "hbm", "achieved": v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": v["frac"], "bytes_per_launch": v["bytes_per_launch"], "mean_launch_ms": v["mean_launch_ms"]}
+            for k, v in lt["stiffness"].items()}
     if not args.no_batch:
         # 256 tanks of mixed size and order in one lockstep batch, one RK4 step
         # each way, against the per-tank sequential FP64 loop
