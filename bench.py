@@ -212,7 +212,11 @@ def batch_workload(args, modes=("lockstep_fp64", "lockstep_mixed", "concurrent_m
     from paper_1512_02548_amd import tune
     specs = wl.batch_tank_specs(count=args.tanks, rtol=1e-10)
     # element tiles of the stiffness kernel from the autotuner, per (P, nz) class
-    table, trep = tune.tune(specs)
+    if getattr(args, "tiles", 0):
+        table = {k: args.tiles for k in tune.classes(specs)}
+        trep = {"fixed": args.tiles}
+    else:
+        table, trep = tune.tune_batch(specs, wl.batch_tank_state)
     print(f"# autotune: {trep}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     tanks = build_meshes(lib, specs, wl.batch_tank_state, tiles=table)
@@ -229,6 +233,21 @@ def batch_workload(args, modes=("lockstep_fp64", "lockstep_mixed", "concurrent_m
             t["phi"].copy_(p)
             t["ws"].zero_()
             t["mesh"].reset_history()
+
+    # the batched stiffness launch over every tank of an order (all live),
+    # against the HBM roof: the C4 roofline
+    bt = lib.Batch([t["mesh"] for t in tanks], 0)
+    res["roofline_batch"] = {}
+    for P in sorted({sp.P for sp in specs}):
+        E = sum(2 * sp.nx * sp.nz for sp in specs if sp.P == P)
+        for name, prec, word, gword in (("fp64", 0, 8, 8), ("fp32", 1, 4, 4), ("bf16_factors", 2, 4, 2)):
+            ms = bt.apply_timed(P, prec, 20)
+            byts = stiffness_bytes_per_elem(P, word, gword=gword) * E
+            res["roofline_batch"][f"P{P}_{name}"] = {
+                "bound": "hbm", "achieved": byts / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": byts, "mean_launch_ms": ms,
+                "elements": E}
+    del bt
 
     def batched(name, nstreams, opts):
         b = lib.Batch([t["mesh"] for t in tanks], nstreams)
@@ -293,7 +312,7 @@ def serving(args):
     from paper_1512_02548_amd import workloads as wl
     n, steps = args.serve_requests, args.serve_steps
     reqs = serve.make_requests(n, 1.0, steps)
-    table, _ = tune.tune([r.spec for r in reqs])
+    table, _ = tune.tune_batch([r.spec for r in reqs], wl.batch_tank_state)
     # capacity: tank-steps/s of the lockstep batch over the first 32 requests
     be = serve.GpuBackend(nstreams=0, tiles=table)
     tanks = [be.create(r.spec, wl.batch_tank_state) for r in reqs[:32]]
@@ -352,6 +371,7 @@ def main():
                     help="comma-separated subset of the batch workload's modes")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--tiles", type=int, default=0, help="batch: stiffness tiles per workgroup (0: autotuner)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=200)

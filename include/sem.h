@@ -297,6 +297,14 @@ sem_status sem_batch_graphs(sem_batch* batch, int32_t enable);
 sem_status sem_batch_graph_count(const sem_batch* batch, int32_t* captured_host);
 void sem_batch_destroy(sem_batch* batch);
 
+/* Benchmark hook: mean device time (ms, HOST) of one batched stiffness
+ * element launch over every tank of `order` in a lockstep batch (all tanks
+ * live, no masking), prec 0 = FP64, 1 = FP32, 2 = FP32 with bfloat16
+ * factors, over `reps` launches after a warm-up launch.  Overwrites the
+ * tanks' scratch vectors. */
+sem_status sem_batch_apply_timed(sem_batch* batch, int32_t order, int32_t prec, int32_t reps, float* ms_host,
+                                 void* stream);
+
 /* Self-test of the matrix-core instructions' lane layout: runs one 16x16x4
  * FP64 and one FP32 MFMA on known operands in the mesh's scratch space and
  * returns the largest deviation from the expected product in *max_err_host

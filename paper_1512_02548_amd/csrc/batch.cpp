@@ -763,6 +763,41 @@ extern "C" sem_status sem_batch_laplace_solve(sem_batch* B, const double* const*
   return s ? s : s2;
 }
 
+extern "C" sem_status sem_batch_apply_timed(sem_batch* B, int32_t order, int32_t prec, int32_t reps, float* ms,
+                                            void* stream) {
+  if (!B || !ms || reps < 1) return fail(SEM_E_INVAL, "bad argument");
+  if (prec < 0 || prec > 2) return fail(SEM_E_INVAL, "unknown precision");
+  if (B->nstreams != 0) return fail(SEM_E_INVAL, "timing needs a lockstep batch");
+  if (order < 1 || order > kMaxOrder || B->stiff[order].items.empty())
+    return fail(SEM_E_INVAL, "no tank of this order in the batch");
+  hipStream_t cst = (hipStream_t)stream;
+  if (sem_status s = enter(B, cst)) return s;
+  hipStream_t st = B->lstream;
+  std::vector<int> all(B->meshes.size());
+  for (size_t t = 0; t < all.size(); ++t) all[t] = (int)t;
+  if (sem_status s = set_live(B, all, st)) return s;
+  const BatchArgs a = args(B);
+  const BatchStage& plan = prec == 0 ? B->stiff[order] : B->stiff32[order];
+  // every tank's tmp vector in, w out (FP32 for prec 1 and 2: the
+  // refinement's inner vectors), no masking, no gating
+  const VSel u = prec == 0 ? VSel{BV_TMP, 0} : VSel{BV_W, 0};
+  const VSel y = prec == 0 ? VSel{BV_W, 0} : VSel{BV_B, 0};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  launch_stiff_b(a, plan, order, u, y, 0, prec, st);   // warm-up
+  HIPCHK(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i) launch_stiff_b(a, plan, order, u, y, 0, prec, st);
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  *ms = t / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return leave(B, cst);
+}
+
 extern "C" sem_status sem_batch_graphs(sem_batch* B, int32_t enable) {
   if (!B) return fail(SEM_E_INVAL, "null batch");
   B->use_graphs = enable != 0;

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <set>
 #include <utility>
@@ -67,6 +68,7 @@ struct StiffArgs {
   const double* lay;              // [2nz][8] element constants (S_z: sigma derivatives and J)
   const double* invd;             // 1/d at the element nodes, tile layout (S_z)
   int32_t nx, nz, nc, nl, cb, tiles, periodic, pad;
+  int32_t kb, pad2;               // blocks per workgroup (single-tank launches)
 };
 
 template <typename T>
@@ -89,6 +91,8 @@ __host__ __device__ inline StiffArgs<T> stiff_args(const TankDev& h, const void*
   a.tiles = h.T;
   a.periodic = h.periodic;
   a.pad = ops_in_lds;
+  a.kb = 1;
+  a.pad2 = 0;
   return a;
 }
 
@@ -309,12 +313,233 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
   }
 }
 
-template <int P, typename T, typename GS, bool OPS_LDS>
+// Workgroup blocks b0 .. b0 + nblk - 1 of the tank's grid, one after the
+// other, for blocks of at most one tile per wavefront (the stiffness grids
+// never exceed four tiles per block).  The operators and the element table go
+// to LDS once; each block then stages its input region, runs its tiles and
+// sums its nodes exactly as stiff_body's workgroup of its own would (the same
+// values, bit for bit).  A wavefront's tile of the next block has its
+// geometric factors in flight while the current tile's second contraction
+// runs.
+template <int P, typename T, typename GS, bool OPS_LDS, bool SZ = false>
+__device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __restrict__ u, T* __restrict__ y,
+                                           T* __restrict__ side, int flags, uint32_t o_loc, uint32_t o_u,
+                                           uint32_t o_st, int b0, int nblk) {
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  constexpr int Np = (P + 1) * (P + 2) / 2;
+  constexpr int NpP = (Np + 15) / 16 * 16;
+  constexpr int MT = NpP / 16;      // M-tiles per operator block
+  constexpr int KS = NpP / 4;       // K-steps of stage 1
+  constexpr int kWaves = kBlockThreads / 64;
+  extern __shared__ unsigned char lds_raw[];
+  T* lop = reinterpret_cast<T*>(lds_raw);                        // [4][NpP][NpP]
+  int32_t* lloc = reinterpret_cast<int32_t*>(lds_raw + o_loc);   // [2nz][NpP]
+  T* ureg = reinterpret_cast<T*>(lds_raw + o_u);                 // [cb nc + nl]
+  T* st3 = reinterpret_cast<T*>(lds_raw + o_st);                 // [T 16][NpP]
+  const int nc = a.nc, nl = a.nl, nz2 = 2 * a.nz;
+  const int nbt = (a.nx + a.cb - 1) / a.cb;
+  const int b1 = min(b0 + nblk, nbt);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  auto tiles_of = [&](int b) {
+    const int cbb = min(a.cb, a.nx - b * a.cb);
+    return (cbb * nz2 + 15) >> 4;
+  };
+  // geometric factors of one tile (tile layout: one (component, M-tile, v)
+  // group is 64 consecutive values)
+  T g[SZ ? 1 : 3][MT][4];
+  auto load_g = [&](int b, int t) {
+    if constexpr (SZ) {
+      // 1/d of node 16 mt + 4 v + grp of element col (its tile-layout row is permuted)
+      const int64_t ibase = ((int64_t)b * a.tiles + t) * (int64_t)NpP * 16;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          g[0][mt][v] = gview(a.invd)[ibase + (16 * mt + 4 * grp + v) * 16 + col];
+    } else {
+      const int64_t gbase = (((int64_t)b * a.tiles + t) * 3) * (int64_t)NpP * 16;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            g[c][mt][v] = GLoad<T, GS>::at(a.G, gbase + (int64_t)c * NpP * 16 + (mt * 16 + v * 4) * 16 + lane);
+    }
+  };
+  // prefetching holds the factors live across stage 1; FP64 with three
+  // M-tiles (P = 8) would run out of registers, it loads them after stage 1
+  constexpr bool kPrefetch = MT <= 2 || sizeof(T) == sizeof(float);
+  if (kPrefetch && wave < tiles_of(b0)) load_g(b0, wave);
+  // stage operators and element tables in LDS, once for all blocks
+  if constexpr (OPS_LDS) {
+    // 16-byte loads; 4 NpP^2 is a multiple of 16 values
+    constexpr int kVec = 16 / sizeof(T);
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    using V = typename std::conditional<sizeof(T) == 8, dv2, f4>::type;
+    const SEM_GLOBAL V* src = (const SEM_GLOBAL V*)gview(a.opf);
+    V* dst = reinterpret_cast<V*>(lop);
+#pragma unroll
+    for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
+  }
+  for (int i = threadIdx.x; i < nz2 * NpP; i += blockDim.x) lloc[i] = gview(a.elem_loc)[i];
+  // operator fragments: LDS copies, or global memory when they do not fit
+  auto opv = [&](int i) -> T {
+    if constexpr (OPS_LDS) return lop[i];
+    else return gview(a.opf)[i];
+  };
+  constexpr int kS2 = 2 * NpP * NpP;   // start of the stage-2 fragments
+  constexpr int NS = NpP + 1;          // padded row stride of the element outputs
+  for (int b = b0; b < b1; ++b) {
+    const int c0 = b * a.cb;
+    const int cbb = min(a.cb, a.nx - c0);
+    const int nreg = cbb * nc + nl;
+    const int EBb = cbb * nz2;
+    const int ntile = (EBb + 15) >> 4;
+    // the block's input region (the previous block's tiles are past their
+    // first contraction: the barrier after them)
+    const int64_t rbase = (c0 + cbb < a.nx) ? (int64_t)(c0 + cbb) * nc : (a.periodic ? 0 : (int64_t)a.nx * nc);
+#pragma unroll 4
+    for (int q = threadIdx.x; q < nreg; q += blockDim.x) {
+      const int lc = q / nc, ql = q - lc * nc;
+      const int64_t gi = (lc < cbb) ? (int64_t)(c0 + lc) * nc + ql : rbase + ql;
+      ureg[q] = (lc < cbb || ql < nl) ? gview(u)[gi] : T(0);
+    }
+    __syncthreads();
+    if (wave < ntile) {
+      const int t = wave;
+      const int eb = t * 16 + col;
+      const bool valid = eb < EBb;
+      const int lc = valid ? eb / nz2 : 0;
+      const int jt = valid ? eb - lc * nz2 : 0;
+      const int32_t* loc = lloc + jt * NpP;
+      // stage 1: [Dr; Ds] U
+      V4 acc[2 * MT];
+#pragma unroll
+      for (int i = 0; i < 2 * MT; ++i) acc[i] = V4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + grp;
+        const T bval = (valid && k < Np) ? ureg[lc * nc + loc[k]] : T(0);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int f = ((mt * KS + s) * 2) * 64 + lane;
+          acc[mt] = MF::op(opv(f), bval, acc[mt]);
+          acc[MT + mt] = MF::op(opv(f + 64), bval, acc[MT + mt]);
+        }
+      }
+      if (!kPrefetch) load_g(b, t);
+      // pointwise mixing with the geometric factors
+      T fr[MT][4], fs[MT][4];
+      T jel = T(1);
+      if constexpr (SZ) {
+        const SEM_GLOBAL double* lay = gview(a.lay) + jt * 8;
+        const T rsig = T(lay[1]), ssig = T(lay[3]);
+        jel = T(lay[4]);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T dsig = rsig * acc[mt][v] + ssig * acc[MT + mt][v];
+            fr[mt][v] = dsig * g[0][mt][v];
+            fs[mt][v] = T(0);
+          }
+      } else {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T tr = acc[mt][v], ts = acc[MT + mt][v];
+            fr[mt][v] = g[0][mt][v] * tr + g[1][mt][v] * ts;
+            fs[mt][v] = g[1][mt][v] * tr + g[2][mt][v] * ts;
+          }
+      }
+      // this wavefront's tile of the next block streams in during stage 2
+      if (kPrefetch && b + 1 < b1 && wave < tiles_of(b + 1)) load_g(b + 1, wave);
+      // stage 2: K index (blk, mt, v, grp) -> operator row 16 mt + row(v, grp)
+      V4 out[MT];
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) out[mo] = V4{0, 0, 0, 0};
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+#pragma unroll
+          for (int mo = 0; mo < MT; ++mo) {
+            const int f = kS2 + (((mt * 4 + v) * MT + mo) * 2) * 64 + lane;
+            out[mo] = MF::op(opv(f), fr[mt][v], out[mo]);
+            if constexpr (!SZ) out[mo] = MF::op(opv(f + 64), fs[mt][v], out[mo]);
+          }
+        }
+      if (valid) {
+#pragma unroll
+        for (int mo = 0; mo < MT; ++mo)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            st3[eb * NS + 16 * mo + MF::row(v, grp)] = SZ ? T(out[mo][v] * jel) : out[mo][v];
+      }
+    }
+    // a wavefront without a tile here still starts its next block's factors
+    if (kPrefetch && wave >= ntile && b + 1 < b1 && wave < tiles_of(b + 1)) load_g(b + 1, wave);
+    __syncthreads();
+    // node sums in a fixed order (same table as the reference kernel)
+    const T sgn = (flags & F_NEG) ? T(-1) : T(1);
+    const int nown = cbb * nc;
+    // unrolled so that the table loads of several nodes are in flight together
+#pragma unroll 4
+    for (int q = threadIdx.x; q < nown + nl; q += blockDim.x) {
+      const int lc = q / nc, ql = q - lc * nc;
+      if (lc >= cbb && ql >= nl) continue;
+      // the node's contributions: count and up to kMaxContrib entries (two 16-byte loads)
+      const int cnt = gview(a.acc_cnt)[ql];
+      int ent[kMaxContrib];
+#pragma unroll
+      for (int k = 0; k < kMaxContrib; ++k) ent[k] = gview(a.acc_ent)[(size_t)ql * kMaxContrib + k];
+      const bool masked = (flags & F_MASK_SURF) && gview(a.is_surf_loc)[ql];
+      T acc = 0;
+      if (lc < cbb) {
+#pragma unroll
+        for (int k = 0; k < kMaxContrib; ++k) {
+          if (k >= cnt) break;
+          const int e = ent[k];
+          const int off = e & 0x3fffffff;             // element-in-column * NpP + node
+          const int pos = (off / NpP) * NS + off % NpP;
+          if ((e >> 30) & 1) {
+            if (lc == 0) continue;  // previous column belongs to the left block
+            acc += st3[(lc - 1) * nz2 * NS + pos];
+          } else {
+            acc += st3[lc * nz2 * NS + pos];
+          }
+        }
+        y[(int64_t)(c0 + lc) * nc + ql] = masked ? T(0) : acc * sgn;
+      } else {
+        // right line: contributions of the block's last column
+#pragma unroll
+        for (int k = 0; k < kMaxContrib; ++k) {
+          if (k >= cnt) break;
+          const int e = ent[k];
+          if (((e >> 30) & 1) == 0) continue;
+          const int off = e & 0x3fffffff;
+          acc += st3[(cbb - 1) * nz2 * NS + (off / NpP) * NS + off % NpP];
+        }
+        side[(size_t)b * nl + ql] = masked ? T(0) : acc * sgn;
+      }
+    }
+    // (the next block's input staging may overlap these sums: they read only
+    // the element outputs, which the next tiles overwrite after the barrier
+    // that follows the staging)
+  }
+}
+
+template <int P, typename T, typename GS, bool OPS_LDS, bool MB>
 __global__ void __launch_bounds__(kBlockThreads)
 k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T* __restrict__ side, int flags,
              uint32_t o_loc, uint32_t o_u, uint32_t o_st) {
   if ((flags & F_GATE) && gview(a.ks)->done) return;
-  stiff_body<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, blockIdx.x);
+  if constexpr (MB) stiff_body_mb<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, blockIdx.x * a.kb, a.kb);
+  else stiff_body<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, blockIdx.x);
 }
 
 template <typename T, typename GS>
@@ -329,16 +554,21 @@ __device__ inline const T* stiff_ops(const TankDev& d) {
   else return d.opf32;
 }
 
-// batched: the tank's arguments and LDS offsets come from its descriptor
-template <int P, typename T, typename GS, bool OPS_LDS>
+// batched: the tank's arguments and LDS offsets come from its descriptor;
+// MB: each work item runs `by` consecutive blocks of its tank
+template <int P, typename T, typename GS, bool OPS_LDS, bool MB>
 __global__ void __launch_bounds__(kBlockThreads) k_stiff_mfma_b(BatchArgs ba, VSel u, VSel y, int flags) {
   SEM_BATCH_TANK(ba)
   if ((flags & F_GATE) && d.ks->done) return;
   const StiffArgs<T> a = stiff_args<T>(d, stiff_factors<T, GS>(d), stiff_ops<T>(d), OPS_LDS ? 1 : 0);
   size_t ol, ou, os;
   stiff_lds_layout<T>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os);
-  stiff_body<P, T, GS, OPS_LDS>(a, bvec<T>(d, u), bvec<T>(d, y), reinterpret_cast<T*>(d.side), flags, (uint32_t)ol,
-                                (uint32_t)ou, (uint32_t)os, it_.bx);
+  if constexpr (MB)
+    stiff_body_mb<P, T, GS, OPS_LDS>(a, bvec<T>(d, u), bvec<T>(d, y), reinterpret_cast<T*>(d.side), flags,
+                                     (uint32_t)ol, (uint32_t)ou, (uint32_t)os, it_.bx, it_.by);
+  else
+    stiff_body<P, T, GS, OPS_LDS>(a, bvec<T>(d, u), bvec<T>(d, y), reinterpret_cast<T*>(d.side), flags, (uint32_t)ol,
+                                  (uint32_t)ou, (uint32_t)os, it_.bx);
 }
 
 // S_z of the w~ recovery on the matrix cores (FP64), single tank and batched
@@ -354,8 +584,14 @@ __global__ void __launch_bounds__(kBlockThreads) k_sz_mfma_b(BatchArgs ba, SSel 
   const StiffArgs<double> a = stiff_args<double>(d, d.G, d.opf_sz, OPS_LDS ? 1 : 0);
   size_t ol, ou, os;
   stiff_lds_layout<double>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os);
-  stiff_body<P, double, double, OPS_LDS, true>(a, svec(ba, d, it_.tank, u), d.b, d.side, 0, (uint32_t)ol,
-                                               (uint32_t)ou, (uint32_t)os, it_.bx);
+  // the stiffness plan's items, which may span several blocks
+  const int nbt = (d.nx + d.cb - 1) / d.cb;
+  const int b1 = min(it_.bx + (it_.by > 1 ? it_.by : 1), nbt);
+  for (int b = it_.bx; b < b1; ++b) {
+    if (b > it_.bx) __syncthreads();
+    stiff_body<P, double, double, OPS_LDS, true>(a, svec(ba, d, it_.tank, u), d.b, d.side, 0, (uint32_t)ol,
+                                                 (uint32_t)ou, (uint32_t)os, b);
+  }
 }
 
 // Lane-layout self-test of the two MFMA builtins: D = A B with known A, B;
@@ -403,6 +639,22 @@ static void allow_lds(K kern, size_t bytes) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
+// Blocks per workgroup of a stiffness launch over `blocks` blocks: one while
+// the launch gives fewer than 2048 workgroups (eight per CU), then enough to
+// keep about 2048, so that the operators' copy into LDS is shared and each
+// wavefront streams its next tile's factors while it computes.  The results
+// do not depend on it; SEM_STIFF_BLOCKS (environment) sets it explicitly.
+// The FP64 variant that reads its operators from global memory (eighth order)
+// has no registers to spare for it and keeps one block per workgroup.
+int stiff_blocks_per_workgroup(int64_t blocks, bool register_bound) {
+  if (register_bound) return 1;
+  if (const char* e = std::getenv("SEM_STIFF_BLOCKS")) {
+    const int k = std::atoi(e);
+    if (k >= 1) return (int)std::min<int64_t>(k, std::max<int64_t>(1, blocks));
+  }
+  return (int)std::max<int64_t>(1, blocks / 2048);
+}
+
 size_t stiff_mfma_lds_bytes(const TankDev& h, size_t word) {
   size_t a, b, c;
   return word == sizeof(double) ? stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c)
@@ -437,21 +689,31 @@ static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T
     G = sizeof(GS) == sizeof(float) ? (const void*)h.G32 : (const void*)h.G16;
     opf = h.opf32;
   }
-  const StiffArgs<T> a = stiff_args<T>(h, G, opf, inl);
-#define SEM_SL(INL)                                                                                           \
-  SEM_MP_SWITCH(h.P, allow_lds(k_stiff_mfma<PP, T, GS, INL>, lds));                                          \
-  if (e0) {                                                                                                  \
-    SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL>), dim3(h.nb), dim3(kBlockThreads),  \
-                                             (uint32_t)lds, st, e0, e1, 0, a, u, y, side, flags, (uint32_t)ol, \
-                                             (uint32_t)ou, (uint32_t)os));                                     \
-  } else {                                                                                                   \
-    SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL>), dim3(h.nb), dim3(kBlockThreads), lds, \
-                                          st, a, u, y, side, flags, (uint32_t)ol, (uint32_t)ou, (uint32_t)os)); \
+  StiffArgs<T> a = stiff_args<T>(h, G, opf, inl);
+  a.kb = stiff_blocks_per_workgroup(h.nb, sizeof(T) == sizeof(double) && !inl);
+  const int nwg = (h.nb + a.kb - 1) / a.kb;
+#define SEM_SL(INL, MB)                                                                                          \
+  SEM_MP_SWITCH(h.P, allow_lds(k_stiff_mfma<PP, T, GS, INL, MB>, lds));                                         \
+  if (e0) {                                                                                                     \
+    SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB>), dim3(nwg), dim3(kBlockThreads),  \
+                                             (uint32_t)lds, st, e0, e1, 0, a, u, y, side, flags, (uint32_t)ol,    \
+                                             (uint32_t)ou, (uint32_t)os));                                        \
+  } else {                                                                                                      \
+    SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB>), dim3(nwg), dim3(kBlockThreads), lds, \
+                                          st, a, u, y, side, flags, (uint32_t)ol, (uint32_t)ou, (uint32_t)os));    \
   }
   if (inl) {
-    SEM_SL(true)
+    if (a.kb > 1) {
+      SEM_SL(true, true)
+    } else {
+      SEM_SL(true, false)
+    }
   } else {
-    SEM_SL(false)
+    if (a.kb > 1) {
+      SEM_SL(false, true)
+    } else {
+      SEM_SL(false, false)
+    }
   }
 #undef SEM_SL
 }
@@ -512,13 +774,20 @@ void launch_sz_mfma_b(const BatchArgs& a0, const BatchStage& p, int P, SSel u, h
 
 void plan_stiff(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int P, int f32, BatchStage* out) {
   *out = BatchStage{};
+  int64_t blocks = 0;
+  for (int t : ids)
+    if (tanks[t].P == P) blocks += tanks[t].nb;
+  TankDev probe{};
+  probe.NpP = ((P + 1) * (P + 2) / 2 + 15) / 16 * 16;
+  const int kb = stiff_blocks_per_workgroup(blocks, !f32 && !stiff_ops_in_lds<double>(probe));
   for (int t : ids) {
     const TankDev& h = tanks[t];
     if (h.P != P) continue;
     size_t a, b, c;
     const size_t lds = f32 ? stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c)
                            : stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c);
-    for (int x = 0; x < h.nb; ++x) out->items.push_back(BatchItem{t, x, 0, h.nb});
+    // item {tank, first block, blocks, tank's block count}
+    for (int x = 0; x < h.nb; x += kb) out->items.push_back(BatchItem{t, x, kb, h.nb});
     out->lds = std::max(out->lds, lds);
   }
 }
@@ -532,16 +801,26 @@ static void stiff_b_t(const BatchArgs& a0, const BatchStage& p, int P, VSel u, V
   TankDev probe{};
   probe.NpP = ((P + 1) * (P + 2) / 2 + 15) / 16 * 16;
   const int inl = stiff_ops_in_lds<T>(probe);
+  const bool mb = p.items[0].by > 1;     // every item of a plan spans the same block count
   const dim3 grid((unsigned)p.items.size());
+#define SEM_SB(INL, MB)                                                                                      \
+  SEM_MP_SWITCH(P, allow_lds(k_stiff_mfma_b<PP, T, GS, INL, MB>, p.lds));                                   \
+  SEM_MP_SWITCH(P, hipLaunchKernelGGL((k_stiff_mfma_b<PP, T, GS, INL, MB>), grid, dim3(kBlockThreads), p.lds, st, \
+                                      a, u, y, flags));
   if (inl) {
-    SEM_MP_SWITCH(P, allow_lds(k_stiff_mfma_b<PP, T, GS, true>, p.lds));
-    SEM_MP_SWITCH(P, hipLaunchKernelGGL((k_stiff_mfma_b<PP, T, GS, true>), grid, dim3(kBlockThreads), p.lds, st, a,
-                                        u, y, flags));
+    if (mb) {
+      SEM_SB(true, true)
+    } else {
+      SEM_SB(true, false)
+    }
   } else {
-    SEM_MP_SWITCH(P, allow_lds(k_stiff_mfma_b<PP, T, GS, false>, p.lds));
-    SEM_MP_SWITCH(P, hipLaunchKernelGGL((k_stiff_mfma_b<PP, T, GS, false>), grid, dim3(kBlockThreads), p.lds, st, a,
-                                        u, y, flags));
+    if (mb) {
+      SEM_SB(false, true)
+    } else {
+      SEM_SB(false, false)
+    }
   }
+#undef SEM_SB
 }
 
 void launch_stiff_b(const BatchArgs& a, const BatchStage& p, int P, VSel u, VSel y, int flags, int gstore,

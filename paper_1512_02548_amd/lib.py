@@ -94,6 +94,7 @@ _SIGS = {
                                      C.POINTER(C.c_uint8), C.POINTER(sem_solve_opts),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
     "sem_batch_destroy": (None, [_P]),
+    "sem_batch_apply_timed": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float), _P]),
     "sem_batch_graphs": (C.c_int, [_P, C.c_int32]),
     "sem_batch_graph_count": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "sem_selftest_mfma": (C.c_int, [_P, C.POINTER(C.c_double), _D, _P]),
@@ -291,6 +292,13 @@ class Batch:
     def graphs(self, enable):
         """Lockstep Arnoldi steps as HIP graph launches (default) or direct launches."""
         check(sem_batch_graphs(self.handle, 1 if enable else 0), "sem_batch_graphs")
+
+    def apply_timed(self, order, prec=SEM_PREC_FP64, reps=20, stream=None):
+        """Mean ms of one batched stiffness launch over the tanks of `order`."""
+        ms = C.c_float()
+        check(sem_batch_apply_timed(self.handle, int(order), int(prec), int(reps), C.byref(ms), _stream(stream)),
+              "sem_batch_apply_timed")
+        return ms.value
 
     def graph_count(self):
         c = C.c_int32()

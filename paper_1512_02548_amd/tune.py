@@ -56,6 +56,51 @@ def tune(specs, candidates=CANDIDATES, reps=40, prec=0, device="cuda"):
     return table, report
 
 
+def tune_batch(specs, state_fn, candidates=CANDIDATES, reps=10, sample=48, seed=7, device="cuda"):
+    """Tiles per workgroup chosen in the batched context: a sample of the
+    tanks (up to `sample`, spread over the (P, nz) classes) is built once per
+    candidate and its batched stiffness launch timed per order with every
+    tank live (sem_batch_apply_timed, FP64 and FP32).  The batched launch
+    covers all tanks of an order at once, so the choice is per order P and
+    applies to every nz.  Returns (table, report) like tune()."""
+    import torch
+
+    from . import lib
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(seed)
+    by_class = {}
+    for i, s in enumerate(specs):
+        by_class.setdefault((int(s.P), int(s.nz)), []).append(i)
+    per = max(1, sample // max(1, len(by_class)))
+    pick = sorted(j for idx in by_class.values() for j in rng.permutation(idx)[:per])
+    orders = sorted({int(specs[i].P) for i in pick})
+    times = {P: {} for P in orders}
+    for tt in candidates:
+        meshes = []
+        for i in pick:
+            s = specs[i]
+            probe = lib.Mesh(s.nx, s.nz, s.P, s.length, s.periodic, np.ones(s.ns), np.zeros(s.ns), bind=False,
+                             tiles_per_block=tt)
+            _, _, h, hx = state_fn(probe.surface_x(), s)
+            meshes.append(lib.Mesh(s.nx, s.nz, s.P, s.length, s.periodic, h, hx, tiles_per_block=tt,
+                                   device=device))
+        b = lib.Batch(meshes, 0)
+        for P in orders:
+            times[P][tt] = 1e3 * (b.apply_timed(P, 0, reps) + b.apply_timed(P, 1, reps))
+        del b, meshes
+        torch.cuda.empty_cache()
+    table, report = {}, {}
+    for P in orders:
+        best = min(times[P], key=times[P].get)
+        for (q, nz) in by_class:
+            if q == P:
+                table[(q, nz)] = best
+        report[f"P{P}"] = {"us_fp64_plus_fp32": {str(k): round(v, 2) for k, v in times[P].items()}, "best": best}
+    report["tanks_sampled"] = len(pick)
+    report["seconds"] = time.perf_counter() - t0
+    return table, report
+
+
 def tiles_for(table, spec):
     """Tiles per workgroup for a spec (0: the library's own choice)."""
     if not table:
