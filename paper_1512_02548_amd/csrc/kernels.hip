@@ -1635,13 +1635,10 @@ void launch_gather_surface(const TankDev& h, const TankDev* d, const double* u, 
   hipLaunchKernelGGL(k_gather_surface, dim3(nblk(h.ns)), dim3(kBlockThreads), 0, st, d, u, out);
 }
 
-// chunking of [0, n) for the reductions: at most 256 workgroups
+// chunking of [0, n) for the reductions (the device side's dot_chunk)
 void dot_layout(int64_t n, int* nchunk, int64_t* chunk) {
-  int64_t c = std::max<int64_t>(512, (n + 255) / 256);
-  int64_t k = (n + c - 1) / c;
-  if (k < 1) k = 1;
-  *nchunk = (int)k;
-  *chunk = c;
+  *chunk = dot_chunk(n);
+  *nchunk = dot_nchunk(n);
 }
 
 template <typename T>

@@ -28,14 +28,6 @@
 
 namespace sem {
 
-// Global-address-space views: pointers read from the argument block are
-// otherwise accessed through flat instructions.
-#define SEM_GLOBAL __attribute__((address_space(1)))
-template <typename T>
-__device__ inline const SEM_GLOBAL T* gview(const T* p) {
-  return (const SEM_GLOBAL T*)p;
-}
-
 template <typename T, typename GS>
 struct GLoad;
 template <>
@@ -98,9 +90,11 @@ __host__ __device__ inline StiffArgs<T> stiff_args(const TankDev& h, const void*
 
 // LDS: [operators 4 NpP^2 (if they fit)] [elem_loc 2nz NpP ints] [u region cb nc + nl]
 // [element outputs T 16 (NpP + 1): rows padded against bank conflicts]
+// [several blocks per workgroup: node-sum table, nc x kMaxContrib 16-bit
+// entries and nc 16-bit counts]
 template <typename T>
 __host__ __device__ inline size_t stiff_lds_layout(const TankDev& h, int ops_in_lds, size_t* o_loc, size_t* o_u,
-                                                   size_t* o_st) {
+                                                   size_t* o_st, bool mb = false, size_t* o_tab = nullptr) {
   size_t off = ops_in_lds ? 4 * (size_t)h.NpP * h.NpP * sizeof(T) : 0;
   *o_loc = off;
   off += (size_t)2 * h.nz * h.NpP * sizeof(int32_t);
@@ -110,7 +104,112 @@ __host__ __device__ inline size_t stiff_lds_layout(const TankDev& h, int ops_in_
   off = (off + 15) / 16 * 16;
   *o_st = off;
   off += (size_t)h.T * 16 * (h.NpP + 1) * sizeof(T);
+  off = (off + 15) / 16 * 16;
+  if (o_tab) *o_tab = off;
+  if (mb) off += (size_t)h.nc * (kMaxContrib + 1) * sizeof(uint16_t);
   return off;
+}
+
+// Registers per thread holding the next block's input region in the
+// several-blocks-per-workgroup kernel: cover cb nc + nl <= 32 P (P + 1) + 64
+// values (blocks of at most four 16-element tiles, a layer or more).
+__host__ __device__ constexpr int stiff_u_regs(int P) { return (32 * P * (P + 1) + 64 + kBlockThreads - 1) / kBlockThreads; }
+
+// Whether a tank's blocks fit that kernel: at most one tile per wavefront,
+// its input region in stiff_u_regs registers per thread, and its node-sum
+// entries (element-in-column x NpP + node) in 15 bits.
+__host__ __device__ inline bool stiff_mb_fits(const TankDev& h) {
+  return h.T <= kBlockThreads / 64 && (int64_t)h.cb * h.nc + h.nl <= (int64_t)stiff_u_regs(h.P) * kBlockThreads &&
+         2 * h.nz * h.NpP < 32768;
+}
+
+// The input region of the block of columns c0 .. c0 + cbb - 1 into LDS: its
+// own nodes and the first line of the next column (the wall line at a wall,
+// line 0 of a periodic tank).  Four loads per thread are issued together,
+// from clamped addresses, before any of them is stored.
+template <typename T>
+__device__ __forceinline__ void stage_region(const StiffArgs<T>& a, const T* __restrict__ u, T* ureg, int c0,
+                                             int cbb) {
+  const int nc = a.nc, nreg = cbb * nc + a.nl;
+  const int64_t rbase = (c0 + cbb < a.nx) ? (int64_t)(c0 + cbb) * nc : (a.periodic ? 0 : (int64_t)a.nx * nc);
+  const SEM_GLOBAL T* ug = gview(u);
+  for (int q0 = threadIdx.x; q0 < nreg; q0 += 4 * kBlockThreads) {
+    T v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = min(q0 + j * kBlockThreads, nreg - 1);
+      const int lc = q / nc, ql = q - lc * nc;
+      v[j] = ug[(lc < cbb) ? (int64_t)(c0 + lc) * nc + ql : rbase + ql];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (q0 + j * kBlockThreads < nreg) ureg[q0 + j * kBlockThreads] = v[j];
+  }
+}
+
+// Node sums of block b (columns c0 .. c0 + cbb - 1) in a fixed order, the
+// same contribution table as the reference kernel; the right line's sum over
+// the block's last column goes to the side buffer.  The tables of kNG nodes
+// per thread are requested together (no branch around the loads).
+template <int NpP, typename T>
+__device__ __forceinline__ void node_sums(const StiffArgs<T>& a, const T* st3, T* __restrict__ y,
+                                          T* __restrict__ side, int flags, int b, int c0, int cbb) {
+  constexpr int NS = NpP + 1;
+  const int nc = a.nc, nl = a.nl, nz2 = 2 * a.nz;
+  const int nown = cbb * nc, nq = nown + nl;
+  const T sgn = (flags & F_NEG) ? T(-1) : T(1);
+  const bool mask_surf = flags & F_MASK_SURF;
+  const SEM_GLOBAL int32_t* cntg = gview(a.acc_cnt);
+  const SEM_GLOBAL int32_t* entg = gview(a.acc_ent);
+  const SEM_GLOBAL int32_t* surfg = gview(a.is_surf_loc);
+  constexpr int kNG = 2;
+  for (int q0 = threadIdx.x; q0 < nq; q0 += kNG * kBlockThreads) {
+    int cnt[kNG], msk[kNG], ent[kNG][kMaxContrib];
+#pragma unroll
+    for (int j = 0; j < kNG; ++j) {
+      const int q = min(q0 + j * kBlockThreads, nq - 1);
+      const int ql = q - (q / nc) * nc;
+      cnt[j] = cntg[ql];
+#pragma unroll
+      for (int k = 0; k < kMaxContrib; ++k) ent[j][k] = entg[(size_t)ql * kMaxContrib + k];
+      msk[j] = surfg[ql];
+    }
+#pragma unroll
+    for (int j = 0; j < kNG; ++j) {
+      const int q = q0 + j * kBlockThreads;
+      if (q >= nq) break;
+      const int lc = q / nc, ql = q - lc * nc;
+      const bool masked = mask_surf && msk[j];
+      T acc = 0;
+      if (lc < cbb) {
+#pragma unroll
+        for (int k = 0; k < kMaxContrib; ++k) {
+          if (k >= cnt[j]) break;
+          const int e = ent[j][k];
+          const int off = e & 0x3fffffff;             // element-in-column * NpP + node
+          const int pos = (off / NpP) * NS + off % NpP;
+          if ((e >> 30) & 1) {
+            if (lc == 0) continue;  // previous column belongs to the left block
+            acc += st3[(lc - 1) * nz2 * NS + pos];
+          } else {
+            acc += st3[lc * nz2 * NS + pos];
+          }
+        }
+        y[(int64_t)(c0 + lc) * nc + ql] = masked ? T(0) : acc * sgn;
+      } else {
+        // right line: contributions of the block's last column
+#pragma unroll
+        for (int k = 0; k < kMaxContrib; ++k) {
+          if (k >= cnt[j]) break;
+          const int e = ent[j][k];
+          if (((e >> 30) & 1) == 0) continue;
+          const int off = e & 0x3fffffff;
+          acc += st3[(cbb - 1) * nz2 * NS + (off / NpP) * NS + off % NpP];
+        }
+        side[(size_t)b * nl + ql] = masked ? T(0) : acc * sgn;
+      }
+    }
+  }
 }
 
 // Workgroup b of the tank's grid (columns b cb .. b cb + cb - 1).
@@ -136,9 +235,8 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
   const int c0 = b * a.cb;
   const int cbb = min(a.cb, a.nx - c0);
   const int nc = a.nc, nl = a.nl, nz2 = 2 * a.nz;
-  const int nreg = cbb * nc + nl;
   const int EBb = cbb * nz2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int col = lane & 15, grp = lane >> 4;
   const int ntile = (EBb + 15) >> 4;
   // geometric factors of this wave's first tile, requested before anything
@@ -180,13 +278,7 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
     for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
   }
   for (int i = threadIdx.x; i < nz2 * NpP; i += blockDim.x) lloc[i] = gview(a.elem_loc)[i];
-  const int64_t rbase = (c0 + cbb < a.nx) ? (int64_t)(c0 + cbb) * nc : (a.periodic ? 0 : (int64_t)a.nx * nc);
-#pragma unroll 4
-  for (int q = threadIdx.x; q < nreg; q += blockDim.x) {
-    const int lc = q / nc, ql = q - lc * nc;
-    const int64_t gi = (lc < cbb) ? (int64_t)(c0 + lc) * nc + ql : rbase + ql;
-    ureg[q] = (lc < cbb || ql < nl) ? gview(u)[gi] : T(0);
-  }
+  stage_region(a, u, ureg, c0, cbb);
   __syncthreads();
   // operator fragments: LDS copies, or global memory when they do not fit
   auto opv = [&](int i) -> T {
@@ -208,7 +300,9 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int k = 4 * s + grp;
-      const T bval = (valid && k < Np) ? ureg[lc * nc + loc[k]] : T(0);
+      // (read from a clamped index, then selected: no branch around the read)
+      const T bv = ureg[lc * nc + loc[min(k, Np - 1)]];
+      const T bval = (valid && k < Np) ? bv : T(0);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const int f = ((mt * KS + s) * 2) * 64 + lane;
@@ -268,86 +362,87 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
     }
   }
   __syncthreads();
-  // node sums in a fixed order (same table as the reference kernel)
-  const T sgn = (flags & F_NEG) ? T(-1) : T(1);
-  const int nown = cbb * nc;
-  // unrolled so that the table loads of several nodes are in flight together
-#pragma unroll 4
-  for (int q = threadIdx.x; q < nown + nl; q += blockDim.x) {
-    const int lc = q / nc, ql = q - lc * nc;
-    if (lc >= cbb && ql >= nl) continue;
-    // the node's contributions: count and up to kMaxContrib entries (two 16-byte loads)
-    const int cnt = gview(a.acc_cnt)[ql];
-    int ent[kMaxContrib];
-#pragma unroll
-    for (int k = 0; k < kMaxContrib; ++k) ent[k] = gview(a.acc_ent)[(size_t)ql * kMaxContrib + k];
-    const bool masked = (flags & F_MASK_SURF) && gview(a.is_surf_loc)[ql];
-    T acc = 0;
-    if (lc < cbb) {
-#pragma unroll
-      for (int k = 0; k < kMaxContrib; ++k) {
-        if (k >= cnt) break;
-        const int e = ent[k];
-        const int off = e & 0x3fffffff;             // element-in-column * NpP + node
-        const int pos = (off / NpP) * NS + off % NpP;
-        if ((e >> 30) & 1) {
-          if (lc == 0) continue;  // previous column belongs to the left block
-          acc += st3[(lc - 1) * nz2 * NS + pos];
-        } else {
-          acc += st3[lc * nz2 * NS + pos];
-        }
-      }
-      y[(int64_t)(c0 + lc) * nc + ql] = masked ? T(0) : acc * sgn;
-    } else {
-      // right line: contributions of the block's last column
-#pragma unroll
-      for (int k = 0; k < kMaxContrib; ++k) {
-        if (k >= cnt) break;
-        const int e = ent[k];
-        if (((e >> 30) & 1) == 0) continue;
-        const int off = e & 0x3fffffff;
-        acc += st3[(cbb - 1) * nz2 * NS + (off / NpP) * NS + off % NpP];
-      }
-      side[(size_t)b * nl + ql] = masked ? T(0) : acc * sgn;
-    }
-  }
+  node_sums<NpP>(a, st3, y, side, flags, b, c0, cbb);
 }
 
 // Workgroup blocks b0 .. b0 + nblk - 1 of the tank's grid, one after the
 // other, for blocks of at most one tile per wavefront (the stiffness grids
-// never exceed four tiles per block).  The operators and the element table go
-// to LDS once; each block then stages its input region, runs its tiles and
-// sums its nodes exactly as stiff_body's workgroup of its own would (the same
-// values, bit for bit).  A wavefront's tile of the next block has its
-// geometric factors in flight while the current tile's second contraction
-// runs.
+// never exceed four tiles per block).  The operators, the element table and
+// the node-sum table (packed to 16-bit entries) go to LDS once; each block
+// then runs its tiles and sums its nodes exactly as stiff_body's workgroup of
+// its own would (the same values, bit for bit).  Every global load of a block
+// is issued one block ahead, unconditionally, from clamped addresses: its
+// input region (into registers, stored to LDS at the block's start) before
+// the first contraction, a wavefront's geometric factors after it; the node
+// sums read LDS only.
 template <int P, typename T, typename GS, bool OPS_LDS, bool SZ = false>
 __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __restrict__ u, T* __restrict__ y,
-                                           T* __restrict__ side, int flags, uint32_t o_loc, uint32_t o_u,
-                                           uint32_t o_st, int b0, int nblk) {
+                                              T* __restrict__ side, int flags, uint32_t o_loc, uint32_t o_u,
+                                              uint32_t o_st, uint32_t o_tab, int b0, int nblk) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   constexpr int Np = (P + 1) * (P + 2) / 2;
   constexpr int NpP = (Np + 15) / 16 * 16;
   constexpr int MT = NpP / 16;      // M-tiles per operator block
   constexpr int KS = NpP / 4;       // K-steps of stage 1
-  constexpr int kWaves = kBlockThreads / 64;
+  constexpr int NS = NpP + 1;       // padded row stride of the element outputs
+  constexpr int kU = stiff_u_regs(P);
   extern __shared__ unsigned char lds_raw[];
   T* lop = reinterpret_cast<T*>(lds_raw);                        // [4][NpP][NpP]
   int32_t* lloc = reinterpret_cast<int32_t*>(lds_raw + o_loc);   // [2nz][NpP]
   T* ureg = reinterpret_cast<T*>(lds_raw + o_u);                 // [cb nc + nl]
-  T* st3 = reinterpret_cast<T*>(lds_raw + o_st);                 // [T 16][NpP]
+  T* st3 = reinterpret_cast<T*>(lds_raw + o_st);                 // [T 16][NpP + 1]
+  uint16_t* tent = reinterpret_cast<uint16_t*>(lds_raw + o_tab); // [nc][kMaxContrib]
+  uint16_t* tcm = tent + (size_t)a.nc * kMaxContrib;             // [nc]: count | masked << 4
   const int nc = a.nc, nl = a.nl, nz2 = 2 * a.nz;
   const int nbt = (a.nx + a.cb - 1) / a.cb;
   const int b1 = min(b0 + nblk, nbt);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int col = lane & 15, grp = lane >> 4;
-  auto tiles_of = [&](int b) {
-    const int cbb = min(a.cb, a.nx - b * a.cb);
-    return (cbb * nz2 + 15) >> 4;
+  auto cols_of = [&](int b) { return min(a.cb, a.nx - b * a.cb); };
+  auto tiles_of = [&](int b) { return (cols_of(b) * nz2 + 15) >> 4; };
+  // operators, element table and node-sum table: requested first, stored once
+  if constexpr (OPS_LDS) {
+    // 16-byte loads; 4 NpP^2 is a multiple of 16 values
+    constexpr int kVec = 16 / sizeof(T);
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    using V = typename std::conditional<sizeof(T) == 8, dv2, f4>::type;
+    const SEM_GLOBAL V* src = (const SEM_GLOBAL V*)gview(a.opf);
+    V* dst = reinterpret_cast<V*>(lop);
+#pragma unroll
+    for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
+  }
+  for (int i = threadIdx.x; i < nz2 * NpP; i += kBlockThreads) lloc[i] = gview(a.elem_loc)[i];
+  {
+    const bool mask_surf = flags & F_MASK_SURF;
+    for (int ql = threadIdx.x; ql < nc; ql += kBlockThreads) {
+      const int cnt = gview(a.acc_cnt)[ql];
+      const int msk = mask_surf && gview(a.is_surf_loc)[ql];
+#pragma unroll
+      for (int k = 0; k < kMaxContrib; ++k) {
+        const int e = gview(a.acc_ent)[(size_t)ql * kMaxContrib + k];
+        // element-in-column * NpP + node (below 2^15, checked by the host) | previous column << 15
+        tent[ql * kMaxContrib + k] = (uint16_t)((e & 0x7fff) | (((e >> 30) & 1) << 15));
+      }
+      tcm[ql] = (uint16_t)(cnt | (msk << 4));
+    }
+  }
+  // input region of block b into registers (kU per thread cover any block;
+  // the host checks cb nc + nl <= kU * kBlockThreads)
+  T ur[kU];
+  auto fetch_u = [&](int b) {
+    const int c0 = b * a.cb, cbb = cols_of(b);
+    const int nreg = cbb * nc + nl;
+    const int64_t rbase = (c0 + cbb < a.nx) ? (int64_t)(c0 + cbb) * nc : (a.periodic ? 0 : (int64_t)a.nx * nc);
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+      const int q = min((int)threadIdx.x + j * kBlockThreads, nreg - 1);
+      const int lc = q / nc, ql = q - lc * nc;
+      ur[j] = gview(u)[(lc < cbb) ? (int64_t)(c0 + lc) * nc + ql : rbase + ql];
+    }
   };
-  // geometric factors of one tile (tile layout: one (component, M-tile, v)
-  // group is 64 consecutive values)
+  // geometric factors of tile t of block b (tile layout: one (component,
+  // M-tile, v) group is 64 consecutive values)
   T g[SZ ? 1 : 3][MT][4];
   auto load_g = [&](int b, int t) {
     if constexpr (SZ) {
@@ -369,51 +464,42 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
             g[c][mt][v] = GLoad<T, GS>::at(a.G, gbase + (int64_t)c * NpP * 16 + (mt * 16 + v * 4) * 16 + lane);
     }
   };
-  // prefetching holds the factors live across stage 1; FP64 with three
-  // M-tiles (P = 8) would run out of registers, it loads them after stage 1
+  // a wavefront's tile of block b, clamped to the block's last one (the
+  // factors of a wavefront without a tile there are loaded but never used)
+  auto tile_of = [&](int b) { return min(wave, tiles_of(b) - 1); };
+  // prefetching holds the factors live across the first contraction; FP64
+  // with three M-tiles (P = 8) would run out of registers, it loads them
+  // after that contraction
   constexpr bool kPrefetch = MT <= 2 || sizeof(T) == sizeof(float);
-  if (kPrefetch && wave < tiles_of(b0)) load_g(b0, wave);
-  // stage operators and element tables in LDS, once for all blocks
-  if constexpr (OPS_LDS) {
-    // 16-byte loads; 4 NpP^2 is a multiple of 16 values
-    constexpr int kVec = 16 / sizeof(T);
-    typedef double dv2 __attribute__((ext_vector_type(2)));
-    using V = typename std::conditional<sizeof(T) == 8, dv2, f4>::type;
-    const SEM_GLOBAL V* src = (const SEM_GLOBAL V*)gview(a.opf);
-    V* dst = reinterpret_cast<V*>(lop);
-#pragma unroll
-    for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
-  }
-  for (int i = threadIdx.x; i < nz2 * NpP; i += blockDim.x) lloc[i] = gview(a.elem_loc)[i];
-  // operator fragments: LDS copies, or global memory when they do not fit
+  fetch_u(b0);
+  if constexpr (kPrefetch) load_g(b0, tile_of(b0));
   auto opv = [&](int i) -> T {
     if constexpr (OPS_LDS) return lop[i];
     else return gview(a.opf)[i];
   };
   constexpr int kS2 = 2 * NpP * NpP;   // start of the stage-2 fragments
-  constexpr int NS = NpP + 1;          // padded row stride of the element outputs
+  const T sgn = (flags & F_NEG) ? T(-1) : T(1);
   for (int b = b0; b < b1; ++b) {
     const int c0 = b * a.cb;
-    const int cbb = min(a.cb, a.nx - c0);
-    const int nreg = cbb * nc + nl;
+    const int cbb = cols_of(b);
     const int EBb = cbb * nz2;
     const int ntile = (EBb + 15) >> 4;
-    // the block's input region (the previous block's tiles are past their
-    // first contraction: the barrier after them)
-    const int64_t rbase = (c0 + cbb < a.nx) ? (int64_t)(c0 + cbb) * nc : (a.periodic ? 0 : (int64_t)a.nx * nc);
-#pragma unroll 4
-    for (int q = threadIdx.x; q < nreg; q += blockDim.x) {
-      const int lc = q / nc, ql = q - lc * nc;
-      const int64_t gi = (lc < cbb) ? (int64_t)(c0 + lc) * nc + ql : rbase + ql;
-      ureg[q] = (lc < cbb || ql < nl) ? gview(u)[gi] : T(0);
-    }
-    __syncthreads();
+    const int nreg = cbb * nc + nl;
+    const int bn = min(b + 1, b1 - 1);
+    // the block's input region into LDS (every wavefront is past the previous
+    // block's node sums, which read only the tables and the element outputs)
+#pragma unroll
+    for (int j = 0; j < kU; ++j)
+      if ((int)threadIdx.x + j * kBlockThreads < nreg) ureg[threadIdx.x + j * kBlockThreads] = ur[j];
+    lds_barrier();
+    if (b + 1 < b1) fetch_u(bn);   // in flight during this block's contractions and sums (uniform)
+    const int eb = wave * 16 + col;
+    const bool valid = eb < EBb;
+    const int lc = valid ? eb / nz2 : 0;
+    const int jt = valid ? eb - lc * nz2 : 0;
+    T fr[MT][4], fs[MT][4];
+    T jel = T(1);
     if (wave < ntile) {
-      const int t = wave;
-      const int eb = t * 16 + col;
-      const bool valid = eb < EBb;
-      const int lc = valid ? eb / nz2 : 0;
-      const int jt = valid ? eb - lc * nz2 : 0;
       const int32_t* loc = lloc + jt * NpP;
       // stage 1: [Dr; Ds] U
       V4 acc[2 * MT];
@@ -422,7 +508,9 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int k = 4 * s + grp;
-        const T bval = (valid && k < Np) ? ureg[lc * nc + loc[k]] : T(0);
+        // (read from a clamped index, then selected: no branch around the read)
+        const T bv = ureg[lc * nc + loc[min(k, Np - 1)]];
+        const T bval = (valid && k < Np) ? bv : T(0);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           const int f = ((mt * KS + s) * 2) * 64 + lane;
@@ -430,10 +518,8 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
           acc[MT + mt] = MF::op(opv(f + 64), bval, acc[MT + mt]);
         }
       }
-      if (!kPrefetch) load_g(b, t);
+      if constexpr (!kPrefetch) load_g(b, wave);
       // pointwise mixing with the geometric factors
-      T fr[MT][4], fs[MT][4];
-      T jel = T(1);
       if constexpr (SZ) {
         const SEM_GLOBAL double* lay = gview(a.lay) + jt * 8;
         const T rsig = T(lay[1]), ssig = T(lay[3]);
@@ -456,8 +542,12 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
             fs[mt][v] = g[1][mt][v] * tr + g[2][mt][v] * ts;
           }
       }
-      // this wavefront's tile of the next block streams in during stage 2
-      if (kPrefetch && b + 1 < b1 && wave < tiles_of(b + 1)) load_g(b + 1, wave);
+    }
+    // this wavefront's factors of the next block stream in during the second
+    // contraction and the node sums
+    if constexpr (kPrefetch)
+      if (b + 1 < b1) load_g(bn, tile_of(bn));   // (uniform)
+    if (wave < ntile) {
       // stage 2: K index (blk, mt, v, grp) -> operator row 16 mt + row(v, grp)
       V4 out[MT];
 #pragma unroll
@@ -481,64 +571,58 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
             st3[eb * NS + 16 * mo + MF::row(v, grp)] = SZ ? T(out[mo][v] * jel) : out[mo][v];
       }
     }
-    // a wavefront without a tile here still starts its next block's factors
-    if (kPrefetch && wave >= ntile && b + 1 < b1 && wave < tiles_of(b + 1)) load_g(b + 1, wave);
-    __syncthreads();
-    // node sums in a fixed order (same table as the reference kernel)
-    const T sgn = (flags & F_NEG) ? T(-1) : T(1);
-    const int nown = cbb * nc;
-    // unrolled so that the table loads of several nodes are in flight together
-#pragma unroll 4
-    for (int q = threadIdx.x; q < nown + nl; q += blockDim.x) {
-      const int lc = q / nc, ql = q - lc * nc;
-      if (lc >= cbb && ql >= nl) continue;
-      // the node's contributions: count and up to kMaxContrib entries (two 16-byte loads)
-      const int cnt = gview(a.acc_cnt)[ql];
-      int ent[kMaxContrib];
+    lds_barrier();
+    // node sums in a fixed order (the reference kernel's table), from LDS
+    for (int q = threadIdx.x; q < nreg; q += kBlockThreads) {
+      const int lq = q / nc, ql = q - lq * nc;
+      const int cm = tcm[ql];
+      const int cnt = cm & 15;
+      const bool masked = (cm >> 4) & 1;
+      uint16_t ent[kMaxContrib];
 #pragma unroll
-      for (int k = 0; k < kMaxContrib; ++k) ent[k] = gview(a.acc_ent)[(size_t)ql * kMaxContrib + k];
-      const bool masked = (flags & F_MASK_SURF) && gview(a.is_surf_loc)[ql];
+      for (int k = 0; k < kMaxContrib; ++k) ent[k] = tent[ql * kMaxContrib + k];
       T acc = 0;
-      if (lc < cbb) {
+      if (lq < cbb) {
 #pragma unroll
         for (int k = 0; k < kMaxContrib; ++k) {
           if (k >= cnt) break;
           const int e = ent[k];
-          const int off = e & 0x3fffffff;             // element-in-column * NpP + node
+          const int off = e & 0x7fff;
           const int pos = (off / NpP) * NS + off % NpP;
-          if ((e >> 30) & 1) {
-            if (lc == 0) continue;  // previous column belongs to the left block
-            acc += st3[(lc - 1) * nz2 * NS + pos];
+          if (e >> 15) {
+            if (lq == 0) continue;  // previous column belongs to the left block
+            acc += st3[(lq - 1) * nz2 * NS + pos];
           } else {
-            acc += st3[lc * nz2 * NS + pos];
+            acc += st3[lq * nz2 * NS + pos];
           }
         }
-        y[(int64_t)(c0 + lc) * nc + ql] = masked ? T(0) : acc * sgn;
+        y[(int64_t)(c0 + lq) * nc + ql] = masked ? T(0) : acc * sgn;
       } else {
         // right line: contributions of the block's last column
 #pragma unroll
         for (int k = 0; k < kMaxContrib; ++k) {
           if (k >= cnt) break;
           const int e = ent[k];
-          if (((e >> 30) & 1) == 0) continue;
-          const int off = e & 0x3fffffff;
+          if ((e >> 15) == 0) continue;
+          const int off = e & 0x7fff;
           acc += st3[(cbb - 1) * nz2 * NS + (off / NpP) * NS + off % NpP];
         }
         side[(size_t)b * nl + ql] = masked ? T(0) : acc * sgn;
       }
     }
-    // (the next block's input staging may overlap these sums: they read only
-    // the element outputs, which the next tiles overwrite after the barrier
-    // that follows the staging)
+    // (the next block's input may be stored while these sums run: they read
+    // only the tables and the element outputs, which the next tiles overwrite
+    // after the barrier that follows that store)
   }
 }
 
 template <int P, typename T, typename GS, bool OPS_LDS, bool MB>
 __global__ void __launch_bounds__(kBlockThreads)
 k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T* __restrict__ side, int flags,
-             uint32_t o_loc, uint32_t o_u, uint32_t o_st) {
+             uint32_t o_loc, uint32_t o_u, uint32_t o_st, uint32_t o_tab) {
   if ((flags & F_GATE) && gview(a.ks)->done) return;
-  if constexpr (MB) stiff_body_mb<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, blockIdx.x * a.kb, a.kb);
+  if constexpr (MB)
+    stiff_body_mb<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, o_tab, blockIdx.x * a.kb, a.kb);
   else stiff_body<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, blockIdx.x);
 }
 
@@ -561,11 +645,11 @@ __global__ void __launch_bounds__(kBlockThreads) k_stiff_mfma_b(BatchArgs ba, VS
   SEM_BATCH_TANK(ba)
   if ((flags & F_GATE) && d.ks->done) return;
   const StiffArgs<T> a = stiff_args<T>(d, stiff_factors<T, GS>(d), stiff_ops<T>(d), OPS_LDS ? 1 : 0);
-  size_t ol, ou, os;
-  stiff_lds_layout<T>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os);
+  size_t ol, ou, os, ot;
+  stiff_lds_layout<T>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os, MB, &ot);
   if constexpr (MB)
     stiff_body_mb<P, T, GS, OPS_LDS>(a, bvec<T>(d, u), bvec<T>(d, y), reinterpret_cast<T*>(d.side), flags,
-                                     (uint32_t)ol, (uint32_t)ou, (uint32_t)os, it_.bx, it_.by);
+                                     (uint32_t)ol, (uint32_t)ou, (uint32_t)os, (uint32_t)ot, it_.bx, it_.by);
   else
     stiff_body<P, T, GS, OPS_LDS>(a, bvec<T>(d, u), bvec<T>(d, y), reinterpret_cast<T*>(d.side), flags, (uint32_t)ol,
                                   (uint32_t)ou, (uint32_t)os, it_.bx);
@@ -612,13 +696,14 @@ __global__ void k_mfma_probe(double* out64, float* out32) {
   }
 }
 
-// operators go to LDS unless they would take more than 40 KiB.  (A workgroup
-// may hold up to 160 KiB of LDS on this chip, but the 72 KiB eighth-order
-// FP64 operators leave room for one workgroup per CU, which measured slower
-// than reading their fragments through the caches with more workgroups.)
+// operators go to LDS unless they would take more than 80 KiB (a workgroup
+// may hold up to 160 KiB).  The 72 KiB seventh- and eighth-order FP64
+// operators leave room for one workgroup per CU, which is also all their
+// registers allow (one wavefront per SIMD); reading the fragments from LDS
+// instead of through the caches measured 1.7x faster on the 256-tank batch.
 template <typename T>
 __host__ __device__ inline int stiff_ops_in_lds(const TankDev& h) {
-  return 4 * (size_t)h.NpP * h.NpP * sizeof(T) <= 40 * 1024 ? 1 : 0;
+  return 4 * (size_t)h.NpP * h.NpP * sizeof(T) <= 80 * 1024 ? 1 : 0;
 }
 
 // Kernels whose dynamic LDS exceeds the default 64 KiB get the chip's full
@@ -645,9 +730,10 @@ static void allow_lds(K kern, size_t bytes) {
 // wavefront streams its next tile's factors while it computes.  The results
 // do not depend on it; SEM_STIFF_BLOCKS (environment) sets it explicitly.
 // The FP64 variant that reads its operators from global memory (eighth order)
-// has no registers to spare for it and keeps one block per workgroup.
-int stiff_blocks_per_workgroup(int64_t blocks, bool register_bound) {
-  if (register_bound) return 1;
+// has no registers to spare for it and keeps one block per workgroup, and so
+// do tanks whose blocks do not fit that kernel (stiff_mb_fits).
+int stiff_blocks_per_workgroup(int64_t blocks, bool register_bound, bool fits) {
+  if (register_bound || !fits) return 1;
   if (const char* e = std::getenv("SEM_STIFF_BLOCKS")) {
     const int k = std::atoi(e);
     if (k >= 1) return (int)std::min<int64_t>(k, std::max<int64_t>(1, blocks));
@@ -678,8 +764,9 @@ template <typename T, typename GS>
 static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T* side, int flags, hipEvent_t e0,
                          hipEvent_t e1, hipStream_t st) {
   const int inl = stiff_ops_in_lds<T>(h);
-  size_t ol, ou, os;
-  const size_t lds = stiff_lds_layout<T>(h, inl, &ol, &ou, &os);
+  const int kb = stiff_blocks_per_workgroup(h.nb, sizeof(T) == sizeof(double) && !inl, stiff_mb_fits(h));
+  size_t ol, ou, os, ot;
+  const size_t lds = stiff_lds_layout<T>(h, inl, &ol, &ou, &os, kb > 1, &ot);
   const void* G;
   const T* opf;
   if constexpr (sizeof(T) == sizeof(double)) {
@@ -690,17 +777,18 @@ static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T
     opf = h.opf32;
   }
   StiffArgs<T> a = stiff_args<T>(h, G, opf, inl);
-  a.kb = stiff_blocks_per_workgroup(h.nb, sizeof(T) == sizeof(double) && !inl);
+  a.kb = kb;
   const int nwg = (h.nb + a.kb - 1) / a.kb;
 #define SEM_SL(INL, MB)                                                                                          \
   SEM_MP_SWITCH(h.P, allow_lds(k_stiff_mfma<PP, T, GS, INL, MB>, lds));                                         \
   if (e0) {                                                                                                     \
     SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB>), dim3(nwg), dim3(kBlockThreads),  \
                                              (uint32_t)lds, st, e0, e1, 0, a, u, y, side, flags, (uint32_t)ol,    \
-                                             (uint32_t)ou, (uint32_t)os));                                        \
+                                             (uint32_t)ou, (uint32_t)os, (uint32_t)ot));                          \
   } else {                                                                                                      \
     SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB>), dim3(nwg), dim3(kBlockThreads), lds, \
-                                          st, a, u, y, side, flags, (uint32_t)ol, (uint32_t)ou, (uint32_t)os));    \
+                                          st, a, u, y, side, flags, (uint32_t)ol, (uint32_t)ou, (uint32_t)os,      \
+                                          (uint32_t)ot));                                                         \
   }
   if (inl) {
     if (a.kb > 1) {
@@ -779,13 +867,16 @@ void plan_stiff(const std::vector<TankDev>& tanks, const std::vector<int>& ids, 
     if (tanks[t].P == P) blocks += tanks[t].nb;
   TankDev probe{};
   probe.NpP = ((P + 1) * (P + 2) / 2 + 15) / 16 * 16;
-  const int kb = stiff_blocks_per_workgroup(blocks, !f32 && !stiff_ops_in_lds<double>(probe));
+  bool fits = true;
+  for (int t : ids)
+    if (tanks[t].P == P) fits = fits && stiff_mb_fits(tanks[t]);
+  const int kb = stiff_blocks_per_workgroup(blocks, !f32 && !stiff_ops_in_lds<double>(probe), fits);
   for (int t : ids) {
     const TankDev& h = tanks[t];
     if (h.P != P) continue;
-    size_t a, b, c;
-    const size_t lds = f32 ? stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c)
-                           : stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c);
+    size_t a, b, c, e;
+    const size_t lds = f32 ? stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c, kb > 1, &e)
+                           : stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c, kb > 1, &e);
     // item {tank, first block, blocks, tank's block count}
     for (int x = 0; x < h.nb; x += kb) out->items.push_back(BatchItem{t, x, kb, h.nb});
     out->lds = std::max(out->lds, lds);

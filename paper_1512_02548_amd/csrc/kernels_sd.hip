@@ -87,7 +87,7 @@ constexpr int kNTMax = 4;    // N-tiles per wave at most
 __host__ __device__ inline bool sd_back_dft(int nx, int q, int fft_n1, int nMT3) {
   return fft_n1 == 0 && nx <= 64 && q <= 32 && sd_shape(nx, nMT3).ntw == 1;
 }
-constexpr int kKC = 24;      // K-steps of the right-hand factor staged in LDS at a time (LDS < 64 KiB)
+constexpr int kKC = 16;      // K-steps of the right-hand factor staged in LDS at a time (64 rows)
 // LDS of the condensation's staging area (and, split, of its wave partials),
 // before the interior index table
 __host__ __device__ inline size_t sd_cond_stage_bytes(int ntw, size_t word, int split) {
@@ -98,93 +98,104 @@ __host__ __device__ inline size_t sd_cond_stage_bytes(int ntw, size_t word, int 
 
 // condense, as the product [Y; T_L; T_R] = A1 R over the tank's columns:
 // workgroup (column group bx, M-tiles 4 by .. 4 by + 3), one M-tile per wave
-// and all N-tiles of the group, the full K range in order (so an output does
+// and NTW N-tiles of 16 columns, the full K range in order (so an output does
 // not depend on the grouping); R is staged in LDS in chunks of kKC K-steps.
-template <typename T>
-__device__ __forceinline__ void sd_cond_body(const TankDev& d, int which, const T* __restrict__ r,
+// SPLIT (small tanks, NTW = 1): one M-tile per workgroup, wave w takes the
+// K-steps w, w + 4, ... and the four partial tiles are added in wave order.
+template <typename T, int NTW, bool SPLIT>
+__device__ __forceinline__ void sd_cond_impl(const TankDev& d, const SDData& sd, const T* __restrict__ r,
                                              const double* __restrict__ nscale, T* __restrict__ vout, int bx,
                                              int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
-  const SDData& sd = d.sd[which];
   extern __shared__ unsigned char lds_raw[];
   const int nI = sd.nI, q = sd.q, nx = d.nx, KS = sd.KS1, nMT = sd.nMT1;
-  const SdShape sh = sd_shape(nx, nMT);
-  const int ntw = sh.ntw;
-  const int ldr = 16 * ntw + 1;                          // odd stride: conflict-free staging
+  constexpr int ldr = 16 * NTW + 1;                      // odd stride: conflict-free staging
   T* Rs = reinterpret_cast<T*>(lds_raw);                 // [4 kKC][ldr]
-  int32_t* lidx = reinterpret_cast<int32_t*>(lds_raw + sd_cond_stage_bytes(ntw, sizeof(T), sh.split));   // [nI]
-  const int c0 = bx * 16 * ntw;
+  int32_t* lidx = reinterpret_cast<int32_t*>(lds_raw + sd_cond_stage_bytes(NTW, sizeof(T), SPLIT));   // [nI]
+  const int c0 = bx * 16 * NTW;
   for (int k = threadIdx.x; k < nI; k += blockDim.x) lidx[k] = sd.I_idx[k];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const int mt = sh.split ? by : 4 * by + wv;
-  const int s_first = sh.split ? wv : 0, s_step = sh.split ? kWaves : 1;
+  const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
+  const int mt = SPLIT ? by : 4 * by + wv;
+  const int s_first = SPLIT ? wv : 0;
+  constexpr int s_step = SPLIT ? kWaves : 1;
+  constexpr int kSteps = kKC / s_step;                   // K-steps of one wave per chunk
   const double rs = sd_in_scale(nscale);
-  const T* A = SdMat<T>::A1(sd) + (size_t)min(mt, nMT - 1) * KS * 64;
-  V4 acc[kNTMax];
+  const SEM_GLOBAL T* A = gview(SdMat<T>::A1(sd)) + (size_t)min(mt, nMT - 1) * KS * 64;
+  const SEM_GLOBAL T* rg = gview(r);
+  V4 acc[NTW];
 #pragma unroll
-  for (int u = 0; u < kNTMax; ++u) acc[u] = V4{0, 0, 0, 0};
+  for (int u = 0; u < NTW; ++u) acc[u] = V4{0, 0, 0, 0};
+  // R chunk s0 (4 kKC = 64 interior rows x 16 NTW columns): lane l of wave w
+  // reads row l of columns w, w + 4, ... (consecutive lanes, consecutive
+  // interior unknowns of a column).  Fetched into registers one chunk ahead,
+  // so that its loads are in flight during the previous chunk's products,
+  // and staged into LDS after them.  Every load is issued unconditionally
+  // from a clamped address (no branch around it, so that all of them are in
+  // flight together); rows and columns outside the tank are staged as zeros,
+  // and the scale is applied, when the chunk is staged.
+  static_assert(4 * kKC == 64, "one chunk row per lane");
+  constexpr int kR = 4 * NTW;
+  const int64_t ncl = d.nc;
+  T pre[kR];
+  auto fetch = [&](int s0) {
+    const int64_t li = lidx[min(4 * s0 + lane, nI - 1)];
+#pragma unroll
+    for (int i = 0; i < kR; ++i) pre[i] = rg[min(c0 + wv + 4 * i, nx - 1) * ncl + li];
+  };
+  auto stage = [&](int s0) {
+    const int k = 4 * s0 + lane;
+    const bool kv = k < nI;
+    const int64_t li = lidx[min(k, nI - 1)];
+#pragma unroll
+    for (int i = 0; i < kR; ++i) {
+      const int cc = wv + 4 * i;
+      const bool ok = kv && c0 + cc < nx;
+      const T v = ok ? (nscale ? T((double)pre[i] * rs) : pre[i]) : T(0);
+      Rs[lane * ldr + cc] = v;
+      if (vout && by == 0 && ok) vout[(c0 + cc) * ncl + li] = v;
+    }
+  };
+  __syncthreads();   // interior index table
+  if (KS > 0) fetch(0);
   for (int s0 = 0; s0 < KS; s0 += kKC) {
     const int kc = min(kKC, KS - s0);
-    const int nk = 4 * kc;
+    __syncthreads();   // every wave is past the previous chunk's products
+    stage(s0);
     __syncthreads();
-    // K fastest: consecutive threads read consecutive interior unknowns of a
-    // column; unrolled so that the loads of several entries are in flight
-#pragma unroll 8
-    for (int t = threadIdx.x; t < nk * 16 * ntw; t += blockDim.x) {
-      const int cc = t / nk, kk = t - cc * nk;
-      const int k = 4 * s0 + kk, c = c0 + cc;
-      T v = T(0);
-      if (k < nI && c < nx) {
-        const int64_t gi = (int64_t)c * d.nc + lidx[k];
-        v = nscale ? T((double)r[gi] * rs) : r[gi];
-        if (vout && by == 0) vout[gi] = v;
-      }
-      Rs[kk * ldr + cc] = v;
-    }
-    __syncthreads();
+    // this wave's factor fragments of the chunk, then the next chunk's input:
+    // both in flight while the products run.  K-steps past the tank's last
+    // (kc < kKC) multiply staged zero rows: they add exact zeros.
+    T ab[kSteps];
+#pragma unroll
+    for (int p2 = 0; p2 < kSteps; ++p2)
+      ab[p2] = A[(size_t)(s0 + min(s_first + p2 * s_step, kc - 1)) * 64 + lane];
+    if (s0 + kKC < KS) fetch(s0 + kKC);
     if (mt < nMT) {
-      // split: wave w takes the chunk's K-steps w, w + 4, ... (the chunk
-      // length is a multiple of 4, so the assignment is global).  The factor
-      // fragments of kPre K-steps are loaded together, ahead of their MFMAs.
-      constexpr int kPre = 8;
-      for (int s = s_first; s < kc; s += kPre * s_step) {
-        T ab[kPre];
 #pragma unroll
-        for (int p2 = 0; p2 < kPre; ++p2) {
-          const int ss = s + p2 * s_step;
-          ab[p2] = ss < kc ? A[(size_t)(s0 + ss) * 64 + lane] : T(0);
-        }
+      for (int p2 = 0; p2 < kSteps; ++p2) {
+        const T* brow = Rs + (4 * (s_first + p2 * s_step) + grp) * ldr + col;
 #pragma unroll
-        for (int p2 = 0; p2 < kPre; ++p2) {
-          const int ss = s + p2 * s_step;
-          if (ss >= kc) break;
-          const T* brow = Rs + (4 * ss + grp) * ldr + col;
-#pragma unroll
-          for (int u = 0; u < kNTMax; ++u)
-            if (u < ntw) acc[u] = MF::op(ab[p2], brow[16 * u], acc[u]);
-        }
+        for (int u = 0; u < NTW; ++u) acc[u] = MF::op(ab[p2], brow[16 * u], acc[u]);
       }
     }
   }
-  if (sh.split) {
+  if constexpr (SPLIT) {
     // partial tiles added in wave order (the staging area is free again)
-    double* red = reinterpret_cast<double*>(lds_raw);   // [kWaves][ntw][256]
+    double* red = reinterpret_cast<double*>(lds_raw);   // [kWaves][NTW][256]
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kNTMax; ++u) {
-      if (u >= ntw) continue;
+    for (int u = 0; u < NTW; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red[(wv * ntw + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[u][v];
-    }
+      for (int v = 0; v < 4; ++v) red[(wv * NTW + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[u][v];
     __syncthreads();
     const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
     const int row = 16 * mt + rr;
-    for (int u = 0; u < ntw; ++u) {
+    for (int u = 0; u < NTW; ++u) {
       const int c = c0 + 16 * u + cc;
       if (c >= nx) continue;
       double val = 0;
-      for (int w = 0; w < kWaves; ++w) val += red[(w * ntw + u) * 256 + threadIdx.x];
+      for (int w = 0; w < kWaves; ++w) val += red[(w * NTW + u) * 256 + threadIdx.x];
       if (row < nI) sd.yI[(size_t)c * nI + row] = val;
       else if (row < nI + q) sd.TL[(size_t)c * q + row - nI] = val;
       else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
@@ -193,9 +204,9 @@ __device__ __forceinline__ void sd_cond_body(const TankDev& d, int which, const 
   }
   if (mt >= nMT) return;
 #pragma unroll
-  for (int u = 0; u < kNTMax; ++u) {
+  for (int u = 0; u < NTW; ++u) {
     const int c = c0 + 16 * u + col;
-    if (u >= ntw || c >= nx) continue;
+    if (c >= nx) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * mt + MF::row(v, grp);
@@ -205,6 +216,18 @@ __device__ __forceinline__ void sd_cond_body(const TankDev& d, int which, const 
       else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
     }
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void sd_cond_body(const TankDev& d, int which, const T* __restrict__ r,
+                                             const double* __restrict__ nscale, T* __restrict__ vout, int bx,
+                                             int by) {
+  const SDData& sd = d.sd[which];
+  const SdShape sh = sd_shape(d.nx, sd.nMT1);
+  if (sh.split) sd_cond_impl<T, 1, true>(d, sd, r, nscale, vout, bx, by);
+  else if (sh.ntw == 4) sd_cond_impl<T, 4, false>(d, sd, r, nscale, vout, bx, by);
+  else if (sh.ntw == 2) sd_cond_impl<T, 2, false>(d, sd, r, nscale, vout, bx, by);
+  else sd_cond_impl<T, 1, false>(d, sd, r, nscale, vout, bx, by);
 }
 
 template <typename T>
@@ -227,7 +250,7 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
   double* part = sh;                      // [kWaves][16][16][2], later x^ of the block's modes [16][q][2]
   double* gh = sh + sd_part_words(q);     // [16][q][2]
   const int nNT = (q + 15) / 16, KS = (nx + 3) / 4;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
   const int kModesPB = modes_per_block(nx), kPairs = kModesPB / 2;
   const double rs = sd_in_scale(nscale);
   // A row of this lane: the mode of slot `col` (rows past the block's slots are discarded)
@@ -242,28 +265,46 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
 #pragma unroll
     for (int u = 0; u < 4; ++u) are[u] = aim[u] = V4{0, 0, 0, 0};
     int mm = (int)(((int64_t)kr * (4 * wv + grp)) % nx);
-#pragma unroll 4
+    // every load of a K-step is issued before its products, from clamped
+    // addresses (no branch around a load); entries outside the tank are
+    // zeroed afterwards
+    const SEM_GLOBAL T* rg = gview(r);
+    const SEM_GLOBAL double* tlg = gview(sd.TL);
+    const SEM_GLOBAL double* trg = gview(sd.TR);
+    const SEM_GLOBAL double* twg = gview(d.twid);
+    const int jb = 16 * nt0 + col;
+#pragma unroll 1
     for (int s = wv; s < KS; s += kWaves) {
       const int c = 4 * s + grp;
       const bool cv = c < nx;
-      const T fre = (cv && kval) ? T(d.twid[2 * mm]) : T(0);
-      const T fim = (cv && kval) ? T(d.twid[2 * mm + 1]) : T(0);
-      const int cm = c == 0 ? nx - 1 : c - 1;
+      const int cc = min(c, nx - 1);
+      const int cm = cc == 0 ? nx - 1 : cc - 1;
+      const double twr = twg[2 * mm], twi = twg[2 * mm + 1];
+      double rv[4], tl[4], tr[4], rw[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u >= ntn) break;   // (uniform)
+        const int jj = min(jb + 16 * u, q - 1);
+        rv[u] = (double)rg[(int64_t)cc * nc + jj];
+        tl[u] = tlg[(size_t)cc * q + jj];
+        tr[u] = trg[(size_t)cm * q + jj];
+        if (sd.wall) rw[u] = (double)rg[(int64_t)nx * nc + jj];   // (uniform: walled tanks fold their wall line onto line 0)
+      }
+      const T fre = (cv && kval) ? T(twr) : T(0);
+      const T fim = (cv && kval) ? T(twi) : T(0);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (u >= ntn) break;
-        const int j = 16 * (nt0 + u) + col;
-        T gv = T(0);
-        if (cv && j < q) {
-          double rv = (double)r[(int64_t)c * nc + j] * rs;
-          if (vout && bx == 0) vout[(int64_t)c * nc + j] = T(rv);
-          if (sd.wall && c == 0) {   // wall line folded onto line 0
-            const double rw = (double)r[(int64_t)nx * nc + j] * rs;
-            if (vout && bx == 0) vout[(int64_t)nx * nc + j] = T(rw);
-            rv += rw;
-          }
-          gv = T(rv - sd.TL[(size_t)c * q + j] - sd.TR[(size_t)cm * q + j]);
+        const int j = jb + 16 * u;
+        const bool ok = cv && j < q;
+        double v = rv[u] * rs;
+        if (vout && bx == 0 && ok) vout[(int64_t)c * nc + j] = T(v);
+        if (sd.wall && c == 0 && ok) {   // wall line folded onto line 0
+          const double w = rw[u] * rs;
+          if (vout && bx == 0) vout[(int64_t)nx * nc + j] = T(w);
+          v += w;
         }
+        const T gv = ok ? T(v - tl[u] - tr[u]) : T(0);
         are[u] = MF::op(fre, gv, are[u]);
         aim[u] = MF::op(fim, gv, aim[u]);
       }
@@ -334,7 +375,7 @@ __device__ __forceinline__ void sd_idft_body(const TankDev& d, int which, int bx
   __shared__ double red[kWaves][256];
   const int q = sd.q, nx = d.nx;
   const int KS = (2 * nx + 3) / 4;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
   const int c0 = bx * 16, nt = by;
   // A[c][kk] = twiddle part (kk & 1) of mode kk / 2 at line c; B[kk][j] = that part of x^_{kk/2}[j]
   const int cr = (c0 + col) % nx;
@@ -343,21 +384,26 @@ __device__ __forceinline__ void sd_idft_body(const TankDev& d, int which, int bx
   const int step = (int)(((int64_t)2 * kWaves * cr) % nx);   // the mode advances by 8 per pass
   int mm = (int)(((int64_t)cr * (2 * wv + (grp >> 1))) % nx);
   V4 acc = V4{0, 0, 0, 0};
+  // operands loaded from clamped addresses and zeroed outside the range (no
+  // branch around a load, so that the loads of several K-steps are in flight)
+  const SEM_GLOBAL double* twg = gview(d.twid);
+  const SEM_GLOBAL double* xhg = gview(sd.XH);
+  const int jc = min(j, q - 1);
 #pragma unroll 4
   for (int s = wv; s < KS; s += kWaves) {
     const int k = 2 * s + (grp >> 1);
     const bool kv = k < nx;
-    const T a = kv ? T(d.twid[2 * mm + pr]) : T(0);
-    const T b = (kv && j < q) ? T(sd.XH[((size_t)k * q + j) * 2 + pr]) : T(0);
-    acc = MF::op(a, b, acc);
+    const double ta = twg[2 * mm + pr];
+    const double tb = xhg[((size_t)min(k, nx - 1) * q + jc) * 2 + pr];
+    acc = MF::op(kv ? T(ta) : T(0), (kv && j < q) ? T(tb) : T(0), acc);
     mm += step;
     if (mm >= nx) mm -= nx;
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) red[wv][MF::row(v, grp) * 16 + col] = (double)acc[v];
   __syncthreads();
-  const int row = threadIdx.x >> 4, jc = threadIdx.x & 15;
-  const int c = c0 + row, jj = 16 * nt + jc;
+  const int row = threadIdx.x >> 4, jl = threadIdx.x & 15;
+  const int c = c0 + row, jj = 16 * nt + jl;
   if (c >= nx || jj >= q) return;
   double v = 0;
   for (int w = 0; w < kWaves; ++w) v += red[w][threadIdx.x];
@@ -370,6 +416,94 @@ k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
   sd_idft_body<T>(d, which, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+// The product of the back-substitution for M-tile mt and NTW N-tiles of 16
+// columns from c0, the line values of the columns in LDS (xl, row stride
+// q + 1): z_I = Y - C [x_L,c; x_L,c+1].  SPLIT: wave w takes the K-steps
+// w, w + 4, ... and the partial tiles are added in wave order.
+template <typename T, int NTW, bool SPLIT>
+__device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& sd, T* __restrict__ z,
+                                                double* xl, int c0, int mt) {
+  using MF = Mfma<T>;
+  using V4 = typename MF::V4;
+  const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc, KS3 = sd.KS3;
+  const int qp = q + 1;
+  const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
+  const int s_first = SPLIT ? wv : 0;
+  constexpr int s_step = SPLIT ? kWaves : 1;
+  const SEM_GLOBAL T* C = gview(SdMat<T>::C3(sd)) + (size_t)mt * KS3 * 64;
+  V4 acc[NTW];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) acc[u] = V4{0, 0, 0, 0};
+  // factor fragments loaded kPre K-steps at a time, one group ahead of their
+  // MFMAs; rows k >= 2q of the last K-step multiply zeros (exact zeros added)
+  constexpr int kPre = 8;
+  T ab[kPre], an[kPre];
+  auto load = [&](int s, T (&dst)[kPre]) {
+#pragma unroll
+    for (int p2 = 0; p2 < kPre; ++p2) dst[p2] = C[(size_t)min(s + p2 * s_step, KS3 - 1) * 64 + lane];
+  };
+  load(s_first, ab);
+  for (int s = s_first; s < KS3; s += kPre * s_step) {
+    if (s + kPre * s_step < KS3) load(s + kPre * s_step, an);
+#pragma unroll
+    for (int p2 = 0; p2 < kPre; ++p2) {
+      if (s + p2 * s_step >= KS3) break;   // (wave-uniform)
+      const int kk = 4 * (s + p2 * s_step) + grp;
+      // B[kk][col] = x_L of column col (kk < q) or of the next column
+      const bool kv = kk < 2 * q;
+      const int off = kk < q ? kk : qp + kk - q;
+#pragma unroll
+      for (int u = 0; u < NTW; ++u) {
+        const double bx = xl[(16 * u + col) * qp + (kv ? off : 0)];
+        acc[u] = MF::op(ab[p2], kv ? T(bx) : T(0), acc[u]);
+      }
+    }
+#pragma unroll
+    for (int p2 = 0; p2 < kPre; ++p2) ab[p2] = an[p2];
+  }
+  if constexpr (SPLIT) {
+    // partial tiles added in wave order
+    const int ncol = 16 * NTW;
+    double* red = xl + (ncol + 1) * qp;   // [kWaves][NTW][256]
+#pragma unroll
+    for (int u = 0; u < NTW; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(wv * NTW + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[u][v];
+    __syncthreads();
+    const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
+    const int row = 16 * mt + rr;
+    for (int u = 0; u < NTW; ++u) {
+      const int c = c0 + 16 * u + cc;
+      if (c >= nx || row >= nI) continue;
+      double sacc = 0;
+      for (int w = 0; w < kWaves; ++w) sacc += red[(w * NTW + u) * 256 + threadIdx.x];
+      z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - sacc);
+    }
+    return;
+  }
+  // the interior indices and Y of the tile's outputs requested together
+  // (clamped addresses), then the stores
+  int idx[4];
+  double yv[NTW][4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) idx[v] = gview(sd.I_idx)[min(16 * mt + MF::row(v, grp), nI - 1)];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      yv[u][v] = gview(sd.yI)[(size_t)min(c0 + 16 * u + col, nx - 1) * nI + min(16 * mt + MF::row(v, grp), nI - 1)];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) {
+    const int c = c0 + 16 * u + col;
+    if (c >= nx) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * mt + MF::row(v, grp);
+      if (row < nI) z[(int64_t)c * nc + idx[v]] = T(yv[u][v] - (double)acc[u][v]);
+    }
+  }
 }
 
 // back-substitution z_I = Y - A_II^-1 [A_IL | A_IR] [x_L,c; x_L,c+1] as a
@@ -390,10 +524,9 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
   const int ncol = 16 * ntw;
   const int qp = q + 1;                      // odd stride: conflict-free reads across columns
   double* xl = sh;                           // [ncol + 1][qp] line solutions of columns c0 .. c0 + ncol
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
   const int c0 = bx * ncol;
   const int mt = shp.split ? by : 4 * by + wv;
-  const int s_first = shp.split ? wv : 0, s_step = shp.split ? kWaves : 1;
   if (sd_back_dft(nx, q, sd.fft_n1, nMT)) {
     // x_L,c = Re sum_k e^{2 pi i k c / nx} x^_k / nx for lines c0 .. c0 + 16:
     // wave (line tile lt, unknown tile jt), the whole K range (modes x re/im)
@@ -402,7 +535,7 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
     const int cr = (c0 + 16 * lt + col) % nx, pr = grp & 1, jb = 16 * jt + col;
     const int KSd = (2 * nx + 3) / 4;
     V4 acc = V4{0, 0, 0, 0};
-    constexpr int kD = 16;
+    constexpr int kD = 8;
     // twiddle index (cr k) mod nx, k = 2 s + grp / 2: advances by 2 cr per K-step
     const int step = (2 * cr) % nx;
     int mm = (cr * (grp >> 1)) % nx;
@@ -410,10 +543,13 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
       T av[kD], bv[kD];
 #pragma unroll
       for (int u = 0; u < kD; ++u) {
+        // (loaded from clamped addresses, zeroed outside the range)
         const int k = 2 * (s0 + u) + (grp >> 1);
         const bool kv = s0 + u < KSd && k < nx;
-        av[u] = kv ? T(d.twid[2 * mm + pr]) : T(0);
-        bv[u] = (kv && jb < q) ? T(sd.XH[((size_t)k * q + jb) * 2 + pr]) : T(0);
+        const double ta = gview(d.twid)[2 * mm + pr];
+        const double tb = gview(sd.XH)[((size_t)min(k, nx - 1) * q + min(jb, q - 1)) * 2 + pr];
+        av[u] = kv ? T(ta) : T(0);
+        bv[u] = (kv && jb < q) ? T(tb) : T(0);
         mm += step;
         if (mm >= nx) mm -= nx;
       }
@@ -458,64 +594,10 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
     }
   }
   if (mt >= nMT) return;   // (uniform over the workgroup in split mode)
-  const T* C = SdMat<T>::C3(sd) + (size_t)mt * KS3 * 64;
-  V4 acc[kNTMax];
-#pragma unroll
-  for (int u = 0; u < kNTMax; ++u) acc[u] = V4{0, 0, 0, 0};
-  constexpr int kPre = 8;   // factor fragments loaded together, ahead of their MFMAs
-  for (int s = s_first; s < KS3; s += kPre * s_step) {
-    T ab[kPre];
-#pragma unroll
-    for (int p2 = 0; p2 < kPre; ++p2) {
-      const int ss = s + p2 * s_step;
-      ab[p2] = ss < KS3 ? C[(size_t)ss * 64 + lane] : T(0);
-    }
-#pragma unroll
-    for (int p2 = 0; p2 < kPre; ++p2) {
-      const int ss = s + p2 * s_step;
-      if (ss >= KS3) break;
-      const int kk = 4 * ss + grp;
-      // B[kk][col] = x_L of column col (kk < q) or of the next column
-      const int off = kk < q ? kk : (kk < 2 * q ? qp + kk - q : -1);
-#pragma unroll
-      for (int u = 0; u < kNTMax; ++u) {
-        if (u >= ntw) continue;
-        const T b = off >= 0 ? T(xl[(16 * u + col) * qp + off]) : T(0);
-        acc[u] = MF::op(ab[p2], b, acc[u]);
-      }
-    }
-  }
-  if (shp.split) {
-    // partial tiles added in wave order
-    double* red = xl + (ncol + 1) * qp;   // [kWaves][ntw][256]
-#pragma unroll
-    for (int u = 0; u < kNTMax; ++u) {
-      if (u >= ntw) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) red[(wv * ntw + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[u][v];
-    }
-    __syncthreads();
-    const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
-    const int row = 16 * mt + rr;
-    for (int u = 0; u < ntw; ++u) {
-      const int c = c0 + 16 * u + cc;
-      if (c >= nx || row >= nI) continue;
-      double sacc = 0;
-      for (int w = 0; w < kWaves; ++w) sacc += red[(w * ntw + u) * 256 + threadIdx.x];
-      z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - sacc);
-    }
-    return;
-  }
-#pragma unroll
-  for (int u = 0; u < kNTMax; ++u) {
-    const int c = c0 + 16 * u + col;
-    if (u >= ntw || c >= nx) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 16 * mt + MF::row(v, grp);
-      if (row < nI) z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - (double)acc[u][v]);
-    }
-  }
+  if (shp.split) sd_back_product<T, 1, true>(d, sd, z, xl, c0, mt);
+  else if (ntw == 4) sd_back_product<T, 4, false>(d, sd, z, xl, c0, mt);
+  else if (ntw == 2) sd_back_product<T, 2, false>(d, sd, z, xl, c0, mt);
+  else sd_back_product<T, 1, false>(d, sd, z, xl, c0, mt);
 }
 
 template <typename T>

@@ -27,4 +27,26 @@ struct Mfma<float> {
   __device__ static V4 op(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
 
+// Global-address-space views: pointers read from argument blocks or device
+// descriptors are otherwise accessed through flat instructions, whose
+// completion the compiler can only wait for together with LDS traffic.
+#define SEM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ inline const SEM_GLOBAL T* gview(const T* p) {
+  return (const SEM_GLOBAL T*)p;
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads still in
+// flight (prefetches) and global stores are not waited for, as they are at
+// __syncthreads().  For kernels whose waves exchange data through LDS alone.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Index of the calling wavefront in its workgroup, as a wave-uniform
+// (scalar) value, so that branches on it are not taken per lane.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 }  // namespace sem

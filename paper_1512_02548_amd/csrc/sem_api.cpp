@@ -260,6 +260,8 @@ static sem_status build_mesh(sem_mesh* M) {
       const size_t region = (size_t)cb * nc + nl;
       const size_t ref = (region + 3 * EB * NpP) * sizeof(double);
       const size_t ops = 4 * (size_t)NpP * NpP * sizeof(double);
+      // (the seventh- and eighth-order FP64 operators, 72 KiB, sit in LDS
+      // beside a block of at most 64 KiB; smaller operators count towards it)
       const size_t mfma = (ops <= 40 * 1024 ? ops : 0) + (size_t)per_col * NpP * 4 + 32 + region * sizeof(double) +
                           T * 16 * (NpP + 1) * sizeof(double);
       return ref <= 65536 && mfma <= 65536;

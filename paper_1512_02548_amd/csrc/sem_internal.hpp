@@ -287,9 +287,12 @@ __host__ __device__ inline double* krylov_norm(const TankDev& d, int j) {
   return d.H + (size_t)(m + 1) * m + 2 * m + (m + 1) + (j - 1);
 }
 
-// Chunking of the fused reductions: at most 256 workgroups of >= 512 entries.
+// Chunking of the fused reductions: at most 256 workgroups of >= 512 entries
+// (1024 workgroups measured slower on the 2048-column tank: the last
+// workgroup's pass over the partials grows with their count).
+constexpr int64_t kDotMaxChunks = 256;
 __host__ __device__ inline int64_t dot_chunk(int64_t n) {
-  const int64_t c = (n + 255) / 256;
+  const int64_t c = (n + kDotMaxChunks - 1) / kDotMaxChunks;
   return c < 512 ? 512 : c;
 }
 __host__ __device__ inline int dot_nchunk(int64_t n) {

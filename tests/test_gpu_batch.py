@@ -110,6 +110,32 @@ def test_lockstep_laplace_equals_single(prec, rtol):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_lockstep_several_blocks_per_workgroup(prec, monkeypatch):
+    """Batched stiffness launches that run several blocks per workgroup
+    (forced through SEM_STIFF_BLOCKS when the batch is built; large batches
+    choose them by themselves) give the single-tank solves bit for bit."""
+    import torch
+    from paper_1512_02548_amd import lib
+    monkeypatch.delenv("SEM_STIFF_BLOCKS", raising=False)
+    tanks = [make_tank(s) for s in mixed_specs()] + [walled_tank()]
+    opts = lib.default_opts(rtol=1e-10, max_iter=4000, prec=prec, inner_rtol=1e-3, max_refine=60)
+    exs = [surface_gradient(t) for t in tanks]
+    single = []
+    for t, ex in zip(tanks, exs):
+        phi = torch.zeros(t["mesh"].n, dtype=torch.float64, device="cuda")
+        t["mesh"].laplace_solve(t["eta"], ex, t["phi"], phi, opts)
+        single.append(phi.cpu().numpy())
+    monkeypatch.setenv("SEM_STIFF_BLOCKS", "3")
+    b = lib.Batch([t["mesh"] for t in tanks], 0)
+    outs = [torch.full((t["mesh"].n,), np.nan, dtype=torch.float64, device="cuda") for t in tanks]
+    code, status, _ = b.laplace_solve([t["eta"] for t in tanks], exs, [t["phi"] for t in tanks], outs, opts=opts)
+    torch.cuda.synchronize()
+    assert code == 0, status
+    for o, s in zip(outs, single):
+        assert np.array_equal(o.cpu().numpy(), s)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_lockstep_rk4_equals_single(prec):
     import torch
     from paper_1512_02548_amd import lib

@@ -43,3 +43,46 @@ def test_mfma_stiffness_matches_reference_and_oracle(case):
     ref.apply(lib.SEM_OP_STIFFNESS, u, y2)
     assert rel_err(host(y1), host(y2)) < 1e-13
     assert rel_err(pm.to_oracle(host(y1)), of["A"] @ u_or) < 1e-13
+
+
+@pytest.mark.parametrize("case", [(40, 2, 4, 2 * np.pi, True), (37, 4, 6, 3.0, False), (26, 8, 6, 2 * np.pi, True),
+                                  (19, 2, 8, 2.0, False), (33, 1, 7, 2 * np.pi, True), (21, 3, 5, 2.5, False)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_several_blocks_per_workgroup_bitwise(case, prec, monkeypatch):
+    """The stiffness kernel that runs several blocks per workgroup (chosen for
+    launches of thousands of blocks) gives the one-block kernel's result bit
+    for bit: forced through SEM_STIFF_BLOCKS on small tanks whose last
+    workgroup gets a ragged share of blocks."""
+    import torch
+    from paper_1512_02548_amd import lib
+    nx, nz, P, L, periodic = case
+    from oracle.mesh import Mesh as OMesh
+    xs = OMesh(nx, 1, P, L, periodic).xs_surf
+    k = 2 * np.pi / L
+    h = 1.0 - 0.2 * np.cos(k * xs) ** 2
+    hx = 0.4 * k * np.cos(k * xs) * np.sin(k * xs)
+    m = lib.Mesh(nx, nz, P, L, periodic, h, hx, tiles_per_block=4 if nz > 1 else 2)
+    eta = 0.1 * np.cos(k * xs) + 0.03 * np.sin(2 * k * xs)
+    ex = 0.1 * k * (-np.sin(k * xs)) + 0.06 * k * np.cos(2 * k * xs)
+    m.set_surface(cuda(eta), cuda(ex))
+    dt = torch.float64 if prec == 0 else torch.float32
+    u = torch.tensor(np.random.default_rng(11).standard_normal(m.n), dtype=dt, device="cuda")
+    outs = {}
+    for kb in (None, 2, 3):
+        if kb is None:
+            monkeypatch.delenv("SEM_STIFF_BLOCKS", raising=False)
+        else:
+            monkeypatch.setenv("SEM_STIFF_BLOCKS", str(kb))
+        y = torch.full_like(u, np.nan)
+        m.apply_timed(lib.SEM_OP_STIFFNESS, u, y, 1, prec)
+        if prec == 0:
+            y2 = torch.full_like(u, np.nan)
+            m.apply(lib.SEM_OP_STIFFNESS, u, y2)
+            outs[kb] = (host(y), host(y2))
+        else:
+            outs[kb] = (y.cpu().numpy(),)
+    for kb in (2, 3):
+        for a, b in zip(outs[None], outs[kb]):
+            # (the single apply leaves a walled tank's wall line to the fix-up: NaN in both)
+            assert np.array_equal(a, b, equal_nan=True), kb
+            assert np.isfinite(a[: m.n - (0 if periodic else nz * P + 1)]).all()
