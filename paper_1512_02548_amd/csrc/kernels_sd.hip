@@ -41,6 +41,12 @@ __device__ inline double sd_in_scale(const double* nscale) {
   return hn > 0.0 ? 1.0 / hn : 0.0;
 }
 
+// (a + b) mod n for a, b in [0, n), as a select rather than a branch
+__device__ inline int wrap_add(int a, int b, int n) {
+  const int s = a + b;
+  return s >= n ? s - n : s;
+}
+
 __device__ inline double wsum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -308,8 +314,7 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
         are[u] = MF::op(fre, gv, are[u]);
         aim[u] = MF::op(fim, gv, aim[u]);
       }
-      mm += step;
-      if (mm >= nx) mm -= nx;
+      mm = wrap_add(mm, step, nx);
     }
     for (int u = 0; u < ntn; ++u) {
 #pragma unroll
@@ -340,7 +345,7 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
     const int kk = t / q, i = t - kk * q, k = paired_mode(bx, kk, kPairs, nx);
     if (k < 0) continue;
     const bool cj = 2 * k > nx;   // stored as the conjugate of mode nx - k
-    const T* S = SdMat<T>::Shat(sd) + (size_t)(cj ? nx - k : k) * q * q * 2;
+    const SEM_GLOBAL T* S = gview(SdMat<T>::Shat(sd)) + (size_t)(cj ? nx - k : k) * q * q * 2;
     const double sgn = cj ? -1.0 : 1.0;
     double xr = 0, xi = 0;
 #pragma unroll 8
@@ -389,15 +394,20 @@ __device__ __forceinline__ void sd_idft_body(const TankDev& d, int which, int bx
   const SEM_GLOBAL double* twg = gview(d.twid);
   const SEM_GLOBAL double* xhg = gview(sd.XH);
   const int jc = min(j, q - 1);
-#pragma unroll 4
-  for (int s = wv; s < KS; s += kWaves) {
-    const int k = 2 * s + (grp >> 1);
-    const bool kv = k < nx;
-    const double ta = twg[2 * mm + pr];
-    const double tb = xhg[((size_t)min(k, nx - 1) * q + jc) * 2 + pr];
-    acc = MF::op(kv ? T(ta) : T(0), (kv && j < q) ? T(tb) : T(0), acc);
-    mm += step;
-    if (mm >= nx) mm -= nx;
+  for (int s0 = wv; s0 < KS; s0 += 4 * kWaves) {
+    double ta[4], tb[4];
+    bool kv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int s = s0 + u * kWaves;
+      const int k = 2 * s + (grp >> 1);
+      kv[u] = s < KS && k < nx;
+      ta[u] = twg[2 * mm + pr];
+      tb[u] = xhg[((size_t)min(k, nx - 1) * q + jc) * 2 + pr];
+      mm = wrap_add(mm, step, nx);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = MF::op(kv[u] ? T(ta[u]) : T(0), (kv[u] && j < q) ? T(tb[u]) : T(0), acc);
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) red[wv][MF::row(v, grp) * 16 + col] = (double)acc[v];
@@ -550,8 +560,7 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
         const double tb = gview(sd.XH)[((size_t)min(k, nx - 1) * q + min(jb, q - 1)) * 2 + pr];
         av[u] = kv ? T(ta) : T(0);
         bv[u] = (kv && jb < q) ? T(tb) : T(0);
-        mm += step;
-        if (mm >= nx) mm -= nx;
+        mm = wrap_add(mm, step, nx);
       }
 #pragma unroll
       for (int u = 0; u < kD; ++u) acc = MF::op(av[u], bv[u], acc);
@@ -751,19 +760,19 @@ __device__ __forceinline__ void sdf_a_body(const TankDev& d, int which, const T*
     gl[t] = v;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
+  const SEM_GLOBAL double* twg = gview(d.twid);
   for (int mt = wv; mt < nMT; mt += kWaves) {
     const int k1 = 16 * mt + col, j = 16 * nt + col;
     V4 ar = V4{0, 0, 0, 0}, ai = V4{0, 0, 0, 0};
 #pragma unroll 4
     for (int s = 0; s < KS; ++s) {
       const int c1 = 4 * s + grp;
-      T wr = T(0), wi = T(0);
-      if (k1 < n1 && c1 < n1) {
-        const int m = sd_mod((int64_t)k1 * c1, n1) * n2;
-        wr = T(d.twid[2 * m]);
-        wi = T(d.twid[2 * m + 1]);
-      }
+      // (twiddle loaded from a clamped index, then selected: no branch around the load)
+      const bool okw = k1 < n1 && c1 < n1;
+      const int m = okw ? sd_mod((int64_t)k1 * c1, n1) * n2 : 0;
+      const double twr = twg[2 * m], twi = twg[2 * m + 1];
+      const T wr = okw ? T(twr) : T(0), wi = okw ? T(twi) : T(0);
       const T b = T(gl[c1 * 16 + col]);
       ar = MF::op(wr, b, ar);
       ai = MF::op(wi, b, ai);
@@ -800,8 +809,9 @@ __device__ __forceinline__ void sdf_b_body(const TankDev& d, int which, int bx, 
   const int q = sd.q, n1 = sd.fft_n1, n2 = sd.fft_n2;
   const int k1 = bx;
   const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const double* ft = sd.FT + (size_t)k1 * n2 * q * 2;
+  const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
+  const SEM_GLOBAL double* ftg = gview(sd.FT) + (size_t)k1 * n2 * q * 2;
+  const SEM_GLOBAL double* twg = gview(d.twid);
   const int nt = by;   // this workgroup's 16 line unknowns
   for (int mt = wv; mt < nMT; mt += kWaves) {
     const int k2 = 16 * mt + col, j = 16 * nt + col;
@@ -809,17 +819,14 @@ __device__ __forceinline__ void sdf_b_body(const TankDev& d, int which, int bx, 
 #pragma unroll 4
     for (int s = 0; s < KS; ++s) {
       const int c2 = 4 * s + grp;
-      T wr = T(0), wi = T(0);
-      if (k2 < n2 && c2 < n2) {
-        const int m = sd_mod((int64_t)k2 * c2, n2) * n1;
-        wr = T(d.twid[2 * m]);
-        wi = T(d.twid[2 * m + 1]);
-      }
-      T br = T(0), bi = T(0);
-      if (c2 < n2 && j < q) {
-        br = T(ft[((size_t)c2 * q + j) * 2]);
-        bi = T(ft[((size_t)c2 * q + j) * 2 + 1]);
-      }
+      // (operands loaded from clamped indices, then selected)
+      const bool okw = k2 < n2 && c2 < n2, okb = c2 < n2 && j < q;
+      const int m = okw ? sd_mod((int64_t)k2 * c2, n2) * n1 : 0;
+      const double twr = twg[2 * m], twi = twg[2 * m + 1];
+      const size_t ob = ((size_t)min(c2, n2 - 1) * q + min(j, q - 1)) * 2;
+      const double fr = ftg[ob], fi = ftg[ob + 1];
+      const T wr = okw ? T(twr) : T(0), wi = okw ? T(twi) : T(0);
+      const T br = okb ? T(fr) : T(0), bi = okb ? T(fi) : T(0);
       gr = MF::op(wr, br, gr);
       gr = MF::op(-wi, bi, gr);
       gi = MF::op(wr, bi, gi);
@@ -857,9 +864,9 @@ __device__ __forceinline__ void sdf_solve_body(const TankDev& d, int which, int 
     double xr = 0, xi = 0;
     if (k >= 0) {
       const bool cj = 2 * k > nx;   // stored as the conjugate of mode nx - k
-      const T* S = SdMat<T>::Shat(sd) + (size_t)(cj ? nx - k : k) * q * q * 2;
+      const SEM_GLOBAL T* S = gview(SdMat<T>::Shat(sd)) + (size_t)(cj ? nx - k : k) * q * q * 2;
       const double sgn = cj ? -1.0 : 1.0;
-      const double* g = sd.FG + (size_t)k * q * 2;
+      const SEM_GLOBAL double* g = gview(sd.FG) + (size_t)k * q * 2;
 #pragma unroll 8
       for (int j = 0; j < q; ++j) {
         const double sr = (double)S[((size_t)j * q + i) * 2], si = sgn * (double)S[((size_t)j * q + i) * 2 + 1];
@@ -890,7 +897,9 @@ __device__ __forceinline__ void sdf_c_body(const TankDev& d, int which, int bx, 
   const int q = sd.q, nx = d.nx, n1 = sd.fft_n1, n2 = sd.fft_n2;
   const int k1 = bx;
   const int KS = (n2 + 3) / 4, nMT = (n2 + 15) / 16;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
+  const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
+  const SEM_GLOBAL double* twg = gview(d.twid);
+  const SEM_GLOBAL double* xhg = gview(sd.XH);
   const int nt = by;   // this workgroup's 16 line unknowns
   for (int mt = wv; mt < nMT; mt += kWaves) {
     const int c2 = 16 * mt + col, j = 16 * nt + col;
@@ -898,18 +907,14 @@ __device__ __forceinline__ void sdf_c_body(const TankDev& d, int which, int bx, 
 #pragma unroll 4
     for (int s = 0; s < KS; ++s) {
       const int k2 = 4 * s + grp;
-      T wr = T(0), wi = T(0);   // conj(w_n2)^{k2 c2} = (twr, -twi)
-      if (c2 < n2 && k2 < n2) {
-        const int m = sd_mod((int64_t)k2 * c2, n2) * n1;
-        wr = T(d.twid[2 * m]);
-        wi = T(-d.twid[2 * m + 1]);
-      }
-      T br = T(0), bi = T(0);
-      if (k2 < n2 && j < q) {
-        const size_t o = (((size_t)k1 + (size_t)n1 * k2) * q + j) * 2;
-        br = T(sd.XH[o]);
-        bi = T(sd.XH[o + 1]);
-      }
+      // conj(w_n2)^{k2 c2} = (twr, -twi); operands loaded from clamped indices, then selected
+      const bool okw = c2 < n2 && k2 < n2, okb = k2 < n2 && j < q;
+      const int m = okw ? sd_mod((int64_t)k2 * c2, n2) * n1 : 0;
+      const double twr = twg[2 * m], twi = twg[2 * m + 1];
+      const size_t o = (((size_t)k1 + (size_t)n1 * min(k2, n2 - 1)) * q + min(j, q - 1)) * 2;
+      const double xr = xhg[o], xi = xhg[o + 1];
+      const T wr = okw ? T(twr) : T(0), wi = okw ? T(-twi) : T(0);
+      const T br = okb ? T(xr) : T(0), bi = okb ? T(xi) : T(0);
       ur = MF::op(wr, br, ur);
       ur = MF::op(-wi, bi, ur);
       ui = MF::op(wr, bi, ui);
@@ -946,8 +951,9 @@ __device__ __forceinline__ void sdf_d_body(const TankDev& d, int which, int bx, 
   const int q = sd.q, nx = d.nx, n1 = sd.fft_n1, n2 = sd.fft_n2;
   const int c2 = bx;
   const int KS = (n1 + 3) / 4, nMT = (n1 + 15) / 16;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  const double* ft = sd.FT + (size_t)c2 * n1 * q * 2;
+  const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
+  const SEM_GLOBAL double* ftg = gview(sd.FT) + (size_t)c2 * n1 * q * 2;
+  const SEM_GLOBAL double* twg = gview(d.twid);
   const double inx = 1.0 / nx;
   const int nt = by;   // this workgroup's 16 line unknowns
   for (int mt = wv; mt < nMT; mt += kWaves) {
@@ -956,17 +962,14 @@ __device__ __forceinline__ void sdf_d_body(const TankDev& d, int which, int bx, 
 #pragma unroll 4
     for (int s = 0; s < KS; ++s) {
       const int k1 = 4 * s + grp;
-      T wr = T(0), wi = T(0);   // Re(conj(w) u) = twr ur + twi ui
-      if (c1 < n1 && k1 < n1) {
-        const int m = sd_mod((int64_t)k1 * c1, n1) * n2;
-        wr = T(d.twid[2 * m]);
-        wi = T(d.twid[2 * m + 1]);
-      }
-      T br = T(0), bi = T(0);
-      if (k1 < n1 && j < q) {
-        br = T(ft[((size_t)k1 * q + j) * 2]);
-        bi = T(ft[((size_t)k1 * q + j) * 2 + 1]);
-      }
+      // Re(conj(w) u) = twr ur + twi ui; operands loaded from clamped indices, then selected
+      const bool okw = c1 < n1 && k1 < n1, okb = k1 < n1 && j < q;
+      const int m = okw ? sd_mod((int64_t)k1 * c1, n1) * n2 : 0;
+      const double twr = twg[2 * m], twi = twg[2 * m + 1];
+      const size_t ob = ((size_t)min(k1, n1 - 1) * q + min(j, q - 1)) * 2;
+      const double fr = ftg[ob], fi = ftg[ob + 1];
+      const T wr = okw ? T(twr) : T(0), wi = okw ? T(twi) : T(0);
+      const T br = okb ? T(fr) : T(0), bi = okb ? T(fi) : T(0);
       acc = MF::op(wr, br, acc);
       acc = MF::op(wi, bi, acc);
     }
