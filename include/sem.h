@@ -77,7 +77,7 @@ typedef enum {
 } sem_operator;
 
 typedef struct {
-  int32_t nx, nz;              /* quads in x, layers in sigma (both >= 1)           */
+  int32_t nx, nz;              /* quads in x (>= 1), layers in sigma (1..256)       */
   int32_t order;               /* polynomial order P, 1..8                          */
   int32_t periodic;            /* 1: periodic in x; 0: impermeable walls            */
   double length;               /* L > 0                                             */

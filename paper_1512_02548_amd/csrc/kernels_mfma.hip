@@ -53,9 +53,8 @@ struct StiffArgs {
   const void* G;                  // factor copy in tile layout (T, or bfloat16 bits)
   const T* opf;                   // operators in MFMA fragment order: stage 1 then stage 2
   const int32_t* elem_loc;        // [2nz][NpP]
-  const int32_t* acc_cnt;         // [nc]
-  const int32_t* acc_ent;         // [nc][kMaxContrib]
-  const int32_t* is_surf_loc;     // [nc + nl]
+  const uint16_t* acc_pk;         // [nc][kMaxContrib] packed node-sum entries
+  const uint16_t* acc_cm;         // [nc] count | surface << 4
   const KrylovState* ks;          // cycle state (launches gated on done)
   const double* lay;              // [2nz][8] element constants (S_z: sigma derivatives and J)
   const double* invd;             // 1/d at the element nodes, tile layout (S_z)
@@ -69,9 +68,8 @@ __host__ __device__ inline StiffArgs<T> stiff_args(const TankDev& h, const void*
   a.G = G;
   a.opf = opf;
   a.elem_loc = h.elem_loc;
-  a.acc_cnt = h.acc_cnt;
-  a.acc_ent = h.acc_ent;
-  a.is_surf_loc = h.is_surf_loc;
+  a.acc_pk = h.acc_pk;
+  a.acc_cm = h.acc_cm;
   a.ks = h.ks;
   a.lay = h.lay;
   a.invd = h.invd;
@@ -115,12 +113,10 @@ __host__ __device__ inline size_t stiff_lds_layout(const TankDev& h, int ops_in_
 // values (blocks of at most four 16-element tiles, a layer or more).
 __host__ __device__ constexpr int stiff_u_regs(int P) { return (32 * P * (P + 1) + 64 + kBlockThreads - 1) / kBlockThreads; }
 
-// Whether a tank's blocks fit that kernel: at most one tile per wavefront,
-// its input region in stiff_u_regs registers per thread, and its node-sum
-// entries (element-in-column x NpP + node) in 15 bits.
+// Whether a tank's blocks fit that kernel: at most one tile per wavefront
+// and its input region in stiff_u_regs registers per thread.
 __host__ __device__ inline bool stiff_mb_fits(const TankDev& h) {
-  return h.T <= kBlockThreads / 64 && (int64_t)h.cb * h.nc + h.nl <= (int64_t)stiff_u_regs(h.P) * kBlockThreads &&
-         2 * h.nz * h.NpP < 32768;
+  return h.T <= kBlockThreads / 64 && (int64_t)h.cb * h.nc + h.nl <= (int64_t)stiff_u_regs(h.P) * kBlockThreads;
 }
 
 // The input region of the block of columns c0 .. c0 + cbb - 1 into LDS: its
@@ -148,68 +144,82 @@ __device__ __forceinline__ void stage_region(const StiffArgs<T>& a, const T* __r
 }
 
 // Node sums of block b (columns c0 .. c0 + cbb - 1) in a fixed order, the
-// same contribution table as the reference kernel; the right line's sum over
-// the block's last column goes to the side buffer.  The tables of kNG nodes
-// per thread are requested together (no branch around the loads).
+// same contributions in the same order as the reference kernel's table; the
+// right line's sum over the block's last column goes to the side buffer.
+// tab(ql, e, cm) yields column-local node ql's packed entries (eight 16-bit
+// offsets into the element outputs, in four words) and its count word; each
+// thread walks its nodes q = tid, tid + kBlockThreads, ... with the column
+// and column-local index advanced incrementally (no division per node).
+static_assert(kMaxContrib == 8, "a node's packed entries are one 16-byte word");
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <int NpP, typename T, typename Tab>
+__device__ __forceinline__ void node_sums_packed(const T* st3, T* __restrict__ y, T* __restrict__ side, int flags,
+                                                 int nc, int nl, int nz2, int b, int c0, int cbb, Tab tab) {
+  constexpr int NS = NpP + 1;
+  const int colstride = nz2 * NS;
+  const int nq = cbb * nc + nl;
+  const T sgn = (flags & F_NEG) ? T(-1) : T(1);
+  const bool mask_surf = flags & F_MASK_SURF;
+  const int dq = kBlockThreads / nc, dr = kBlockThreads - dq * nc;
+  int lq = threadIdx.x / nc, ql = threadIdx.x - lq * nc;
+  for (int q = threadIdx.x; q < nq; q += kBlockThreads) {
+    uint32_t e[kMaxContrib / 2];
+    int cm;
+    tab(ql, e, cm);
+    const int cnt = cm & 15;
+    const bool masked = mask_surf && ((cm >> 4) & 1);
+    T acc = 0;
+    if (lq < cbb) {
+      const T* own = st3 + lq * colstride;
+#pragma unroll
+      for (int k = 0; k < kMaxContrib; ++k) {
+        if (k >= cnt) break;
+        const int en = (e[k >> 1] >> (16 * (k & 1))) & 0xffff;
+        if (en >> 15) {
+          if (lq == 0) continue;  // previous column belongs to the left block
+          acc += own[(en & 0x7fff) - colstride];
+        } else {
+          acc += own[en];
+        }
+      }
+      y[(int64_t)(c0 + lq) * nc + ql] = masked ? T(0) : acc * sgn;
+    } else {
+      // right line: contributions of the block's last column
+      const T* last = st3 + (cbb - 1) * colstride;
+#pragma unroll
+      for (int k = 0; k < kMaxContrib; ++k) {
+        if (k >= cnt) break;
+        const int en = (e[k >> 1] >> (16 * (k & 1))) & 0xffff;
+        if ((en >> 15) == 0) continue;
+        acc += last[en & 0x7fff];
+      }
+      side[(size_t)b * nl + ql] = masked ? T(0) : acc * sgn;
+    }
+    ql += dr;
+    lq += dq;
+    if (ql >= nc) {
+      ql -= nc;
+      ++lq;
+    }
+  }
+}
+
+// node sums of a one-block workgroup, the table read from global memory
+// (one node's entries as a 16-byte load)
 template <int NpP, typename T>
 __device__ __forceinline__ void node_sums(const StiffArgs<T>& a, const T* st3, T* __restrict__ y,
                                           T* __restrict__ side, int flags, int b, int c0, int cbb) {
-  constexpr int NS = NpP + 1;
-  const int nc = a.nc, nl = a.nl, nz2 = 2 * a.nz;
-  const int nown = cbb * nc, nq = nown + nl;
-  const T sgn = (flags & F_NEG) ? T(-1) : T(1);
-  const bool mask_surf = flags & F_MASK_SURF;
-  const SEM_GLOBAL int32_t* cntg = gview(a.acc_cnt);
-  const SEM_GLOBAL int32_t* entg = gview(a.acc_ent);
-  const SEM_GLOBAL int32_t* surfg = gview(a.is_surf_loc);
-  constexpr int kNG = 2;
-  for (int q0 = threadIdx.x; q0 < nq; q0 += kNG * kBlockThreads) {
-    int cnt[kNG], msk[kNG], ent[kNG][kMaxContrib];
-#pragma unroll
-    for (int j = 0; j < kNG; ++j) {
-      const int q = min(q0 + j * kBlockThreads, nq - 1);
-      const int ql = q - (q / nc) * nc;
-      cnt[j] = cntg[ql];
-#pragma unroll
-      for (int k = 0; k < kMaxContrib; ++k) ent[j][k] = entg[(size_t)ql * kMaxContrib + k];
-      msk[j] = surfg[ql];
-    }
-#pragma unroll
-    for (int j = 0; j < kNG; ++j) {
-      const int q = q0 + j * kBlockThreads;
-      if (q >= nq) break;
-      const int lc = q / nc, ql = q - lc * nc;
-      const bool masked = mask_surf && msk[j];
-      T acc = 0;
-      if (lc < cbb) {
-#pragma unroll
-        for (int k = 0; k < kMaxContrib; ++k) {
-          if (k >= cnt[j]) break;
-          const int e = ent[j][k];
-          const int off = e & 0x3fffffff;             // element-in-column * NpP + node
-          const int pos = (off / NpP) * NS + off % NpP;
-          if ((e >> 30) & 1) {
-            if (lc == 0) continue;  // previous column belongs to the left block
-            acc += st3[(lc - 1) * nz2 * NS + pos];
-          } else {
-            acc += st3[lc * nz2 * NS + pos];
-          }
-        }
-        y[(int64_t)(c0 + lc) * nc + ql] = masked ? T(0) : acc * sgn;
-      } else {
-        // right line: contributions of the block's last column
-#pragma unroll
-        for (int k = 0; k < kMaxContrib; ++k) {
-          if (k >= cnt[j]) break;
-          const int e = ent[j][k];
-          if (((e >> 30) & 1) == 0) continue;
-          const int off = e & 0x3fffffff;
-          acc += st3[(cbb - 1) * nz2 * NS + (off / NpP) * NS + off % NpP];
-        }
-        side[(size_t)b * nl + ql] = masked ? T(0) : acc * sgn;
-      }
-    }
-  }
+  const SEM_GLOBAL u32x4* pk = (const SEM_GLOBAL u32x4*)gview(a.acc_pk);
+  const SEM_GLOBAL uint16_t* cmg = gview(a.acc_cm);
+  node_sums_packed<NpP, T>(st3, y, side, flags, a.nc, a.nl, 2 * a.nz, b, c0, cbb,
+                           [&](int ql, uint32_t(&e)[kMaxContrib / 2], int& cm) {
+                             const u32x4 v = pk[ql];
+                             e[0] = v.x;
+                             e[1] = v.y;
+                             e[2] = v.z;
+                             e[3] = v.w;
+                             cm = cmg[ql];
+                           });
 }
 
 // Workgroup b of the tank's grid (columns b cb .. b cb + cb - 1).
@@ -368,7 +378,7 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
 // Workgroup blocks b0 .. b0 + nblk - 1 of the tank's grid, one after the
 // other, for blocks of at most one tile per wavefront (the stiffness grids
 // never exceed four tiles per block).  The operators, the element table and
-// the node-sum table (packed to 16-bit entries) go to LDS once; each block
+// the packed node-sum table go to LDS once; each block
 // then runs its tiles and sums its nodes exactly as stiff_body's workgroup of
 // its own would (the same values, bit for bit).  Every global load of a block
 // is issued one block ahead, unconditionally, from clamped addresses: its
@@ -392,8 +402,8 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
   int32_t* lloc = reinterpret_cast<int32_t*>(lds_raw + o_loc);   // [2nz][NpP]
   T* ureg = reinterpret_cast<T*>(lds_raw + o_u);                 // [cb nc + nl]
   T* st3 = reinterpret_cast<T*>(lds_raw + o_st);                 // [T 16][NpP + 1]
-  uint16_t* tent = reinterpret_cast<uint16_t*>(lds_raw + o_tab); // [nc][kMaxContrib]
-  uint16_t* tcm = tent + (size_t)a.nc * kMaxContrib;             // [nc]: count | masked << 4
+  u32x4* tent4 = reinterpret_cast<u32x4*>(lds_raw + o_tab);      // [nc]: kMaxContrib packed entries
+  uint16_t* tcm = reinterpret_cast<uint16_t*>(tent4 + a.nc);      // [nc]: count | surface << 4
   const int nc = a.nc, nl = a.nl, nz2 = 2 * a.nz;
   const int nbt = (a.nx + a.cb - 1) / a.cb;
   const int b1 = min(b0 + nblk, nbt);
@@ -413,19 +423,9 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
     for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
   }
   for (int i = threadIdx.x; i < nz2 * NpP; i += kBlockThreads) lloc[i] = gview(a.elem_loc)[i];
-  {
-    const bool mask_surf = flags & F_MASK_SURF;
-    for (int ql = threadIdx.x; ql < nc; ql += kBlockThreads) {
-      const int cnt = gview(a.acc_cnt)[ql];
-      const int msk = mask_surf && gview(a.is_surf_loc)[ql];
-#pragma unroll
-      for (int k = 0; k < kMaxContrib; ++k) {
-        const int e = gview(a.acc_ent)[(size_t)ql * kMaxContrib + k];
-        // element-in-column * NpP + node (below 2^15, checked by the host) | previous column << 15
-        tent[ql * kMaxContrib + k] = (uint16_t)((e & 0x7fff) | (((e >> 30) & 1) << 15));
-      }
-      tcm[ql] = (uint16_t)(cnt | (msk << 4));
-    }
+  for (int ql = threadIdx.x; ql < nc; ql += kBlockThreads) {
+    tent4[ql] = ((const SEM_GLOBAL u32x4*)gview(a.acc_pk))[ql];
+    tcm[ql] = gview(a.acc_cm)[ql];
   }
   // input region of block b into registers (kU per thread cover any block;
   // the host checks cb nc + nl <= kU * kBlockThreads)
@@ -478,7 +478,6 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
     else return gview(a.opf)[i];
   };
   constexpr int kS2 = 2 * NpP * NpP;   // start of the stage-2 fragments
-  const T sgn = (flags & F_NEG) ? T(-1) : T(1);
   for (int b = b0; b < b1; ++b) {
     const int c0 = b * a.cb;
     const int cbb = cols_of(b);
@@ -573,43 +572,15 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
     }
     lds_barrier();
     // node sums in a fixed order (the reference kernel's table), from LDS
-    for (int q = threadIdx.x; q < nreg; q += kBlockThreads) {
-      const int lq = q / nc, ql = q - lq * nc;
-      const int cm = tcm[ql];
-      const int cnt = cm & 15;
-      const bool masked = (cm >> 4) & 1;
-      uint16_t ent[kMaxContrib];
-#pragma unroll
-      for (int k = 0; k < kMaxContrib; ++k) ent[k] = tent[ql * kMaxContrib + k];
-      T acc = 0;
-      if (lq < cbb) {
-#pragma unroll
-        for (int k = 0; k < kMaxContrib; ++k) {
-          if (k >= cnt) break;
-          const int e = ent[k];
-          const int off = e & 0x7fff;
-          const int pos = (off / NpP) * NS + off % NpP;
-          if (e >> 15) {
-            if (lq == 0) continue;  // previous column belongs to the left block
-            acc += st3[(lq - 1) * nz2 * NS + pos];
-          } else {
-            acc += st3[lq * nz2 * NS + pos];
-          }
-        }
-        y[(int64_t)(c0 + lq) * nc + ql] = masked ? T(0) : acc * sgn;
-      } else {
-        // right line: contributions of the block's last column
-#pragma unroll
-        for (int k = 0; k < kMaxContrib; ++k) {
-          if (k >= cnt) break;
-          const int e = ent[k];
-          if ((e >> 15) == 0) continue;
-          const int off = e & 0x7fff;
-          acc += st3[(cbb - 1) * nz2 * NS + (off / NpP) * NS + off % NpP];
-        }
-        side[(size_t)b * nl + ql] = masked ? T(0) : acc * sgn;
-      }
-    }
+    node_sums_packed<NpP, T>(st3, y, side, flags, nc, nl, nz2, b, c0, cbb,
+                             [&](int ql, uint32_t(&e)[kMaxContrib / 2], int& cm) {
+                               const u32x4 v = tent4[ql];
+                               e[0] = v.x;
+                               e[1] = v.y;
+                               e[2] = v.z;
+                               e[3] = v.w;
+                               cm = tcm[ql];
+                             });
     // (the next block's input may be stored while these sums run: they read
     // only the tables and the element outputs, which the next tiles overwrite
     // after the barrier that follows that store)

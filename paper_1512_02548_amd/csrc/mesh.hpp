@@ -50,6 +50,7 @@ struct sem_mesh {
   int64_t n = 0, ns = 0, E = 0;
   // host tables
   std::vector<int32_t> elem_loc, acc_cnt, acc_ent, surf_loc, is_surf_loc;
+  std::vector<uint16_t> acc_pk, acc_cm;   // packed node-sum table of the matrix-core kernels
   std::vector<double> node_x, node_sig;
   std::vector<int64_t> surf_nodes;
   // layout

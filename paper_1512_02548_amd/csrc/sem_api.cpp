@@ -199,6 +199,22 @@ static sem_status build_mesh(sem_mesh* M) {
           if (M->elem_loc[(size_t)e * NpP + k] == nc + q && !add(q, (1 << 30) | (e * NpP + k)))
             return fail(SEM_E_INVAL, "accumulation table overflow");
   }
+  // the same table packed for the matrix-core stiffness kernels: per node
+  // kMaxContrib 16-bit entries, the contribution's offset in the kernel's
+  // element outputs (element-in-column x (NpP + 1) + node, below 2^15 for
+  // nz <= 256) | previous column << 15, and one word count | surface << 4
+  M->acc_pk.assign((size_t)nc * kMaxContrib, 0);
+  M->acc_cm.assign(nc, 0);
+  for (int q = 0; q < nc; ++q) {
+    for (int k = 0; k < M->acc_cnt[q]; ++k) {
+      const int e = M->acc_ent[(size_t)q * kMaxContrib + k];
+      const int off = e & 0x3fffffff;
+      const int pos = (off / NpP) * (NpP + 1) + off % NpP;
+      if (pos >= (1 << 15)) return fail(SEM_E_INVAL, "packed accumulation table overflow");
+      M->acc_pk[(size_t)q * kMaxContrib + k] = (uint16_t)(pos | (((e >> 30) & 1) << 15));
+    }
+    M->acc_cm[q] = (uint16_t)(M->acc_cnt[q] | (M->is_surf_loc[q] << 4));
+  }
   // global coordinates
   M->node_x.assign(M->n, 0.0);
   M->node_sig.assign(M->n, 0.0);
@@ -906,6 +922,8 @@ static sem_status build_mesh(sem_mesh* M) {
   put(M, "elem_loc", M->elem_loc);
   put(M, "acc_cnt", M->acc_cnt);
   put(M, "acc_ent", M->acc_ent);
+  put(M, "acc_pk", M->acc_pk);
+  put(M, "acc_cm", M->acc_cm);
   put(M, "surf_loc", M->surf_loc);
   put(M, "is_surf_loc", M->is_surf_loc);
   put(M, "lay", lay);
@@ -1006,6 +1024,7 @@ extern "C" sem_status sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out)
   if (!desc || !out) return fail(SEM_E_INVAL, "null argument");
   *out = nullptr;
   if (desc->nx < 1 || desc->nz < 1) return fail(SEM_E_INVAL, "nx and nz must be >= 1");
+  if (desc->nz > 256) return fail(SEM_E_INVAL, "nz must be <= 256");
   if (desc->order < 1 || desc->order > kMaxOrder) return fail(SEM_E_INVAL, "order must be in 1..8");
   if (!(desc->length > 0)) return fail(SEM_E_INVAL, "length must be positive");
   if (desc->periodic && desc->nx < 2) return fail(SEM_E_INVAL, "a periodic tank needs nx >= 2");
@@ -1168,6 +1187,8 @@ extern "C" sem_status sem_mesh_bind(sem_mesh* M, void* workspace, size_t bytes, 
   h.elem_loc = at<int32_t>(M, "elem_loc");
   h.acc_cnt = at<int32_t>(M, "acc_cnt");
   h.acc_ent = at<int32_t>(M, "acc_ent");
+  h.acc_pk = at<uint16_t>(M, "acc_pk");
+  h.acc_cm = at<uint16_t>(M, "acc_cm");
   h.surf_loc = at<int32_t>(M, "surf_loc");
   h.is_surf_loc = at<int32_t>(M, "is_surf_loc");
   h.lay = at<double>(M, "lay");

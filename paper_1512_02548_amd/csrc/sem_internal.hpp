@@ -143,6 +143,8 @@ struct TankDev {
   const int32_t* acc_ent;         // [nc][kMaxContrib]: bit 30 = previous column, low bits e_in_col*NpP + m
   const int32_t* surf_loc;        // [P] column-local index of the surface nodes of a column
   const int32_t* is_surf_loc;     // [nc + nl] 1 if the column-local node lies on sigma = 1
+  const uint16_t* acc_pk;         // [nc][kMaxContrib]: offset in the element outputs (e_in_col (NpP+1) + m) | prev << 15
+  const uint16_t* acc_cm;         // [nc]: count | surface << 4
   const double* lay;              // [2nz][8]: Lam_rx, Lam_rs(sig), Lam_sx, Lam_ss, J, sigma_j, dsigma_j, 0
   const double* nodeq;            // [2][NpP][2]: xi, zeta of each reference node in the unit quad
   const double* colw;             // [2][NpP][P+1]: column interpolation weights at xi
