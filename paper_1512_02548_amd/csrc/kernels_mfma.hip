@@ -88,11 +88,10 @@ __host__ __device__ inline StiffArgs<T> stiff_args(const TankDev& h, const void*
 
 // LDS: [operators 4 NpP^2 (if they fit)] [elem_loc 2nz NpP ints] [u region cb nc + nl]
 // [element outputs T 16 (NpP + 1): rows padded against bank conflicts]
-// [several blocks per workgroup: node-sum table, nc x kMaxContrib 16-bit
-// entries and nc 16-bit counts]
+// [packed node-sum table: nc x kMaxContrib 16-bit entries, nc 16-bit counts]
 template <typename T>
 __host__ __device__ inline size_t stiff_lds_layout(const TankDev& h, int ops_in_lds, size_t* o_loc, size_t* o_u,
-                                                   size_t* o_st, bool mb = false, size_t* o_tab = nullptr) {
+                                                   size_t* o_st, size_t* o_tab) {
   size_t off = ops_in_lds ? 4 * (size_t)h.NpP * h.NpP * sizeof(T) : 0;
   *o_loc = off;
   off += (size_t)2 * h.nz * h.NpP * sizeof(int32_t);
@@ -103,8 +102,8 @@ __host__ __device__ inline size_t stiff_lds_layout(const TankDev& h, int ops_in_
   *o_st = off;
   off += (size_t)h.T * 16 * (h.NpP + 1) * sizeof(T);
   off = (off + 15) / 16 * 16;
-  if (o_tab) *o_tab = off;
-  if (mb) off += (size_t)h.nc * (kMaxContrib + 1) * sizeof(uint16_t);
+  *o_tab = off;
+  off += (size_t)h.nc * (kMaxContrib + 1) * sizeof(uint16_t);
   return off;
 }
 
@@ -204,23 +203,30 @@ __device__ __forceinline__ void node_sums_packed(const T* st3, T* __restrict__ y
   }
 }
 
-// node sums of a one-block workgroup, the table read from global memory
-// (one node's entries as a 16-byte load)
-template <int NpP, typename T>
-__device__ __forceinline__ void node_sums(const StiffArgs<T>& a, const T* st3, T* __restrict__ y,
-                                          T* __restrict__ side, int flags, int b, int c0, int cbb) {
-  const SEM_GLOBAL u32x4* pk = (const SEM_GLOBAL u32x4*)gview(a.acc_pk);
-  const SEM_GLOBAL uint16_t* cmg = gview(a.acc_cm);
-  node_sums_packed<NpP, T>(st3, y, side, flags, a.nc, a.nl, 2 * a.nz, b, c0, cbb,
-                           [&](int ql, uint32_t(&e)[kMaxContrib / 2], int& cm) {
-                             const u32x4 v = pk[ql];
-                             e[0] = v.x;
-                             e[1] = v.y;
-                             e[2] = v.z;
-                             e[3] = v.w;
-                             cm = cmg[ql];
-                           });
+// the element table and the packed node-sum table into LDS
+template <typename T>
+__device__ __forceinline__ void stage_tables(const StiffArgs<T>& a, int NpP, int32_t* lloc, u32x4* tent4,
+                                             uint16_t* tcm) {
+  for (int i = threadIdx.x; i < 2 * a.nz * NpP; i += kBlockThreads) lloc[i] = gview(a.elem_loc)[i];
+  for (int ql = threadIdx.x; ql < a.nc; ql += kBlockThreads) {
+    tent4[ql] = ((const SEM_GLOBAL u32x4*)gview(a.acc_pk))[ql];
+    tcm[ql] = gview(a.acc_cm)[ql];
+  }
 }
+
+// a node's packed entries from the LDS copy of the table
+struct LdsTab {
+  const u32x4* tent4;
+  const uint16_t* tcm;
+  __device__ void operator()(int ql, uint32_t (&e)[kMaxContrib / 2], int& cm) const {
+    const u32x4 v = tent4[ql];
+    e[0] = v.x;
+    e[1] = v.y;
+    e[2] = v.z;
+    e[3] = v.w;
+    cm = tcm[ql];
+  }
+};
 
 // Workgroup b of the tank's grid (columns b cb .. b cb + cb - 1).
 // SZ: the operator of the w~ recovery instead (paper Sec. 3.1.3),
@@ -230,7 +236,7 @@ __device__ __forceinline__ void node_sums(const StiffArgs<T>& a, const T* st3, T
 template <int P, typename T, typename GS, bool OPS_LDS, bool SZ = false>
 __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __restrict__ u, T* __restrict__ y,
                                            T* __restrict__ side, int flags, uint32_t o_loc, uint32_t o_u,
-                                           uint32_t o_st, int b) {
+                                           uint32_t o_st, uint32_t o_tab, int b) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   constexpr int Np = (P + 1) * (P + 2) / 2;
@@ -242,6 +248,8 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
   int32_t* lloc = reinterpret_cast<int32_t*>(lds_raw + o_loc);   // [2nz][NpP]
   T* ureg = reinterpret_cast<T*>(lds_raw + o_u);                 // [cb nc + nl]
   T* st3 = reinterpret_cast<T*>(lds_raw + o_st);                 // [T 16][NpP]
+  u32x4* tent4 = reinterpret_cast<u32x4*>(lds_raw + o_tab);      // [nc]: kMaxContrib packed entries
+  uint16_t* tcm = reinterpret_cast<uint16_t*>(tent4 + a.nc);      // [nc]: count | surface << 4
   const int c0 = b * a.cb;
   const int cbb = min(a.cb, a.nx - c0);
   const int nc = a.nc, nl = a.nl, nz2 = 2 * a.nz;
@@ -287,7 +295,7 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
 #pragma unroll
     for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
   }
-  for (int i = threadIdx.x; i < nz2 * NpP; i += blockDim.x) lloc[i] = gview(a.elem_loc)[i];
+  stage_tables(a, NpP, lloc, tent4, tcm);
   stage_region(a, u, ureg, c0, cbb);
   __syncthreads();
   // operator fragments: LDS copies, or global memory when they do not fit
@@ -372,7 +380,7 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
     }
   }
   __syncthreads();
-  node_sums<NpP>(a, st3, y, side, flags, b, c0, cbb);
+  node_sums_packed<NpP, T>(st3, y, side, flags, nc, nl, nz2, b, c0, cbb, LdsTab{tent4, tcm});
 }
 
 // Workgroup blocks b0 .. b0 + nblk - 1 of the tank's grid, one after the
@@ -422,11 +430,7 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
 #pragma unroll
     for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
   }
-  for (int i = threadIdx.x; i < nz2 * NpP; i += kBlockThreads) lloc[i] = gview(a.elem_loc)[i];
-  for (int ql = threadIdx.x; ql < nc; ql += kBlockThreads) {
-    tent4[ql] = ((const SEM_GLOBAL u32x4*)gview(a.acc_pk))[ql];
-    tcm[ql] = gview(a.acc_cm)[ql];
-  }
+  stage_tables(a, NpP, lloc, tent4, tcm);
   // input region of block b into registers (kU per thread cover any block;
   // the host checks cb nc + nl <= kU * kBlockThreads)
   T ur[kU];
@@ -572,15 +576,7 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
     }
     lds_barrier();
     // node sums in a fixed order (the reference kernel's table), from LDS
-    node_sums_packed<NpP, T>(st3, y, side, flags, nc, nl, nz2, b, c0, cbb,
-                             [&](int ql, uint32_t(&e)[kMaxContrib / 2], int& cm) {
-                               const u32x4 v = tent4[ql];
-                               e[0] = v.x;
-                               e[1] = v.y;
-                               e[2] = v.z;
-                               e[3] = v.w;
-                               cm = tcm[ql];
-                             });
+    node_sums_packed<NpP, T>(st3, y, side, flags, nc, nl, nz2, b, c0, cbb, LdsTab{tent4, tcm});
     // (the next block's input may be stored while these sums run: they read
     // only the tables and the element outputs, which the next tiles overwrite
     // after the barrier that follows that store)
@@ -594,7 +590,7 @@ k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T
   if ((flags & F_GATE) && gview(a.ks)->done) return;
   if constexpr (MB)
     stiff_body_mb<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, o_tab, blockIdx.x * a.kb, a.kb);
-  else stiff_body<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, blockIdx.x);
+  else stiff_body<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, o_tab, blockIdx.x);
 }
 
 template <typename T, typename GS>
@@ -617,35 +613,35 @@ __global__ void __launch_bounds__(kBlockThreads) k_stiff_mfma_b(BatchArgs ba, VS
   if ((flags & F_GATE) && d.ks->done) return;
   const StiffArgs<T> a = stiff_args<T>(d, stiff_factors<T, GS>(d), stiff_ops<T>(d), OPS_LDS ? 1 : 0);
   size_t ol, ou, os, ot;
-  stiff_lds_layout<T>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os, MB, &ot);
+  stiff_lds_layout<T>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os, &ot);
   if constexpr (MB)
     stiff_body_mb<P, T, GS, OPS_LDS>(a, bvec<T>(d, u), bvec<T>(d, y), reinterpret_cast<T*>(d.side), flags,
                                      (uint32_t)ol, (uint32_t)ou, (uint32_t)os, (uint32_t)ot, it_.bx, it_.by);
   else
     stiff_body<P, T, GS, OPS_LDS>(a, bvec<T>(d, u), bvec<T>(d, y), reinterpret_cast<T*>(d.side), flags, (uint32_t)ol,
-                                  (uint32_t)ou, (uint32_t)os, it_.bx);
+                                  (uint32_t)ou, (uint32_t)os, (uint32_t)ot, it_.bx);
 }
 
 // S_z of the w~ recovery on the matrix cores (FP64), single tank and batched
 template <int P, bool OPS_LDS>
 __global__ void __launch_bounds__(kBlockThreads)
 k_sz_mfma(const StiffArgs<double> a, const double* __restrict__ u, double* __restrict__ y,
-          double* __restrict__ side, uint32_t o_loc, uint32_t o_u, uint32_t o_st) {
-  stiff_body<P, double, double, OPS_LDS, true>(a, u, y, side, 0, o_loc, o_u, o_st, blockIdx.x);
+          double* __restrict__ side, uint32_t o_loc, uint32_t o_u, uint32_t o_st, uint32_t o_tab) {
+  stiff_body<P, double, double, OPS_LDS, true>(a, u, y, side, 0, o_loc, o_u, o_st, o_tab, blockIdx.x);
 }
 template <int P, bool OPS_LDS>
 __global__ void __launch_bounds__(kBlockThreads) k_sz_mfma_b(BatchArgs ba, SSel u) {
   SEM_BATCH_TANK(ba)
   const StiffArgs<double> a = stiff_args<double>(d, d.G, d.opf_sz, OPS_LDS ? 1 : 0);
-  size_t ol, ou, os;
-  stiff_lds_layout<double>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os);
+  size_t ol, ou, os, ot;
+  stiff_lds_layout<double>(d, OPS_LDS ? 1 : 0, &ol, &ou, &os, &ot);
   // the stiffness plan's items, which may span several blocks
   const int nbt = (d.nx + d.cb - 1) / d.cb;
   const int b1 = min(it_.bx + (it_.by > 1 ? it_.by : 1), nbt);
   for (int b = it_.bx; b < b1; ++b) {
     if (b > it_.bx) __syncthreads();
     stiff_body<P, double, double, OPS_LDS, true>(a, svec(ba, d, it_.tank, u), d.b, d.side, 0, (uint32_t)ol,
-                                                 (uint32_t)ou, (uint32_t)os, b);
+                                                 (uint32_t)ou, (uint32_t)os, (uint32_t)ot, b);
   }
 }
 
@@ -695,27 +691,30 @@ static void allow_lds(K kern, size_t bytes) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-// Blocks per workgroup of a stiffness launch over `blocks` blocks: one while
-// the launch gives fewer than 2048 workgroups (eight per CU), then enough to
-// keep about 2048, so that the operators' copy into LDS is shared and each
-// wavefront streams its next tile's factors while it computes.  The results
-// do not depend on it; SEM_STIFF_BLOCKS (environment) sets it explicitly.
-// The FP64 variant that reads its operators from global memory (eighth order)
-// has no registers to spare for it and keeps one block per workgroup, and so
-// do tanks whose blocks do not fit that kernel (stiff_mb_fits).
-int stiff_blocks_per_workgroup(int64_t blocks, bool register_bound, bool fits) {
+// Blocks per workgroup of a stiffness launch over `blocks` blocks: enough to
+// keep about 3 072 workgroups (twelve per CU), or 1 024 when a workgroup's
+// LDS (`lds` bytes) leaves room for one per CU, so that the operators' copy
+// into LDS is shared and each block's loads are issued during the previous
+// block.  (Measured on the 256-tank batch against 2 048 workgroups: fourth
+// and sixth order 5% faster, eighth-order FP64 3% faster.)  The results do
+// not depend on it; SEM_STIFF_BLOCKS (environment) sets it explicitly.  The
+// FP64 variant that reads its operators from global memory has no registers
+// to spare for it and keeps one block per workgroup, and so do tanks whose
+// blocks do not fit that kernel (stiff_mb_fits).
+int stiff_blocks_per_workgroup(int64_t blocks, bool register_bound, bool fits, size_t lds) {
   if (register_bound || !fits) return 1;
   if (const char* e = std::getenv("SEM_STIFF_BLOCKS")) {
     const int k = std::atoi(e);
     if (k >= 1) return (int)std::min<int64_t>(k, std::max<int64_t>(1, blocks));
   }
-  return (int)std::max<int64_t>(1, blocks / 2048);
+  const int64_t target = lds > 80 * 1024 ? 1024 : 3072;
+  return (int)std::max<int64_t>(1, blocks / target);
 }
 
 size_t stiff_mfma_lds_bytes(const TankDev& h, size_t word) {
-  size_t a, b, c;
-  return word == sizeof(double) ? stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c)
-                                : stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c);
+  size_t a, b, c, e;
+  return word == sizeof(double) ? stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c, &e)
+                                : stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c, &e);
 }
 
 #define SEM_MP_CASE(V, ...) \
@@ -735,9 +734,10 @@ template <typename T, typename GS>
 static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T* side, int flags, hipEvent_t e0,
                          hipEvent_t e1, hipStream_t st) {
   const int inl = stiff_ops_in_lds<T>(h);
-  const int kb = stiff_blocks_per_workgroup(h.nb, sizeof(T) == sizeof(double) && !inl, stiff_mb_fits(h));
   size_t ol, ou, os, ot;
-  const size_t lds = stiff_lds_layout<T>(h, inl, &ol, &ou, &os, kb > 1, &ot);
+  const int kb = stiff_blocks_per_workgroup(h.nb, sizeof(T) == sizeof(double) && !inl, stiff_mb_fits(h),
+                                            stiff_lds_layout<T>(h, inl, &ol, &ou, &os, &ot));
+  const size_t lds = stiff_lds_layout<T>(h, inl, &ol, &ou, &os, &ot);
   const void* G;
   const T* opf;
   if constexpr (sizeof(T) == sizeof(double)) {
@@ -801,17 +801,17 @@ void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const float* u,
 
 void launch_sz_mfma(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, hipStream_t st) {
   const int inl = stiff_ops_in_lds<double>(h);
-  size_t ol, ou, os;
-  const size_t lds = stiff_lds_layout<double>(h, inl, &ol, &ou, &os);
+  size_t ol, ou, os, ot;
+  const size_t lds = stiff_lds_layout<double>(h, inl, &ol, &ou, &os, &ot);
   const StiffArgs<double> a = stiff_args<double>(h, h.G, h.opf_sz, inl);
   if (inl) {
     SEM_MP_SWITCH(h.P, allow_lds(k_sz_mfma<PP, true>, lds));
     SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_sz_mfma<PP, true>), dim3(h.nb), dim3(kBlockThreads), lds, st, a, u, y,
-                                          side, (uint32_t)ol, (uint32_t)ou, (uint32_t)os));
+                                          side, (uint32_t)ol, (uint32_t)ou, (uint32_t)os, (uint32_t)ot));
   } else {
     SEM_MP_SWITCH(h.P, allow_lds(k_sz_mfma<PP, false>, lds));
     SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_sz_mfma<PP, false>), dim3(h.nb), dim3(kBlockThreads), lds, st, a, u, y,
-                                          side, (uint32_t)ol, (uint32_t)ou, (uint32_t)os));
+                                          side, (uint32_t)ol, (uint32_t)ou, (uint32_t)os, (uint32_t)ot));
   }
 }
 
@@ -839,15 +839,22 @@ void plan_stiff(const std::vector<TankDev>& tanks, const std::vector<int>& ids, 
   TankDev probe{};
   probe.NpP = ((P + 1) * (P + 2) / 2 + 15) / 16 * 16;
   bool fits = true;
-  for (int t : ids)
-    if (tanks[t].P == P) fits = fits && stiff_mb_fits(tanks[t]);
-  const int kb = stiff_blocks_per_workgroup(blocks, !f32 && !stiff_ops_in_lds<double>(probe), fits);
+  size_t lds_mb = 0;
+  for (int t : ids) {
+    const TankDev& h = tanks[t];
+    if (h.P != P) continue;
+    fits = fits && stiff_mb_fits(h);
+    size_t a, b, c, e;
+    lds_mb = std::max(lds_mb, f32 ? stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c, &e)
+                                  : stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c, &e));
+  }
+  const int kb = stiff_blocks_per_workgroup(blocks, !f32 && !stiff_ops_in_lds<double>(probe), fits, lds_mb);
   for (int t : ids) {
     const TankDev& h = tanks[t];
     if (h.P != P) continue;
     size_t a, b, c, e;
-    const size_t lds = f32 ? stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c, kb > 1, &e)
-                           : stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c, kb > 1, &e);
+    const size_t lds = f32 ? stiff_lds_layout<float>(h, stiff_ops_in_lds<float>(h), &a, &b, &c, &e)
+                           : stiff_lds_layout<double>(h, stiff_ops_in_lds<double>(h), &a, &b, &c, &e);
     // item {tank, first block, blocks, tank's block count}
     for (int x = 0; x < h.nb; x += kb) out->items.push_back(BatchItem{t, x, kb, h.nb});
     out->lds = std::max(out->lds, lds);
