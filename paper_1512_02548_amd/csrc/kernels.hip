@@ -537,12 +537,26 @@ __device__ __forceinline__ void self_dot_partial(int64_t n, int64_t chunk, int b
 
 // final sums of nblk partials: wave w takes vectors w, w+4, ...; lanes stride
 // over the workgroup partials in a fixed order, then a butterfly
+// (a lane's partials are requested four at a time from clamped addresses and
+// added in order, so that one round trip serves four of them)
+__device__ __forceinline__ double lane_partials(const double* __restrict__ part, int ldp, int k, int nblk, int lane) {
+  double t = 0;
+  for (int b0 = lane; b0 < nblk; b0 += 4 * 64) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = part[(size_t)min(b0 + 64 * u, nblk - 1) * ldp + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (b0 + 64 * u < nblk) t += v[u];
+  }
+  return t;
+}
+
 __device__ __forceinline__ void dots_reduce(int nvec, const double* __restrict__ part, int ldp,
                                             double* __restrict__ out, int nblk) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int k = wv; k < nvec; k += kBlockThreads / 64) {
-    double t = 0;
-    for (int b2 = lane; b2 < nblk; b2 += 64) t += part[(size_t)b2 * ldp + k];
+    double t = lane_partials(part, ldp, k, nblk, lane);
     t = wave_sum(t);
     if (lane == 0) out[k] = t;
   }
@@ -596,8 +610,7 @@ __device__ __forceinline__ void orth_reduce(int j, const double* __restrict__ pa
                                             int32_t* __restrict__ status, int32_t* __restrict__ mirror,
                                             double* __restrict__ smirror = nullptr) {
   if (threadIdx.x < 64) {
-    double t = 0;
-    for (int b2 = threadIdx.x; b2 < nblk; b2 += 64) t += part[(size_t)b2 * ldp];
+    double t = lane_partials(part, ldp, 0, nblk, threadIdx.x);
     t = wave_sum(t);
     if (threadIdx.x == 0) {
       givens_update(ks, Hbase, m, j, t, status);
