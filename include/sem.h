@@ -103,7 +103,9 @@ typedef struct {
   double rtol;          /* ||b - A x||_2 <= rtol ||b||_2 (free nodes)              */
   int32_t max_iter;     /* total Krylov iterations (inner iterations for IR)       */
   int32_t prec;         /* sem_precision                                           */
-  double inner_rtol;    /* IR: relative tolerance of each inner solve              */
+  double inner_rtol;    /* IR: relative tolerance of each inner solve, loosened to
+                           min(1/2, rtol ||b|| / (2 ||r||)) when that is larger
+                           (the last refinement only needs what is left)    */
   int32_t max_refine;   /* IR: maximum outer refinements                           */
   int32_t warm_start;   /* 1: phi holds the initial guess on entry                 */
   int32_t lookahead;    /* Krylov steps the host may queue ahead of the device (>=1) */

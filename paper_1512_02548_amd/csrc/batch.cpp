@@ -65,6 +65,7 @@ struct sem_batch {
   double* scal_host = nullptr;    // [count] tank scalars read back
   double* scal_dev = nullptr;
   double* dscale = nullptr;       // device [count] per-tank factors of the refinement
+  double* drtol = nullptr;        // device [count] per-tank tolerances of the inner solves
   double* ddt = nullptr;          // device [count] time steps of the RK4 call
   const double** ptr_host = nullptr;
   BatchStage vec, dots, fixup, per_tank;
@@ -174,7 +175,7 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   const size_t o_live_d = (off + 255) / 256 * 256;
   off = o_live_d + count * sizeof(int32_t);
   const size_t o_scale_d = (off + 255) / 256 * 256;
-  off = o_scale_d + 2 * count * sizeof(double);
+  off = o_scale_d + 3 * count * sizeof(double);
   const size_t o_ptr_d = (off + 255) / 256 * 256;
   off = o_ptr_d + (size_t)PT_COUNT * count * sizeof(double*);
   std::vector<size_t> o_items;
@@ -190,6 +191,7 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   B->dlive = (int32_t*)(B->dmem + o_live_d);
   B->dscale = (double*)(B->dmem + o_scale_d);
   B->ddt = B->dscale + count;
+  B->drtol = B->ddt + count;
   B->dptr = (const double**)(B->dmem + o_ptr_d);
   HIPCHK(hipMemcpyAsync(B->dtanks, B->tanks.data(), count * sizeof(TankDev), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(B->dlive, 0, count * sizeof(int32_t), st));
@@ -307,8 +309,12 @@ static sem_status arnoldi_step(sem_batch* B, int j, int f32, int gstore, hipStre
 // FP32 copies b32, x32 with FP32 (gstore 1) or bfloat16 (gstore 2) factors).
 // iters[t] accumulates.  Tanks whose status word is set leave `act`; with
 // mark_noconv, unconverged tanks get the no-convergence bit (and leave too).
+// rtol_t (optional, device): a tolerance per tank instead of rtol; x_zero:
+// the start vector is zero, so the first cycle's residual is b itself (the
+// operator is not applied to it; A 0 = 0 exactly).
 static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rtol, int max_iter, int ahead, int f32,
-                                 int gstore, int mark_noconv, std::vector<int32_t>& iters, hipStream_t st) {
+                                 int gstore, int mark_noconv, std::vector<int32_t>& iters, hipStream_t st,
+                                 const double* rtol_t = nullptr, bool x_zero = false) {
   if (act.empty()) return SEM_OK;
   const BatchArgs a = args(B);
   const BatchStage* stiff = f32 ? B->stiff32 : B->stiff;
@@ -317,16 +323,20 @@ static sem_status lockstep_gmres(sem_batch* B, std::vector<int>& act, double rto
   ahead = std::max(1, ahead);
   sem_status s = set_live(B, act, st);
   if (s) return s;
-  launch_ks_init_b(a, B->per_tank, rtol, st);
+  launch_ks_init_b(a, B->per_tank, rtol, rtol_t, st);
   launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_B, 0}, VSel{BV_B, 0}, -1, 1, 0, 0, f32, st);
   std::vector<int> live = act;
   bool first = true;
   while (true) {
     for (int t : live) prog[t] = 0;
     // r = b - A x
-    for (int P : B->orders) launch_stiff_b(a, stiff[P], P, VSel{BV_XS, 0}, VSel{BV_W, 0}, F_MASK_SURF, gstore, st);
-    launch_fixup_b(a, B->fixup, VSel{BV_W, 0}, F_MASK_SURF, f32, st);
-    launch_residual_b(a, B->vec, VSel{BV_B, 0}, VSel{BV_W, 0}, VSel{BV_V, 0}, f32, st);
+    if (first && x_zero) {
+      launch_residual_b(a, B->vec, VSel{BV_B, 0}, VSel{BV_NONE, 0}, VSel{BV_V, 0}, f32, st);
+    } else {
+      for (int P : B->orders) launch_stiff_b(a, stiff[P], P, VSel{BV_XS, 0}, VSel{BV_W, 0}, F_MASK_SURF, gstore, st);
+      launch_fixup_b(a, B->fixup, VSel{BV_W, 0}, F_MASK_SURF, f32, st);
+      launch_residual_b(a, B->vec, VSel{BV_B, 0}, VSel{BV_W, 0}, VSel{BV_V, 0}, f32, st);
+    }
     launch_dots_b(a, B->dots, B->per_tank, 1, VSel{BV_V, 0}, VSel{BV_V, 0}, -1, 0, 0, 0, f32, st);
     launch_cycle_start_b(a, B->per_tank, B->vec, first ? 1 : 0, f32, st);
     first = false;
@@ -407,7 +417,7 @@ static sem_status lockstep_ir(sem_batch* B, std::vector<int>& act, const sem_sol
   launch_scal_out_b(a, B->per_tank, 4, B->scal_dev, st);
   s = drain(B, st);
   if (s) return s;
-  std::vector<double> bnorm(count, 0.0), rn(count, 0.0), scale(count, 0.0);
+  std::vector<double> bnorm(count, 0.0), rn(count, 0.0), scale(count, 0.0), itol(count, 0.0);
   for (int t : act) bnorm[t] = std::sqrt(B->scal_host[t]);
   std::vector<int> cur = act, noconv, nonfinite;
   for (int k = 0; k <= o.max_refine && !cur.empty(); ++k) {
@@ -437,13 +447,18 @@ static sem_status lockstep_ir(sem_batch* B, std::vector<int>& act, const sem_sol
       min_iters = std::min(min_iters, (int)iters[t]);
     }
     if (next.empty()) break;
-    for (int t : next) scale[t] = 1.0 / rn[t];
+    for (int t : next) {
+      scale[t] = 1.0 / rn[t];
+      itol[t] = inner_tolerance(o.inner_rtol, o.rtol, bnorm[t], rn[t]);
+    }
     s = set_live(B, next, st);
     if (!s) s = upload(B, B->dscale, scale.data(), count * sizeof(double), st);
+    if (!s) s = upload(B, B->drtol, itol.data(), count * sizeof(double), st);
     if (s) return s;
     launch_to_float_b(a, B->vec, B->dscale, st);
     std::vector<int> inner = next;
-    s = lockstep_gmres(B, inner, o.inner_rtol, o.max_iter - min_iters, o.lookahead, 1, gstore, 0, iters, st);
+    s = lockstep_gmres(B, inner, o.inner_rtol, o.max_iter - min_iters, o.lookahead, 1, gstore, 0, iters, st, B->drtol,
+                       true);
     if (s) return s;
     s = set_live(B, inner, st);
     if (!s) s = upload(B, B->dscale, rn.data(), count * sizeof(double), st);

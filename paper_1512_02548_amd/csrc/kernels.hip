@@ -906,13 +906,14 @@ __global__ void __launch_bounds__(kBlockThreads) k_fixup_b(BatchArgs ba, VSel y,
 }
 
 template <typename T>
+// (ysel = BV_NONE: y = A x for x = 0, exactly zero, is not read)
 __global__ void __launch_bounds__(kBlockThreads) k_residual_b(BatchArgs ba, VSel bsel, VSel ysel, VSel rsel) {
   SEM_BATCH_TANK(ba)
   const int64_t i = (int64_t)it_.bx * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   const T* bv = bvec<T>(d, bsel);
-  const T* y = bvec<T>(d, ysel);
-  T v = bv[i] - y[i];
+  T v = bv[i];
+  if (ysel.kind != BV_NONE) v -= bvec<T>(d, ysel)[i];
   if (is_surface_node(d, i)) v = T(0);
   bvec<T>(d, rsel)[i] = v;
 }
@@ -933,11 +934,12 @@ __global__ void k_cycle_start_b(BatchArgs ba, int first) {
 }
 
 // fresh Krylov state (including the reductions' completion counter)
-__global__ void k_ks_init_b(BatchArgs ba, double rtol) {
+// rtol_t (optional): a tolerance per tank
+__global__ void k_ks_init_b(BatchArgs ba, double rtol, const double* __restrict__ rtol_t) {
   SEM_BATCH_TANK(ba)
   if (threadIdx.x != 0) return;
   KrylovState k{};
-  k.rtol = rtol;
+  k.rtol = rtol_t ? rtol_t[it_.tank] : rtol;
   *d.ks = k;
 }
 
@@ -1796,8 +1798,9 @@ void launch_solve_update_b(const BatchArgs& a0, const BatchStage& per_tank, cons
   if (f32) SEM_BLAUNCH(vec, k_update_x_b<float>, x);
   else SEM_BLAUNCH(vec, k_update_x_b<double>, x);
 }
-void launch_ks_init_b(const BatchArgs& a0, const BatchStage& per_tank, double rtol, hipStream_t st) {
-  SEM_BLAUNCH(per_tank, k_ks_init_b, rtol);
+void launch_ks_init_b(const BatchArgs& a0, const BatchStage& per_tank, double rtol, const double* rtol_t,
+                      hipStream_t st) {
+  SEM_BLAUNCH(per_tank, k_ks_init_b, rtol, rtol_t);
 }
 void launch_status_clear_b(const BatchArgs& a0, const BatchStage& per_tank, hipStream_t st) {
   SEM_BLAUNCH(per_tank, k_status_clear_b, 0);

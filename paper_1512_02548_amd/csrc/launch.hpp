@@ -142,7 +142,8 @@ void launch_cycle_start_b(const BatchArgs& a, const BatchStage& per_tank, const 
                           hipStream_t st);
 void launch_solve_update_b(const BatchArgs& a, const BatchStage& per_tank, const BatchStage& vec, VSel x, int f32,
                            hipStream_t st);
-void launch_ks_init_b(const BatchArgs& a, const BatchStage& per_tank, double rtol, hipStream_t st);
+void launch_ks_init_b(const BatchArgs& a, const BatchStage& per_tank, double rtol, const double* rtol_t,
+                      hipStream_t st);
 void launch_status_clear_b(const BatchArgs& a, const BatchStage& per_tank, hipStream_t st);
 // ks_out / st_out: host-visible arrays indexed by tank
 void launch_state_out_b(const BatchArgs& a, const BatchStage& per_tank, KrylovState* ks_out, int32_t* st_out,

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -103,5 +104,14 @@ sem_status status_from_word(int32_t w);
 void default_opts(sem_solve_opts* o);
 // w~ from M w = S_z Phi with the factors 1/d current; out [ns]
 sem_status recover_w_core(sem_mesh* M, const double* Phi, double* out, hipStream_t st);
+
+// Tolerance of a refinement's inner solve (single tank and batch alike): the
+// configured inner tolerance, loosened (up to 1/2) when the residual is
+// already near the target, so that the last refinement reduces it only by
+// the factor still needed, with a margin of 2.
+inline double inner_tolerance(double inner, double rtol, double bnorm, double rn) {
+  const double need = rn > 0 ? 0.5 * rtol * bnorm / rn : 0.5;
+  return std::max(inner, std::min(0.5, need));
+}
 
 }  // namespace sem

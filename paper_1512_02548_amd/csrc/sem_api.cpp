@@ -1789,6 +1789,7 @@ static sem_status laplace_core(sem_mesh* M, const double* phi_s, double* phi, co
       launch_to_float(n, h.tmp, 1.0 / rn, h.b32, st);
       launch_fill_f(n, h.x32, st);
       cfg.max_iter = o->max_iter - iters;
+      cfg.rtol = inner_tolerance(o->inner_rtol, o->rtol, bnorm, rn);
       int it = 0;
       double rr32 = 0;
       sem_status si = gmres(M, cfg, buf32(M), h.x32, h.b32, &it, &rr32, st);
