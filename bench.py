@@ -278,7 +278,7 @@ def batch_workload(args, modes=("lockstep_fp64", "lockstep_mixed", "concurrent_m
 
     fp64 = lib.default_opts(rtol=1e-10, warm_start=1, max_iter=20000)
     mixed = lib.default_opts(rtol=1e-10, warm_start=1, prec=lib.SEM_PREC_FP32_IR,
-                             inner_rtol=getattr(args, "inner_rtol", 1e-3), max_iter=20000)
+                             inner_rtol=getattr(args, "inner_rtol", 1e-5), max_iter=20000)
     tl = batched("lockstep_fp64", 0, fp64) if "lockstep_fp64" in modes else None
     if "lockstep_mixed" in modes:
         batched("lockstep_mixed", 0, mixed)
@@ -378,7 +378,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--streams", type=int, default=8)
     ap.add_argument("--tiles", type=int, default=0, help="batch: stiffness tiles per workgroup (0: autotuner)")
-    ap.add_argument("--inner-rtol", type=float, default=1e-3,
+    ap.add_argument("--inner-rtol", type=float, default=1e-5,
                     help="batch: relative tolerance of the FP32 inner solves of iterative refinement")
     ap.add_argument("--large-inner-rtol", type=float, default=None,
                     help="large tank: inner tolerance for both reduced precisions (default: per precision)")

@@ -61,7 +61,7 @@ class GpuBackend:
         self.nstreams = nstreams
         self.device = device
         self.opts = opts if opts is not None else lib.default_opts(
-            rtol=1e-8, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-3, lookahead=3)
+            rtol=1e-8, warm_start=1, prec=lib.SEM_PREC_FP32_IR, inner_rtol=1e-5, lookahead=3)
         self._batch = None
         self._members = []        # tanks of the current device batch, in its order
         self._retired = []        # retired members kept alive until the next rebuild
