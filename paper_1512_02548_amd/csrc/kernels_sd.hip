@@ -22,6 +22,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <utility>
+#include <vector>
 
 #include "launch.hpp"
 #include "mfma.hpp"
@@ -1085,6 +1088,52 @@ void add_grid(BatchStage& st, int tank, int gx, int gy, size_t lds) {
     for (int x = 0; x < gx; ++x) st.items.push_back(BatchItem{tank, x, y, gx});
   st.lds = std::max(st.lds, lds);
 }
+
+// Orders a product's work items so that those reading the same factor rows
+// (same tank and M-tile group `by`) sit at positions of the same residue mod
+// 8: the chip hands consecutive workgroups to its eight XCDs in turn, so the
+// rows are fetched into one XCD's L2 instead of all eight.  Groups go to the
+// least loaded XCD; once a residue's queue is empty its positions take items
+// of the longest remaining queue.  (Each item writes its own outputs: the
+// order does not change any result.)
+void xcd_affine(BatchStage& st) {
+  constexpr int kXcd = 8;
+  std::vector<std::vector<BatchItem>> groups;
+  std::map<std::pair<int, int>, size_t> gid;
+  for (const BatchItem& it : st.items) {
+    auto key = std::make_pair(it.tank, it.by);
+    auto f = gid.find(key);
+    if (f == gid.end()) {
+      f = gid.emplace(key, groups.size()).first;
+      groups.emplace_back();
+    }
+    groups[f->second].push_back(it);
+  }
+  std::vector<std::vector<BatchItem>> q(kXcd);
+  for (const auto& g : groups) {
+    size_t best = 0;
+    for (size_t k = 1; k < q.size(); ++k)
+      if (q[k].size() < q[best].size()) best = k;
+    q[best].insert(q[best].end(), g.begin(), g.end());
+  }
+  std::vector<size_t> head(kXcd, 0);
+  std::vector<BatchItem> out;
+  out.reserve(st.items.size());
+  while (out.size() < st.items.size()) {
+    const int r = (int)(out.size() % kXcd);
+    int k = r;
+    if (head[k] == q[k].size()) {
+      size_t rem = 0;
+      for (int k2 = 0; k2 < kXcd; ++k2)
+        if (q[k2].size() - head[k2] > rem) {
+          rem = q[k2].size() - head[k2];
+          k = k2;
+        }
+    }
+    out.push_back(q[k][head[k]++]);
+  }
+  st.items.swap(out);
+}
 }  // namespace
 
 void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int which, int f32, BatchSD* out) {
@@ -1115,6 +1164,8 @@ void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int
     }
     add_grid(out->back, t, g.bx, g.by, l.back);
   }
+  xcd_affine(out->cond);
+  xcd_affine(out->back);
 }
 
 template <typename T>
