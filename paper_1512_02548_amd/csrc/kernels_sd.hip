@@ -76,19 +76,36 @@ struct SdMat<float> {
 // reuse each factor fragment over more columns) and four M-tiles, one per
 // wave; or, for small tanks (split = 1), one M-tile per workgroup with its K
 // range split over the four waves (more workgroups, shorter chains).  A
-// function of the tank alone, so a tank gets the same launch shape alone and
-// in a batch.
+// function of the tank alone.  ch: accumulator chains per tile (below).
 struct SdShape {
-  int ntw, split;
+  int ntw, split, ch;
 };
 __host__ __device__ inline SdShape sd_shape(int nx, int nMT) {
   const int ct = (nx + 15) / 16, mg = (nMT + 3) / 4;
-  if (((ct + 3) / 4) * mg >= 256) return SdShape{4, 0};
-  if (((ct + 1) / 2) * mg >= 256) return SdShape{2, 0};
-  if (ct * mg >= 256) return SdShape{1, 0};
-  return SdShape{1, 1};
+  if (((ct + 3) / 4) * mg >= 256) return SdShape{4, 0, 1};
+  if (((ct + 1) / 2) * mg >= 256) return SdShape{2, 0, 1};
+  if (ct * mg >= 256) return SdShape{1, 0, 1};
+  return SdShape{1, 1, 1};
 }
 constexpr int kNTMax = 4;    // N-tiles per wave at most
+// In a batched launch workgroups never run short, so every tank's products
+// run as wide tiles: four M-tiles (one per wave) and kNTB N-tiles per
+// workgroup, which reuse each factor fragment and each staged column over
+// more of the product than the split shape does.  An output must not depend
+// on the launch, so a tank whose own launch splits K keeps that summation
+// order: its wide tiles carry four accumulator chains (chain r takes the
+// K-steps = r mod 4, as wave r does in the split shape, and the chains are
+// added in order at the end).  narrow: one N-tile (the back-substitution of
+// tanks that form their line values by the inverse transform in the
+// workgroup, whose layout covers 16 columns).
+constexpr int kNTB = 4;      // N-tiles of a wide tile, one chain
+// N-tiles of a wide tile with four chains: two in FP32, one in FP64 (two
+// would halve the FP64 kernels' occupancy)
+__host__ __device__ constexpr int ntb4(size_t word) { return word == 4 ? 2 : 1; }
+__host__ __device__ inline SdShape sd_shape_b(int nx, int nMT, bool narrow, size_t word) {
+  const SdShape s = sd_shape(nx, nMT);
+  return SdShape{narrow ? 1 : (s.split ? ntb4(word) : kNTB), 0, s.split ? 4 : 1};
+}
 // Small direct-transform tanks (nx <= 64, lines of at most 32 unknowns): the
 // back-substitution workgroups form the line values they need by the inverse
 // transform themselves (17 lines x 32 unknowns, one 16 x 16 tile per wave),
@@ -111,7 +128,9 @@ __host__ __device__ inline size_t sd_cond_stage_bytes(int ntw, size_t word, int 
 // not depend on the grouping); R is staged in LDS in chunks of kKC K-steps.
 // SPLIT (small tanks, NTW = 1): one M-tile per workgroup, wave w takes the
 // K-steps w, w + 4, ... and the four partial tiles are added in wave order.
-template <typename T, int NTW, bool SPLIT>
+// CH = 4 (batched wide tiles of such tanks): the same sums, chain r of a
+// tile taking the K-steps = r mod 4.
+template <typename T, int NTW, bool SPLIT, int CH>
 __device__ __forceinline__ void sd_cond_impl(const TankDev& d, const SDData& sd, const T* __restrict__ r,
                                              const double* __restrict__ nscale, T* __restrict__ vout, int bx,
                                              int by) {
@@ -132,9 +151,12 @@ __device__ __forceinline__ void sd_cond_impl(const TankDev& d, const SDData& sd,
   const double rs = sd_in_scale(nscale);
   const SEM_GLOBAL T* A = gview(SdMat<T>::A1(sd)) + (size_t)min(mt, nMT - 1) * KS * 64;
   const SEM_GLOBAL T* rg = gview(r);
-  V4 acc[NTW];
+  static_assert(CH == 1 || (CH == 4 && !SPLIT && kKC % 4 == 0), "chains: wide tiles, whole chunks of 4 K-steps");
+  V4 acc[CH][NTW];
 #pragma unroll
-  for (int u = 0; u < NTW; ++u) acc[u] = V4{0, 0, 0, 0};
+  for (int c = 0; c < CH; ++c)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) acc[c][u] = V4{0, 0, 0, 0};
   // R chunk s0 (4 kKC = 64 interior rows x 16 NTW columns): lane l of wave w
   // reads row l of columns w, w + 4, ... (consecutive lanes, consecutive
   // interior unknowns of a column).  Fetched into registers one chunk ahead,
@@ -165,27 +187,36 @@ __device__ __forceinline__ void sd_cond_impl(const TankDev& d, const SDData& sd,
       if (vout && by == 0 && ok) vout[(c0 + cc) * ncl + li] = v;
     }
   };
-  __syncthreads();   // interior index table
-  if (KS > 0) fetch(0);
-  for (int s0 = 0; s0 < KS; s0 += kKC) {
+  // This wave's factor fragments, requested one chunk ahead: a fragment of
+  // chunk s0 + kKC is requested as soon as the products of the same slot of
+  // chunk s0 have been issued.  K-steps past the tank's last (kc < kKC) take
+  // the chunk's last fragment and multiply staged zero rows: they add exact
+  // zeros.  The barriers order LDS only, so that these requests stay in
+  // flight across them.
+  T ab[kSteps];
+  auto load_ab = [&](int p2, int s0) {
     const int kc = min(kKC, KS - s0);
-    __syncthreads();   // every wave is past the previous chunk's products
-    stage(s0);
-    __syncthreads();
-    // this wave's factor fragments of the chunk, then the next chunk's input:
-    // both in flight while the products run.  K-steps past the tank's last
-    // (kc < kKC) multiply staged zero rows: they add exact zeros.
-    T ab[kSteps];
+    ab[p2] = A[(size_t)(s0 + min(s_first + p2 * s_step, kc - 1)) * 64 + lane];
+  };
+  lds_barrier();   // interior index table
+  if (KS > 0) {
+    fetch(0);
 #pragma unroll
-    for (int p2 = 0; p2 < kSteps; ++p2)
-      ab[p2] = A[(size_t)(s0 + min(s_first + p2 * s_step, kc - 1)) * 64 + lane];
-    if (s0 + kKC < KS) fetch(s0 + kKC);
+    for (int p2 = 0; p2 < kSteps; ++p2) load_ab(p2, 0);
+  }
+  for (int s0 = 0; s0 < KS; s0 += kKC) {
+    const bool more = s0 + kKC < KS;
+    lds_barrier();   // every wave is past the previous chunk's products
+    stage(s0);
+    lds_barrier();
+    if (more) fetch(s0 + kKC);   // the next chunk's input, in flight during the products
     if (mt < nMT) {
 #pragma unroll
       for (int p2 = 0; p2 < kSteps; ++p2) {
         const T* brow = Rs + (4 * (s_first + p2 * s_step) + grp) * ldr + col;
 #pragma unroll
-        for (int u = 0; u < NTW; ++u) acc[u] = MF::op(ab[p2], brow[16 * u], acc[u]);
+        for (int u = 0; u < NTW; ++u) acc[p2 % CH][u] = MF::op(ab[p2], brow[16 * u], acc[p2 % CH][u]);
+        if (more) load_ab(p2, s0 + kKC);
       }
     }
   }
@@ -196,7 +227,7 @@ __device__ __forceinline__ void sd_cond_impl(const TankDev& d, const SDData& sd,
 #pragma unroll
     for (int u = 0; u < NTW; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red[(wv * NTW + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[u][v];
+      for (int v = 0; v < 4; ++v) red[(wv * NTW + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[0][u][v];
     __syncthreads();
     const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
     const int row = 16 * mt + rr;
@@ -219,7 +250,13 @@ __device__ __forceinline__ void sd_cond_impl(const TankDev& d, const SDData& sd,
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * mt + MF::row(v, grp);
-      const double val = (double)acc[u][v];
+      double val = 0;
+      if constexpr (CH == 1) {
+        val = (double)acc[0][u][v];
+      } else {
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) val += (double)acc[ch][u][v];
+      }
       if (row < nI) sd.yI[(size_t)c * nI + row] = val;
       else if (row < nI + q) sd.TL[(size_t)c * q + row - nI] = val;
       else if (row < nI + 2 * q) sd.TR[(size_t)c * q + row - nI - q] = val;
@@ -227,16 +264,23 @@ __device__ __forceinline__ void sd_cond_impl(const TankDev& d, const SDData& sd,
   }
 }
 
-template <typename T>
+// B: a batched launch (wide tiles, sd_shape_b)
+template <typename T, bool B>
 __device__ __forceinline__ void sd_cond_body(const TankDev& d, int which, const T* __restrict__ r,
                                              const double* __restrict__ nscale, T* __restrict__ vout, int bx,
                                              int by) {
   const SDData& sd = d.sd[which];
+  if constexpr (B) {
+    if (sd_shape_b(d.nx, sd.nMT1, false, sizeof(T)).ch == 4)
+      sd_cond_impl<T, ntb4(sizeof(T)), false, 4>(d, sd, r, nscale, vout, bx, by);
+    else sd_cond_impl<T, kNTB, false, 1>(d, sd, r, nscale, vout, bx, by);
+    return;
+  }
   const SdShape sh = sd_shape(d.nx, sd.nMT1);
-  if (sh.split) sd_cond_impl<T, 1, true>(d, sd, r, nscale, vout, bx, by);
-  else if (sh.ntw == 4) sd_cond_impl<T, 4, false>(d, sd, r, nscale, vout, bx, by);
-  else if (sh.ntw == 2) sd_cond_impl<T, 2, false>(d, sd, r, nscale, vout, bx, by);
-  else sd_cond_impl<T, 1, false>(d, sd, r, nscale, vout, bx, by);
+  if (sh.split) sd_cond_impl<T, 1, true, 1>(d, sd, r, nscale, vout, bx, by);
+  else if (sh.ntw == 4) sd_cond_impl<T, 4, false, 1>(d, sd, r, nscale, vout, bx, by);
+  else if (sh.ntw == 2) sd_cond_impl<T, 2, false, 1>(d, sd, r, nscale, vout, bx, by);
+  else sd_cond_impl<T, 1, false, 1>(d, sd, r, nscale, vout, bx, by);
 }
 
 template <typename T>
@@ -245,7 +289,7 @@ k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
           const double* __restrict__ nscale, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
-  sd_cond_body<T>(d, which, r, nscale, vout, (int)blockIdx.x, (int)blockIdx.y);
+  sd_cond_body<T, false>(d, which, r, nscale, vout, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // modes: one block per 16 Fourier modes; waves split the sum over columns
@@ -434,8 +478,9 @@ k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
 // The product of the back-substitution for M-tile mt and NTW N-tiles of 16
 // columns from c0, the line values of the columns in LDS (xl, row stride
 // q + 1): z_I = Y - C [x_L,c; x_L,c+1].  SPLIT: wave w takes the K-steps
-// w, w + 4, ... and the partial tiles are added in wave order.
-template <typename T, int NTW, bool SPLIT>
+// w, w + 4, ... and the partial tiles are added in wave order; CH = 4: the
+// same sums, chain r of the tile taking the K-steps = r mod 4.
+template <typename T, int NTW, bool SPLIT, int CH>
 __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& sd, T* __restrict__ z,
                                                 double* xl, int c0, int mt) {
   using MF = Mfma<T>;
@@ -446,12 +491,15 @@ __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& 
   const int s_first = SPLIT ? wv : 0;
   constexpr int s_step = SPLIT ? kWaves : 1;
   const SEM_GLOBAL T* C = gview(SdMat<T>::C3(sd)) + (size_t)mt * KS3 * 64;
-  V4 acc[NTW];
-#pragma unroll
-  for (int u = 0; u < NTW; ++u) acc[u] = V4{0, 0, 0, 0};
   // factor fragments loaded kPre K-steps at a time, one group ahead of their
   // MFMAs; rows k >= 2q of the last K-step multiply zeros (exact zeros added)
   constexpr int kPre = 8;
+  static_assert(CH == 1 || (CH == 4 && !SPLIT && kPre % 4 == 0), "chains: wide tiles, groups of 4 K-steps");
+  V4 acc[CH][NTW];
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) acc[c][u] = V4{0, 0, 0, 0};
   T ab[kPre], an[kPre];
   auto load = [&](int s, T (&dst)[kPre]) {
 #pragma unroll
@@ -470,7 +518,7 @@ __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& 
 #pragma unroll
       for (int u = 0; u < NTW; ++u) {
         const double bx = xl[(16 * u + col) * qp + (kv ? off : 0)];
-        acc[u] = MF::op(ab[p2], kv ? T(bx) : T(0), acc[u]);
+        acc[p2 % CH][u] = MF::op(ab[p2], kv ? T(bx) : T(0), acc[p2 % CH][u]);
       }
     }
 #pragma unroll
@@ -483,7 +531,7 @@ __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& 
 #pragma unroll
     for (int u = 0; u < NTW; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red[(wv * NTW + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[u][v];
+      for (int v = 0; v < 4; ++v) red[(wv * NTW + u) * 256 + MF::row(v, grp) * 16 + col] = (double)acc[0][u][v];
     __syncthreads();
     const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
     const int row = 16 * mt + rr;
@@ -514,7 +562,14 @@ __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * mt + MF::row(v, grp);
-      if (row < nI) z[(int64_t)c * nc + idx[v]] = T(yv[u][v] - (double)acc[u][v]);
+      double sacc = 0;
+      if constexpr (CH == 1) {
+        sacc = (double)acc[0][u][v];
+      } else {
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) sacc += (double)acc[ch][u][v];
+      }
+      if (row < nI) z[(int64_t)c * nc + idx[v]] = T(yv[u][v] - sacc);
     }
   }
 }
@@ -523,8 +578,9 @@ __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& 
 // tiled product: workgroup (column group bx, M-tiles 4 by .. 4 by + 3), one
 // M-tile per wave, the full K range (2q) in order; the lines of the group's
 // columns and the next one come from XL through LDS.  Workgroups of row 0
-// also write the line values (and the wall line).
-template <typename T>
+// also write the line values (and the wall line).  B: a batched launch
+// (wide tiles, sd_shape_b).
+template <typename T, bool B>
 __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __restrict__ z, T* __restrict__ vout,
                                              int bx, int by) {
   using MF = Mfma<T>;
@@ -532,7 +588,8 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
   const SDData& sd = d.sd[which];
   extern __shared__ double sh[];
   const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc, nMT = sd.nMT3, KS3 = sd.KS3;
-  const SdShape shp = sd_shape(nx, nMT);
+  const bool dft = sd_back_dft(nx, q, sd.fft_n1, nMT);
+  const SdShape shp = B ? sd_shape_b(nx, nMT, dft, sizeof(T)) : sd_shape(nx, nMT);
   const int ntw = shp.ntw;
   const int ncol = 16 * ntw;
   const int qp = q + 1;                      // odd stride: conflict-free reads across columns
@@ -540,7 +597,7 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
   const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
   const int c0 = bx * ncol;
   const int mt = shp.split ? by : 4 * by + wv;
-  if (sd_back_dft(nx, q, sd.fft_n1, nMT)) {
+  if (dft) {
     // x_L,c = Re sum_k e^{2 pi i k c / nx} x^_k / nx for lines c0 .. c0 + 16:
     // wave (line tile lt, unknown tile jt), the whole K range (modes x re/im)
     // in order, operands loaded kD K-steps at a time
@@ -606,10 +663,20 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
     }
   }
   if (mt >= nMT) return;   // (uniform over the workgroup in split mode)
-  if (shp.split) sd_back_product<T, 1, true>(d, sd, z, xl, c0, mt);
-  else if (ntw == 4) sd_back_product<T, 4, false>(d, sd, z, xl, c0, mt);
-  else if (ntw == 2) sd_back_product<T, 2, false>(d, sd, z, xl, c0, mt);
-  else sd_back_product<T, 1, false>(d, sd, z, xl, c0, mt);
+  if constexpr (B) {
+    if (shp.ch == 4) {
+      if (ntw == 1) sd_back_product<T, 1, false, 4>(d, sd, z, xl, c0, mt);
+      else sd_back_product<T, ntb4(sizeof(T)), false, 4>(d, sd, z, xl, c0, mt);
+    } else {
+      if (ntw == 1) sd_back_product<T, 1, false, 1>(d, sd, z, xl, c0, mt);
+      else sd_back_product<T, kNTB, false, 1>(d, sd, z, xl, c0, mt);
+    }
+    return;
+  }
+  if (shp.split) sd_back_product<T, 1, true, 1>(d, sd, z, xl, c0, mt);
+  else if (ntw == 4) sd_back_product<T, 4, false, 1>(d, sd, z, xl, c0, mt);
+  else if (ntw == 2) sd_back_product<T, 2, false, 1>(d, sd, z, xl, c0, mt);
+  else sd_back_product<T, 1, false, 1>(d, sd, z, xl, c0, mt);
 }
 
 template <typename T>
@@ -617,7 +684,7 @@ __global__ void __launch_bounds__(kBlockThreads)
 k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
-  sd_back_body<T>(d, which, z, vout, (int)blockIdx.x, (int)blockIdx.y);
+  sd_back_body<T, false>(d, which, z, vout, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // Sum of a workgroup's values in a fixed order (wave butterflies, then the
@@ -998,8 +1065,21 @@ namespace {
 struct SdLds {
   size_t cond, modes, back, fa, fsolve, wall;
 };
-SdLds sd_lds(const TankDev& h, const SDData& sd, size_t word) {
-  const SdShape s1 = sd_shape(h.nx, sd.nMT1), s3 = sd_shape(h.nx, sd.nMT3);
+// shapes of a tank's condensation and back-substitution products, alone or
+// in a batched launch
+// in a batched launch (word: bytes of the arithmetic type)
+void sd_shapes(const TankDev& h, const SDData& sd, size_t word, bool batched, SdShape* s1, SdShape* s3) {
+  if (!batched) {
+    *s1 = sd_shape(h.nx, sd.nMT1);
+    *s3 = sd_shape(h.nx, sd.nMT3);
+    return;
+  }
+  *s1 = sd_shape_b(h.nx, sd.nMT1, false, word);
+  *s3 = sd_shape_b(h.nx, sd.nMT3, sd_back_dft(h.nx, sd.q, sd.fft_n1, sd.nMT3), word);
+}
+SdLds sd_lds(const TankDev& h, const SDData& sd, size_t word, bool batched) {
+  SdShape s1, s3;
+  sd_shapes(h, sd, word, batched, &s1, &s3);
   SdLds l;
   l.cond = sd_cond_stage_bytes(s1.ntw, word, s1.split) + sizeof(int32_t) * sd.nI;
   l.modes = sizeof(double) * (sd_part_words(sd.q) + kModesPerBlockMax * (size_t)sd.q * 2);
@@ -1013,8 +1093,9 @@ struct SdGrid {
   int cx, cy, bx, by;
 };
 // grids of the condensation (cx, cy) and back-substitution (bx, by) products
-SdGrid sd_grid(const TankDev& h, const SDData& sd) {
-  const SdShape s1 = sd_shape(h.nx, sd.nMT1), s3 = sd_shape(h.nx, sd.nMT3);
+SdGrid sd_grid(const TankDev& h, const SDData& sd, size_t word, bool batched) {
+  SdShape s1, s3;
+  sd_shapes(h, sd, word, batched, &s1, &s3);
   const int ct = (h.nx + 15) / 16;
   return SdGrid{(ct + s1.ntw - 1) / s1.ntw, s1.split ? sd.nMT1 : (sd.nMT1 + 3) / 4, (ct + s3.ntw - 1) / s3.ntw,
                 s3.split ? sd.nMT3 : (sd.nMT3 + 3) / 4};
@@ -1029,7 +1110,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlockThreads) k_sd_cond_b(BatchArgs ba, int which, VSel rin, int jn, int gate) {
   SEM_BATCH_TANK(ba)
   if (gate && d.ks->done) return;
-  sd_cond_body<T>(d, which, bvec<T>(d, rin), jn > 0 ? krylov_norm(d, jn) : nullptr,
+  sd_cond_body<T, true>(d, which, bvec<T>(d, rin), jn > 0 ? krylov_norm(d, jn) : nullptr,
                   jn > 0 ? bvec<T>(d, VSel{BV_V, jn}) : nullptr, it_.bx, it_.by);
 }
 template <typename T>
@@ -1056,7 +1137,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlockThreads) k_sd_back_b(BatchArgs ba, int which, VSel zout, int jn, int gate) {
   SEM_BATCH_TANK(ba)
   if (gate && d.ks->done) return;
-  sd_back_body<T>(d, which, bvec<T>(d, zout), jn > 0 ? bvec<T>(d, VSel{BV_V, jn}) : nullptr, it_.bx, it_.by);
+  sd_back_body<T, true>(d, which, bvec<T>(d, zout), jn > 0 ? bvec<T>(d, VSel{BV_V, jn}) : nullptr, it_.bx, it_.by);
 }
 #define SEM_SD_PLAIN_B(NAME, BODY)                                                          \
   template <typename T>                                                                     \
@@ -1141,8 +1222,8 @@ void plan_sd(const std::vector<TankDev>& tanks, const std::vector<int>& ids, int
   for (int t : ids) {
     const TankDev& h = tanks[t];
     const SDData& sd = h.sd[which];
-    const SdLds l = sd_lds(h, sd, f32 ? sizeof(float) : sizeof(double));
-    const SdGrid g = sd_grid(h, sd);
+    const SdLds l = sd_lds(h, sd, f32 ? sizeof(float) : sizeof(double), true);
+    const SdGrid g = sd_grid(h, sd, f32 ? sizeof(float) : sizeof(double), true);
     const int ct = (h.nx + 15) / 16;
     add_grid(out->cond, t, g.cx, g.cy, l.cond);
     if (sd.fft_n1) {
@@ -1204,8 +1285,8 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
                  T* vout, hipStream_t st) {
   const SDData& sd = h.sd[which];
   const unsigned ct = (unsigned)((h.nx + 15) / 16);
-  const SdLds lds = sd_lds(h, sd, sizeof(T));
-  const SdGrid g = sd_grid(h, sd);
+  const SdLds lds = sd_lds(h, sd, sizeof(T), false);
+  const SdGrid g = sd_grid(h, sd, sizeof(T), false);
   const size_t l2 = lds.modes;
   hipLaunchKernelGGL(k_sd_cond<T>, dim3(g.cx, g.cy), dim3(kBlockThreads), lds.cond, st, d, which, u, gate, nscale,
                      vout);
