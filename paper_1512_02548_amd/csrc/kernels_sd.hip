@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <map>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -292,8 +293,18 @@ k_sd_cond(const TankDev* __restrict__ td, int which, const T* __restrict__ r, in
   sd_cond_body<T, false>(d, which, r, nscale, vout, (int)blockIdx.x, (int)blockIdx.y);
 }
 
-// modes: one block per 16 Fourier modes; waves split the sum over columns
-template <typename T>
+// modes: one block per 8 or 16 Fourier modes; waves split the sum over
+// columns.  U: K-steps of a wave whose loads are requested together.  SQ:
+// the mode solves of tanks with at most kSolveQ line unknowns and one (mode,
+// row) item per thread, whose row of the inverse symbol is requested at once
+// (the other tanks walk it kSolveUnroll entries at a time).
+constexpr int kSolveQ = 32;
+constexpr int kSolveChunk = 16;
+constexpr int kSolveUnroll = 8;
+__host__ __device__ inline bool sd_modes_small(int nx, int q) {
+  return q <= kSolveQ && modes_per_block(nx) * q <= kBlockThreads;
+}
+template <typename T, int U, bool SQ>
 __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const T* __restrict__ r, const double* __restrict__ nscale, T* __restrict__ vout, int bx, int by) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
@@ -318,50 +329,57 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
 #pragma unroll
     for (int u = 0; u < 4; ++u) are[u] = aim[u] = V4{0, 0, 0, 0};
     int mm = (int)(((int64_t)kr * (4 * wv + grp)) % nx);
-    // every load of a K-step is issued before its products, from clamped
+    // the loads of U K-steps are issued before their products, from clamped
     // addresses (no branch around a load); entries outside the tank are
-    // zeroed afterwards
+    // zeroed afterwards, and K-steps past the last multiply zeros
     const SEM_GLOBAL T* rg = gview(r);
     const SEM_GLOBAL double* tlg = gview(sd.TL);
     const SEM_GLOBAL double* trg = gview(sd.TR);
     const SEM_GLOBAL double* twg = gview(d.twid);
     const int jb = 16 * nt0 + col;
 #pragma unroll 1
-    for (int s = wv; s < KS; s += kWaves) {
-      const int c = 4 * s + grp;
-      const bool cv = c < nx;
-      const int cc = min(c, nx - 1);
-      const int cm = cc == 0 ? nx - 1 : cc - 1;
-      const double twr = twg[2 * mm], twi = twg[2 * mm + 1];
-      double rv[4], tl[4], tr[4], rw[4];
+    for (int s0 = wv; s0 < KS; s0 += U * kWaves) {
+      double twr[U], twi[U], rv[U][4], tl[U][4], tr[U][4], rw[U][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (u >= ntn) break;   // (uniform)
-        const int jj = min(jb + 16 * u, q - 1);
-        rv[u] = (double)rg[(int64_t)cc * nc + jj];
-        tl[u] = tlg[(size_t)cc * q + jj];
-        tr[u] = trg[(size_t)cm * q + jj];
-        if (sd.wall) rw[u] = (double)rg[(int64_t)nx * nc + jj];   // (uniform: walled tanks fold their wall line onto line 0)
-      }
-      const T fre = (cv && kval) ? T(twr) : T(0);
-      const T fim = (cv && kval) ? T(twi) : T(0);
+      for (int e = 0; e < U; ++e) {
+        const int cc = min(4 * (s0 + e * kWaves) + grp, nx - 1);
+        const int cm = cc == 0 ? nx - 1 : cc - 1;
+        twr[e] = twg[2 * mm];
+        twi[e] = twg[2 * mm + 1];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (u >= ntn) break;
-        const int j = jb + 16 * u;
-        const bool ok = cv && j < q;
-        double v = rv[u] * rs;
-        if (vout && bx == 0 && ok) vout[(int64_t)c * nc + j] = T(v);
-        if (sd.wall && c == 0 && ok) {   // wall line folded onto line 0
-          const double w = rw[u] * rs;
-          if (vout && bx == 0) vout[(int64_t)nx * nc + j] = T(w);
-          v += w;
+        for (int u = 0; u < 4; ++u) {
+          if (u >= ntn) break;   // (uniform)
+          const int jj = min(jb + 16 * u, q - 1);
+          rv[e][u] = (double)rg[(int64_t)cc * nc + jj];
+          tl[e][u] = tlg[(size_t)cc * q + jj];
+          tr[e][u] = trg[(size_t)cm * q + jj];
+          if (sd.wall) rw[e][u] = (double)rg[(int64_t)nx * nc + jj];   // (uniform: walled tanks fold their wall line onto line 0)
         }
-        const T gv = ok ? T(v - tl[u] - tr[u]) : T(0);
-        are[u] = MF::op(fre, gv, are[u]);
-        aim[u] = MF::op(fim, gv, aim[u]);
+        mm = wrap_add(mm, step, nx);
       }
-      mm = wrap_add(mm, step, nx);
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        const int c = 4 * (s0 + e * kWaves) + grp;
+        const bool cv = c < nx;
+        const T fre = (cv && kval) ? T(twr[e]) : T(0);
+        const T fim = (cv && kval) ? T(twi[e]) : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (u >= ntn) break;
+          const int j = jb + 16 * u;
+          const bool ok = cv && j < q;
+          double v = rv[e][u] * rs;
+          if (vout && bx == 0 && ok) vout[(int64_t)c * nc + j] = T(v);
+          if (sd.wall && c == 0 && ok) {   // wall line folded onto line 0
+            const double w = rw[e][u] * rs;
+            if (vout && bx == 0) vout[(int64_t)nx * nc + j] = T(w);
+            v += w;
+          }
+          const T gv = ok ? T(v - tl[e][u] - tr[e][u]) : T(0);
+          are[u] = MF::op(fre, gv, are[u]);
+          aim[u] = MF::op(fim, gv, aim[u]);
+        }
+      }
     }
     for (int u = 0; u < ntn; ++u) {
 #pragma unroll
@@ -387,23 +405,67 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
       __syncthreads();
     }
   }
-  // x^_k = S^_k^{-1} g^_k (column-major: thread per (mode, row))
-  for (int t = threadIdx.x; t < kModesPB * q; t += blockDim.x) {
-    const int kk = t / q, i = t - kk * q, k = paired_mode(bx, kk, kPairs, nx);
-    if (k < 0) continue;
+  // x^_k = S^_k^{-1} g^_k (column-major: thread per (mode, row)), the sum
+  // over j in order
+  auto solve = [&](int kk, int i, int k, auto load_all) {
     const bool cj = 2 * k > nx;   // stored as the conjugate of mode nx - k
     const SEM_GLOBAL T* S = gview(SdMat<T>::Shat(sd)) + (size_t)(cj ? nx - k : k) * q * q * 2;
     const double sgn = cj ? -1.0 : 1.0;
     double xr = 0, xi = 0;
-#pragma unroll 8
-    for (int j = 0; j < q; ++j) {
-      const double sr = (double)S[((size_t)j * q + i) * 2], si = sgn * (double)S[((size_t)j * q + i) * 2 + 1];
-      const double gr = gh[(kk * q + j) * 2], gi = gh[(kk * q + j) * 2 + 1];
-      xr += sr * gr - si * gi;
-      xi += sr * gi + si * gr;
+    if constexpr (decltype(load_all)::value) {
+      // kSolveChunk entries requested together (clamped addresses)
+      for (int j0 = 0; j0 < q; j0 += kSolveChunk) {
+        double sv[2 * kSolveChunk];
+#pragma unroll
+        for (int e = 0; e < kSolveChunk; ++e) {
+          const int jj = min(j0 + e, q - 1);
+          sv[2 * e] = (double)S[((size_t)jj * q + i) * 2];
+          sv[2 * e + 1] = (double)S[((size_t)jj * q + i) * 2 + 1];
+        }
+#pragma unroll
+        for (int e = 0; e < kSolveChunk; ++e) {
+          const int j = j0 + e;
+          if (j < q) {   // (uniform)
+            const double sr = sv[2 * e], si = sgn * sv[2 * e + 1];
+            const double gr = gh[(kk * q + j) * 2], gi = gh[(kk * q + j) * 2 + 1];
+            xr += sr * gr - si * gi;
+            xi += sr * gi + si * gr;
+          }
+        }
+      }
+    } else {
+#pragma unroll kSolveUnroll
+      for (int j = 0; j < q; ++j) {
+        const double sr = (double)S[((size_t)j * q + i) * 2], si = sgn * (double)S[((size_t)j * q + i) * 2 + 1];
+        const double gr = gh[(kk * q + j) * 2], gi = gh[(kk * q + j) * 2 + 1];
+        xr += sr * gr - si * gi;
+        xi += sr * gi + si * gr;
+      }
     }
     sd.XH[((size_t)k * q + i) * 2] = xr;
     sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
+  };
+  for (int t = threadIdx.x; t < kModesPB * q; t += blockDim.x) {
+    const int kk = t / q, i = t - kk * q, k = paired_mode(bx, kk, kPairs, nx);
+    if (k < 0) continue;
+    solve(kk, i, k, std::integral_constant<bool, SQ>{});
+  }
+}
+
+// K-steps per wave requested together by the direct transform: two, or all
+// four of a tank of at most 64 columns launched alone (B: a batched launch,
+// whose registers also serve its long tanks).  Only K-steps past the last
+// depend on it, and they add zeros.
+template <typename T, bool B>
+__device__ __forceinline__ void sd_modes_any(const TankDev& d, int which, const T* __restrict__ r,
+                                             const double* __restrict__ nscale, T* __restrict__ vout, int bx,
+                                             int by) {
+  const int q = d.sd[which].q;
+  if (sd_modes_small(d.nx, q)) {
+    if (!B && d.nx <= 64) sd_modes_body<T, B ? 2 : 4, true>(d, which, r, nscale, vout, bx, by);
+    else sd_modes_body<T, 2, true>(d, which, r, nscale, vout, bx, by);
+  } else {
+    sd_modes_body<T, 2, false>(d, which, r, nscale, vout, bx, by);
   }
 }
 
@@ -413,7 +475,7 @@ k_sd_modes(const TankDev* __restrict__ td, int which, const T* __restrict__ r, i
            const double* __restrict__ nscale, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
-  sd_modes_body<T>(d, which, r, nscale, vout, (int)blockIdx.x, (int)blockIdx.y);
+  sd_modes_any<T, false>(d, which, r, nscale, vout, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // inverse transform of the line solution (direct products, small nx): grid
@@ -1117,8 +1179,8 @@ template <typename T>
 __global__ void __launch_bounds__(kBlockThreads) k_sd_modes_b(BatchArgs ba, int which, VSel rin, int jn, int gate) {
   SEM_BATCH_TANK(ba)
   if (gate && d.ks->done) return;
-  sd_modes_body<T>(d, which, bvec<T>(d, rin), jn > 0 ? krylov_norm(d, jn) : nullptr,
-                   jn > 0 ? bvec<T>(d, VSel{BV_V, jn}) : nullptr, it_.bx, it_.by);
+  sd_modes_any<T, true>(d, which, bvec<T>(d, rin), jn > 0 ? krylov_norm(d, jn) : nullptr,
+                  jn > 0 ? bvec<T>(d, VSel{BV_V, jn}) : nullptr, it_.bx, it_.by);
 }
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads) k_sdf_a_b(BatchArgs ba, int which, VSel rin, int jn, int gate) {
