@@ -68,7 +68,7 @@ struct sem_batch {
   double* drtol = nullptr;        // device [count] per-tank tolerances of the inner solves
   double* ddt = nullptr;          // device [count] time steps of the RK4 call
   const double** ptr_host = nullptr;
-  BatchStage vec, dots, fixup, per_tank;
+  BatchStage vec, dots, dblocks, fixup, per_tank;
   BatchStage stiff[kMaxOrder + 1], stiff32[kMaxOrder + 1];   // FP64, FP32 (LDS sized per word)
   BatchSD sdlap, sdlap32;
   BatchSD sdmass;                 // exact inverse of the 2D mass matrix (w recovery)
@@ -145,6 +145,9 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
     for (int x = 0; x < nv; ++x) B->vec.items.push_back(BatchItem{t, x, 0, nv});
     const int nd = dot_nchunk(h.n);
     for (int x = 0; x < nd; ++x) B->dots.items.push_back(BatchItem{t, x, 0, nd});
+    // products per stiffness block: about 2 048 nodes per workgroup
+    const int kbd = std::max(1, std::min(8, 2048 / (h.cb * h.nc + h.nl)));
+    for (int x = 0; x < h.nb; x += kbd) B->dblocks.items.push_back(BatchItem{t, x, kbd, h.nb});
     const int nf = (h.nb * h.nl + kBlockThreads - 1) / kBlockThreads;
     for (int x = 0; x < nf; ++x) B->fixup.items.push_back(BatchItem{t, x, 0, nf});
     B->per_tank.items.push_back(BatchItem{t, 0, 0, 1});
@@ -158,7 +161,7 @@ static sem_status setup_lockstep(sem_batch* B, hipStream_t st) {
   plan_sd(B->tanks, ids, 0, 1, &B->sdlap32);
   plan_sd(B->tanks, ids, 1, 0, &B->sdmass);
   plan_stage(B->tanks, ids, &B->stage);
-  std::vector<BatchStage*> stages = {&B->vec, &B->dots, &B->fixup, &B->per_tank};
+  std::vector<BatchStage*> stages = {&B->vec, &B->dots, &B->dblocks, &B->fixup, &B->per_tank};
   for (int P : B->orders) {
     stages.push_back(&B->stiff[P]);
     stages.push_back(&B->stiff32[P]);
@@ -258,8 +261,10 @@ static sem_status put_pointers(sem_batch* B, int which, const double* const* p, 
 // ------------------------------------------------------------ lockstep GMRES
 // Kernels of Arnoldi step j over all tanks: z_j = M^-1 v_j (for j > 0,
 // v_j = w / ||w|| is formed on the way), w = A z_j, the products with
-// V_0..V_j, the orthogonalisation and Givens update.  Every launch returns at
-// once for a tank whose cycle is done.
+// V_0..V_j per stiffness block and their sums, the orthogonalisation (w's
+// shared-line fix-up on the way) and Givens update: the single-tank step's
+// arithmetic (there the stiffness launch forms the products itself).  Every launch returns at once for a tank
+// whose cycle is done.
 static void issue_step(sem_batch* B, int j, int f32, int gstore, hipStream_t st) {
   const BatchArgs a = args(B);
   const BatchStage* stiff = f32 ? B->stiff32 : B->stiff;
@@ -267,8 +272,8 @@ static void issue_step(sem_batch* B, int j, int f32, int gstore, hipStream_t st)
   launch_sd_b(a, sdp, 0, j == 0 ? VSel{BV_V, 0} : VSel{BV_W, 0}, VSel{BV_Z, j}, j, 1, f32, st);
   for (int P : B->orders)
     launch_stiff_b(a, stiff[P], P, VSel{BV_Z, j}, VSel{BV_W, 0}, F_MASK_SURF | F_GATE | F_NOFIX, gstore, st);
-  launch_dots_b(a, B->dots, B->per_tank, j + 1, VSel{BV_V, 0}, VSel{BV_W, 0}, j, 0, 1, 1, f32, st);
-  launch_orth_b(a, B->dots, B->per_tank, j, f32, st);
+  launch_dots_blocks_b(a, B->dblocks, B->per_tank, j + 1, j, f32, st);
+  launch_orth_b(a, B->dots, B->per_tank, j, f32, st, 1);
 }
 
 // The step as a graph launch: captured from the stream on first use (the

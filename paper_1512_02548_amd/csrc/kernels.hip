@@ -19,6 +19,7 @@
 #include <cmath>
 
 #include "launch.hpp"
+#include "reduce.hpp"
 
 namespace sem {
 
@@ -38,12 +39,6 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 __device__ inline bool finite(double v) { return v - v == 0.0; }
-
-// butterfly sum over a 64-lane wavefront (every lane gets the total)
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 __device__ inline int64_t right_line_base(const TankDev& d, int c) {
   // global index of the first node of the vertical line at x_c (c in 0..nx)
@@ -440,21 +435,6 @@ __device__ inline double* progress_scalars(int32_t* mirror) {
 }
 
 
-// Whether this workgroup is the last of nblk to finish its partials.  The
-// barrier orders every wave's partial stores before thread 0's count, whose
-// device-scope release makes them visible and whose acquire (in the last
-// workgroup) makes the others' visible; the second barrier passes that on to
-// the workgroup.  (One release-acquire operation per workgroup: a device-scope
-// fence in every thread cost about 1.3 us more per launch.)
-__device__ inline bool last_block(int32_t* counter, int nblk) {
-  __shared__ int is_last;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    is_last = (__hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == nblk - 1);
-  __syncthreads();
-  return is_last != 0;
-}
-
 // y[i] of an element-kernel output with its shared-line contribution from
 // the side buffer added (the fix-up pass, done by the consumer; the same
 // addition as the separate pass)
@@ -539,33 +519,6 @@ __device__ __forceinline__ void self_dot_partial(int64_t n, int64_t chunk, int b
   if (threadIdx.x == 0) part[(size_t)bx * ldp] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-// final sums of nblk partials: wave w takes vectors w, w+4, ...; lanes stride
-// over the workgroup partials in a fixed order, then a butterfly
-// (a lane's partials are requested four at a time from clamped addresses and
-// added in order, so that one round trip serves four of them)
-__device__ __forceinline__ double lane_partials(const double* __restrict__ part, int ldp, int k, int nblk, int lane) {
-  double t = 0;
-  for (int b0 = lane; b0 < nblk; b0 += 4 * 64) {
-    double v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = part[(size_t)min(b0 + 64 * u, nblk - 1) * ldp + k];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (b0 + 64 * u < nblk) t += v[u];
-  }
-  return t;
-}
-
-__device__ __forceinline__ void dots_reduce(int nvec, const double* __restrict__ part, int ldp,
-                                            double* __restrict__ out, int nblk) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k = wv; k < nvec; k += kBlockThreads / 64) {
-    double t = lane_partials(part, ldp, k, nblk, lane);
-    t = wave_sum(t);
-    if (lane == 0) out[k] = t;
-  }
-}
-
 template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, T* __restrict__ w,
@@ -580,16 +533,20 @@ k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, T* __res
 }
 
 // w' = w - sum_{i<=j} h_i V_i, and this workgroup's part of ||w'||^2
+// (fixd: w is an operator output whose shared-line contributions are still
+// in the side buffer, added as it is read)
 template <typename T>
 __device__ __forceinline__ void orth_partial(int64_t n, int j, const T* __restrict__ V,
                                              const double* __restrict__ Hbase, int m, T* __restrict__ w,
-                                             double* __restrict__ part, int ldp, int64_t chunk, int bx) {
+                                             double* __restrict__ part, int ldp, int64_t chunk, int bx,
+                                             const TankDev* __restrict__ fixd = nullptr,
+                                             const T* __restrict__ side = nullptr) {
   __shared__ double red[4];
   const double* hcol = Hbase + (size_t)j * (m + 1);
   const int64_t lo = (int64_t)bx * chunk, hi = min(lo + chunk, n);
   double sacc = 0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double v = w[i];
+    double v = fixd ? (double)fixed_value<T>(*fixd, w, side, i) : (double)w[i];
     for (int k0 = 0; k0 <= j; k0 += 8) {
       T vv[8];
 #pragma unroll
@@ -628,9 +585,10 @@ template <typename T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_orth_fused(int64_t n, int j, const T* __restrict__ V, double* __restrict__ Hbase, int m, T* __restrict__ w,
              double* __restrict__ part, int ldp, int64_t chunk, KrylovState* __restrict__ ks,
-             int32_t* __restrict__ counter, int32_t* __restrict__ status, int32_t* __restrict__ mirror) {
+             int32_t* __restrict__ counter, int32_t* __restrict__ status, int32_t* __restrict__ mirror,
+             const TankDev* __restrict__ fixd, const T* __restrict__ side) {
   if (ks->done) return;
-  orth_partial<T>(n, j, V, Hbase, m, w, part, ldp, chunk, blockIdx.x);
+  orth_partial<T>(n, j, V, Hbase, m, w, part, ldp, chunk, blockIdx.x, fixd, side);
   if (!last_block(counter, gridDim.x)) return;
   if (threadIdx.x == 0) *counter = 0;
   orth_reduce(j, part, ldp, gridDim.x, ks, Hbase, m, status, mirror, progress_scalars(mirror));
@@ -888,12 +846,35 @@ __global__ void __launch_bounds__(kBlockThreads) k_dots_sum_b(BatchArgs ba, int 
   dots_reduce(nvec, d.part, d.m + 2, out, dot_nchunk(d.n));
 }
 
+// the products of a stiffness output (before its fix-up) with V_0 ..
+// V_{nvec-1}, per stiffness block as the single-tank stiffness launch forms
+// them: item (tank, first block bx, blocks by)
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads) k_orth_b(BatchArgs ba, int j) {
+__global__ void __launch_bounds__(kBlockThreads) k_dots_blocks_b(BatchArgs ba, int nvec) {
+  SEM_BATCH_TANK(ba)
+  if (d.ks->done) return;
+  const T* y = bvec<T>(d, VSel{BV_W, 0});
+  const T* V = bvec<T>(d, VSel{BV_V, 0});
+  for (int b = it_.bx; b < min(it_.bx + it_.by, d.nb); ++b)
+    block_dots_part<T>(d.cb, d.nx, d.nc, d.nl, d.periodic, y, reinterpret_cast<const T*>(d.side), V, d.n, nvec,
+                       d.part, d.m + 2, b);
+}
+
+// one workgroup per tank: the products' sums from the per-block partials
+// into H column hcol
+__global__ void __launch_bounds__(kBlockThreads) k_dots_sum_blocks_b(BatchArgs ba, int nvec, int hcol) {
+  SEM_BATCH_TANK(ba)
+  if (d.ks->done) return;
+  dots_reduce(nvec, d.part, d.m + 2, d.H + (size_t)hcol * (d.m + 1), d.nb);
+}
+
+// fix: w's shared-line contributions are still in the side buffer
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) k_orth_b(BatchArgs ba, int j, int fix) {
   SEM_BATCH_TANK(ba)
   if (d.ks->done) return;
   orth_partial<T>(d.n, j, bvec<T>(d, VSel{BV_V, 0}), d.H, d.m, bvec<T>(d, VSel{BV_W, 0}), d.part, d.m + 2,
-                  dot_chunk(d.n), it_.bx);
+                  dot_chunk(d.n), it_.bx, fix ? &d : nullptr, fix ? reinterpret_cast<const T*>(d.side) : nullptr);
 }
 
 __global__ void __launch_bounds__(kBlockThreads) k_orth_sum_b(BatchArgs ba, int j) {
@@ -1682,20 +1663,23 @@ void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* 
 
 template <typename T>
 static void orth_t(int64_t n, int j, const T* V, double* H, int m, T* w, double* part, int ldp, KrylovState* ks,
-                   int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st) {
+                   int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st, const TankDev* fixd,
+                   const T* side) {
   int nc;
   int64_t chunk;
   dot_layout(n, &nc, &chunk);
   hipLaunchKernelGGL(k_orth_fused<T>, dim3(nc), dim3(kBlockThreads), 0, st, n, j, V, H, m, w, part, ldp, chunk, ks,
-                     counter, status, mirror);
+                     counter, status, mirror, fixd, side);
 }
 void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
-                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st) {
-  orth_t<double>(n, j, V, H, m, w, part, ldp, ks, counter, status, mirror, st);
+                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st,
+                        const TankDev* fixd, const double* side) {
+  orth_t<double>(n, j, V, H, m, w, part, ldp, ks, counter, status, mirror, st, fixd, side);
 }
 void launch_orth_givens(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
-                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st) {
-  orth_t<float>(n, j, V, H, m, w, part, ldp, ks, counter, status, mirror, st);
+                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st,
+                        const TankDev* fixd, const float* side) {
+  orth_t<float>(n, j, V, H, m, w, part, ldp, ks, counter, status, mirror, st, fixd, side);
 }
 
 void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m,
@@ -1770,10 +1754,16 @@ void launch_dots_b(const BatchArgs& a0, const BatchStage& p, const BatchStage& p
   SEM_BLAUNCH(per_tank, k_dots_sum_b, nvec, hcol, sidx, gate);
 }
 void launch_orth_b(const BatchArgs& a0, const BatchStage& p, const BatchStage& per_tank, int j, int f32,
-                   hipStream_t st) {
-  if (f32) SEM_BLAUNCH(p, k_orth_b<float>, j);
-  else SEM_BLAUNCH(p, k_orth_b<double>, j);
+                   hipStream_t st, int fix) {
+  if (f32) SEM_BLAUNCH(p, k_orth_b<float>, j, fix);
+  else SEM_BLAUNCH(p, k_orth_b<double>, j, fix);
   SEM_BLAUNCH(per_tank, k_orth_sum_b, j);
+}
+void launch_dots_blocks_b(const BatchArgs& a0, const BatchStage& p, const BatchStage& per_tank, int nvec, int hcol,
+                          int f32, hipStream_t st) {
+  if (f32) SEM_BLAUNCH(p, k_dots_blocks_b<float>, nvec);
+  else SEM_BLAUNCH(p, k_dots_blocks_b<double>, nvec);
+  SEM_BLAUNCH(per_tank, k_dots_sum_blocks_b, nvec, hcol);
 }
 void launch_fixup_b(const BatchArgs& a0, const BatchStage& p, VSel y, int flags, int f32, hipStream_t st) {
   if (f32) SEM_BLAUNCH(p, k_fixup_b<float>, y, flags);

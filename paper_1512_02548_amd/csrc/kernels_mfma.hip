@@ -25,6 +25,7 @@
 
 #include "launch.hpp"
 #include "mfma.hpp"
+#include "reduce.hpp"
 
 namespace sem {
 
@@ -583,14 +584,32 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
   }
 }
 
+// Block b's part of the products of its output with the Krylov vectors
+template <typename T>
+__device__ inline void stiff_block_dots(const StiffArgs<T>& a, const T* __restrict__ y, const T* __restrict__ side,
+                                        const T* __restrict__ V, int64_t n, int nvec, double* __restrict__ part,
+                                        int ldp, int b) {
+  block_dots_part<T>(a.cb, a.nx, a.nc, a.nl, a.periodic, y, side, V, n, nvec, part, ldp, b);
+}
+
 template <int P, typename T, typename GS, bool OPS_LDS, bool MB>
 __global__ void __launch_bounds__(kBlockThreads)
 k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T* __restrict__ side, int flags,
-             uint32_t o_loc, uint32_t o_u, uint32_t o_st, uint32_t o_tab) {
+             uint32_t o_loc, uint32_t o_u, uint32_t o_st, uint32_t o_tab, StiffDots dt) {
   if ((flags & F_GATE) && gview(a.ks)->done) return;
-  if constexpr (MB)
-    stiff_body_mb<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, o_tab, blockIdx.x * a.kb, a.kb);
-  else stiff_body<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, o_tab, blockIdx.x);
+  const int b0 = MB ? (int)blockIdx.x * a.kb : (int)blockIdx.x;
+  if constexpr (MB) stiff_body_mb<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, o_tab, b0, a.kb);
+  else stiff_body<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, o_tab, b0);
+  if (dt.nvec <= 0) return;
+  // the inner products with the Krylov vectors: the blocks' parts, then their
+  // sum in the last workgroup
+  const int nbt = (a.nx + a.cb - 1) / a.cb;
+  __syncthreads();
+  for (int b = b0; b < min(b0 + (MB ? a.kb : 1), nbt); ++b)
+    stiff_block_dots<T>(a, y, side, reinterpret_cast<const T*>(dt.V), dt.n, dt.nvec, dt.part, dt.ldp, b);
+  if (!last_block(dt.counter, gridDim.x)) return;
+  dots_reduce(dt.nvec, dt.part, dt.ldp, dt.out, nbt);
+  if (threadIdx.x == 0) *dt.counter = 0;
 }
 
 template <typename T, typename GS>
@@ -681,14 +700,23 @@ __host__ __device__ inline int stiff_ops_in_lds(const TankDev& h) {
 static std::mutex g_lds_mu;
 static std::set<std::pair<const void*, int>> g_lds_done;
 
+// The limit on a kernel's dynamic LDS is raised once per kernel and device
+// to what its static LDS leaves of the 160 KiB (the fused inner products give
+// the stiffness kernels some), for every kernel that takes dynamic LDS.
 template <typename K>
 static void allow_lds(K kern, size_t bytes) {
-  if (bytes <= 64 * 1024) return;
+  if (bytes == 0) return;
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lock(g_lds_mu);
-  if (g_lds_done.insert({(const void*)kern, dev}).second)
-    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (g_lds_done.insert({(const void*)kern, dev}).second) {
+    hipFuncAttributes fa{};
+    size_t stat = 0;
+    if (hipFuncGetAttributes(&fa, (const void*)kern) == hipSuccess) stat = fa.sharedSizeBytes;
+    const int lim = (int)(160 * 1024 - std::min<size_t>(stat, 160 * 1024));
+    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
+      (void)hipGetLastError();   // (the launch itself reports a size beyond the limit)
+  }
 }
 
 // Blocks per workgroup of a stiffness launch over `blocks` blocks: enough to
@@ -732,7 +760,7 @@ size_t stiff_mfma_lds_bytes(const TankDev& h, size_t word) {
 // gstore: 0 = FP64 factors (T = double), 1 = FP32, 2 = bfloat16
 template <typename T, typename GS>
 static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T* side, int flags, hipEvent_t e0,
-                         hipEvent_t e1, hipStream_t st) {
+                         hipEvent_t e1, hipStream_t st, const StiffDots& dots = StiffDots{}) {
   const int inl = stiff_ops_in_lds<T>(h);
   size_t ol, ou, os, ot;
   const int kb = stiff_blocks_per_workgroup(h.nb, sizeof(T) == sizeof(double) && !inl, stiff_mb_fits(h),
@@ -755,11 +783,11 @@ static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T
   if (e0) {                                                                                                     \
     SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB>), dim3(nwg), dim3(kBlockThreads),  \
                                              (uint32_t)lds, st, e0, e1, 0, a, u, y, side, flags, (uint32_t)ol,    \
-                                             (uint32_t)ou, (uint32_t)os, (uint32_t)ot));                          \
+                                             (uint32_t)ou, (uint32_t)os, (uint32_t)ot, dots));                    \
   } else {                                                                                                      \
     SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB>), dim3(nwg), dim3(kBlockThreads), lds, \
                                           st, a, u, y, side, flags, (uint32_t)ol, (uint32_t)ou, (uint32_t)os,      \
-                                          (uint32_t)ot));                                                         \
+                                          (uint32_t)ot, dots));                                                   \
   }
   if (inl) {
     if (a.kb > 1) {
@@ -790,13 +818,13 @@ void launch_stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float
 // Same launches with start/stop events taken from the dispatch itself (no
 // marker packets around the kernel): used to time the kernel inside solves.
 void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, int flags,
-                             hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
-  stiff_launch<double, double>(h, d, u, y, side, flags, e0, e1, st);
+                             hipEvent_t e0, hipEvent_t e1, hipStream_t st, const StiffDots& dots) {
+  stiff_launch<double, double>(h, d, u, y, side, flags, e0, e1, st, dots);
 }
 void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
-                             int gstore, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
-  if (gstore == 2) stiff_launch<float, BF16m>(h, d, u, y, side, flags, e0, e1, st);
-  else stiff_launch<float, float>(h, d, u, y, side, flags, e0, e1, st);
+                             int gstore, hipEvent_t e0, hipEvent_t e1, hipStream_t st, const StiffDots& dots) {
+  if (gstore == 2) stiff_launch<float, BF16m>(h, d, u, y, side, flags, e0, e1, st, dots);
+  else stiff_launch<float, float>(h, d, u, y, side, flags, e0, e1, st, dots);
 }
 
 void launch_sz_mfma(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, hipStream_t st) {

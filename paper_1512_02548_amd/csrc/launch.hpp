@@ -16,6 +16,21 @@ enum { F_MASK_SURF = 1, F_NEG = 2, F_GATE = 4, F_NOFIX = 8 };   // F_NOFIX: elem
 // progress word mirrored to host memory by the Krylov kernels
 enum { PROG_STEPS = 0xffff, PROG_DONE = 1 << 16, PROG_CONV = 1 << 17 };
 
+// Inner products of a stiffness output y with Krylov vectors, done by the
+// stiffness launch itself: each block's part of <y, V_i> (i < nvec) from its
+// own contributions (at a shared line, the value it stores or puts in the
+// side buffer, so no fix-up has to come first), then the blocks' parts added
+// in a fixed order by the last workgroup into out.
+struct StiffDots {
+  const void* V = nullptr;     // V_0 .. V_{nvec-1} (working type), stride n
+  int64_t n = 0;
+  int nvec = 0;                // 0: no products
+  int ldp = 0;
+  double* part = nullptr;      // [blocks][ldp]
+  double* out = nullptr;       // nvec results
+  int32_t* counter = nullptr;  // completion count (zero between launches)
+};
+
 size_t gather_lds_bytes(const TankDev& h, size_t word);
 void launch_coef(const TankDev& h, const TankDev* d, const double* eta, const double* etax, int what, hipStream_t st);
 void launch_gather(const TankDev& h, const TankDev* d, int op, const double* u, double* y, double* side, int flags,
@@ -28,10 +43,12 @@ void launch_stiff_mfma(const TankDev& h, const TankDev* d, const double* u, doub
                        hipStream_t st);
 void launch_stiff_mfma(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
                        int gstore, hipStream_t st);
+// e0, e1 (optional): events stamped by the dispatch; dots: fused inner products
 void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, int flags,
-                             hipEvent_t e0, hipEvent_t e1, hipStream_t st);
+                             hipEvent_t e0, hipEvent_t e1, hipStream_t st, const StiffDots& dots = StiffDots{});
 void launch_stiff_mfma_timed(const TankDev& h, const TankDev* d, const float* u, float* y, float* side, int flags,
-                             int gstore, hipEvent_t e0, hipEvent_t e1, hipStream_t st);
+                             int gstore, hipEvent_t e0, hipEvent_t e1, hipStream_t st,
+                             const StiffDots& dots = StiffDots{});
 void launch_mfma_probe(double* out64, float* out32, hipStream_t st);
 void launch_fixup(const TankDev& h, const TankDev* d, double* y, double* side, int flags, hipStream_t st);
 void launch_fixup(const TankDev& h, const TankDev* d, float* y, float* side, int flags, hipStream_t st);
@@ -62,10 +79,14 @@ void launch_dots(int64_t n, int nvec, const double* X, int64_t ldx, const double
 void launch_dots(int64_t n, int nvec, const float* X, int64_t ldx, const float* w, double* part, int ldp,
                  double* out, int32_t* counter, const KrylovState* gate, hipStream_t st,
                  const TankDev* fixd = nullptr, const float* side = nullptr);
+// With fixd (the tank) and side: w's shared-line contributions are still in
+// `side`; they are added as w is read.
 void launch_orth_givens(int64_t n, int j, const double* V, double* H, int m, double* w, double* part, int ldp,
-                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st);
+                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st,
+                        const TankDev* fixd = nullptr, const double* side = nullptr);
 void launch_orth_givens(int64_t n, int j, const float* V, double* H, int m, float* w, double* part, int ldp,
-                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st);
+                        KrylovState* ks, int32_t* counter, int32_t* status, int32_t* mirror, hipStream_t st,
+                        const TankDev* fixd = nullptr, const float* side = nullptr);
 void launch_scale_next(int64_t n, int j, const double* w, double* V, const double* H, int m, const KrylovState* ks,
                        hipStream_t st);
 void launch_scale_next(int64_t n, int j, const float* w, float* V, const double* H, int m, const KrylovState* ks,
@@ -131,11 +152,18 @@ void launch_sd_b(const BatchArgs& a, const BatchSD& p, int which, VSel rin, VSel
 // gstore as for the single-tank kernel (0 FP64, 1 FP32, 2 bfloat16 factors)
 void launch_stiff_b(const BatchArgs& a, const BatchStage& p, int P, VSel u, VSel y, int flags, int gstore,
                     hipStream_t st);
+// products of the stiffness output w (before its fix-up) with V_0 ..
+// V_{nvec-1} as the single-tank stiffness launch forms them (per stiffness
+// block, over p's items {tank, first block, blocks}), then their sums into
+// H column hcol
+void launch_dots_blocks_b(const BatchArgs& a, const BatchStage& p, const BatchStage& per_tank, int nvec, int hcol,
+                          int f32, hipStream_t st);
 // partial products over p's work items, then their sums in one workgroup per tank
 void launch_dots_b(const BatchArgs& a, const BatchStage& p, const BatchStage& per_tank, int nvec, VSel X, VSel w,
                    int hcol, int sidx, int fix, int gate, int f32, hipStream_t st);
+// fix: w's shared-line contributions are still in the side buffer
 void launch_orth_b(const BatchArgs& a, const BatchStage& p, const BatchStage& per_tank, int j, int f32,
-                   hipStream_t st);
+                   hipStream_t st, int fix = 0);
 void launch_fixup_b(const BatchArgs& a, const BatchStage& p, VSel y, int flags, int f32, hipStream_t st);
 void launch_residual_b(const BatchArgs& a, const BatchStage& p, VSel b, VSel y, VSel r, int f32, hipStream_t st);
 void launch_cycle_start_b(const BatchArgs& a, const BatchStage& per_tank, const BatchStage& vec, int first, int f32,

@@ -1380,22 +1380,28 @@ static void gather_t(sem_mesh* M, const GmresCfg& c, int op, const float* u, flo
 }
 
 static void stiff_timed_launch(sem_mesh* M, const GmresCfg&, const double* u, double* y, double* side, int flags,
-                               hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
-  launch_stiff_mfma_timed(M->hd, M->dtank, u, y, side, flags, e0, e1, st);
+                               hipEvent_t e0, hipEvent_t e1, hipStream_t st, const StiffDots& dots) {
+  launch_stiff_mfma_timed(M->hd, M->dtank, u, y, side, flags, e0, e1, st, dots);
 }
 static void stiff_timed_launch(sem_mesh* M, const GmresCfg& c, const float* u, float* y, float* side, int flags,
-                               hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
-  launch_stiff_mfma_timed(M->hd, M->dtank, u, y, side, flags, c.gstore, e0, e1, st);
+                               hipEvent_t e0, hipEvent_t e1, hipStream_t st, const StiffDots& dots) {
+  launch_stiff_mfma_timed(M->hd, M->dtank, u, y, side, flags, c.gstore, e0, e1, st, dots);
 }
 
 // Stiffness application inside the Krylov loop, bracketed by timing events
 // when enabled (the fix-up of shared lines runs after the end event).
+// dots (matrix-core stiffness only): the inner products fused into the launch
 template <typename T>
 static sem_status stiff_timed(sem_mesh* M, const GmresCfg& cfg, const T* u, T* y, T* side, int flags,
-                              hipStream_t st) {
+                              hipStream_t st, const StiffDots* dots = nullptr) {
   const bool nofix = (flags & F_NOFIX) != 0;   // the caller adds the side buffer itself
   if (!M->kt_on || cfg.op != OP_STIFF) {
-    gather_t(M, cfg, cfg.op, u, y, side, flags, st);
+    if (dots) {
+      stiff_timed_launch(M, cfg, u, y, side, flags, nullptr, nullptr, st, *dots);
+      if (!nofix) launch_fixup(M->hd, M->dtank, y, side, flags, st);
+    } else {
+      gather_t(M, cfg, cfg.op, u, y, side, flags, st);
+    }
     return SEM_OK;
   }
   if (M->kt_used == M->kt_ev.size()) {
@@ -1407,7 +1413,7 @@ static sem_status stiff_timed(sem_mesh* M, const GmresCfg& cfg, const T* u, T* y
   auto& e = M->kt_ev[M->kt_used++];
   if (M->hd.use_mfma) {
     // events stamped by the kernel's own dispatch
-    stiff_timed_launch(M, cfg, u, y, side, flags, e.first, e.second, st);
+    stiff_timed_launch(M, cfg, u, y, side, flags, e.first, e.second, st, dots ? *dots : StiffDots{});
   } else {
     HIPCHK(hipEventRecord(e.first, st));
     gather_t(M, cfg, cfg.op, u, y, side, flags | F_NOFIX, st);
@@ -1485,14 +1491,20 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       T* Zj = B.Z + (size_t)j * n;
       if (fused && j > 0) launch_sd(h, d, 0, B.w, Zj, 1, st, hnorm + (j - 1), Vj);
       else gather_t(M, cfg, cfg.pre, Vj, Zj, B.side, gflags, st);
+      double* Hcol = h.H + (size_t)j * (m + 1);
+      // the matrix-core stiffness launch also forms the products with V_0..V_j
+      // (from each block's own contributions); the shared-line fix-up of w is
+      // then done as the orthogonalisation reads it, otherwise inside the
+      // separate products
+      const bool fdots = h.use_mfma && cfg.op == OP_STIFF;
+      const StiffDots dots{B.V, n, j + 1, ldp, h.part, Hcol, cnt};
       {
-        // the operator's shared-line fix-up is done inside the products below
-        sem_status e = stiff_timed(M, cfg, Zj, B.w, B.side, gflags | F_NOFIX, st);
+        sem_status e = stiff_timed(M, cfg, Zj, B.w, B.side, gflags | F_NOFIX, st, fdots ? &dots : nullptr);
         if (e) return e;
       }
-      double* Hcol = h.H + (size_t)j * (m + 1);
-      launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st, d, B.side);
-      launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st);
+      if (!fdots) launch_dots(n, j + 1, B.V, n, B.w, h.part, ldp, Hcol, cnt, h.ks, st, d, B.side);
+      launch_orth_givens(n, j, B.V, h.H, m, B.w, h.part, ldp, h.ks, cnt, h.status, M->prog_dev, st,
+                         fdots ? d : nullptr, fdots ? B.side : nullptr);
       if (!fused) launch_scale_next(n, j, B.w, B.V, h.H, m, h.ks, st);
       // wait while the device is more than `ahead` steps behind: spin on the
       // progress word; ask the runtime whether the queue drained only every
