@@ -607,11 +607,29 @@ __device__ void givens_update(KrylovState* __restrict__ ks, double* __restrict__
   double* col = H + (size_t)j * (m + 1);
   double hn = sqrt(fmax(hnorm2, 0.0));
   col[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
+  // the previous rotations applied to the column in order, the running entry
+  // in a register; their operands requested eight at a time from clamped
+  // addresses (one round trip per eight rotations, not one per rotation)
+  double ci = col[0];
+  for (int i0 = 0; i0 < j; i0 += 8) {
+    double c8[8], s8[8], h8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = min(i0 + u, j - 1);
+      c8[u] = cs[i];
+      s8[u] = sn[i];
+      h8[u] = col[i + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i0 + u < j) {
+        const double t = c8[u] * ci + s8[u] * h8[u];
+        ci = -s8[u] * ci + c8[u] * h8[u];
+        col[i0 + u] = t;
+      }
+    }
   }
+  col[j] = ci;
   double den = hypot(col[j], col[j + 1]);
   if (!(den > 0.0) || !finite(den)) {
     atomicOr(status, finite(den) ? ST_BREAKDOWN : ST_NONFINITE);
