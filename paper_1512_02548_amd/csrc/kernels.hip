@@ -435,21 +435,50 @@ __device__ inline double* progress_scalars(int32_t* mirror) {
 }
 
 
+// The tank sizes the fix-up needs, read once into registers (a loop that
+// stores to a vector would otherwise read them again after every store).
+struct LineFix {
+  int32_t nc = 1, nl = 0, nx = 0, cb = 1, nb = 0, periodic = 0;
+  LineFix() = default;
+  __device__ explicit LineFix(const TankDev& d)
+      : nc(d.nc), nl(d.nl), nx(d.nx), cb(d.cb), nb(d.nb), periodic(d.periodic) {}
+};
+
+// Where node i's shared-line contribution is: the side-buffer index (0
+// when there is none) and whether it is added (a line shared by two blocks)
+// or is the value (the wall line, which has one contribution).  Selects
+// only, no branch.
+__device__ inline void fix_index(const LineFix& f, int64_t i, int* sidx, bool* add, bool* wall) {
+  const int c = (int)(i / f.nc);
+  const int ql = (int)(i - (int64_t)c * f.nc);
+  const bool line = ql < f.nl;
+  const bool wl = line && c == f.nx;
+  const bool first = line && !wl && c % f.cb == 0;
+  const int blf = c > 0 ? c / f.cb - 1 : (f.periodic ? f.nb - 1 : -1);
+  const int bl = wl ? f.nb - 1 : (first ? blf : -1);
+  *sidx = (bl >= 0 ? bl : 0) * f.nl + (line ? ql : 0);
+  *add = bl >= 0 && !wl;
+  *wall = wl;
+}
+// the fixed-up value from the loaded y[i] and side[sidx]
+template <typename T>
+__device__ inline T fix_combine(T v, T sv, bool add, bool wall) {
+  const T sum = v + (add ? sv : T(0));   // (adding zero leaves v)
+  return wall ? sv : sum;
+}
 // y[i] of an element-kernel output with its shared-line contribution from
 // the side buffer added (the fix-up pass, done by the consumer; the same
-// addition as the separate pass)
+// addition as the separate pass).  Both loads are issued unconditionally.
+template <typename T>
+__device__ inline T fixed_value(const LineFix& f, const T* __restrict__ y, const T* __restrict__ side, int64_t i) {
+  int sidx;
+  bool add, wall;
+  fix_index(f, i, &sidx, &add, &wall);
+  return fix_combine<T>(y[i], side[sidx], add, wall);
+}
 template <typename T>
 __device__ inline T fixed_value(const TankDev& d, const T* __restrict__ y, const T* __restrict__ side, int64_t i) {
-  const int64_t c = i / d.nc;
-  const int ql = (int)(i - c * d.nc);
-  T v = y[i];
-  if (ql >= d.nl) return v;
-  if (c == d.nx) return side[(size_t)(d.nb - 1) * d.nl + ql];   // the wall line has one contribution
-  if (c % d.cb == 0) {
-    const int bl = c > 0 ? (int)(c / d.cb) - 1 : (d.periodic ? d.nb - 1 : -1);
-    if (bl >= 0) v += side[(size_t)bl * d.nl + ql];
-  }
-  return v;
+  return fixed_value<T>(LineFix(d), y, side, i);
 }
 
 // Workgroup bx: partial products of its chunk into part[bx].  Shared by the
@@ -534,35 +563,74 @@ k_dots_fused(int64_t n, int nvec, const T* __restrict__ X, int64_t ldx, T* __res
 
 // w' = w - sum_{i<=j} h_i V_i, and this workgroup's part of ||w'||^2
 // (fixd: w is an operator output whose shared-line contributions are still
-// in the side buffer, added as it is read)
+// in the side buffer, added as it is read).  A thread takes its entries two
+// at a time, their loads requested together (clamped addresses); its sum
+// runs over its entries in order.
+template <typename T, bool FIX>
+__device__ __forceinline__ void orth_partial_t(int64_t n, int j, const T* __restrict__ V,
+                                               const double* __restrict__ Hbase, int m, T* __restrict__ w,
+                                               double* __restrict__ part, int ldp, int64_t chunk, int bx,
+                                               const TankDev* __restrict__ fixd, const T* __restrict__ side) {
+  constexpr int U = 2;
+  __shared__ double red[4];
+  const double* hcol = Hbase + (size_t)j * (m + 1);
+  const int64_t lo = (int64_t)bx * chunk, hi = min(lo + chunk, n);
+  constexpr bool fix = FIX;
+  const LineFix lf = FIX ? LineFix(*fixd) : LineFix();
+  double sacc = 0;
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (int64_t)U * blockDim.x) {
+    // the entries' indices, then all their loads, then the arithmetic
+    int64_t ii[U];
+    int sidx[U];
+    bool add[U], wall[U];
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      ii[e] = min(i0 + (int64_t)e * blockDim.x, hi - 1);
+      if constexpr (fix) fix_index(lf, ii[e], &sidx[e], &add[e], &wall[e]);
+    }
+    T wv[U], sv[U];
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      wv[e] = w[ii[e]];
+      if constexpr (fix) sv[e] = side[sidx[e]];
+    }
+    double v[U];
+#pragma unroll
+    for (int e = 0; e < U; ++e) v[e] = fix ? (double)fix_combine<T>(wv[e], sv[e], add[e], wall[e]) : (double)wv[e];
+    for (int k0 = 0; k0 <= j; k0 += 8) {
+      T vv[U][8];
+#pragma unroll
+      for (int e = 0; e < U; ++e)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vv[e][u] = V[(int64_t)min(k0 + u, j) * n + ii[e]];
+#pragma unroll
+      for (int e = 0; e < U; ++e)
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (k0 + u <= j) v[e] -= hcol[k0 + u] * (double)vv[e][u];
+    }
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      if (i0 + (int64_t)e * blockDim.x < hi) {
+        const T vt = T(v[e]);
+        w[ii[e]] = vt;
+        sacc += (double)vt * (double)vt;
+      }
+    }
+  }
+  sacc = wave_sum(sacc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sacc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)bx * ldp] = ((red[0] + red[1]) + red[2]) + red[3];
+}
 template <typename T>
 __device__ __forceinline__ void orth_partial(int64_t n, int j, const T* __restrict__ V,
                                              const double* __restrict__ Hbase, int m, T* __restrict__ w,
                                              double* __restrict__ part, int ldp, int64_t chunk, int bx,
                                              const TankDev* __restrict__ fixd = nullptr,
                                              const T* __restrict__ side = nullptr) {
-  __shared__ double red[4];
-  const double* hcol = Hbase + (size_t)j * (m + 1);
-  const int64_t lo = (int64_t)bx * chunk, hi = min(lo + chunk, n);
-  double sacc = 0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double v = fixd ? (double)fixed_value<T>(*fixd, w, side, i) : (double)w[i];
-    for (int k0 = 0; k0 <= j; k0 += 8) {
-      T vv[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) vv[u] = V[(int64_t)min(k0 + u, j) * n + i];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (k0 + u <= j) v -= hcol[k0 + u] * (double)vv[u];
-    }
-    T vt = T(v);
-    w[i] = vt;
-    sacc += (double)vt * (double)vt;
-  }
-  sacc = wave_sum(sacc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sacc;
-  __syncthreads();
-  if (threadIdx.x == 0) part[(size_t)bx * ldp] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (fixd) orth_partial_t<T, true>(n, j, V, Hbase, m, w, part, ldp, chunk, bx, fixd, side);
+  else orth_partial_t<T, false>(n, j, V, Hbase, m, w, part, ldp, chunk, bx, fixd, side);
 }
 
 // ||w'||^2 from nblk partials (first wave), then the Givens update of column j

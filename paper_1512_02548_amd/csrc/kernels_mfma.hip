@@ -592,7 +592,9 @@ __device__ inline void stiff_block_dots(const StiffArgs<T>& a, const T* __restri
   block_dots_part<T>(a.cb, a.nx, a.nc, a.nl, a.periodic, y, side, V, n, nvec, part, ldp, b);
 }
 
-template <int P, typename T, typename GS, bool OPS_LDS, bool MB>
+// DOTS: the variant with the fused inner products (dt), a kernel of its own
+// (the plain apply keeps its registers, and a profile tells the two apart)
+template <int P, typename T, typename GS, bool OPS_LDS, bool MB, bool DOTS>
 __global__ void __launch_bounds__(kBlockThreads)
 k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T* __restrict__ side, int flags,
              uint32_t o_loc, uint32_t o_u, uint32_t o_st, uint32_t o_tab, StiffDots dt) {
@@ -600,7 +602,7 @@ k_stiff_mfma(const StiffArgs<T> a, const T* __restrict__ u, T* __restrict__ y, T
   const int b0 = MB ? (int)blockIdx.x * a.kb : (int)blockIdx.x;
   if constexpr (MB) stiff_body_mb<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, o_tab, b0, a.kb);
   else stiff_body<P, T, GS, OPS_LDS>(a, u, y, side, flags, o_loc, o_u, o_st, o_tab, b0);
-  if (dt.nvec <= 0) return;
+  if constexpr (!DOTS) return;
   // the inner products with the Krylov vectors: the blocks' parts, then their
   // sum in the last workgroup
   const int nbt = (a.nx + a.cb - 1) / a.cb;
@@ -778,16 +780,23 @@ static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T
   StiffArgs<T> a = stiff_args<T>(h, G, opf, inl);
   a.kb = kb;
   const int nwg = (h.nb + a.kb - 1) / a.kb;
-#define SEM_SL(INL, MB)                                                                                          \
-  SEM_MP_SWITCH(h.P, allow_lds(k_stiff_mfma<PP, T, GS, INL, MB>, lds));                                         \
+#define SEM_SL3(INL, MB, DT)                                                                                     \
+  SEM_MP_SWITCH(h.P, allow_lds(k_stiff_mfma<PP, T, GS, INL, MB, DT>, lds));                                     \
   if (e0) {                                                                                                     \
-    SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB>), dim3(nwg), dim3(kBlockThreads),  \
-                                             (uint32_t)lds, st, e0, e1, 0, a, u, y, side, flags, (uint32_t)ol,    \
-                                             (uint32_t)ou, (uint32_t)os, (uint32_t)ot, dots));                    \
+    SEM_MP_SWITCH(h.P, hipExtLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB, DT>), dim3(nwg),                   \
+                                             dim3(kBlockThreads), (uint32_t)lds, st, e0, e1, 0, a, u, y, side,    \
+                                             flags, (uint32_t)ol, (uint32_t)ou, (uint32_t)os, (uint32_t)ot,       \
+                                             dots));                                                              \
   } else {                                                                                                      \
-    SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB>), dim3(nwg), dim3(kBlockThreads), lds, \
-                                          st, a, u, y, side, flags, (uint32_t)ol, (uint32_t)ou, (uint32_t)os,      \
+    SEM_MP_SWITCH(h.P, hipLaunchKernelGGL((k_stiff_mfma<PP, T, GS, INL, MB, DT>), dim3(nwg), dim3(kBlockThreads), \
+                                          lds, st, a, u, y, side, flags, (uint32_t)ol, (uint32_t)ou, (uint32_t)os, \
                                           (uint32_t)ot, dots));                                                   \
+  }
+#define SEM_SL(INL, MB)      \
+  if (dots.nvec > 0) {       \
+    SEM_SL3(INL, MB, true)   \
+  } else {                   \
+    SEM_SL3(INL, MB, false)  \
   }
   if (inl) {
     if (a.kb > 1) {
@@ -803,6 +812,7 @@ static void stiff_launch(const TankDev& h, const TankDev* d, const T* u, T* y, T
     }
   }
 #undef SEM_SL
+#undef SEM_SL3
 }
 
 void launch_stiff_mfma(const TankDev& h, const TankDev* d, const double* u, double* y, double* side, int flags,

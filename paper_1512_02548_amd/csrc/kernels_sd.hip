@@ -641,9 +641,8 @@ __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& 
 // M-tile per wave, the full K range (2q) in order; the lines of the group's
 // columns and the next one come from XL through LDS.  Workgroups of row 0
 // also write the line values (and the wall line).  B: a batched launch
-// (wide tiles, sd_shape_b).  KD: K-steps of the in-workgroup inverse
-// transform whose loads are requested together.
-template <typename T, bool B, int KD = 8>
+// (wide tiles, sd_shape_b).
+template <typename T, bool B>
 __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __restrict__ z, T* __restrict__ vout,
                                              int bx, int by) {
   using MF = Mfma<T>;
@@ -668,7 +667,7 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
     const int cr = (c0 + 16 * lt + col) % nx, pr = grp & 1, jb = 16 * jt + col;
     const int KSd = (2 * nx + 3) / 4;
     V4 acc = V4{0, 0, 0, 0};
-    constexpr int kD = KD;
+    constexpr int kD = 8;
     // twiddle index (cr k) mod nx, k = 2 s + grp / 2: advances by 2 cr per K-step
     const int step = (2 * cr) % nx;
     int mm = (cr * (grp >> 1)) % nx;
@@ -751,17 +750,7 @@ __global__ void __launch_bounds__(kBlockThreads)
 k_sd_back(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate, T* __restrict__ vout) {
   const TankDev& d = *td;
   if (gate && d.ks->done) return;
-  sd_back_body<T, false, 8>(d, which, z, vout, (int)blockIdx.x, (int)blockIdx.y);
-}
-// Tanks that form their line values in the workgroup, launched alone (a few
-// dozen workgroups: registers matter more than occupancy): the whole inverse
-// transform of a 64-column tank in one request
-template <typename T>
-__global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(1, 2)))
-k_sd_back_small(const TankDev* __restrict__ td, int which, T* __restrict__ z, int gate, T* __restrict__ vout) {
-  const TankDev& d = *td;
-  if (gate && d.ks->done) return;
-  sd_back_body<T, false, 32>(d, which, z, vout, (int)blockIdx.x, (int)blockIdx.y);
+  sd_back_body<T, false>(d, which, z, vout, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // Sum of a workgroup's values in a fixed order (wave butterflies, then the
@@ -1394,11 +1383,7 @@ static void sd_t(const TankDev& h, const TankDev* d, int which, const T* u, T* y
   } else if (!sd_back_dft(h.nx, sd.q, sd.fft_n1, sd.nMT3)) {
     hipLaunchKernelGGL(k_sd_idft<T>, dim3(ct, (sd.q + 15) / 16), dim3(kBlockThreads), 0, st, d, which, gate);
   }
-  if (sd_back_dft(h.nx, sd.q, sd.fft_n1, sd.nMT3))
-    hipLaunchKernelGGL(k_sd_back_small<T>, dim3(g.bx, g.by), dim3(kBlockThreads), lds.back, st, d, which, y, gate,
-                       vout);
-  else
-    hipLaunchKernelGGL(k_sd_back<T>, dim3(g.bx, g.by), dim3(kBlockThreads), lds.back, st, d, which, y, gate, vout);
+  hipLaunchKernelGGL(k_sd_back<T>, dim3(g.bx, g.by), dim3(kBlockThreads), lds.back, st, d, which, y, gate, vout);
 }
 
 void launch_sd(const TankDev& h, const TankDev* d, int which, const double* u, double* y, int gate, hipStream_t st,

@@ -81,22 +81,34 @@ __device__ inline void block_dots_part(int cb, int nx, int nc, int nl, int perio
   const SEM_GLOBAL T* yg = gview(y);
   const SEM_GLOBAL T* sg = gview(side);
   const SEM_GLOBAL T* vg = gview(V);
-  // eight vectors per pass; every load from a clamped address
+  // eight vectors per pass, a thread's nodes two at a time (their loads
+  // requested together, from clamped addresses; the sums run over its nodes
+  // in order)
+  constexpr int U = 2;
   for (int k0 = 0; k0 < nvec; k0 += 8) {
     double sacc[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) sacc[u] = 0;
-    for (int q = threadIdx.x; q < nq; q += kBlockThreads) {
-      const bool own = q < nown;
-      const T yo = yg[obase + min(q, nown - 1)];
-      const T ys = sg[(size_t)b * nl + max(q - nown, 0)];
-      const int64_t gi = own ? obase + q : rbase + (q - nown);
-      T xv[8];
+    for (int q0 = threadIdx.x; q0 < nq; q0 += U * kBlockThreads) {
+      T yv[U], xv[U][8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) xv[u] = vg[(int64_t)min(k0 + u, nvec - 1) * n + gi];
-      const double yv = (double)(own ? yo : ys);
+      for (int e = 0; e < U; ++e) {
+        const int q = min(q0 + e * kBlockThreads, nq - 1);
+        const bool own = q < nown;
+        const T yo = yg[obase + min(q, nown - 1)];
+        const T ys = sg[(size_t)b * nl + max(q - nown, 0)];
+        const int64_t gi = own ? obase + q : rbase + (q - nown);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) sacc[u] += (double)xv[u] * yv;
+        for (int u = 0; u < 8; ++u) xv[e][u] = vg[(int64_t)min(k0 + u, nvec - 1) * n + gi];
+        yv[e] = own ? yo : ys;
+      }
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        if (q0 + e * kBlockThreads < nq) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sacc[u] += (double)xv[e][u] * (double)yv[e];
+        }
+      }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {

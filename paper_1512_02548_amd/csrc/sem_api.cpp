@@ -1496,7 +1496,9 @@ static sem_status gmres(sem_mesh* M, const GmresCfg& cfg, const Buf& B, T* x, co
       // (from each block's own contributions); the shared-line fix-up of w is
       // then done as the orthogonalisation reads it, otherwise inside the
       // separate products
-      const bool fdots = h.use_mfma && cfg.op == OP_STIFF;
+      // (not while the stiffness launches are timed: the timing is the plain
+      // apply's)
+      const bool fdots = h.use_mfma && cfg.op == OP_STIFF && !M->kt_on;
       const StiffDots dots{B.V, n, j + 1, ldp, h.part, Hcol, cnt};
       {
         sem_status e = stiff_timed(M, cfg, Zj, B.w, B.side, gflags | F_NOFIX, st, fdots ? &dots : nullptr);
