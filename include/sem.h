@@ -319,8 +319,10 @@ sem_status sem_selftest_mfma(sem_mesh* mesh, double* max_err_host, double* raw_h
  * launch of the GMRES iterations of sem_laplace_solve / sem_rk4_step (and the
  * batch step), in whatever precision the iterations run, is bracketed by HIP
  * events on the solve's stream; launches queued after convergence, which
- * return at once, are not counted.  enable = 1 starts (and clears) the
- * accumulation, 0 stops it.  sem_kernel_timing_read returns the number of
+ * return at once, are not counted.  While enabled the Arnoldi steps use the
+ * plain apply with a separate inner-product launch (otherwise the products
+ * are fused into the stiffness launch), so that the timing is the apply's
+ * alone.  enable = 1 starts (and clears) the accumulation, 0 stops it.  sem_kernel_timing_read returns the number of
  * counted launches and their summed duration in milliseconds (HOST
  * pointers).  Timing adds event records to the stream; leave it off in
  * production. */
