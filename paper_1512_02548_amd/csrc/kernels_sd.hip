@@ -503,11 +503,14 @@ __device__ __forceinline__ void sd_idft_body(const TankDev& d, int which, int bx
   const SEM_GLOBAL double* twg = gview(d.twid);
   const SEM_GLOBAL double* xhg = gview(sd.XH);
   const int jc = min(j, q - 1);
-  for (int s0 = wv; s0 < KS; s0 += 4 * kWaves) {
-    double ta[4], tb[4];
-    bool kv[4];
+  // kIU K-steps of a wave per request (the kernel's registers leave room:
+  // fewer round trips over the long tanks' modes)
+  constexpr int kIU = 8;
+  for (int s0 = wv; s0 < KS; s0 += kIU * kWaves) {
+    double ta[kIU], tb[kIU];
+    bool kv[kIU];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kIU; ++u) {
       const int s = s0 + u * kWaves;
       const int k = 2 * s + (grp >> 1);
       kv[u] = s < KS && k < nx;
@@ -516,7 +519,7 @@ __device__ __forceinline__ void sd_idft_body(const TankDev& d, int which, int bx
       mm = wrap_add(mm, step, nx);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = MF::op(kv[u] ? T(ta[u]) : T(0), (kv[u] && j < q) ? T(tb[u]) : T(0), acc);
+    for (int u = 0; u < kIU; ++u) acc = MF::op(kv[u] ? T(ta[u]) : T(0), (kv[u] && j < q) ? T(tb[u]) : T(0), acc);
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) red[wv][MF::row(v, grp) * 16 + col] = (double)acc[v];
