@@ -775,36 +775,60 @@ __device__ __forceinline__ void sd_wall_lines_body(const TankDev& d, int which, 
   const int q = sd.q, nx = d.nx;
   const int ln = bx / q, j = bx - ln * q;
   const int c = ln == 0 ? nx - 1 : 0;
+  const SEM_GLOBAL double* xh = gview(sd.XH);
+  const SEM_GLOBAL double* tw = gview(d.twid);
+  // a thread's modes k = tid, tid + 256, ... four at a time: their loads
+  // requested together (clamped indices), the sum in order
+  constexpr int kU = 4;
   double acc = 0;
-  for (int k = threadIdx.x; k < nx; k += blockDim.x) {
-    const int mm = (int)(((int64_t)k * c) % nx);
-    const double hr = sd.XH[((size_t)k * q + j) * 2], hi = sd.XH[((size_t)k * q + j) * 2 + 1];
-    acc += hr * d.twid[2 * mm] + hi * d.twid[2 * mm + 1];
+  for (int k0 = threadIdx.x; k0 < nx; k0 += kU * kBlockThreads) {
+    double hr[kU], hi[kU], tr[kU], ti[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = min(k0 + u * kBlockThreads, nx - 1);
+      const int mm = (int)(((int64_t)k * c) % nx);
+      hr[u] = xh[((size_t)k * q + j) * 2];
+      hi[u] = xh[((size_t)k * q + j) * 2 + 1];
+      tr[u] = tw[2 * mm];
+      ti[u] = tw[2 * mm + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u * kBlockThreads < nx) acc += hr[u] * tr[u] + hi[u] * ti[u];
   }
   acc = block_total(acc);
   if (threadIdx.x == 0) sd.WP[bx] = acc / nx;
 }
 
 // Wall correction, second part (a workgroup per component a of v):
-// v_a = W_a . [r_wall; x_{nx-1}; x_0; y_I(nx-1)]
+// v_a = W_a . [r_wall; x_{nx-1}; x_0; y_I(nx-1)]  (the three sources loaded
+// from clamped indices and selected: no branch around a load)
 template <typename T>
-__device__ __forceinline__ void sd_wall_body(const TankDev& d, int which, const T* __restrict__ r,
+__device__ __forceinline__ void sd_wall_body(const TankDev& d, const SDData& sd, const T* __restrict__ r,
                                              const double* __restrict__ nscale, int bx, int by) {
-  const SDData& sd = d.sd[which];
   const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc;
   const int np = 3 * q + nI;
   const double rs = sd_in_scale(nscale);
-  const double* row = sd.Wv + (size_t)bx * np;
+  const SEM_GLOBAL double* row = gview(sd.Wv) + (size_t)bx * np;
+  const SEM_GLOBAL T* rg = gview(r);
+  const SEM_GLOBAL double* wp = gview(sd.WP);
+  const SEM_GLOBAL double* yi = gview(sd.yI);
   double acc = 0;
   for (int p = threadIdx.x; p < np; p += blockDim.x) {
-    double in;
-    if (p < q) in = (double)r[(int64_t)nx * nc + p] * rs;
-    else if (p < 3 * q) in = sd.WP[p - q];
-    else in = sd.yI[(size_t)(nx - 1) * nI + p - 3 * q];
-    acc += row[p] * in;
+    const double w = row[p];
+    const double a = (double)rg[(int64_t)nx * nc + min(p, q - 1)] * rs;
+    const double b = wp[min(max(p - q, 0), 2 * q - 1)];
+    const double c = yi[(size_t)(nx - 1) * nI + max(p - 3 * q, 0)];
+    const double in = p < q ? a : (p < 3 * q ? b : c);
+    acc += w * in;
   }
   acc = block_total(acc);
   if (threadIdx.x == 0) sd.vbuf[bx] = acc;
+}
+template <typename T>
+__device__ __forceinline__ void sd_wall_body(const TankDev& d, int which, const T* __restrict__ r,
+                                             const double* __restrict__ nscale, int bx, int by) {
+  sd_wall_body<T>(d, d.sd[which], r, nscale, bx, by);
 }
 
 template <typename T>

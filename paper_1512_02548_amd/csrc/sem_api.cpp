@@ -1024,7 +1024,7 @@ extern "C" sem_status sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out)
   if (!desc || !out) return fail(SEM_E_INVAL, "null argument");
   *out = nullptr;
   if (desc->nx < 1 || desc->nz < 1) return fail(SEM_E_INVAL, "nx and nz must be >= 1");
-  if (desc->nz > 256) return fail(SEM_E_INVAL, "nz must be <= 256");
+  if (desc->nz > kMaxLayers) return fail(SEM_E_INVAL, "nz must be <= 256");
   if (desc->order < 1 || desc->order > kMaxOrder) return fail(SEM_E_INVAL, "order must be in 1..8");
   if (!(desc->length > 0)) return fail(SEM_E_INVAL, "length must be positive");
   if (desc->periodic && desc->nx < 2) return fail(SEM_E_INVAL, "a periodic tank needs nx >= 2");

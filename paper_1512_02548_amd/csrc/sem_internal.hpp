@@ -12,6 +12,7 @@ constexpr int kMaxContrib = 8;      // element contributions to one column-local
 constexpr int kBlockThreads = 256;
 constexpr int kMaxRestart = 64;     // GMRES restart length limit
 constexpr int kMaxVec = kMaxRestart + 1;
+constexpr int kMaxLayers = 256;     // sigma layers (nz) at most
 // Fourier modes per workgroup of the direct-transform mode solves: 8 for
 // short tanks (more workgroups), 16 from nx > 128 on (full 16-row MFMA tiles,
 // each workgroup's pass over the columns shared by more modes)
