@@ -109,6 +109,47 @@ def test_lockstep_laplace_equals_single(prec, rtol):
         assert np.array_equal(o.cpu().numpy(), r)
 
 
+def wide_specs():
+    """Eighth-order, eight-layer tanks long enough that their own launch of
+    the condensation and back-substitution does not split K (nx = 456: one
+    N-tile per workgroup; nx = 904: two), beside a short one that does: the
+    batched launch runs all three as wide tiles (the split one through four
+    accumulator chains)."""
+    specs = wl.batch_tank_specs(count=3, steps=3, bar_fraction=0.0, seed=777)
+    for s, nx in zip(specs, [456, 904, 40]):
+        s.nx, s.nz, s.P = nx, 8, 8
+        s.params["mwav"] = max(1, nx // 8)
+        s.length = s.params["mwav"] * 2 * np.pi / s.params["k"]
+    return specs
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lockstep_wide_tiles_equal_single(prec):
+    """Batched exact-inverse products as wide tiles give each tank's own
+    launch bit for bit, for tanks whose own launch splits K and for tanks
+    whose own launch takes one or two N-tiles per workgroup."""
+    import torch
+    from paper_1512_02548_amd import lib
+    tanks = [make_tank(s) for s in wide_specs()]
+    opts = lib.default_opts(rtol=1e-10, max_iter=4000, prec=prec, inner_rtol=1e-3, max_refine=60)
+    exs = [surface_gradient(t) for t in tanks]
+    single, its = [], []
+    for t, ex in zip(tanks, exs):
+        phi = torch.zeros(t["mesh"].n, dtype=torch.float64, device="cuda")
+        st = t["mesh"].laplace_solve(t["eta"], ex, t["phi"], phi, opts)
+        its.append(st["iters"])
+        single.append(phi.cpu().numpy())
+    outs = [torch.full((t["mesh"].n,), np.nan, dtype=torch.float64, device="cuda") for t in tanks]
+    b = lib.Batch([t["mesh"] for t in tanks], 0)
+    code, status, iters = b.laplace_solve([t["eta"] for t in tanks], exs, [t["phi"] for t in tanks], outs,
+                                          opts=opts)
+    torch.cuda.synchronize()
+    assert code == 0 and all(s == 0 for s in status), status
+    assert list(iters) == its
+    for o, s in zip(outs, single):
+        assert np.array_equal(o.cpu().numpy(), s)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_lockstep_several_blocks_per_workgroup(prec, monkeypatch):
     """Batched stiffness launches that run several blocks per workgroup
