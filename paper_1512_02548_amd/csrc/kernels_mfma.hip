@@ -278,7 +278,12 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            g[c][mt][v] = GLoad<T, GS>::at(a.G, gbase + (int64_t)c * NpP * 16 + (mt * 16 + v * 4) * 16 + lane);
+            // (a group whose four rows are all past the element's nodes is
+            // padding and not read: FP64 groups hold rows 16 mt + 4 v + 0..3,
+            // FP32 groups rows 16 mt + v + 0, 4, 8, 12)
+            g[c][mt][v] = mt * 16 + (sizeof(T) == sizeof(double) ? 4 * v : v) < Np
+                              ? GLoad<T, GS>::at(a.G, gbase + (int64_t)c * NpP * 16 + (mt * 16 + v * 4) * 16 + lane)
+                              : T(0);
     }
   };
   // prefetching holds the factors live across stage 1; FP64 with three
@@ -466,7 +471,12 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            g[c][mt][v] = GLoad<T, GS>::at(a.G, gbase + (int64_t)c * NpP * 16 + (mt * 16 + v * 4) * 16 + lane);
+            // (a group whose four rows are all past the element's nodes is
+            // padding and not read: FP64 groups hold rows 16 mt + 4 v + 0..3,
+            // FP32 groups rows 16 mt + v + 0, 4, 8, 12)
+            g[c][mt][v] = mt * 16 + (sizeof(T) == sizeof(double) ? 4 * v : v) < Np
+                              ? GLoad<T, GS>::at(a.G, gbase + (int64_t)c * NpP * 16 + (mt * 16 + v * 4) * 16 + lane)
+                              : T(0);
     }
   };
   // a wavefront's tile of block b, clamped to the block's last one (the
