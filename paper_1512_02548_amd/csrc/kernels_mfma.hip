@@ -119,30 +119,6 @@ __host__ __device__ inline bool stiff_mb_fits(const TankDev& h) {
   return h.T <= kBlockThreads / 64 && (int64_t)h.cb * h.nc + h.nl <= (int64_t)stiff_u_regs(h.P) * kBlockThreads;
 }
 
-// The input region of the block of columns c0 .. c0 + cbb - 1 into LDS: its
-// own nodes and the first line of the next column (the wall line at a wall,
-// line 0 of a periodic tank).  Four loads per thread are issued together,
-// from clamped addresses, before any of them is stored.
-template <typename T>
-__device__ __forceinline__ void stage_region(const StiffArgs<T>& a, const T* __restrict__ u, T* ureg, int c0,
-                                             int cbb) {
-  const int nc = a.nc, nreg = cbb * nc + a.nl;
-  const int64_t rbase = (c0 + cbb < a.nx) ? (int64_t)(c0 + cbb) * nc : (a.periodic ? 0 : (int64_t)a.nx * nc);
-  const SEM_GLOBAL T* ug = gview(u);
-  for (int q0 = threadIdx.x; q0 < nreg; q0 += 4 * kBlockThreads) {
-    T v[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = min(q0 + j * kBlockThreads, nreg - 1);
-      const int lc = q / nc, ql = q - lc * nc;
-      v[j] = ug[(lc < cbb) ? (int64_t)(c0 + lc) * nc + ql : rbase + ql];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (q0 + j * kBlockThreads < nreg) ureg[q0 + j * kBlockThreads] = v[j];
-  }
-}
-
 // Node sums of block b (columns c0 .. c0 + cbb - 1) in a fixed order, the
 // same contributions in the same order as the reference kernel's table; the
 // right line's sum over the block's last column goes to the side buffer.
@@ -204,15 +180,80 @@ __device__ __forceinline__ void node_sums_packed(const T* st3, T* __restrict__ y
   }
 }
 
-// the element table and the packed node-sum table into LDS
-template <typename T>
-__device__ __forceinline__ void stage_tables(const StiffArgs<T>& a, int NpP, int32_t* lloc, u32x4* tent4,
-                                             uint16_t* tcm) {
-  for (int i = threadIdx.x; i < 2 * a.nz * NpP; i += kBlockThreads) lloc[i] = gview(a.elem_loc)[i];
-  for (int ql = threadIdx.x; ql < a.nc; ql += kBlockThreads) {
-    tent4[ql] = ((const SEM_GLOBAL u32x4*)gview(a.acc_pk))[ql];
-    tcm[ql] = gview(a.acc_cm)[ql];
+// A workgroup's staging into LDS, every global load requested before any
+// store (one round trip, not one per table): the four operators (OPS_LDS),
+// the element table, the packed node-sum table and, KU > 0, the input
+// region of columns c0 .. c0 + cbb - 1 (their own nodes and the first line
+// of the next column: the wall line at a wall, line 0 of a periodic tank)
+// from clamped addresses; the first
+// kStageRegs entries per thread of each table and KU of the region come
+// through registers, any rest (deeper tanks) in a loop after them.
+constexpr int kStageRegs = 2;
+template <int NpP, int KU, bool OPS_LDS, typename T>
+__device__ __forceinline__ void stage_block(const StiffArgs<T>& a, const T* __restrict__ u, T* lop, int32_t* lloc,
+                                            u32x4* tent4, uint16_t* tcm, T* ureg, int c0, int cbb) {
+  const int tid = threadIdx.x;
+  constexpr int kVec = 16 / sizeof(T);
+  typedef double dv2 __attribute__((ext_vector_type(2)));
+  using V = typename std::conditional<sizeof(T) == 8, dv2, f4>::type;
+  static_assert((4 * NpP * NpP / kVec) % kBlockThreads == 0, "whole operator fragments per thread");
+  constexpr int KO = OPS_LDS ? 4 * NpP * NpP / kVec / kBlockThreads : 0;
+  V ov[KO > 0 ? KO : 1];
+  if constexpr (OPS_LDS) {
+    const SEM_GLOBAL V* src = (const SEM_GLOBAL V*)gview(a.opf);
+#pragma unroll
+    for (int k = 0; k < KO; ++k) ov[k] = src[tid + k * kBlockThreads];
   }
+  const int nloc = 2 * a.nz * NpP, nc = a.nc;
+  int32_t lv[kStageRegs];
+  u32x4 tv[kStageRegs];
+  uint16_t cv[kStageRegs];
+#pragma unroll
+  for (int k = 0; k < kStageRegs; ++k) {
+    lv[k] = gview(a.elem_loc)[min(tid + k * kBlockThreads, nloc - 1)];
+    const int q = min(tid + k * kBlockThreads, nc - 1);
+    tv[k] = ((const SEM_GLOBAL u32x4*)gview(a.acc_pk))[q];
+    cv[k] = gview(a.acc_cm)[q];
+  }
+  const int nreg = KU > 0 ? cbb * nc + a.nl : 0;
+  const int64_t rbase = (c0 + cbb < a.nx) ? (int64_t)(c0 + cbb) * nc : (a.periodic ? 0 : (int64_t)a.nx * nc);
+  auto region_at = [&](int q) -> int64_t {
+    const int lc = q / nc, ql = q - lc * nc;
+    return (lc < cbb) ? (int64_t)(c0 + lc) * nc + ql : rbase + ql;
+  };
+  T rv[KU > 0 ? KU : 1];
+  if constexpr (KU > 0) {
+#pragma unroll
+    for (int k = 0; k < KU; ++k) rv[k] = gview(u)[region_at(min(tid + k * kBlockThreads, nreg - 1))];
+  }
+  // the stores
+  if constexpr (OPS_LDS) {
+    V* dst = reinterpret_cast<V*>(lop);
+#pragma unroll
+    for (int k = 0; k < KO; ++k) dst[tid + k * kBlockThreads] = ov[k];
+  }
+#pragma unroll
+  for (int k = 0; k < kStageRegs; ++k) {
+    const int i = tid + k * kBlockThreads;
+    if (i < nloc) lloc[i] = lv[k];
+    if (i < nc) {
+      tent4[i] = tv[k];
+      tcm[i] = cv[k];
+    }
+  }
+  if constexpr (KU > 0) {
+#pragma unroll
+    for (int k = 0; k < KU; ++k)
+      if (tid + k * kBlockThreads < nreg) ureg[tid + k * kBlockThreads] = rv[k];
+  }
+  // the rest
+  for (int i = tid + kStageRegs * kBlockThreads; i < nloc; i += kBlockThreads) lloc[i] = gview(a.elem_loc)[i];
+  for (int q = tid + kStageRegs * kBlockThreads; q < nc; q += kBlockThreads) {
+    tent4[q] = ((const SEM_GLOBAL u32x4*)gview(a.acc_pk))[q];
+    tcm[q] = gview(a.acc_cm)[q];
+  }
+  if constexpr (KU > 0)
+    for (int q = tid + KU * kBlockThreads; q < nreg; q += kBlockThreads) ureg[q] = gview(u)[region_at(q)];
 }
 
 // a node's packed entries from the LDS copy of the table
@@ -291,18 +332,7 @@ __device__ __forceinline__ void stiff_body(const StiffArgs<T>& a, const T* __res
   constexpr bool kPrefetch = MT <= 2 || sizeof(T) == sizeof(float);
   if (kPrefetch && wave < ntile) load_g(wave);
   // stage operators, element tables and the input region in LDS
-  if constexpr (OPS_LDS) {
-    // 16-byte loads; 4 NpP^2 is a multiple of 16 values
-    constexpr int kVec = 16 / sizeof(T);
-    typedef double dv2 __attribute__((ext_vector_type(2)));
-    using V = typename std::conditional<sizeof(T) == 8, dv2, f4>::type;
-    const SEM_GLOBAL V* src = (const SEM_GLOBAL V*)gview(a.opf);
-    V* dst = reinterpret_cast<V*>(lop);
-#pragma unroll
-    for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
-  }
-  stage_tables(a, NpP, lloc, tent4, tcm);
-  stage_region(a, u, ureg, c0, cbb);
+  stage_block<NpP, stiff_u_regs(P), OPS_LDS>(a, u, lop, lloc, tent4, tcm, ureg, c0, cbb);
   __syncthreads();
   // operator fragments: LDS copies, or global memory when they do not fit
   auto opv = [&](int i) -> T {
@@ -426,17 +456,7 @@ __device__ __forceinline__ void stiff_body_mb(const StiffArgs<T>& a, const T* __
   auto cols_of = [&](int b) { return min(a.cb, a.nx - b * a.cb); };
   auto tiles_of = [&](int b) { return (cols_of(b) * nz2 + 15) >> 4; };
   // operators, element table and node-sum table: requested first, stored once
-  if constexpr (OPS_LDS) {
-    // 16-byte loads; 4 NpP^2 is a multiple of 16 values
-    constexpr int kVec = 16 / sizeof(T);
-    typedef double dv2 __attribute__((ext_vector_type(2)));
-    using V = typename std::conditional<sizeof(T) == 8, dv2, f4>::type;
-    const SEM_GLOBAL V* src = (const SEM_GLOBAL V*)gview(a.opf);
-    V* dst = reinterpret_cast<V*>(lop);
-#pragma unroll
-    for (int i = threadIdx.x; i < 4 * NpP * NpP / kVec; i += kBlockThreads) dst[i] = src[i];
-  }
-  stage_tables(a, NpP, lloc, tent4, tcm);
+  stage_block<NpP, 0, OPS_LDS>(a, u, lop, lloc, tent4, tcm, static_cast<T*>(nullptr), 0, 0);
   // input region of block b into registers (kU per thread cover any block;
   // the host checks cb nc + nl <= kU * kBlockThreads)
   T ur[kU];
