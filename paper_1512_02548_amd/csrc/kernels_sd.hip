@@ -545,9 +545,13 @@ k_sd_idft(const TankDev* __restrict__ td, int which, int gate) {
 // q + 1): z_I = Y - C [x_L,c; x_L,c+1].  SPLIT: wave w takes the K-steps
 // w, w + 4, ... and the partial tiles are added in wave order; CH = 4: the
 // same sums, chain r of the tile taking the K-steps = r mod 4.
-template <typename T, int NTW, bool SPLIT, int CH>
+// PRE (split): the first group of factor fragments (pre), and Y and the
+// interior index of the thread's output (ypre, ipre) were requested by the
+// caller, before the line solutions were formed.
+template <typename T, int NTW, bool SPLIT, int CH, bool PRE = false>
 __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& sd, T* __restrict__ z,
-                                                double* xl, int c0, int mt) {
+                                                double* xl, int c0, int mt, const T* pre = nullptr,
+                                                double ypre = 0, int ipre = 0) {
   using MF = Mfma<T>;
   using V4 = typename MF::V4;
   const int nI = sd.nI, q = sd.q, nx = d.nx, nc = d.nc, KS3 = sd.KS3;
@@ -570,7 +574,12 @@ __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& 
 #pragma unroll
     for (int p2 = 0; p2 < kPre; ++p2) dst[p2] = C[(size_t)min(s + p2 * s_step, KS3 - 1) * 64 + lane];
   };
-  load(s_first, ab);
+  if constexpr (PRE) {
+#pragma unroll
+    for (int p2 = 0; p2 < kPre; ++p2) ab[p2] = pre[p2];
+  } else {
+    load(s_first, ab);
+  }
   for (int s = s_first; s < KS3; s += kPre * s_step) {
     if (s + kPre * s_step < KS3) load(s + kPre * s_step, an);
 #pragma unroll
@@ -605,7 +614,8 @@ __device__ __forceinline__ void sd_back_product(const TankDev& d, const SDData& 
       if (c >= nx || row >= nI) continue;
       double sacc = 0;
       for (int w = 0; w < kWaves; ++w) sacc += red[(w * NTW + u) * 256 + threadIdx.x];
-      z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - sacc);
+      if constexpr (PRE && NTW == 1) z[(int64_t)c * nc + ipre] = T(ypre - sacc);
+      else z[(int64_t)c * nc + sd.I_idx[row]] = T(sd.yI[(size_t)c * nI + row] - sacc);
     }
     return;
   }
@@ -662,6 +672,22 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
   const int lane = threadIdx.x & 63, wv = wave_id(), col = lane & 15, grp = lane >> 4;
   const int c0 = bx * ncol;
   const int mt = shp.split ? by : 4 * by + wv;
+  // a single tank's split product: its first factor fragments, and Y and the
+  // interior index of the thread's output, requested before the line
+  // solutions are formed (they do not depend on them)
+  constexpr int kPreB = 8;
+  T abp[kPreB];
+  double ysp = 0;
+  int isp = 0;
+  if (!B && shp.split && mt < nMT) {
+    const SEM_GLOBAL T* C = gview(SdMat<T>::C3(sd)) + (size_t)mt * KS3 * 64;
+#pragma unroll
+    for (int p2 = 0; p2 < kPreB; ++p2) abp[p2] = C[(size_t)min(wv + p2 * kWaves, KS3 - 1) * 64 + lane];
+    const int row = min(16 * mt + (int)(threadIdx.x >> 4), nI - 1);
+    const int c = min(c0 + (int)(threadIdx.x & 15), nx - 1);
+    ysp = gview(sd.yI)[(size_t)c * nI + row];
+    isp = gview(sd.I_idx)[row];
+  }
   if (dft) {
     // x_L,c = Re sum_k e^{2 pi i k c / nx} x^_k / nx for lines c0 .. c0 + 16:
     // wave (line tile lt, unknown tile jt), the whole K range (modes x re/im)
@@ -742,7 +768,7 @@ __device__ __forceinline__ void sd_back_body(const TankDev& d, int which, T* __r
     }
     return;
   }
-  if (shp.split) sd_back_product<T, 1, true, 1>(d, sd, z, xl, c0, mt);
+  if (shp.split) sd_back_product<T, 1, true, 1, true>(d, sd, z, xl, c0, mt, abp, ysp, isp);
   else if (ntw == 4) sd_back_product<T, 4, false, 1>(d, sd, z, xl, c0, mt);
   else if (ntw == 2) sd_back_product<T, 2, false, 1>(d, sd, z, xl, c0, mt);
   else sd_back_product<T, 1, false, 1>(d, sd, z, xl, c0, mt);
