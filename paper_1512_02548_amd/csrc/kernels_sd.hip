@@ -323,6 +323,22 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
   const int kr = kval ? kmode : 0;
   // twiddle index (kmode * c) mod nx for c = 4 s + grp, s = wv, wv + 4, ...
   const int step = (int)(((int64_t)16 * kr) % nx);
+  // small tanks (SQ: one (mode, row) of the solve per thread): the first
+  // kSolveChunk entries of the thread's row of the inverse symbol, requested
+  // before the transform (they do not depend on it)
+  const int tk = (int)threadIdx.x / max(q, 1), ti = (int)threadIdx.x - tk * q;
+  const int tmode = SQ && tk < kModesPB ? paired_mode(bx, tk, kPairs, nx) : -1;
+  const int tkm = tmode >= 0 ? tmode : 0;
+  const SEM_GLOBAL T* tS = gview(SdMat<T>::Shat(sd)) + (size_t)(2 * tkm > nx ? nx - tkm : tkm) * q * q * 2;
+  double sv0[SQ ? 2 * kSolveChunk : 1];
+  if constexpr (SQ) {
+#pragma unroll
+    for (int e = 0; e < kSolveChunk; ++e) {
+      const int jj = min(e, q - 1);
+      sv0[2 * e] = (double)tS[((size_t)jj * q + min(ti, q - 1)) * 2];
+      sv0[2 * e + 1] = (double)tS[((size_t)jj * q + min(ti, q - 1)) * 2 + 1];
+    }
+  }
   for (int nt0 = 0; nt0 < nNT; nt0 += 4) {
     const int ntn = min(4, nNT - nt0);
     V4 are[4], aim[4];
@@ -413,14 +429,15 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
     const double sgn = cj ? -1.0 : 1.0;
     double xr = 0, xi = 0;
     if constexpr (decltype(load_all)::value) {
-      // kSolveChunk entries requested together (clamped addresses)
+      // kSolveChunk entries requested together (clamped addresses; the first
+      // chunk's came before the transform)
       for (int j0 = 0; j0 < q; j0 += kSolveChunk) {
         double sv[2 * kSolveChunk];
 #pragma unroll
         for (int e = 0; e < kSolveChunk; ++e) {
           const int jj = min(j0 + e, q - 1);
-          sv[2 * e] = (double)S[((size_t)jj * q + i) * 2];
-          sv[2 * e + 1] = (double)S[((size_t)jj * q + i) * 2 + 1];
+          sv[2 * e] = j0 == 0 ? sv0[2 * e] : (double)S[((size_t)jj * q + i) * 2];
+          sv[2 * e + 1] = j0 == 0 ? sv0[2 * e + 1] : (double)S[((size_t)jj * q + i) * 2 + 1];
         }
 #pragma unroll
         for (int e = 0; e < kSolveChunk; ++e) {
@@ -445,10 +462,15 @@ __device__ __forceinline__ void sd_modes_body(const TankDev& d, int which, const
     sd.XH[((size_t)k * q + i) * 2] = xr;
     sd.XH[((size_t)k * q + i) * 2 + 1] = xi;
   };
-  for (int t = threadIdx.x; t < kModesPB * q; t += blockDim.x) {
-    const int kk = t / q, i = t - kk * q, k = paired_mode(bx, kk, kPairs, nx);
-    if (k < 0) continue;
-    solve(kk, i, k, std::integral_constant<bool, SQ>{});
+  if constexpr (SQ) {
+    // (kModesPB q <= kBlockThreads: thread (tk, ti) alone)
+    if (tmode >= 0) solve(tk, ti, tmode, std::integral_constant<bool, SQ>{});
+  } else {
+    for (int t = threadIdx.x; t < kModesPB * q; t += blockDim.x) {
+      const int kk = t / q, i = t - kk * q, k = paired_mode(bx, kk, kPairs, nx);
+      if (k < 0) continue;
+      solve(kk, i, k, std::integral_constant<bool, SQ>{});
+    }
   }
 }
 
