@@ -603,11 +603,18 @@ __device__ __forceinline__ void orth_partial_t(int64_t n, int j, const T* __rest
       for (int e = 0; e < U; ++e)
 #pragma unroll
         for (int u = 0; u < 8; ++u) vv[e][u] = V[(int64_t)min(k0 + u, j) * n + ii[e]];
+      // (h read from clamped indices and the update selected: a branch per
+      // vector would wait for each h on its own)
+      double hk[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) hk[u] = hcol[min(k0 + u, j)];
 #pragma unroll
       for (int e = 0; e < U; ++e)
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (k0 + u <= j) v[e] -= hcol[k0 + u] * (double)vv[e][u];
+        for (int u = 0; u < 8; ++u) {
+          const double t = v[e] - hk[u] * (double)vv[e][u];
+          v[e] = k0 + u <= j ? t : v[e];
+        }
     }
 #pragma unroll
     for (int e = 0; e < U; ++e) {
