@@ -875,14 +875,38 @@ k_solve_update(int64_t n, const T* __restrict__ Z, const double* __restrict__ Hb
                const KrylovState* __restrict__ ks, T* __restrict__ x, const TankDev* __restrict__ td,
                const double* __restrict__ phis, double* __restrict__ phi, int stage) {
   __shared__ double ys[kMaxRestart];
+  // the triangle of H (column k: rows 0 .. k, from index k (k + 1) / 2) and
+  // g, staged by the workgroup (every load requested before its store), so
+  // that the back-substitution reads LDS instead of one global round trip
+  // per entry
+  __shared__ double ht[kMaxRestart * (kMaxRestart + 1) / 2];
+  __shared__ double gs[kMaxRestart];
   const int jn = ks->j;
-  if (threadIdx.x == 0) {
+  {
     const double* H = Hbase;
     const double* g = Hbase + (m + 1) * m + 2 * m;
+    constexpr int kU = 4;
+    for (int t0 = threadIdx.x; t0 < jn * jn; t0 += kU * kBlockThreads) {
+      double hv[kU];
+#pragma unroll
+      for (int e = 0; e < kU; ++e) {
+        const int t = min(t0 + e * kBlockThreads, jn * jn - 1), k = t / jn, i = t - k * jn;
+        hv[e] = H[(size_t)k * (m + 1) + i];
+      }
+#pragma unroll
+      for (int e = 0; e < kU; ++e) {
+        const int t = t0 + e * kBlockThreads, k = t / jn, i = t - k * jn;
+        if (t < jn * jn && i <= k) ht[k * (k + 1) / 2 + i] = hv[e];
+      }
+    }
+    if ((int)threadIdx.x < jn) gs[threadIdx.x] = g[threadIdx.x];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     for (int i = jn - 1; i >= 0; --i) {
-      double sacc = g[i];
-      for (int k = i + 1; k < jn; ++k) sacc -= H[(size_t)k * (m + 1) + i] * ys[k];
-      ys[i] = sacc / H[(size_t)i * (m + 1) + i];
+      double sacc = gs[i];
+      for (int k = i + 1; k < jn; ++k) sacc -= ht[k * (k + 1) / 2 + i] * ys[k];
+      ys[i] = sacc / ht[i * (i + 1) / 2 + i];
     }
   }
   __syncthreads();
